@@ -1,0 +1,168 @@
+"""Sparse preconditioner for GoFD-2 (Section 3.4, "Preconditioning with sparse matrices").
+
+1. Take the entries of A_FD on a Laplacian-like pattern: 5-point or 9-point
+   in 2D (the paper), 27-point in 3D (Example 4).  This is the matrix
+   A_FD^(p) whose entry for nodes j, m is T_{j-m} when j - m lies in the
+   pattern and 0 otherwise.
+2. A_h^(p) = I^T A_FD^(p) I  (eq. Ah-4), restricted to the interior block.
+3. Incomplete Cholesky of A_h^(p) with level-1 fill-in.
+
+The paper does not define the level-of-fill rule, the ordering, or what
+happens on a non-positive pivot.  Readings: the classical level-of-fill rule
+(lev = 0 on the pattern of the matrix, lev(i,j) = min over k < min(i,j) of
+lev(i,k) + lev(k,j) + 1, keep lev <= 1), the vertex numbering given with the
+mesh, and on a pivot <= 0 a restart on A + alpha diag(A) with alpha = 1e-3,
+doubled until the factorisation succeeds.
+
+Counts of iterations that the preconditioner saves are shown in the paper
+only in figures, so the iteration counts themselves are "parity unpinned".
+"""
+
+from __future__ import annotations
+
+import heapq
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+PATTERNS = {"IC1_5": 5, "IC1_9": 9, "IC1_27": 27}
+
+
+def stencil_offsets(d: int, npts: int):
+    """Offsets of the 5-, 9- or 27-point pattern."""
+    if d == 2 and npts == 5:
+        return [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)]
+    if d == 2 and npts == 9:
+        return [(a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+    if d == 3 and npts == 7:
+        return [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    if d == 3 and npts == 27:
+        return [(a, b, c) for c in (-1, 0, 1) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+    raise ValueError("unsupported pattern")
+
+
+def afd_pattern_matrix(T, d, W, npts) -> sp.csr_matrix:
+    """A_FD^(p): the entries of A_FD on the stencil pattern (step 1)."""
+    n = W ** d
+    idx = np.indices((W,) * d).reshape(d, -1)    # idx[0] slowest = coordinate axis d-1
+    rows, cols, vals = [], [], []
+    k = np.arange(n)
+    for off in stencil_offsets(d, npts):
+        ok = np.ones(n, dtype=bool)
+        nb = np.zeros(n, dtype=np.int64)
+        mult = 1
+        for a in range(d):                        # coordinate axis a
+            ia = idx[d - 1 - a] + off[a]
+            ok &= (ia >= 0) & (ia < W)
+            nb += np.clip(ia, 0, W - 1) * mult
+            mult *= W
+        rows.append(k[ok])
+        cols.append(nb[ok])
+        tv = T[tuple(abs(off[a]) for a in reversed(range(d)))]
+        vals.append(np.full(int(ok.sum()), tv))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def Ah_pattern(tr, T, npts) -> sp.csr_matrix:
+    """A_h^(p) = I_J^T A_FD^(p) I_J on the interior block (eq. Ah-4)."""
+    Ap = afd_pattern_matrix(T, tr.d, tr.W, npts)
+    return (tr.IJ.T @ Ap @ tr.IJ).tocsr()
+
+
+def ic1_pattern(A: sp.csr_matrix, level: int = 1):
+    """Lower-triangular pattern of incomplete factorisation with level-of-fill <= level.
+
+    Row by row (Gaussian-elimination order): start from the structural
+    pattern of row i (level 0); for each k < i in the row, in increasing
+    order, propagate lev(i,j) = min(lev(i,j), lev(i,k) + lev(k,j) + 1) for the
+    upper part j > k of the already-final row k.  Symmetric A: the lower
+    pattern is the transpose of the upper pattern.
+    """
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    upper_levels = [None] * n   # row k: dict j -> lev for j > k (the part of U used later)
+    lower_rows = []
+    for i in range(n):
+        cols = A.indices[A.indptr[i]:A.indptr[i + 1]]
+        lev = {int(j): 0 for j in cols}
+        lev[i] = 0
+        k_list = sorted(j for j in lev if j < i)
+        heap = list(k_list)
+        heapq.heapify(heap)
+        seen = set(k_list)
+        while heap:
+            k = heapq.heappop(heap)
+            lik = lev[k]
+            if lik > level:
+                continue
+            for j, lkj in upper_levels[k].items():
+                nl = lik + lkj + 1
+                if nl <= level and nl < lev.get(j, level + 1):
+                    lev[j] = nl
+                    if j < i and j not in seen:
+                        heapq.heappush(heap, j)
+                        seen.add(j)
+        kept = {j: l for j, l in lev.items() if l <= level}
+        upper_levels[i] = {j: l for j, l in kept.items() if j > i}
+        lower_rows.append(sorted(j for j in kept if j <= i))
+    return lower_rows
+
+
+def ic_numeric(A: sp.csr_matrix, lower_rows):
+    """Incomplete Cholesky on a given lower pattern: (L L^T)_ij = a_ij on the pattern.
+
+    Row-oriented: for j < i in the pattern of row i,
+      L_ij = (a_ij - sum_{k<j} L_ik L_jk) / L_jj,
+      L_ii = sqrt(a_ii - sum_{k<i} L_ik^2);
+    contributions outside the pattern are dropped.  Returns (L as CSR, ok).
+    """
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    rows = []
+    for i in range(n):
+        a_row = {int(j): float(v) for j, v in zip(A.indices[A.indptr[i]:A.indptr[i + 1]],
+                                                  A.data[A.indptr[i]:A.indptr[i + 1]])}
+        Li = {}
+        for j in lower_rows[i]:
+            if j == i:
+                continue
+            acc = a_row.get(j, 0.0)
+            Lj = rows[j]
+            for k, v in Li.items():
+                if k < j and k in Lj:
+                    acc -= v * Lj[k]
+            Li[j] = acc / Lj[j]
+        diag = a_row.get(i, 0.0) - sum(v * v for v in Li.values())
+        if not diag > 0.0:
+            return None, False
+        Li[i] = math.sqrt(diag)
+        rows.append(Li)
+    indptr = [0]
+    ind, val = [], []
+    for i in range(n):
+        for j in sorted(rows[i]):
+            ind.append(j)
+            val.append(rows[i][j])
+        indptr.append(len(ind))
+    return sp.csr_matrix((np.array(val), np.array(ind), np.array(indptr)), shape=(n, n)), True
+
+
+def ic1(A: sp.csr_matrix, level: int = 1):
+    """IC(level) with the diagonal-shift restart; returns (L, alpha)."""
+    A = sp.csr_matrix(A)
+    pattern = ic1_pattern(A, level)
+    alpha = 0.0
+    while True:
+        As = A if alpha == 0.0 else (A + alpha * sp.diags(A.diagonal())).tocsr()
+        L, ok = ic_numeric(As, pattern)
+        if ok:
+            return L, alpha
+        alpha = 1e-3 if alpha == 0.0 else 2 * alpha
+
+
+def apply_ic(L: sp.csr_matrix, r: np.ndarray) -> np.ndarray:
+    """z = (L L^T)^{-1} r by a forward then a backward triangular solve."""
+    from scipy.sparse.linalg import spsolve_triangular
+    y = spsolve_triangular(L, r, lower=True)
+    return spsolve_triangular(L.T.tocsr(), y, lower=False)
