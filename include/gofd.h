@@ -1,0 +1,296 @@
+/*
+ * gofd.h -- C ABI of the grid-overlay finite difference (GoFD) library for the
+ * fractional Laplacian on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: W. Huang and J. Shen, "A grid-overlay finite difference method for
+ * the fractional Laplacian on arbitrary bounded domains".  The library
+ * discretises the homogeneous Dirichlet problem (-Delta)^s u = f in Omega,
+ * u = 0 outside Omega, 0 < s < 1 (eq. FL-1), on an unstructured simplicial
+ * mesh T_h overlaid by a uniform grid T_FD, through
+ *
+ *     A_h = D_h^{-1} (I_h^FD)^T A_FD I_h^FD                      (eq. Ah-1)
+ *
+ * where I_h^FD is P1 interpolation from the mesh to the grid (eq. IhFD-1),
+ * D_h holds its column sums, and A_FD is the multilevel Toeplitz matrix of the
+ * uniform-grid FD approximation (eqs. T-1, A-1, AFD-1), applied through a
+ * zero-padded circulant embedding and FFTs (eq. AU-1).  The linear system is
+ * GoFD-2 on the interior vertices,
+ *
+ *     (I^T A_FD I) u = h^{2s} I^T f_FD                            (eq. GoFD-2)
+ *
+ * solved by preconditioned conjugate gradients with the incomplete Cholesky
+ * factor (level-1 fill) of A_h^(p) = I^T A_FD^(p) I (eq. Ah-4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: GOFD_OK (0) on success, a negative gofd_status otherwise;
+ *    gofd_last_error(ctx) gives a human-readable reason.  On error no output
+ *    buffer is guaranteed to hold anything meaningful.
+ *  - Pointers named *_dev are device pointers (HIP global memory of the
+ *    context's device), owned by the caller, read-only unless documented as an
+ *    output, and must stay valid until the work enqueued by the call has
+ *    finished on the context's stream.  Pointers without the suffix are host
+ *    pointers.
+ *  - Work is enqueued on the context's stream.  Calls that return results on
+ *    the host (info structs, T tables) synchronise that stream before
+ *    returning; gofd_apply_* calls are asynchronous.
+ *  - Handles (gofd_transfer, gofd_fdop, gofd_precond) are owned by the library
+ *    and freed with their *_free function; a handle copies whatever it needs
+ *    from the inputs, so inputs may be freed after the creating call returns.
+ *  - Grid geometry: the cube (c - R, c + R)^d carries W = 2N+1 nodes per axis
+ *    with spacing h = R/N (Section 3.1).  Node i along axis a is located at
+ *    (c_a - R) + i*h with each operation rounded separately in double
+ *    precision (no fused multiply-add).  Grid arrays are stored in C order with
+ *    the x index fastest: node (i_0, .., i_{d-1}) has linear number
+ *    i_0 + W i_1 (+ W^2 i_2), the natural ordering.
+ *  - Vertex vectors have length N_v in the mesh's vertex numbering.  With
+ *    nrhs > 1, right-hand sides / fields are stored one after another.
+ */
+#ifndef GOFD_H
+#define GOFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GOFD_OK = 0,
+  GOFD_E_ARG = -1,            /* bad pointer, size, dimension, s not in (0,1), N < 1 ... */
+  GOFD_E_DEGENERATE = -2,     /* a mesh element has zero volume                          */
+  GOFD_E_RANK = -3,           /* (2N+1)^d < N_v: I cannot have full column rank          */
+  GOFD_E_ZERO_COLSUM = -4,    /* an interior vertex has D_j = 0 (grid too coarse)         */
+  GOFD_E_NOT_CONVERGED = -5,  /* iteration limit reached before the tolerance             */
+  GOFD_E_BREAKDOWN = -6,      /* CG breakdown (p^T K p <= 0) or a non-finite value        */
+  GOFD_E_HIP = -7,            /* a HIP runtime call failed                                */
+  GOFD_E_OOM = -8,            /* device or host allocation failed                         */
+  GOFD_E_NUMERIC = -9,        /* exact-arithmetic capacity exceeded in point location     */
+  GOFD_E_UNSUPPORTED = -10    /* valid request this build does not implement              */
+} gofd_status;
+
+typedef struct gofd_ctx_s* gofd_ctx;
+typedef struct gofd_transfer_s* gofd_transfer;
+typedef struct gofd_fdop_s* gofd_fdop;
+typedef struct gofd_precond_s* gofd_precond;
+
+/* Overlay grid T_FD (Section 3.1): W = 2N+1 nodes per axis, h = R/N. */
+typedef struct {
+  int d;              /* 2 or 3                                          */
+  int N;              /* half the number of intervals per axis, N >= 1   */
+  double R;           /* half side of the cube                           */
+  double center[3];   /* cube centre (unused entries ignored)            */
+} gofd_grid;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to the current HIP device and the given stream
+ * (a hipStream_t passed as void*; NULL means the null stream).
+ * Errors: GOFD_E_ARG (out == NULL), GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_create(gofd_ctx* out, void* hip_stream);
+/* Destroy a context (handles created from it must be freed first). */
+int gofd_destroy(gofd_ctx ctx);
+/* Re-bind the context to another stream of the same device. */
+int gofd_set_stream(gofd_ctx ctx, void* hip_stream);
+/* Last error message of this context (static storage owned by ctx). */
+const char* gofd_last_error(gofd_ctx ctx);
+/* Name of a status code. */
+const char* gofd_strerror(int status);
+
+/* ---------------------------------------------------------------- transfer */
+
+typedef struct {
+  int64_t n_nodes;          /* W^d                                                        */
+  int64_t n_inside;         /* grid nodes lying in a closed mesh element                  */
+  int64_t nnz;              /* structural nonzeros of I: (d+1) * n_inside                 */
+  int64_t n_interior;       /* vertices not on a boundary facet                           */
+  int64_t n_boundary;       /* Dirichlet vertices (on a facet owned by one element)       */
+  double dmin_interior;     /* min D_j over interior vertices                             */
+  double a_h;               /* minimum element height                                     */
+  double h_bound;           /* a_h / ((d+1) sqrt(d)), the sufficient spacing of eq. hFD-1  */
+  int64_t exact_tests;      /* orientation signs decided by exact expansion arithmetic    */
+  int64_t max_col_count;    /* largest number of grid nodes touching one vertex          */
+} gofd_transfer_info;
+
+/* Build I_h^FD, its transpose structure and D_h (Section 3.1, eqs. interp-1 to
+ * IhFD-1; D_h after eq. Ah-1 and Lemma IhFD-1(iv)).
+ *   X_dev      N_v x d doubles, row-major vertex coordinates.
+ *   elems_dev  N_e x (d+1) int32, 0-based vertex ids, either orientation.
+ *   grid       overlay grid (host struct).
+ * Point location: node k belongs to the element with the smallest id among
+ * the closed elements that contain it (exact orientation signs); a node in no
+ * closed element has a zero row.  The barycentric weights of node k are
+ * lambda = E^{-1}[x_k; 1] (proof of the simplex interpolation lemma).
+ * Dirichlet vertices are the vertices of facets owned by a single element;
+ * the solve keeps them at zero (remark after eq. GoFD-2).
+ * info (host, nullable) receives the statistics above.
+ * Errors: GOFD_E_ARG, GOFD_E_DEGENERATE, GOFD_E_RANK, GOFD_E_ZERO_COLSUM,
+ * GOFD_E_NUMERIC, GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double* X_dev, int64_t ne,
+                        const int32_t* elems_dev, const gofd_grid* grid, gofd_transfer* out,
+                        gofd_transfer_info* info);
+int gofd_transfer_free(gofd_transfer tr);
+
+/* Copy parts of a transfer to caller buffers (device pointers, enqueued on the
+ * stream).  Sizes: ELEM int32[W^d] (element of each node or -1);
+ * ELL_VERTS int32[W^d*(d+1)] and ELL_WEIGHTS double[W^d*(d+1)] (vertex ids and
+ * barycentric weights of each node's element, zero rows for outside nodes,
+ * vertex ids -1 there); CSC_OFFSETS int32[N_v+1]; CSC_NODES int32[nnz] (grid
+ * node of each entry, vertex-major, ascending node number inside a vertex);
+ * CSC_WEIGHTS double[nnz]; D double[N_v]; BOUNDARY uint8[N_v] (1 = Dirichlet). */
+typedef enum {
+  GOFD_TR_ELEM = 0,
+  GOFD_TR_ELL_VERTS = 1,
+  GOFD_TR_ELL_WEIGHTS = 2,
+  GOFD_TR_CSC_OFFSETS = 3,
+  GOFD_TR_CSC_NODES = 4,
+  GOFD_TR_CSC_WEIGHTS = 5,
+  GOFD_TR_D = 6,
+  GOFD_TR_BOUNDARY = 7
+} gofd_transfer_part;
+int gofd_transfer_export(gofd_ctx ctx, gofd_transfer tr, int part, void* dst_dev);
+
+/* ---------------------------------------------------------------- FD operator */
+
+typedef struct {
+  int64_t M;        /* finest quadrature level M (power of two); 0 = the paper's
+                       default: 2^14 for d = 2, 2^11 for d = 3, raised if needed so
+                       that M/2 >= 2(2N)+1                                          */
+  int richardson;   /* 1 = combine levels M and M/2 (the paper), 0 = level M only  */
+} gofd_fdw_opts;
+
+/* Toeplitz coefficients T_p, p in {0..2N}^d, of the FD fractional Laplacian
+ * (eqs. T-0, T-1) by Filon's rule with piecewise-linear psi~ (eq. Tp-1D-2,
+ * applied along every axis) and Richardson extrapolation over M and M/2
+ * (Section 2.3), computed on the device; then the real, even DFT of the
+ * circulant embedding used by the FFT product (eq. AU-1).  h^{2s} is stored
+ * for the right-hand side of eq. GoFD-2.  opts may be NULL (defaults).
+ * Errors: GOFD_E_ARG (s not in (0,1), bad grid), GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_fd_weights(gofd_ctx ctx, double s, const gofd_grid* grid, const gofd_fdw_opts* opts,
+                    gofd_fdop* out);
+
+/* Same operator from a caller-supplied T octant (host, (2N+1)^d doubles in the
+ * grid-array layout: T[p_0 + W p_1 (+ W^2 p_2)] = T_{p}).  s only scales the
+ * right-hand side (h^{2s}). */
+int gofd_fdop_from_table(gofd_ctx ctx, double s, const gofd_grid* grid, const double* T_host,
+                         gofd_fdop* out);
+/* Copy the T octant ((2N+1)^d doubles) to a host buffer (synchronises). */
+int gofd_fdop_get_table(gofd_ctx ctx, gofd_fdop op, double* T_host);
+int gofd_fdop_free(gofd_fdop op);
+
+/* Flags of the apply calls. */
+enum {
+  GOFD_FP32_GRID = 1,     /* grid-side arrays and FFTs in single precision (mesh vectors,
+                             weights and the final accumulation stay double)             */
+  GOFD_SYMMETRIC = 2,     /* apply A~_h = D^{-1/2} I^T A_FD I D^{-1/2} (eq. Ah-3)           */
+  GOFD_UNSCALED = 4,      /* apply I^T A_FD I (the matrix of eq. GoFD-2, all vertices)     */
+  GOFD_SCALE_H2S = 8,     /* multiply the result by h^{-2s} (the operator of eq. GoFD-1)   */
+  GOFD_INTERIOR = 16      /* zero the input and output on Dirichlet vertices              */
+};
+
+/* y = A_FD v on the grid (eq. AFD-1) for nrhs fields of W^d doubles.
+ * v_dev and y_dev may not alias. */
+int gofd_apply_afd(gofd_ctx ctx, gofd_fdop op, int nrhs, const double* v_dev, double* y_dev,
+                   int flags);
+
+/* y = A_h u = D^{-1} I^T A_FD I u (eq. Ah-1) for nrhs vertex vectors of N_v
+ * doubles; variants by flags as above.  u_dev and y_dev may not alias.
+ * Errors: GOFD_E_ARG (grids of op and tr differ, nrhs < 1), GOFD_E_HIP. */
+int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const double* u_dev,
+                  double* y_dev, int flags);
+
+/* ---------------------------------------------------------------- solve */
+
+typedef enum {
+  GOFD_PC_NONE = 0,       /* plain CG                                                      */
+  GOFD_PC_DIAG = 1,       /* M = D_h: CG on the symmetric form A~_h (eq. Ah-3)             */
+  GOFD_PC_IC1_5 = 5,      /* IC(1) of I^T A_FD^(5) I  (Section 3.4, 2D)                     */
+  GOFD_PC_IC1_9 = 9,      /* IC(1) of I^T A_FD^(9) I  (Section 3.4, 2D)                     */
+  GOFD_PC_IC1_27 = 27     /* IC(1) of I^T A_FD^(27) I (Example 4, 3D)                       */
+} gofd_pc_kind;
+
+typedef struct {
+  double shift;           /* alpha of the final factor of A + alpha diag(A) (0 = none)    */
+  int64_t nnz_L;          /* nonzeros of the lower factor                                  */
+  int levels;             /* dependency levels of the forward triangular solve             */
+  double setup_ms;        /* host + device setup time                                      */
+} gofd_precond_info;
+
+/* Build a preconditioner for eq. GoFD-2 on the interior block.  For the IC(1)
+ * kinds: the entries of A_FD on the 5/9/27-point pattern (Section 3.4), the
+ * sparse triple product I^T A_FD^(p) I, a level-of-fill <= 1 incomplete
+ * Cholesky factorisation in the mesh's vertex order (pivot <= 0: restart on
+ * A + alpha diag(A), alpha = 1e-3 doubling), uploaded with its dependency
+ * levels for the triangular solves.  Setup runs on the host (the factor is
+ * sequential by nature); applies run on the device.  info nullable. */
+int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int kind, gofd_precond* out,
+                        gofd_precond_info* info);
+int gofd_precond_free(gofd_precond pc);
+/* Export the IC factor L (lower CSR over all N_v vertices; Dirichlet rows are
+ * identity rows).  Sizes from info->nnz_L; host buffers (synchronises). */
+int gofd_precond_export(gofd_ctx ctx, gofd_precond pc, int32_t* rowptr_host, int32_t* cols_host,
+                        double* vals_host);
+
+enum { GOFD_F_GRID = 0, GOFD_F_VERTEX = 1 };
+enum {
+  GOFD_MODE_FP64 = 0,            /* every product in double precision                         */
+  GOFD_MODE_FP32_REFINE = 1      /* FP32-grid CG corrections inside FP64 iterative refinement */
+};
+
+typedef struct {
+  int mode;              /* GOFD_MODE_*                                                     */
+  int max_iter;          /* total CG iterations allowed (0 = 20000)                         */
+  int check_every;       /* host reads of the convergence flag every k iterations (0 = 8)   */
+  double inner_tol;      /* FP32 mode: relative tolerance of each correction solve (0 = 1e-5)*/
+  int max_refine;        /* FP32 mode: maximum outer refinement steps (0 = 30)              */
+  int use_graph;         /* capture k CG iterations in a hipGraph and replay it (1 = yes)   */
+  double* history;       /* optional host array of max_iter+1 relative residuals, or NULL   */
+} gofd_solve_opts;
+
+typedef struct {
+  int iterations;        /* CG iterations (all refinement steps)                            */
+  int refinements;       /* outer FP64 residual recomputations (FP32 mode)                  */
+  double rel_residual;   /* ||b - K u|| / ||b|| recomputed in FP64 at exit                  */
+  double time_ms;        /* wall time of the call                                           */
+  int status;            /* GOFD_OK or the error returned                                   */
+} gofd_solve_info;
+
+/* Solve eq. GoFD-2 (f on the grid, f_loc = GOFD_F_GRID: W^d doubles per rhs,
+ * values outside the mesh are ignored since their rows of I are zero) or
+ * eq. GoFD-3 (f_loc = GOFD_F_VERTEX: N_v doubles per rhs) for u on the
+ * vertices, with u = 0 on Dirichlet vertices, to ||b - K u||_2 <= tol ||b||_2
+ * (CG from u = 0).  pc may be NULL (plain CG) or a gofd_precond.
+ *   f_dev: nrhs right-hand sides; u_dev: nrhs * N_v doubles (output).
+ *   info: host array of nrhs entries (nullable).
+ * Errors: GOFD_E_ARG, GOFD_E_NOT_CONVERGED, GOFD_E_BREAKDOWN, GOFD_E_HIP. */
+int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, int nrhs,
+               const double* f_dev, int f_loc, double tol, const gofd_solve_opts* opts,
+               double* u_dev, gofd_solve_info* info);
+
+/* Many independent problems (mesh, grid, s, right-hand sides) in one call:
+ * problem q uses tr[q], op[q], pc[q] (nullable) and nrhs[q] right-hand sides
+ * f_dev[q] -> u_dev[q].  The CG iterations of all problems advance together,
+ * each stage issued once per iteration for the whole batch; converged systems
+ * are masked.  info: host array of sum(nrhs) entries (nullable). */
+int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* tr, const gofd_fdop* op,
+                       const gofd_precond* pc, const int* nrhs, const double* const* f_dev,
+                       int f_loc, double tol, const gofd_solve_opts* opts, double* const* u_dev,
+                       gofd_solve_info* info);
+
+/* Gradients of a scalar loss L(u) of the GoFD-2 solution u (f on the grid)
+ * by the adjoint method: lambda = K^{-1} dL/du (K is symmetric, same solver),
+ * dL/df_FD = h^{2s} I lambda, dL/dI_kj = lambda_j r_k - (A_FD I lambda)_k u_j
+ * with r = h^{2s} f_FD - A_FD I u, chained to the vertex coordinates through
+ * d lambda_r/d X_{i,a} = -(E^{-1})_{r,a} lambda_i (point location held fixed).
+ *   dLdu_dev, u_dev: N_v doubles (u from gofd_solve); f_dev: W^d doubles.
+ *   grad_f_dev: W^d doubles or NULL; grad_X_dev: N_v*d doubles or NULL.
+ *   lambda_dev: optional output of the adjoint solution (N_v doubles) or NULL. */
+int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc,
+                       const double* dLdu_dev, const double* u_dev, const double* f_dev, double tol,
+                       const gofd_solve_opts* opts, double* grad_f_dev, double* grad_X_dev,
+                       double* lambda_dev, gofd_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOFD_H */

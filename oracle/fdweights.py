@@ -49,12 +49,13 @@ def psi_tilde(xis, s: float) -> np.ndarray:
 def closed_form_1d(s: float, P: int) -> np.ndarray:
     """T_p = (-1)^p Gamma(2s+1) / (Gamma(p+s+1) Gamma(s-p+1)), p = 0..P (eq. T-1D-0).
 
-    Evaluated with the reciprocal gamma function so that the large factors
-    of the two gammas never overflow separately.
+    Evaluated in logarithms (ln|Gamma| and the sign of Gamma) so that the large
+    factors of the two gammas never overflow separately.
     """
     p = np.arange(P + 1, dtype=np.float64)
-    sign = np.where(p % 2 == 0, 1.0, -1.0)
-    return sign * special.gamma(2 * s + 1) * special.rgamma(p + s + 1) * special.rgamma(s - p + 1)
+    sign = np.where(p % 2 == 0, 1.0, -1.0) * special.gammasgn(s - p + 1)
+    logmag = special.gammaln(2 * s + 1) - special.gammaln(p + s + 1) - special.gammaln(s - p + 1)
+    return sign * np.exp(logmag)
 
 
 def _signs(P: int, d: int) -> np.ndarray:
@@ -153,6 +154,19 @@ def filon_richardson(s: float, d: int, P: int, M: int) -> np.ndarray:
     return (4.0 * fine - coarse) / 3.0
 
 
+def _ive(q: int, x: float) -> float:
+    """e^{-x} I_q(x); scipy for moderate x, the Hankel large-argument series beyond."""
+    if x < 5e8:
+        return float(special.ive(q, x))
+    mu = 4.0 * q * q
+    z8 = 8.0 * x
+    term, acc = 1.0, 1.0
+    for k in range(1, 6):
+        term *= -(mu - (2 * k - 1) ** 2) / (k * z8)
+        acc += term
+    return acc / math.sqrt(2.0 * math.pi * x)
+
+
 def bessel_route(s: float, p, epsabs: float = 1e-15, epsrel: float = 1e-13) -> float:
     """T_p from the subordination identity (independent of the paper; used as a pin).
 
@@ -164,7 +178,7 @@ def bessel_route(s: float, p, epsabs: float = 1e-15, epsrel: float = 1e-13) -> f
     def prod_ive(t):
         v = 1.0
         for q in p:
-            v *= special.ive(q, 2.0 * t)
+            v *= _ive(q, 2.0 * t)
         return v
 
     # [0, 1]: write the integrand as g(t) * t^{-s} with g(t) = (delta - prod)/t smooth
@@ -177,8 +191,23 @@ def bessel_route(s: float, p, epsabs: float = 1e-15, epsrel: float = 1e-13) -> f
 
     a, _ = integrate.quad(g, 0.0, 1.0, weight="alg", wvar=(-s, 0.0), epsabs=epsabs, epsrel=epsrel,
                           limit=400)
-    # [1, inf): delta part integrates to 1/s exactly
-    b, _ = integrate.quad(lambda t: prod_ive(t) * t ** (-1.0 - s), 1.0, np.inf, epsabs=epsabs,
-                          epsrel=epsrel, limit=400)
+    # [1, inf): delta part integrates to 1/s exactly.  In tau = ln t the rest is
+    # int_0^inf prod ive(p_a, 2 e^tau) e^{-s tau} dtau, smooth with a bump near
+    # t ~ |p|^2, so the range is split around it.
+    def h(tau):
+        return prod_ive(math.exp(tau)) * math.exp(-s * tau)
+
+    tp = 2.0 * math.log(max(p) + 1.0)
+    cuts = sorted({0.0, max(0.0, tp - 6), max(0.0, tp - 3), max(0.0, tp - 1), tp, tp + 1, tp + 3, tp + 6,
+                   tp + 12, tp + 24})
+    b = 0.0
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        if hi > lo:
+            b += integrate.quad(h, lo, hi, epsabs=epsabs, epsrel=epsrel, limit=400)[0]
+    # up to t = e^{tp + 60}, then the large-t form e^{-2t} I_q(2t) ~ (4 pi t)^{-1/2}
+    top = tp + 60.0
+    b += integrate.quad(h, cuts[-1], top, epsabs=epsabs, epsrel=epsrel, limit=400)[0]
+    e = 0.5 * len(p) + s
+    b += (4.0 * math.pi) ** (-0.5 * len(p)) * math.exp(-e * top) / e
     tail = (1.0 / s if is0 else 0.0) - b
     return s / math.gamma(1.0 - s) * (a + tail)

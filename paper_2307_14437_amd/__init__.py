@@ -1,0 +1,374 @@
+"""Python binding of libgofd (the GoFD fractional-Laplacian library for MI355X).
+
+Argument marshalling only: every step of the method runs in the HIP library
+behind the C ABI declared in ``include/gofd.h``.  PyTorch supplies device
+memory and the current stream.  There is no CPU fallback: importing this
+module fails loudly when the compiled library is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgofd.so")
+
+# status codes
+OK = 0
+E_ARG, E_DEGENERATE, E_RANK, E_ZERO_COLSUM, E_NOT_CONVERGED = -1, -2, -3, -4, -5
+E_BREAKDOWN, E_HIP, E_OOM, E_NUMERIC, E_UNSUPPORTED = -6, -7, -8, -9, -10
+
+# transfer parts
+TR_ELEM, TR_ELL_VERTS, TR_ELL_WEIGHTS, TR_CSC_OFFSETS = 0, 1, 2, 3
+TR_CSC_NODES, TR_CSC_WEIGHTS, TR_D, TR_BOUNDARY = 4, 5, 6, 7
+
+# apply flags
+FP32_GRID, SYMMETRIC, UNSCALED, SCALE_H2S, INTERIOR = 1, 2, 4, 8, 16
+
+# preconditioners
+PC_NONE, PC_DIAG, PC_IC1_5, PC_IC1_9, PC_IC1_27 = 0, 1, 5, 9, 27
+PC_BY_NAME = {"NONE": PC_NONE, "DIAG": PC_DIAG, "IC1_5": PC_IC1_5, "IC1_9": PC_IC1_9, "IC1_27": PC_IC1_27}
+
+F_GRID, F_VERTEX = 0, 1
+MODE_FP64, MODE_FP32_REFINE = 0, 1
+
+
+class GofdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("N", ctypes.c_int), ("R", ctypes.c_double),
+                ("center", ctypes.c_double * 3)]
+
+
+class TransferInfo(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_inside", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("n_interior", ctypes.c_int64), ("n_boundary", ctypes.c_int64),
+                ("dmin_interior", ctypes.c_double), ("a_h", ctypes.c_double), ("h_bound", ctypes.c_double),
+                ("exact_tests", ctypes.c_int64), ("max_col_count", ctypes.c_int64)]
+
+
+class FdwOpts(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("richardson", ctypes.c_int)]
+
+
+class PrecondInfo(ctypes.Structure):
+    _fields_ = [("shift", ctypes.c_double), ("nnz_L", ctypes.c_int64), ("levels", ctypes.c_int),
+                ("setup_ms", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double))]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("time_ms", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libgofd.so is not built ({LIB_PATH}); run __graft_entry__.build() or "
+                          "python paper_2307_14437_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "gofd_create": [ctypes.POINTER(vp), vp],
+        "gofd_destroy": [vp],
+        "gofd_set_stream": [vp, vp],
+        "gofd_build_transfer": [vp, i32, i64, vp, i64, vp, ctypes.POINTER(_Grid), ctypes.POINTER(vp),
+                                ctypes.POINTER(TransferInfo)],
+        "gofd_transfer_free": [vp],
+        "gofd_transfer_export": [vp, vp, i32, vp],
+        "gofd_fd_weights": [vp, dbl, ctypes.POINTER(_Grid), ctypes.POINTER(FdwOpts), ctypes.POINTER(vp)],
+        "gofd_fdop_from_table": [vp, dbl, ctypes.POINTER(_Grid), ctypes.POINTER(dbl), ctypes.POINTER(vp)],
+        "gofd_fdop_get_table": [vp, vp, ctypes.POINTER(dbl)],
+        "gofd_fdop_free": [vp],
+        "gofd_apply_afd": [vp, vp, i32, vp, vp, i32],
+        "gofd_apply_Ah": [vp, vp, vp, i32, vp, vp, i32],
+        "gofd_precond_create": [vp, vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(PrecondInfo)],
+        "gofd_precond_free": [vp],
+        "gofd_precond_export": [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(dbl)],
+        "gofd_solve": [vp, vp, vp, vp, i32, vp, i32, dbl, ctypes.POINTER(SolveOpts), vp,
+                       ctypes.POINTER(SolveInfo)],
+        "gofd_solve_batched": [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                               ctypes.POINTER(i32), ctypes.POINTER(vp), i32, dbl, ctypes.POINTER(SolveOpts),
+                               ctypes.POINTER(vp), ctypes.POINTER(SolveInfo)],
+        "gofd_solve_adjoint": [vp, vp, vp, vp, vp, vp, vp, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp,
+                               ctypes.POINTER(SolveInfo)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.gofd_last_error.argtypes = [vp]
+    lib.gofd_last_error.restype = ctypes.c_char_p
+    lib.gofd_strerror.argtypes = [ctypes.c_int]
+    lib.gofd_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+EXPORTED = [
+    "gofd_create", "gofd_destroy", "gofd_set_stream", "gofd_last_error", "gofd_strerror",
+    "gofd_build_transfer", "gofd_transfer_free", "gofd_transfer_export", "gofd_fd_weights",
+    "gofd_fdop_from_table", "gofd_fdop_get_table", "gofd_fdop_free", "gofd_apply_afd", "gofd_apply_Ah",
+    "gofd_precond_create", "gofd_precond_free", "gofd_precond_export", "gofd_solve", "gofd_solve_batched",
+    "gofd_solve_adjoint",
+]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _grid(grid) -> _Grid:
+    c = list(grid.center) + [0.0] * (3 - len(grid.center))
+    return _Grid(int(grid.d), int(grid.N), float(grid.R), (ctypes.c_double * 3)(*c))
+
+
+class Context:
+    """A library context bound to torch's current HIP stream on the current device."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the GoFD library runs on the GPU only")
+        self._torch = torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = ctypes.c_void_p()
+        self._check(lib.gofd_create(ctypes.byref(h), ctypes.c_void_p(s.cuda_stream)), None)
+        self.handle = h
+
+    def _check(self, code, h="self"):
+        if code != OK:
+            msg = lib.gofd_last_error(self.handle).decode() if h == "self" and getattr(self, "handle", None) \
+                else lib.gofd_strerror(code).decode()
+            raise GofdError(code, msg)
+
+    def check(self, code):
+        self._check(code)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gofd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Transfer:
+    def __init__(self, ctx: Context, X, elems, grid):
+        torch = ctx._torch
+        if X.dtype != torch.float64 or elems.dtype != torch.int32 or not X.is_cuda or not elems.is_cuda:
+            raise TypeError("X must be a CUDA float64 tensor and elems a CUDA int32 tensor")
+        X = X.contiguous()
+        elems = elems.contiguous()
+        self.ctx, self.grid = ctx, grid
+        self.d = int(X.shape[1])
+        self.nv = int(X.shape[0])
+        self.ne = int(elems.shape[0])
+        self.W = 2 * grid.N + 1
+        self.n_nodes = self.W ** self.d
+        h = ctypes.c_void_p()
+        info = TransferInfo()
+        g = _grid(grid)
+        ctx.check(lib.gofd_build_transfer(ctx.handle, self.d, self.nv, _ptr(X), self.ne, _ptr(elems),
+                                          ctypes.byref(g), ctypes.byref(h), ctypes.byref(info)))
+        self.handle = h
+        self.info = {k: getattr(info, k) for k, _ in TransferInfo._fields_}
+
+    def export(self, part):
+        torch = self.ctx._torch
+        nnz = self.info["nnz"]
+        d1 = self.d + 1
+        spec = {
+            TR_ELEM: (self.n_nodes, torch.int32), TR_ELL_VERTS: (self.n_nodes * d1, torch.int32),
+            TR_ELL_WEIGHTS: (self.n_nodes * d1, torch.float64), TR_CSC_OFFSETS: (self.nv + 1, torch.int32),
+            TR_CSC_NODES: (nnz, torch.int32), TR_CSC_WEIGHTS: (nnz, torch.float64),
+            TR_D: (self.nv, torch.float64), TR_BOUNDARY: (self.nv, torch.uint8),
+        }[part]
+        out = torch.empty(max(spec[0], 1), dtype=spec[1], device="cuda")
+        self.ctx.check(lib.gofd_transfer_export(self.ctx.handle, self.handle, part, _ptr(out)))
+        return out[: spec[0]]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gofd_transfer_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FdOp:
+    def __init__(self, ctx: Context, s, grid, T=None, M=0, richardson=True):
+        self.ctx, self.s, self.grid = ctx, float(s), grid
+        self.W = 2 * grid.N + 1
+        h = ctypes.c_void_p()
+        g = _grid(grid)
+        if T is None:
+            opts = FdwOpts(int(M), 1 if richardson else 0)
+            ctx.check(lib.gofd_fd_weights(ctx.handle, self.s, ctypes.byref(g), ctypes.byref(opts), ctypes.byref(h)))
+        else:
+            T = np.ascontiguousarray(T, dtype=np.float64)
+            if T.size != self.W ** grid.d:
+                raise ValueError("T must hold (2N+1)^d values")
+            ctx.check(lib.gofd_fdop_from_table(ctx.handle, self.s, ctypes.byref(g),
+                                               T.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                               ctypes.byref(h)))
+        self.handle = h
+
+    def table(self):
+        out = np.empty((self.W,) * self.grid.d, dtype=np.float64)
+        self.ctx.check(lib.gofd_fdop_get_table(self.ctx.handle, self.handle,
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gofd_fdop_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def apply_afd(ctx: Context, op: FdOp, v, flags=0):
+    v = v.contiguous()
+    nrhs = v.numel() // (op.W ** op.grid.d)
+    y = ctx._torch.empty_like(v)
+    ctx.check(lib.gofd_apply_afd(ctx.handle, op.handle, nrhs, _ptr(v), _ptr(y), int(flags)))
+    return y
+
+
+def apply_Ah(ctx: Context, tr: Transfer, op: FdOp, u, flags=0):
+    u = u.contiguous()
+    nrhs = u.numel() // tr.nv
+    y = ctx._torch.empty_like(u)
+    ctx.check(lib.gofd_apply_Ah(ctx.handle, tr.handle, op.handle, nrhs, _ptr(u), _ptr(y), int(flags)))
+    return y
+
+
+class Precond:
+    def __init__(self, ctx: Context, tr: Transfer, op: FdOp, kind):
+        if isinstance(kind, str):
+            kind = PC_BY_NAME[kind]
+        self.ctx, self.kind, self.nv = ctx, int(kind), tr.nv
+        h = ctypes.c_void_p()
+        info = PrecondInfo()
+        ctx.check(lib.gofd_precond_create(ctx.handle, tr.handle, op.handle, self.kind, ctypes.byref(h),
+                                          ctypes.byref(info)))
+        self.handle = h
+        self.info = {k: getattr(info, k) for k, _ in PrecondInfo._fields_}
+
+    def export(self):
+        import scipy.sparse as sp
+        nnz = int(self.info["nnz_L"])
+        rp = np.empty(self.nv + 1, dtype=np.int32)
+        ci = np.empty(nnz, dtype=np.int32)
+        va = np.empty(nnz, dtype=np.float64)
+        self.ctx.check(lib.gofd_precond_export(self.ctx.handle, self.handle,
+                                               rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               va.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return sp.csr_matrix((va, ci, rp), shape=(self.nv, self.nv))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gofd_precond_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(mode=MODE_FP64, max_iter=0, check_every=0, inner_tol=0.0, max_refine=0, use_graph=1, history=None):
+    o = SolveOpts(int(mode), int(max_iter), int(check_every), float(inner_tol), int(max_refine), int(use_graph),
+                  None)
+    if history is not None:
+        o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return o
+
+
+def solve(ctx: Context, tr: Transfer, op: FdOp, f, tol=1e-10, pc: Precond | None = None, f_loc=F_GRID,
+          raise_on_error=True, **kw):
+    """Solve eq. GoFD-2 (f on the grid) or GoFD-3 (f on the vertices); returns (u, [info dicts])."""
+    torch = ctx._torch
+    f = f.contiguous()
+    per = tr.n_nodes if f_loc == F_GRID else tr.nv
+    nrhs = f.numel() // per
+    u = torch.empty(nrhs * tr.nv, dtype=torch.float64, device=f.device)
+    infos = (SolveInfo * nrhs)()
+    opts = _opts(**kw)
+    code = lib.gofd_solve(ctx.handle, tr.handle, op.handle, pc.handle if pc else None, nrhs, _ptr(f), int(f_loc),
+                          float(tol), ctypes.byref(opts), _ptr(u), infos)
+    if code != OK and raise_on_error:
+        ctx.check(code)
+    return u.view(nrhs, tr.nv) if nrhs > 1 else u, [infos[i].as_dict() for i in range(nrhs)]
+
+
+def solve_batched(ctx: Context, trs, ops, pcs, fs, tol=1e-8, f_loc=F_GRID, raise_on_error=True, **kw):
+    """Many problems in one call: fs[q] holds nrhs[q] right-hand sides of problem q."""
+    torch = ctx._torch
+    n = len(trs)
+    nr = []
+    us = []
+    for q in range(n):
+        per = trs[q].n_nodes if f_loc == F_GRID else trs[q].nv
+        nr.append(fs[q].numel() // per)
+        us.append(torch.empty(nr[-1] * trs[q].nv, dtype=torch.float64, device=fs[q].device))
+    fs = [f.contiguous() for f in fs]
+    arr = lambda xs: (ctypes.c_void_p * n)(*[x.handle if x is not None else None for x in xs])
+    fp = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    up = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+    nrr = (ctypes.c_int * n)(*nr)
+    infos = (SolveInfo * sum(nr))()
+    opts = _opts(**kw)
+    code = lib.gofd_solve_batched(ctx.handle, n, arr(trs), arr(ops), arr(pcs if pcs else [None] * n), nrr, fp,
+                                  int(f_loc), float(tol), ctypes.byref(opts), up, infos)
+    if code != OK and raise_on_error:
+        ctx.check(code)
+    return us, [infos[i].as_dict() for i in range(sum(nr))]
+
+
+def solve_adjoint(ctx: Context, tr: Transfer, op: FdOp, dLdu, u, f, tol=1e-10, pc: Precond | None = None,
+                  want_f=True, want_X=True, **kw):
+    torch = ctx._torch
+    gf = torch.empty(tr.n_nodes, dtype=torch.float64, device=u.device) if want_f else None
+    gX = torch.empty(tr.nv * tr.d, dtype=torch.float64, device=u.device) if want_X else None
+    lam = torch.empty(tr.nv, dtype=torch.float64, device=u.device)
+    info = SolveInfo()
+    opts = _opts(**kw)
+    ctx.check(lib.gofd_solve_adjoint(ctx.handle, tr.handle, op.handle, pc.handle if pc else None,
+                                     _ptr(dLdu.contiguous()), _ptr(u.contiguous()), _ptr(f.contiguous()),
+                                     float(tol), ctypes.byref(opts), _ptr(gf) if gf is not None else None,
+                                     _ptr(gX) if gX is not None else None, _ptr(lam), ctypes.byref(info)))
+    return gf, (gX.view(tr.nv, tr.d) if gX is not None else None), lam, info.as_dict()

@@ -1,0 +1,145 @@
+// Internal declarations of the GoFD HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gofd.h"
+
+// ------------------------------------------------------------------ errors
+
+#define GOFD_TRY(expr)                  \
+  do {                                  \
+    int _st = (expr);                   \
+    if (_st != GOFD_OK) return _st;     \
+  } while (0)
+
+#define HIP_TRY(ctx, expr)                                                         \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return gofd_fail((ctx), GOFD_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+struct gofd_ctx_s;
+int gofd_fail(gofd_ctx_s* ctx, int code, const std::string& msg);
+
+// ------------------------------------------------------------------ complex
+
+template <typename R>
+struct cplx {
+  R x, y;
+};
+
+// ------------------------------------------------------------------ device buffer
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// grow-only allocation; returns GOFD_OK / GOFD_E_OOM
+int dev_reserve(gofd_ctx_s* ctx, DevBuf& b, size_t bytes);
+
+// ------------------------------------------------------------------ context
+
+struct TwiddleTables {
+  DevBuf tw64;   // cplx<double>[L], exp(-2 pi i t / L)
+  DevBuf tw32;   // cplx<float>[L]
+};
+
+struct gofd_ctx_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cu = 256;
+  std::string last_error;
+  std::map<int, TwiddleTables*> twiddles;   // keyed by L
+  DevBuf scratch;                           // small reduction scratch (partials, counters)
+  DevBuf flag;                              // int status flags
+  ~gofd_ctx_s();
+};
+
+const cplx<double>* twiddles64(gofd_ctx_s* ctx, int L);
+const cplx<float>* twiddles32(gofd_ctx_s* ctx, int L);
+
+// ------------------------------------------------------------------ handles
+
+struct gofd_transfer_s {
+  int d = 2, N = 0, W = 0;
+  double R = 1.0, center[3] = {0, 0, 0};
+  double h = 0.0, lo[3] = {0, 0, 0};
+  int64_t nv = 0, ne = 0, n_nodes = 0, nnz = 0;
+  DevBuf X;          // double[nv*d]
+  DevBuf elems;      // int32[ne*(d+1)]
+  DevBuf elem;       // int32[n_nodes], element of each node or -1
+  DevBuf csc_off;    // int32[nv+1]
+  DevBuf csc_node;   // int32[nnz]
+  DevBuf csc_w;      // double[nnz]
+  DevBuf csc_w32;    // float[nnz]
+  DevBuf D;          // double[nv]
+  DevBuf dscale;     // double[nv]: 1/D_j (0 where D_j == 0)
+  DevBuf dsqrt;      // double[nv]: 1/sqrt(D_j) (0 where D_j == 0)
+  DevBuf bmask;      // uint8[nv], 1 = Dirichlet vertex
+  DevBuf imask;      // double[nv], 1.0 interior, 0.0 Dirichlet
+  std::vector<int32_t> elems_host;
+  std::vector<uint8_t> bmask_host;
+  std::vector<double> X_host;
+  gofd_transfer_info info{};
+  gofd_ctx_s* ctx = nullptr;
+};
+
+struct gofd_fdop_s {
+  int d = 2, N = 0, W = 0, L = 0, half = 0;
+  double s = 0.5, h = 0.0, h2s = 1.0, R = 1.0, center[3] = {0, 0, 0};
+  std::vector<double> T_host;   // octant (W^d)
+  DevBuf T;                     // double[W^d]
+  DevBuf That64;                // double[half^d], includes the 1/L^d normalisation
+  DevBuf That32;                // float [half^d]
+  DevBuf Z;                     // spectra workspace
+  DevBuf Y;                     // grid-field workspace
+  gofd_ctx_s* ctx = nullptr;
+};
+
+// ------------------------------------------------------------------ internal API
+
+// Exclusive scan of int32 counts (n entries) into out (n+1 entries).
+int scan_exclusive_i32(gofd_ctx_s* ctx, const int32_t* in, int32_t* out, int64_t n);
+
+// Grid-space convolution y = A_FD v for fields on the grid; `src` selects how
+// the field is produced (from a grid array or gathered from vertex values).
+struct GatherSpec {
+  // gather v = I u: all pointers device; u has nrhs*nv entries (stride nv)
+  const gofd_transfer_s* tr = nullptr;
+  const double* u = nullptr;
+  const double* col_scale = nullptr;   // optional per-vertex scale applied to u (D^{-1/2})
+  const double* mask = nullptr;        // optional per-vertex mask (interior)
+};
+
+// Apply A_FD with the FFT embedding: input either a grid field (v != nullptr,
+// nrhs*W^d doubles) or a gather spec; output grid field y (double or float,
+// nrhs*W^d).  fp32 selects the single-precision pipeline.
+int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g,
+               void* y, bool fp32);
+
+// z_j = scale_j * sum_k w_kj y_k over the CSC structure (I^T y), optionally
+// masked; y is double or float (fp32).  nrhs fields.
+int scatter_apply(gofd_ctx_s* ctx, const gofd_transfer_s* tr, int nrhs, const void* y, bool fp32,
+                  const double* scale, const double* mask, double* z);
+
+int fdop_init_geometry(gofd_ctx_s* ctx, gofd_fdop_s* op, double s, const gofd_grid* grid);
+
+// Compute the spectral multiplier of the circulant embedding from T (device).
+int fdop_finish(gofd_ctx_s* ctx, gofd_fdop_s* op);

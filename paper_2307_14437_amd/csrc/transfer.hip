@@ -1,0 +1,546 @@
+// Transfer matrix I_h^FD: point location, barycentric weights, the vertex-major
+// (transposed) structure, column sums D_h, and the I^T scatter.
+//
+// Section 3.1 of the paper: (I_h^FD)_{k,j} = phi_j(x_k^FD) (eq. IhFD-1); a node
+// outside the closed mesh has a zero row; D_{h,j} = sum_k (I_h^FD)_{k,j}.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "bary.h"
+#include "internal.h"
+#include "predicates.h"
+
+namespace {
+
+constexpr int NO_ELEM = 0x7fffffff;
+
+GridGeom make_geom(const gofd_transfer_s* tr) {
+  GridGeom g;
+  g.d = tr->d;
+  g.W = tr->W;
+  g.h = tr->h;
+  for (int a = 0; a < 3; ++a) g.lo[a] = tr->lo[a];
+  return g;
+}
+
+// ---------------------------------------------------------------- K1: location
+//
+// One thread per element: the element's bounding box in grid-index space is
+// enlarged by one node on each side (a conservative candidate set), and every
+// candidate node is tested against the closed simplex with exact orientation
+// signs.  elem_of_node[k] receives the smallest containing element id through
+// an integer atomicMin, so the result does not depend on scheduling.
+template <int D>
+__global__ __launch_bounds__(256) void k_locate(GridGeom g, const double* __restrict__ X,
+                                                const int* __restrict__ elems, long long ne,
+                                                int* __restrict__ elem_of_node,
+                                                unsigned long long* __restrict__ counters) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double V[D + 1][3];
+  for (int r = 0; r <= D; ++r) {
+    const int v = elems[e * (D + 1) + r];
+    for (int a = 0; a < D; ++a) V[r][a] = X[(long long)v * D + a];
+  }
+  int exact_used = 0;
+  int esign;
+  if constexpr (D == 2)
+    esign = gofd_exact::orient2_sign(V[0], V[1], V[2], &exact_used);
+  else
+    esign = gofd_exact::orient3_sign(V[0], V[1], V[2], V[3], &exact_used);
+  if (esign == 0) {
+    atomicOr((unsigned int*)&counters[1], 1u);   // degenerate element
+    return;
+  }
+  if (esign == 2) {
+    atomicOr((unsigned int*)&counters[2], 1u);   // expansion capacity
+    return;
+  }
+  int ilo[3], ihi[3];
+  for (int a = 0; a < D; ++a) {
+    double mn = V[0][a], mx = V[0][a];
+    for (int r = 1; r <= D; ++r) {
+      mn = fmin(mn, V[r][a]);
+      mx = fmax(mx, V[r][a]);
+    }
+    const double fl = floor((mn - g.lo[a]) / g.h) - 1.0;
+    const double cl = ceil((mx - g.lo[a]) / g.h) + 1.0;
+    ilo[a] = (int)fmax(0.0, fmin((double)(g.W - 1), fl));
+    ihi[a] = (int)fmax(0.0, fmin((double)(g.W - 1), cl));
+  }
+  unsigned long long nexact = exact_used;
+  const int nz = (D == 3) ? (ihi[2] - ilo[2] + 1) : 1;
+  for (int iz = 0; iz < nz; ++iz) {
+    for (int iy = ilo[1]; iy <= ihi[1]; ++iy) {
+      for (int ix = ilo[0]; ix <= ihi[0]; ++ix) {
+        double p[3];
+        p[0] = node_coord(g, 0, ix);
+        p[1] = node_coord(g, 1, iy);
+        if constexpr (D == 3) p[2] = node_coord(g, 2, ilo[2] + iz);
+        bool inside = true;
+        for (int r = 0; r <= D && inside; ++r) {
+          int ex = 0;
+          int sg;
+          if constexpr (D == 2) {
+            const double* q[3] = {V[0], V[1], V[2]};
+            q[r] = p;
+            sg = gofd_exact::orient2_sign(q[0], q[1], q[2], &ex);
+          } else {
+            const double* q[4] = {V[0], V[1], V[2], V[3]};
+            q[r] = p;
+            sg = gofd_exact::orient3_sign(q[0], q[1], q[2], q[3], &ex);
+          }
+          nexact += ex;
+          if (sg == 2) {
+            atomicOr((unsigned int*)&counters[2], 1u);
+            inside = false;
+          } else if (sg * esign < 0) {
+            inside = false;
+          }
+        }
+        if (inside) {
+          long long k = (long long)ix + (long long)g.W * iy;
+          if constexpr (D == 3) k += (long long)g.W * g.W * (ilo[2] + iz);
+          atomicMin(&elem_of_node[k], (int)e);
+        }
+      }
+    }
+  }
+  if (nexact) atomicAdd(&counters[0], nexact);
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, long long n, int v) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_finish_location(int* __restrict__ elem_of_node, long long n,
+                                  unsigned long long* __restrict__ counters) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  if (elem_of_node[k] == NO_ELEM)
+    elem_of_node[k] = -1;
+  else
+    atomicAdd(&counters[3], 1ull);
+}
+
+// ---------------------------------------------------------------- K3: CSC
+template <int D>
+__global__ void k_count(const int* __restrict__ elem_of_node, const int* __restrict__ elems, long long n,
+                        int* __restrict__ cnt) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int e = elem_of_node[k];
+  if (e < 0) return;
+  for (int r = 0; r <= D; ++r) atomicAdd(&cnt[elems[(long long)e * (D + 1) + r]], 1);
+}
+
+template <int D>
+__global__ void k_fill_csc(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+                           const int* __restrict__ elem_of_node, long long n, int* __restrict__ cursor,
+                           int* __restrict__ node_out, double* __restrict__ w_out) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int e = elem_of_node[k];
+  if (e < 0) return;
+  int vid[D + 1];
+  double lam[D + 1];
+  node_weights<D>(g, X, elems, e, k, vid, lam);
+  for (int r = 0; r <= D; ++r) {
+    const int pos = atomicAdd(&cursor[vid[r]], 1);
+    node_out[pos] = (int)k;
+    w_out[pos] = lam[r];
+  }
+}
+
+// one 64-lane wavefront per vertex: rank each entry of the segment by node
+// number (node numbers are distinct inside a segment) and scatter it to its
+// sorted position.  Deterministic regardless of the fill order above.
+__global__ __launch_bounds__(256) void k_sort_segments(const int* __restrict__ off, long long nv,
+                                                       const int* __restrict__ node_in,
+                                                       const double* __restrict__ w_in,
+                                                       int* __restrict__ node_out, double* __restrict__ w_out) {
+  const long long v = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int lane = threadIdx.x & 63;
+  if (v >= nv) return;
+  const int b = off[v], e = off[v + 1];
+  for (int i = b + lane; i < e; i += 64) {
+    const int key = node_in[i];
+    int rank = 0;
+    for (int j = b; j < e; ++j) rank += (node_in[j] < key);
+    node_out[b + rank] = key;
+    w_out[b + rank] = w_in[i];
+  }
+}
+
+// D_j = sum of the column's weights in ascending node order; scale factors
+__global__ void k_colsum(const int* __restrict__ off, long long nv, const double* __restrict__ w,
+                         const unsigned char* __restrict__ bmask, double* __restrict__ D,
+                         double* __restrict__ dscale, double* __restrict__ dsqrt, double* __restrict__ imask,
+                         float* __restrict__ w32, long long nnz) {
+  long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  double s = 0.0;
+  for (int i = off[v]; i < off[v + 1]; ++i) {
+    s += w[i];
+    w32[i] = (float)w[i];
+  }
+  D[v] = s;
+  dscale[v] = s > 0.0 ? 1.0 / s : 0.0;
+  dsqrt[v] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  imask[v] = bmask[v] ? 0.0 : 1.0;
+}
+
+template <int D>
+__global__ void k_export_ell(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+                             const int* __restrict__ elem_of_node, long long n, int* __restrict__ verts,
+                             double* __restrict__ wts) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int e = elem_of_node[k];
+  if (e < 0) {
+    for (int r = 0; r <= D; ++r) {
+      if (verts) verts[k * (D + 1) + r] = -1;
+      if (wts) wts[k * (D + 1) + r] = 0.0;
+    }
+    return;
+  }
+  int vid[D + 1];
+  double lam[D + 1];
+  node_weights<D>(g, X, elems, e, k, vid, lam);
+  for (int r = 0; r <= D; ++r) {
+    if (verts) verts[k * (D + 1) + r] = vid[r];
+    if (wts) wts[k * (D + 1) + r] = lam[r];
+  }
+}
+
+inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- host helpers
+
+// Dirichlet vertices: vertices of facets owned by exactly one element.
+static void boundary_mask(int d, int64_t nv, const std::vector<int32_t>& el, std::vector<uint8_t>& mask) {
+  const int64_t ne = (int64_t)el.size() / (d + 1);
+  std::vector<std::pair<uint64_t, uint64_t>> keys;
+  keys.reserve(ne * (d + 1));
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int r = 0; r <= d; ++r) {
+      int32_t f[3];
+      int c = 0;
+      for (int q = 0; q <= d; ++q)
+        if (q != r) f[c++] = el[e * (d + 1) + q];
+      std::sort(f, f + d);
+      uint64_t k0 = (uint64_t)(uint32_t)f[0] << 32 | (uint32_t)f[1];
+      uint64_t k1 = (d == 3) ? (uint64_t)(uint32_t)f[2] : 0;
+      keys.push_back({k0, k1});
+    }
+  }
+  std::sort(keys.begin(), keys.end());
+  mask.assign(nv, 0);
+  for (size_t i = 0; i < keys.size();) {
+    size_t j = i + 1;
+    while (j < keys.size() && keys[j] == keys[i]) ++j;
+    if (j - i == 1) {
+      mask[(uint32_t)(keys[i].first >> 32)] = 1;
+      mask[(uint32_t)(keys[i].first & 0xffffffffu)] = 1;
+      if (d == 3) mask[(uint32_t)keys[i].second] = 1;
+    }
+    i = j;
+  }
+}
+
+static double min_height(int d, const std::vector<double>& X, const std::vector<int32_t>& el) {
+  const int64_t ne = (int64_t)el.size() / (d + 1);
+  double best = INFINITY;
+  for (int64_t e = 0; e < ne; ++e) {
+    double P[4][3];
+    for (int r = 0; r <= d; ++r)
+      for (int a = 0; a < d; ++a) P[r][a] = X[(int64_t)el[e * (d + 1) + r] * d + a];
+    if (d == 2) {
+      const double area2 = std::fabs((P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[1][1] - P[0][1]) * (P[2][0] - P[0][0]));
+      for (int j = 0; j < 3; ++j) {
+        const int a = (j + 1) % 3, b = (j + 2) % 3;
+        const double len = std::hypot(P[b][0] - P[a][0], P[b][1] - P[a][1]);
+        best = std::min(best, area2 / len);
+      }
+    } else {
+      double u[3], v[3], w[3];
+      for (int a = 0; a < 3; ++a) {
+        u[a] = P[1][a] - P[0][a];
+        v[a] = P[2][a] - P[0][a];
+        w[a] = P[3][a] - P[0][a];
+      }
+      const double vol6 = std::fabs(u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
+                                    u[2] * (v[0] * w[1] - v[1] * w[0]));
+      for (int j = 0; j < 4; ++j) {
+        int o[3], c = 0;
+        for (int q = 0; q < 4; ++q)
+          if (q != j) o[c++] = q;
+        double s[3], t[3];
+        for (int a = 0; a < 3; ++a) {
+          s[a] = P[o[1]][a] - P[o[0]][a];
+          t[a] = P[o[2]][a] - P[o[0]][a];
+        }
+        const double cx = s[1] * t[2] - s[2] * t[1], cy = s[2] * t[0] - s[0] * t[2], cz = s[0] * t[1] - s[1] * t[0];
+        const double area2 = std::sqrt(cx * cx + cy * cy + cz * cz);
+        best = std::min(best, vol6 / area2);
+      }
+    }
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------- ABI
+
+extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double* X_dev, int64_t ne,
+                                   const int32_t* elems_dev, const gofd_grid* grid, gofd_transfer* out,
+                                   gofd_transfer_info* info) {
+  if (!ctx || !out || !grid || !X_dev || !elems_dev) return gofd_fail(ctx, GOFD_E_ARG, "null argument");
+  if (d != 2 && d != 3) return gofd_fail(ctx, GOFD_E_ARG, "d must be 2 or 3");
+  if (grid->d != d || grid->N < 1 || !(grid->R > 0)) return gofd_fail(ctx, GOFD_E_ARG, "bad grid");
+  if (nv < d + 1 || ne < 1) return gofd_fail(ctx, GOFD_E_ARG, "empty mesh");
+  const int W = 2 * grid->N + 1;
+  int64_t n_nodes = 1;
+  for (int a = 0; a < d; ++a) n_nodes *= W;
+  if (n_nodes >= (int64_t)1 << 31) return gofd_fail(ctx, GOFD_E_ARG, "grid too large for 32-bit node numbers");
+  if (n_nodes < nv)
+    return gofd_fail(ctx, GOFD_E_RANK, "(2N+1)^d < N_v: I_h^FD cannot have full column rank");
+  auto* tr = new (std::nothrow) gofd_transfer_s();
+  if (!tr) return GOFD_E_OOM;
+  std::unique_ptr<gofd_transfer_s> guard(tr);
+  tr->ctx = ctx;
+  tr->d = d;
+  tr->N = grid->N;
+  tr->W = W;
+  tr->R = grid->R;
+  tr->h = grid->R / (double)grid->N;
+  for (int a = 0; a < 3; ++a) {
+    tr->center[a] = a < d ? grid->center[a] : 0.0;
+    tr->lo[a] = tr->center[a] - grid->R;
+  }
+  tr->nv = nv;
+  tr->ne = ne;
+  tr->n_nodes = n_nodes;
+  hipStream_t st = ctx->stream;
+
+  // host copies for topology (boundary facets) and heights
+  tr->elems_host.resize(ne * (d + 1));
+  tr->X_host.resize(nv * d);
+  HIP_TRY(ctx, hipMemcpyAsync(tr->elems_host.data(), elems_dev, sizeof(int32_t) * ne * (d + 1),
+                              hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->X_host.data(), X_dev, sizeof(double) * nv * d, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  for (int64_t i = 0; i < ne * (d + 1); ++i)
+    if (tr->elems_host[i] < 0 || tr->elems_host[i] >= nv)
+      return gofd_fail(ctx, GOFD_E_ARG, "element vertex id out of range");
+  for (int64_t i = 0; i < nv * d; ++i)
+    if (!std::isfinite(tr->X_host[i])) return gofd_fail(ctx, GOFD_E_ARG, "non-finite vertex coordinate");
+
+  GOFD_TRY(dev_reserve(ctx, tr->X, sizeof(double) * nv * d));
+  GOFD_TRY(dev_reserve(ctx, tr->elems, sizeof(int32_t) * ne * (d + 1)));
+  GOFD_TRY(dev_reserve(ctx, tr->elem, sizeof(int32_t) * n_nodes));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->X.p, X_dev, sizeof(double) * nv * d, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->elems.p, elems_dev, sizeof(int32_t) * ne * (d + 1), hipMemcpyDeviceToDevice, st));
+
+  GridGeom g = make_geom(tr);
+  unsigned long long* counters = ctx->scratch.as<unsigned long long>();
+  HIP_TRY(ctx, hipMemsetAsync(counters, 0, 8 * sizeof(unsigned long long), st));
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(), n_nodes, NO_ELEM);
+  if (d == 2)
+    hipLaunchKernelGGL(k_locate<2>, dim3(grid1(ne, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
+                       tr->elems.as<int>(), (long long)ne, tr->elem.as<int>(), counters);
+  else
+    hipLaunchKernelGGL(k_locate<3>, dim3(grid1(ne, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
+                       tr->elems.as<int>(), (long long)ne, tr->elem.as<int>(), counters);
+  hipLaunchKernelGGL(k_finish_location, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
+                     n_nodes, counters);
+  HIP_TRY(ctx, hipGetLastError());
+  unsigned long long hc[4];
+  HIP_TRY(ctx, hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (hc[1]) return gofd_fail(ctx, GOFD_E_DEGENERATE, "mesh has an element of zero volume");
+  if (hc[2]) return gofd_fail(ctx, GOFD_E_NUMERIC, "exact orientation exceeded its expansion capacity");
+  const int64_t n_inside = (int64_t)hc[3];
+  const int64_t nnz = n_inside * (d + 1);
+  tr->nnz = nnz;
+
+  // boundary (host topology)
+  boundary_mask(d, nv, tr->elems_host, tr->bmask_host);
+  GOFD_TRY(dev_reserve(ctx, tr->bmask, nv));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->bmask.p, tr->bmask_host.data(), nv, hipMemcpyHostToDevice, st));
+
+  // CSC: counts, offsets, fill, per-segment sort, column sums
+  DevBuf cnt, cursor, node_tmp, w_tmp;
+  GOFD_TRY(dev_reserve(ctx, cnt, sizeof(int32_t) * (nv + 1)));
+  GOFD_TRY(dev_reserve(ctx, cursor, sizeof(int32_t) * (nv + 1)));
+  GOFD_TRY(dev_reserve(ctx, tr->csc_off, sizeof(int32_t) * (nv + 1)));
+  GOFD_TRY(dev_reserve(ctx, tr->csc_node, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+  GOFD_TRY(dev_reserve(ctx, tr->csc_w, sizeof(double) * std::max<int64_t>(nnz, 1)));
+  GOFD_TRY(dev_reserve(ctx, tr->csc_w32, sizeof(float) * std::max<int64_t>(nnz, 1)));
+  GOFD_TRY(dev_reserve(ctx, node_tmp, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+  GOFD_TRY(dev_reserve(ctx, w_tmp, sizeof(double) * std::max<int64_t>(nnz, 1)));
+  HIP_TRY(ctx, hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nv + 1), st));
+  if (d == 2)
+    hipLaunchKernelGGL(k_count<2>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
+                       tr->elems.as<int>(), n_nodes, cnt.as<int>());
+  else
+    hipLaunchKernelGGL(k_count<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
+                       tr->elems.as<int>(), n_nodes, cnt.as<int>());
+  GOFD_TRY(scan_exclusive_i32(ctx, cnt.as<int32_t>(), tr->csc_off.as<int32_t>(), nv));
+  HIP_TRY(ctx, hipMemcpyAsync(cursor.p, tr->csc_off.p, sizeof(int32_t) * (nv + 1), hipMemcpyDeviceToDevice, st));
+  if (d == 2)
+    hipLaunchKernelGGL(k_fill_csc<2>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
+                       tr->elems.as<int>(), tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(),
+                       w_tmp.as<double>());
+  else
+    hipLaunchKernelGGL(k_fill_csc<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
+                       tr->elems.as<int>(), tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(),
+                       w_tmp.as<double>());
+  hipLaunchKernelGGL(k_sort_segments, dim3(grid1(nv * 64, 256)), dim3(256), 0, st, tr->csc_off.as<int>(),
+                     (long long)nv, node_tmp.as<int>(), w_tmp.as<double>(), tr->csc_node.as<int>(),
+                     tr->csc_w.as<double>());
+  GOFD_TRY(dev_reserve(ctx, tr->D, sizeof(double) * nv));
+  GOFD_TRY(dev_reserve(ctx, tr->dscale, sizeof(double) * nv));
+  GOFD_TRY(dev_reserve(ctx, tr->dsqrt, sizeof(double) * nv));
+  GOFD_TRY(dev_reserve(ctx, tr->imask, sizeof(double) * nv));
+  hipLaunchKernelGGL(k_colsum, dim3(grid1(nv, 256)), dim3(256), 0, st, tr->csc_off.as<int>(), (long long)nv,
+                     tr->csc_w.as<double>(), tr->bmask.as<unsigned char>(), tr->D.as<double>(),
+                     tr->dscale.as<double>(), tr->dsqrt.as<double>(), tr->imask.as<double>(),
+                     tr->csc_w32.as<float>(), (long long)nnz);
+  HIP_TRY(ctx, hipGetLastError());
+
+  // statistics and checks on the host
+  std::vector<double> Dh(nv);
+  std::vector<int32_t> offh(nv + 1);
+  HIP_TRY(ctx, hipMemcpyAsync(Dh.data(), tr->D.p, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(offh.data(), tr->csc_off.p, sizeof(int32_t) * (nv + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  gofd_transfer_info inf{};
+  inf.n_nodes = n_nodes;
+  inf.n_inside = n_inside;
+  inf.nnz = nnz;
+  inf.exact_tests = (int64_t)hc[0];
+  double dmin = INFINITY;
+  int64_t nb = 0, maxc = 0;
+  for (int64_t j = 0; j < nv; ++j) {
+    maxc = std::max<int64_t>(maxc, offh[j + 1] - offh[j]);
+    if (tr->bmask_host[j]) {
+      ++nb;
+    } else {
+      dmin = std::min(dmin, Dh[j]);
+    }
+  }
+  inf.n_boundary = nb;
+  inf.n_interior = nv - nb;
+  inf.dmin_interior = dmin;
+  inf.max_col_count = maxc;
+  inf.a_h = min_height(d, tr->X_host, tr->elems_host);
+  inf.h_bound = inf.a_h / ((d + 1) * std::sqrt((double)d));
+  tr->info = inf;
+  if (info) *info = inf;
+  if (inf.n_interior > 0 && !(dmin > 0.0))
+    return gofd_fail(ctx, GOFD_E_ZERO_COLSUM, "an interior vertex has zero column sum D_j (grid too coarse)");
+  *out = guard.release();
+  return GOFD_OK;
+}
+
+extern "C" int gofd_transfer_free(gofd_transfer tr) {
+  if (!tr) return GOFD_E_ARG;
+  if (tr->ctx) (void)hipStreamSynchronize(tr->ctx->stream);
+  delete tr;
+  return GOFD_OK;
+}
+
+extern "C" int gofd_transfer_export(gofd_ctx ctx, gofd_transfer tr, int part, void* dst) {
+  if (!ctx || !tr || !dst) return gofd_fail(ctx, GOFD_E_ARG, "null argument");
+  hipStream_t st = ctx->stream;
+  const int d = tr->d;
+  GridGeom g = make_geom(tr);
+  switch (part) {
+    case GOFD_TR_ELEM:
+      HIP_TRY(ctx, hipMemcpyAsync(dst, tr->elem.p, sizeof(int32_t) * tr->n_nodes, hipMemcpyDeviceToDevice, st));
+      break;
+    case GOFD_TR_ELL_VERTS:
+    case GOFD_TR_ELL_WEIGHTS: {
+      int* vv = part == GOFD_TR_ELL_VERTS ? static_cast<int*>(dst) : nullptr;
+      double* ww = part == GOFD_TR_ELL_WEIGHTS ? static_cast<double*>(dst) : nullptr;
+      if (d == 2)
+        hipLaunchKernelGGL(k_export_ell<2>, dim3(grid1(tr->n_nodes, 256)), dim3(256), 0, st, g,
+                           tr->X.as<double>(), tr->elems.as<int>(), tr->elem.as<int>(), (long long)tr->n_nodes, vv, ww);
+      else
+        hipLaunchKernelGGL(k_export_ell<3>, dim3(grid1(tr->n_nodes, 256)), dim3(256), 0, st, g,
+                           tr->X.as<double>(), tr->elems.as<int>(), tr->elem.as<int>(), (long long)tr->n_nodes, vv, ww);
+      break;
+    }
+    case GOFD_TR_CSC_OFFSETS:
+      HIP_TRY(ctx, hipMemcpyAsync(dst, tr->csc_off.p, sizeof(int32_t) * (tr->nv + 1), hipMemcpyDeviceToDevice, st));
+      break;
+    case GOFD_TR_CSC_NODES:
+      HIP_TRY(ctx, hipMemcpyAsync(dst, tr->csc_node.p, sizeof(int32_t) * tr->nnz, hipMemcpyDeviceToDevice, st));
+      break;
+    case GOFD_TR_CSC_WEIGHTS:
+      HIP_TRY(ctx, hipMemcpyAsync(dst, tr->csc_w.p, sizeof(double) * tr->nnz, hipMemcpyDeviceToDevice, st));
+      break;
+    case GOFD_TR_D:
+      HIP_TRY(ctx, hipMemcpyAsync(dst, tr->D.p, sizeof(double) * tr->nv, hipMemcpyDeviceToDevice, st));
+      break;
+    case GOFD_TR_BOUNDARY:
+      HIP_TRY(ctx, hipMemcpyAsync(dst, tr->bmask.p, tr->nv, hipMemcpyDeviceToDevice, st));
+      break;
+    default:
+      return gofd_fail(ctx, GOFD_E_ARG, "unknown transfer part");
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
+}
+
+// ---------------------------------------------------------------- K8: I^T scatter
+//
+// z_j = scale_j * mask_j * sum_{k in column j} w_kj y_k.  A group of G lanes
+// owns one vertex; lanes stride through the column (ascending node order) and
+// the partial sums are combined with cross-lane shuffles, always in the same
+// order, so the result is deterministic.
+template <typename Y, int G>
+__global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ off, const int* __restrict__ node,
+                                                 const double* __restrict__ w, const Y* __restrict__ y,
+                                                 long long nv, long long n_nodes, int nrhs,
+                                                 const double* __restrict__ scale, const double* __restrict__ mask,
+                                                 double* __restrict__ z) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long v = gid / G;
+  const int lane = threadIdx.x % G;
+  const int rhs = blockIdx.y;
+  if (v >= nv) return;
+  const int b = off[v], e = off[v + 1];
+  const Y* yr = y + (long long)rhs * n_nodes;
+  double acc = 0.0;
+  for (int i = b + lane; i < e; i += G) acc += w[i] * (double)yr[node[i]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (lane == 0) {
+    double r = acc;
+    if (scale) r *= scale[v];
+    if (mask) r *= mask[v];
+    z[(long long)rhs * nv + v] = r;
+  }
+}
+
+int scatter_apply(gofd_ctx_s* ctx, const gofd_transfer_s* tr, int nrhs, const void* y, bool fp32,
+                  const double* scale, const double* mask, double* z) {
+  constexpr int G = 16;
+  dim3 grid(grid1(tr->nv * G, 256), nrhs);
+  if (fp32)
+    hipLaunchKernelGGL((k_scatter<float, G>), grid, dim3(256), 0, ctx->stream, tr->csc_off.as<int>(),
+                       tr->csc_node.as<int>(), tr->csc_w.as<double>(), static_cast<const float*>(y),
+                       (long long)tr->nv, (long long)tr->n_nodes, nrhs, scale, mask, z);
+  else
+    hipLaunchKernelGGL((k_scatter<double, G>), grid, dim3(256), 0, ctx->stream, tr->csc_off.as<int>(),
+                       tr->csc_node.as<int>(), tr->csc_w.as<double>(), static_cast<const double*>(y),
+                       (long long)tr->nv, (long long)tr->n_nodes, nrhs, scale, mask, z);
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
+}
