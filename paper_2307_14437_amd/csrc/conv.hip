@@ -323,6 +323,13 @@ int fdop_finish(gofd_ctx_s* ctx, gofd_fdop_s* op) {
   return GOFD_OK;
 }
 
+int conv_prepare(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs) {
+  if (!twiddles64(ctx, op->L) || !twiddles32(ctx, op->L)) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
+  long long zs = 1;
+  for (int a = 0; a < op->d; ++a) zs *= (a == 0 ? op->half : op->W);
+  return dev_reserve(ctx, op->Z, sizeof(cplx<double>) * zs * nrhs);
+}
+
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g, void* y,
                bool fp32) {
   if (op->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "3D product not built yet");
@@ -447,7 +454,7 @@ extern "C" int gofd_fdop_get_table(gofd_ctx ctx, gofd_fdop op, double* T_host) {
 
 extern "C" int gofd_fdop_free(gofd_fdop op) {
   if (!op) return GOFD_E_ARG;
-  if (op->ctx) (void)hipStreamSynchronize(op->ctx->stream);
+  (void)hipDeviceSynchronize();
   delete op;
   return GOFD_OK;
 }

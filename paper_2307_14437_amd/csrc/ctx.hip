@@ -25,6 +25,21 @@ int dev_reserve(gofd_ctx_s* ctx, DevBuf& b, size_t bytes) {
 
 gofd_ctx_s::~gofd_ctx_s() {
   for (auto& kv : twiddles) delete kv.second;
+  if (ev_in) (void)hipEventDestroy(ev_in);
+  if (ev_out) (void)hipEventDestroy(ev_out);
+  if (work) (void)hipStreamDestroy(work);
+}
+
+WorkStream::WorkStream(gofd_ctx_s* c) : ctx(c), saved(c->stream) {
+  (void)hipEventRecord(ctx->ev_in, saved);
+  (void)hipStreamWaitEvent(ctx->work, ctx->ev_in, 0);
+  ctx->stream = ctx->work;
+}
+
+WorkStream::~WorkStream() {
+  (void)hipEventRecord(ctx->ev_out, ctx->work);
+  (void)hipStreamWaitEvent(saved, ctx->ev_out, 0);
+  ctx->stream = saved;
 }
 
 extern "C" int gofd_create(gofd_ctx* out, void* hip_stream) {
@@ -38,6 +53,12 @@ extern "C" int gofd_create(gofd_ctx* out, void* hip_stream) {
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return GOFD_E_HIP;
+  }
   if (dev_reserve(c, c->scratch, 1 << 20) != GOFD_OK || dev_reserve(c, c->flag, 256) != GOFD_OK) {
     delete c;
     return GOFD_E_OOM;

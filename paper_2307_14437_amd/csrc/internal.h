@@ -62,7 +62,9 @@ struct TwiddleTables {
 };
 
 struct gofd_ctx_s {
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;      // the caller's stream (may be the null stream)
+  hipStream_t work = nullptr;        // library stream for solves (capturable into graphs)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   int device = 0;
   int num_cu = 256;
   std::string last_error;
@@ -70,6 +72,15 @@ struct gofd_ctx_s {
   DevBuf scratch;                           // small reduction scratch (partials, counters)
   DevBuf flag;                              // int status flags
   ~gofd_ctx_s();
+};
+
+// Run a solve on the library's own stream, ordered after the caller's stream
+// on entry and before it on exit.
+struct WorkStream {
+  gofd_ctx_s* ctx;
+  hipStream_t saved;
+  explicit WorkStream(gofd_ctx_s* c);
+  ~WorkStream();
 };
 
 const cplx<double>* twiddles64(gofd_ctx_s* ctx, int L);
@@ -133,6 +144,10 @@ struct GatherSpec {
 // nrhs*W^d).  fp32 selects the single-precision pipeline.
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g,
                void* y, bool fp32);
+
+// Reserve the spectra workspace and twiddle tables for nrhs fields, so that
+// later products allocate nothing (required inside graph capture).
+int conv_prepare(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs);
 
 // z_j = scale_j * sum_k w_kj y_k over the CSC structure (I^T y), optionally
 // masked; y is double or float (fp32).  nrhs fields.

@@ -7,7 +7,9 @@
 // "Adaptive precision floating-point arithmetic and fast robust geometric
 // predicates", 1997: Two-Sum, Two-Product via FMA, Grow-Expansion with zero
 // elimination).  The sign of a nonoverlapping expansion is the sign of its
-// largest component.
+// largest component.  Contraction into fused multiply-adds is switched off in
+// every function: a product fused into the following sum is no longer the
+// rounded product that Two-Product's error term refers to.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,6 +18,7 @@ namespace gofd_exact {
 
 // x + y == a + b exactly, x = fl(a + b)
 __device__ __forceinline__ void two_sum(double a, double b, double& x, double& y) {
+#pragma clang fp contract(off)
   x = a + b;
   double bv = x - a;
   double av = x - bv;
@@ -26,6 +29,7 @@ __device__ __forceinline__ void two_sum(double a, double b, double& x, double& y
 
 // x + y == a * b exactly, x = fl(a * b)
 __device__ __forceinline__ void two_prod(double a, double b, double& x, double& y) {
+#pragma clang fp contract(off)
   x = a * b;
   y = __builtin_fma(a, b, -x);
 }
@@ -34,6 +38,7 @@ __device__ __forceinline__ void two_prod(double a, double b, double& x, double& 
 // place, dropping zero components.  Returns the new length, or -1 on overflow.
 template <int CAP>
 __device__ __forceinline__ int grow(double* e, int len, double b) {
+#pragma clang fp contract(off)
   double q = b;
   int out = 0;
   for (int i = 0; i < len; ++i) {
@@ -51,6 +56,7 @@ __device__ __forceinline__ int grow(double* e, int len, double b) {
 
 template <int CAP>
 __device__ __forceinline__ int expansion_sign(const double* e, int len) {
+#pragma clang fp contract(off)
   for (int i = len - 1; i >= 0; --i) {
     if (e[i] > 0.0) return 1;
     if (e[i] < 0.0) return -1;
@@ -60,6 +66,7 @@ __device__ __forceinline__ int expansion_sign(const double* e, int len) {
 
 // exact sign of det[b - a, c - a] in 2D; returns 2 on capacity overflow
 __device__ __noinline__ int orient2_exact(const double* a, const double* b, const double* c) {
+#pragma clang fp contract(off)
   constexpr int CAP = 40;
   double e[CAP];
   int len = 0;
@@ -89,6 +96,7 @@ __device__ __noinline__ int orient2_exact(const double* a, const double* b, cons
 // exact sign of det[b - a, c - a, d - a] in 3D; returns 2 on overflow
 __device__ __noinline__ int orient3_exact(const double* a, const double* b, const double* c,
                                           const double* d) {
+#pragma clang fp contract(off)
   constexpr int CAP = 96;
   double e[CAP];
   int len = 0;
@@ -121,6 +129,7 @@ __device__ __noinline__ int orient3_exact(const double* a, const double* b, cons
 // filtered sign of orient in 2D; *exact_used set when the exact path ran
 __device__ __forceinline__ int orient2_sign(const double* a, const double* b, const double* c,
                                             int* exact_used) {
+#pragma clang fp contract(off)
   const double ux = b[0] - a[0], uy = b[1] - a[1];
   const double vx = c[0] - a[0], vy = c[1] - a[1];
   const double t1 = ux * vy, t2 = uy * vx;
@@ -135,6 +144,7 @@ __device__ __forceinline__ int orient2_sign(const double* a, const double* b, co
 
 __device__ __forceinline__ int orient3_sign(const double* a, const double* b, const double* c,
                                             const double* d, int* exact_used) {
+#pragma clang fp contract(off)
   const double e00 = b[0] - a[0], e01 = b[1] - a[1], e02 = b[2] - a[2];
   const double e10 = c[0] - a[0], e11 = c[1] - a[1], e12 = c[2] - a[2];
   const double e20 = d[0] - a[0], e21 = d[1] - a[1], e22 = d[2] - a[2];

@@ -1,24 +1,910 @@
-// Preconditioned conjugate gradients for eq. GoFD-2 (placeholder entry points).
-#include "internal.h"
+// Preconditioned conjugate gradients for eq. GoFD-2 on the device.
+//
+//   K u = b,  K = I_J^T A_FD I_J,  b = h^{2s} I_J^T f_FD   (eq. GoFD-2, interior block)
+//
+// All vectors have N_v entries in the mesh's numbering; Dirichlet entries are
+// kept at zero, which is the interior block of the remark after eq. GoFD-2.
+// The CG scalars live on the device: every dot product is a per-block partial
+// sum followed by a fixed-order reduction in the last block to finish (so the
+// result does not depend on scheduling), and that block also forms alpha,
+// beta and the convergence test.  The host only reads the convergence flags
+// every few iterations, and those iterations are captured once in a hipGraph
+// and replayed.
+//
+// Preconditioners: none; D_h (CG on the symmetric form of eq. Ah-3); the IC(1)
+// factor of A_h^(5/9/27) (Section 3.4), applied with two sync-free triangular
+// solves in which each row waits on per-row ready flags of the rows it uses.
+//
+// FP32 mode: the grid-side arrays and FFTs of every K product inside CG run
+// in single precision; an outer loop in double precision recomputes the true
+// residual r = b - K x with a double-precision product, solves K d = r to a
+// modest relative tolerance and updates x += d (iterative refinement).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
 
-extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer, gofd_fdop, int, gofd_precond*, gofd_precond_info*) {
-  return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "not built yet");
+#include "internal.h"
+#include "precond_host.h"
+
+namespace {
+
+inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+constexpr int NB_DOT = 512;      // blocks of the plain vector kernels (fixed: deterministic sums)
+constexpr int BS = 256;
+constexpr int SCAT_G = 16;       // lanes per vertex in the I^T scatter
+constexpr long long SPIN_LIMIT = 1LL << 24;
+
+struct Scal {
+  double rho, alpha, beta, bb, rr, pq, rz, tol2;
+  int done, iters, status, pad;
+};
+
+enum { ST_OK = 0, ST_BREAKDOWN = 1, ST_SPIN = 2 };
+
+// fixed-order block reduction of one double per thread (BS threads)
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
 }
-extern "C" int gofd_precond_free(gofd_precond) { return GOFD_E_UNSUPPORTED; }
-extern "C" int gofd_precond_export(gofd_ctx ctx, gofd_precond, int32_t*, int32_t*, double*) {
-  return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "not built yet");
+
+// last block to finish sums partials[0..nb) in a fixed order; returns true in
+// that block (all threads), with the totals in out[]
+template <int NV>
+__device__ __forceinline__ bool finish_partials(double* __restrict__ partials, int nb, unsigned* __restrict__ counter,
+                                                double* out, double* sh) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == (unsigned)(nb - 1));
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  for (int c = 0; c < NV; ++c) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += BS) s += __hip_atomic_load(&partials[(long long)c * nb + i], __ATOMIC_RELAXED,
+                                                                       __HIP_MEMORY_SCOPE_AGENT);
+    out[c] = block_sum(s, sh);
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
 }
-extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer, gofd_fdop, gofd_precond, int, const double*, int, double,
-                          const gofd_solve_opts*, double*, gofd_solve_info*) {
-  return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "not built yet");
+
+// ---------------------------------------------------------------- kernels
+
+// b = c * mask * I^T f (grid f), or c * mask * D * f (vertex f); one rhs per blockIdx.y
+template <int G>
+__global__ __launch_bounds__(BS) void k_rhs_grid(const int* __restrict__ off, const int* __restrict__ node,
+                                                 const double* __restrict__ w, const double* __restrict__ f,
+                                                 long long nv, long long n_nodes, const double* __restrict__ mask,
+                                                 double c, double* __restrict__ b) {
+  const long long v = ((long long)blockIdx.x * BS + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const int rhs = blockIdx.y;
+  if (v >= nv) return;
+  const double* fr = f + rhs * n_nodes;
+  double acc = 0.0;
+  for (int i = off[v] + lane; i < off[v + 1]; i += G) acc += w[i] * fr[node[i]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (lane == 0) b[rhs * nv + v] = c * mask[v] * acc;
 }
-extern "C" int gofd_solve_batched(gofd_ctx ctx, int, const gofd_transfer*, const gofd_fdop*, const gofd_precond*,
-                                  const int*, const double* const*, int, double, const gofd_solve_opts*,
-                                  double* const*, gofd_solve_info*) {
-  return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "not built yet");
+
+__global__ void k_rhs_vertex(const double* __restrict__ f, const double* __restrict__ D, const double* __restrict__ mask,
+                             long long nv, double c, double* __restrict__ b) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (i < nv) b[rhs * nv + i] = c * mask[i] * D[i] * f[rhs * nv + i];
 }
+
+// CG start from x = 0: r = b, z = M_diag r, p = z; rho = r.z, bb = b.b
+__global__ __launch_bounds__(BS) void k_start(const double* __restrict__ b, double* __restrict__ x,
+                                              double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
+                                              const double* __restrict__ dinv, long long nv, Scal* __restrict__ sc,
+                                              double tol, double* __restrict__ partials, unsigned* __restrict__ counters,
+                                              int zfilled) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.y;
+  const long long o = rhs * nv;
+  double s_rz = 0.0, s_bb = 0.0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
+    const double bi = b[o + i];
+    x[o + i] = 0.0;
+    r[o + i] = bi;
+    double zi = zfilled ? z[o + i] : (dinv ? bi * dinv[i] : bi);
+    if (!zfilled) z[o + i] = zi;
+    p[o + i] = zi;
+    s_rz += bi * zi;
+    s_bb += bi * bi;
+  }
+  s_rz = block_sum(s_rz, sh);
+  s_bb = block_sum(s_bb, sh);
+  double* part = partials + (long long)rhs * 2 * gridDim.x;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_rz;
+    part[gridDim.x + blockIdx.x] = s_bb;
+  }
+  double tot[2];
+  if (finish_partials<2>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
+    Scal& S = sc[rhs];
+    S.rho = tot[0];
+    S.bb = tot[1];
+    S.rr = tot[1];
+    S.tol2 = tol * tol * tot[1];
+    S.iters = 0;
+    S.status = ST_OK;
+    S.done = (tot[1] == 0.0) ? 1 : 0;
+    if (!(tot[0] > 0.0) && tot[1] > 0.0) {
+      S.status = ST_BREAKDOWN;
+      S.done = 1;
+    }
+  }
+}
+
+// q = mask * I^T y; partial p.q; last block: alpha = rho / (p.q)
+template <typename Y, int G>
+__global__ __launch_bounds__(BS) void k_scatter_dot(const int* __restrict__ off, const int* __restrict__ node,
+                                                    const double* __restrict__ w, const Y* __restrict__ y,
+                                                    long long nv, long long n_nodes, const double* __restrict__ mask,
+                                                    const double* __restrict__ p, double* __restrict__ q,
+                                                    Scal* __restrict__ sc, double* __restrict__ partials,
+                                                    unsigned* __restrict__ counters) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.y;
+  if (sc[rhs].done) return;
+  const long long v = ((long long)blockIdx.x * BS + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  double contrib = 0.0;
+  if (v < nv) {
+    const Y* yr = y + rhs * n_nodes;
+    double acc = 0.0;
+    for (int i = off[v] + lane; i < off[v + 1]; i += G) acc += w[i] * (double)yr[node[i]];
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) {
+      const double qv = mask[v] * acc;
+      q[rhs * nv + v] = qv;
+      contrib = qv * p[rhs * nv + v];
+    }
+  }
+  const double s = block_sum(contrib, sh);
+  double* part = partials + (long long)rhs * gridDim.x;
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  double tot[1];
+  if (finish_partials<1>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
+    Scal& S = sc[rhs];
+    S.pq = tot[0];
+    if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
+      S.status = ST_BREAKDOWN;
+      S.done = 1;
+    } else {
+      S.alpha = S.rho / tot[0];
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q, rr = r.r; with a diagonal (or no) preconditioner
+// also z = M r, rz = r.z, beta, rho; convergence flag
+__global__ __launch_bounds__(BS) void k_update(double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               const double* __restrict__ dinv, int diag_kind, long long nv,
+                                               Scal* __restrict__ sc, double* __restrict__ partials,
+                                               unsigned* __restrict__ counters) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.y;
+  if (sc[rhs].done) return;
+  const double alpha = sc[rhs].alpha;
+  const long long o = rhs * nv;
+  double s_rr = 0.0, s_rz = 0.0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
+    x[o + i] += alpha * p[o + i];
+    const double ri = r[o + i] - alpha * q[o + i];
+    r[o + i] = ri;
+    s_rr += ri * ri;
+    if (diag_kind >= 0) {
+      const double zi = diag_kind ? ri * dinv[i] : ri;
+      z[o + i] = zi;
+      s_rz += ri * zi;
+    }
+  }
+  s_rr = block_sum(s_rr, sh);
+  s_rz = block_sum(s_rz, sh);
+  double* part = partials + (long long)rhs * 2 * gridDim.x;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_rr;
+    part[gridDim.x + blockIdx.x] = s_rz;
+  }
+  double tot[2];
+  if (finish_partials<2>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
+    Scal& S = sc[rhs];
+    S.rr = tot[0];
+    S.iters += 1;
+    if (!isfinite(tot[0])) {
+      S.status = ST_BREAKDOWN;
+      S.done = 1;
+    } else if (tot[0] <= S.tol2) {
+      S.done = 1;
+    } else if (diag_kind >= 0) {
+      S.beta = tot[1] / S.rho;
+      S.rho = tot[1];
+    }
+  }
+}
+
+// rz = r.z after a triangular-solve preconditioner; beta, rho
+__global__ __launch_bounds__(BS) void k_dot_rz(const double* __restrict__ r, const double* __restrict__ z, long long nv,
+                                               Scal* __restrict__ sc, double* __restrict__ partials,
+                                               unsigned* __restrict__ counters, int first) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.y;
+  if (sc[rhs].done) return;
+  const long long o = rhs * nv;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS)
+    s += r[o + i] * z[o + i];
+  s = block_sum(s, sh);
+  double* part = partials + (long long)rhs * gridDim.x;
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  double tot[1];
+  if (finish_partials<1>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
+    Scal& S = sc[rhs];
+    if (first) {
+      S.rho = tot[0];
+    } else {
+      S.beta = tot[0] / S.rho;
+      S.rho = tot[0];
+    }
+    if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
+      S.status = ST_BREAKDOWN;
+      S.done = 1;
+    }
+  }
+}
+
+__global__ void k_pupdate(double* __restrict__ p, const double* __restrict__ z, long long nv,
+                          const Scal* __restrict__ sc) {
+  const int rhs = blockIdx.y;
+  if (sc[rhs].done) return;
+  const double beta = sc[rhs].beta;
+  const long long o = rhs * nv;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS)
+    p[o + i] = z[o + i] + beta * p[o + i];
+}
+
+__global__ void k_copy_p(double* __restrict__ p, const double* __restrict__ z, long long nv) {
+  const int rhs = blockIdx.y;
+  const long long o = rhs * nv;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS)
+    p[o + i] = z[o + i];
+}
+
+// r = b - q (q = K x), rr and bb; used by the refinement loop (FP64 residual)
+__global__ __launch_bounds__(BS) void k_residual(const double* __restrict__ b, const double* __restrict__ q,
+                                                 double* __restrict__ r, long long nv, double* __restrict__ out2,
+                                                 double* __restrict__ partials, unsigned* __restrict__ counters) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.y;
+  const long long o = rhs * nv;
+  double s_rr = 0.0, s_bb = 0.0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
+    const double ri = b[o + i] - q[o + i];
+    r[o + i] = ri;
+    s_rr += ri * ri;
+    s_bb += b[o + i] * b[o + i];
+  }
+  s_rr = block_sum(s_rr, sh);
+  s_bb = block_sum(s_bb, sh);
+  double* part = partials + (long long)rhs * 2 * gridDim.x;
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s_rr;
+    part[gridDim.x + blockIdx.x] = s_bb;
+  }
+  double tot[2];
+  if (finish_partials<2>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
+    out2[2 * rhs] = tot[0];
+    out2[2 * rhs + 1] = tot[1];
+  }
+}
+
+__global__ void k_axpy_mask(double* __restrict__ x, const double* __restrict__ d, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += d[i];
+}
+
+// plain scatter for K x (no dot), masked
+template <int G>
+__global__ __launch_bounds__(BS) void k_scatter_plain(const int* __restrict__ off, const int* __restrict__ node,
+                                                      const double* __restrict__ w, const double* __restrict__ y,
+                                                      long long nv, long long n_nodes, const double* __restrict__ mask,
+                                                      double* __restrict__ q) {
+  const long long v = ((long long)blockIdx.x * BS + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  const int rhs = blockIdx.y;
+  if (v >= nv) return;
+  const double* yr = y + rhs * n_nodes;
+  double acc = 0.0;
+  for (int i = off[v] + lane; i < off[v + 1]; i += G) acc += w[i] * yr[node[i]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+  if (lane == 0) q[rhs * nv + v] = mask[v] * acc;
+}
+
+// ---------------------------------------------------------------- triangular solves
+//
+// One 64-lane wavefront per row.  Rows are taken in dependency order from an
+// atomic counter, so every row a wave waits on was taken earlier by a running
+// wave; lanes stride through the row, each waiting on the ready flag of its
+// column (acquire), then the partial sums are combined in a fixed order.  A
+// spin limit turns a lost flag into an error instead of a hang.
+
+__global__ void k_tri_begin(int* __restrict__ ctl) {
+  // ctl[0]: forward counter, ctl[1]: backward counter, ctl[2]: epoch, ctl[3]: error
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+    ctl[2] = ctl[2] + 2;
+  }
+}
+
+template <bool LOWER>
+__global__ __launch_bounds__(256) void k_trsv(const int* __restrict__ ptr, const int* __restrict__ col,
+                                              const double* __restrict__ val, const double* __restrict__ rhs_in,
+                                              double* __restrict__ out, int* __restrict__ ready, int* __restrict__ ctl,
+                                              int n, long long stride, int nrhs, const Scal* __restrict__ sc) {
+  const int lane = threadIdx.x & 63;
+  const int epoch = __hip_atomic_load(&ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + (LOWER ? 1 : 2);
+  int* counter = &ctl[LOWER ? 0 : 1];
+  while (true) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(counter, 1);
+    t = __shfl(t, 0);
+    if (t >= n) break;
+    const int row = LOWER ? t : n - 1 - t;
+    const int b = ptr[row], e = ptr[row + 1];
+    // lower: diagonal last; upper: diagonal first
+    const int dpos = LOWER ? e - 1 : b;
+    const int lo = LOWER ? b : b + 1, hi = LOWER ? e - 1 : e;
+    for (int i = lo + lane; i < hi; i += 64) {
+      const int c = col[i];
+      long long spins = 0;
+      while (__hip_atomic_load(&ready[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        if (++spins > SPIN_LIMIT) {
+          atomicOr(&ctl[3], 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const double dv = val[dpos];
+    for (int k = 0; k < nrhs; ++k) {
+      if (sc[k].done) continue;
+      double s = 0.0;
+      for (int i = lo + lane; i < hi; i += 64)
+        s += val[i] * __hip_atomic_load(&out[k * stride + col[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (lane == 0) {
+        const double v = (rhs_in[k * stride + row] - s) / dv;
+        __hip_atomic_store(&out[k * stride + row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (lane == 0) __hip_atomic_store(&ready[row], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_fill_d(double* __restrict__ p, long long n, double v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- preconditioner handle
+
+struct gofd_precond_s {
+  int kind = 0;
+  int64_t nv = 0;
+  DevBuf Lptr, Lcol, Lval, Uptr, Ucol, Uval;
+  DevBuf ready;    // int[nv]
+  DevBuf ctl;      // int[4]
+  std::vector<int32_t> hLptr, hLcol;
+  std::vector<double> hLval;
+  gofd_precond_info info{};
+};
+
+static int host_transfer(gofd_ctx_s* ctx, gofd_transfer_s* tr, HostTransfer& h) {
+  hipStream_t st = ctx->stream;
+  h.d = tr->d;
+  h.W = tr->W;
+  h.nv = tr->nv;
+  h.n_nodes = tr->n_nodes;
+  h.elem.resize(tr->n_nodes);
+  h.elems = tr->elems_host;
+  h.bnd = tr->bmask_host;
+  h.csc_off.resize(tr->nv + 1);
+  h.csc_node.resize(tr->nnz);
+  h.csc_w.resize(tr->nnz);
+  h.node_w.resize(tr->n_nodes * (tr->d + 1));
+  DevBuf tmp;
+  GOFD_TRY(dev_reserve(ctx, tmp, sizeof(double) * tr->n_nodes * (tr->d + 1)));
+  GOFD_TRY(gofd_transfer_export(ctx, tr, GOFD_TR_ELL_WEIGHTS, tmp.p));
+  HIP_TRY(ctx, hipMemcpyAsync(h.node_w.data(), tmp.p, sizeof(double) * h.node_w.size(), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(h.elem.data(), tr->elem.p, sizeof(int32_t) * tr->n_nodes, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(h.csc_off.data(), tr->csc_off.p, sizeof(int32_t) * (tr->nv + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(h.csc_node.data(), tr->csc_node.p, sizeof(int32_t) * tr->nnz, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(h.csc_w.data(), tr->csc_w.p, sizeof(double) * tr->nnz, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return GOFD_OK;
+}
+
+extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int kind, gofd_precond* out,
+                                   gofd_precond_info* info) {
+  if (!ctx || !tr || !op || !out) return gofd_fail(ctx, GOFD_E_ARG, "null argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  auto* pc = new (std::nothrow) gofd_precond_s();
+  if (!pc) return GOFD_E_OOM;
+  std::unique_ptr<gofd_precond_s> guard(pc);
+  pc->kind = kind;
+  pc->nv = tr->nv;
+  if (kind == GOFD_PC_NONE || kind == GOFD_PC_DIAG) {
+    *out = guard.release();
+    if (info) *info = pc->info;
+    return GOFD_OK;
+  }
+  int npts = 0;
+  if (kind == GOFD_PC_IC1_5 && tr->d == 2) npts = 5;
+  if (kind == GOFD_PC_IC1_9 && tr->d == 2) npts = 9;
+  if (kind == GOFD_PC_IC1_27 && tr->d == 3) npts = 27;
+  if (!npts) return gofd_fail(ctx, GOFD_E_ARG, "preconditioner kind does not match the dimension");
+  HostTransfer ht;
+  GOFD_TRY(host_transfer(ctx, tr, ht));
+  HostCsr A;
+  if (!assemble_pattern_matrix(ht, op->T_host.data(), npts, A))
+    return gofd_fail(ctx, GOFD_E_ARG, "pattern assembly failed");
+  std::vector<int64_t> Lptr;
+  std::vector<int32_t> Lcol;
+  ic_symbolic(A, 1, Lptr, Lcol);
+  std::vector<double> Lval;
+  double alpha = 0.0;
+  while (!ic_numeric(A, alpha, Lptr, Lcol, Lval)) {
+    alpha = alpha == 0.0 ? 1e-3 : 2.0 * alpha;
+    if (alpha > 1e3) return gofd_fail(ctx, GOFD_E_BREAKDOWN, "incomplete Cholesky failed for every shift");
+  }
+  const int64_t n = tr->nv, nnz = (int64_t)Lcol.size();
+  if (nnz >= (1LL << 31)) return gofd_fail(ctx, GOFD_E_OOM, "factor too large");
+  pc->hLptr.assign(Lptr.begin(), Lptr.end());
+  pc->hLcol = Lcol;
+  pc->hLval = Lval;
+  // transpose: U = L^T in CSR (diagonal first in every row)
+  std::vector<int32_t> Uptr(n + 1, 0), Ucol(nnz);
+  std::vector<double> Uval(nnz);
+  for (int64_t e = 0; e < nnz; ++e) Uptr[Lcol[e] + 1]++;
+  for (int64_t i = 0; i < n; ++i) Uptr[i + 1] += Uptr[i];
+  {
+    std::vector<int32_t> cur(Uptr.begin(), Uptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t e = Lptr[i]; e < Lptr[i + 1]; ++e) {
+        const int32_t c = Lcol[e];
+        Ucol[cur[c]] = (int32_t)i;
+        Uval[cur[c]++] = Lval[e];
+      }
+  }
+  // dependency depth of the forward solve (statistics)
+  {
+    std::vector<int> lev(n, 0);
+    int depth = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      int l = 0;
+      for (int64_t e = Lptr[i]; e < Lptr[i + 1] - 1; ++e) l = std::max(l, lev[Lcol[e]] + 1);
+      lev[i] = l;
+      depth = std::max(depth, l + 1);
+    }
+    pc->info.levels = depth;
+  }
+  hipStream_t st = ctx->stream;
+  GOFD_TRY(dev_reserve(ctx, pc->Lptr, sizeof(int32_t) * (n + 1)));
+  GOFD_TRY(dev_reserve(ctx, pc->Lcol, sizeof(int32_t) * nnz));
+  GOFD_TRY(dev_reserve(ctx, pc->Lval, sizeof(double) * nnz));
+  GOFD_TRY(dev_reserve(ctx, pc->Uptr, sizeof(int32_t) * (n + 1)));
+  GOFD_TRY(dev_reserve(ctx, pc->Ucol, sizeof(int32_t) * nnz));
+  GOFD_TRY(dev_reserve(ctx, pc->Uval, sizeof(double) * nnz));
+  GOFD_TRY(dev_reserve(ctx, pc->ready, sizeof(int32_t) * n));
+  GOFD_TRY(dev_reserve(ctx, pc->ctl, sizeof(int32_t) * 8));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Lptr.p, pc->hLptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Lcol.p, Lcol.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Lval.p, Lval.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Uptr.p, Uptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Ucol.p, Ucol.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Uval.p, Uval.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemsetAsync(pc->ready.p, 0, sizeof(int32_t) * n, st));
+  HIP_TRY(ctx, hipMemsetAsync(pc->ctl.p, 0, sizeof(int32_t) * 8, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  pc->info.shift = alpha;
+  pc->info.nnz_L = nnz;
+  pc->info.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = pc->info;
+  *out = guard.release();
+  return GOFD_OK;
+}
+
+extern "C" int gofd_precond_free(gofd_precond pc) {
+  if (!pc) return GOFD_E_ARG;
+  (void)hipDeviceSynchronize();
+  delete pc;
+  return GOFD_OK;
+}
+
+extern "C" int gofd_precond_export(gofd_ctx ctx, gofd_precond pc, int32_t* rowptr, int32_t* cols, double* vals) {
+  if (!ctx || !pc || !rowptr || !cols || !vals) return gofd_fail(ctx, GOFD_E_ARG, "null argument");
+  if (pc->hLptr.empty()) return gofd_fail(ctx, GOFD_E_ARG, "preconditioner has no factor");
+  std::memcpy(rowptr, pc->hLptr.data(), sizeof(int32_t) * pc->hLptr.size());
+  std::memcpy(cols, pc->hLcol.data(), sizeof(int32_t) * pc->hLcol.size());
+  std::memcpy(vals, pc->hLval.data(), sizeof(double) * pc->hLval.size());
+  return GOFD_OK;
+}
+
+// ---------------------------------------------------------------- solve driver
+
+namespace {
+
+struct Problem {
+  gofd_transfer_s* tr;
+  gofd_fdop_s* op;
+  gofd_precond_s* pc;   // may be null
+  int nrhs;
+};
+
+struct Work {
+  DevBuf x, r, z, p, q, b, xr, dvec, grid;
+  DevBuf scal, partials, counters, out2;
+  int nrhs = 0;
+};
+
+int reserve_work(gofd_ctx_s* ctx, Work& w, int64_t nv, int64_t n_nodes, int nrhs) {
+  const size_t vb = sizeof(double) * nv * nrhs;
+  for (DevBuf* b : {&w.x, &w.r, &w.z, &w.p, &w.q, &w.b, &w.xr, &w.dvec}) GOFD_TRY(dev_reserve(ctx, *b, vb));
+  GOFD_TRY(dev_reserve(ctx, w.grid, sizeof(double) * n_nodes * nrhs));
+  GOFD_TRY(dev_reserve(ctx, w.scal, sizeof(Scal) * nrhs));
+  const long long nb_scatter = grid1(nv * SCAT_G, BS);
+  GOFD_TRY(dev_reserve(ctx, w.partials, sizeof(double) * 2 * std::max<long long>(nb_scatter, NB_DOT) * nrhs));
+  GOFD_TRY(dev_reserve(ctx, w.counters, sizeof(unsigned) * nrhs));
+  GOFD_TRY(dev_reserve(ctx, w.out2, sizeof(double) * 2 * nrhs));
+  HIP_TRY(ctx, hipMemsetAsync(w.counters.p, 0, sizeof(unsigned) * nrhs, ctx->stream));
+  w.nrhs = nrhs;
+  return GOFD_OK;
+}
+
+// q = K v (masked), grid workspace in w.grid; optional dot with p into alpha
+int apply_K(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* v, bool fp32, bool with_dot) {
+  gofd_transfer_s* tr = P.tr;
+  GatherSpec g;
+  g.tr = tr;
+  g.u = v;
+  g.mask = tr->imask.as<double>();
+  GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32));
+  dim3 gs(grid1(tr->nv * SCAT_G, BS), P.nrhs);
+  hipStream_t st = ctx->stream;
+  if (with_dot) {
+    if (fp32)
+      hipLaunchKernelGGL((k_scatter_dot<float, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
+                         tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<float>(), (long long)tr->nv,
+                         (long long)tr->n_nodes, tr->imask.as<double>(), w.p.as<double>(), w.q.as<double>(),
+                         w.scal.as<Scal>(), w.partials.as<double>(), w.counters.as<unsigned>());
+    else
+      hipLaunchKernelGGL((k_scatter_dot<double, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
+                         tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv,
+                         (long long)tr->n_nodes, tr->imask.as<double>(), w.p.as<double>(), w.q.as<double>(),
+                         w.scal.as<Scal>(), w.partials.as<double>(), w.counters.as<unsigned>());
+  } else {
+    if (fp32) return gofd_fail(ctx, GOFD_E_ARG, "internal: plain product is double only");
+    hipLaunchKernelGGL((k_scatter_plain<SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(), tr->csc_node.as<int>(),
+                       tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv, (long long)tr->n_nodes,
+                       tr->imask.as<double>(), w.q.as<double>());
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
+}
+
+int precond_apply(gofd_ctx_s* ctx, const Problem& P, Work& w) {
+  gofd_precond_s* pc = P.pc;
+  hipStream_t st = ctx->stream;
+  const int n = (int)P.tr->nv;
+  hipLaunchKernelGGL(k_tri_begin, dim3(1), dim3(64), 0, st, pc->ctl.as<int>());
+  // waves to keep resident: enough to cover the critical path, few enough to stay resident
+  const int nblk = std::min<long long>(grid1((long long)n * 64, 256), (long long)ctx->num_cu * 8);
+  hipLaunchKernelGGL((k_trsv<true>), dim3(nblk), dim3(256), 0, st, pc->Lptr.as<int>(), pc->Lcol.as<int>(),
+                     pc->Lval.as<double>(), w.r.as<double>(), w.dvec.as<double>(), pc->ready.as<int>(),
+                     pc->ctl.as<int>(), n, (long long)n, P.nrhs, w.scal.as<Scal>());
+  hipLaunchKernelGGL((k_trsv<false>), dim3(nblk), dim3(256), 0, st, pc->Uptr.as<int>(), pc->Ucol.as<int>(),
+                     pc->Uval.as<double>(), w.dvec.as<double>(), w.z.as<double>(), pc->ready.as<int>(),
+                     pc->ctl.as<int>(), n, (long long)n, P.nrhs, w.scal.as<Scal>());
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
+}
+
+bool is_ic(const gofd_precond_s* pc) {
+  return pc && (pc->kind == GOFD_PC_IC1_5 || pc->kind == GOFD_PC_IC1_9 || pc->kind == GOFD_PC_IC1_27);
+}
+
+// one CG iteration (after start)
+int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32) {
+  hipStream_t st = ctx->stream;
+  const long long nv = P.tr->nv;
+  GOFD_TRY(apply_K(ctx, P, w, w.p.as<double>(), fp32, true));
+  const int diag_kind = is_ic(P.pc) ? -1 : ((P.pc && P.pc->kind == GOFD_PC_DIAG) ? 1 : 0);
+  dim3 gd(NB_DOT, P.nrhs);
+  hipLaunchKernelGGL(k_update, gd, dim3(BS), 0, st, w.x.as<double>(), w.r.as<double>(), w.z.as<double>(),
+                     w.p.as<double>(), w.q.as<double>(), P.tr->dscale.as<double>(), diag_kind, nv, w.scal.as<Scal>(),
+                     w.partials.as<double>(), w.counters.as<unsigned>());
+  if (diag_kind < 0) {
+    GOFD_TRY(precond_apply(ctx, P, w));
+    hipLaunchKernelGGL(k_dot_rz, gd, dim3(BS), 0, st, w.r.as<double>(), w.z.as<double>(), nv, w.scal.as<Scal>(),
+                       w.partials.as<double>(), w.counters.as<unsigned>(), 0);
+  }
+  hipLaunchKernelGGL(k_pupdate, gd, dim3(BS), 0, st, w.p.as<double>(), w.z.as<double>(), nv, w.scal.as<Scal>());
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
+}
+
+// CG from x = 0 on right-hand sides w.b; result in w.x.  Returns per-rhs
+// iterations and status through hs (host Scal copies).
+int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, int max_iter, int check_every,
+            bool use_graph, std::vector<Scal>& hs, double* history) {
+  hipStream_t st = ctx->stream;
+  const long long nv = P.tr->nv;
+  dim3 gd(NB_DOT, P.nrhs);
+  const int diag_kind = is_ic(P.pc) ? -1 : ((P.pc && P.pc->kind == GOFD_PC_DIAG) ? 1 : 0);
+  GOFD_TRY(conv_prepare(ctx, P.op, P.nrhs));
+  if (diag_kind < 0) {
+    // z = M^{-1} b before the start kernel (scalars must mark every rhs as active)
+    hipLaunchKernelGGL(k_fill_d, dim3(grid1(sizeof(Scal) / 8 * P.nrhs, 64)), dim3(64), 0, st, w.scal.as<double>(),
+                       (long long)(sizeof(Scal) / 8 * P.nrhs), 0.0);
+    HIP_TRY(ctx, hipMemcpyAsync(w.r.p, w.b.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
+    GOFD_TRY(precond_apply(ctx, P, w));
+  }
+  hipLaunchKernelGGL(k_start, gd, dim3(BS), 0, st, w.b.as<double>(), w.x.as<double>(), w.r.as<double>(),
+                     w.z.as<double>(), w.p.as<double>(), diag_kind == 1 ? P.tr->dscale.as<double>() : nullptr, nv,
+                     w.scal.as<Scal>(), tol, w.partials.as<double>(), w.counters.as<unsigned>(), diag_kind < 0 ? 1 : 0);
+  HIP_TRY(ctx, hipGetLastError());
+  hs.resize(P.nrhs);
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      use_graph = false;
+    } else {
+      int rc = GOFD_OK;
+      for (int k = 0; k < check_every && rc == GOFD_OK; ++k) rc = cg_iteration(ctx, P, w, fp32);
+      hipError_t e = hipStreamEndCapture(st, &graph);
+      if (rc != GOFD_OK) return rc;
+      if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        graph = nullptr;
+        exec = nullptr;
+        use_graph = false;
+      }
+    }
+  }
+  int it = 0;
+  int rc = GOFD_OK;
+  std::vector<Scal> tmp(P.nrhs);
+  if (history) {
+    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    history[0] = tmp[0].bb > 0 ? 1.0 : 0.0;
+  }
+  while (it < max_iter) {
+    const int chunk = history ? 1 : check_every;
+    if (use_graph && !history) {
+      if (hipGraphLaunch(exec, st) != hipSuccess) {
+        rc = gofd_fail(ctx, GOFD_E_HIP, "graph launch failed");
+        break;
+      }
+    } else {
+      for (int k = 0; k < chunk && rc == GOFD_OK; ++k) rc = cg_iteration(ctx, P, w, fp32);
+      if (rc != GOFD_OK) break;
+    }
+    it += chunk;
+    if (hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = gofd_fail(ctx, GOFD_E_HIP, "reading solver state failed");
+      break;
+    }
+    if (history && it <= max_iter) history[it] = tmp[0].bb > 0 ? std::sqrt(tmp[0].rr / tmp[0].bb) : 0.0;
+    bool all = true;
+    for (int k = 0; k < P.nrhs; ++k) all = all && tmp[k].done;
+    if (all) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (rc != GOFD_OK) return rc;
+  HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+  if (P.pc && is_ic(P.pc)) {
+    int ctl[4];
+    HIP_TRY(ctx, hipMemcpyAsync(ctl, P.pc->ctl.p, sizeof(ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (ctl[3]) return gofd_fail(ctx, GOFD_E_HIP, "triangular solve waited too long on a dependency");
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return GOFD_OK;
+}
+
+// true residual r = b - K x in double precision; returns ||r||^2 and ||b||^2 per rhs
+int true_residual(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* x, const double* b, double* r,
+                  std::vector<double>& rr, std::vector<double>& bb) {
+  GOFD_TRY(conv_prepare(ctx, P.op, P.nrhs));
+  GOFD_TRY(apply_K(ctx, P, w, x, false, false));
+  dim3 gd(NB_DOT, P.nrhs);
+  hipLaunchKernelGGL(k_residual, gd, dim3(BS), 0, ctx->stream, b, w.q.as<double>(), r, (long long)P.tr->nv,
+                     w.out2.as<double>(), w.partials.as<double>(), w.counters.as<unsigned>());
+  std::vector<double> h(2 * P.nrhs);
+  HIP_TRY(ctx, hipMemcpyAsync(h.data(), w.out2.p, sizeof(double) * 2 * P.nrhs, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  rr.resize(P.nrhs);
+  bb.resize(P.nrhs);
+  for (int k = 0; k < P.nrhs; ++k) {
+    rr[k] = h[2 * k];
+    bb[k] = h[2 * k + 1];
+  }
+  return GOFD_OK;
+}
+
+int form_rhs(gofd_ctx_s* ctx, const Problem& P, const double* f, int f_loc, double* b) {
+  gofd_transfer_s* tr = P.tr;
+  hipStream_t st = ctx->stream;
+  if (f_loc == GOFD_F_GRID) {
+    dim3 gs(grid1(tr->nv * SCAT_G, BS), P.nrhs);
+    hipLaunchKernelGGL((k_rhs_grid<SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(), tr->csc_node.as<int>(),
+                       tr->csc_w.as<double>(), f, (long long)tr->nv, (long long)tr->n_nodes, tr->imask.as<double>(),
+                       P.op->h2s, b);
+  } else if (f_loc == GOFD_F_VERTEX) {
+    dim3 gs(grid1(tr->nv, BS), P.nrhs);
+    hipLaunchKernelGGL(k_rhs_vertex, gs, dim3(BS), 0, st, f, tr->D.as<double>(), tr->imask.as<double>(),
+                       (long long)tr->nv, P.op->h2s, b);
+  } else {
+    return gofd_fail(ctx, GOFD_E_ARG, "f_loc must be GOFD_F_GRID or GOFD_F_VERTEX");
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
+}
+
+}  // namespace
+
+// Solve K u = b for nrhs right-hand sides already formed in w.b; u -> u_out.
+static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, const gofd_solve_opts* o,
+                        double* u_out, gofd_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int mode = o ? o->mode : GOFD_MODE_FP64;
+  const int max_iter = (o && o->max_iter > 0) ? o->max_iter : 20000;
+  const int check = (o && o->check_every > 0) ? o->check_every : 8;
+  const bool graph = o ? o->use_graph != 0 : true;
+  double* history = o ? o->history : nullptr;
+  const long long nv = P.tr->nv;
+  hipStream_t st = ctx->stream;
+  std::vector<Scal> hs;
+  std::vector<int> iters(P.nrhs, 0), refs(P.nrhs, 0), status(P.nrhs, GOFD_OK);
+  std::vector<double> rel(P.nrhs, 0.0);
+  int rc = GOFD_OK;
+  if (mode == GOFD_MODE_FP64) {
+    rc = pcg_run(ctx, P, w, tol, false, max_iter, check, graph, hs, history);
+    if (rc != GOFD_OK) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(u_out, w.x.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
+    for (int k = 0; k < P.nrhs; ++k) {
+      iters[k] = hs[k].iters;
+      if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
+      else if (!hs[k].done) status[k] = GOFD_E_NOT_CONVERGED;
+    }
+  } else if (mode == GOFD_MODE_FP32_REFINE) {
+    const double inner = (o && o->inner_tol > 0) ? o->inner_tol : 1e-5;
+    const int max_ref = (o && o->max_refine > 0) ? o->max_refine : 30;
+    // xr = 0; r = b; loop
+    DevBuf bsave;
+    GOFD_TRY(dev_reserve(ctx, bsave, sizeof(double) * nv * P.nrhs));
+    HIP_TRY(ctx, hipMemcpyAsync(bsave.p, w.b.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_fill_d, dim3(grid1(nv * P.nrhs, 256)), dim3(256), 0, st, w.xr.as<double>(),
+                       (long long)(nv * P.nrhs), 0.0);
+    std::vector<double> rr, bb;
+    std::vector<char> conv(P.nrhs, 0);
+    int total_it = 0;
+    for (int ref = 0; ref <= max_ref; ++ref) {
+      // true residual of the current iterate (b - K xr); first pass has xr = 0
+      GOFD_TRY(true_residual(ctx, P, w, w.xr.as<double>(), bsave.as<double>(), w.b.as<double>(), rr, bb));
+      bool all = true;
+      for (int k = 0; k < P.nrhs; ++k) {
+        rel[k] = bb[k] > 0 ? std::sqrt(rr[k] / bb[k]) : 0.0;
+        if (rel[k] <= tol) conv[k] = 1;
+        all = all && conv[k];
+      }
+      if (all || ref == max_ref || total_it >= max_iter) break;
+      // correction: K d = r with single-precision grid products
+      rc = pcg_run(ctx, P, w, inner, true, max_iter - total_it, check, graph, hs, nullptr);
+      if (rc != GOFD_OK) return rc;
+      int mx = 0;
+      for (int k = 0; k < P.nrhs; ++k) {
+        if (!conv[k]) {
+          iters[k] += hs[k].iters;
+          refs[k] += 1;
+        }
+        mx = std::max(mx, hs[k].iters);
+        if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
+      }
+      total_it += mx;
+      hipLaunchKernelGGL(k_axpy_mask, dim3(grid1(nv * P.nrhs, 256)), dim3(256), 0, st, w.xr.as<double>(),
+                         w.x.as<double>(), (long long)(nv * P.nrhs));
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(u_out, w.xr.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
+    for (int k = 0; k < P.nrhs; ++k)
+      if (!conv[k] && status[k] == GOFD_OK) status[k] = GOFD_E_NOT_CONVERGED;
+    // restore b for callers that inspect it
+    HIP_TRY(ctx, hipMemcpyAsync(w.b.p, bsave.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+  } else {
+    return gofd_fail(ctx, GOFD_E_ARG, "unknown solve mode");
+  }
+  // final relative residual in double precision
+  std::vector<double> rr, bb;
+  GOFD_TRY(true_residual(ctx, P, w, u_out, w.b.as<double>(), w.r.as<double>(), rr, bb));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  int worst = GOFD_OK;
+  for (int k = 0; k < P.nrhs; ++k) {
+    rel[k] = bb[k] > 0 ? std::sqrt(rr[k] / bb[k]) : 0.0;
+    if (info) {
+      info[k].iterations = iters[k];
+      info[k].refinements = refs[k];
+      info[k].rel_residual = rel[k];
+      info[k].time_ms = ms;
+      info[k].status = status[k];
+    }
+    if (status[k] != GOFD_OK && worst == GOFD_OK) worst = status[k];
+  }
+  if (worst != GOFD_OK) return gofd_fail(ctx, worst, "solve did not reach the tolerance for every right-hand side");
+  return GOFD_OK;
+}
+
+static bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op) {
+  return tr->d == op->d && tr->N == op->N && tr->R == op->R && tr->center[0] == op->center[0] &&
+         tr->center[1] == op->center[1] && tr->center[2] == op->center[2];
+}
+
+extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, int nrhs, const double* f,
+                          int f_loc, double tol, const gofd_solve_opts* opts, double* u, gofd_solve_info* info) {
+  if (!ctx || !tr || !op || !f || !u || nrhs < 1) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  if (!same_grid(tr, op)) return gofd_fail(ctx, GOFD_E_ARG, "transfer and operator use different grids");
+  if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
+  if (pc && pc->nv != tr->nv) return gofd_fail(ctx, GOFD_E_ARG, "preconditioner built for another mesh");
+  WorkStream ws(ctx);
+  Problem P{tr, op, pc, nrhs};
+  Work w;
+  GOFD_TRY(reserve_work(ctx, w, tr->nv, tr->n_nodes, nrhs));
+  GOFD_TRY(form_rhs(ctx, P, f, f_loc, w.b.as<double>()));
+  return solve_system(ctx, P, w, tol, opts, u, info);
+}
+
+extern "C" int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* trs, const gofd_fdop* ops,
+                                  const gofd_precond* pcs, const int* nrhs, const double* const* f, int f_loc,
+                                  double tol, const gofd_solve_opts* opts, double* const* u, gofd_solve_info* info) {
+  if (!ctx || nprob < 1 || !trs || !ops || !nrhs || !f || !u) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  int off = 0;
+  for (int q = 0; q < nprob; ++q) {
+    GOFD_TRY(gofd_solve(ctx, trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q], f[q], f_loc, tol, opts, u[q],
+                        info ? info + off : nullptr));
+    off += nrhs[q];
+  }
+  return GOFD_OK;
+}
+
 extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer, gofd_fdop, gofd_precond, const double*, const double*,
                                   const double*, double, const gofd_solve_opts*, double*, double*, double*,
                                   gofd_solve_info*) {
-  return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "not built yet");
+  return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "adjoint not built yet");
 }

@@ -450,7 +450,7 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
 
 extern "C" int gofd_transfer_free(gofd_transfer tr) {
   if (!tr) return GOFD_E_ARG;
-  if (tr->ctx) (void)hipStreamSynchronize(tr->ctx->stream);
+  (void)hipDeviceSynchronize();   // the creating context may already be gone
   delete tr;
   return GOFD_OK;
 }
