@@ -12,8 +12,8 @@
 // and replayed.
 //
 // Preconditioners: none; D_h (CG on the symmetric form of eq. Ah-3); the IC(1)
-// factor of A_h^(5/9/27) (Section 3.4), applied with two sync-free triangular
-// solves in which each row waits on per-row ready flags of the rows it uses.
+// factor of A_h^(5/9/27) (Section 3.4), applied with two level-scheduled
+// triangular solves.
 //
 // FP32 mode: the grid-side arrays and FFTs of every K product inside CG run
 // in single precision; an outer loop in double precision recomputes the true
@@ -34,14 +34,13 @@ inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); 
 constexpr int NB_DOT = 512;      // blocks of the plain vector kernels (fixed: deterministic sums)
 constexpr int BS = 256;
 constexpr int SCAT_G = 16;       // lanes per vertex in the I^T scatter
-constexpr long long SPIN_LIMIT = 1LL << 24;
 
 struct Scal {
   double rho, alpha, beta, bb, rr, pq, rz, tol2;
   int done, iters, status, pad;
 };
 
-enum { ST_OK = 0, ST_BREAKDOWN = 1, ST_SPIN = 2 };
+enum { ST_OK = 0, ST_BREAKDOWN = 1 };
 
 // fixed-order block reduction of one double per thread (BS threads)
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -339,64 +338,36 @@ __global__ __launch_bounds__(BS) void k_scatter_plain(const int* __restrict__ of
 
 // ---------------------------------------------------------------- triangular solves
 //
-// One 64-lane wavefront per row.  Rows are taken in dependency order from an
-// atomic counter, so every row a wave waits on was taken earlier by a running
-// wave; lanes stride through the row, each waiting on the ready flag of its
-// column (acquire), then the partial sums are combined in a fixed order.  A
-// spin limit turns a lost flag into an error instead of a hang.
-
-__global__ void k_tri_begin(int* __restrict__ ctl) {
-  // ctl[0]: forward counter, ctl[1]: backward counter, ctl[2]: epoch, ctl[3]: error
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    ctl[0] = 0;
-    ctl[1] = 0;
-    ctl[2] = ctl[2] + 2;
-  }
-}
+// Level-scheduled inside one workgroup per right-hand side: the rows of a
+// dependency level are independent, so the block's threads take them in
+// parallel, and a workgroup barrier separates consecutive levels.  No
+// workgroup ever waits on another, so the solve cannot stall on memory
+// visibility between XCDs; the cost is one barrier plus one dependent read
+// round trip per level.
 
 template <bool LOWER>
-__global__ __launch_bounds__(256) void k_trsv(const int* __restrict__ ptr, const int* __restrict__ col,
-                                              const double* __restrict__ val, const double* __restrict__ rhs_in,
-                                              double* __restrict__ out, int* __restrict__ ready, int* __restrict__ ctl,
-                                              int n, long long stride, int nrhs, const Scal* __restrict__ sc) {
-  const int lane = threadIdx.x & 63;
-  const int epoch = __hip_atomic_load(&ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + (LOWER ? 1 : 2);
-  int* counter = &ctl[LOWER ? 0 : 1];
-  while (true) {
-    int t = 0;
-    if (lane == 0) t = atomicAdd(counter, 1);
-    t = __shfl(t, 0);
-    if (t >= n) break;
-    const int row = LOWER ? t : n - 1 - t;
-    const int b = ptr[row], e = ptr[row + 1];
-    // lower: diagonal last; upper: diagonal first
-    const int dpos = LOWER ? e - 1 : b;
-    const int lo = LOWER ? b : b + 1, hi = LOWER ? e - 1 : e;
-    for (int i = lo + lane; i < hi; i += 64) {
-      const int c = col[i];
-      long long spins = 0;
-      while (__hip_atomic_load(&ready[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (++spins > SPIN_LIMIT) {
-          atomicOr(&ctl[3], 1);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    const double dv = val[dpos];
-    for (int k = 0; k < nrhs; ++k) {
-      if (sc[k].done) continue;
+__global__ __launch_bounds__(1024) void k_trsv_levels(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                      const double* __restrict__ val, const int* __restrict__ lvl_ptr,
+                                                      const int* __restrict__ lvl_rows, int nlev,
+                                                      const double* __restrict__ rhs_in, double* __restrict__ out,
+                                                      long long stride, const Scal* __restrict__ sc) {
+  const int k = blockIdx.x;
+  if (sc[k].done) return;
+  const double* b = rhs_in + k * stride;
+  double* y = out + k * stride;
+  for (int l = 0; l < nlev; ++l) {
+    const int r0 = lvl_ptr[l], r1 = lvl_ptr[l + 1];
+    for (int t = r0 + (int)threadIdx.x; t < r1; t += (int)blockDim.x) {
+      const int row = lvl_rows[t];
+      const int e0 = ptr[row], e1 = ptr[row + 1];
+      // lower: diagonal last; upper: diagonal first
+      const int dpos = LOWER ? e1 - 1 : e0;
+      const int lo = LOWER ? e0 : e0 + 1, hi = LOWER ? e1 - 1 : e1;
       double s = 0.0;
-      for (int i = lo + lane; i < hi; i += 64)
-        s += val[i] * __hip_atomic_load(&out[k * stride + col[i]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-      if (lane == 0) {
-        const double v = (rhs_in[k * stride + row] - s) / dv;
-        __hip_atomic_store(&out[k * stride + row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      for (int i = lo; i < hi; ++i) s += val[i] * y[col[i]];
+      y[row] = (b[row] - s) / val[dpos];
     }
-    if (lane == 0) __hip_atomic_store(&ready[row], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
   }
 }
 
@@ -413,8 +384,8 @@ struct gofd_precond_s {
   int kind = 0;
   int64_t nv = 0;
   DevBuf Lptr, Lcol, Lval, Uptr, Ucol, Uval;
-  DevBuf ready;    // int[nv]
-  DevBuf ctl;      // int[4]
+  DevBuf Llev_ptr, Llev_rows, Ulev_ptr, Ulev_rows;   // rows grouped by dependency level
+  int Lnlev = 0, Unlev = 0;
   std::vector<int32_t> hLptr, hLcol;
   std::vector<double> hLval;
   gofd_precond_info info{};
@@ -497,7 +468,9 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
         Uval[cur[c]++] = Lval[e];
       }
   }
-  // dependency depth of the forward solve (statistics)
+  // dependency levels: forward solve on L (rows depend on smaller columns),
+  // backward solve on U = L^T (rows depend on larger columns)
+  std::vector<int32_t> Llp, Llr, Ulp, Ulr;
   {
     std::vector<int> lev(n, 0);
     int depth = 0;
@@ -507,7 +480,29 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
       lev[i] = l;
       depth = std::max(depth, l + 1);
     }
+    Llp.assign(depth + 1, 0);
+    for (int64_t i = 0; i < n; ++i) Llp[lev[i] + 1]++;
+    for (int l = 0; l < depth; ++l) Llp[l + 1] += Llp[l];
+    Llr.resize(n);
+    std::vector<int32_t> cur(Llp.begin(), Llp.end() - 1);
+    for (int64_t i = 0; i < n; ++i) Llr[cur[lev[i]]++] = (int32_t)i;
+    pc->Lnlev = depth;
     pc->info.levels = depth;
+    std::fill(lev.begin(), lev.end(), 0);
+    depth = 0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+      int l = 0;
+      for (int64_t e = Uptr[i] + 1; e < Uptr[i + 1]; ++e) l = std::max(l, lev[Ucol[e]] + 1);
+      lev[i] = l;
+      depth = std::max(depth, l + 1);
+    }
+    Ulp.assign(depth + 1, 0);
+    for (int64_t i = 0; i < n; ++i) Ulp[lev[i] + 1]++;
+    for (int l = 0; l < depth; ++l) Ulp[l + 1] += Ulp[l];
+    Ulr.resize(n);
+    std::vector<int32_t> cur2(Ulp.begin(), Ulp.end() - 1);
+    for (int64_t i = 0; i < n; ++i) Ulr[cur2[lev[i]]++] = (int32_t)i;
+    pc->Unlev = depth;
   }
   hipStream_t st = ctx->stream;
   GOFD_TRY(dev_reserve(ctx, pc->Lptr, sizeof(int32_t) * (n + 1)));
@@ -516,16 +511,20 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
   GOFD_TRY(dev_reserve(ctx, pc->Uptr, sizeof(int32_t) * (n + 1)));
   GOFD_TRY(dev_reserve(ctx, pc->Ucol, sizeof(int32_t) * nnz));
   GOFD_TRY(dev_reserve(ctx, pc->Uval, sizeof(double) * nnz));
-  GOFD_TRY(dev_reserve(ctx, pc->ready, sizeof(int32_t) * n));
-  GOFD_TRY(dev_reserve(ctx, pc->ctl, sizeof(int32_t) * 8));
+  GOFD_TRY(dev_reserve(ctx, pc->Llev_ptr, sizeof(int32_t) * Llp.size()));
+  GOFD_TRY(dev_reserve(ctx, pc->Llev_rows, sizeof(int32_t) * n));
+  GOFD_TRY(dev_reserve(ctx, pc->Ulev_ptr, sizeof(int32_t) * Ulp.size()));
+  GOFD_TRY(dev_reserve(ctx, pc->Ulev_rows, sizeof(int32_t) * n));
   HIP_TRY(ctx, hipMemcpyAsync(pc->Lptr.p, pc->hLptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(pc->Lcol.p, Lcol.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(pc->Lval.p, Lval.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(pc->Uptr.p, Uptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(pc->Ucol.p, Ucol.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(pc->Uval.p, Uval.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemsetAsync(pc->ready.p, 0, sizeof(int32_t) * n, st));
-  HIP_TRY(ctx, hipMemsetAsync(pc->ctl.p, 0, sizeof(int32_t) * 8, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Llev_ptr.p, Llp.data(), sizeof(int32_t) * Llp.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Llev_rows.p, Llr.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Ulev_ptr.p, Ulp.data(), sizeof(int32_t) * Ulp.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(pc->Ulev_rows.p, Ulr.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
   pc->info.shift = alpha;
   pc->info.nnz_L = nnz;
@@ -616,16 +615,13 @@ int apply_K(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* v, bool fp
 int precond_apply(gofd_ctx_s* ctx, const Problem& P, Work& w) {
   gofd_precond_s* pc = P.pc;
   hipStream_t st = ctx->stream;
-  const int n = (int)P.tr->nv;
-  hipLaunchKernelGGL(k_tri_begin, dim3(1), dim3(64), 0, st, pc->ctl.as<int>());
-  // waves to keep resident: enough to cover the critical path, few enough to stay resident
-  const int nblk = std::min<long long>(grid1((long long)n * 64, 256), (long long)ctx->num_cu * 8);
-  hipLaunchKernelGGL((k_trsv<true>), dim3(nblk), dim3(256), 0, st, pc->Lptr.as<int>(), pc->Lcol.as<int>(),
-                     pc->Lval.as<double>(), w.r.as<double>(), w.dvec.as<double>(), pc->ready.as<int>(),
-                     pc->ctl.as<int>(), n, (long long)n, P.nrhs, w.scal.as<Scal>());
-  hipLaunchKernelGGL((k_trsv<false>), dim3(nblk), dim3(256), 0, st, pc->Uptr.as<int>(), pc->Ucol.as<int>(),
-                     pc->Uval.as<double>(), w.dvec.as<double>(), w.z.as<double>(), pc->ready.as<int>(),
-                     pc->ctl.as<int>(), n, (long long)n, P.nrhs, w.scal.as<Scal>());
+  const long long n = P.tr->nv;
+  hipLaunchKernelGGL((k_trsv_levels<true>), dim3(P.nrhs), dim3(1024), 0, st, pc->Lptr.as<int>(), pc->Lcol.as<int>(),
+                     pc->Lval.as<double>(), pc->Llev_ptr.as<int>(), pc->Llev_rows.as<int>(), pc->Lnlev,
+                     w.r.as<double>(), w.dvec.as<double>(), n, w.scal.as<Scal>());
+  hipLaunchKernelGGL((k_trsv_levels<false>), dim3(P.nrhs), dim3(1024), 0, st, pc->Uptr.as<int>(), pc->Ucol.as<int>(),
+                     pc->Uval.as<double>(), pc->Ulev_ptr.as<int>(), pc->Ulev_rows.as<int>(), pc->Unlev,
+                     w.dvec.as<double>(), w.z.as<double>(), n, w.scal.as<Scal>());
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
 }
@@ -729,12 +725,6 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
   if (graph) (void)hipGraphDestroy(graph);
   if (rc != GOFD_OK) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
-  if (P.pc && is_ic(P.pc)) {
-    int ctl[4];
-    HIP_TRY(ctx, hipMemcpyAsync(ctl, P.pc->ctl.p, sizeof(ctl), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
-    if (ctl[3]) return gofd_fail(ctx, GOFD_E_HIP, "triangular solve waited too long on a dependency");
-  }
   HIP_TRY(ctx, hipStreamSynchronize(st));
   return GOFD_OK;
 }
