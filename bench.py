@@ -1,0 +1,205 @@
+"""Benchmark: GoFD solves of the 2D L-shape workload on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): L-shaped domain
+[-1,1]^2 minus [0,1]^2, seeded Delaunay mesh of ~67k vertices graded toward
+the reentrant corner, 1024 x 1024 overlay grid (W = 1025 nodes per axis,
+FFT length 2048), s in {0.25, 0.75}, f a seeded 16-mode Fourier series,
+tolerance 1e-8 on the relative residual of eq. GoFD-2.
+
+One step = the batched solve of both orders s with FP32 grid products inside
+FP64 iterative refinement (every step of the hot path: gather + FFT passes +
+I^T scatter inside CG, FP64 residuals and updates).  The same steps are also
+timed with plain FP64 products, and the A_h products alone, for comparison.
+Transfer, T tables and preconditioners are per-(mesh, grid, s) setup, built
+before the timed region and reported separately.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _bytes_passB(W, half, b):
+    """Algorithmic HBM bytes of one column line of pass B: read and write W complex
+    values, read half real multipliers."""
+    return 2 * (2 * b * W) + b * half
+
+
+def cpu_baseline(cfg, iters_by_s, precond, budget_iters=6):
+    """The oracle (plain numpy FP64, FFT product of eq. AU-1) timed on a bounded sample:
+    `budget_iters` CG iterations per order s on the same workload, scaled by the CG
+    iteration count of a full solve (taken from the GPU FP64 run of the same method)."""
+    import numpy as np
+    from oracle import fdweights as fw, operator, solve, transfer
+    m, g, f = cfg["mesh"], cfg["grid"], cfg["f"][0]
+    otr = transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
+    total = 0.0
+    for s in cfg["s"]:
+        T = fw.filon(s, 2, 2 * g.N, 4 * g.N + 4)          # timing sample: a valid table at a small level
+        b = operator.rhs_grid(otr, s, f)
+        pc = (lambda r, d=otr.D[otr.J]: r / d) if precond == "DIAG" else None
+        t0 = time.perf_counter()
+        try:
+            solve.pcg(lambda v: operator.apply_K(otr, T, v, "fft"), b, tol=1e-300, maxiter=budget_iters,
+                      precond=pc)
+        except RuntimeError:
+            pass                                             # stopped by the iteration budget, as intended
+        dt = (time.perf_counter() - t0) / budget_iters
+        total += dt * iters_by_s[s]
+    return {"value": len(cfg["s"]) / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{budget_iters} oracle CG iterations per s on the full workload (numpy FFT product, one "
+                      f"thread), per-iteration time scaled by the FP64 solve's iteration counts "
+                      f"{dict((str(k), v) for k, v in iters_by_s.items())}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precond", default="NONE", choices=["NONE", "DIAG", "IC1_9", "IC1_5"])
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the workload runs on one "
+              "MI355X; see the design notes on sharding)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2307_14437_amd as gofd
+    from workloads import config_inputs
+
+    cfg = config_inputs("c2")
+    m, g, f = cfg["mesh"], cfg["grid"], cfg["f"][0]
+    svals = cfg["s"]
+    tol = cfg["tol"]
+    ctx = gofd.Context()
+    X = torch.tensor(m.X, device="cuda")
+    E = torch.tensor(m.elems, dtype=torch.int32, device="cuda")
+    fd = torch.tensor(f, device="cuda")
+
+    setup = {}
+    _sync(); t = time.perf_counter()
+    tr = gofd.Transfer(ctx, X, E, g)
+    _sync(); setup["build_transfer_ms"] = (time.perf_counter() - t) * 1e3
+    ops, pcs = [], []
+    for s in svals:
+        _sync(); t = time.perf_counter()
+        ops.append(gofd.FdOp(ctx, s, g))
+        _sync(); setup[f"fd_weights_ms_s{s}"] = (time.perf_counter() - t) * 1e3
+        t = time.perf_counter()
+        pcs.append(gofd.Precond(ctx, tr, ops[-1], args.precond))
+        setup[f"precond_ms_s{s}"] = (time.perf_counter() - t) * 1e3
+
+    def step(mode):
+        us, infos = gofd.solve_batched(ctx, [tr] * len(svals), ops, pcs, [fd] * len(svals), tol=tol,
+                                       mode=mode, inner_tol=args.inner_tol)
+        return us, infos
+
+    # reference FP64 solutions (also the accuracy yardstick of the FP32 mode)
+    u64, info64 = step(gofd.MODE_FP64)
+    for _ in range(args.warmup):
+        step(gofd.MODE_FP32_REFINE)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u32, info32 = step(gofd.MODE_FP32_REFINE)
+    _sync()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    for _ in range(args.warmup):
+        step(gofd.MODE_FP64)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u64, info64 = step(gofd.MODE_FP64)
+    _sync()
+    ms_step64 = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    errs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(u32, u64)]
+
+    # A_h products alone (the K matrix of eq. GoFD-2): window points per second
+    W = g.W
+    u = torch.randn(tr.nv, dtype=torch.float64, device="cuda")
+    mv = {}
+    for name, flags in (("fp64", gofd.UNSCALED | gofd.INTERIOR),
+                        ("fp32", gofd.UNSCALED | gofd.INTERIOR | gofd.FP32_GRID)):
+        for _ in range(3):
+            gofd.apply_Ah(ctx, tr, ops[1], u, flags)
+        _sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        n = 50
+        e0.record()
+        for _ in range(n):
+            gofd.apply_Ah(ctx, tr, ops[1], u, flags)
+        e1.record()
+        _sync()
+        mv[name] = e0.elapsed_time(e1) / n
+    gpts = {k: W * W / (v * 1e-3) / 1e9 for k, v in mv.items()}
+
+    # roofline of the dominant kernel (pass B, FP32 grid, the mode the step runs in)
+    kt = {}
+    for name, which in (("passA", gofd.K_PASS_A), ("passB", gofd.K_PASS_B), ("passC", gofd.K_PASS_C),
+                        ("scatter", gofd.K_SCATTER)):
+        kt[name] = gofd.time_kernel(ctx, tr, ops[1], which, u, gofd.FP32_GRID, reps=50)
+    half = 2 * g.N + 1
+    bytes_B = _bytes_passB(W, half, 4) * half
+    achieved = bytes_B / (kt["passB"] * 1e-3) / 1e9
+
+    its64 = {s: info64[i]["iterations"] for i, s in enumerate(svals)}
+    line = {
+        "metric": "PCG solves/s + A_h matvec Gpts/s, batched FP32+refine vs plain FP64 @1e-8",
+        "value": len(svals) / (ms_step * 1e-3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-grid/f64-refine",
+        "data": "synthetic",
+        "config": {"workload": "2D L-shape, 67k-vertex graded Delaunay mesh, 1024x1024 overlay grid, "
+                               "s in {0.25, 0.75}, 16-mode Fourier f, tol 1e-8",
+                   "nv": tr.nv, "grid": f"{W}x{W}", "fft_length": 2 * (W - 1), "precond": args.precond,
+                   "inner_tol": args.inner_tol},
+        "fp64": {"solves_per_s": len(svals) / (ms_step64 * 1e-3), "ms_per_step": ms_step64,
+                 "iterations": {str(k): v for k, v in its64.items()}},
+        "fp32_refine": {"iterations": {str(s): info32[i]["iterations"] for i, s in enumerate(svals)},
+                        "refinements": {str(s): info32[i]["refinements"] for i, s in enumerate(svals)},
+                        "rel_error_vs_fp64": {str(s): errs[i] for i, s in enumerate(svals)},
+                        "rel_residual": {str(s): info32[i]["rel_residual"] for i, s in enumerate(svals)}},
+        "matvec_gpts": gpts,
+        "matvec_us": {k: v * 1e3 for k, v in mv.items()},
+        "kernel_us_fp32": {k: v * 1e3 for k, v in kt.items()},
+        "setup_ms": setup,
+        "roofline": {"bound": "hbm", "kernel": "passB (fp32)", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg, its64, args.precond)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,7 @@ def _load():
                                ctypes.POINTER(vp), ctypes.POINTER(SolveInfo)],
         "gofd_solve_adjoint": [vp, vp, vp, vp, vp, vp, vp, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp,
                                ctypes.POINTER(SolveInfo)],
+        "gofd_time_kernel": [vp, vp, vp, i32, i32, vp, i32, i32, ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -127,8 +128,10 @@ EXPORTED = [
     "gofd_build_transfer", "gofd_transfer_free", "gofd_transfer_export", "gofd_fd_weights",
     "gofd_fdop_from_table", "gofd_fdop_get_table", "gofd_fdop_free", "gofd_apply_afd", "gofd_apply_Ah",
     "gofd_precond_create", "gofd_precond_free", "gofd_precond_export", "gofd_solve", "gofd_solve_batched",
-    "gofd_solve_adjoint",
+    "gofd_solve_adjoint", "gofd_time_kernel",
 ]
+
+K_PASS_A, K_PASS_B, K_PASS_C, K_SCATTER = 0, 1, 2, 3
 
 
 def _ptr(t):
@@ -372,3 +375,13 @@ def solve_adjoint(ctx: Context, tr: Transfer, op: FdOp, dLdu, u, f, tol=1e-10, p
                                      float(tol), ctypes.byref(opts), _ptr(gf) if gf is not None else None,
                                      _ptr(gX) if gX is not None else None, _ptr(lam), ctypes.byref(info)))
     return gf, (gX.view(tr.nv, tr.d) if gX is not None else None), lam, info.as_dict()
+
+
+def time_kernel(ctx: Context, tr: Transfer, op: FdOp, which, u, flags=0, reps=20):
+    """Average duration (ms) of one kernel of the K product, timed with HIP events on the library stream."""
+    u = u.contiguous()
+    nrhs = u.numel() // tr.nv
+    ms = ctypes.c_double()
+    ctx.check(lib.gofd_time_kernel(ctx.handle, tr.handle, op.handle, int(which), nrhs, _ptr(u), int(flags),
+                                   int(reps), ctypes.byref(ms)))
+    return ms.value

@@ -198,7 +198,7 @@ struct Cfg {
 };
 
 template <typename R, int L, class Src, typename Y>
-int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y) {
+int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes = 7) {
   const int W = op->W, half = op->half;
   const long long zs = (long long)W * half;
   const cplx<R>* tw;
@@ -217,30 +217,33 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y) {
   const int pairs = (W + 1) / 2;
   const int nbA = (pairs + C::LINES_A - 1) / C::LINES_A;
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL((k_passA<R, L, C::LINES_A, C::TPL, Src>), dim3(nbA, nrhs), dim3(C::NT_A), 0, st, src, Z, W,
-                     half, tw, zs);
+  if (passes & 1)
+    hipLaunchKernelGGL((k_passA<R, L, C::LINES_A, C::TPL, Src>), dim3(nbA, nrhs), dim3(C::NT_A), 0, st, src, Z, W,
+                       half, tw, zs);
   const int nb = (half + Cfg<L>::LINES_B - 1) / Cfg<L>::LINES_B;
-  hipLaunchKernelGGL((k_passB<R, L, Cfg<L>::LINES_B, Cfg<L>::NT_B>), dim3(nb, nrhs), dim3(Cfg<L>::NT_B), 0, st, Z,
-                     W, half, That, tw, zs);
-  hipLaunchKernelGGL((k_passC<R, Y, L, C::LINES_A, C::TPL>), dim3(nbA, nrhs), dim3(C::NT_A), 0, st, Z, W, half,
-                     tw, zs, y, (long long)W * W);
+  if (passes & 2)
+    hipLaunchKernelGGL((k_passB<R, L, Cfg<L>::LINES_B, Cfg<L>::NT_B>), dim3(nb, nrhs), dim3(Cfg<L>::NT_B), 0, st,
+                       Z, W, half, That, tw, zs);
+  if (passes & 4)
+    hipLaunchKernelGGL((k_passC<R, Y, L, C::LINES_A, C::TPL>), dim3(nbA, nrhs), dim3(C::NT_A), 0, st, Z, W, half,
+                       tw, zs, y, (long long)W * W);
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
 }
 
 template <typename R, class Src, typename Y>
-int dispatch_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y) {
+int dispatch_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes = 7) {
   switch (op->L) {
-    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y);
-    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y);
-    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y);
-    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y);
-    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y);
-    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y);
-    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y);
-    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y);
-    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y);
-    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y);
+    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y, passes);
+    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y, passes);
+    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y, passes);
+    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y, passes);
+    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y, passes);
+    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y, passes);
+    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y, passes);
+    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y, passes);
+    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y, passes);
+    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y, passes);
     default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "FFT length " + std::to_string(op->L) + " not built");
   }
 }
@@ -331,12 +334,12 @@ int conv_prepare(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs) {
 }
 
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g, void* y,
-               bool fp32) {
+               bool fp32, int passes) {
   if (op->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "3D product not built yet");
   if (v) {
     SrcGrid src{v, (long long)op->W * op->W};
-    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y))
-                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y));
+    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes)
+                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes);
   }
   const gofd_transfer_s* tr = g->tr;
   SrcGather<2> src;
@@ -351,13 +354,13 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   src.scale = g->col_scale;
   src.mask = g->mask;
   src.nv = tr->nv;
-  return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y))
-              : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y));
+  return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes)
+              : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes);
 }
 
 // ---------------------------------------------------------------- ABI
 
-static bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op) {
+bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op) {
   return tr->d == op->d && tr->N == op->N && tr->R == op->R && tr->center[0] == op->center[0] &&
          tr->center[1] == op->center[1] && tr->center[2] == op->center[2];
 }
@@ -456,5 +459,45 @@ extern "C" int gofd_fdop_free(gofd_fdop op) {
   if (!op) return GOFD_E_ARG;
   (void)hipDeviceSynchronize();
   delete op;
+  return GOFD_OK;
+}
+
+extern "C" int gofd_time_kernel(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int which, int nrhs, const double* u,
+                                int flags, int reps, double* avg_ms) {
+  if (!ctx || !tr || !op || !u || !avg_ms || nrhs < 1 || reps < 1 || which < 0 || which > 3)
+    return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  if (!same_grid(tr, op)) return gofd_fail(ctx, GOFD_E_ARG, "transfer and operator use different grids");
+  const bool fp32 = flags & GOFD_FP32_GRID;
+  WorkStream ws(ctx);
+  GOFD_TRY(conv_prepare(ctx, op, nrhs));
+  GOFD_TRY(dev_reserve(ctx, op->Y, sizeof(double) * tr->n_nodes * nrhs));
+  DevBuf z;
+  GOFD_TRY(dev_reserve(ctx, z, sizeof(double) * tr->nv * nrhs));
+  GatherSpec g;
+  g.tr = tr;
+  g.u = u;
+  g.mask = tr->imask.as<double>();
+  // fill the workspaces once with a full product
+  GOFD_TRY(conv_apply(ctx, op, nrhs, nullptr, &g, op->Y.p, fp32, 7));
+  auto launch = [&]() -> int {
+    if (which == GOFD_K_SCATTER)
+      return scatter_apply(ctx, tr, nrhs, op->Y.p, fp32, nullptr, tr->imask.as<double>(), z.as<double>());
+    return conv_apply(ctx, op, nrhs, nullptr, &g, op->Y.p, fp32, 1 << which);
+  };
+  GOFD_TRY(launch());
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+  int rc = GOFD_OK;
+  for (int i = 0; i < reps && rc == GOFD_OK; ++i) rc = launch();
+  HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+  HIP_TRY(ctx, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  GOFD_TRY(rc);
+  *avg_ms = ms / reps;
   return GOFD_OK;
 }

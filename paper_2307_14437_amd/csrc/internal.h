@@ -142,8 +142,11 @@ struct GatherSpec {
 // Apply A_FD with the FFT embedding: input either a grid field (v != nullptr,
 // nrhs*W^d doubles) or a gather spec; output grid field y (double or float,
 // nrhs*W^d).  fp32 selects the single-precision pipeline.
+// passes: bit mask of the FFT passes to launch (1: A, 2: B, 4: C), 7 = all.
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g,
-               void* y, bool fp32);
+               void* y, bool fp32, int passes = 7);
+
+bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op);
 
 // Reserve the spectra workspace and twiddle tables for nrhs fields, so that
 // later products allocate nothing (required inside graph capture).

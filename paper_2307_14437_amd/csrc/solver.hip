@@ -55,26 +55,20 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// last block to finish sums partials[0..nb) in a fixed order; returns true in
-// that block (all threads), with the totals in out[]
-template <int NV>
-__device__ __forceinline__ bool finish_partials(double* __restrict__ partials, int nb, unsigned* __restrict__ counter,
-                                                double* out, double* sh) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == (unsigned)(nb - 1));
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  for (int c = 0; c < NV; ++c) {
+// Dot products are two-stage: each block of a vector kernel writes one
+// partial sum per quantity, and a one-block finishing kernel per rhs adds the
+// partials in a fixed order and updates the CG scalars.  The kernel boundary
+// orders the two stages, so no block needs a device-wide memory fence (on a
+// multi-XCD part such a fence writes back the L2 of the issuing XCD).
+enum FinOp { FIN_START = 0, FIN_ALPHA = 1, FIN_UPDATE = 2, FIN_RZ_FIRST = 3, FIN_RZ = 4, FIN_RESIDUAL = 5 };
+
+template <int NQ>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nb, double* out, double* sh) {
+  for (int c = 0; c < NQ; ++c) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += BS) s += __hip_atomic_load(&partials[(long long)c * nb + i], __ATOMIC_RELAXED,
-                                                                       __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = threadIdx.x; i < nb; i += BS) s += part[(long long)c * nb + i];
     out[c] = block_sum(s, sh);
   }
-  if (threadIdx.x == 0) *counter = 0u;
-  return true;
 }
 
 // ---------------------------------------------------------------- kernels
@@ -131,21 +125,6 @@ __global__ __launch_bounds__(BS) void k_start(const double* __restrict__ b, doub
     part[blockIdx.x] = s_rz;
     part[gridDim.x + blockIdx.x] = s_bb;
   }
-  double tot[2];
-  if (finish_partials<2>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
-    Scal& S = sc[rhs];
-    S.rho = tot[0];
-    S.bb = tot[1];
-    S.rr = tot[1];
-    S.tol2 = tol * tol * tot[1];
-    S.iters = 0;
-    S.status = ST_OK;
-    S.done = (tot[1] == 0.0) ? 1 : 0;
-    if (!(tot[0] > 0.0) && tot[1] > 0.0) {
-      S.status = ST_BREAKDOWN;
-      S.done = 1;
-    }
-  }
 }
 
 // q = mask * I^T y; partial p.q; last block: alpha = rho / (p.q)
@@ -175,19 +154,7 @@ __global__ __launch_bounds__(BS) void k_scatter_dot(const int* __restrict__ off,
     }
   }
   const double s = block_sum(contrib, sh);
-  double* part = partials + (long long)rhs * gridDim.x;
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-  double tot[1];
-  if (finish_partials<1>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
-    Scal& S = sc[rhs];
-    S.pq = tot[0];
-    if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-      S.status = ST_BREAKDOWN;
-      S.done = 1;
-    } else {
-      S.alpha = S.rho / tot[0];
-    }
-  }
+  if (threadIdx.x == 0) partials[(long long)rhs * gridDim.x + blockIdx.x] = s;
 }
 
 // x += alpha p, r -= alpha q, rr = r.r; with a diagonal (or no) preconditioner
@@ -221,21 +188,6 @@ __global__ __launch_bounds__(BS) void k_update(double* __restrict__ x, double* _
     part[blockIdx.x] = s_rr;
     part[gridDim.x + blockIdx.x] = s_rz;
   }
-  double tot[2];
-  if (finish_partials<2>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
-    Scal& S = sc[rhs];
-    S.rr = tot[0];
-    S.iters += 1;
-    if (!isfinite(tot[0])) {
-      S.status = ST_BREAKDOWN;
-      S.done = 1;
-    } else if (tot[0] <= S.tol2) {
-      S.done = 1;
-    } else if (diag_kind >= 0) {
-      S.beta = tot[1] / S.rho;
-      S.rho = tot[1];
-    }
-  }
 }
 
 // rz = r.z after a triangular-solve preconditioner; beta, rho
@@ -250,22 +202,7 @@ __global__ __launch_bounds__(BS) void k_dot_rz(const double* __restrict__ r, con
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS)
     s += r[o + i] * z[o + i];
   s = block_sum(s, sh);
-  double* part = partials + (long long)rhs * gridDim.x;
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-  double tot[1];
-  if (finish_partials<1>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
-    Scal& S = sc[rhs];
-    if (first) {
-      S.rho = tot[0];
-    } else {
-      S.beta = tot[0] / S.rho;
-      S.rho = tot[0];
-    }
-    if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-      S.status = ST_BREAKDOWN;
-      S.done = 1;
-    }
-  }
+  if (threadIdx.x == 0) partials[(long long)rhs * gridDim.x + blockIdx.x] = s;
 }
 
 __global__ void k_pupdate(double* __restrict__ p, const double* __restrict__ z, long long nv,
@@ -306,10 +243,78 @@ __global__ __launch_bounds__(BS) void k_residual(const double* __restrict__ b, c
     part[blockIdx.x] = s_rr;
     part[gridDim.x + blockIdx.x] = s_bb;
   }
-  double tot[2];
-  if (finish_partials<2>(part, gridDim.x, counters + rhs, tot, sh) && threadIdx.x == 0) {
-    out2[2 * rhs] = tot[0];
-    out2[2 * rhs + 1] = tot[1];
+}
+
+// one block per rhs: fixed-order sum of the partials of the previous kernel
+// and the scalar update that goes with it
+__global__ __launch_bounds__(BS) void k_finish(int op, const double* __restrict__ partials, int nb,
+                                               Scal* __restrict__ sc, double tol, int diag_kind,
+                                               double* __restrict__ out2) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.x;
+  Scal& S = sc[rhs];
+  if (op != FIN_START && op != FIN_RESIDUAL && S.done) return;
+  double tot[2] = {0.0, 0.0};
+  const int nq = (op == FIN_ALPHA || op == FIN_RZ || op == FIN_RZ_FIRST) ? 1 : 2;
+  const double* part = partials + (long long)rhs * nq * nb;
+  if (nq == 1)
+    sum_partials<1>(part, nb, tot, sh);
+  else
+    sum_partials<2>(part, nb, tot, sh);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case FIN_START:
+      S.rho = tot[0];
+      S.bb = tot[1];
+      S.rr = tot[1];
+      S.tol2 = tol * tol * tot[1];
+      S.iters = 0;
+      S.status = ST_OK;
+      S.done = (tot[1] == 0.0) ? 1 : 0;
+      if (!(tot[0] > 0.0) && tot[1] > 0.0) {
+        S.status = ST_BREAKDOWN;
+        S.done = 1;
+      }
+      break;
+    case FIN_ALPHA:
+      S.pq = tot[0];
+      if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
+        S.status = ST_BREAKDOWN;
+        S.done = 1;
+      } else {
+        S.alpha = S.rho / tot[0];
+      }
+      break;
+    case FIN_UPDATE:
+      S.rr = tot[0];
+      S.iters += 1;
+      if (!isfinite(tot[0])) {
+        S.status = ST_BREAKDOWN;
+        S.done = 1;
+      } else if (tot[0] <= S.tol2) {
+        S.done = 1;
+      } else if (diag_kind >= 0) {
+        S.beta = tot[1] / S.rho;
+        S.rho = tot[1];
+      }
+      break;
+    case FIN_RZ_FIRST:
+    case FIN_RZ:
+      if (op == FIN_RZ_FIRST) {
+        S.rho = tot[0];
+      } else {
+        S.beta = tot[0] / S.rho;
+        S.rho = tot[0];
+      }
+      if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
+        S.status = ST_BREAKDOWN;
+        S.done = 1;
+      }
+      break;
+    case FIN_RESIDUAL:
+      out2[2 * rhs] = tot[0];
+      out2[2 * rhs + 1] = tot[1];
+      break;
   }
 }
 
@@ -602,6 +607,8 @@ int apply_K(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* v, bool fp
                          tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv,
                          (long long)tr->n_nodes, tr->imask.as<double>(), w.p.as<double>(), w.q.as<double>(),
                          w.scal.as<Scal>(), w.partials.as<double>(), w.counters.as<unsigned>());
+    hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_ALPHA, w.partials.as<double>(), (int)gs.x,
+                       w.scal.as<Scal>(), 0.0, 0, nullptr);
   } else {
     if (fp32) return gofd_fail(ctx, GOFD_E_ARG, "internal: plain product is double only");
     hipLaunchKernelGGL((k_scatter_plain<SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(), tr->csc_node.as<int>(),
@@ -640,10 +647,14 @@ int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32) {
   hipLaunchKernelGGL(k_update, gd, dim3(BS), 0, st, w.x.as<double>(), w.r.as<double>(), w.z.as<double>(),
                      w.p.as<double>(), w.q.as<double>(), P.tr->dscale.as<double>(), diag_kind, nv, w.scal.as<Scal>(),
                      w.partials.as<double>(), w.counters.as<unsigned>());
+  hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_UPDATE, w.partials.as<double>(), NB_DOT,
+                     w.scal.as<Scal>(), 0.0, diag_kind, nullptr);
   if (diag_kind < 0) {
     GOFD_TRY(precond_apply(ctx, P, w));
     hipLaunchKernelGGL(k_dot_rz, gd, dim3(BS), 0, st, w.r.as<double>(), w.z.as<double>(), nv, w.scal.as<Scal>(),
                        w.partials.as<double>(), w.counters.as<unsigned>(), 0);
+    hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_RZ, w.partials.as<double>(), NB_DOT,
+                       w.scal.as<Scal>(), 0.0, 0, nullptr);
   }
   hipLaunchKernelGGL(k_pupdate, gd, dim3(BS), 0, st, w.p.as<double>(), w.z.as<double>(), nv, w.scal.as<Scal>());
   HIP_TRY(ctx, hipGetLastError());
@@ -669,6 +680,8 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
   hipLaunchKernelGGL(k_start, gd, dim3(BS), 0, st, w.b.as<double>(), w.x.as<double>(), w.r.as<double>(),
                      w.z.as<double>(), w.p.as<double>(), diag_kind == 1 ? P.tr->dscale.as<double>() : nullptr, nv,
                      w.scal.as<Scal>(), tol, w.partials.as<double>(), w.counters.as<unsigned>(), diag_kind < 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_START, w.partials.as<double>(), NB_DOT,
+                     w.scal.as<Scal>(), tol, 0, nullptr);
   HIP_TRY(ctx, hipGetLastError());
   hs.resize(P.nrhs);
   hipGraphExec_t exec = nullptr;
@@ -737,6 +750,8 @@ int true_residual(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* x, c
   dim3 gd(NB_DOT, P.nrhs);
   hipLaunchKernelGGL(k_residual, gd, dim3(BS), 0, ctx->stream, b, w.q.as<double>(), r, (long long)P.tr->nv,
                      w.out2.as<double>(), w.partials.as<double>(), w.counters.as<unsigned>());
+  hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, ctx->stream, (int)FIN_RESIDUAL, w.partials.as<double>(),
+                     NB_DOT, w.scal.as<Scal>(), 0.0, 0, w.out2.as<double>());
   std::vector<double> h(2 * P.nrhs);
   HIP_TRY(ctx, hipMemcpyAsync(h.data(), w.out2.p, sizeof(double) * 2 * P.nrhs, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -859,11 +874,6 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
   }
   if (worst != GOFD_OK) return gofd_fail(ctx, worst, "solve did not reach the tolerance for every right-hand side");
   return GOFD_OK;
-}
-
-static bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op) {
-  return tr->d == op->d && tr->N == op->N && tr->R == op->R && tr->center[0] == op->center[0] &&
-         tr->center[1] == op->center[1] && tr->center[2] == op->center[2];
 }
 
 extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, int nrhs, const double* f,
