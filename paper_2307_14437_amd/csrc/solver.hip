@@ -24,6 +24,7 @@
 #include <cstring>
 #include <memory>
 
+#include "bary.h"
 #include "internal.h"
 #include "precond_host.h"
 
@@ -903,8 +904,169 @@ extern "C" int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* 
   return GOFD_OK;
 }
 
-extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer, gofd_fdop, gofd_precond, const double*, const double*,
-                                  const double*, double, const gofd_solve_opts*, double*, double*, double*,
-                                  gofd_solve_info*) {
-  return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "adjoint not built yet");
+// ---------------------------------------------------------------- adjoint
+
+namespace {
+
+// grid field v = c * I (mask * x): gather of vertex values at every node
+template <int D>
+__global__ void k_gather_grid(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+                              const int* __restrict__ elem, const double* __restrict__ x,
+                              const double* __restrict__ mask, long long n_nodes, double c, double* __restrict__ v) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_nodes) return;
+  const int e = elem[k];
+  if (e < 0) {
+    v[k] = 0.0;
+    return;
+  }
+  int vid[D + 1];
+  double lam[D + 1];
+  node_weights<D>(g, X, elems, e, k, vid, lam);
+  double s = 0.0;
+  for (int r = 0; r <= D; ++r) s += lam[r] * mask[vid[r]] * x[vid[r]];
+  v[k] = c * s;
+}
+
+// inverse of the (D+1)x(D+1) matrix E = [[x_0 .. x_D]; [1 .. 1]] by Gauss-Jordan
+template <int D>
+__device__ void inverse_E(const double* V, double* Ei) {
+  constexpr int n = D + 1;
+  double A[n][2 * n];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < 2 * n; ++j) A[i][j] = 0.0;
+  for (int r = 0; r < n; ++r) {        // column r = vertex r
+    for (int a = 0; a < D; ++a) A[a][r] = V[r * D + a];
+    A[D][r] = 1.0;
+  }
+  for (int i = 0; i < n; ++i) A[i][n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < n; ++i)
+      if (fabs(A[i][c]) > fabs(A[piv][c])) piv = i;
+    if (piv != c)
+      for (int j = 0; j < 2 * n; ++j) {
+        const double t = A[c][j];
+        A[c][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    const double inv = 1.0 / A[c][c];
+    for (int j = 0; j < 2 * n; ++j) A[c][j] *= inv;
+    for (int i = 0; i < n; ++i) {
+      if (i == c) continue;
+      const double f = A[i][c];
+      for (int j = 0; j < 2 * n; ++j) A[i][j] -= f * A[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Ei[i * n + j] = A[i][n + j];
+}
+
+// dL/dX_{j,a} = sum over nodes k touching vertex j (as vertex i of elem(k)) of
+//   sum_r G_r(k) * (-(E^{-1})_{r,a} phi_i(x_k)),  G_r = lam_{v_r} r_k - (A I lam)_k u_{v_r}
+// One thread per vertex, nodes in ascending order: deterministic.
+template <int D>
+__global__ void k_grad_X(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+                         const int* __restrict__ elem, const int* __restrict__ off, const int* __restrict__ node,
+                         long long nv, const double* __restrict__ u, const double* __restrict__ lam_v,
+                         const double* __restrict__ mask, const double* __restrict__ rgrid,
+                         const double* __restrict__ ylam, double* __restrict__ gX) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nv) return;
+  double acc[D] = {};
+  for (int q = off[j]; q < off[j + 1]; ++q) {
+    const long long k = node[q];
+    const int e = elem[k];
+    int vid[D + 1];
+    double phi[D + 1];
+    node_weights<D>(g, X, elems, e, k, vid, phi);
+    int i = 0;
+    for (int r = 0; r <= D; ++r)
+      if (vid[r] == (int)j) i = r;
+    double V[(D + 1) * D];
+    for (int r = 0; r <= D; ++r)
+      for (int a = 0; a < D; ++a) V[r * D + a] = X[(long long)vid[r] * D + a];
+    double Ei[(D + 1) * (D + 1)];
+    inverse_E<D>(V, Ei);
+    const double rk = rgrid[k], yk = ylam[k];
+    for (int r = 0; r <= D; ++r) {
+      const double mr = mask[vid[r]];
+      const double G = mr * (lam_v[vid[r]] * rk - yk * u[vid[r]]);
+      for (int a = 0; a < D; ++a) acc[a] += G * (-Ei[r * (D + 1) + a] * phi[i]);
+    }
+  }
+  for (int a = 0; a < D; ++a) gX[j * D + a] = acc[a];
+}
+
+__global__ void k_rgrid(const double* __restrict__ f, const double* __restrict__ yu, const int* __restrict__ elem,
+                        long long n, double h2s, double* __restrict__ r) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) r[k] = elem[k] >= 0 ? h2s * f[k] - yu[k] : 0.0;
+}
+
+__global__ void k_mask_copy(const double* __restrict__ a, const double* __restrict__ mask, long long n,
+                            double* __restrict__ b) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i] * mask[i];
+}
+
+}  // namespace
+
+extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, const double* dLdu,
+                                  const double* u, const double* f, double tol, const gofd_solve_opts* opts,
+                                  double* grad_f, double* grad_X, double* lambda, gofd_solve_info* info) {
+  if (!ctx || !tr || !op || !dLdu || !u || !f) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  if (!same_grid(tr, op)) return gofd_fail(ctx, GOFD_E_ARG, "transfer and operator use different grids");
+  if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
+  if (tr->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "adjoint in 3D needs the 3D product");
+  WorkStream ws(ctx);
+  hipStream_t st = ctx->stream;
+  Problem P{tr, op, pc, 1};
+  Work w;
+  GOFD_TRY(reserve_work(ctx, w, tr->nv, tr->n_nodes, 1));
+  const long long nv = tr->nv, nn = tr->n_nodes;
+  // adjoint right-hand side: dL/du on the interior block (K is symmetric)
+  hipLaunchKernelGGL(k_mask_copy, dim3(grid1(nv, 256)), dim3(256), 0, st, dLdu, tr->imask.as<double>(), nv,
+                     w.b.as<double>());
+  DevBuf lam;
+  GOFD_TRY(dev_reserve(ctx, lam, sizeof(double) * nv));
+  GOFD_TRY(solve_system(ctx, P, w, tol, opts, lam.as<double>(), info));
+  if (lambda) HIP_TRY(ctx, hipMemcpyAsync(lambda, lam.p, sizeof(double) * nv, hipMemcpyDeviceToDevice, st));
+  GridGeom g;
+  g.d = tr->d;
+  g.W = tr->W;
+  g.h = tr->h;
+  for (int a = 0; a < 3; ++a) g.lo[a] = tr->lo[a];
+  if (grad_f)
+    hipLaunchKernelGGL(k_gather_grid<2>, dim3(grid1(nn, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
+                       tr->elems.as<int>(), tr->elem.as<int>(), lam.as<double>(), tr->imask.as<double>(), nn,
+                       op->h2s, grad_f);
+  if (grad_X) {
+    DevBuf yu, yl, rg;
+    GOFD_TRY(dev_reserve(ctx, yu, sizeof(double) * nn));
+    GOFD_TRY(dev_reserve(ctx, yl, sizeof(double) * nn));
+    GOFD_TRY(dev_reserve(ctx, rg, sizeof(double) * nn));
+    GOFD_TRY(conv_prepare(ctx, op, 1));
+    GatherSpec gs;
+    gs.tr = tr;
+    gs.mask = tr->imask.as<double>();
+    gs.u = u;
+    GOFD_TRY(conv_apply(ctx, op, 1, nullptr, &gs, yu.p, false));        // A I u
+    gs.u = lam.as<double>();
+    GOFD_TRY(conv_apply(ctx, op, 1, nullptr, &gs, yl.p, false));        // A I lambda
+    hipLaunchKernelGGL(k_rgrid, dim3(grid1(nn, 256)), dim3(256), 0, st, f, yu.as<double>(), tr->elem.as<int>(), nn,
+                       op->h2s, rg.as<double>());
+    // u restricted to the interior (the solve's unknowns)
+    hipLaunchKernelGGL(k_mask_copy, dim3(grid1(nv, 256)), dim3(256), 0, st, u, tr->imask.as<double>(), nv,
+                       w.x.as<double>());
+    hipLaunchKernelGGL(k_grad_X<2>, dim3(grid1(nv, 128)), dim3(128), 0, st, g, tr->X.as<double>(),
+                       tr->elems.as<int>(), tr->elem.as<int>(), tr->csc_off.as<int>(), tr->csc_node.as<int>(), nv,
+                       w.x.as<double>(), lam.as<double>(), tr->imask.as<double>(), rg.as<double>(), yl.as<double>(),
+                       grad_X);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return GOFD_OK;
 }
