@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 struct GridGeom {
   int d;
   int W;
@@ -66,26 +68,87 @@ __device__ __forceinline__ void bary3(const double* V, const double* p, double* 
   }
 }
 
-// weights of grid node k (linear number) in element e; writes d+1 vertex ids
-// and weights
+// Per-element record of the affine barycentric map, built once per transfer:
+// lambda_r(x) = g_r . (x - x_0) for r >= 1, lambda_0 = 1 - sum_{r>=1} lambda_r.
+// Every kernel that needs the weight of a node evaluates it from the record of
+// its element with the same function, so the two sides of I^T A I use
+// bit-identical weights.
+struct ElemRec2 {
+  int v[4];        // vertex ids (v[3] unused)
+  double x0[2];    // vertex 0
+  double g[2][2];  // gradients of lambda_1, lambda_2
+};
+struct ElemRec3 {
+  int v[4];
+  double x0[3];
+  double g[3][3];
+  double pad;
+};
 template <int D>
-__device__ __forceinline__ void node_weights(const GridGeom& g, const double* __restrict__ X,
-                                             const int* __restrict__ elems, int e, long long k,
-                                             int* vid, double* lam) {
-  double p[3];
+using ElemRec = typename std::conditional<D == 2, ElemRec2, ElemRec3>::type;
+
+template <int D>
+__device__ __forceinline__ void make_record(const double* __restrict__ X, const int* __restrict__ elems, long long e,
+                                            ElemRec<D>& rec) {
+#pragma clang fp contract(off)
+  double P[D + 1][D];
+  for (int r = 0; r <= D; ++r) {
+    rec.v[r] = elems[e * (D + 1) + r];
+    for (int a = 0; a < D; ++a) P[r][a] = X[(long long)rec.v[r] * D + a];
+  }
+  for (int a = 0; a < D; ++a) rec.x0[a] = P[0][a];
+  if constexpr (D == 2) {
+    rec.v[3] = -1;
+    const double ax = P[1][0] - P[0][0], ay = P[1][1] - P[0][1];
+    const double bx = P[2][0] - P[0][0], by = P[2][1] - P[0][1];
+    const double inv = 1.0 / (ax * by - ay * bx);
+    rec.g[0][0] = by * inv;
+    rec.g[0][1] = -bx * inv;
+    rec.g[1][0] = -ay * inv;
+    rec.g[1][1] = ax * inv;
+  } else {
+    // columns of M are the edge vectors x_r - x_0; rows of M^{-1} are the gradients
+    double M[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int a = 0; a < 3; ++a) M[a][r] = P[r + 1][a] - P[0][a];
+    const double c00 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    const double c01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    const double c02 = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    const double det = M[0][0] * c00 + M[0][1] * c01 + M[0][2] * c02;
+    const double inv = 1.0 / det;
+    rec.g[0][0] = c00 * inv;
+    rec.g[1][0] = c01 * inv;
+    rec.g[2][0] = c02 * inv;
+    rec.g[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) * inv;
+    rec.g[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) * inv;
+    rec.g[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) * inv;
+    rec.g[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) * inv;
+    rec.g[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) * inv;
+    rec.g[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) * inv;
+    rec.pad = 0.0;
+  }
+}
+
+// weights of grid node k (linear number) from its element's record
+template <int D>
+__device__ __forceinline__ void node_weights(const GridGeom& g, const ElemRec<D>* __restrict__ recs, int e,
+                                             long long k, int* vid, double* lam) {
+#pragma clang fp contract(off)
+  const ElemRec<D> rec = recs[e];
+  double dx[3];
   long long rem = k;
   for (int a = 0; a < D; ++a) {
     const int i = (int)(rem % g.W);
     rem /= g.W;
-    p[a] = node_coord(g, a, i);
+    dx[a] = node_coord(g, a, i) - rec.x0[a];
   }
-  double V[(D + 1) * D];
-  for (int r = 0; r <= D; ++r) {
-    vid[r] = elems[(long long)e * (D + 1) + r];
-    for (int a = 0; a < D; ++a) V[r * D + a] = X[(long long)vid[r] * D + a];
+  double s = 0.0;
+  for (int r = 1; r <= D; ++r) {
+    double l = 0.0;
+    for (int a = 0; a < D; ++a) l += rec.g[r - 1][a] * dx[a];
+    lam[r] = l;
+    s += l;
   }
-  if constexpr (D == 2)
-    bary2(V, p, lam);
-  else
-    bary3(V, p, lam);
+  lam[0] = 1.0 - s;
+  for (int r = 0; r <= D; ++r) vid[r] = rec.v[r];
 }

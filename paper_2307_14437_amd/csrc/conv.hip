@@ -51,8 +51,7 @@ struct SrcGrid {
 template <int D>
 struct SrcGather {
   GridGeom g;
-  const double* X;
-  const int* elems;
+  const ElemRec<D>* recs;
   const int* elem;
   const double* u;
   const double* scale;
@@ -63,7 +62,7 @@ struct SrcGather {
     if (e < 0) return 0.0;
     int vid[D + 1];
     double lam[D + 1];
-    node_weights<D>(g, X, elems, e, k, vid, lam);
+    node_weights<D>(g, recs, e, k, vid, lam);
     const double* ur = u + rhs * nv;
     double s = 0.0;
 #pragma unroll
@@ -90,6 +89,7 @@ __global__ __launch_bounds__(LINES* TPL) void k_passA(Src src, cplx<R>* __restri
   const int rhs = blockIdx.y;
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
+#pragma unroll
   for (int m = t; m < L; m += TPL) {
     R a = 0, b = 0;
     if (m < W) {
@@ -111,21 +111,35 @@ __global__ __launch_bounds__(LINES* TPL) void k_passA(Src src, cplx<R>* __restri
 }
 
 // ---------------------------------------------------------------- pass B
+// Column slots 0..L/2-1: slot c > 0 is spectrum column k0 = c; slot 0 carries
+// the two real columns k0 = 0 and k0 = L/2 packed as one complex column
+// (after pass A both are exactly real), so the slots divide evenly into blocks.
+// For the packed slot, with C = FFT(a + i b) and m = L - k:
+//   A_k = (C_k + conj C_m)/2,  i B_k = (C_k - conj C_m)/2, and the product
+//   D = T0 A + i T1 B gives D_k = (T0+T1)/2 C_k + (T0-T1)/2 conj C_m;
+// the inverse FFT of D is (T0 * a) + i (T1 * b) with both parts real.
 template <typename R, int L, int LINES, int NT>
 __global__ __launch_bounds__(NT) void k_passB(cplx<R>* __restrict__ Z, int W, int half, const R* __restrict__ That,
                                               const cplx<R>* __restrict__ tw, long long zs) {
   constexpr int TPL = NT / LINES;
   constexpr int PL = padded_len<L>();
+  constexpr int NQ = L / 2;                 // Nyquist column
   __shared__ cplx<R> buf[LINES * PL];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int rhs = blockIdx.y;
   const int k0 = b * LINES;
   cplx<R>* Zr = Z + rhs * zs;
+#pragma unroll
   for (int idx = threadIdx.x; idx < L * LINES; idx += NT) {
     const int c = idx % LINES, i = idx / LINES;
     const int col = k0 + c;
     cplx<R> v = {0, 0};
-    if (i < W && col < half) v = Zr[(long long)i * half + col];
+    if (i < W) {
+      if (col == 0)
+        v = {Zr[(long long)i * half].x, Zr[(long long)i * half + NQ].x};
+      else
+        v = Zr[(long long)i * half + col];
+    }
     buf[c * PL + pidx<L>(i)] = v;
   }
   __syncthreads();
@@ -134,20 +148,39 @@ __global__ __launch_bounds__(NT) void k_passB(cplx<R>* __restrict__ Z, int W, in
   fft_line<R, L, TPL, false>(lb, tw, t);
   {
     const int col = k0 + line;
-    const R* Tc = That + (long long)(col < half ? col : 0) * half;
-    for (int k1 = t; k1 < L; k1 += TPL) {
-      const int kk = (k1 <= L / 2) ? k1 : L - k1;
-      const R m = (col < half) ? Tc[kk] : (R)0;
-      cplx<R> v = lb[pidx<L>(k1)];
-      lb[pidx<L>(k1)] = {v.x * m, v.y * m};
+    if (col == 0) {
+      for (int k1 = t; k1 <= L / 2; k1 += TPL) {
+        const int m = (L - k1) & (L - 1);
+        const R t0 = That[k1];                            // multiplier column k0 = 0
+        const R t1 = That[(long long)NQ * half + k1];     // multiplier column k0 = L/2
+        const R p = (t0 + t1) * (R)0.5, q = (t0 - t1) * (R)0.5;
+        const cplx<R> ck = lb[pidx<L>(k1)], cm = lb[pidx<L>(m)];
+        lb[pidx<L>(k1)] = {p * ck.x + q * cm.x, p * ck.y - q * cm.y};
+        if (m != k1) lb[pidx<L>(m)] = {p * cm.x + q * ck.x, p * cm.y - q * ck.y};
+      }
+    } else {
+      const R* Tc = That + (long long)col * half;
+      for (int k1 = t; k1 < L; k1 += TPL) {
+        const int kk = (k1 <= L / 2) ? k1 : L - k1;
+        const R mlt = Tc[kk];
+        cplx<R> v = lb[pidx<L>(k1)];
+        lb[pidx<L>(k1)] = {v.x * mlt, v.y * mlt};
+      }
     }
   }
   __syncthreads();
   fft_line<R, L, TPL, true>(lb, tw, t);
+#pragma unroll 4
   for (int idx = threadIdx.x; idx < W * LINES; idx += NT) {
     const int c = idx % LINES, i = idx / LINES;
     const int col = k0 + c;
-    if (col < half) Zr[(long long)i * half + col] = buf[c * PL + pidx<L>(i)];
+    const cplx<R> v = buf[c * PL + pidx<L>(i)];
+    if (col == 0) {
+      Zr[(long long)i * half] = {v.x, (R)0};
+      Zr[(long long)i * half + NQ] = {v.y, (R)0};
+    } else {
+      Zr[(long long)i * half + col] = v;
+    }
   }
 }
 
@@ -165,6 +198,7 @@ __global__ __launch_bounds__(LINES* TPL) void k_passC(const cplx<R>* __restrict_
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
   const cplx<R>* z0 = Z + rhs * zs + (long long)row0 * half;
+#pragma unroll 4
   for (int k = t; k < half; k += TPL) {
     cplx<R> a = has0 ? z0[k] : cplx<R>{0, 0};
     cplx<R> b = has1 ? z0[half + k] : cplx<R>{0, 0};
@@ -192,7 +226,7 @@ template <int L>
 struct Cfg {
   static constexpr int TPL = (L / 8 < 512) ? L / 8 : 512;                  // threads per line
   static constexpr int LINES_A = (TPL >= 64) ? 1 : 64 / TPL;               // row pairs per block
-  static constexpr int LINES_B = (L <= 256) ? 8 : (L <= 1024 ? 4 : 2);     // columns per block
+  static constexpr int LINES_B = (L <= 256) ? ((L / 2 >= 8) ? 8 : L / 2) : (L <= 2048 ? 4 : 2);   // columns per block
   static constexpr int NT_A = LINES_A * TPL;
   static constexpr int NT_B = LINES_B * TPL;
 };
@@ -220,7 +254,7 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   if (passes & 1)
     hipLaunchKernelGGL((k_passA<R, L, C::LINES_A, C::TPL, Src>), dim3(nbA, nrhs), dim3(C::NT_A), 0, st, src, Z, W,
                        half, tw, zs);
-  const int nb = (half + Cfg<L>::LINES_B - 1) / Cfg<L>::LINES_B;
+  const int nb = (L / 2) / Cfg<L>::LINES_B;     // column slots 0..L/2-1 (DC and Nyquist share slot 0)
   if (passes & 2)
     hipLaunchKernelGGL((k_passB<R, L, Cfg<L>::LINES_B, Cfg<L>::NT_B>), dim3(nb, nrhs), dim3(Cfg<L>::NT_B), 0, st,
                        Z, W, half, That, tw, zs);
@@ -347,8 +381,7 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   src.g.W = tr->W;
   src.g.h = tr->h;
   for (int a = 0; a < 3; ++a) src.g.lo[a] = tr->lo[a];
-  src.X = tr->X.as<double>();
-  src.elems = tr->elems.as<int>();
+  src.recs = tr->rec.as<ElemRec2>();
   src.elem = tr->elem.as<int>();
   src.u = g->u;
   src.scale = g->col_scale;

@@ -124,11 +124,22 @@ __device__ __forceinline__ void stages(cplx<R>* buf, const cplx<R>* __restrict__
       const int j = t + p * TPL;
       const int k = j & (NS - 1);
       if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) {
-          const cplx<R> w = tw[r * k * TWS];
-          a[p][r] = INV ? cmulc(a[p][r], w) : cmul(a[p][r], w);
+        // w^r for r = 1..RAD-1 from the table entries w^1, w^2, w^4 (products
+        // for the others: at most two roundings away from the table values)
+        cplx<R> w[8];
+        w[1] = tw[k * TWS];
+        if constexpr (RAD >= 4) {
+          w[2] = tw[2 * k * TWS];
+          w[3] = cmul(w[1], w[2]);
         }
+        if constexpr (RAD == 8) {
+          w[4] = tw[4 * k * TWS];
+          w[5] = cmul(w[4], w[1]);
+          w[6] = cmul(w[4], w[2]);
+          w[7] = cmul(w[4], w[3]);
+        }
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) a[p][r] = INV ? cmulc(a[p][r], w[r]) : cmul(a[p][r], w[r]);
       }
       dft<R, RAD, INV>(a[p]);
       const int base = (j - k) * RAD + k;

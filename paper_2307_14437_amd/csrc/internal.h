@@ -96,6 +96,7 @@ struct gofd_transfer_s {
   DevBuf X;          // double[nv*d]
   DevBuf elems;      // int32[ne*(d+1)]
   DevBuf elem;       // int32[n_nodes], element of each node or -1
+  DevBuf rec;        // ElemRec2/ElemRec3[ne]: affine barycentric map per element
   DevBuf csc_off;    // int32[nv+1]
   DevBuf csc_node;   // int32[nnz]
   DevBuf csc_w;      // double[nnz]

@@ -129,9 +129,9 @@ __global__ __launch_bounds__(BS) void k_start(const double* __restrict__ b, doub
 }
 
 // q = mask * I^T y; partial p.q; last block: alpha = rho / (p.q)
-template <typename Y, int G>
+template <typename Y, typename WT, int G>
 __global__ __launch_bounds__(BS) void k_scatter_dot(const int* __restrict__ off, const int* __restrict__ node,
-                                                    const double* __restrict__ w, const Y* __restrict__ y,
+                                                    const WT* __restrict__ w, const Y* __restrict__ y,
                                                     long long nv, long long n_nodes, const double* __restrict__ mask,
                                                     const double* __restrict__ p, double* __restrict__ q,
                                                     Scal* __restrict__ sc, double* __restrict__ partials,
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(BS) void k_scatter_dot(const int* __restrict__ off,
   if (v < nv) {
     const Y* yr = y + rhs * n_nodes;
     double acc = 0.0;
-    for (int i = off[v] + lane; i < off[v + 1]; i += G) acc += w[i] * (double)yr[node[i]];
+    for (int i = off[v] + lane; i < off[v + 1]; i += G) acc += (double)w[i] * (double)yr[node[i]];
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
@@ -599,12 +599,12 @@ int apply_K(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* v, bool fp
   hipStream_t st = ctx->stream;
   if (with_dot) {
     if (fp32)
-      hipLaunchKernelGGL((k_scatter_dot<float, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
-                         tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<float>(), (long long)tr->nv,
+      hipLaunchKernelGGL((k_scatter_dot<float, float, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
+                         tr->csc_node.as<int>(), tr->csc_w32.as<float>(), w.grid.as<float>(), (long long)tr->nv,
                          (long long)tr->n_nodes, tr->imask.as<double>(), w.p.as<double>(), w.q.as<double>(),
                          w.scal.as<Scal>(), w.partials.as<double>(), w.counters.as<unsigned>());
     else
-      hipLaunchKernelGGL((k_scatter_dot<double, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
+      hipLaunchKernelGGL((k_scatter_dot<double, double, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
                          tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv,
                          (long long)tr->n_nodes, tr->imask.as<double>(), w.p.as<double>(), w.q.as<double>(),
                          w.scal.as<Scal>(), w.partials.as<double>(), w.counters.as<unsigned>());
@@ -910,7 +910,7 @@ namespace {
 
 // grid field v = c * I (mask * x): gather of vertex values at every node
 template <int D>
-__global__ void k_gather_grid(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+__global__ void k_gather_grid(GridGeom g, const ElemRec<D>* __restrict__ recs,
                               const int* __restrict__ elem, const double* __restrict__ x,
                               const double* __restrict__ mask, long long n_nodes, double c, double* __restrict__ v) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -922,7 +922,7 @@ __global__ void k_gather_grid(GridGeom g, const double* __restrict__ X, const in
   }
   int vid[D + 1];
   double lam[D + 1];
-  node_weights<D>(g, X, elems, e, k, vid, lam);
+  node_weights<D>(g, recs, e, k, vid, lam);
   double s = 0.0;
   for (int r = 0; r <= D; ++r) s += lam[r] * mask[vid[r]] * x[vid[r]];
   v[k] = c * s;
@@ -966,7 +966,7 @@ __device__ void inverse_E(const double* V, double* Ei) {
 //   sum_r G_r(k) * (-(E^{-1})_{r,a} phi_i(x_k)),  G_r = lam_{v_r} r_k - (A I lam)_k u_{v_r}
 // One thread per vertex, nodes in ascending order: deterministic.
 template <int D>
-__global__ void k_grad_X(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+__global__ void k_grad_X(GridGeom g, const double* __restrict__ X, const ElemRec<D>* __restrict__ recs,
                          const int* __restrict__ elem, const int* __restrict__ off, const int* __restrict__ node,
                          long long nv, const double* __restrict__ u, const double* __restrict__ lam_v,
                          const double* __restrict__ mask, const double* __restrict__ rgrid,
@@ -979,7 +979,7 @@ __global__ void k_grad_X(GridGeom g, const double* __restrict__ X, const int* __
     const int e = elem[k];
     int vid[D + 1];
     double phi[D + 1];
-    node_weights<D>(g, X, elems, e, k, vid, phi);
+    node_weights<D>(g, recs, e, k, vid, phi);
     int i = 0;
     for (int r = 0; r <= D; ++r)
       if (vid[r] == (int)j) i = r;
@@ -1038,9 +1038,8 @@ extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, 
   g.h = tr->h;
   for (int a = 0; a < 3; ++a) g.lo[a] = tr->lo[a];
   if (grad_f)
-    hipLaunchKernelGGL(k_gather_grid<2>, dim3(grid1(nn, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
-                       tr->elems.as<int>(), tr->elem.as<int>(), lam.as<double>(), tr->imask.as<double>(), nn,
-                       op->h2s, grad_f);
+    hipLaunchKernelGGL(k_gather_grid<2>, dim3(grid1(nn, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec2>(),
+                       tr->elem.as<int>(), lam.as<double>(), tr->imask.as<double>(), nn, op->h2s, grad_f);
   if (grad_X) {
     DevBuf yu, yl, rg;
     GOFD_TRY(dev_reserve(ctx, yu, sizeof(double) * nn));
@@ -1060,7 +1059,7 @@ extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, 
     hipLaunchKernelGGL(k_mask_copy, dim3(grid1(nv, 256)), dim3(256), 0, st, u, tr->imask.as<double>(), nv,
                        w.x.as<double>());
     hipLaunchKernelGGL(k_grad_X<2>, dim3(grid1(nv, 128)), dim3(128), 0, st, g, tr->X.as<double>(),
-                       tr->elems.as<int>(), tr->elem.as<int>(), tr->csc_off.as<int>(), tr->csc_node.as<int>(), nv,
+                       tr->rec.as<ElemRec2>(), tr->elem.as<int>(), tr->csc_off.as<int>(), tr->csc_node.as<int>(), nv,
                        w.x.as<double>(), lam.as<double>(), tr->imask.as<double>(), rg.as<double>(), yl.as<double>(),
                        grad_X);
     HIP_TRY(ctx, hipGetLastError());

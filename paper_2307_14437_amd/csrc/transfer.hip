@@ -138,7 +138,17 @@ __global__ void k_count(const int* __restrict__ elem_of_node, const int* __restr
 }
 
 template <int D>
-__global__ void k_fill_csc(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+__global__ void k_make_records(const double* __restrict__ X, const int* __restrict__ elems, long long ne,
+                               ElemRec<D>* __restrict__ recs) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  ElemRec<D> r;
+  make_record<D>(X, elems, e, r);
+  recs[e] = r;
+}
+
+template <int D>
+__global__ void k_fill_csc(GridGeom g, const ElemRec<D>* __restrict__ recs,
                            const int* __restrict__ elem_of_node, long long n, int* __restrict__ cursor,
                            int* __restrict__ node_out, double* __restrict__ w_out) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -147,7 +157,7 @@ __global__ void k_fill_csc(GridGeom g, const double* __restrict__ X, const int* 
   if (e < 0) return;
   int vid[D + 1];
   double lam[D + 1];
-  node_weights<D>(g, X, elems, e, k, vid, lam);
+  node_weights<D>(g, recs, e, k, vid, lam);
   for (int r = 0; r <= D; ++r) {
     const int pos = atomicAdd(&cursor[vid[r]], 1);
     node_out[pos] = (int)k;
@@ -194,7 +204,7 @@ __global__ void k_colsum(const int* __restrict__ off, long long nv, const double
 }
 
 template <int D>
-__global__ void k_export_ell(GridGeom g, const double* __restrict__ X, const int* __restrict__ elems,
+__global__ void k_export_ell(GridGeom g, const ElemRec<D>* __restrict__ recs,
                              const int* __restrict__ elem_of_node, long long n, int* __restrict__ verts,
                              double* __restrict__ wts) {
   long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +219,7 @@ __global__ void k_export_ell(GridGeom g, const double* __restrict__ X, const int
   }
   int vid[D + 1];
   double lam[D + 1];
-  node_weights<D>(g, X, elems, e, k, vid, lam);
+  node_weights<D>(g, recs, e, k, vid, lam);
   for (int r = 0; r <= D; ++r) {
     if (verts) verts[k * (D + 1) + r] = vid[r];
     if (wts) wts[k * (D + 1) + r] = lam[r];
@@ -347,6 +357,13 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   HIP_TRY(ctx, hipMemcpyAsync(tr->elems.p, elems_dev, sizeof(int32_t) * ne * (d + 1), hipMemcpyDeviceToDevice, st));
 
   GridGeom g = make_geom(tr);
+  GOFD_TRY(dev_reserve(ctx, tr->rec, (d == 2 ? sizeof(ElemRec2) : sizeof(ElemRec3)) * ne));
+  if (d == 2)
+    hipLaunchKernelGGL(k_make_records<2>, dim3(grid1(ne, 256)), dim3(256), 0, st, tr->X.as<double>(),
+                       tr->elems.as<int>(), (long long)ne, tr->rec.as<ElemRec2>());
+  else
+    hipLaunchKernelGGL(k_make_records<3>, dim3(grid1(ne, 256)), dim3(256), 0, st, tr->X.as<double>(),
+                       tr->elems.as<int>(), (long long)ne, tr->rec.as<ElemRec3>());
   unsigned long long* counters = ctx->scratch.as<unsigned long long>();
   HIP_TRY(ctx, hipMemsetAsync(counters, 0, 8 * sizeof(unsigned long long), st));
   hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(), n_nodes, NO_ELEM);
@@ -393,13 +410,11 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   GOFD_TRY(scan_exclusive_i32(ctx, cnt.as<int32_t>(), tr->csc_off.as<int32_t>(), nv));
   HIP_TRY(ctx, hipMemcpyAsync(cursor.p, tr->csc_off.p, sizeof(int32_t) * (nv + 1), hipMemcpyDeviceToDevice, st));
   if (d == 2)
-    hipLaunchKernelGGL(k_fill_csc<2>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
-                       tr->elems.as<int>(), tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(),
-                       w_tmp.as<double>());
+    hipLaunchKernelGGL(k_fill_csc<2>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec2>(),
+                       tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(), w_tmp.as<double>());
   else
-    hipLaunchKernelGGL(k_fill_csc<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
-                       tr->elems.as<int>(), tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(),
-                       w_tmp.as<double>());
+    hipLaunchKernelGGL(k_fill_csc<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec3>(),
+                       tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(), w_tmp.as<double>());
   hipLaunchKernelGGL(k_sort_segments, dim3(grid1(nv * 64, 256)), dim3(256), 0, st, tr->csc_off.as<int>(),
                      (long long)nv, node_tmp.as<int>(), w_tmp.as<double>(), tr->csc_node.as<int>(),
                      tr->csc_w.as<double>());
@@ -470,10 +485,10 @@ extern "C" int gofd_transfer_export(gofd_ctx ctx, gofd_transfer tr, int part, vo
       double* ww = part == GOFD_TR_ELL_WEIGHTS ? static_cast<double*>(dst) : nullptr;
       if (d == 2)
         hipLaunchKernelGGL(k_export_ell<2>, dim3(grid1(tr->n_nodes, 256)), dim3(256), 0, st, g,
-                           tr->X.as<double>(), tr->elems.as<int>(), tr->elem.as<int>(), (long long)tr->n_nodes, vv, ww);
+                           tr->rec.as<ElemRec2>(), tr->elem.as<int>(), (long long)tr->n_nodes, vv, ww);
       else
         hipLaunchKernelGGL(k_export_ell<3>, dim3(grid1(tr->n_nodes, 256)), dim3(256), 0, st, g,
-                           tr->X.as<double>(), tr->elems.as<int>(), tr->elem.as<int>(), (long long)tr->n_nodes, vv, ww);
+                           tr->rec.as<ElemRec3>(), tr->elem.as<int>(), (long long)tr->n_nodes, vv, ww);
       break;
     }
     case GOFD_TR_CSC_OFFSETS:
@@ -504,9 +519,9 @@ extern "C" int gofd_transfer_export(gofd_ctx ctx, gofd_transfer tr, int part, vo
 // owns one vertex; lanes stride through the column (ascending node order) and
 // the partial sums are combined with cross-lane shuffles, always in the same
 // order, so the result is deterministic.
-template <typename Y, int G>
+template <typename Y, typename WT, int G>
 __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ off, const int* __restrict__ node,
-                                                 const double* __restrict__ w, const Y* __restrict__ y,
+                                                 const WT* __restrict__ w, const Y* __restrict__ y,
                                                  long long nv, long long n_nodes, int nrhs,
                                                  const double* __restrict__ scale, const double* __restrict__ mask,
                                                  double* __restrict__ z) {
@@ -518,7 +533,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ off, co
   const int b = off[v], e = off[v + 1];
   const Y* yr = y + (long long)rhs * n_nodes;
   double acc = 0.0;
-  for (int i = b + lane; i < e; i += G) acc += w[i] * (double)yr[node[i]];
+  for (int i = b + lane; i < e; i += G) acc += (double)w[i] * (double)yr[node[i]];
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
   if (lane == 0) {
@@ -534,11 +549,11 @@ int scatter_apply(gofd_ctx_s* ctx, const gofd_transfer_s* tr, int nrhs, const vo
   constexpr int G = 16;
   dim3 grid(grid1(tr->nv * G, 256), nrhs);
   if (fp32)
-    hipLaunchKernelGGL((k_scatter<float, G>), grid, dim3(256), 0, ctx->stream, tr->csc_off.as<int>(),
-                       tr->csc_node.as<int>(), tr->csc_w.as<double>(), static_cast<const float*>(y),
+    hipLaunchKernelGGL((k_scatter<float, float, G>), grid, dim3(256), 0, ctx->stream, tr->csc_off.as<int>(),
+                       tr->csc_node.as<int>(), tr->csc_w32.as<float>(), static_cast<const float*>(y),
                        (long long)tr->nv, (long long)tr->n_nodes, nrhs, scale, mask, z);
   else
-    hipLaunchKernelGGL((k_scatter<double, G>), grid, dim3(256), 0, ctx->stream, tr->csc_off.as<int>(),
+    hipLaunchKernelGGL((k_scatter<double, double, G>), grid, dim3(256), 0, ctx->stream, tr->csc_off.as<int>(),
                        tr->csc_node.as<int>(), tr->csc_w.as<double>(), static_cast<const double*>(y),
                        (long long)tr->nv, (long long)tr->n_nodes, nrhs, scale, mask, z);
   HIP_TRY(ctx, hipGetLastError());
