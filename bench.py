@@ -158,8 +158,8 @@ def main():
 
     # roofline of the dominant kernel (pass B, FP32 grid, the mode the step runs in)
     kt = {}
-    for name, which in (("passA", gofd.K_PASS_A), ("passB", gofd.K_PASS_B), ("passC", gofd.K_PASS_C),
-                        ("scatter", gofd.K_SCATTER)):
+    for name, which in (("gather", gofd.K_GATHER), ("passA", gofd.K_PASS_A), ("passB", gofd.K_PASS_B),
+                        ("passC", gofd.K_PASS_C), ("scatter", gofd.K_SCATTER)):
         kt[name] = gofd.time_kernel(ctx, tr, ops[1], which, u, gofd.FP32_GRID, reps=50)
     half = 2 * g.N + 1
     bytes_B = _bytes_passB(W, half, 4) * half

@@ -200,13 +200,13 @@ int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const 
                   double* y_dev, int flags);
 
 /* Timing of one kernel of the K product in isolation (for roofline reports):
- * launches kernel `which` (GOFD_K_PASS_A: gather + first FFT pass, PASS_B: the
+ * launches kernel `which` (GOFD_K_PASS_A: first FFT pass (rows), PASS_B: the
  * column pass with the spectral multiply, PASS_C: last FFT pass, SCATTER: the
- * I^T reduction) `reps` times on the library's stream between two HIP events,
+ * I^T reduction, GATHER: the interpolation I u onto the grid) `reps` times on the library's stream between two HIP events,
  * after one untimed launch, with nrhs fields taken from u_dev (N_v doubles
  * each), and writes the average duration in milliseconds to *avg_ms (host).
  * Synchronises.  Errors: GOFD_E_ARG, GOFD_E_HIP. */
-enum { GOFD_K_PASS_A = 0, GOFD_K_PASS_B = 1, GOFD_K_PASS_C = 2, GOFD_K_SCATTER = 3 };
+enum { GOFD_K_PASS_A = 0, GOFD_K_PASS_B = 1, GOFD_K_PASS_C = 2, GOFD_K_SCATTER = 3, GOFD_K_GATHER = 4 };
 int gofd_time_kernel(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int which, int nrhs, const double* u_dev,
                      int flags, int reps, double* avg_ms);
 

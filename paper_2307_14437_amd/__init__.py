@@ -131,7 +131,7 @@ EXPORTED = [
     "gofd_solve_adjoint", "gofd_time_kernel",
 ]
 
-K_PASS_A, K_PASS_B, K_PASS_C, K_SCATTER = 0, 1, 2, 3
+K_PASS_A, K_PASS_B, K_PASS_C, K_SCATTER, K_GATHER = 0, 1, 2, 3, 4
 
 
 def _ptr(t):

@@ -20,10 +20,11 @@
 #include <memory>
 
 #include "bary.h"
+#include "cg_state.h"
 #include "fft.h"
 #include "internal.h"
 
-using gofd_fft::fft_line;
+using gofd_fft::fft_regs;
 using gofd_fft::padded_len;
 using gofd_fft::pidx;
 
@@ -31,40 +32,43 @@ namespace {
 
 inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2); renumber them so that logically adjacent blocks share an XCD.
-__device__ __forceinline__ int xcd_remap(int b, int n) {
-  const int per = n / 8, rem = n % 8;
-  const int x = b % 8, i = b / 8;
-  const int start = (x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
-  return start + i;
-}
-
 // ---------------------------------------------------------------- sources
 
-struct SrcGrid {
-  const double* v;
-  long long n_nodes;
-  __device__ __forceinline__ double operator()(int rhs, long long k) const { return v[rhs * n_nodes + k]; }
+// Optional per-rhs flag (a converged solve): blocks of a finished rhs return at once.
+struct Skip {
+  const int* flag;
+  int stride;
+  __device__ __forceinline__ bool operator()(int rhs) const { return flag && flag[(long long)rhs * stride]; }
 };
 
-template <int D>
-struct SrcGather {
-  GridGeom g;
-  const ElemRec<D>* recs;
-  const int* elem;
-  const double* u;
-  const double* scale;
-  const double* mask;
-  long long nv;
-  __device__ __forceinline__ double operator()(int rhs, long long k) const {
-    const int e = elem[k];
-    if (e < 0) return 0.0;
+template <typename T>
+struct SrcGrid {
+  const T* v;
+  long long n_nodes;
+  __device__ __forceinline__ T operator()(int rhs, long long k) const { return v[rhs * n_nodes + k]; }
+};
+
+// v = I u on the grid (eq. GoFD-1's interpolation): one thread per node, the
+// weights from the record of the node's element; zero outside the mesh.  The
+// optional per-vertex scale and mask multiply u first.  Kept apart from the
+// row transform so that the dependent loads (element, record, vertex values)
+// run with one node per thread.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_gather(GridGeom g, const ElemRec<D>* __restrict__ recs,
+                                                const int* __restrict__ elem, const double* __restrict__ u,
+                                                const double* __restrict__ scale, const double* __restrict__ mask,
+                                                long long nv, long long n_nodes, R* __restrict__ out, Skip skip) {
+  const long long k = (long long)xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (k >= n_nodes) return;
+  const int e = elem[k];
+  if (skip(rhs)) return;
+  double s = 0.0;
+  if (e >= 0) {
     int vid[D + 1];
     double lam[D + 1];
     node_weights<D>(g, recs, e, k, vid, lam);
     const double* ur = u + rhs * nv;
-    double s = 0.0;
 #pragma unroll
     for (int r = 0; r <= D; ++r) {
       double uv = ur[vid[r]];
@@ -72,16 +76,32 @@ struct SrcGather {
       if (mask) uv *= mask[vid[r]];
       s += lam[r] * uv;
     }
-    return s;
   }
-};
+  out[rhs * n_nodes + k] = (R)s;
+}
+
+// ---------------------------------------------------------------- spectra layout
+// Z holds, per rhs, the L/2 column slots of the W window rows after the row
+// transform, in tiles of four slots: Z[slot/4][row][slot%4].  A block of the
+// column pass reads one tile as a contiguous stretch, and a row pair of the
+// row passes touches 2 x 4 consecutive entries per tile.  Slot c > 0 is
+// spectrum column k0 = c; slot 0 carries the two real columns k0 = 0 and
+// k0 = L/2 packed as one complex value (both are exactly real for real rows).
+template <typename R>
+__device__ __forceinline__ long long zidx(int slot, int row, int W) {
+  return ((long long)(slot >> 2) * W + row) * 4 + (slot & 3);
+}
 
 // ---------------------------------------------------------------- pass A
-// LINES row pairs per block, TPL threads per row pair.
-template <typename R, int L, int LINES, int TPL, class Src>
-__global__ __launch_bounds__(LINES* TPL) void k_passA(Src src, cplx<R>* __restrict__ Z, int W, int half,
-                                                      const cplx<R>* __restrict__ tw, long long zs) {
-  constexpr int PL = padded_len<L>();
+// LINES row pairs per block, TPL = L/E threads per row pair.  Two real rows
+// are packed as one complex line (a + i b); after the forward transform the
+// half spectra are split off with the mirror entry L - k.
+template <typename R, int L, int E, int LINES, class Src>
+__global__ __launch_bounds__(LINES*(L / E)) void k_passA(Src src, cplx<R>* __restrict__ Z, int W,
+                                                         const cplx<R>* __restrict__ tw, long long zs, Skip skip) {
+  constexpr int TPL = L / E;
+  constexpr int PL = padded_len<L, E>();
+  constexpr int H = L / 2;
   __shared__ cplx<R> sbuf[LINES * PL];
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
@@ -89,152 +109,253 @@ __global__ __launch_bounds__(LINES* TPL) void k_passA(Src src, cplx<R>* __restri
   const int rhs = blockIdx.y;
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
+  cplx<R> v[E];
 #pragma unroll
-  for (int m = t; m < L; m += TPL) {
-    R a = 0, b = 0;
-    if (m < W) {
-      if (has0) a = (R)src(rhs, (long long)row0 * W + m);
-      if (has1) b = (R)src(rhs, (long long)(row0 + 1) * W + m);
+  for (int m = 0; m < E; ++m) {
+    const int col = t + m * TPL;       // columns beyond L/2 are outside the window (W <= L/2 + 1)
+    R x = 0, y = 0;
+    if (m <= E / 2 && col < W) {
+      if (has0) x = (R)src(rhs, (long long)row0 * W + col);
+      if (has1) y = (R)src(rhs, (long long)(row0 + 1) * W + col);
     }
-    buf[pidx<L>(m)] = {a, b};
+    v[m] = {x, y};
   }
+  // the finished-rhs test after the loads, so that its latency overlaps theirs
+  if (skip(rhs)) return;
+  fft_regs<R, L, E, false>(v, buf, tw, t);
   __syncthreads();
-  fft_line<R, L, TPL, false>(buf, tw, t);
+#pragma unroll
+  for (int m = 0; m < E; ++m) buf[pidx<E>(t + m * TPL)] = v[m];
+  __syncthreads();
   if (!has0) return;
-  cplx<R>* z0 = Z + rhs * zs + (long long)row0 * half;
-  for (int k = t; k < half; k += TPL) {
-    const cplx<R> zk = buf[pidx<L>(k)];
-    const cplx<R> zm = buf[pidx<L>((L - k) & (L - 1))];
-    z0[k] = {(zk.x + zm.x) * (R)0.5, (zk.y - zm.y) * (R)0.5};
-    if (has1) z0[half + k] = {(zk.y + zm.y) * (R)0.5, (zm.x - zk.x) * (R)0.5};
+  cplx<R>* Zr = Z + rhs * zs;
+#pragma unroll
+  for (int q = 0; q < E / 2; ++q) {
+    const int k = t + q * TPL;
+    cplx<R> z0, z1;
+    if (k == 0) {
+      const cplx<R> dc = buf[pidx<E>(0)], nq = buf[pidx<E>(H)];
+      z0 = {dc.x, nq.x};
+      z1 = {dc.y, nq.y};
+    } else {
+      const cplx<R> zk = buf[pidx<E>(k)], zm = buf[pidx<E>(L - k)];
+      z0 = {(zk.x + zm.x) * (R)0.5, (zk.y - zm.y) * (R)0.5};
+      z1 = {(zk.y + zm.y) * (R)0.5, (zm.x - zk.x) * (R)0.5};
+    }
+    cplx<R>* dst = Zr + zidx<R>(k, row0, W);
+    dst[0] = z0;
+    if (has1) dst[4] = z1;
   }
 }
 
 // ---------------------------------------------------------------- pass B
-// Column slots 0..L/2-1: slot c > 0 is spectrum column k0 = c; slot 0 carries
-// the two real columns k0 = 0 and k0 = L/2 packed as one complex column
-// (after pass A both are exactly real), so the slots divide evenly into blocks.
-// For the packed slot, with C = FFT(a + i b) and m = L - k:
+// LB column slots per block (LB divides the tile width 4), TPL threads each.
+// Forward FFT along the rows (W nonzero of L), multiply by the real spectrum,
+// inverse FFT, keep the W window rows; the product happens in registers
+// between the last forward and the first inverse stage.  For the packed slot
+// 0, with C = FFT(a + i b) and m = L - k:
 //   A_k = (C_k + conj C_m)/2,  i B_k = (C_k - conj C_m)/2, and the product
 //   D = T0 A + i T1 B gives D_k = (T0+T1)/2 C_k + (T0-T1)/2 conj C_m;
 // the inverse FFT of D is (T0 * a) + i (T1 * b) with both parts real.
-template <typename R, int L, int LINES, int NT>
-__global__ __launch_bounds__(NT) void k_passB(cplx<R>* __restrict__ Z, int W, int half, const R* __restrict__ That,
-                                              const cplx<R>* __restrict__ tw, long long zs) {
-  constexpr int TPL = NT / LINES;
-  constexpr int PL = padded_len<L>();
-  constexpr int NQ = L / 2;                 // Nyquist column
-  __shared__ cplx<R> buf[LINES * PL];
+//
+// With dpart given, the block also leaves the partial sum of
+//   (A v, v) = sum_k That_k |V_k|^2   (Parseval for the circulant embedding;
+// the half spectrum counts the columns 0 < k0 < L/2 twice), which is the
+// (K u, u) of CG when v = I u, and the sums of its slice of the level-1
+// partials of gamma and (r, r): dpart[rhs][q][block], q = gamma, (r, r), delta.
+template <typename R, int L, int E, int LB, bool DOT>
+__global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, int W, int half,
+                                                      const R* __restrict__ That, const cplx<R>* __restrict__ tw,
+                                                      long long zs, Skip skip, double* __restrict__ dpart,
+                                                      gofd_cg::Level1 lv1) {
+  constexpr int TPL = L / E;
+  constexpr int PL = padded_len<L, E>();
+  constexpr int H = L / 2;
+  constexpr int NT = LB * TPL;
+  __shared__ cplx<R> sbuf[LB * PL];
+  __shared__ double shd[gofd_cg::block_sum_lds<NT, 3>()];
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int rhs = blockIdx.y;
-  const int k0 = b * LINES;
-  cplx<R>* Zr = Z + rhs * zs;
+  const int c = threadIdx.x % LB, t = threadIdx.x / LB;
+  cplx<R>* buf = sbuf + c * PL;
+  const int slot = b * LB + c;
+  cplx<R>* Zc = Z + blockIdx.y * zs + zidx<R>(slot, 0, W);
+  cplx<R> v[E];
 #pragma unroll
-  for (int idx = threadIdx.x; idx < L * LINES; idx += NT) {
-    const int c = idx % LINES, i = idx / LINES;
-    const int col = k0 + c;
-    cplx<R> v = {0, 0};
-    if (i < W) {
-      if (col == 0)
-        v = {Zr[(long long)i * half].x, Zr[(long long)i * half + NQ].x};
-      else
-        v = Zr[(long long)i * half + col];
-    }
-    buf[c * PL + pidx<L>(i)] = v;
+  for (int m = 0; m < E; ++m) {
+    const int i = t + m * TPL;
+    v[m] = (m <= E / 2 && i < W) ? Zc[(long long)i * 4] : cplx<R>{0, 0};
   }
-  __syncthreads();
-  const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
-  cplx<R>* lb = buf + line * PL;
-  fft_line<R, L, TPL, false>(lb, tw, t);
+  // multipliers of this slot, fetched before the transform; element k1 of the
+  // line takes row min(k1, L - k1) of the stored (L/2+1)-row spectrum column
+  // (for slot 0 this is column k0 = 0; column L/2 is read when it is used)
+  R pm[E];
   {
-    const int col = k0 + line;
-    if (col == 0) {
-      for (int k1 = t; k1 <= L / 2; k1 += TPL) {
-        const int m = (L - k1) & (L - 1);
-        const R t0 = That[k1];                            // multiplier column k0 = 0
-        const R t1 = That[(long long)NQ * half + k1];     // multiplier column k0 = L/2
-        const R p = (t0 + t1) * (R)0.5, q = (t0 - t1) * (R)0.5;
-        const cplx<R> ck = lb[pidx<L>(k1)], cm = lb[pidx<L>(m)];
-        lb[pidx<L>(k1)] = {p * ck.x + q * cm.x, p * ck.y - q * cm.y};
-        if (m != k1) lb[pidx<L>(m)] = {p * cm.x + q * ck.x, p * cm.y - q * ck.y};
-      }
-    } else {
-      const R* Tc = That + (long long)col * half;
-      for (int k1 = t; k1 < L; k1 += TPL) {
-        const int kk = (k1 <= L / 2) ? k1 : L - k1;
-        const R mlt = Tc[kk];
-        cplx<R> v = lb[pidx<L>(k1)];
-        lb[pidx<L>(k1)] = {v.x * mlt, v.y * mlt};
+    const R* Tc = That + (long long)slot * half;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k1 = t + m * TPL;
+      pm[m] = Tc[(k1 <= H) ? k1 : L - k1];
+    }
+  }
+  // this block's slice of the level-1 partials (usually one value per thread)
+  double red[3] = {0.0, 0.0, 0.0};
+  if constexpr (DOT) {
+    const int chunk = (lv1.n1 + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * chunk, hi = min(lo + chunk, lv1.n1);
+    for (int i = lo + threadIdx.x; i < hi; i += NT) {
+      red[0] += lv1.partG[(long long)blockIdx.y * lv1.n1 + i];
+      red[1] += lv1.partR[(long long)blockIdx.y * lv1.n1 + i];
+    }
+  }
+  if (skip(blockIdx.y)) return;
+  double& dacc = red[2];
+  fft_regs<R, L, E, false>(v, buf, tw, t);
+  if (b == 0) {                     // block-uniform: this block holds slot 0
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) buf[pidx<E>(t + m * TPL)] = v[m];
+    __syncthreads();
+    if (c == 0) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int k1 = t + m * TPL;
+        const R t0 = pm[m];                                                  // column k0 = 0
+        const R t1 = That[(long long)H * half + ((k1 <= H) ? k1 : L - k1)];  // column k0 = L/2
+        const R pp = (t0 + t1) * (R)0.5, qq = (t0 - t1) * (R)0.5;
+        const cplx<R> ck = v[m], cm = buf[pidx<E>((L - k1) & (L - 1))];
+        if constexpr (DOT) {
+          // columns k0 = 0 and L/2: A = (C_k + conj C_m)/2, B = (C_k - conj C_m)/(2i)
+          const double ax = (double)ck.x + cm.x, ay = (double)ck.y - cm.y;
+          const double bx = (double)ck.y + cm.y, by = (double)ck.x - cm.x;
+          dacc += 0.25 * ((double)t0 * (ax * ax + ay * ay) + (double)t1 * (bx * bx + by * by));
+        }
+        v[m] = {pp * ck.x + qq * cm.x, pp * ck.y - qq * cm.y};
       }
     }
   }
-  __syncthreads();
-  fft_line<R, L, TPL, true>(lb, tw, t);
-#pragma unroll 4
-  for (int idx = threadIdx.x; idx < W * LINES; idx += NT) {
-    const int c = idx % LINES, i = idx / LINES;
-    const int col = k0 + c;
-    const cplx<R> v = buf[c * PL + pidx<L>(i)];
-    if (col == 0) {
-      Zr[(long long)i * half] = {v.x, (R)0};
-      Zr[(long long)i * half + NQ] = {v.y, (R)0};
-    } else {
-      Zr[(long long)i * half + col] = v;
+  if (slot != 0) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      if constexpr (DOT) dacc += 2.0 * (double)pm[m] * ((double)v[m].x * v[m].x + (double)v[m].y * v[m].y);
+      v[m] = {v[m].x * pm[m], v[m].y * pm[m]};
     }
+  }
+  if constexpr (DOT) {
+    static_assert(NT % 64 == 0 || NT < 64, "block size");
+    gofd_cg::block_sum_n<NT, 3>(red, shd);
+    if (threadIdx.x == 0) {
+      double* d = dpart + (long long)blockIdx.y * 3 * gridDim.x;
+      d[blockIdx.x] = red[0];
+      d[gridDim.x + blockIdx.x] = red[1];
+      d[2 * gridDim.x + blockIdx.x] = red[2];
+    }
+  }
+  __syncthreads();
+  fft_regs<R, L, E, true>(v, buf, tw, t);
+#pragma unroll
+  for (int m = 0; m <= E / 2; ++m) {
+    const int i = t + m * TPL;
+    if (i < W) Zc[(long long)i * 4] = v[m];
   }
 }
 
 // ---------------------------------------------------------------- pass C
-template <typename R, typename Y, int L, int LINES, int TPL>
-__global__ __launch_bounds__(LINES* TPL) void k_passC(const cplx<R>* __restrict__ Z, int W, int half,
-                                                      const cplx<R>* __restrict__ tw, long long zs,
-                                                      Y* __restrict__ y, long long n_nodes) {
-  constexpr int PL = padded_len<L>();
+// Row pairs: rebuild the Hermitian spectra of two real rows as one complex
+// line (a + i b at k, conj(a) + i conj(b) at L - k), inverse FFT, write the
+// W window values of both rows.
+//
+// With fin active, one extra block (the last) finishes the CG reductions of
+// the iteration instead (the step's scalars are needed only by later
+// kernels), concurrently with the transforms.
+template <typename R, typename Y, int L, int E, int LINES>
+__global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restrict__ Z, int W,
+                                                         const cplx<R>* __restrict__ tw, long long zs,
+                                                         Y* __restrict__ y, long long n_nodes, Skip skip,
+                                                         gofd_cg::Finish fin) {
+  constexpr int TPL = L / E;
+  constexpr int PL = padded_len<L, E>();
+  constexpr int H = L / 2;
+  constexpr int NT = LINES * TPL;
   __shared__ cplx<R> sbuf[LINES * PL];
+  __shared__ double shf[gofd_cg::block_sum_lds<NT, 3>()];
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
   const int row0 = (blockIdx.x * LINES + line) * 2;
   const int rhs = blockIdx.y;
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
-  const cplx<R>* z0 = Z + rhs * zs + (long long)row0 * half;
-#pragma unroll 4
-  for (int k = t; k < half; k += TPL) {
-    cplx<R> a = has0 ? z0[k] : cplx<R>{0, 0};
-    cplx<R> b = has1 ? z0[half + k] : cplx<R>{0, 0};
-    if (k == 0 || k == L / 2) {
-      a.y = 0;
-      b.y = 0;
-    }
-    buf[pidx<L>(k)] = {a.x - b.y, a.y + b.x};                                 // a + i b
-    if (k > 0 && k < L / 2) buf[pidx<L>(L - k)] = {a.x + b.y, b.x - a.y};     // conj(a) + i conj(b)
+  const cplx<R>* Zr = Z + rhs * zs;
+  if (fin.sc && blockIdx.x == gridDim.x - 1) {     // block-uniform: the finishing block
+    fin.run<NT>(rhs, shf);
+    return;
   }
-  __syncthreads();
-  fft_line<R, L, TPL, true>(buf, tw, t);
+  cplx<R> v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + m * TPL;
+    const bool dcnq = (m == 0 || m == E / 2) && t == 0;      // k = 0 or k = L/2: packed slot 0
+    const bool mirror = !dcnq && m >= E / 2;                  // k > L/2: conjugate of slot L - k
+    const int sl = dcnq ? 0 : (mirror ? L - k : k);
+    const cplx<R> a = has0 ? Zr[zidx<R>(sl, row0, W)] : cplx<R>{0, 0};
+    const cplx<R> bb = has1 ? Zr[zidx<R>(sl, row0 + 1, W)] : cplx<R>{0, 0};
+    if (dcnq)
+      v[m] = (m == 0) ? cplx<R>{a.x, bb.x} : cplx<R>{a.y, bb.y};
+    else if (mirror)
+      v[m] = {a.x + bb.y, bb.x - a.y};                        // conj(a) + i conj(b)
+    else
+      v[m] = {a.x - bb.y, a.y + bb.x};                        // a + i b
+  }
+  if (skip(rhs)) return;
+  fft_regs<R, L, E, true>(v, buf, tw, t);
   if (!has0) return;
   Y* yr = y + rhs * n_nodes + (long long)row0 * W;
-  for (int m = t; m < W; m += TPL) {
-    const cplx<R> v = buf[pidx<L>(m)];
-    yr[m] = (Y)v.x;
-    if (has1) yr[W + m] = (Y)v.y;
+#pragma unroll
+  for (int m = 0; m <= E / 2; ++m) {
+    const int col = t + m * TPL;
+    if (col < W) {
+      yr[col] = (Y)v[m].x;
+      if (has1) yr[W + col] = (Y)v[m].y;
+    }
   }
 }
 
 // ---------------------------------------------------------------- launch
 
-template <int L>
+// Values per thread of the row passes (A, C) and of the column pass (B):
+// build-time tuning knobs, powers of two in 4..16.
+#ifndef GOFD_FFT_E_ROWS
+#define GOFD_FFT_E_ROWS 16
+#endif
+#ifndef GOFD_FFT_E_COLS
+#define GOFD_FFT_E_COLS 16
+#endif
+// most column slots per block of pass B (1, 2 or 4)
+#ifndef GOFD_FFT_LB
+#define GOFD_FFT_LB 2
+#endif
+
+template <typename R, int L>
 struct Cfg {
-  static constexpr int TPL = (L / 8 < 512) ? L / 8 : 512;                  // threads per line
-  static constexpr int LINES_A = (TPL >= 64) ? 1 : 64 / TPL;               // row pairs per block
-  static constexpr int LINES_B = (L <= 256) ? ((L / 2 >= 8) ? 8 : L / 2) : (L <= 2048 ? 4 : 2);   // columns per block
-  static constexpr int NT_A = LINES_A * TPL;
-  static constexpr int NT_B = LINES_B * TPL;
+  static constexpr int EA = (L >= GOFD_FFT_E_ROWS) ? GOFD_FFT_E_ROWS : L;
+  static constexpr int TA = L / EA;                                         // threads per row pair
+  static constexpr int LINES_A = (TA >= 64) ? 1 : 64 / TA;                  // row pairs per block
+  static constexpr int EB = (L >= GOFD_FFT_E_COLS) ? GOFD_FFT_E_COLS : L;
+  static constexpr int TB = L / EB;                                         // threads per column slot
+  static constexpr int LINE_BYTES = padded_len<L, EB>() * (int)sizeof(cplx<R>);
+  static constexpr int LB_MEM = (GOFD_FFT_LB >= 4 && 4 * LINE_BYTES <= 150 * 1024)
+                                    ? 4
+                                    : ((GOFD_FFT_LB >= 2 && 2 * LINE_BYTES <= 150 * 1024) ? 2 : 1);
+  static constexpr int LB = (LB_MEM * TB <= 1024) ? LB_MEM : ((2 * TB <= 1024) ? 2 : 1);   // slots per block
+  static_assert(4 % LB == 0 && (L / 2) % 4 == 0, "tile layout");
+  static_assert(LINES_A * TA <= 1024 && LINES_A * padded_len<L, EA>() * (int)sizeof(cplx<R>) <= 150 * 1024,
+                "row pass block");
 };
 
 template <typename R, int L, class Src, typename Y>
-int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes = 7) {
+int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
+           double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin) {
   const int W = op->W, half = op->half;
-  const long long zs = (long long)W * half;
+  const long long zs = (long long)W * (L / 2);
   const cplx<R>* tw;
   const R* That;
   if constexpr (sizeof(R) == 8) {
@@ -245,39 +366,44 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
     That = op->That32.as<R>();
   }
   if (!tw) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
+  if (2 * (W - 1) > L) return gofd_fail(ctx, GOFD_E_ARG, "internal: window wider than half the period");
   GOFD_TRY(dev_reserve(ctx, op->Z, sizeof(cplx<R>) * zs * nrhs));
   cplx<R>* Z = op->Z.as<cplx<R>>();
-  using C = Cfg<L>;
+  using C = Cfg<R, L>;
   const int pairs = (W + 1) / 2;
   const int nbA = (pairs + C::LINES_A - 1) / C::LINES_A;
   hipStream_t st = ctx->stream;
   if (passes & 1)
-    hipLaunchKernelGGL((k_passA<R, L, C::LINES_A, C::TPL, Src>), dim3(nbA, nrhs), dim3(C::NT_A), 0, st, src, Z, W,
-                       half, tw, zs);
-  const int nb = (L / 2) / Cfg<L>::LINES_B;     // column slots 0..L/2-1 (DC and Nyquist share slot 0)
-  if (passes & 2)
-    hipLaunchKernelGGL((k_passB<R, L, Cfg<L>::LINES_B, Cfg<L>::NT_B>), dim3(nb, nrhs), dim3(Cfg<L>::NT_B), 0, st,
-                       Z, W, half, That, tw, zs);
+    hipLaunchKernelGGL((k_passA<R, L, C::EA, C::LINES_A, Src>), dim3(nbA, nrhs), dim3(C::LINES_A * C::TA), 0, st,
+                       src, Z, W, tw, zs, skip);
+  if ((passes & 2) && dpart)
+    hipLaunchKernelGGL((k_passB<R, L, C::EB, C::LB, true>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
+                       st, Z, W, half, That, tw, zs, skip, dpart, lv1);
+  else if (passes & 2)
+    hipLaunchKernelGGL((k_passB<R, L, C::EB, C::LB, false>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
+                       st, Z, W, half, That, tw, zs, skip, dpart, lv1);
   if (passes & 4)
-    hipLaunchKernelGGL((k_passC<R, Y, L, C::LINES_A, C::TPL>), dim3(nbA, nrhs), dim3(C::NT_A), 0, st, Z, W, half,
-                       tw, zs, y, (long long)W * W);
+    hipLaunchKernelGGL((k_passC<R, Y, L, C::EA, C::LINES_A>), dim3(nbA + (fin.sc ? 1 : 0), nrhs), dim3(C::LINES_A * C::TA), 0, st, Z,
+                       W, tw, zs, y, (long long)W * W, skip, fin);
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
 }
 
 template <typename R, class Src, typename Y>
-int dispatch_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes = 7) {
+int dispatch_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
+                double* dpart = nullptr, const gofd_cg::Level1& lv1 = gofd_cg::Level1(),
+                const gofd_cg::Finish& fin = gofd_cg::Finish()) {
   switch (op->L) {
-    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y, passes);
-    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y, passes);
-    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y, passes);
-    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y, passes);
-    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y, passes);
-    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y, passes);
-    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y, passes);
-    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y, passes);
-    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y, passes);
-    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y, passes);
+    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
     default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "FFT length " + std::to_string(op->L) + " not built");
   }
 }
@@ -362,33 +488,72 @@ int fdop_finish(gofd_ctx_s* ctx, gofd_fdop_s* op) {
 
 int conv_prepare(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs) {
   if (!twiddles64(ctx, op->L) || !twiddles32(ctx, op->L)) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
-  long long zs = 1;
-  for (int a = 0; a < op->d; ++a) zs *= (a == 0 ? op->half : op->W);
+  long long zs = 1, nn = 1;
+  for (int a = 0; a < op->d; ++a) {
+    zs *= (a == 0 ? op->half : op->W);
+    nn *= op->W;
+  }
+  GOFD_TRY(dev_reserve(ctx, op->G, sizeof(double) * nn * nrhs));
   return dev_reserve(ctx, op->Z, sizeof(cplx<double>) * zs * nrhs);
 }
 
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g, void* y,
                bool fp32, int passes) {
   if (op->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "3D product not built yet");
+  const long long nn = (long long)op->W * op->W;
+  const Skip skip{g ? g->skip : nullptr, g ? g->skip_stride : 0};
   if (v) {
-    SrcGrid src{v, (long long)op->W * op->W};
-    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes)
-                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes);
+    SrcGrid<double> src{v, nn};
+    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip)
+                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip);
   }
   const gofd_transfer_s* tr = g->tr;
-  SrcGather<2> src;
-  src.g.d = 2;
-  src.g.W = tr->W;
-  src.g.h = tr->h;
-  for (int a = 0; a < 3; ++a) src.g.lo[a] = tr->lo[a];
-  src.recs = tr->rec.as<ElemRec2>();
-  src.elem = tr->elem.as<int>();
-  src.u = g->u;
-  src.scale = g->col_scale;
-  src.mask = g->mask;
-  src.nv = tr->nv;
-  return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes)
-              : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes);
+  GridGeom geom;
+  geom.d = 2;
+  geom.W = tr->W;
+  geom.h = tr->h;
+  for (int a = 0; a < 3; ++a) geom.lo[a] = tr->lo[a];
+  GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
+  const dim3 gg(grid1(nn, 256), nrhs);
+  if (g->pregathered) passes &= ~8;
+  double* dpart = g->dpart;
+  const gofd_cg::Level1 lv1 = g->lv1;
+  const gofd_cg::Finish fin = g->fin;
+  if (fp32) {
+    if (passes & 8)
+      hipLaunchKernelGGL((k_gather<float, 2>), gg, dim3(256), 0, ctx->stream, geom, tr->rec.as<ElemRec2>(),
+                         tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
+                         skip);
+    SrcGrid<float> src{op->G.as<float>(), nn};
+    return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin);
+  }
+  if (passes & 8)
+    hipLaunchKernelGGL((k_gather<double, 2>), gg, dim3(256), 0, ctx->stream, geom, tr->rec.as<ElemRec2>(),
+                       tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(),
+                       skip);
+  SrcGrid<double> src{op->G.as<double>(), nn};
+  return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin);
+}
+
+template <typename R>
+static int passB_blocks(int L) {
+  switch (L) {
+    case 8: return 4 / Cfg<R, 8>::LB;
+    case 16: return 8 / Cfg<R, 16>::LB;
+    case 32: return 16 / Cfg<R, 32>::LB;
+    case 64: return 32 / Cfg<R, 64>::LB;
+    case 128: return 64 / Cfg<R, 128>::LB;
+    case 256: return 128 / Cfg<R, 256>::LB;
+    case 512: return 256 / Cfg<R, 512>::LB;
+    case 1024: return 512 / Cfg<R, 1024>::LB;
+    case 2048: return 1024 / Cfg<R, 2048>::LB;
+    case 4096: return 2048 / Cfg<R, 4096>::LB;
+    default: return 1;
+  }
+}
+
+int conv_passB_blocks(const gofd_fdop_s* op, bool fp32) {
+  return fp32 ? passB_blocks<float>(op->L) : passB_blocks<double>(op->L);
 }
 
 // ---------------------------------------------------------------- ABI
@@ -497,7 +662,7 @@ extern "C" int gofd_fdop_free(gofd_fdop op) {
 
 extern "C" int gofd_time_kernel(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int which, int nrhs, const double* u,
                                 int flags, int reps, double* avg_ms) {
-  if (!ctx || !tr || !op || !u || !avg_ms || nrhs < 1 || reps < 1 || which < 0 || which > 3)
+  if (!ctx || !tr || !op || !u || !avg_ms || nrhs < 1 || reps < 1 || which < 0 || which > 4)
     return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
   if (!same_grid(tr, op)) return gofd_fail(ctx, GOFD_E_ARG, "transfer and operator use different grids");
   const bool fp32 = flags & GOFD_FP32_GRID;
@@ -511,11 +676,11 @@ extern "C" int gofd_time_kernel(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, in
   g.u = u;
   g.mask = tr->imask.as<double>();
   // fill the workspaces once with a full product
-  GOFD_TRY(conv_apply(ctx, op, nrhs, nullptr, &g, op->Y.p, fp32, 7));
+  GOFD_TRY(conv_apply(ctx, op, nrhs, nullptr, &g, op->Y.p, fp32, 15));
   auto launch = [&]() -> int {
     if (which == GOFD_K_SCATTER)
       return scatter_apply(ctx, tr, nrhs, op->Y.p, fp32, nullptr, tr->imask.as<double>(), z.as<double>());
-    return conv_apply(ctx, op, nrhs, nullptr, &g, op->Y.p, fp32, 1 << which);
+    return conv_apply(ctx, op, nrhs, nullptr, &g, op->Y.p, fp32, which == GOFD_K_GATHER ? 8 : 1 << which);
   };
   GOFD_TRY(launch());
   hipEvent_t e0, e1;

@@ -1,13 +1,17 @@
-// Radix-8/4/2 Stockham FFT of one line held in LDS, for wave64 gfx950.
+// Radix-16/8/4/2 Stockham FFT of one line, for wave64 gfx950.
 //
-// A line of L complex values (L a power of two) is transformed by TPL threads.
+// A line of L complex values (L a power of two) is transformed by TPL = L/E
+// threads that each hold E values in registers: thread t holds elements
+// t + m TPL (m = 0..E-1) both before the first stage and after the last.
 // Stage s with radix RAD and sub-transform size NS (1, RAD0, RAD0*RAD1, ...):
 // butterfly j reads x[j + r L/RAD], applies the twiddles w^{r k}
 // (k = j mod NS, w = exp(-+2 pi i / (NS RAD))), does a RAD-point DFT and
-// writes y[(j - k) RAD + k + r NS].  After all stages the result is in natural
-// order (the Stockham auto-sort formulation, Govindaraju et al. 2008).  Every
-// stage keeps RAD values per butterfly in registers and is done in place with
-// two workgroup barriers (read all, then write all).
+// writes y[(j - k) RAD + k + r NS]; after all stages the result is in natural
+// order (the Stockham auto-sort formulation, Govindaraju et al. 2008).  The
+// first stage takes its inputs from registers and the last stage leaves its
+// outputs in registers, so a line needs one LDS exchange per stage boundary
+// and none for loading or storing: callers load from and store to HBM
+// directly with the element-to-thread map above.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -82,9 +86,57 @@ __device__ __forceinline__ void dft8(cplx<R>* a) {
   a[7] = csub(e3, o3);
 }
 
+// a * exp(-+ i theta) with c = cos theta, s = sin theta
+template <typename R, bool INV>
+__device__ __forceinline__ cplx<R> rotc(cplx<R> a, R c, R s) {
+  if constexpr (!INV)
+    return {a.x * c + a.y * s, a.y * c - a.x * s};
+  else
+    return {a.x * c - a.y * s, a.y * c + a.x * s};
+}
+
+// 16-point DFT as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+template <typename R, bool INV>
+__device__ __forceinline__ void dft16(cplx<R>* a) {
+  const R c1 = (R)0.92387953251128675612818318939678828682;   // cos(pi/8)
+  const R s1 = (R)0.38268343236508977172845998403039886676;   // sin(pi/8)
+  const R c2 = (R)0.70710678118654752440084436210484903928;   // cos(pi/4)
+  cplx<R> b[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cplx<R> x0 = a[n2], x1 = a[n2 + 4], x2 = a[n2 + 8], x3 = a[n2 + 12];
+    dft4<R, INV>(x0, x1, x2, x3);
+    b[n2][0] = x0;
+    b[n2][1] = x1;
+    b[n2][2] = x2;
+    b[n2][3] = x3;
+  }
+  // b[n2][k1] *= w16^(n2 k1)
+  b[1][1] = rotc<R, INV>(b[1][1], c1, s1);
+  b[1][2] = rotc<R, INV>(b[1][2], c2, c2);
+  b[1][3] = rotc<R, INV>(b[1][3], s1, c1);
+  b[2][1] = rotc<R, INV>(b[2][1], c2, c2);
+  b[2][2] = rot90<R, INV>(b[2][2]);
+  b[2][3] = rotc<R, INV>(b[2][3], -c2, c2);
+  b[3][1] = rotc<R, INV>(b[3][1], s1, c1);
+  b[3][2] = rotc<R, INV>(b[3][2], -c2, c2);
+  b[3][3] = rotc<R, INV>(b[3][3], -c1, -s1);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cplx<R> y0 = b[0][k1], y1 = b[1][k1], y2 = b[2][k1], y3 = b[3][k1];
+    dft4<R, INV>(y0, y1, y2, y3);
+    a[k1] = y0;
+    a[k1 + 4] = y1;
+    a[k1 + 8] = y2;
+    a[k1 + 12] = y3;
+  }
+}
+
 template <typename R, int RAD, bool INV>
 __device__ __forceinline__ void dft(cplx<R>* a) {
-  if constexpr (RAD == 8)
+  if constexpr (RAD == 16)
+    dft16<R, INV>(a);
+  else if constexpr (RAD == 8)
     dft8<R, INV>(a);
   else if constexpr (RAD == 4)
     dft4<R, INV>(a[0], a[1], a[2], a[3]);
@@ -92,71 +144,105 @@ __device__ __forceinline__ void dft(cplx<R>* a) {
     dft2<R, INV>(a);
 }
 
-// LDS index with padding against bank conflicts of strided stage stores
-template <int L>
+// LDS index of element i: one pad entry after every E entries, so that the
+// stride-E writes of the first stage hit distinct banks.
+template <int E>
 __device__ __forceinline__ int pidx(int i) {
-  return i + (i >> 5);
+  return i + i / E;
 }
-template <int L>
+template <int L, int E>
 constexpr int padded_len() {
-  return L + L / 32 + 1;
+  return L + L / E;
 }
 
-template <typename R, int L, int TPL, bool INV, int NS>
-__device__ __forceinline__ void stages(cplx<R>* buf, const cplx<R>* __restrict__ tw, int t) {
-  if constexpr (NS < L) {
-    constexpr int REM = L / NS;
-    constexpr int RAD = (REM >= 8) ? 8 : REM;
-    constexpr int NB = L / RAD;             // butterflies in this stage
-    static_assert(NB % TPL == 0, "threads per line must divide the butterfly count");
-    constexpr int PER = NB / TPL;
-    constexpr int TWS = L / (NS * RAD);     // twiddle table stride
-    cplx<R> a[PER][RAD];
+// w^r for r = 1..RAD-1 from the table entries w^1, w^2, w^4, w^8 (products for
+// the others: at most three roundings away from the table values)
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void twiddle(cplx<R>* a, const cplx<R>* wb) {
+  cplx<R> w[16];
+  w[1] = wb[0];
+  if constexpr (RAD >= 4) {
+    w[2] = wb[1];
+    w[3] = cmul(w[1], w[2]);
+  }
+  if constexpr (RAD >= 8) {
+    w[4] = wb[2];
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+  }
+  if constexpr (RAD >= 16) {
+    w[8] = wb[3];
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+  }
+#pragma unroll
+  for (int r = 1; r < RAD; ++r) a[r] = INV ? cmulc(a[r], w[r]) : cmul(a[r], w[r]);
+}
+
+// One Stockham stage and, recursively, the ones after it.  LDS protocol: the
+// first stage writes the buffer (callers guarantee no thread still reads
+// it), every later stage waits for the previous writes, reads, and (unless
+// it is the last) waits again before overwriting the buffer.
+template <typename R, int L, int E, bool INV, int NS>
+__device__ __forceinline__ void rstage(cplx<R> (&v)[E], cplx<R>* buf, const cplx<R>* __restrict__ tw, int t) {
+  constexpr int TPL = L / E;
+  constexpr int REM = L / NS;
+  constexpr int RAD = (REM >= E) ? E : REM;
+  constexpr int PER = E / RAD;                  // butterflies per thread
+  constexpr bool FIRST = (NS == 1);
+  constexpr bool LAST = (NS * RAD == L);
+  constexpr int TWS = L / (NS * RAD);           // twiddle table stride
+  static_assert(RAD >= 2 && PER * RAD == E, "radix plan");
+  cplx<R> a[PER][RAD];
+  cplx<R> wb[PER][4];
+  if constexpr (!FIRST) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-      const int j = t + p * TPL;
-#pragma unroll
-      for (int r = 0; r < RAD; ++r) a[p][r] = buf[pidx<L>(j + r * NB)];
+      const int k = (t + p * TPL) & (NS - 1);
+      wb[p][0] = tw[k * TWS];
+      if constexpr (RAD >= 4) wb[p][1] = tw[2 * k * TWS];
+      if constexpr (RAD >= 8) wb[p][2] = tw[4 * k * TWS];
+      if constexpr (RAD >= 16) wb[p][3] = tw[8 * k * TWS];
     }
     __syncthreads();
+  }
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
+  for (int p = 0; p < PER; ++p)
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      const int m = p + r * PER;                // element t + m TPL = j + r L/RAD
+      if constexpr (FIRST)
+        a[p][r] = v[m];
+      else
+        a[p][r] = buf[pidx<E>(t + m * TPL)];
+    }
+  if constexpr (!FIRST && !LAST) __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    if constexpr (!FIRST) twiddle<R, RAD, INV>(a[p], wb[p]);
+    dft<R, RAD, INV>(a[p]);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[p + r * PER] = a[p][r];
+    } else {
       const int j = t + p * TPL;
       const int k = j & (NS - 1);
-      if constexpr (NS > 1) {
-        // w^r for r = 1..RAD-1 from the table entries w^1, w^2, w^4 (products
-        // for the others: at most two roundings away from the table values)
-        cplx<R> w[8];
-        w[1] = tw[k * TWS];
-        if constexpr (RAD >= 4) {
-          w[2] = tw[2 * k * TWS];
-          w[3] = cmul(w[1], w[2]);
-        }
-        if constexpr (RAD == 8) {
-          w[4] = tw[4 * k * TWS];
-          w[5] = cmul(w[4], w[1]);
-          w[6] = cmul(w[4], w[2]);
-          w[7] = cmul(w[4], w[3]);
-        }
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) a[p][r] = INV ? cmulc(a[p][r], w[r]) : cmul(a[p][r], w[r]);
-      }
-      dft<R, RAD, INV>(a[p]);
       const int base = (j - k) * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) buf[pidx<L>(base + r * NS)] = a[p][r];
+      for (int r = 0; r < RAD; ++r) buf[pidx<E>(base + r * NS)] = a[p][r];
     }
-    __syncthreads();
-    stages<R, L, TPL, INV, NS * RAD>(buf, tw, t);
   }
+  if constexpr (!LAST) rstage<R, L, E, INV, NS * RAD>(v, buf, tw, t);
 }
 
 // Forward (INV = false, exponent -) or unnormalised inverse (exponent +)
-// transform of buf[pidx(0..L)] by threads t = 0..TPL-1 of a line.  Callers
-// must synchronise before (data ready); the routine ends with a barrier.
-template <typename R, int L, int TPL, bool INV>
-__device__ __forceinline__ void fft_line(cplx<R>* buf, const cplx<R>* __restrict__ tw, int t) {
-  stages<R, L, TPL, INV, 1>(buf, tw, t);
+// transform of the line held in v by threads t = 0..L/E-1, with buf (padded
+// length) as exchange space.  On entry no thread may still read buf; on exit
+// other threads may still read it (synchronise before writing it again).
+template <typename R, int L, int E, bool INV>
+__device__ __forceinline__ void fft_regs(cplx<R> (&v)[E], cplx<R>* buf, const cplx<R>* __restrict__ tw, int t) {
+  rstage<R, L, E, INV, 1>(v, buf, tw, t);
 }
 
 }  // namespace gofd_fft

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "cg_state.h"
+
 #include <cstdint>
 #include <map>
 #include <string>
@@ -121,9 +123,20 @@ struct gofd_fdop_s {
   DevBuf That64;                // double[half^d], includes the 1/L^d normalisation
   DevBuf That32;                // float [half^d]
   DevBuf Z;                     // spectra workspace
+  DevBuf G;                     // gathered grid field (I u) workspace
   DevBuf Y;                     // grid-field workspace
   gofd_ctx_s* ctx = nullptr;
 };
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2); renumber them so that logically adjacent blocks share an XCD, which
+// keeps a kernel's reads of neighbouring data in one L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int per = n / 8, rem = n % 8;
+  const int x = b % 8, i = b / 8;
+  const int start = (x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+  return start + i;
+}
 
 // ------------------------------------------------------------------ internal API
 
@@ -138,16 +151,26 @@ struct GatherSpec {
   const double* u = nullptr;
   const double* col_scale = nullptr;   // optional per-vertex scale applied to u (D^{-1/2})
   const double* mask = nullptr;        // optional per-vertex mask (interior)
+  const int* skip = nullptr;           // optional per-rhs flag (stride skip_stride ints): rhs already finished
+  int skip_stride = 0;
+  bool pregathered = false;            // the grid field I u is already in the operator's G workspace
+  double* dpart = nullptr;             // optional: per-block partials (gamma, (r, r), (A v, v)) of the column pass
+  gofd_cg::Level1 lv1;                 // level-1 partials of gamma and (r, r) the column pass sums up
+  gofd_cg::Finish fin;                 // optional: CG reductions finished by the last pass
 };
 
 // Apply A_FD with the FFT embedding: input either a grid field (v != nullptr,
 // nrhs*W^d doubles) or a gather spec; output grid field y (double or float,
 // nrhs*W^d).  fp32 selects the single-precision pipeline.
-// passes: bit mask of the FFT passes to launch (1: A, 2: B, 4: C), 7 = all.
+// passes: bit mask of the kernels to launch (1: pass A, 2: pass B, 4: pass C,
+// 8: the gather I u when g is given), 15 = all.
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g,
-               void* y, bool fp32, int passes = 7);
+               void* y, bool fp32, int passes = 15);
 
 bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op);
+
+// Number of blocks of the column pass (one partial of (A v, v) each).
+int conv_passB_blocks(const gofd_fdop_s* op, bool fp32);
 
 // Reserve the spectra workspace and twiddle tables for nrhs fields, so that
 // later products allocate nothing (required inside graph capture).

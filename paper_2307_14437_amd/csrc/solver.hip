@@ -4,12 +4,18 @@
 //
 // All vectors have N_v entries in the mesh's numbering; Dirichlet entries are
 // kept at zero, which is the interior block of the remark after eq. GoFD-2.
-// The CG scalars live on the device: every dot product is a per-block partial
-// sum followed by a fixed-order reduction in the last block to finish (so the
-// result does not depend on scheduling), and that block also forms alpha,
-// beta and the convergence test.  The host only reads the convergence flags
-// every few iterations, and those iterations are captured once in a hipGraph
-// and replayed.
+//
+// CG runs in the single-reduction form of Chronopoulos and Gear (1989), whose
+// iterates equal those of preconditioned CG in exact arithmetic.  One
+// iteration is five kernels: the gather I u, the three FFT passes of A_FD
+// (the column pass also leaves the partial sums of delta = (K u, u) by
+// Parseval, and block 0 of the last pass finishes every reduction and decides
+// alpha, beta and convergence), and the I^T scatter, which applies the step
+// to the vertex vectors as it forms w = K u and leaves the partial sums of
+// the next gamma = (r, u) and (r, r).  All sums are fixed-order, so results
+// do not depend on scheduling; the host reads the convergence flags every
+// few iterations, and those iterations are captured once in a hipGraph and
+// replayed.
 //
 // Preconditioners: none; D_h (CG on the symmetric form of eq. Ah-3); the IC(1)
 // factor of A_h^(5/9/27) (Section 3.4), applied with two level-scheduled
@@ -32,22 +38,26 @@ namespace {
 
 inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-constexpr int NB_DOT = 512;      // blocks of the plain vector kernels (fixed: deterministic sums)
+constexpr int NB_DOT = 256;      // blocks of the residual kernel (fixed: deterministic sums)
 constexpr int BS = 256;
-constexpr int SCAT_G = 16;       // lanes per vertex in the I^T scatter
+constexpr int MAX_SC = 16384;    // most blocks of the CG scatter (one partial sum each)
+#ifndef GOFD_SCAT_G
+#define GOFD_SCAT_G 16
+#endif
+constexpr int SCAT_G = GOFD_SCAT_G;   // lanes per vertex in the I^T scatter (build-time knob: 8, 16, 32)
 
-struct Scal {
-  double rho, alpha, beta, bb, rr, pq, rz, tol2;
-  int done, iters, status, pad;
-};
+using gofd_cg::block_sum_n;
+using gofd_cg::Scal;
+using gofd_cg::ST_BREAKDOWN;
+using gofd_cg::ST_OK;
 
-enum { ST_OK = 0, ST_BREAKDOWN = 1 };
-
-// fixed-order block reduction of one double per thread (BS threads)
+// fixed-order block reduction of one double per thread (NT threads)
+template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
   __syncthreads();
-  for (int o = BS / 2; o > 0; o >>= 1) {
+#pragma unroll
+  for (int o = NT / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
@@ -56,20 +66,12 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// Dot products are two-stage: each block of a vector kernel writes one
-// partial sum per quantity, and a one-block finishing kernel per rhs adds the
-// partials in a fixed order and updates the CG scalars.  The kernel boundary
-// orders the two stages, so no block needs a device-wide memory fence (on a
-// multi-XCD part such a fence writes back the L2 of the issuing XCD).
-enum FinOp { FIN_START = 0, FIN_ALPHA = 1, FIN_UPDATE = 2, FIN_RZ_FIRST = 3, FIN_RZ = 4, FIN_RESIDUAL = 5 };
-
-template <int NQ>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nb, double* out, double* sh) {
-  for (int c = 0; c < NQ; ++c) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += BS) s += part[(long long)c * nb + i];
-    out[c] = block_sum(s, sh);
-  }
+// Sum of n partials in a fixed order (strided per thread, then the block
+// tree): every block that calls it gets the same bits.
+__device__ __forceinline__ double sum_fixed(const double* __restrict__ part, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += BS) s += part[i];
+  return block_sum<BS>(s, sh);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -99,134 +101,159 @@ __global__ void k_rhs_vertex(const double* __restrict__ f, const double* __restr
   if (i < nv) b[rhs * nv + i] = c * mask[i] * D[i] * f[rhs * nv + i];
 }
 
-// CG start from x = 0: r = b, z = M_diag r, p = z; rho = r.z, bb = b.b
-__global__ __launch_bounds__(BS) void k_start(const double* __restrict__ b, double* __restrict__ x,
-                                              double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
-                                              const double* __restrict__ dinv, long long nv, Scal* __restrict__ sc,
-                                              double tol, double* __restrict__ partials, unsigned* __restrict__ counters,
-                                              int zfilled) {
-  __shared__ double sh[BS];
+// CG step in the form of Chronopoulos and Gear: with u = M r and w = K u,
+//   gamma = (r, u), delta = (w, u), beta = gamma / gamma_prev,
+//   alpha = gamma / (delta - beta gamma / alpha_prev),
+//   p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s.
+// The vector kernels below run nbs blocks of BS threads, each over a
+// contiguous range of vertices, and leave one partial sum per block.
+
+// start from x = 0: r = b, u = M_diag b (or u given), p = s = 0; partials of
+// gamma = (r, u) and (r, r)
+__global__ __launch_bounds__(BS) void k_cg_start(const double* __restrict__ b, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ u,
+                                                 double* __restrict__ p, double* __restrict__ s,
+                                                 const double* __restrict__ dinv, long long nv, int ufilled,
+                                                 double* __restrict__ partG, double* __restrict__ partR) {
+  __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
   const int rhs = blockIdx.y;
   const long long o = rhs * nv;
-  double s_rz = 0.0, s_bb = 0.0;
+  double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
     const double bi = b[o + i];
     x[o + i] = 0.0;
     r[o + i] = bi;
-    double zi = zfilled ? z[o + i] : (dinv ? bi * dinv[i] : bi);
-    if (!zfilled) z[o + i] = zi;
-    p[o + i] = zi;
-    s_rz += bi * zi;
-    s_bb += bi * bi;
+    double ui = ufilled ? u[o + i] : (dinv ? bi * dinv[i] : bi);
+    if (!ufilled) u[o + i] = ui;
+    p[o + i] = 0.0;
+    s[o + i] = 0.0;
+    acc[0] += bi * ui;
+    acc[1] += bi * bi;
   }
-  s_rz = block_sum(s_rz, sh);
-  s_bb = block_sum(s_bb, sh);
-  double* part = partials + (long long)rhs * 2 * gridDim.x;
+  block_sum_n<BS, 2>(acc, sh);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s_rz;
-    part[gridDim.x + blockIdx.x] = s_bb;
+    partG[(long long)rhs * gridDim.x + blockIdx.x] = acc[0];
+    partR[(long long)rhs * gridDim.x + blockIdx.x] = acc[1];
   }
 }
 
-// q = mask * I^T y; partial p.q; last block: alpha = rho / (p.q)
+// one block per rhs: initial state (gamma_prev = inf, alpha_prev = 1 make the
+// first beta zero and the first alpha gamma / delta)
+__global__ __launch_bounds__(BS) void k_cg_init(const double* __restrict__ partG, const double* __restrict__ partR,
+                                                int nb, Scal* __restrict__ sc, double tol) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.x;
+  const double g = sum_fixed(partG + (long long)rhs * nb, nb, sh);
+  const double bb = sum_fixed(partR + (long long)rhs * nb, nb, sh);
+  if (threadIdx.x != 0) return;
+  Scal S{};
+  S.alpha = 1.0;
+  S.beta = 0.0;
+  S.gamma = HUGE_VAL;
+  S.rr = bb;
+  S.bb = bb;
+  S.tol2 = tol * tol * bb;
+  S.done = (bb == 0.0) ? 1 : 0;
+  S.status = ST_OK;
+  if (!(g > 0.0) && bb > 0.0) {
+    S.status = ST_BREAKDOWN;
+    S.done = 1;
+  }
+  sc[rhs] = S;
+}
+
+// w = mask * I^T y (the product K u, G lanes per vertex) and, in the same
+// pass, the step decided by the last FFT pass: s = w + beta s, p = u + beta p,
+// x += alpha p, r -= alpha s and, for a diagonal (or no) preconditioner,
+// u = M r; partials of the next (r, r) and gamma = (r, u).  Block b takes the
+// vertex groups [b*per, (b+1)*per) in XCD-contiguous order.
 template <typename Y, typename WT, int G>
-__global__ __launch_bounds__(BS) void k_scatter_dot(const int* __restrict__ off, const int* __restrict__ node,
-                                                    const WT* __restrict__ w, const Y* __restrict__ y,
-                                                    long long nv, long long n_nodes, const double* __restrict__ mask,
-                                                    const double* __restrict__ p, double* __restrict__ q,
-                                                    Scal* __restrict__ sc, double* __restrict__ partials,
-                                                    unsigned* __restrict__ counters) {
-  __shared__ double sh[BS];
+__global__ __launch_bounds__(BS) void k_scatter_cg(const int* __restrict__ off, const int* __restrict__ node,
+                                                   const WT* __restrict__ wts, const Y* __restrict__ y, long long nv,
+                                                   long long n_nodes, const double* __restrict__ mask,
+                                                   const Scal* __restrict__ sc, double* __restrict__ x,
+                                                   double* __restrict__ p, double* __restrict__ s,
+                                                   double* __restrict__ r, double* __restrict__ u,
+                                                   const double* __restrict__ dinv, int dk, int per,
+                                                   double* __restrict__ partG, double* __restrict__ partR) {
+  constexpr int VPB = BS / G;                 // vertices per block pass
+  __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
   const int rhs = blockIdx.y;
-  if (sc[rhs].done) return;
-  const long long v = ((long long)blockIdx.x * BS + threadIdx.x) / G;
+  const long long o = rhs * nv;
   const int lane = threadIdx.x % G;
-  double contrib = 0.0;
-  if (v < nv) {
-    const Y* yr = y + rhs * n_nodes;
+  const long long g0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * per;
+  const Y* yr = y + rhs * n_nodes;
+  // first segment bounds before the finished-rhs test, so that the loads overlap
+  const long long vf = g0 * VPB + threadIdx.x / G;
+  int f0 = 0, f1 = 0;
+  if (vf < nv) {
+    f0 = off[vf];
+    f1 = off[vf + 1];
+  }
+  const Scal& S = sc[rhs];
+  if (S.done) return;                         // block-uniform
+  const double alpha = S.alpha, beta = S.beta;
+  double acc2[2] = {0.0, 0.0};                // (r, r), (r, u)
+  for (int q = 0; q < per; ++q) {
+    const long long v = (g0 + q) * VPB + threadIdx.x / G;
     double acc = 0.0;
-    for (int i = off[v] + lane; i < off[v + 1]; i += G) acc += (double)w[i] * (double)yr[node[i]];
+    double vm = 0, vs = 0, vp = 0, vu = 0, vr = 0, vx = 0, vd = 0;
+    if (v < nv) {
+      const int i0 = q == 0 ? f0 : off[v], i1 = q == 0 ? f1 : off[v + 1];
+      // the vertex's own vectors, fetched with the first entries
+      if (lane == 0) {
+        vm = mask[v];
+        vs = s[o + v];
+        vp = p[o + v];
+        vu = u[o + v];
+        vr = r[o + v];
+        vx = x[o + v];
+        if (dk > 0) vd = dinv[v];
+      }
+      int nd[4];
+      WT wt[4];
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-    if (lane == 0) {
-      const double qv = mask[v] * acc;
-      q[rhs * nv + v] = qv;
-      contrib = qv * p[rhs * nv + v];
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + lane + k * G;
+        nd[k] = i < i1 ? node[i] : -1;
+        wt[k] = i < i1 ? wts[i] : (WT)0;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (nd[k] >= 0) acc += (double)wt[k] * (double)yr[nd[k]];
+      for (int i = i0 + lane + 4 * G; i < i1; i += G) acc += (double)wts[i] * (double)yr[node[i]];
+    }
+#pragma unroll
+    for (int k = G / 2; k > 0; k >>= 1) acc += __shfl_xor(acc, k, G);
+    if (lane == 0 && v < nv) {
+      const double wv = vm * acc;
+      const double sn = fma(beta, vs, wv);
+      const double pn = fma(beta, vp, vu);
+      const double rn = fma(-alpha, sn, vr);
+      s[o + v] = sn;
+      p[o + v] = pn;
+      x[o + v] = fma(alpha, pn, vx);
+      r[o + v] = rn;
+      acc2[0] += rn * rn;
+      if (dk >= 0) {
+        const double un = dk ? rn * vd : rn;
+        u[o + v] = un;
+        acc2[1] += rn * un;
+      }
     }
   }
-  const double s = block_sum(contrib, sh);
-  if (threadIdx.x == 0) partials[(long long)rhs * gridDim.x + blockIdx.x] = s;
-}
-
-// x += alpha p, r -= alpha q, rr = r.r; with a diagonal (or no) preconditioner
-// also z = M r, rz = r.z, beta, rho; convergence flag
-__global__ __launch_bounds__(BS) void k_update(double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
-                                               const double* __restrict__ p, const double* __restrict__ q,
-                                               const double* __restrict__ dinv, int diag_kind, long long nv,
-                                               Scal* __restrict__ sc, double* __restrict__ partials,
-                                               unsigned* __restrict__ counters) {
-  __shared__ double sh[BS];
-  const int rhs = blockIdx.y;
-  if (sc[rhs].done) return;
-  const double alpha = sc[rhs].alpha;
-  const long long o = rhs * nv;
-  double s_rr = 0.0, s_rz = 0.0;
-  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
-    x[o + i] += alpha * p[o + i];
-    const double ri = r[o + i] - alpha * q[o + i];
-    r[o + i] = ri;
-    s_rr += ri * ri;
-    if (diag_kind >= 0) {
-      const double zi = diag_kind ? ri * dinv[i] : ri;
-      z[o + i] = zi;
-      s_rz += ri * zi;
-    }
-  }
-  s_rr = block_sum(s_rr, sh);
-  s_rz = block_sum(s_rz, sh);
-  double* part = partials + (long long)rhs * 2 * gridDim.x;
+  block_sum_n<BS, 2>(acc2, sh);
   if (threadIdx.x == 0) {
-    part[blockIdx.x] = s_rr;
-    part[gridDim.x + blockIdx.x] = s_rz;
+    partR[(long long)rhs * gridDim.x + blockIdx.x] = acc2[0];
+    if (dk >= 0) partG[(long long)rhs * gridDim.x + blockIdx.x] = acc2[1];
   }
 }
 
-// rz = r.z after a triangular-solve preconditioner; beta, rho
-__global__ __launch_bounds__(BS) void k_dot_rz(const double* __restrict__ r, const double* __restrict__ z, long long nv,
-                                               Scal* __restrict__ sc, double* __restrict__ partials,
-                                               unsigned* __restrict__ counters, int first) {
-  __shared__ double sh[BS];
-  const int rhs = blockIdx.y;
-  if (sc[rhs].done) return;
-  const long long o = rhs * nv;
-  double s = 0.0;
-  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS)
-    s += r[o + i] * z[o + i];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) partials[(long long)rhs * gridDim.x + blockIdx.x] = s;
-}
-
-__global__ void k_pupdate(double* __restrict__ p, const double* __restrict__ z, long long nv,
-                          const Scal* __restrict__ sc) {
-  const int rhs = blockIdx.y;
-  if (sc[rhs].done) return;
-  const double beta = sc[rhs].beta;
-  const long long o = rhs * nv;
-  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS)
-    p[o + i] = z[o + i] + beta * p[o + i];
-}
-
-__global__ void k_copy_p(double* __restrict__ p, const double* __restrict__ z, long long nv) {
-  const int rhs = blockIdx.y;
-  const long long o = rhs * nv;
-  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS)
-    p[o + i] = z[o + i];
-}
-
-// r = b - q (q = K x), rr and bb; used by the refinement loop (FP64 residual)
+// r = b - q (q = K x), partials of (r, r) and (b, b); used by the refinement
+// loop (FP64 residual)
 __global__ __launch_bounds__(BS) void k_residual(const double* __restrict__ b, const double* __restrict__ q,
-                                                 double* __restrict__ r, long long nv, double* __restrict__ out2,
-                                                 double* __restrict__ partials, unsigned* __restrict__ counters) {
+                                                 double* __restrict__ r, long long nv,
+                                                 double* __restrict__ partials) {
   __shared__ double sh[BS];
   const int rhs = blockIdx.y;
   const long long o = rhs * nv;
@@ -237,85 +264,24 @@ __global__ __launch_bounds__(BS) void k_residual(const double* __restrict__ b, c
     s_rr += ri * ri;
     s_bb += b[o + i] * b[o + i];
   }
-  s_rr = block_sum(s_rr, sh);
-  s_bb = block_sum(s_bb, sh);
-  double* part = partials + (long long)rhs * 2 * gridDim.x;
+  s_rr = block_sum<BS>(s_rr, sh);
+  s_bb = block_sum<BS>(s_bb, sh);
+  double* part = partials + (long long)rhs * 2 * NB_DOT;
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s_rr;
-    part[gridDim.x + blockIdx.x] = s_bb;
+    part[NB_DOT + blockIdx.x] = s_bb;
   }
 }
 
-// one block per rhs: fixed-order sum of the partials of the previous kernel
-// and the scalar update that goes with it
-__global__ __launch_bounds__(BS) void k_finish(int op, const double* __restrict__ partials, int nb,
-                                               Scal* __restrict__ sc, double tol, int diag_kind,
-                                               double* __restrict__ out2) {
+__global__ __launch_bounds__(BS) void k_residual_finish(const double* __restrict__ partials, double* __restrict__ out2) {
   __shared__ double sh[BS];
   const int rhs = blockIdx.x;
-  Scal& S = sc[rhs];
-  if (op != FIN_START && op != FIN_RESIDUAL && S.done) return;
-  double tot[2] = {0.0, 0.0};
-  const int nq = (op == FIN_ALPHA || op == FIN_RZ || op == FIN_RZ_FIRST) ? 1 : 2;
-  const double* part = partials + (long long)rhs * nq * nb;
-  if (nq == 1)
-    sum_partials<1>(part, nb, tot, sh);
-  else
-    sum_partials<2>(part, nb, tot, sh);
-  if (threadIdx.x != 0) return;
-  switch (op) {
-    case FIN_START:
-      S.rho = tot[0];
-      S.bb = tot[1];
-      S.rr = tot[1];
-      S.tol2 = tol * tol * tot[1];
-      S.iters = 0;
-      S.status = ST_OK;
-      S.done = (tot[1] == 0.0) ? 1 : 0;
-      if (!(tot[0] > 0.0) && tot[1] > 0.0) {
-        S.status = ST_BREAKDOWN;
-        S.done = 1;
-      }
-      break;
-    case FIN_ALPHA:
-      S.pq = tot[0];
-      if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-        S.status = ST_BREAKDOWN;
-        S.done = 1;
-      } else {
-        S.alpha = S.rho / tot[0];
-      }
-      break;
-    case FIN_UPDATE:
-      S.rr = tot[0];
-      S.iters += 1;
-      if (!isfinite(tot[0])) {
-        S.status = ST_BREAKDOWN;
-        S.done = 1;
-      } else if (tot[0] <= S.tol2) {
-        S.done = 1;
-      } else if (diag_kind >= 0) {
-        S.beta = tot[1] / S.rho;
-        S.rho = tot[1];
-      }
-      break;
-    case FIN_RZ_FIRST:
-    case FIN_RZ:
-      if (op == FIN_RZ_FIRST) {
-        S.rho = tot[0];
-      } else {
-        S.beta = tot[0] / S.rho;
-        S.rho = tot[0];
-      }
-      if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-        S.status = ST_BREAKDOWN;
-        S.done = 1;
-      }
-      break;
-    case FIN_RESIDUAL:
-      out2[2 * rhs] = tot[0];
-      out2[2 * rhs + 1] = tot[1];
-      break;
+  const double* part = partials + (long long)rhs * 2 * NB_DOT;
+  const double rr = sum_fixed(part, NB_DOT, sh);
+  const double bb = sum_fixed(part + NB_DOT, NB_DOT, sh);
+  if (threadIdx.x == 0) {
+    out2[2 * rhs] = rr;
+    out2[2 * rhs + 1] = bb;
   }
 }
 
@@ -351,14 +317,19 @@ __global__ __launch_bounds__(BS) void k_scatter_plain(const int* __restrict__ of
 // visibility between XCDs; the cost is one barrier plus one dependent read
 // round trip per level.
 
+// The upper solve also forms gamma = (r, u) for CG (fixed-order block sum,
+// written as partial 0 of nbu with the others zero).
 template <bool LOWER>
 __global__ __launch_bounds__(1024) void k_trsv_levels(const int* __restrict__ ptr, const int* __restrict__ col,
                                                       const double* __restrict__ val, const int* __restrict__ lvl_ptr,
                                                       const int* __restrict__ lvl_rows, int nlev,
                                                       const double* __restrict__ rhs_in, double* __restrict__ out,
-                                                      long long stride, const Scal* __restrict__ sc) {
+                                                      long long stride, const Scal* __restrict__ sc,
+                                                      const double* __restrict__ rvec, double* __restrict__ partG,
+                                                      int nbu) {
+  __shared__ double sh[1024 / 64];
   const int k = blockIdx.x;
-  if (sc[k].done) return;
+  if (sc && sc[k].done) return;
   const double* b = rhs_in + k * stride;
   double* y = out + k * stride;
   for (int l = 0; l < nlev; ++l) {
@@ -374,6 +345,13 @@ __global__ __launch_bounds__(1024) void k_trsv_levels(const int* __restrict__ pt
       y[row] = (b[row] - s) / val[dpos];
     }
     __syncthreads();
+  }
+  if (!LOWER && partG) {
+    const double* rv = rvec + k * stride;
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < stride; i += 1024) s += rv[i] * y[i];
+    block_sum_n<1024, 1>(&s, sh);
+    for (int i = threadIdx.x; i < nbu; i += 1024) partG[(long long)k * nbu + i] = (i == 0) ? s : 0.0;
   }
 }
 
@@ -568,68 +546,60 @@ struct Problem {
 };
 
 struct Work {
-  DevBuf x, r, z, p, q, b, xr, dvec, grid;
-  DevBuf scal, partials, counters, out2;
+  DevBuf x, r, u, p, s, b, xr, dvec, q, grid;
+  DevBuf scal;                  // Scal[nrhs]
+  DevBuf partG, partR;          // double[nrhs][nbs]: gamma and (r, r) partials
+  DevBuf partD;                 // double[nrhs][pass-B blocks]: delta partials
+  DevBuf partials, out2;        // residual partials, ||r||^2 and ||b||^2
   int nrhs = 0;
+  int nbs = 1;                  // blocks of the CG vector kernels (scatter, start)
+  int per = 1;                  // vertex groups per scatter block
 };
 
 int reserve_work(gofd_ctx_s* ctx, Work& w, int64_t nv, int64_t n_nodes, int nrhs) {
   const size_t vb = sizeof(double) * nv * nrhs;
-  for (DevBuf* b : {&w.x, &w.r, &w.z, &w.p, &w.q, &w.b, &w.xr, &w.dvec}) GOFD_TRY(dev_reserve(ctx, *b, vb));
+  for (DevBuf* b : {&w.x, &w.r, &w.u, &w.p, &w.s, &w.b, &w.xr, &w.dvec, &w.q}) GOFD_TRY(dev_reserve(ctx, *b, vb));
   GOFD_TRY(dev_reserve(ctx, w.grid, sizeof(double) * n_nodes * nrhs));
   GOFD_TRY(dev_reserve(ctx, w.scal, sizeof(Scal) * nrhs));
-  const long long nb_scatter = grid1(nv * SCAT_G, BS);
-  GOFD_TRY(dev_reserve(ctx, w.partials, sizeof(double) * 2 * std::max<long long>(nb_scatter, NB_DOT) * nrhs));
-  GOFD_TRY(dev_reserve(ctx, w.counters, sizeof(unsigned) * nrhs));
+  const long long groups = (nv + BS / SCAT_G - 1) / (BS / SCAT_G);
+  w.per = (int)std::max<long long>(1, (groups + MAX_SC - 1) / MAX_SC);
+  w.nbs = (int)std::max<long long>(1, (groups + w.per - 1) / w.per);
+  GOFD_TRY(dev_reserve(ctx, w.partG, sizeof(double) * w.nbs * nrhs));
+  GOFD_TRY(dev_reserve(ctx, w.partR, sizeof(double) * w.nbs * nrhs));
+  GOFD_TRY(dev_reserve(ctx, w.partials, sizeof(double) * 2 * NB_DOT * nrhs));
   GOFD_TRY(dev_reserve(ctx, w.out2, sizeof(double) * 2 * nrhs));
-  HIP_TRY(ctx, hipMemsetAsync(w.counters.p, 0, sizeof(unsigned) * nrhs, ctx->stream));
   w.nrhs = nrhs;
   return GOFD_OK;
 }
 
-// q = K v (masked), grid workspace in w.grid; optional dot with p into alpha
-int apply_K(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* v, bool fp32, bool with_dot) {
+// q = K v in double precision (masked), for true residuals
+int apply_K_plain(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* v, double* q) {
   gofd_transfer_s* tr = P.tr;
   GatherSpec g;
   g.tr = tr;
   g.u = v;
   g.mask = tr->imask.as<double>();
-  GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32));
+  GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, false));
   dim3 gs(grid1(tr->nv * SCAT_G, BS), P.nrhs);
-  hipStream_t st = ctx->stream;
-  if (with_dot) {
-    if (fp32)
-      hipLaunchKernelGGL((k_scatter_dot<float, float, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
-                         tr->csc_node.as<int>(), tr->csc_w32.as<float>(), w.grid.as<float>(), (long long)tr->nv,
-                         (long long)tr->n_nodes, tr->imask.as<double>(), w.p.as<double>(), w.q.as<double>(),
-                         w.scal.as<Scal>(), w.partials.as<double>(), w.counters.as<unsigned>());
-    else
-      hipLaunchKernelGGL((k_scatter_dot<double, double, SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(),
-                         tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv,
-                         (long long)tr->n_nodes, tr->imask.as<double>(), w.p.as<double>(), w.q.as<double>(),
-                         w.scal.as<Scal>(), w.partials.as<double>(), w.counters.as<unsigned>());
-    hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_ALPHA, w.partials.as<double>(), (int)gs.x,
-                       w.scal.as<Scal>(), 0.0, 0, nullptr);
-  } else {
-    if (fp32) return gofd_fail(ctx, GOFD_E_ARG, "internal: plain product is double only");
-    hipLaunchKernelGGL((k_scatter_plain<SCAT_G>), gs, dim3(BS), 0, st, tr->csc_off.as<int>(), tr->csc_node.as<int>(),
-                       tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv, (long long)tr->n_nodes,
-                       tr->imask.as<double>(), w.q.as<double>());
-  }
+  hipLaunchKernelGGL((k_scatter_plain<SCAT_G>), gs, dim3(BS), 0, ctx->stream, tr->csc_off.as<int>(),
+                     tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv,
+                     (long long)tr->n_nodes, tr->imask.as<double>(), q);
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
 }
 
-int precond_apply(gofd_ctx_s* ctx, const Problem& P, Work& w) {
+// u = M^{-1} r with the IC(1) factor; the upper solve also writes the
+// partials of gamma = (r, u) into partG (if given)
+int precond_apply(gofd_ctx_s* ctx, const Problem& P, Work& w, const Scal* sc, double* partG) {
   gofd_precond_s* pc = P.pc;
   hipStream_t st = ctx->stream;
   const long long n = P.tr->nv;
   hipLaunchKernelGGL((k_trsv_levels<true>), dim3(P.nrhs), dim3(1024), 0, st, pc->Lptr.as<int>(), pc->Lcol.as<int>(),
                      pc->Lval.as<double>(), pc->Llev_ptr.as<int>(), pc->Llev_rows.as<int>(), pc->Lnlev,
-                     w.r.as<double>(), w.dvec.as<double>(), n, w.scal.as<Scal>());
+                     w.r.as<double>(), w.dvec.as<double>(), n, sc, nullptr, nullptr, w.nbs);
   hipLaunchKernelGGL((k_trsv_levels<false>), dim3(P.nrhs), dim3(1024), 0, st, pc->Uptr.as<int>(), pc->Ucol.as<int>(),
                      pc->Uval.as<double>(), pc->Ulev_ptr.as<int>(), pc->Ulev_rows.as<int>(), pc->Unlev,
-                     w.dvec.as<double>(), w.z.as<double>(), n, w.scal.as<Scal>());
+                     w.dvec.as<double>(), w.u.as<double>(), n, sc, w.r.as<double>(), partG, w.nbs);
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
 }
@@ -638,27 +608,47 @@ bool is_ic(const gofd_precond_s* pc) {
   return pc && (pc->kind == GOFD_PC_IC1_5 || pc->kind == GOFD_PC_IC1_9 || pc->kind == GOFD_PC_IC1_27);
 }
 
-// one CG iteration (after start)
+// 1: diagonal (D_h), 0: none, -1: IC(1) factor
+int diag_kind_of(const gofd_precond_s* pc) {
+  return is_ic(pc) ? -1 : ((pc && pc->kind == GOFD_PC_DIAG) ? 1 : 0);
+}
+
+// One CG iteration: product w = K u (gather, FFT passes with the delta
+// partials and the step decision, scatter with the vector update), then for
+// IC(1) the triangular solves u = M^{-1} r with the next gamma.
 int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32) {
+  gofd_transfer_s* tr = P.tr;
+  const int dk = diag_kind_of(P.pc);
+  const long long nn = tr->n_nodes, nv = tr->nv;
   hipStream_t st = ctx->stream;
-  const long long nv = P.tr->nv;
-  GOFD_TRY(apply_K(ctx, P, w, w.p.as<double>(), fp32, true));
-  const int diag_kind = is_ic(P.pc) ? -1 : ((P.pc && P.pc->kind == GOFD_PC_DIAG) ? 1 : 0);
-  dim3 gd(NB_DOT, P.nrhs);
-  hipLaunchKernelGGL(k_update, gd, dim3(BS), 0, st, w.x.as<double>(), w.r.as<double>(), w.z.as<double>(),
-                     w.p.as<double>(), w.q.as<double>(), P.tr->dscale.as<double>(), diag_kind, nv, w.scal.as<Scal>(),
-                     w.partials.as<double>(), w.counters.as<unsigned>());
-  hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_UPDATE, w.partials.as<double>(), NB_DOT,
-                     w.scal.as<Scal>(), 0.0, diag_kind, nullptr);
-  if (diag_kind < 0) {
-    GOFD_TRY(precond_apply(ctx, P, w));
-    hipLaunchKernelGGL(k_dot_rz, gd, dim3(BS), 0, st, w.r.as<double>(), w.z.as<double>(), nv, w.scal.as<Scal>(),
-                       w.partials.as<double>(), w.counters.as<unsigned>(), 0);
-    hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_RZ, w.partials.as<double>(), NB_DOT,
-                       w.scal.as<Scal>(), 0.0, 0, nullptr);
-  }
-  hipLaunchKernelGGL(k_pupdate, gd, dim3(BS), 0, st, w.p.as<double>(), w.z.as<double>(), nv, w.scal.as<Scal>());
+  GatherSpec g;
+  g.tr = tr;
+  g.u = w.u.as<double>();
+  g.mask = nullptr;                 // CG keeps every Dirichlet entry of u at zero
+  g.skip = &w.scal.as<Scal>()->done;
+  g.skip_stride = (int)(sizeof(Scal) / sizeof(int));
+  g.dpart = w.partD.as<double>();
+  g.lv1.partG = w.partG.as<double>();
+  g.lv1.partR = w.partR.as<double>();
+  g.lv1.n1 = w.nbs;
+  g.fin.sc = w.scal.as<Scal>();
+  g.fin.part = w.partD.as<double>();
+  g.fin.nb = conv_passB_blocks(P.op, fp32);
+  GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32));
+  const dim3 gs(w.nbs, P.nrhs);
+#define GOFD_SCATTER_ARGS(WTS, Y)                                                                                \
+  tr->csc_off.as<int>(), tr->csc_node.as<int>(), WTS, Y, nv, nn, tr->imask.as<double>(), w.scal.as<Scal>(),     \
+      w.x.as<double>(), w.p.as<double>(), w.s.as<double>(), w.r.as<double>(), w.u.as<double>(),                  \
+      tr->dscale.as<double>(), dk, w.per, w.partG.as<double>(), w.partR.as<double>()
+  if (fp32)
+    hipLaunchKernelGGL((k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st,
+                       GOFD_SCATTER_ARGS(tr->csc_w32.as<float>(), w.grid.as<float>()));
+  else
+    hipLaunchKernelGGL((k_scatter_cg<double, double, SCAT_G>), gs, dim3(BS), 0, st,
+                       GOFD_SCATTER_ARGS(tr->csc_w.as<double>(), w.grid.as<double>()));
+#undef GOFD_SCATTER_ARGS
   HIP_TRY(ctx, hipGetLastError());
+  if (dk < 0) GOFD_TRY(precond_apply(ctx, P, w, w.scal.as<Scal>(), w.partG.as<double>()));
   return GOFD_OK;
 }
 
@@ -668,34 +658,37 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
             bool use_graph, std::vector<Scal>& hs, double* history) {
   hipStream_t st = ctx->stream;
   const long long nv = P.tr->nv;
-  dim3 gd(NB_DOT, P.nrhs);
-  const int diag_kind = is_ic(P.pc) ? -1 : ((P.pc && P.pc->kind == GOFD_PC_DIAG) ? 1 : 0);
+  const int dk = diag_kind_of(P.pc);
   GOFD_TRY(conv_prepare(ctx, P.op, P.nrhs));
-  if (diag_kind < 0) {
-    // z = M^{-1} b before the start kernel (scalars must mark every rhs as active)
-    hipLaunchKernelGGL(k_fill_d, dim3(grid1(sizeof(Scal) / 8 * P.nrhs, 64)), dim3(64), 0, st, w.scal.as<double>(),
-                       (long long)(sizeof(Scal) / 8 * P.nrhs), 0.0);
+  GOFD_TRY(dev_reserve(ctx, w.partD, sizeof(double) * 3 * conv_passB_blocks(P.op, fp32) * P.nrhs));
+  if (dk < 0) {
+    // u = M^{-1} b before the start kernel (no state is read: pass none)
     HIP_TRY(ctx, hipMemcpyAsync(w.r.p, w.b.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
-    GOFD_TRY(precond_apply(ctx, P, w));
+    GOFD_TRY(precond_apply(ctx, P, w, nullptr, nullptr));
   }
-  hipLaunchKernelGGL(k_start, gd, dim3(BS), 0, st, w.b.as<double>(), w.x.as<double>(), w.r.as<double>(),
-                     w.z.as<double>(), w.p.as<double>(), diag_kind == 1 ? P.tr->dscale.as<double>() : nullptr, nv,
-                     w.scal.as<Scal>(), tol, w.partials.as<double>(), w.counters.as<unsigned>(), diag_kind < 0 ? 1 : 0);
-  hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, st, (int)FIN_START, w.partials.as<double>(), NB_DOT,
-                     w.scal.as<Scal>(), tol, 0, nullptr);
+  hipLaunchKernelGGL(k_cg_start, dim3(w.nbs, P.nrhs), dim3(BS), 0, st, w.b.as<double>(), w.x.as<double>(),
+                     w.r.as<double>(), w.u.as<double>(), w.p.as<double>(), w.s.as<double>(),
+                     dk == 1 ? P.tr->dscale.as<double>() : nullptr, nv, dk < 0 ? 1 : 0, w.partG.as<double>(),
+                     w.partR.as<double>());
+  hipLaunchKernelGGL(k_cg_init, dim3(P.nrhs), dim3(BS), 0, st, w.partG.as<double>(), w.partR.as<double>(), w.nbs,
+                     w.scal.as<Scal>(), tol);
   HIP_TRY(ctx, hipGetLastError());
   hs.resize(P.nrhs);
+  check_every = std::max(1, check_every);
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  if (use_graph) {
+  if (use_graph && !history) {
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
       use_graph = false;
     } else {
       int rc = GOFD_OK;
-      for (int k = 0; k < check_every && rc == GOFD_OK; ++k) rc = cg_iteration(ctx, P, w, fp32);
+      for (int j = 0; j < check_every && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, P, w, fp32);
       hipError_t e = hipStreamEndCapture(st, &graph);
-      if (rc != GOFD_OK) return rc;
+      if (rc != GOFD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
       if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGetLastError();
         if (graph) (void)hipGraphDestroy(graph);
@@ -705,14 +698,12 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
       }
     }
   }
+  // Iteration j tests x_j (its last pass) and then applies step j, so after
+  // `it` iterations `it` steps are applied unless the solve stopped earlier.
   int it = 0;
   int rc = GOFD_OK;
   std::vector<Scal> tmp(P.nrhs);
-  if (history) {
-    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
-    history[0] = tmp[0].bb > 0 ? 1.0 : 0.0;
-  }
+  if (history) history[0] = 1.0;
   while (it < max_iter) {
     const int chunk = history ? 1 : check_every;
     if (use_graph && !history) {
@@ -721,7 +712,7 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
         break;
       }
     } else {
-      for (int k = 0; k < chunk && rc == GOFD_OK; ++k) rc = cg_iteration(ctx, P, w, fp32);
+      for (int j = 0; j < chunk && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, P, w, fp32);
       if (rc != GOFD_OK) break;
     }
     it += chunk;
@@ -730,7 +721,8 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
       rc = gofd_fail(ctx, GOFD_E_HIP, "reading solver state failed");
       break;
     }
-    if (history && it <= max_iter) history[it] = tmp[0].bb > 0 ? std::sqrt(tmp[0].rr / tmp[0].bb) : 0.0;
+    // the state's rr is that of the iterate tested last: x_{it-1}
+    if (history && it - 1 <= max_iter) history[it - 1] = tmp[0].bb > 0 ? std::sqrt(tmp[0].rr / tmp[0].bb) : 0.0;
     bool all = true;
     for (int k = 0; k < P.nrhs; ++k) all = all && tmp[k].done;
     if (all) break;
@@ -738,8 +730,10 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (rc != GOFD_OK) return rc;
-  HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
-  HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (!history || !hs.empty()) {
+    HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+  }
   return GOFD_OK;
 }
 
@@ -747,12 +741,12 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
 int true_residual(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* x, const double* b, double* r,
                   std::vector<double>& rr, std::vector<double>& bb) {
   GOFD_TRY(conv_prepare(ctx, P.op, P.nrhs));
-  GOFD_TRY(apply_K(ctx, P, w, x, false, false));
+  GOFD_TRY(apply_K_plain(ctx, P, w, x, w.q.as<double>()));
   dim3 gd(NB_DOT, P.nrhs);
   hipLaunchKernelGGL(k_residual, gd, dim3(BS), 0, ctx->stream, b, w.q.as<double>(), r, (long long)P.tr->nv,
-                     w.out2.as<double>(), w.partials.as<double>(), w.counters.as<unsigned>());
-  hipLaunchKernelGGL(k_finish, dim3(P.nrhs), dim3(BS), 0, ctx->stream, (int)FIN_RESIDUAL, w.partials.as<double>(),
-                     NB_DOT, w.scal.as<Scal>(), 0.0, 0, w.out2.as<double>());
+                     w.partials.as<double>());
+  hipLaunchKernelGGL(k_residual_finish, dim3(P.nrhs), dim3(BS), 0, ctx->stream, w.partials.as<double>(),
+                     w.out2.as<double>());
   std::vector<double> h(2 * P.nrhs);
   HIP_TRY(ctx, hipMemcpyAsync(h.data(), w.out2.p, sizeof(double) * 2 * P.nrhs, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -525,7 +525,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ off, co
                                                  long long nv, long long n_nodes, int nrhs,
                                                  const double* __restrict__ scale, const double* __restrict__ mask,
                                                  double* __restrict__ z) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gid = (long long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const long long v = gid / G;
   const int lane = threadIdx.x % G;
   const int rhs = blockIdx.y;
