@@ -245,14 +245,20 @@ int gofd_precond_export(gofd_ctx ctx, gofd_precond pc, int32_t* rowptr_host, int
 enum { GOFD_F_GRID = 0, GOFD_F_VERTEX = 1 };
 enum {
   GOFD_MODE_FP64 = 0,            /* every product in double precision                         */
-  GOFD_MODE_FP32_REFINE = 1      /* FP32-grid CG corrections inside FP64 iterative refinement */
+  GOFD_MODE_FP32_REFINE = 1,     /* FP32-grid CG corrections inside FP64 iterative refinement */
+  GOFD_MODE_FP32_RELIABLE = 2    /* one CG run with FP32-grid products whose residual is      */
+                                 /* replaced by the FP64 true residual b - K x whenever it    */
+                                 /* has dropped by the factor inner_tol since the last        */
+                                 /* replacement, and before stopping (reliable updating,      */
+                                 /* Sleijpen and van der Vorst 1996)                          */
 };
 
 typedef struct {
   int mode;              /* GOFD_MODE_*                                                     */
   int max_iter;          /* total CG iterations allowed (0 = 20000)                         */
   int check_every;       /* host reads of the convergence flag every k iterations (0 = 8)   */
-  double inner_tol;      /* FP32 mode: relative tolerance of each correction solve (0 = 1e-5)*/
+  double inner_tol;      /* FP32_REFINE: relative tolerance of each correction solve (0 =   */
+                         /* 1e-5); FP32_RELIABLE: residual drop between replacements (0 = 1e-2) */
   int max_refine;        /* FP32 mode: maximum outer refinement steps (0 = 30)              */
   int use_graph;         /* capture k CG iterations in a hipGraph and replay it (1 = yes)   */
   double* history;       /* optional host array of max_iter+1 relative residuals, or NULL   */
@@ -260,7 +266,7 @@ typedef struct {
 
 typedef struct {
   int iterations;        /* CG iterations (all refinement steps)                            */
-  int refinements;       /* outer FP64 residual recomputations (FP32 mode)                  */
+  int refinements;       /* FP64 residual recomputations (FP32 modes)                       */
   double rel_residual;   /* ||b - K u|| / ||b|| recomputed in FP64 at exit                  */
   double time_ms;        /* wall time of the call                                           */
   int status;            /* GOFD_OK or the error returned                                   */

@@ -33,7 +33,7 @@ PC_NONE, PC_DIAG, PC_IC1_5, PC_IC1_9, PC_IC1_27 = 0, 1, 5, 9, 27
 PC_BY_NAME = {"NONE": PC_NONE, "DIAG": PC_DIAG, "IC1_5": PC_IC1_5, "IC1_9": PC_IC1_9, "IC1_27": PC_IC1_27}
 
 F_GRID, F_VERTEX = 0, 1
-MODE_FP64, MODE_FP32_REFINE = 0, 1
+MODE_FP64, MODE_FP32_REFINE, MODE_FP32_RELIABLE = 0, 1, 2
 
 
 class GofdError(RuntimeError):

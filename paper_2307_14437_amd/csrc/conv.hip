@@ -53,31 +53,45 @@ struct SrcGrid {
 // optional per-vertex scale and mask multiply u first.  Kept apart from the
 // row transform so that the dependent loads (element, record, vertex values)
 // run with one node per thread.
+#ifndef GOFD_GATHER_NPT
+#define GOFD_GATHER_NPT 2
+#endif
+constexpr int GATHER_NPT = GOFD_GATHER_NPT;   // nodes per thread of the gather (build-time knob)
+
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_gather(GridGeom g, const ElemRec<D>* __restrict__ recs,
                                                 const int* __restrict__ elem, const double* __restrict__ u,
                                                 const double* __restrict__ scale, const double* __restrict__ mask,
                                                 long long nv, long long n_nodes, R* __restrict__ out, Skip skip) {
-  const long long k = (long long)xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const long long k0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * (256 * GATHER_NPT) + threadIdx.x;
   const int rhs = blockIdx.y;
-  if (k >= n_nodes) return;
-  const int e = elem[k];
-  if (skip(rhs)) return;
-  double s = 0.0;
-  if (e >= 0) {
-    int vid[D + 1];
-    double lam[D + 1];
-    node_weights<D>(g, recs, e, k, vid, lam);
-    const double* ur = u + rhs * nv;
+  int e[GATHER_NPT];
 #pragma unroll
-    for (int r = 0; r <= D; ++r) {
-      double uv = ur[vid[r]];
-      if (scale) uv *= scale[vid[r]];
-      if (mask) uv *= mask[vid[r]];
-      s += lam[r] * uv;
-    }
+  for (int j = 0; j < GATHER_NPT; ++j) {
+    const long long k = k0 + j * 256;
+    e[j] = k < n_nodes ? elem[k] : -2;
   }
-  out[rhs * n_nodes + k] = (R)s;
+  if (skip(rhs)) return;
+  const double* ur = u + rhs * nv;
+#pragma unroll
+  for (int j = 0; j < GATHER_NPT; ++j) {
+    const long long k = k0 + j * 256;
+    if (e[j] == -2) continue;
+    double s = 0.0;
+    if (e[j] >= 0) {
+      int vid[D + 1];
+      double lam[D + 1];
+      node_weights<D>(g, recs, e[j], k, vid, lam);
+#pragma unroll
+      for (int r = 0; r <= D; ++r) {
+        double uv = ur[vid[r]];
+        if (scale) uv *= scale[vid[r]];
+        if (mask) uv *= mask[vid[r]];
+        s += lam[r] * uv;
+      }
+    }
+    out[rhs * n_nodes + k] = (R)s;
+  }
 }
 
 // ---------------------------------------------------------------- spectra layout
@@ -514,7 +528,7 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   geom.h = tr->h;
   for (int a = 0; a < 3; ++a) geom.lo[a] = tr->lo[a];
   GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
-  const dim3 gg(grid1(nn, 256), nrhs);
+  const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if (g->pregathered) passes &= ~8;
   double* dpart = g->dpart;
   const gofd_cg::Level1 lv1 = g->lv1;

@@ -162,6 +162,50 @@ __global__ __launch_bounds__(BS) void k_cg_init(const double* __restrict__ partG
   sc[rhs] = S;
 }
 
+// Residual replacement (reliable updating): r = b - q with q = K x from a
+// double-precision product, u = M_diag r; partials of gamma and (r, r).
+__global__ __launch_bounds__(BS) void k_cg_replace(const double* __restrict__ b, const double* __restrict__ q,
+                                                   double* __restrict__ r, double* __restrict__ u,
+                                                   const double* __restrict__ dinv, int dk, long long nv,
+                                                   const Scal* __restrict__ sc, double* __restrict__ partG,
+                                                   double* __restrict__ partR) {
+  __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
+  const int rhs = blockIdx.y;
+  if (sc[rhs].status != ST_OK) return;
+  const long long o = rhs * nv;
+  double acc[2] = {0.0, 0.0};
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
+    const double ri = b[o + i] - q[o + i];
+    r[o + i] = ri;
+    acc[1] += ri * ri;
+    if (dk >= 0) {
+      const double ui = dk ? ri * dinv[i] : ri;
+      u[o + i] = ui;
+      acc[0] += ri * ui;
+    }
+  }
+  block_sum_n<BS, 2>(acc, sh);
+  if (threadIdx.x == 0) {
+    if (dk >= 0) partG[(long long)rhs * gridDim.x + blockIdx.x] = acc[0];
+    partR[(long long)rhs * gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
+// one block per rhs: after a replacement the true (r, r) decides whether the
+// rhs has converged; a rhs that had stopped on its recursive residual resumes
+// when the true one is still above the tolerance
+__global__ __launch_bounds__(BS) void k_cg_reopen(const double* __restrict__ partR, int nb, Scal* __restrict__ sc) {
+  __shared__ double sh[BS];
+  const int rhs = blockIdx.x;
+  const double rr = sum_fixed(partR + (long long)rhs * nb, nb, sh);
+  if (threadIdx.x != 0) return;
+  Scal S = sc[rhs];
+  if (S.status != ST_OK) return;
+  S.rr = rr;
+  S.done = (rr <= S.tol2) ? 1 : 0;
+  sc[rhs] = S;
+}
+
 // w = mask * I^T y (the product K u, G lanes per vertex) and, in the same
 // pass, the step decided by the last FFT pass: s = w + beta s, p = u + beta p,
 // x += alpha p, r -= alpha s and, for a diagonal (or no) preconditioner,
@@ -654,11 +698,18 @@ int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32) {
 
 // CG from x = 0 on right-hand sides w.b; result in w.x.  Returns per-rhs
 // iterations and status through hs (host Scal copies).
+// With replace_drop > 0 the recursively updated residual is replaced by the
+// true one, r = b - K x with a double-precision product, whenever (r, r) has
+// dropped by replace_drop^2 since the last replacement and whenever a rhs
+// stops on its recursive residual (reliable updating); the count goes to
+// *n_replace.
 int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, int max_iter, int check_every,
-            bool use_graph, std::vector<Scal>& hs, double* history) {
+            bool use_graph, std::vector<Scal>& hs, double* history, double replace_drop = 0.0,
+            int* n_replace = nullptr) {
   hipStream_t st = ctx->stream;
   const long long nv = P.tr->nv;
   const int dk = diag_kind_of(P.pc);
+  if (n_replace) *n_replace = 0;
   GOFD_TRY(conv_prepare(ctx, P.op, P.nrhs));
   GOFD_TRY(dev_reserve(ctx, w.partD, sizeof(double) * 3 * conv_passB_blocks(P.op, fp32) * P.nrhs));
   if (dk < 0) {
@@ -698,12 +749,34 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
       }
     }
   }
+  // residual replacement: true residual of x in double precision, then the
+  // state's flags from it (reads the state back into tmp)
+  std::vector<double> rr_ref(P.nrhs, 0.0);
+  for (auto& v : rr_ref) v = HUGE_VAL;
+  auto replace_residual = [&](std::vector<Scal>& tmp) -> int {
+    GOFD_TRY(apply_K_plain(ctx, P, w, w.x.as<double>(), w.q.as<double>()));
+    hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, P.nrhs), dim3(BS), 0, st, w.b.as<double>(), w.q.as<double>(),
+                       w.r.as<double>(), w.u.as<double>(), P.tr->dscale.as<double>(), dk, nv, w.scal.as<Scal>(),
+                       w.partG.as<double>(), w.partR.as<double>());
+    hipLaunchKernelGGL(k_cg_reopen, dim3(P.nrhs), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>());
+    HIP_TRY(ctx, hipGetLastError());
+    if (dk < 0) GOFD_TRY(precond_apply(ctx, P, w, w.scal.as<Scal>(), w.partG.as<double>()));
+    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int k = 0; k < P.nrhs; ++k) rr_ref[k] = tmp[k].rr;
+    return GOFD_OK;
+  };
   // Iteration j tests x_j (its last pass) and then applies step j, so after
   // `it` iterations `it` steps are applied unless the solve stopped earlier.
   int it = 0;
   int rc = GOFD_OK;
   std::vector<Scal> tmp(P.nrhs);
   if (history) history[0] = 1.0;
+  if (replace_drop > 0.0) {
+    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int k = 0; k < P.nrhs; ++k) rr_ref[k] = tmp[k].rr;
+  }
   while (it < max_iter) {
     const int chunk = history ? 1 : check_every;
     if (use_graph && !history) {
@@ -723,6 +796,15 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
     }
     // the state's rr is that of the iterate tested last: x_{it-1}
     if (history && it - 1 <= max_iter) history[it - 1] = tmp[0].bb > 0 ? std::sqrt(tmp[0].rr / tmp[0].bb) : 0.0;
+    if (replace_drop > 0.0) {
+      bool need = false;
+      for (int k = 0; k < P.nrhs; ++k)
+        if (tmp[k].status == ST_OK && (tmp[k].done || tmp[k].rr < replace_drop * replace_drop * rr_ref[k])) need = true;
+      if (need) {
+        if ((rc = replace_residual(tmp)) != GOFD_OK) break;
+        if (n_replace) ++*n_replace;
+      }
+    }
     bool all = true;
     for (int k = 0; k < P.nrhs; ++k) all = all && tmp[k].done;
     if (all) break;
@@ -730,10 +812,8 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (rc != GOFD_OK) return rc;
-  if (!history || !hs.empty()) {
-    HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
-  }
+  HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
   return GOFD_OK;
 }
 
@@ -801,6 +881,18 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
     HIP_TRY(ctx, hipMemcpyAsync(u_out, w.x.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
     for (int k = 0; k < P.nrhs; ++k) {
       iters[k] = hs[k].iters;
+      if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
+      else if (!hs[k].done) status[k] = GOFD_E_NOT_CONVERGED;
+    }
+  } else if (mode == GOFD_MODE_FP32_RELIABLE) {
+    const double drop = (o && o->inner_tol > 0) ? o->inner_tol : 1e-2;
+    int nrep = 0;
+    rc = pcg_run(ctx, P, w, tol, true, max_iter, check, graph, hs, history, drop, &nrep);
+    if (rc != GOFD_OK) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(u_out, w.x.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
+    for (int k = 0; k < P.nrhs; ++k) {
+      iters[k] = hs[k].iters;
+      refs[k] = nrep;
       if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
       else if (!hs[k].done) status[k] = GOFD_E_NOT_CONVERGED;
     }

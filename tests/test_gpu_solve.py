@@ -98,6 +98,24 @@ def test_c1_fp32_refinement_reaches_fp64_accuracy(gctx, c1_setup):
         assert np.linalg.norm(u - uref) / np.linalg.norm(uref) < 1e-8
 
 
+def test_c1_fp32_reliable_updates_reach_fp64_accuracy(gctx, c1_setup):
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    f = np.ones((g.W, g.W))
+    b = operator.rhs_grid(otr, 0.5, f)
+    uref = _full(otr, solve.solve_dense(K, b))
+    _, i64 = gofd.solve(gctx, tr, op, _dev(f), tol=1e-11, pc=gofd.Precond(gctx, tr, op, "DIAG"))
+    for pcn in ("NONE", "DIAG", "IC1_9"):
+        pc = gofd.Precond(gctx, tr, op, pcn)
+        u, info = gofd.solve(gctx, tr, op, _dev(f), tol=1e-11, pc=pc, mode=gofd.MODE_FP32_RELIABLE)
+        u = u.cpu().numpy()
+        print(pcn, info[0], flush=True)
+        assert info[0]["refinements"] >= 1 and info[0]["rel_residual"] <= 1e-11
+        assert np.linalg.norm(u - uref) / np.linalg.norm(uref) < 1e-8
+        if pcn == "DIAG":       # one Krylov run: close to the FP64 iteration count
+            assert info[0]["iterations"] <= 1.3 * i64[0]["iterations"] + 5, (info[0], i64[0])
+
+
 def test_c1_vertex_rhs_and_multi_rhs(gctx, c1_setup):
     import paper_2307_14437_amd as gofd
     m, g, otr, T, tr, op, K = c1_setup
