@@ -79,7 +79,13 @@ __device__ __forceinline__ bool cg_decide(const Scal& S, double g, double rr, do
     stop = true;
   } else {
     beta = g / S.gamma;
-    const double den = d - beta * g / S.alpha;
+    double den = d - beta * g / S.alpha;
+    if (!(den > 0.0) && d > 0.0) {
+      // (p, K p) lost to cancellation (possible with single-precision
+      // products): restart along u, i.e. beta = 0 and (p, K p) = delta
+      beta = 0.0;
+      den = d;
+    }
     if (!(g > 0.0) || !(den > 0.0) || !isfinite(den)) {
       O.status = ST_BREAKDOWN;
       stop = true;

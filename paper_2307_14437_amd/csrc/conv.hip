@@ -21,6 +21,7 @@
 
 #include "bary.h"
 #include "cg_state.h"
+#include "conv_common.h"
 #include "fft.h"
 #include "internal.h"
 
@@ -33,20 +34,6 @@ namespace {
 inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------- sources
-
-// Optional per-rhs flag (a converged solve): blocks of a finished rhs return at once.
-struct Skip {
-  const int* flag;
-  int stride;
-  __device__ __forceinline__ bool operator()(int rhs) const { return flag && flag[(long long)rhs * stride]; }
-};
-
-template <typename T>
-struct SrcGrid {
-  const T* v;
-  long long n_nodes;
-  __device__ __forceinline__ T operator()(int rhs, long long k) const { return v[rhs * n_nodes + k]; }
-};
 
 // v = I u on the grid (eq. GoFD-1's interpolation): one thread per node, the
 // weights from the record of the node's element; zero outside the mesh.  The
@@ -119,7 +106,7 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passA(Src src, cplx<R>* __res
   __shared__ cplx<R> sbuf[LINES * PL];
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
-  const int row0 = (blockIdx.x * LINES + line) * 2;
+  const int row0 = (xcd_remap(blockIdx.x, gridDim.x) * LINES + line) * 2;   // row bands per XCD
   const int rhs = blockIdx.y;
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
@@ -294,7 +281,8 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restri
   __shared__ double shf[gofd_cg::block_sum_lds<NT, 3>()];
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
-  const int row0 = (blockIdx.x * LINES + line) * 2;
+  const int nrb = gridDim.x - (fin.sc ? 1 : 0);                            // row-pair blocks
+  const int row0 = (xcd_remap(min((int)blockIdx.x, nrb - 1), nrb) * LINES + line) * 2;   // row bands per XCD
   const int rhs = blockIdx.y;
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
@@ -507,44 +495,66 @@ int conv_prepare(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs) {
     zs *= (a == 0 ? op->half : op->W);
     nn *= op->W;
   }
+  if (op->d == 3) zs = conv3_workspace(op);
   GOFD_TRY(dev_reserve(ctx, op->G, sizeof(double) * nn * nrhs));
   return dev_reserve(ctx, op->Z, sizeof(cplx<double>) * zs * nrhs);
 }
 
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g, void* y,
                bool fp32, int passes) {
-  if (op->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "3D product not built yet");
-  const long long nn = (long long)op->W * op->W;
+  const int d = op->d;
+  if (d != 2 && d != 3) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "dimension");
+  long long nn = 1;
+  for (int a = 0; a < d; ++a) nn *= op->W;
   const Skip skip{g ? g->skip : nullptr, g ? g->skip_stride : 0};
+  double* dpart = g ? g->dpart : nullptr;
+  const gofd_cg::Level1 lv1 = g ? g->lv1 : gofd_cg::Level1();
+  const gofd_cg::Finish fin = g ? g->fin : gofd_cg::Finish();
   if (v) {
+    if (d == 3) return conv3_run(ctx, op, nrhs, v, nullptr, y, fp32, passes & 7, skip.flag, skip.stride, dpart, lv1, fin);
     SrcGrid<double> src{v, nn};
-    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip)
-                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip);
+    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin)
+                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin);
   }
   const gofd_transfer_s* tr = g->tr;
   GridGeom geom;
-  geom.d = 2;
+  geom.d = d;
   geom.W = tr->W;
   geom.h = tr->h;
   for (int a = 0; a < 3; ++a) geom.lo[a] = tr->lo[a];
   GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
   const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if (g->pregathered) passes &= ~8;
-  double* dpart = g->dpart;
-  const gofd_cg::Level1 lv1 = g->lv1;
-  const gofd_cg::Finish fin = g->fin;
+  hipStream_t st = ctx->stream;
+  if (passes & 8) {
+    if (d == 2) {
+      if (fp32)
+        hipLaunchKernelGGL((k_gather<float, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
+                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
+                           skip);
+      else
+        hipLaunchKernelGGL((k_gather<double, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
+                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
+                           op->G.as<double>(), skip);
+    } else {
+      if (fp32)
+        hipLaunchKernelGGL((k_gather<float, 3>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec3>(),
+                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
+                           skip);
+      else
+        hipLaunchKernelGGL((k_gather<double, 3>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec3>(),
+                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
+                           op->G.as<double>(), skip);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  if (d == 3)
+    return conv3_run(ctx, op, nrhs, fp32 ? nullptr : op->G.as<double>(), fp32 ? op->G.as<float>() : nullptr, y, fp32,
+                     passes & 7, skip.flag, skip.stride, dpart, lv1, fin);
   if (fp32) {
-    if (passes & 8)
-      hipLaunchKernelGGL((k_gather<float, 2>), gg, dim3(256), 0, ctx->stream, geom, tr->rec.as<ElemRec2>(),
-                         tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
-                         skip);
     SrcGrid<float> src{op->G.as<float>(), nn};
     return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin);
   }
-  if (passes & 8)
-    hipLaunchKernelGGL((k_gather<double, 2>), gg, dim3(256), 0, ctx->stream, geom, tr->rec.as<ElemRec2>(),
-                       tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(),
-                       skip);
   SrcGrid<double> src{op->G.as<double>(), nn};
   return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin);
 }
@@ -567,6 +577,7 @@ static int passB_blocks(int L) {
 }
 
 int conv_passB_blocks(const gofd_fdop_s* op, bool fp32) {
+  if (op->d == 3) return conv3_passC_blocks(op, fp32);
   return fp32 ? passB_blocks<float>(op->L) : passB_blocks<double>(op->L);
 }
 

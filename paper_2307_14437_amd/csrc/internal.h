@@ -169,8 +169,18 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
 
 bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op);
 
-// Number of blocks of the column pass (one partial of (A v, v) each).
+// Number of blocks of the column pass (one partial of (A v, v) each; in 3D
+// the z-line pass).
 int conv_passB_blocks(const gofd_fdop_s* op, bool fp32);
+
+// 3D product on grid fields (v64 or v32 source, nrhs fields of W^3 values);
+// passes: 1 x forward, 2 y/z/y passes, 4 x inverse.  Workspace op->Z holds
+// conv3_workspace(op) complex values per rhs.
+int conv3_run(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v64, const float* v32, void* y, bool fp32,
+              int passes, const int* skip_flag, int skip_stride, double* dpart, const gofd_cg::Level1& lv1,
+              const gofd_cg::Finish& fin);
+long long conv3_workspace(const gofd_fdop_s* op);
+int conv3_passC_blocks(const gofd_fdop_s* op, bool fp32);
 
 // Reserve the spectra workspace and twiddle tables for nrhs fields, so that
 // later products allocate nothing (required inside graph capture).

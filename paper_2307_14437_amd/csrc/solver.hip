@@ -1104,7 +1104,6 @@ extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, 
   if (!ctx || !tr || !op || !dLdu || !u || !f) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
   if (!same_grid(tr, op)) return gofd_fail(ctx, GOFD_E_ARG, "transfer and operator use different grids");
   if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
-  if (tr->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "adjoint in 3D needs the 3D product");
   WorkStream ws(ctx);
   hipStream_t st = ctx->stream;
   Problem P{tr, op, pc, 1};
@@ -1123,9 +1122,14 @@ extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, 
   g.W = tr->W;
   g.h = tr->h;
   for (int a = 0; a < 3; ++a) g.lo[a] = tr->lo[a];
-  if (grad_f)
-    hipLaunchKernelGGL(k_gather_grid<2>, dim3(grid1(nn, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec2>(),
-                       tr->elem.as<int>(), lam.as<double>(), tr->imask.as<double>(), nn, op->h2s, grad_f);
+  if (grad_f) {
+    if (tr->d == 2)
+      hipLaunchKernelGGL(k_gather_grid<2>, dim3(grid1(nn, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec2>(),
+                         tr->elem.as<int>(), lam.as<double>(), tr->imask.as<double>(), nn, op->h2s, grad_f);
+    else
+      hipLaunchKernelGGL(k_gather_grid<3>, dim3(grid1(nn, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec3>(),
+                         tr->elem.as<int>(), lam.as<double>(), tr->imask.as<double>(), nn, op->h2s, grad_f);
+  }
   if (grad_X) {
     DevBuf yu, yl, rg;
     GOFD_TRY(dev_reserve(ctx, yu, sizeof(double) * nn));
@@ -1144,10 +1148,16 @@ extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, 
     // u restricted to the interior (the solve's unknowns)
     hipLaunchKernelGGL(k_mask_copy, dim3(grid1(nv, 256)), dim3(256), 0, st, u, tr->imask.as<double>(), nv,
                        w.x.as<double>());
-    hipLaunchKernelGGL(k_grad_X<2>, dim3(grid1(nv, 128)), dim3(128), 0, st, g, tr->X.as<double>(),
-                       tr->rec.as<ElemRec2>(), tr->elem.as<int>(), tr->csc_off.as<int>(), tr->csc_node.as<int>(), nv,
-                       w.x.as<double>(), lam.as<double>(), tr->imask.as<double>(), rg.as<double>(), yl.as<double>(),
-                       grad_X);
+    if (tr->d == 2)
+      hipLaunchKernelGGL(k_grad_X<2>, dim3(grid1(nv, 128)), dim3(128), 0, st, g, tr->X.as<double>(),
+                         tr->rec.as<ElemRec2>(), tr->elem.as<int>(), tr->csc_off.as<int>(), tr->csc_node.as<int>(),
+                         nv, w.x.as<double>(), lam.as<double>(), tr->imask.as<double>(), rg.as<double>(),
+                         yl.as<double>(), grad_X);
+    else
+      hipLaunchKernelGGL(k_grad_X<3>, dim3(grid1(nv, 128)), dim3(128), 0, st, g, tr->X.as<double>(),
+                         tr->rec.as<ElemRec3>(), tr->elem.as<int>(), tr->csc_off.as<int>(), tr->csc_node.as<int>(),
+                         nv, w.x.as<double>(), lam.as<double>(), tr->imask.as<double>(), rg.as<double>(),
+                         yl.as<double>(), grad_X);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(st));
   }
