@@ -7,9 +7,13 @@ FFT length 2048), s in {0.25, 0.75}, f a seeded 16-mode Fourier series,
 tolerance 1e-8 on the relative residual of eq. GoFD-2.
 
 One step = the batched solve of both orders s with FP32 grid products inside
-FP64 iterative refinement (every step of the hot path: gather + FFT passes +
-I^T scatter inside CG, FP64 residuals and updates).  The same steps are also
-timed with plain FP64 products, and the A_h products alone, for comparison.
+FP64 refinement by residual replacement (every step of the hot path: gather +
+FFT passes + I^T scatter inside CG, FP64 true residuals, vectors and scalars).
+The same steps are also timed with plain FP64 products and with restarted
+FP32 refinement, and the A_h products alone, for comparison.
+
+--copy-probe MiB only runs a device-to-device copy of that size (the
+calibration kernel for HBM byte counters) and exits.
 Transfer, T tables and preconditioners are per-(mesh, grid, s) setup, built
 before the timed region and reported separately.
 
@@ -35,10 +39,39 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def _bytes_passB(W, half, b):
-    """Algorithmic HBM bytes of one column line of pass B: read and write W complex
-    values, read half real multipliers."""
-    return 2 * (2 * b * W) + b * half
+def _kernel_bytes(W, L, tr, m, b, precond):
+    """Algorithmic HBM bytes per launch of each kernel of one CG iteration of the 2D product (one field,
+    grid values of b bytes): every array the kernel needs is read or written once."""
+    nn, H = W * W, L // 2
+    info = tr.info
+    n_in, nnz, nv = info["n_inside"], info["nnz"], tr.nv
+    rec = 64 * len(m.elems)                               # element records of the barycentric maps
+    vec = 8 * nv * (6 + 5 + (1 if precond == "DIAG" else 0))   # mask, s, p, u, r, x (+ D^-1) in; s, p, x, r, u out
+    return {
+        "gather": 4 * nn + rec + 8 * nv + b * nn,         # element of each node, records, u; grid out
+        "passA": b * nn + 2 * b * W * H,                  # grid in; W rows of L/2 complex slots out
+        "passB": 4 * b * W * H + b * H * (H + 1),         # slots in and out; multiplier columns
+        "passC": 2 * b * W * H + b * nn,                  # slots in; grid out
+        "scatter": (4 + b) * nnz + b * n_in + vec,        # node ids, weights, y at inside nodes; CG vectors
+    }
+
+
+def _traffic(stage):
+    """HBM bytes per launch of the stage's kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy of known size),
+    or None when the library sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_gofd_pmc", os.path.join(ROOT, "paper_2307_14437_amd", "pmc.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != mod.source_hash() or stage not in d.get("stages", {}):
+        return None
+    return d["stages"][stage]["bytes"]
 
 
 def cpu_baseline(cfg, iters_by_s, precond, budget_iters=6):
@@ -74,9 +107,21 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precond", default="NONE", choices=["NONE", "DIAG", "IC1_9", "IC1_5"])
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--drop", type=float, default=0.1,
+                    help="FP32 mode: residual drop between FP64 residual replacements")
+    ap.add_argument("--inner-tol", type=float, default=1e-4, help="restarted-refinement comparison: inner tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0)
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        _sync()
+        print(json.dumps({"copy_probe_bytes_each_way": a.numel() * 8, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the workload runs on one "
               "MI355X; see the design notes on sharding)", file=sys.stderr)
@@ -110,20 +155,28 @@ def main():
         setup[f"precond_ms_s{s}"] = (time.perf_counter() - t) * 1e3
 
     def step(mode):
+        it = args.drop if mode == gofd.MODE_FP32_RELIABLE else args.inner_tol
         us, infos = gofd.solve_batched(ctx, [tr] * len(svals), ops, pcs, [fd] * len(svals), tol=tol,
-                                       mode=mode, inner_tol=args.inner_tol)
+                                       mode=mode, inner_tol=it)
         return us, infos
 
     # reference FP64 solutions (also the accuracy yardstick of the FP32 mode)
     u64, info64 = step(gofd.MODE_FP64)
     for _ in range(args.warmup):
-        step(gofd.MODE_FP32_REFINE)
+        step(gofd.MODE_FP32_RELIABLE)
     _sync()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        u32, info32 = step(gofd.MODE_FP32_REFINE)
+        u32, info32 = step(gofd.MODE_FP32_RELIABLE)
     _sync()
     ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    # restarted refinement (FP32 correction solves to inner_tol), one timed step for comparison
+    step(gofd.MODE_FP32_REFINE)
+    _sync()
+    t0 = time.perf_counter()
+    ur, infor = step(gofd.MODE_FP32_REFINE)
+    _sync()
+    ms_refine = (time.perf_counter() - t0) * 1e3
 
     for _ in range(args.warmup):
         step(gofd.MODE_FP64)
@@ -156,14 +209,26 @@ def main():
         mv[name] = e0.elapsed_time(e1) / n
     gpts = {k: W * W / (v * 1e-3) / 1e9 for k, v in mv.items()}
 
-    # roofline of the dominant kernel (pass B, FP32 grid, the mode the step runs in)
-    kt = {}
-    for name, which in (("gather", gofd.K_GATHER), ("passA", gofd.K_PASS_A), ("passB", gofd.K_PASS_B),
-                        ("passC", gofd.K_PASS_C), ("scatter", gofd.K_SCATTER)):
-        kt[name] = gofd.time_kernel(ctx, tr, ops[1], which, u, gofd.FP32_GRID, reps=50)
-    half = 2 * g.N + 1
-    bytes_B = _bytes_passB(W, half, 4) * half
-    achieved = bytes_B / (kt["passB"] * 1e-3) / 1e9
+    # per-kernel rooflines (FP32 grid, the mode of the step): the step's solves once more with every
+    # stage of every iteration bracketed by HIP events on the library's stream (no graph); algorithmic
+    # bytes per launch from the layouts (each array read or written once)
+    stage_sum = np.zeros(len(gofd.STAGES))
+    stage_n = 0
+    for i, s in enumerate(svals):
+        st_ms = np.zeros(len(gofd.STAGES))
+        _, inf = gofd.solve(ctx, tr, ops[i], fd, tol=tol, pc=pcs[i], mode=gofd.MODE_FP32_RELIABLE,
+                            inner_tol=args.drop, stage_ms=st_ms)
+        n_it = inf[0]["iterations"] + 1
+        stage_sum += st_ms * n_it
+        stage_n += n_it
+    stage_ms = stage_sum / stage_n
+    nb = _kernel_bytes(W, 2 * (W - 1), tr, m, 4, args.precond)
+    kernels = {k: {"us": stage_ms[j] * 1e3, "bytes": nb[k], "GBs": nb[k] / (stage_ms[j] * 1e-3) / 1e9,
+                   "frac": nb[k] / (stage_ms[j] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+               for j, k in enumerate(gofd.STAGES) if k in nb and stage_ms[j] > 0}
+    dom = max(kernels, key=lambda k: kernels[k]["us"])
+    achieved = kernels[dom]["GBs"]
+    traffic = _traffic(dom)
 
     its64 = {s: info64[i]["iterations"] for i, s in enumerate(svals)}
     line = {
@@ -182,19 +247,23 @@ def main():
         "config": {"workload": "2D L-shape, 67k-vertex graded Delaunay mesh, 1024x1024 overlay grid, "
                                "s in {0.25, 0.75}, 16-mode Fourier f, tol 1e-8",
                    "nv": tr.nv, "grid": f"{W}x{W}", "fft_length": 2 * (W - 1), "precond": args.precond,
-                   "inner_tol": args.inner_tol},
+                   "fp32_mode": "reliable updating", "drop": args.drop},
         "fp64": {"solves_per_s": len(svals) / (ms_step64 * 1e-3), "ms_per_step": ms_step64,
                  "iterations": {str(k): v for k, v in its64.items()}},
-        "fp32_refine": {"iterations": {str(s): info32[i]["iterations"] for i, s in enumerate(svals)},
-                        "refinements": {str(s): info32[i]["refinements"] for i, s in enumerate(svals)},
-                        "rel_error_vs_fp64": {str(s): errs[i] for i, s in enumerate(svals)},
-                        "rel_residual": {str(s): info32[i]["rel_residual"] for i, s in enumerate(svals)}},
+        "fp32_reliable": {"iterations": {str(s): info32[i]["iterations"] for i, s in enumerate(svals)},
+                          "fp64_replacements": {str(s): info32[i]["refinements"] for i, s in enumerate(svals)},
+                          "rel_error_vs_fp64": {str(s): errs[i] for i, s in enumerate(svals)},
+                          "rel_residual": {str(s): info32[i]["rel_residual"] for i, s in enumerate(svals)}},
+        "fp32_restarted_refinement": {"solves_per_s": len(svals) / (ms_refine * 1e-3), "ms_per_step": ms_refine,
+                                      "iterations": {str(s): infor[i]["iterations"] for i, s in enumerate(svals)},
+                                      "inner_tol": args.inner_tol},
         "matvec_gpts": gpts,
         "matvec_us": {k: v * 1e3 for k, v in mv.items()},
-        "kernel_us_fp32": {k: v * 1e3 for k, v in kt.items()},
+        "kernels_fp32": kernels,
         "setup_ms": setup,
-        "roofline": {"bound": "hbm", "kernel": "passB (fp32)", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": f"{dom} (fp32)", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": kernels[dom]["bytes"]},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, its64, args.precond)

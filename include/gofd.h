@@ -262,7 +262,15 @@ typedef struct {
   int max_refine;        /* FP32 mode: maximum outer refinement steps (0 = 30)              */
   int use_graph;         /* capture k CG iterations in a hipGraph and replay it (1 = yes)   */
   double* history;       /* optional host array of max_iter+1 relative residuals, or NULL   */
+  double* stage_ms;      /* optional host array of GOFD_N_STAGES: the iterations then run   */
+                         /* without a graph, each stage bracketed by HIP events on the       */
+                         /* library's stream, and the average milliseconds per launch of     */
+                         /* every stage are written here (0 for a stage that never ran)      */
 } gofd_solve_opts;
+
+/* stages of one CG iteration, in the order of stage_ms */
+enum { GOFD_ST_GATHER = 0, GOFD_ST_PASS_A = 1, GOFD_ST_PASS_B = 2, GOFD_ST_PASS_C = 3, GOFD_ST_SCATTER = 4,
+       GOFD_ST_PRECOND = 5, GOFD_N_STAGES = 6 };
 
 typedef struct {
   int iterations;        /* CG iterations (all refinement steps)                            */

@@ -66,7 +66,7 @@ class PrecondInfo(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("history", ctypes.POINTER(ctypes.c_double))]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("stage_ms", ctypes.POINTER(ctypes.c_double))]
 
 
 class SolveInfo(ctypes.Structure):
@@ -313,11 +313,19 @@ class Precond:
             pass
 
 
-def _opts(mode=MODE_FP64, max_iter=0, check_every=0, inner_tol=0.0, max_refine=0, use_graph=1, history=None):
+STAGES = ("gather", "passA", "passB", "passC", "scatter", "precond")
+
+
+def _opts(mode=MODE_FP64, max_iter=0, check_every=0, inner_tol=0.0, max_refine=0, use_graph=1, history=None,
+          stage_ms=None):
     o = SolveOpts(int(mode), int(max_iter), int(check_every), float(inner_tol), int(max_refine), int(use_graph),
-                  None)
+                  None, None)
     if history is not None:
         o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if stage_ms is not None:
+        if stage_ms.dtype != np.float64 or stage_ms.size < len(STAGES):
+            raise ValueError("stage_ms must be a float64 array of 6 entries")
+        o.stage_ms = stage_ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return o
 
 

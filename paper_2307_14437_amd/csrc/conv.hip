@@ -81,6 +81,37 @@ __global__ __launch_bounds__(256) void k_gather(GridGeom g, const ElemRec<D>* __
   }
 }
 
+// The same from compact per-node rows (3D): row c = idx[k] of an inside node
+// holds its four vertex ids and weights.
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather_ell(const int* __restrict__ idx, const int4* __restrict__ ev,
+                                                    const double2* __restrict__ ew, const double* __restrict__ u,
+                                                    const double* __restrict__ scale,
+                                                    const double* __restrict__ mask, long long nv, long long n_nodes,
+                                                    R* __restrict__ out, Skip skip) {
+  const long long k = (long long)xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int rhs = blockIdx.y;
+  if (k >= n_nodes) return;
+  const int c = idx[k];
+  if (skip(rhs)) return;
+  double s = 0.0;
+  if (c >= 0) {
+    const int4 v = ev[c];
+    const double2 w01 = ew[2 * (long long)c], w23 = ew[2 * (long long)c + 1];
+    const int vid[4] = {v.x, v.y, v.z, v.w};
+    const double lam[4] = {w01.x, w01.y, w23.x, w23.y};
+    const double* ur = u + rhs * nv;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double uv = ur[vid[r]];
+      if (scale) uv *= scale[vid[r]];
+      if (mask) uv *= mask[vid[r]];
+      s += lam[r] * uv;
+    }
+  }
+  out[rhs * n_nodes + k] = (R)s;
+}
+
 // ---------------------------------------------------------------- spectra layout
 // Z holds, per rhs, the L/2 column slots of the W window rows after the row
 // transform, in tiles of four slots: Z[slot/4][row][slot%4].  A block of the
@@ -376,16 +407,16 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   const int nbA = (pairs + C::LINES_A - 1) / C::LINES_A;
   hipStream_t st = ctx->stream;
   if (passes & 1)
-    hipLaunchKernelGGL((k_passA<R, L, C::EA, C::LINES_A, Src>), dim3(nbA, nrhs), dim3(C::LINES_A * C::TA), 0, st,
+    GOFD_LAUNCH(ctx, (k_passA<R, L, C::EA, C::LINES_A, Src>), dim3(nbA, nrhs), dim3(C::LINES_A * C::TA), 0, st,
                        src, Z, W, tw, zs, skip);
   if ((passes & 2) && dpart)
-    hipLaunchKernelGGL((k_passB<R, L, C::EB, C::LB, true>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
+    GOFD_LAUNCH(ctx, (k_passB<R, L, C::EB, C::LB, true>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
                        st, Z, W, half, That, tw, zs, skip, dpart, lv1);
   else if (passes & 2)
-    hipLaunchKernelGGL((k_passB<R, L, C::EB, C::LB, false>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
+    GOFD_LAUNCH(ctx, (k_passB<R, L, C::EB, C::LB, false>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
                        st, Z, W, half, That, tw, zs, skip, dpart, lv1);
   if (passes & 4)
-    hipLaunchKernelGGL((k_passC<R, Y, L, C::EA, C::LINES_A>), dim3(nbA + (fin.sc ? 1 : 0), nrhs), dim3(C::LINES_A * C::TA), 0, st, Z,
+    GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A>), dim3(nbA + (fin.sc ? 1 : 0), nrhs), dim3(C::LINES_A * C::TA), 0, st, Z,
                        W, tw, zs, y, (long long)W * W, skip, fin);
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
@@ -529,21 +560,22 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   if (passes & 8) {
     if (d == 2) {
       if (fp32)
-        hipLaunchKernelGGL((k_gather<float, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
+        GOFD_LAUNCH(ctx, (k_gather<float, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
                            tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
                            skip);
       else
-        hipLaunchKernelGGL((k_gather<double, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
+        GOFD_LAUNCH(ctx, (k_gather<double, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
                            tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
                            op->G.as<double>(), skip);
     } else {
+      const dim3 ge(grid1(nn, 256), nrhs);
       if (fp32)
-        hipLaunchKernelGGL((k_gather<float, 3>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec3>(),
-                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
-                           skip);
+        GOFD_LAUNCH(ctx, (k_gather_ell<float>), ge, dim3(256), 0, st, tr->ell_idx.as<int>(), tr->ell_v.as<int4>(),
+                           tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
+                           op->G.as<float>(), skip);
       else
-        hipLaunchKernelGGL((k_gather<double, 3>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec3>(),
-                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
+        GOFD_LAUNCH(ctx, (k_gather_ell<double>), ge, dim3(256), 0, st, tr->ell_idx.as<int>(), tr->ell_v.as<int4>(),
+                           tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
                            op->G.as<double>(), skip);
     }
     HIP_TRY(ctx, hipGetLastError());

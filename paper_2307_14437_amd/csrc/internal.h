@@ -1,6 +1,7 @@
 // Internal declarations of the GoFD HIP library (gfx950).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "cg_state.h"
@@ -73,8 +74,24 @@ struct gofd_ctx_s {
   std::map<int, TwiddleTables*> twiddles;   // keyed by L
   DevBuf scratch;                           // small reduction scratch (partials, counters)
   DevBuf flag;                              // int status flags
+  // When set, the next kernel launched through GOFD_LAUNCH records these
+  // events at its own start and end (stage timing); the launch clears them.
+  hipEvent_t timer_start = nullptr, timer_stop = nullptr;
   ~gofd_ctx_s();
 };
+
+// Launch on a stream; if the context holds a pending pair of timing events,
+// the launch records them at the kernel's start and end (AMD extended launch).
+#define GOFD_LAUNCH(CTX, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                               \
+  do {                                                                                                          \
+    if ((CTX)->timer_start) {                                                                                   \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, (CTX)->timer_start, (CTX)->timer_stop, 0,        \
+                            __VA_ARGS__);                                                                       \
+      (CTX)->timer_start = (CTX)->timer_stop = nullptr;                                                         \
+    } else {                                                                                                    \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                                      \
+    }                                                                                                           \
+  } while (0)
 
 // Run a solve on the library's own stream, ordered after the caller's stream
 // on entry and before it on exit.
@@ -108,6 +125,9 @@ struct gofd_transfer_s {
   DevBuf dsqrt;      // double[nv]: 1/sqrt(D_j) (0 where D_j == 0)
   DevBuf bmask;      // uint8[nv], 1 = Dirichlet vertex
   DevBuf imask;      // double[nv], 1.0 interior, 0.0 Dirichlet
+  DevBuf ell_idx;    // 3D: int32[n_nodes+1], compact row of each inside node or -1
+  DevBuf ell_v;      // 3D: int32[n_inside*4], vertex ids of the interpolation row
+  DevBuf ell_w;      // 3D: double[n_inside*4], barycentric weights (same bits as the CSC)
   std::vector<int32_t> elems_host;
   std::vector<uint8_t> bmask_host;
   std::vector<double> X_host;

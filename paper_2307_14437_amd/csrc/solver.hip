@@ -657,10 +657,33 @@ int diag_kind_of(const gofd_precond_s* pc) {
   return is_ic(pc) ? -1 : ((pc && pc->kind == GOFD_PC_DIAG) ? 1 : 0);
 }
 
+// Per-stage timing of the iterations (no graph): every stage's kernel is
+// launched with the extended launch that records a start and an end event on
+// the library's stream at the kernel's own start and end; the two
+// triangular solves of IC(1) are bracketed by ordinary events.
+struct StageProf {
+  hipEvent_t ev[2 * GOFD_N_STAGES] = {};      // start and end of each stage
+  double sum[GOFD_N_STAGES] = {};
+  int cnt[GOFD_N_STAGES] = {};
+  bool ok = false;
+  explicit StageProf(bool on) {
+    if (!on) return;
+    ok = true;
+    for (auto& e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+  }
+  ~StageProf() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void write(double* out) const {
+    for (int i = 0; i < GOFD_N_STAGES; ++i) out[i] = cnt[i] ? sum[i] / cnt[i] : 0.0;
+  }
+};
+
 // One CG iteration: product w = K u (gather, FFT passes with the delta
 // partials and the step decision, scatter with the vector update), then for
 // IC(1) the triangular solves u = M^{-1} r with the next gamma.
-int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32) {
+int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32, StageProf* prof = nullptr) {
   gofd_transfer_s* tr = P.tr;
   const int dk = diag_kind_of(P.pc);
   const long long nn = tr->n_nodes, nv = tr->nv;
@@ -678,21 +701,50 @@ int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32) {
   g.fin.sc = w.scal.as<Scal>();
   g.fin.part = w.partD.as<double>();
   g.fin.nb = conv_passB_blocks(P.op, fp32);
-  GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32));
+  if (prof) {
+    // the same launches one stage at a time, each kernel recording its own
+    // start and end events
+    static const int stage_passes[4] = {8, 1, 2, 4};
+    for (int k = 0; k < 4; ++k) {
+      ctx->timer_start = prof->ev[2 * k];
+      ctx->timer_stop = prof->ev[2 * k + 1];
+      GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32, stage_passes[k]));
+      ctx->timer_start = ctx->timer_stop = nullptr;
+    }
+    ctx->timer_start = prof->ev[8];
+    ctx->timer_stop = prof->ev[9];
+  } else {
+    GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32));
+  }
   const dim3 gs(w.nbs, P.nrhs);
 #define GOFD_SCATTER_ARGS(WTS, Y)                                                                                \
   tr->csc_off.as<int>(), tr->csc_node.as<int>(), WTS, Y, nv, nn, tr->imask.as<double>(), w.scal.as<Scal>(),     \
       w.x.as<double>(), w.p.as<double>(), w.s.as<double>(), w.r.as<double>(), w.u.as<double>(),                  \
       tr->dscale.as<double>(), dk, w.per, w.partG.as<double>(), w.partR.as<double>()
   if (fp32)
-    hipLaunchKernelGGL((k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st,
-                       GOFD_SCATTER_ARGS(tr->csc_w32.as<float>(), w.grid.as<float>()));
+    GOFD_LAUNCH(ctx, (k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st,
+                GOFD_SCATTER_ARGS(tr->csc_w32.as<float>(), w.grid.as<float>()));
   else
-    hipLaunchKernelGGL((k_scatter_cg<double, double, SCAT_G>), gs, dim3(BS), 0, st,
-                       GOFD_SCATTER_ARGS(tr->csc_w.as<double>(), w.grid.as<double>()));
+    GOFD_LAUNCH(ctx, (k_scatter_cg<double, double, SCAT_G>), gs, dim3(BS), 0, st,
+                GOFD_SCATTER_ARGS(tr->csc_w.as<double>(), w.grid.as<double>()));
 #undef GOFD_SCATTER_ARGS
   HIP_TRY(ctx, hipGetLastError());
+  if (prof) {
+    ctx->timer_start = ctx->timer_stop = nullptr;
+    if (dk < 0) HIP_TRY(ctx, hipEventRecord(prof->ev[10], st));
+  }
   if (dk < 0) GOFD_TRY(precond_apply(ctx, P, w, w.scal.as<Scal>(), w.partG.as<double>()));
+  if (prof) {
+    if (dk < 0) HIP_TRY(ctx, hipEventRecord(prof->ev[11], st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    for (int k = 0; k < GOFD_N_STAGES; ++k) {
+      if (k == GOFD_ST_PRECOND && dk >= 0) continue;
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, prof->ev[2 * k], prof->ev[2 * k + 1]));
+      prof->sum[k] += ms;
+      prof->cnt[k] += 1;
+    }
+  }
   return GOFD_OK;
 }
 
@@ -705,7 +757,7 @@ int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32) {
 // *n_replace.
 int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, int max_iter, int check_every,
             bool use_graph, std::vector<Scal>& hs, double* history, double replace_drop = 0.0,
-            int* n_replace = nullptr) {
+            int* n_replace = nullptr, StageProf* prof = nullptr) {
   hipStream_t st = ctx->stream;
   const long long nv = P.tr->nv;
   const int dk = diag_kind_of(P.pc);
@@ -726,6 +778,10 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
   HIP_TRY(ctx, hipGetLastError());
   hs.resize(P.nrhs);
   check_every = std::max(1, check_every);
+  if (prof) {
+    use_graph = false;                // stages timed one by one, state read every iteration
+    check_every = 1;
+  }
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   if (use_graph && !history) {
@@ -785,7 +841,7 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
         break;
       }
     } else {
-      for (int j = 0; j < chunk && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, P, w, fp32);
+      for (int j = 0; j < chunk && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, P, w, fp32, prof);
       if (rc != GOFD_OK) break;
     }
     it += chunk;
@@ -869,6 +925,9 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
   const int check = (o && o->check_every > 0) ? o->check_every : 8;
   const bool graph = o ? o->use_graph != 0 : true;
   double* history = o ? o->history : nullptr;
+  StageProf profobj(o && o->stage_ms);
+  StageProf* prof = (o && o->stage_ms) ? &profobj : nullptr;
+  if (prof && !prof->ok) return gofd_fail(ctx, GOFD_E_HIP, "event creation failed");
   const long long nv = P.tr->nv;
   hipStream_t st = ctx->stream;
   std::vector<Scal> hs;
@@ -876,7 +935,7 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
   std::vector<double> rel(P.nrhs, 0.0);
   int rc = GOFD_OK;
   if (mode == GOFD_MODE_FP64) {
-    rc = pcg_run(ctx, P, w, tol, false, max_iter, check, graph, hs, history);
+    rc = pcg_run(ctx, P, w, tol, false, max_iter, check, graph, hs, history, 0.0, nullptr, prof);
     if (rc != GOFD_OK) return rc;
     HIP_TRY(ctx, hipMemcpyAsync(u_out, w.x.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
     for (int k = 0; k < P.nrhs; ++k) {
@@ -887,7 +946,7 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
   } else if (mode == GOFD_MODE_FP32_RELIABLE) {
     const double drop = (o && o->inner_tol > 0) ? o->inner_tol : 1e-2;
     int nrep = 0;
-    rc = pcg_run(ctx, P, w, tol, true, max_iter, check, graph, hs, history, drop, &nrep);
+    rc = pcg_run(ctx, P, w, tol, true, max_iter, check, graph, hs, history, drop, &nrep, prof);
     if (rc != GOFD_OK) return rc;
     HIP_TRY(ctx, hipMemcpyAsync(u_out, w.x.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
     for (int k = 0; k < P.nrhs; ++k) {
@@ -919,7 +978,7 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
       }
       if (all || ref == max_ref || total_it >= max_iter) break;
       // correction: K d = r with single-precision grid products
-      rc = pcg_run(ctx, P, w, inner, true, max_iter - total_it, check, graph, hs, nullptr);
+      rc = pcg_run(ctx, P, w, inner, true, max_iter - total_it, check, graph, hs, nullptr, 0.0, nullptr, prof);
       if (rc != GOFD_OK) return rc;
       int mx = 0;
       for (int k = 0; k < P.nrhs; ++k) {
@@ -959,6 +1018,7 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
     }
     if (status[k] != GOFD_OK && worst == GOFD_OK) worst = status[k];
   }
+  if (prof) prof->write(o->stage_ms);
   if (worst != GOFD_OK) return gofd_fail(ctx, worst, "solve did not reach the tolerance for every right-hand side");
   return GOFD_OK;
 }

@@ -226,6 +226,33 @@ __global__ void k_export_ell(GridGeom g, const ElemRec<D>* __restrict__ recs,
   }
 }
 
+__global__ void k_inside_flag(const int* __restrict__ elem, long long n, int* __restrict__ flag) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) flag[k] = elem[k] >= 0 ? 1 : 0;
+}
+
+// Interpolation rows of the inside nodes, compacted: idx holds the exclusive
+// prefix of the inside flags on entry and the row (or -1) on exit.
+template <int D>
+__global__ void k_fill_ell(GridGeom g, const ElemRec<D>* __restrict__ recs, const int* __restrict__ elem_of_node,
+                           long long n, int* __restrict__ idx, int* __restrict__ ev, double* __restrict__ ew) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int e = elem_of_node[k];
+  if (e < 0) {
+    idx[k] = -1;
+    return;
+  }
+  const long long c = idx[k];
+  int vid[D + 1];
+  double lam[D + 1];
+  node_weights<D>(g, recs, e, k, vid, lam);
+  for (int r = 0; r <= D; ++r) {
+    ev[c * (D + 1) + r] = vid[r];
+    ew[c * (D + 1) + r] = lam[r];
+  }
+}
+
 inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -418,6 +445,22 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   hipLaunchKernelGGL(k_sort_segments, dim3(grid1(nv * 64, 256)), dim3(256), 0, st, tr->csc_off.as<int>(),
                      (long long)nv, node_tmp.as<int>(), w_tmp.as<double>(), tr->csc_node.as<int>(),
                      tr->csc_w.as<double>());
+  if (d == 3) {
+    // compact interpolation rows for the gather: in 3D the nodes of an element
+    // lie in different planes, so per-node rows stream better than records
+    GOFD_TRY(dev_reserve(ctx, tr->ell_idx, sizeof(int32_t) * (n_nodes + 1)));
+    GOFD_TRY(dev_reserve(ctx, tr->ell_v, sizeof(int32_t) * 4 * std::max<int64_t>(n_inside, 1)));
+    GOFD_TRY(dev_reserve(ctx, tr->ell_w, sizeof(double) * 4 * std::max<int64_t>(n_inside, 1)));
+    DevBuf flag;
+    GOFD_TRY(dev_reserve(ctx, flag, sizeof(int32_t) * (n_nodes + 1)));
+    hipLaunchKernelGGL(k_inside_flag, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
+                       (long long)n_nodes, flag.as<int>());
+    GOFD_TRY(scan_exclusive_i32(ctx, flag.as<int32_t>(), tr->ell_idx.as<int32_t>(), n_nodes));
+    hipLaunchKernelGGL(k_fill_ell<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec3>(),
+                       tr->elem.as<int>(), (long long)n_nodes, tr->ell_idx.as<int>(), tr->ell_v.as<int>(),
+                       tr->ell_w.as<double>());
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+  }
   GOFD_TRY(dev_reserve(ctx, tr->D, sizeof(double) * nv));
   GOFD_TRY(dev_reserve(ctx, tr->dscale, sizeof(double) * nv));
   GOFD_TRY(dev_reserve(ctx, tr->dsqrt, sizeof(double) * nv));

@@ -180,3 +180,16 @@ def test_lshape_full_size_solves_oracle_system(gctx, s):
         assert np.linalg.norm(r) / np.linalg.norm(b) < 1.5e-8
     a, c = u64.cpu().numpy(), u32.cpu().numpy()
     assert np.linalg.norm(a - c) / np.linalg.norm(a) < 1e-6
+
+
+def test_stage_timing_reports_every_stage(gctx, c1_setup):
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    f = _dev(np.ones((g.W, g.W)))
+    u0, i0 = gofd.solve(gctx, tr, op, f, tol=1e-10, pc=gofd.Precond(gctx, tr, op, "DIAG"))
+    st = np.zeros(len(gofd.STAGES))
+    u1, i1 = gofd.solve(gctx, tr, op, f, tol=1e-10, pc=gofd.Precond(gctx, tr, op, "DIAG"), stage_ms=st)
+    print(dict(zip(gofd.STAGES, st)), flush=True)
+    assert np.all(st[:5] > 0) and np.all(st[:5] < 10.0) and st[5] == 0.0
+    assert i1[0]["iterations"] == i0[0]["iterations"]                  # same iterates without the graph
+    assert np.array_equal(u0.cpu().numpy(), u1.cpu().numpy())
