@@ -294,9 +294,14 @@ int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, in
 
 /* Many independent problems (mesh, grid, s, right-hand sides) in one call:
  * problem q uses tr[q], op[q], pc[q] (nullable) and nrhs[q] right-hand sides
- * f_dev[q] -> u_dev[q].  The CG iterations of all problems advance together,
- * each stage issued once per iteration for the whole batch; converged systems
- * are masked.  info: host array of sum(nrhs) entries (nullable). */
+ * f_dev[q] -> u_dev[q].  Problems are grouped by grid shape (d, 2N+1 and the
+ * FFT length); within a group the CG iterations of all (problem, rhs) items
+ * advance together, every stage of an iteration one kernel launch for the
+ * whole group (items index per-item descriptors of their mesh, vectors and
+ * kernel spectrum), captured in a hipGraph; converged items are masked.  IC(1)
+ * triangular solves run per problem.  Groups are solved one after another.
+ * info: host array of sum(nrhs) entries in problem order (nullable).
+ * Errors: as gofd_solve. */
 int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* tr, const gofd_fdop* op,
                        const gofd_precond* pc, const int* nrhs, const double* const* f_dev,
                        int f_loc, double tol, const gofd_solve_opts* opts, double* const* u_dev,

@@ -1,0 +1,31 @@
+// Work items of a batched solve: one item per (problem, right-hand side).
+//
+// Every kernel of a CG iteration runs once per batch with blockIdx.y = item;
+// a block reads its item's descriptor (mesh arrays, vector offset, grid
+// geometry) and works on that item only.  Problems of one batch share the
+// grid shape (d, W, L) and may differ in mesh, box and order s.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bary.h"
+
+struct CgItem {
+  // transfer of the item's problem
+  const int* csc_off;
+  const int* csc_node;
+  const double* csc_w;
+  const float* csc_w32;
+  const double* imask;        // 1 interior, 0 Dirichlet
+  const double* dscale;       // 1 / D_j
+  const void* recs;           // ElemRec2 / ElemRec3 per element
+  const int* elem;            // element of each grid node or -1
+  const int* ell_idx;         // 3D: compact row of each inside node or -1
+  const int4* ell_v;          // 3D: vertex ids of the rows
+  const double2* ell_w;       // 3D: weights of the rows
+  GridGeom g;
+  long long nv;               // vertices of the mesh
+  long long off;              // offset of the item's vectors in the batch vectors
+  int dk;                     // preconditioner: 1 diagonal, 0 none, -1 IC(1)
+  int pad;
+};

@@ -20,6 +20,7 @@
 #include <memory>
 
 #include "bary.h"
+#include "cg_items.h"
 #include "cg_state.h"
 #include "conv_common.h"
 #include "fft.h"
@@ -112,6 +113,54 @@ __global__ __launch_bounds__(256) void k_gather_ell(const int* __restrict__ idx,
   out[rhs * n_nodes + k] = (R)s;
 }
 
+// Batched gather: item blockIdx.y of the batch (its mesh, its vector at
+// ubase + off); with use_mask the interior mask multiplies u first.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_gather_items(const CgItem* __restrict__ items,
+                                                      const double* __restrict__ ubase, int use_mask,
+                                                      long long n_nodes, R* __restrict__ out, Skip skip) {
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  const long long k0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * (256 * GATHER_NPT) + threadIdx.x;
+  int e[GATHER_NPT];
+#pragma unroll
+  for (int j = 0; j < GATHER_NPT; ++j) {
+    const long long k = k0 + j * 256;
+    if constexpr (D == 2)
+      e[j] = k < n_nodes ? I.elem[k] : -2;
+    else
+      e[j] = k < n_nodes ? I.ell_idx[k] : -2;
+  }
+  if (skip(it)) return;
+  const double* ur = ubase + I.off;
+  const double* mask = use_mask ? I.imask : nullptr;
+#pragma unroll
+  for (int j = 0; j < GATHER_NPT; ++j) {
+    const long long k = k0 + j * 256;
+    if (e[j] == -2) continue;
+    double s = 0.0;
+    if (e[j] >= 0) {
+      int vid[D + 1];
+      double lam[D + 1];
+      if constexpr (D == 2) {
+        node_weights<2>(I.g, static_cast<const ElemRec2*>(I.recs), e[j], k, vid, lam);
+      } else {
+        const int4 v = I.ell_v[e[j]];
+        const double2 w01 = I.ell_w[2 * (long long)e[j]], w23 = I.ell_w[2 * (long long)e[j] + 1];
+        vid[0] = v.x, vid[1] = v.y, vid[2] = v.z, vid[3] = v.w;
+        lam[0] = w01.x, lam[1] = w01.y, lam[2] = w23.x, lam[3] = w23.y;
+      }
+#pragma unroll
+      for (int r = 0; r <= D; ++r) {
+        double uv = ur[vid[r]];
+        if (mask) uv *= mask[vid[r]];
+        s += lam[r] * uv;
+      }
+    }
+    out[it * n_nodes + k] = (R)s;
+  }
+}
+
 // ---------------------------------------------------------------- spectra layout
 // Z holds, per rhs, the L/2 column slots of the W window rows after the row
 // transform, in tiles of four slots: Z[slot/4][row][slot%4].  A block of the
@@ -197,9 +246,9 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passA(Src src, cplx<R>* __res
 // partials of gamma and (r, r): dpart[rhs][q][block], q = gamma, (r, r), delta.
 template <typename R, int L, int E, int LB, bool DOT>
 __global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, int W, int half,
-                                                      const R* __restrict__ That, const cplx<R>* __restrict__ tw,
+                                                      const R* That, const cplx<R>* __restrict__ tw,
                                                       long long zs, Skip skip, double* __restrict__ dpart,
-                                                      gofd_cg::Level1 lv1) {
+                                                      gofd_cg::Level1 lv1, const void* const* __restrict__ that_tab) {
   constexpr int TPL = L / E;
   constexpr int PL = padded_len<L, E>();
   constexpr int H = L / 2;
@@ -221,6 +270,7 @@ __global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, i
   // line takes row min(k1, L - k1) of the stored (L/2+1)-row spectrum column
   // (for slot 0 this is column k0 = 0; column L/2 is read when it is used)
   R pm[E];
+  if (that_tab) That = static_cast<const R*>(that_tab[blockIdx.y]);     // per-item spectrum (batched solves)
   {
     const R* Tc = That + (long long)slot * half;
 #pragma unroll
@@ -386,7 +436,7 @@ struct Cfg {
 
 template <typename R, int L, class Src, typename Y>
 int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
-           double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin) {
+           double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab) {
   const int W = op->W, half = op->half;
   const long long zs = (long long)W * (L / 2);
   const cplx<R>* tw;
@@ -411,10 +461,10 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
                        src, Z, W, tw, zs, skip);
   if ((passes & 2) && dpart)
     GOFD_LAUNCH(ctx, (k_passB<R, L, C::EB, C::LB, true>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
-                       st, Z, W, half, That, tw, zs, skip, dpart, lv1);
+                       st, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab);
   else if (passes & 2)
     GOFD_LAUNCH(ctx, (k_passB<R, L, C::EB, C::LB, false>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
-                       st, Z, W, half, That, tw, zs, skip, dpart, lv1);
+                       st, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab);
   if (passes & 4)
     GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A>), dim3(nbA + (fin.sc ? 1 : 0), nrhs), dim3(C::LINES_A * C::TA), 0, st, Z,
                        W, tw, zs, y, (long long)W * W, skip, fin);
@@ -425,18 +475,18 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
 template <typename R, class Src, typename Y>
 int dispatch_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
                 double* dpart = nullptr, const gofd_cg::Level1& lv1 = gofd_cg::Level1(),
-                const gofd_cg::Finish& fin = gofd_cg::Finish()) {
+                const gofd_cg::Finish& fin = gofd_cg::Finish(), const void* const* that_tab = nullptr) {
   switch (op->L) {
-    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
     default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "FFT length " + std::to_string(op->L) + " not built");
   }
 }
@@ -541,54 +591,68 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   double* dpart = g ? g->dpart : nullptr;
   const gofd_cg::Level1 lv1 = g ? g->lv1 : gofd_cg::Level1();
   const gofd_cg::Finish fin = g ? g->fin : gofd_cg::Finish();
+  const void* const* that_tab = g ? (fp32 ? g->that32_tab : g->that64_tab) : nullptr;
   if (v) {
-    if (d == 3) return conv3_run(ctx, op, nrhs, v, nullptr, y, fp32, passes & 7, skip.flag, skip.stride, dpart, lv1, fin);
+    if (d == 3)
+      return conv3_run(ctx, op, nrhs, v, nullptr, y, fp32, passes & 7, skip.flag, skip.stride, dpart, lv1, fin,
+                       that_tab);
     SrcGrid<double> src{v, nn};
-    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin)
-                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin);
+    return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin,
+                                     that_tab)
+                : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin,
+                                      that_tab);
   }
-  const gofd_transfer_s* tr = g->tr;
-  GridGeom geom;
-  geom.d = d;
-  geom.W = tr->W;
-  geom.h = tr->h;
-  for (int a = 0; a < 3; ++a) geom.lo[a] = tr->lo[a];
   GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
   const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if (g->pregathered) passes &= ~8;
   hipStream_t st = ctx->stream;
-  if (passes & 8) {
+  if ((passes & 8) && g->items) {
+    // batched: every item gathers from its own mesh
+#define GOFD_GI(R, D) \
+  GOFD_LAUNCH(ctx, (k_gather_items<R, D>), gg, dim3(256), 0, st, g->items, g->ubase, g->items_mask ? 1 : 0, nn, op->G.as<R>(), skip)
+    if (d == 2) {
+      if (fp32) GOFD_GI(float, 2); else GOFD_GI(double, 2);
+    } else {
+      if (fp32) GOFD_GI(float, 3); else GOFD_GI(double, 3);
+    }
+#undef GOFD_GI
+    HIP_TRY(ctx, hipGetLastError());
+  } else if (passes & 8) {
+    const gofd_transfer_s* tr = g->tr;
+    GridGeom geom;
+    geom.d = d;
+    geom.W = tr->W;
+    geom.h = tr->h;
+    for (int a = 0; a < 3; ++a) geom.lo[a] = tr->lo[a];
     if (d == 2) {
       if (fp32)
         GOFD_LAUNCH(ctx, (k_gather<float, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
-                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
-                           skip);
+                    tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(), skip);
       else
         GOFD_LAUNCH(ctx, (k_gather<double, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
-                           tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
-                           op->G.as<double>(), skip);
+                    tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(), skip);
     } else {
       const dim3 ge(grid1(nn, 256), nrhs);
       if (fp32)
         GOFD_LAUNCH(ctx, (k_gather_ell<float>), ge, dim3(256), 0, st, tr->ell_idx.as<int>(), tr->ell_v.as<int4>(),
-                           tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
-                           op->G.as<float>(), skip);
+                    tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
+                    skip);
       else
         GOFD_LAUNCH(ctx, (k_gather_ell<double>), ge, dim3(256), 0, st, tr->ell_idx.as<int>(), tr->ell_v.as<int4>(),
-                           tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn,
-                           op->G.as<double>(), skip);
+                    tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(),
+                    skip);
     }
     HIP_TRY(ctx, hipGetLastError());
   }
   if (d == 3)
     return conv3_run(ctx, op, nrhs, fp32 ? nullptr : op->G.as<double>(), fp32 ? op->G.as<float>() : nullptr, y, fp32,
-                     passes & 7, skip.flag, skip.stride, dpart, lv1, fin);
+                     passes & 7, skip.flag, skip.stride, dpart, lv1, fin, that_tab);
   if (fp32) {
     SrcGrid<float> src{op->G.as<float>(), nn};
-    return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin);
+    return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab);
   }
   SrcGrid<double> src{op->G.as<double>(), nn};
-  return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin);
+  return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin, that_tab);
 }
 
 template <typename R>

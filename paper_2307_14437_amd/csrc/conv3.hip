@@ -137,9 +137,9 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3BD(cplx<R>* __restrict__ Z1, c
 // partials: dpart[rhs][q][block], q = gamma, (r, r), delta.
 template <typename R, int L, int E, int LB, bool DOT>
 __global__ __launch_bounds__(LB*(L / E)) void k_p3C(cplx<R>* __restrict__ Z2, int W, int half, int nsb,
-                                                     const R* __restrict__ That, const cplx<R>* __restrict__ tw,
+                                                     const R* That, const cplx<R>* __restrict__ tw,
                                                      long long z2s, Skip skip, double* __restrict__ dpart,
-                                                     gofd_cg::Level1 lv1) {
+                                                     gofd_cg::Level1 lv1, const void* const* __restrict__ that_tab) {
   constexpr int TPL = L / E;
   constexpr int PL = padded_len<L, E>();
   constexpr int H = L / 2;
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3C(cplx<R>* __restrict__ Z2, in
   cplx<R> v[E];
   R pm[E];
   const int kk1 = (k1 <= H) ? k1 : L - k1;
+  if (that_tab) That = static_cast<const R*>(that_tab[blockIdx.y]);     // per-item spectrum (batched solves)
   // That is half^3 with axis 0 fastest; by symmetry of the kernel the axes
   // may take k0, k1, k2 in any order: index (k2 half + k1) half + k0
   const R* Tc = That + (long long)kk1 * half + (act ? slot : 0);
@@ -272,7 +273,7 @@ struct Cfg3 {
 
 template <typename R, int L, class Src, typename Y>
 int run_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip, double* dpart,
-           const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin) {
+           const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab) {
   using C = Cfg3<R, L>;
   const int W = op->W, half = op->half;
   const long long z1s = (long long)C::NTILE * 4 * W * W;
@@ -303,10 +304,10 @@ int run_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
                        z1s, z2s, skip);
     if (dpart)
       hipLaunchKernelGGL((k_p3C<R, L, C::E, C::LB, true>), gC, dim3(C::LB * C::TPL), 0, st, Z2, W, half, C::NSB,
-                         That, tw, z2s, skip, dpart, lv1);
+                         That, tw, z2s, skip, dpart, lv1, that_tab);
     else
       hipLaunchKernelGGL((k_p3C<R, L, C::E, C::LB, false>), gC, dim3(C::LB * C::TPL), 0, st, Z2, W, half, C::NSB,
-                         That, tw, z2s, skip, dpart, lv1);
+                         That, tw, z2s, skip, dpart, lv1, that_tab);
     hipLaunchKernelGGL((k_p3BD<R, L, C::E, C::LB, true>), gBD, dim3(C::LB * C::TPL), 0, st, Z1, Z2, W, C::NSB, tw,
                        z1s, z2s, skip);
   }
@@ -319,16 +320,16 @@ int run_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
 
 template <typename R, class Src, typename Y>
 int dispatch_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
-                double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin) {
+                double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab) {
   switch (op->L) {
-    case 8: return run_3d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 16: return run_3d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 32: return run_3d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 64: return run_3d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 128: return run_3d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 256: return run_3d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 512: return run_3d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
-    case 1024: return run_3d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin);
+    case 8: return run_3d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 16: return run_3d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 32: return run_3d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 64: return run_3d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 128: return run_3d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 256: return run_3d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 512: return run_3d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 1024: return run_3d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
     default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "3D FFT length " + std::to_string(op->L) + " not built");
   }
 }
@@ -361,17 +362,17 @@ int conv3_passC_blocks(const gofd_fdop_s* op, bool fp32) {
 
 int conv3_run(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v64, const float* v32, void* y, bool fp32,
               int passes, const int* skip_flag, int skip_stride, double* dpart, const gofd_cg::Level1& lv1,
-              const gofd_cg::Finish& fin) {
+              const gofd_cg::Finish& fin, const void* const* that_tab) {
   const Skip skip{skip_flag, skip_stride};
   const long long nn = (long long)op->W * op->W * op->W;
   if (fp32) {
     if (v32) {
       SrcGrid<float> src{v32, nn};
-      return dispatch_3d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin);
+      return dispatch_3d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab);
     }
     SrcGrid<double> src{v64, nn};
-    return dispatch_3d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin);
+    return dispatch_3d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab);
   }
   SrcGrid<double> src{v64, nn};
-  return dispatch_3d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin);
+  return dispatch_3d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin, that_tab);
 }

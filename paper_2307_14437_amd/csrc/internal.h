@@ -4,6 +4,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include "cg_items.h"
 #include "cg_state.h"
 
 #include <cstdint>
@@ -177,6 +178,12 @@ struct GatherSpec {
   double* dpart = nullptr;             // optional: per-block partials (gamma, (r, r), (A v, v)) of the column pass
   gofd_cg::Level1 lv1;                 // level-1 partials of gamma and (r, r) the column pass sums up
   gofd_cg::Finish fin;                 // optional: CG reductions finished by the last pass
+  // batched mode: item blockIdx.y gathers from items[it] (its mesh) at ubase + off
+  const CgItem* items = nullptr;
+  const double* ubase = nullptr;
+  bool items_mask = false;             // multiply by the item's interior mask
+  const void* const* that64_tab = nullptr;   // per-item spectrum of the embedded kernel (device tables)
+  const void* const* that32_tab = nullptr;
 };
 
 // Apply A_FD with the FFT embedding: input either a grid field (v != nullptr,
@@ -198,7 +205,7 @@ int conv_passB_blocks(const gofd_fdop_s* op, bool fp32);
 // conv3_workspace(op) complex values per rhs.
 int conv3_run(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v64, const float* v32, void* y, bool fp32,
               int passes, const int* skip_flag, int skip_stride, double* dpart, const gofd_cg::Level1& lv1,
-              const gofd_cg::Finish& fin);
+              const gofd_cg::Finish& fin, const void* const* that_tab = nullptr);
 long long conv3_workspace(const gofd_fdop_s* op);
 int conv3_passC_blocks(const gofd_fdop_s* op, bool fp32);
 

@@ -109,15 +109,18 @@ __global__ void k_rhs_vertex(const double* __restrict__ f, const double* __restr
 // contiguous range of vertices, and leave one partial sum per block.
 
 // start from x = 0: r = b, u = M_diag b (or u given), p = s = 0; partials of
-// gamma = (r, u) and (r, r)
-__global__ __launch_bounds__(BS) void k_cg_start(const double* __restrict__ b, double* __restrict__ x,
-                                                 double* __restrict__ r, double* __restrict__ u,
-                                                 double* __restrict__ p, double* __restrict__ s,
-                                                 const double* __restrict__ dinv, long long nv, int ufilled,
-                                                 double* __restrict__ partG, double* __restrict__ partR) {
+// gamma = (r, u) and (r, r).  Item blockIdx.y, vectors at off.
+__global__ __launch_bounds__(BS) void k_cg_start(const CgItem* __restrict__ items, const double* __restrict__ b,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ u, double* __restrict__ p,
+                                                 double* __restrict__ s, double* __restrict__ partG,
+                                                 double* __restrict__ partR) {
   __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
-  const int rhs = blockIdx.y;
-  const long long o = rhs * nv;
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  const long long o = I.off, nv = I.nv;
+  const bool ufilled = I.dk < 0;              // IC(1): u = M^{-1} b was formed before
+  const double* dinv = I.dk == 1 ? I.dscale : nullptr;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
     const double bi = b[o + i];
@@ -132,8 +135,8 @@ __global__ __launch_bounds__(BS) void k_cg_start(const double* __restrict__ b, d
   }
   block_sum_n<BS, 2>(acc, sh);
   if (threadIdx.x == 0) {
-    partG[(long long)rhs * gridDim.x + blockIdx.x] = acc[0];
-    partR[(long long)rhs * gridDim.x + blockIdx.x] = acc[1];
+    partG[(long long)it * gridDim.x + blockIdx.x] = acc[0];
+    partR[(long long)it * gridDim.x + blockIdx.x] = acc[1];
   }
 }
 
@@ -164,30 +167,31 @@ __global__ __launch_bounds__(BS) void k_cg_init(const double* __restrict__ partG
 
 // Residual replacement (reliable updating): r = b - q with q = K x from a
 // double-precision product, u = M_diag r; partials of gamma and (r, r).
-__global__ __launch_bounds__(BS) void k_cg_replace(const double* __restrict__ b, const double* __restrict__ q,
-                                                   double* __restrict__ r, double* __restrict__ u,
-                                                   const double* __restrict__ dinv, int dk, long long nv,
-                                                   const Scal* __restrict__ sc, double* __restrict__ partG,
-                                                   double* __restrict__ partR) {
+__global__ __launch_bounds__(BS) void k_cg_replace(const CgItem* __restrict__ items, const double* __restrict__ b,
+                                                   const double* __restrict__ q, double* __restrict__ r,
+                                                   double* __restrict__ u, const Scal* __restrict__ sc,
+                                                   double* __restrict__ partG, double* __restrict__ partR) {
   __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
-  const int rhs = blockIdx.y;
-  if (sc[rhs].status != ST_OK) return;
-  const long long o = rhs * nv;
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  if (sc[it].status != ST_OK) return;
+  const long long o = I.off, nv = I.nv;
+  const int dk = I.dk;
   double acc[2] = {0.0, 0.0};
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
     const double ri = b[o + i] - q[o + i];
     r[o + i] = ri;
     acc[1] += ri * ri;
     if (dk >= 0) {
-      const double ui = dk ? ri * dinv[i] : ri;
+      const double ui = dk ? ri * I.dscale[i] : ri;
       u[o + i] = ui;
       acc[0] += ri * ui;
     }
   }
   block_sum_n<BS, 2>(acc, sh);
   if (threadIdx.x == 0) {
-    if (dk >= 0) partG[(long long)rhs * gridDim.x + blockIdx.x] = acc[0];
-    partR[(long long)rhs * gridDim.x + blockIdx.x] = acc[1];
+    if (dk >= 0) partG[(long long)it * gridDim.x + blockIdx.x] = acc[0];
+    partR[(long long)it * gridDim.x + blockIdx.x] = acc[1];
   }
 }
 
@@ -209,24 +213,32 @@ __global__ __launch_bounds__(BS) void k_cg_reopen(const double* __restrict__ par
 // w = mask * I^T y (the product K u, G lanes per vertex) and, in the same
 // pass, the step decided by the last FFT pass: s = w + beta s, p = u + beta p,
 // x += alpha p, r -= alpha s and, for a diagonal (or no) preconditioner,
-// u = M r; partials of the next (r, r) and gamma = (r, u).  Block b takes the
-// vertex groups [b*per, (b+1)*per) in XCD-contiguous order.
+// u = M r; partials of the next (r, r) and gamma = (r, u).  Item blockIdx.y;
+// block b takes the vertex groups [b*per, (b+1)*per) in XCD-contiguous order
+// (blocks past the item's vertices leave zero partials).
 template <typename Y, typename WT, int G>
-__global__ __launch_bounds__(BS) void k_scatter_cg(const int* __restrict__ off, const int* __restrict__ node,
-                                                   const WT* __restrict__ wts, const Y* __restrict__ y, long long nv,
-                                                   long long n_nodes, const double* __restrict__ mask,
-                                                   const Scal* __restrict__ sc, double* __restrict__ x,
-                                                   double* __restrict__ p, double* __restrict__ s,
-                                                   double* __restrict__ r, double* __restrict__ u,
-                                                   const double* __restrict__ dinv, int dk, int per,
-                                                   double* __restrict__ partG, double* __restrict__ partR) {
+__global__ __launch_bounds__(BS) void k_scatter_cg(const CgItem* __restrict__ items, const Y* __restrict__ y,
+                                                   long long n_nodes, const Scal* __restrict__ sc,
+                                                   double* __restrict__ x, double* __restrict__ p,
+                                                   double* __restrict__ s, double* __restrict__ r,
+                                                   double* __restrict__ u, int per, double* __restrict__ partG,
+                                                   double* __restrict__ partR) {
   constexpr int VPB = BS / G;                 // vertices per block pass
   __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
-  const int rhs = blockIdx.y;
-  const long long o = rhs * nv;
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  const long long o = I.off, nv = I.nv;
+  const int dk = I.dk;
+  const int* __restrict__ off = I.csc_off;
+  const int* __restrict__ node = I.csc_node;
+  const WT* __restrict__ wts;
+  if constexpr (sizeof(WT) == 4)
+    wts = reinterpret_cast<const WT*>(I.csc_w32);
+  else
+    wts = reinterpret_cast<const WT*>(I.csc_w);
   const int lane = threadIdx.x % G;
   const long long g0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * per;
-  const Y* yr = y + rhs * n_nodes;
+  const Y* yr = y + it * n_nodes;
   // first segment bounds before the finished-rhs test, so that the loads overlap
   const long long vf = g0 * VPB + threadIdx.x / G;
   int f0 = 0, f1 = 0;
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(BS) void k_scatter_cg(const int* __restrict__ off, 
     f0 = off[vf];
     f1 = off[vf + 1];
   }
-  const Scal& S = sc[rhs];
+  const Scal& S = sc[it];
   if (S.done) return;                         // block-uniform
   const double alpha = S.alpha, beta = S.beta;
   double acc2[2] = {0.0, 0.0};                // (r, r), (r, u)
@@ -246,13 +258,13 @@ __global__ __launch_bounds__(BS) void k_scatter_cg(const int* __restrict__ off, 
       const int i0 = q == 0 ? f0 : off[v], i1 = q == 0 ? f1 : off[v + 1];
       // the vertex's own vectors, fetched with the first entries
       if (lane == 0) {
-        vm = mask[v];
+        vm = I.imask[v];
         vs = s[o + v];
         vp = p[o + v];
         vu = u[o + v];
         vr = r[o + v];
         vx = x[o + v];
-        if (dk > 0) vd = dinv[v];
+        if (dk > 0) vd = I.dscale[v];
       }
       int nd[4];
       WT wt[4];
@@ -288,19 +300,20 @@ __global__ __launch_bounds__(BS) void k_scatter_cg(const int* __restrict__ off, 
   }
   block_sum_n<BS, 2>(acc2, sh);
   if (threadIdx.x == 0) {
-    partR[(long long)rhs * gridDim.x + blockIdx.x] = acc2[0];
-    if (dk >= 0) partG[(long long)rhs * gridDim.x + blockIdx.x] = acc2[1];
+    partR[(long long)it * gridDim.x + blockIdx.x] = acc2[0];
+    if (dk >= 0) partG[(long long)it * gridDim.x + blockIdx.x] = acc2[1];
   }
 }
 
 // r = b - q (q = K x), partials of (r, r) and (b, b); used by the refinement
-// loop (FP64 residual)
-__global__ __launch_bounds__(BS) void k_residual(const double* __restrict__ b, const double* __restrict__ q,
-                                                 double* __restrict__ r, long long nv,
+// loop (FP64 residual).  Item blockIdx.y.
+__global__ __launch_bounds__(BS) void k_residual(const CgItem* __restrict__ items, const double* __restrict__ b,
+                                                 const double* __restrict__ q, double* __restrict__ r,
                                                  double* __restrict__ partials) {
   __shared__ double sh[BS];
-  const int rhs = blockIdx.y;
-  const long long o = rhs * nv;
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  const long long o = I.off, nv = I.nv;
   double s_rr = 0.0, s_bb = 0.0;
   for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < nv; i += (long long)gridDim.x * BS) {
     const double ri = b[o + i] - q[o + i];
@@ -310,7 +323,7 @@ __global__ __launch_bounds__(BS) void k_residual(const double* __restrict__ b, c
   }
   s_rr = block_sum<BS>(s_rr, sh);
   s_bb = block_sum<BS>(s_bb, sh);
-  double* part = partials + (long long)rhs * 2 * NB_DOT;
+  double* part = partials + (long long)it * 2 * NB_DOT;
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s_rr;
     part[NB_DOT + blockIdx.x] = s_bb;
@@ -334,22 +347,21 @@ __global__ void k_axpy_mask(double* __restrict__ x, const double* __restrict__ d
   if (i < n) x[i] += d[i];
 }
 
-// plain scatter for K x (no dot), masked
+// plain scatter q = mask * I^T y (no dot), item blockIdx.y
 template <int G>
-__global__ __launch_bounds__(BS) void k_scatter_plain(const int* __restrict__ off, const int* __restrict__ node,
-                                                      const double* __restrict__ w, const double* __restrict__ y,
-                                                      long long nv, long long n_nodes, const double* __restrict__ mask,
-                                                      double* __restrict__ q) {
-  const long long v = ((long long)blockIdx.x * BS + threadIdx.x) / G;
+__global__ __launch_bounds__(BS) void k_scatter_plain(const CgItem* __restrict__ items, const double* __restrict__ y,
+                                                      long long n_nodes, double* __restrict__ q) {
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  const long long v = ((long long)xcd_remap(blockIdx.x, gridDim.x) * BS + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
-  const int rhs = blockIdx.y;
-  if (v >= nv) return;
-  const double* yr = y + rhs * n_nodes;
+  if (v >= I.nv) return;
+  const double* yr = y + it * n_nodes;
   double acc = 0.0;
-  for (int i = off[v] + lane; i < off[v + 1]; i += G) acc += w[i] * yr[node[i]];
+  for (int i = I.csc_off[v] + lane; i < I.csc_off[v + 1]; i += G) acc += I.csc_w[i] * yr[I.csc_node[i]];
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-  if (lane == 0) q[rhs * nv + v] = mask[v] * acc;
+  if (lane == 0) q[I.off + v] = I.imask[v] * acc;
 }
 
 // ---------------------------------------------------------------- triangular solves
@@ -589,65 +601,6 @@ struct Problem {
   int nrhs;
 };
 
-struct Work {
-  DevBuf x, r, u, p, s, b, xr, dvec, q, grid;
-  DevBuf scal;                  // Scal[nrhs]
-  DevBuf partG, partR;          // double[nrhs][nbs]: gamma and (r, r) partials
-  DevBuf partD;                 // double[nrhs][pass-B blocks]: delta partials
-  DevBuf partials, out2;        // residual partials, ||r||^2 and ||b||^2
-  int nrhs = 0;
-  int nbs = 1;                  // blocks of the CG vector kernels (scatter, start)
-  int per = 1;                  // vertex groups per scatter block
-};
-
-int reserve_work(gofd_ctx_s* ctx, Work& w, int64_t nv, int64_t n_nodes, int nrhs) {
-  const size_t vb = sizeof(double) * nv * nrhs;
-  for (DevBuf* b : {&w.x, &w.r, &w.u, &w.p, &w.s, &w.b, &w.xr, &w.dvec, &w.q}) GOFD_TRY(dev_reserve(ctx, *b, vb));
-  GOFD_TRY(dev_reserve(ctx, w.grid, sizeof(double) * n_nodes * nrhs));
-  GOFD_TRY(dev_reserve(ctx, w.scal, sizeof(Scal) * nrhs));
-  const long long groups = (nv + BS / SCAT_G - 1) / (BS / SCAT_G);
-  w.per = (int)std::max<long long>(1, (groups + MAX_SC - 1) / MAX_SC);
-  w.nbs = (int)std::max<long long>(1, (groups + w.per - 1) / w.per);
-  GOFD_TRY(dev_reserve(ctx, w.partG, sizeof(double) * w.nbs * nrhs));
-  GOFD_TRY(dev_reserve(ctx, w.partR, sizeof(double) * w.nbs * nrhs));
-  GOFD_TRY(dev_reserve(ctx, w.partials, sizeof(double) * 2 * NB_DOT * nrhs));
-  GOFD_TRY(dev_reserve(ctx, w.out2, sizeof(double) * 2 * nrhs));
-  w.nrhs = nrhs;
-  return GOFD_OK;
-}
-
-// q = K v in double precision (masked), for true residuals
-int apply_K_plain(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* v, double* q) {
-  gofd_transfer_s* tr = P.tr;
-  GatherSpec g;
-  g.tr = tr;
-  g.u = v;
-  g.mask = tr->imask.as<double>();
-  GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, false));
-  dim3 gs(grid1(tr->nv * SCAT_G, BS), P.nrhs);
-  hipLaunchKernelGGL((k_scatter_plain<SCAT_G>), gs, dim3(BS), 0, ctx->stream, tr->csc_off.as<int>(),
-                     tr->csc_node.as<int>(), tr->csc_w.as<double>(), w.grid.as<double>(), (long long)tr->nv,
-                     (long long)tr->n_nodes, tr->imask.as<double>(), q);
-  HIP_TRY(ctx, hipGetLastError());
-  return GOFD_OK;
-}
-
-// u = M^{-1} r with the IC(1) factor; the upper solve also writes the
-// partials of gamma = (r, u) into partG (if given)
-int precond_apply(gofd_ctx_s* ctx, const Problem& P, Work& w, const Scal* sc, double* partG) {
-  gofd_precond_s* pc = P.pc;
-  hipStream_t st = ctx->stream;
-  const long long n = P.tr->nv;
-  hipLaunchKernelGGL((k_trsv_levels<true>), dim3(P.nrhs), dim3(1024), 0, st, pc->Lptr.as<int>(), pc->Lcol.as<int>(),
-                     pc->Lval.as<double>(), pc->Llev_ptr.as<int>(), pc->Llev_rows.as<int>(), pc->Lnlev,
-                     w.r.as<double>(), w.dvec.as<double>(), n, sc, nullptr, nullptr, w.nbs);
-  hipLaunchKernelGGL((k_trsv_levels<false>), dim3(P.nrhs), dim3(1024), 0, st, pc->Uptr.as<int>(), pc->Ucol.as<int>(),
-                     pc->Uval.as<double>(), pc->Ulev_ptr.as<int>(), pc->Ulev_rows.as<int>(), pc->Unlev,
-                     w.dvec.as<double>(), w.u.as<double>(), n, sc, w.r.as<double>(), partG, w.nbs);
-  HIP_TRY(ctx, hipGetLastError());
-  return GOFD_OK;
-}
-
 bool is_ic(const gofd_precond_s* pc) {
   return pc && (pc->kind == GOFD_PC_IC1_5 || pc->kind == GOFD_PC_IC1_9 || pc->kind == GOFD_PC_IC1_27);
 }
@@ -655,6 +608,151 @@ bool is_ic(const gofd_precond_s* pc) {
 // 1: diagonal (D_h), 0: none, -1: IC(1) factor
 int diag_kind_of(const gofd_precond_s* pc) {
   return is_ic(pc) ? -1 : ((pc && pc->kind == GOFD_PC_DIAG) ? 1 : 0);
+}
+
+// A batch: problems of one grid shape (d, W, L), solved together.  Items are
+// (problem, rhs) pairs in problem order; the vectors of all items are laid
+// end to end (item i at off[i], N_v of its mesh entries each).
+struct Batch {
+  std::vector<Problem> probs;
+  std::vector<long long> poff;     // offset of problem q's first vector
+  std::vector<int> pitem;          // first item of problem q
+  std::vector<long long> ioff;     // offset of item i
+  std::vector<long long> inv;      // N_v of item i
+  int nitems = 0;
+  long long ntot = 0, nv_max = 0;
+  bool any_ic = false;
+  gofd_fdop_s* op0 = nullptr;      // shape and FFT workspaces of the batch
+  DevBuf items, tab64, tab32;      // CgItem[nitems]; spectrum pointer tables
+};
+
+int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
+  B.probs = probs;
+  B.op0 = probs[0].op;
+  std::vector<CgItem> h;
+  std::vector<const void*> t64, t32;
+  long long off = 0;
+  for (const Problem& P : probs) {
+    gofd_transfer_s* tr = P.tr;
+    if (P.op->d != B.op0->d || P.op->W != B.op0->W || P.op->L != B.op0->L)
+      return gofd_fail(ctx, GOFD_E_ARG, "internal: batch with different grid shapes");
+    B.poff.push_back(off);
+    B.pitem.push_back((int)h.size());
+    B.any_ic = B.any_ic || is_ic(P.pc);
+    B.nv_max = std::max<long long>(B.nv_max, tr->nv);
+    for (int k = 0; k < P.nrhs; ++k) {
+      CgItem I{};
+      I.csc_off = tr->csc_off.as<int>();
+      I.csc_node = tr->csc_node.as<int>();
+      I.csc_w = tr->csc_w.as<double>();
+      I.csc_w32 = tr->csc_w32.as<float>();
+      I.imask = tr->imask.as<double>();
+      I.dscale = tr->dscale.as<double>();
+      I.recs = tr->rec.p;
+      I.elem = tr->elem.as<int>();
+      I.ell_idx = tr->ell_idx.as<int>();
+      I.ell_v = tr->ell_v.as<int4>();
+      I.ell_w = tr->ell_w.as<double2>();
+      I.g.d = tr->d;
+      I.g.W = tr->W;
+      I.g.h = tr->h;
+      for (int a = 0; a < 3; ++a) I.g.lo[a] = tr->lo[a];
+      I.nv = tr->nv;
+      I.off = off;
+      I.dk = diag_kind_of(P.pc);
+      h.push_back(I);
+      t64.push_back(P.op->That64.p);
+      t32.push_back(P.op->That32.p);
+      B.ioff.push_back(off);
+      B.inv.push_back(tr->nv);
+      off += tr->nv;
+    }
+  }
+  B.nitems = (int)h.size();
+  B.ntot = off;
+  GOFD_TRY(dev_reserve(ctx, B.items, sizeof(CgItem) * h.size()));
+  GOFD_TRY(dev_reserve(ctx, B.tab64, sizeof(void*) * h.size()));
+  GOFD_TRY(dev_reserve(ctx, B.tab32, sizeof(void*) * h.size()));
+  hipStream_t st = ctx->stream;
+  HIP_TRY(ctx, hipMemcpyAsync(B.items.p, h.data(), sizeof(CgItem) * h.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(B.tab64.p, t64.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(B.tab32.p, t32.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));      // the host arrays go out of scope
+  return GOFD_OK;
+}
+
+struct Work {
+  DevBuf x, r, u, p, s, b, xr, dvec, q, grid;
+  DevBuf scal;                  // Scal[nitems]
+  DevBuf partG, partR;          // double[nitems][nbs]: gamma and (r, r) partials
+  DevBuf partD;                 // double[nitems][3][pass-B blocks]: partials summed by the column pass
+  DevBuf partials, out2;        // residual partials, ||r||^2 and ||b||^2
+  int nbs = 1;                  // blocks of the CG vector kernels (scatter, start) per item
+  int per = 1;                  // vertex groups per scatter block
+};
+
+int reserve_work(gofd_ctx_s* ctx, Work& w, const Batch& B) {
+  const size_t vb = sizeof(double) * std::max<long long>(B.ntot, 1);
+  for (DevBuf* b : {&w.x, &w.r, &w.u, &w.p, &w.s, &w.b, &w.xr, &w.dvec, &w.q}) GOFD_TRY(dev_reserve(ctx, *b, vb));
+  long long nn = 1;
+  for (int a = 0; a < B.op0->d; ++a) nn *= B.op0->W;
+  const int ni = B.nitems;
+  GOFD_TRY(dev_reserve(ctx, w.grid, sizeof(double) * nn * ni));
+  GOFD_TRY(dev_reserve(ctx, w.scal, sizeof(Scal) * ni));
+  const long long groups = (B.nv_max + BS / SCAT_G - 1) / (BS / SCAT_G);
+  w.per = (int)std::max<long long>(1, (groups + MAX_SC - 1) / MAX_SC);
+  w.nbs = (int)std::max<long long>(1, (groups + w.per - 1) / w.per);
+  GOFD_TRY(dev_reserve(ctx, w.partG, sizeof(double) * w.nbs * ni));
+  GOFD_TRY(dev_reserve(ctx, w.partR, sizeof(double) * w.nbs * ni));
+  GOFD_TRY(dev_reserve(ctx, w.partials, sizeof(double) * 2 * NB_DOT * ni));
+  GOFD_TRY(dev_reserve(ctx, w.out2, sizeof(double) * 2 * ni));
+  return GOFD_OK;
+}
+
+long long grid_nodes(const gofd_fdop_s* op) {
+  long long nn = 1;
+  for (int a = 0; a < op->d; ++a) nn *= op->W;
+  return nn;
+}
+
+// q = K v for every item in double precision (masked), for true residuals;
+// v and q are batch vectors
+int apply_K_plain(gofd_ctx_s* ctx, const Batch& B, Work& w, const double* v, double* q) {
+  GatherSpec g;
+  g.items = B.items.as<CgItem>();
+  g.ubase = v;
+  g.items_mask = true;
+  g.that64_tab = static_cast<const void* const*>(B.tab64.p);
+  g.that32_tab = static_cast<const void* const*>(B.tab32.p);
+  GOFD_TRY(conv_apply(ctx, B.op0, B.nitems, nullptr, &g, w.grid.p, false));
+  dim3 gs(grid1(B.nv_max * SCAT_G, BS), B.nitems);
+  hipLaunchKernelGGL((k_scatter_plain<SCAT_G>), gs, dim3(BS), 0, ctx->stream, B.items.as<CgItem>(),
+                     w.grid.as<double>(), grid_nodes(B.op0), q);
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
+}
+
+// u = M^{-1} r with the IC(1) factor of every IC problem; the upper solve also
+// writes the partials of gamma = (r, u) into partG (if given)
+int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, double* partG) {
+  hipStream_t st = ctx->stream;
+  for (size_t q = 0; q < B.probs.size(); ++q) {
+    const Problem& P = B.probs[q];
+    if (!is_ic(P.pc)) continue;
+    gofd_precond_s* pc = P.pc;
+    const long long n = P.tr->nv, o = B.poff[q];
+    const int i0 = B.pitem[q];
+    const Scal* scq = sc ? sc + i0 : nullptr;
+    hipLaunchKernelGGL((k_trsv_levels<true>), dim3(P.nrhs), dim3(1024), 0, st, pc->Lptr.as<int>(),
+                       pc->Lcol.as<int>(), pc->Lval.as<double>(), pc->Llev_ptr.as<int>(), pc->Llev_rows.as<int>(),
+                       pc->Lnlev, w.r.as<double>() + o, w.dvec.as<double>() + o, n, scq, nullptr, nullptr, w.nbs);
+    hipLaunchKernelGGL((k_trsv_levels<false>), dim3(P.nrhs), dim3(1024), 0, st, pc->Uptr.as<int>(),
+                       pc->Ucol.as<int>(), pc->Uval.as<double>(), pc->Ulev_ptr.as<int>(), pc->Ulev_rows.as<int>(),
+                       pc->Unlev, w.dvec.as<double>() + o, w.u.as<double>() + o, n, scq, w.r.as<double>() + o,
+                       partG ? partG + (long long)i0 * w.nbs : nullptr, w.nbs);
+  }
+  HIP_TRY(ctx, hipGetLastError());
+  return GOFD_OK;
 }
 
 // Per-stage timing of the iterations (no graph): every stage's kernel is
@@ -680,18 +778,18 @@ struct StageProf {
   }
 };
 
-// One CG iteration: product w = K u (gather, FFT passes with the delta
-// partials and the step decision, scatter with the vector update), then for
-// IC(1) the triangular solves u = M^{-1} r with the next gamma.
-int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32, StageProf* prof = nullptr) {
-  gofd_transfer_s* tr = P.tr;
-  const int dk = diag_kind_of(P.pc);
-  const long long nn = tr->n_nodes, nv = tr->nv;
+// One CG iteration of the whole batch: product w = K u (gather, FFT passes
+// with the delta partials and the step decision, scatter with the vector
+// update), then for IC(1) problems the triangular solves u = M^{-1} r with
+// the next gamma.
+int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf* prof = nullptr) {
   hipStream_t st = ctx->stream;
   GatherSpec g;
-  g.tr = tr;
-  g.u = w.u.as<double>();
-  g.mask = nullptr;                 // CG keeps every Dirichlet entry of u at zero
+  g.items = B.items.as<CgItem>();
+  g.ubase = w.u.as<double>();
+  g.items_mask = false;             // CG keeps every Dirichlet entry of u at zero
+  g.that64_tab = static_cast<const void* const*>(B.tab64.p);
+  g.that32_tab = static_cast<const void* const*>(B.tab32.p);
   g.skip = &w.scal.as<Scal>()->done;
   g.skip_stride = (int)(sizeof(Scal) / sizeof(int));
   g.dpart = w.partD.as<double>();
@@ -700,7 +798,7 @@ int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32, StagePro
   g.lv1.n1 = w.nbs;
   g.fin.sc = w.scal.as<Scal>();
   g.fin.part = w.partD.as<double>();
-  g.fin.nb = conv_passB_blocks(P.op, fp32);
+  g.fin.nb = conv_passB_blocks(B.op0, fp32);
   if (prof) {
     // the same launches one stage at a time, each kernel recording its own
     // start and end events
@@ -708,37 +806,36 @@ int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32, StagePro
     for (int k = 0; k < 4; ++k) {
       ctx->timer_start = prof->ev[2 * k];
       ctx->timer_stop = prof->ev[2 * k + 1];
-      GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32, stage_passes[k]));
+      GOFD_TRY(conv_apply(ctx, B.op0, B.nitems, nullptr, &g, w.grid.p, fp32, stage_passes[k]));
       ctx->timer_start = ctx->timer_stop = nullptr;
     }
     ctx->timer_start = prof->ev[8];
     ctx->timer_stop = prof->ev[9];
   } else {
-    GOFD_TRY(conv_apply(ctx, P.op, P.nrhs, nullptr, &g, w.grid.p, fp32));
+    GOFD_TRY(conv_apply(ctx, B.op0, B.nitems, nullptr, &g, w.grid.p, fp32));
   }
-  const dim3 gs(w.nbs, P.nrhs);
-#define GOFD_SCATTER_ARGS(WTS, Y)                                                                                \
-  tr->csc_off.as<int>(), tr->csc_node.as<int>(), WTS, Y, nv, nn, tr->imask.as<double>(), w.scal.as<Scal>(),     \
-      w.x.as<double>(), w.p.as<double>(), w.s.as<double>(), w.r.as<double>(), w.u.as<double>(),                  \
-      tr->dscale.as<double>(), dk, w.per, w.partG.as<double>(), w.partR.as<double>()
+  const dim3 gs(w.nbs, B.nitems);
+  const long long nn = grid_nodes(B.op0);
+#define GOFD_SCATTER_ARGS(Y)                                                                                     \
+  B.items.as<CgItem>(), Y, nn, w.scal.as<Scal>(), w.x.as<double>(), w.p.as<double>(), w.s.as<double>(),          \
+      w.r.as<double>(), w.u.as<double>(), w.per, w.partG.as<double>(), w.partR.as<double>()
   if (fp32)
-    GOFD_LAUNCH(ctx, (k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st,
-                GOFD_SCATTER_ARGS(tr->csc_w32.as<float>(), w.grid.as<float>()));
+    GOFD_LAUNCH(ctx, (k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st, GOFD_SCATTER_ARGS(w.grid.as<float>()));
   else
     GOFD_LAUNCH(ctx, (k_scatter_cg<double, double, SCAT_G>), gs, dim3(BS), 0, st,
-                GOFD_SCATTER_ARGS(tr->csc_w.as<double>(), w.grid.as<double>()));
+                GOFD_SCATTER_ARGS(w.grid.as<double>()));
 #undef GOFD_SCATTER_ARGS
   HIP_TRY(ctx, hipGetLastError());
   if (prof) {
     ctx->timer_start = ctx->timer_stop = nullptr;
-    if (dk < 0) HIP_TRY(ctx, hipEventRecord(prof->ev[10], st));
+    if (B.any_ic) HIP_TRY(ctx, hipEventRecord(prof->ev[10], st));
   }
-  if (dk < 0) GOFD_TRY(precond_apply(ctx, P, w, w.scal.as<Scal>(), w.partG.as<double>()));
+  if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
   if (prof) {
-    if (dk < 0) HIP_TRY(ctx, hipEventRecord(prof->ev[11], st));
+    if (B.any_ic) HIP_TRY(ctx, hipEventRecord(prof->ev[11], st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     for (int k = 0; k < GOFD_N_STAGES; ++k) {
-      if (k == GOFD_ST_PRECOND && dk >= 0) continue;
+      if (k == GOFD_ST_PRECOND && !B.any_ic) continue;
       float ms = 0.f;
       HIP_TRY(ctx, hipEventElapsedTime(&ms, prof->ev[2 * k], prof->ev[2 * k + 1]));
       prof->sum[k] += ms;
@@ -748,35 +845,34 @@ int cg_iteration(gofd_ctx_s* ctx, const Problem& P, Work& w, bool fp32, StagePro
   return GOFD_OK;
 }
 
-// CG from x = 0 on right-hand sides w.b; result in w.x.  Returns per-rhs
-// iterations and status through hs (host Scal copies).
+// CG from x = 0 on the batch right-hand sides w.b; result in w.x.  Returns
+// per-item iterations and status through hs (host Scal copies).
+//
 // With replace_drop > 0 the recursively updated residual is replaced by the
 // true one, r = b - K x with a double-precision product, whenever (r, r) has
-// dropped by replace_drop^2 since the last replacement and whenever a rhs
+// dropped by replace_drop^2 since the last replacement and whenever an item
 // stops on its recursive residual (reliable updating); the count goes to
 // *n_replace.
-int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, int max_iter, int check_every,
+int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int max_iter, int check_every,
             bool use_graph, std::vector<Scal>& hs, double* history, double replace_drop = 0.0,
             int* n_replace = nullptr, StageProf* prof = nullptr) {
   hipStream_t st = ctx->stream;
-  const long long nv = P.tr->nv;
-  const int dk = diag_kind_of(P.pc);
+  const int ni = B.nitems;
   if (n_replace) *n_replace = 0;
-  GOFD_TRY(conv_prepare(ctx, P.op, P.nrhs));
-  GOFD_TRY(dev_reserve(ctx, w.partD, sizeof(double) * 3 * conv_passB_blocks(P.op, fp32) * P.nrhs));
-  if (dk < 0) {
+  GOFD_TRY(conv_prepare(ctx, B.op0, ni));
+  GOFD_TRY(dev_reserve(ctx, w.partD, sizeof(double) * 3 * conv_passB_blocks(B.op0, fp32) * ni));
+  if (B.any_ic) {
     // u = M^{-1} b before the start kernel (no state is read: pass none)
-    HIP_TRY(ctx, hipMemcpyAsync(w.r.p, w.b.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
-    GOFD_TRY(precond_apply(ctx, P, w, nullptr, nullptr));
+    HIP_TRY(ctx, hipMemcpyAsync(w.r.p, w.b.p, sizeof(double) * B.ntot, hipMemcpyDeviceToDevice, st));
+    GOFD_TRY(precond_apply(ctx, B, w, nullptr, nullptr));
   }
-  hipLaunchKernelGGL(k_cg_start, dim3(w.nbs, P.nrhs), dim3(BS), 0, st, w.b.as<double>(), w.x.as<double>(),
-                     w.r.as<double>(), w.u.as<double>(), w.p.as<double>(), w.s.as<double>(),
-                     dk == 1 ? P.tr->dscale.as<double>() : nullptr, nv, dk < 0 ? 1 : 0, w.partG.as<double>(),
-                     w.partR.as<double>());
-  hipLaunchKernelGGL(k_cg_init, dim3(P.nrhs), dim3(BS), 0, st, w.partG.as<double>(), w.partR.as<double>(), w.nbs,
+  hipLaunchKernelGGL(k_cg_start, dim3(w.nbs, ni), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
+                     w.x.as<double>(), w.r.as<double>(), w.u.as<double>(), w.p.as<double>(), w.s.as<double>(),
+                     w.partG.as<double>(), w.partR.as<double>());
+  hipLaunchKernelGGL(k_cg_init, dim3(ni), dim3(BS), 0, st, w.partG.as<double>(), w.partR.as<double>(), w.nbs,
                      w.scal.as<Scal>(), tol);
   HIP_TRY(ctx, hipGetLastError());
-  hs.resize(P.nrhs);
+  hs.resize(ni);
   check_every = std::max(1, check_every);
   if (prof) {
     use_graph = false;                // stages timed one by one, state read every iteration
@@ -790,7 +886,7 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
       use_graph = false;
     } else {
       int rc = GOFD_OK;
-      for (int j = 0; j < check_every && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, P, w, fp32);
+      for (int j = 0; j < check_every && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, B, w, fp32);
       hipError_t e = hipStreamEndCapture(st, &graph);
       if (rc != GOFD_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -807,31 +903,30 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
   }
   // residual replacement: true residual of x in double precision, then the
   // state's flags from it (reads the state back into tmp)
-  std::vector<double> rr_ref(P.nrhs, 0.0);
-  for (auto& v : rr_ref) v = HUGE_VAL;
+  std::vector<double> rr_ref(ni, HUGE_VAL);
   auto replace_residual = [&](std::vector<Scal>& tmp) -> int {
-    GOFD_TRY(apply_K_plain(ctx, P, w, w.x.as<double>(), w.q.as<double>()));
-    hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, P.nrhs), dim3(BS), 0, st, w.b.as<double>(), w.q.as<double>(),
-                       w.r.as<double>(), w.u.as<double>(), P.tr->dscale.as<double>(), dk, nv, w.scal.as<Scal>(),
-                       w.partG.as<double>(), w.partR.as<double>());
-    hipLaunchKernelGGL(k_cg_reopen, dim3(P.nrhs), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>());
+    GOFD_TRY(apply_K_plain(ctx, B, w, w.x.as<double>(), w.q.as<double>()));
+    hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, ni), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
+                       w.q.as<double>(), w.r.as<double>(), w.u.as<double>(), w.scal.as<Scal>(), w.partG.as<double>(),
+                       w.partR.as<double>());
+    hipLaunchKernelGGL(k_cg_reopen, dim3(ni), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>());
     HIP_TRY(ctx, hipGetLastError());
-    if (dk < 0) GOFD_TRY(precond_apply(ctx, P, w, w.scal.as<Scal>(), w.partG.as<double>()));
-    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+    if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
+    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
-    for (int k = 0; k < P.nrhs; ++k) rr_ref[k] = tmp[k].rr;
+    for (int k = 0; k < ni; ++k) rr_ref[k] = tmp[k].rr;
     return GOFD_OK;
   };
   // Iteration j tests x_j (its last pass) and then applies step j, so after
   // `it` iterations `it` steps are applied unless the solve stopped earlier.
   int it = 0;
   int rc = GOFD_OK;
-  std::vector<Scal> tmp(P.nrhs);
+  std::vector<Scal> tmp(ni);
   if (history) history[0] = 1.0;
   if (replace_drop > 0.0) {
-    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
-    for (int k = 0; k < P.nrhs; ++k) rr_ref[k] = tmp[k].rr;
+    for (int k = 0; k < ni; ++k) rr_ref[k] = tmp[k].rr;
   }
   while (it < max_iter) {
     const int chunk = history ? 1 : check_every;
@@ -841,11 +936,11 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
         break;
       }
     } else {
-      for (int j = 0; j < chunk && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, P, w, fp32, prof);
+      for (int j = 0; j < chunk && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, B, w, fp32, prof);
       if (rc != GOFD_OK) break;
     }
     it += chunk;
-    if (hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+    if (hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       rc = gofd_fail(ctx, GOFD_E_HIP, "reading solver state failed");
       break;
@@ -854,7 +949,7 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
     if (history && it - 1 <= max_iter) history[it - 1] = tmp[0].bb > 0 ? std::sqrt(tmp[0].rr / tmp[0].bb) : 0.0;
     if (replace_drop > 0.0) {
       bool need = false;
-      for (int k = 0; k < P.nrhs; ++k)
+      for (int k = 0; k < ni; ++k)
         if (tmp[k].status == ST_OK && (tmp[k].done || tmp[k].rr < replace_drop * replace_drop * rr_ref[k])) need = true;
       if (need) {
         if ((rc = replace_residual(tmp)) != GOFD_OK) break;
@@ -862,39 +957,42 @@ int pcg_run(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, bool fp32, i
       }
     }
     bool all = true;
-    for (int k = 0; k < P.nrhs; ++k) all = all && tmp[k].done;
+    for (int k = 0; k < ni; ++k) all = all && tmp[k].done;
     if (all) break;
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (rc != GOFD_OK) return rc;
-  HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * P.nrhs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
   return GOFD_OK;
 }
 
-// true residual r = b - K x in double precision; returns ||r||^2 and ||b||^2 per rhs
-int true_residual(gofd_ctx_s* ctx, const Problem& P, Work& w, const double* x, const double* b, double* r,
+// true residual r = b - K x in double precision (batch vectors); returns
+// ||r||^2 and ||b||^2 per item
+int true_residual(gofd_ctx_s* ctx, const Batch& B, Work& w, const double* x, const double* b, double* r,
                   std::vector<double>& rr, std::vector<double>& bb) {
-  GOFD_TRY(conv_prepare(ctx, P.op, P.nrhs));
-  GOFD_TRY(apply_K_plain(ctx, P, w, x, w.q.as<double>()));
-  dim3 gd(NB_DOT, P.nrhs);
-  hipLaunchKernelGGL(k_residual, gd, dim3(BS), 0, ctx->stream, b, w.q.as<double>(), r, (long long)P.tr->nv,
+  const int ni = B.nitems;
+  GOFD_TRY(conv_prepare(ctx, B.op0, ni));
+  GOFD_TRY(apply_K_plain(ctx, B, w, x, w.q.as<double>()));
+  dim3 gd(NB_DOT, ni);
+  hipLaunchKernelGGL(k_residual, gd, dim3(BS), 0, ctx->stream, B.items.as<CgItem>(), b, w.q.as<double>(), r,
                      w.partials.as<double>());
-  hipLaunchKernelGGL(k_residual_finish, dim3(P.nrhs), dim3(BS), 0, ctx->stream, w.partials.as<double>(),
+  hipLaunchKernelGGL(k_residual_finish, dim3(ni), dim3(BS), 0, ctx->stream, w.partials.as<double>(),
                      w.out2.as<double>());
-  std::vector<double> h(2 * P.nrhs);
-  HIP_TRY(ctx, hipMemcpyAsync(h.data(), w.out2.p, sizeof(double) * 2 * P.nrhs, hipMemcpyDeviceToHost, ctx->stream));
+  std::vector<double> h(2 * ni);
+  HIP_TRY(ctx, hipMemcpyAsync(h.data(), w.out2.p, sizeof(double) * 2 * ni, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  rr.resize(P.nrhs);
-  bb.resize(P.nrhs);
-  for (int k = 0; k < P.nrhs; ++k) {
+  rr.resize(ni);
+  bb.resize(ni);
+  for (int k = 0; k < ni; ++k) {
     rr[k] = h[2 * k];
     bb[k] = h[2 * k + 1];
   }
   return GOFD_OK;
 }
 
+// right-hand sides of problem q into the batch vector b
 int form_rhs(gofd_ctx_s* ctx, const Problem& P, const double* f, int f_loc, double* b) {
   gofd_transfer_s* tr = P.tr;
   hipStream_t st = ctx->stream;
@@ -916,9 +1014,10 @@ int form_rhs(gofd_ctx_s* ctx, const Problem& P, const double* f, int f_loc, doub
 
 }  // namespace
 
-// Solve K u = b for nrhs right-hand sides already formed in w.b; u -> u_out.
-static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, const gofd_solve_opts* o,
-                        double* u_out, gofd_solve_info* info) {
+// Solve K u = b for the batch right-hand sides already formed in w.b; the
+// solution of problem q goes to u_out[q] (nrhs_q * N_v doubles).
+static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, const gofd_solve_opts* o,
+                        double* const* u_out, gofd_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
   const int mode = o ? o->mode : GOFD_MODE_FP64;
   const int max_iter = (o && o->max_iter > 0) ? o->max_iter : 20000;
@@ -928,28 +1027,27 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
   StageProf profobj(o && o->stage_ms);
   StageProf* prof = (o && o->stage_ms) ? &profobj : nullptr;
   if (prof && !prof->ok) return gofd_fail(ctx, GOFD_E_HIP, "event creation failed");
-  const long long nv = P.tr->nv;
+  const int ni = B.nitems;
+  const long long ntot = B.ntot;
   hipStream_t st = ctx->stream;
   std::vector<Scal> hs;
-  std::vector<int> iters(P.nrhs, 0), refs(P.nrhs, 0), status(P.nrhs, GOFD_OK);
-  std::vector<double> rel(P.nrhs, 0.0);
+  std::vector<int> iters(ni, 0), refs(ni, 0), status(ni, GOFD_OK);
+  std::vector<double> rel(ni, 0.0);
+  auto copy_out = [&](const double* src) -> int {
+    for (size_t q = 0; q < B.probs.size(); ++q)
+      HIP_TRY(ctx, hipMemcpyAsync(u_out[q], src + B.poff[q],
+                                  sizeof(double) * B.probs[q].tr->nv * B.probs[q].nrhs, hipMemcpyDeviceToDevice, st));
+    return GOFD_OK;
+  };
   int rc = GOFD_OK;
-  if (mode == GOFD_MODE_FP64) {
-    rc = pcg_run(ctx, P, w, tol, false, max_iter, check, graph, hs, history, 0.0, nullptr, prof);
-    if (rc != GOFD_OK) return rc;
-    HIP_TRY(ctx, hipMemcpyAsync(u_out, w.x.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
-    for (int k = 0; k < P.nrhs; ++k) {
-      iters[k] = hs[k].iters;
-      if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
-      else if (!hs[k].done) status[k] = GOFD_E_NOT_CONVERGED;
-    }
-  } else if (mode == GOFD_MODE_FP32_RELIABLE) {
-    const double drop = (o && o->inner_tol > 0) ? o->inner_tol : 1e-2;
+  if (mode == GOFD_MODE_FP64 || mode == GOFD_MODE_FP32_RELIABLE) {
+    const bool rel32 = mode == GOFD_MODE_FP32_RELIABLE;
+    const double drop = rel32 ? ((o && o->inner_tol > 0) ? o->inner_tol : 1e-2) : 0.0;
     int nrep = 0;
-    rc = pcg_run(ctx, P, w, tol, true, max_iter, check, graph, hs, history, drop, &nrep, prof);
+    rc = pcg_run(ctx, B, w, tol, rel32, max_iter, check, graph, hs, history, drop, &nrep, prof);
     if (rc != GOFD_OK) return rc;
-    HIP_TRY(ctx, hipMemcpyAsync(u_out, w.x.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
-    for (int k = 0; k < P.nrhs; ++k) {
+    GOFD_TRY(copy_out(w.x.as<double>()));
+    for (int k = 0; k < ni; ++k) {
       iters[k] = hs[k].iters;
       refs[k] = nrep;
       if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
@@ -960,28 +1058,27 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
     const int max_ref = (o && o->max_refine > 0) ? o->max_refine : 30;
     // xr = 0; r = b; loop
     DevBuf bsave;
-    GOFD_TRY(dev_reserve(ctx, bsave, sizeof(double) * nv * P.nrhs));
-    HIP_TRY(ctx, hipMemcpyAsync(bsave.p, w.b.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_fill_d, dim3(grid1(nv * P.nrhs, 256)), dim3(256), 0, st, w.xr.as<double>(),
-                       (long long)(nv * P.nrhs), 0.0);
+    GOFD_TRY(dev_reserve(ctx, bsave, sizeof(double) * ntot));
+    HIP_TRY(ctx, hipMemcpyAsync(bsave.p, w.b.p, sizeof(double) * ntot, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_fill_d, dim3(grid1(ntot, 256)), dim3(256), 0, st, w.xr.as<double>(), ntot, 0.0);
     std::vector<double> rr, bb;
-    std::vector<char> conv(P.nrhs, 0);
+    std::vector<char> conv(ni, 0);
     int total_it = 0;
     for (int ref = 0; ref <= max_ref; ++ref) {
       // true residual of the current iterate (b - K xr); first pass has xr = 0
-      GOFD_TRY(true_residual(ctx, P, w, w.xr.as<double>(), bsave.as<double>(), w.b.as<double>(), rr, bb));
+      GOFD_TRY(true_residual(ctx, B, w, w.xr.as<double>(), bsave.as<double>(), w.b.as<double>(), rr, bb));
       bool all = true;
-      for (int k = 0; k < P.nrhs; ++k) {
+      for (int k = 0; k < ni; ++k) {
         rel[k] = bb[k] > 0 ? std::sqrt(rr[k] / bb[k]) : 0.0;
         if (rel[k] <= tol) conv[k] = 1;
         all = all && conv[k];
       }
       if (all || ref == max_ref || total_it >= max_iter) break;
       // correction: K d = r with single-precision grid products
-      rc = pcg_run(ctx, P, w, inner, true, max_iter - total_it, check, graph, hs, nullptr, 0.0, nullptr, prof);
+      rc = pcg_run(ctx, B, w, inner, true, max_iter - total_it, check, graph, hs, nullptr, 0.0, nullptr, prof);
       if (rc != GOFD_OK) return rc;
       int mx = 0;
-      for (int k = 0; k < P.nrhs; ++k) {
+      for (int k = 0; k < ni; ++k) {
         if (!conv[k]) {
           iters[k] += hs[k].iters;
           refs[k] += 1;
@@ -990,24 +1087,25 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
         if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
       }
       total_it += mx;
-      hipLaunchKernelGGL(k_axpy_mask, dim3(grid1(nv * P.nrhs, 256)), dim3(256), 0, st, w.xr.as<double>(),
-                         w.x.as<double>(), (long long)(nv * P.nrhs));
+      hipLaunchKernelGGL(k_axpy_mask, dim3(grid1(ntot, 256)), dim3(256), 0, st, w.xr.as<double>(), w.x.as<double>(),
+                         ntot);
     }
-    HIP_TRY(ctx, hipMemcpyAsync(u_out, w.xr.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
-    for (int k = 0; k < P.nrhs; ++k)
+    GOFD_TRY(copy_out(w.xr.as<double>()));
+    for (int k = 0; k < ni; ++k)
       if (!conv[k] && status[k] == GOFD_OK) status[k] = GOFD_E_NOT_CONVERGED;
-    // restore b for callers that inspect it
-    HIP_TRY(ctx, hipMemcpyAsync(w.b.p, bsave.p, sizeof(double) * nv * P.nrhs, hipMemcpyDeviceToDevice, st));
+    // restore b for the final residual
+    HIP_TRY(ctx, hipMemcpyAsync(w.b.p, bsave.p, sizeof(double) * ntot, hipMemcpyDeviceToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
   } else {
     return gofd_fail(ctx, GOFD_E_ARG, "unknown solve mode");
   }
-  // final relative residual in double precision
+  // final relative residual in double precision (of the solution just copied out)
+  const double* xfin = (mode == GOFD_MODE_FP32_REFINE) ? w.xr.as<double>() : w.x.as<double>();
   std::vector<double> rr, bb;
-  GOFD_TRY(true_residual(ctx, P, w, u_out, w.b.as<double>(), w.r.as<double>(), rr, bb));
+  GOFD_TRY(true_residual(ctx, B, w, xfin, w.b.as<double>(), w.r.as<double>(), rr, bb));
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   int worst = GOFD_OK;
-  for (int k = 0; k < P.nrhs; ++k) {
+  for (int k = 0; k < ni; ++k) {
     rel[k] = bb[k] > 0 ? std::sqrt(rr[k] / bb[k]) : 0.0;
     if (info) {
       info[k].iterations = iters[k];
@@ -1023,30 +1121,72 @@ static int solve_system(gofd_ctx_s* ctx, const Problem& P, Work& w, double tol, 
   return GOFD_OK;
 }
 
-extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, int nrhs, const double* f,
-                          int f_loc, double tol, const gofd_solve_opts* opts, double* u, gofd_solve_info* info) {
-  if (!ctx || !tr || !op || !f || !u || nrhs < 1) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+static int check_problem(gofd_ctx_s* ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, int nrhs) {
+  if (!tr || !op || nrhs < 1) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
   if (!same_grid(tr, op)) return gofd_fail(ctx, GOFD_E_ARG, "transfer and operator use different grids");
-  if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
   if (pc && pc->nv != tr->nv) return gofd_fail(ctx, GOFD_E_ARG, "preconditioner built for another mesh");
-  WorkStream ws(ctx);
-  Problem P{tr, op, pc, nrhs};
-  Work w;
-  GOFD_TRY(reserve_work(ctx, w, tr->nv, tr->n_nodes, nrhs));
-  GOFD_TRY(form_rhs(ctx, P, f, f_loc, w.b.as<double>()));
-  return solve_system(ctx, P, w, tol, opts, u, info);
+  return GOFD_OK;
 }
 
+extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, int nrhs, const double* f,
+                          int f_loc, double tol, const gofd_solve_opts* opts, double* u, gofd_solve_info* info) {
+  if (!ctx || !f || !u) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  GOFD_TRY(check_problem(ctx, tr, op, pc, nrhs));
+  if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
+  WorkStream ws(ctx);
+  Batch B;
+  GOFD_TRY(batch_init(ctx, B, {Problem{tr, op, pc, nrhs}}));
+  Work w;
+  GOFD_TRY(reserve_work(ctx, w, B));
+  GOFD_TRY(form_rhs(ctx, B.probs[0], f, f_loc, w.b.as<double>()));
+  double* outs[1] = {u};
+  return solve_system(ctx, B, w, tol, opts, outs, info);
+}
+
+// Problems are grouped by grid shape (d, W, L); each group is one batch whose
+// CG iterations advance together, every stage one launch for the group.
 extern "C" int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* trs, const gofd_fdop* ops,
                                   const gofd_precond* pcs, const int* nrhs, const double* const* f, int f_loc,
                                   double tol, const gofd_solve_opts* opts, double* const* u, gofd_solve_info* info) {
   if (!ctx || nprob < 1 || !trs || !ops || !nrhs || !f || !u) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
-  int off = 0;
+  if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
+  std::vector<int> item0(nprob + 1, 0);
   for (int q = 0; q < nprob; ++q) {
-    GOFD_TRY(gofd_solve(ctx, trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q], f[q], f_loc, tol, opts, u[q],
-                        info ? info + off : nullptr));
-    off += nrhs[q];
+    GOFD_TRY(check_problem(ctx, trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q]));
+    if (!f[q] || !u[q]) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+    item0[q + 1] = item0[q] + nrhs[q];
   }
+  WorkStream ws(ctx);
+  std::vector<char> done(nprob, 0);
+  int worst = GOFD_OK;
+  for (int q0 = 0; q0 < nprob; ++q0) {
+    if (done[q0]) continue;
+    std::vector<int> members;
+    for (int q = q0; q < nprob; ++q)
+      if (!done[q] && ops[q]->d == ops[q0]->d && ops[q]->W == ops[q0]->W && ops[q]->L == ops[q0]->L) {
+        members.push_back(q);
+        done[q] = 1;
+      }
+    std::vector<Problem> probs;
+    for (int q : members) probs.push_back(Problem{trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q]});
+    Batch B;
+    GOFD_TRY(batch_init(ctx, B, probs));
+    Work w;
+    GOFD_TRY(reserve_work(ctx, w, B));
+    std::vector<double*> outs;
+    for (size_t j = 0; j < members.size(); ++j) {
+      GOFD_TRY(form_rhs(ctx, B.probs[j], f[members[j]], f_loc, w.b.as<double>() + B.poff[j]));
+      outs.push_back(u[members[j]]);
+    }
+    std::vector<gofd_solve_info> inf(B.nitems);
+    const int rc = solve_system(ctx, B, w, tol, opts, outs.data(), inf.data());
+    if (rc != GOFD_OK && rc != GOFD_E_NOT_CONVERGED && rc != GOFD_E_BREAKDOWN) return rc;
+    if (rc != GOFD_OK && worst == GOFD_OK) worst = rc;
+    if (info)
+      for (size_t j = 0; j < members.size(); ++j)
+        for (int k = 0; k < nrhs[members[j]]; ++k) info[item0[members[j]] + k] = inf[B.pitem[j] + k];
+  }
+  if (worst != GOFD_OK) return gofd_fail(ctx, worst, "solve did not reach the tolerance for every right-hand side");
   return GOFD_OK;
 }
 
@@ -1166,16 +1306,19 @@ extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, 
   if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
   WorkStream ws(ctx);
   hipStream_t st = ctx->stream;
-  Problem P{tr, op, pc, 1};
+  GOFD_TRY(check_problem(ctx, tr, op, pc, 1));
+  Batch B;
+  GOFD_TRY(batch_init(ctx, B, {Problem{tr, op, pc, 1}}));
   Work w;
-  GOFD_TRY(reserve_work(ctx, w, tr->nv, tr->n_nodes, 1));
+  GOFD_TRY(reserve_work(ctx, w, B));
   const long long nv = tr->nv, nn = tr->n_nodes;
   // adjoint right-hand side: dL/du on the interior block (K is symmetric)
   hipLaunchKernelGGL(k_mask_copy, dim3(grid1(nv, 256)), dim3(256), 0, st, dLdu, tr->imask.as<double>(), nv,
                      w.b.as<double>());
   DevBuf lam;
   GOFD_TRY(dev_reserve(ctx, lam, sizeof(double) * nv));
-  GOFD_TRY(solve_system(ctx, P, w, tol, opts, lam.as<double>(), info));
+  double* outs[1] = {lam.as<double>()};
+  GOFD_TRY(solve_system(ctx, B, w, tol, opts, outs, info));
   if (lambda) HIP_TRY(ctx, hipMemcpyAsync(lambda, lam.p, sizeof(double) * nv, hipMemcpyDeviceToDevice, st));
   GridGeom g;
   g.d = tr->d;
