@@ -741,7 +741,7 @@ int fdop_init_geometry(gofd_ctx_s* ctx, gofd_fdop_s* op, double s, const gofd_gr
   op->d = grid->d;
   op->N = grid->N;
   op->W = 2 * grid->N + 1;
-  op->L = next_pow2(4LL * grid->N);
+  op->L = std::max(8, next_pow2(4LL * grid->N));     // L >= 4N keeps the embedding exact (R7); 8 is the smallest built
   op->half = op->L / 2 + 1;
   op->s = s;
   op->R = grid->R;

@@ -13,7 +13,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("n,s", [(8, 0.3), (42, 0.5), (64, 0.75), (128, 0.25)])
+@pytest.mark.parametrize("n,s", [(2, 0.5), (4, 0.4), (8, 0.3), (42, 0.5), (64, 0.75), (128, 0.25)])
 def test_afd_matches_direct_sums(gctx, n, s):
     import torch
     import paper_2307_14437_amd as gofd
@@ -45,6 +45,39 @@ def test_afd_full_size_sampled(gctx):
     got = np.array([y[k] for k in nodes])
     assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(y))
     assert _rel(y, afd.apply_fft(T, v)) < 1e-12
+
+
+def _synthetic_table(d, W):
+    """A symmetric, decaying table: any T serves the product check (the product is linear in T)."""
+    idx = np.indices((W,) * d).astype(np.float64)
+    r = np.sqrt(np.sum(idx ** 2, axis=0))
+    T = -1.0 / (1.0 + r) ** 2.5
+    T.flat[0] = 0.0
+    T.flat[0] = -T.sum() * 1.01
+    return T
+
+
+@pytest.mark.parametrize("d,n", [(2, 2048), (3, 256)])
+def test_afd_largest_grids_sampled(gctx, d, n):
+    """The largest workloads' grids (C5: 2048^2, FFT length 4096; C3: 256^3, length 512) against direct
+    sums of sampled rows, in both precisions."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    g = grid_for_box(d, n, R=1.0)
+    T = _synthetic_table(d, g.W)
+    op = gofd.FdOp(gctx, 0.5, g, T=T)
+    v = np.random.default_rng(d).standard_normal((g.W,) * d)
+    print(f"afd largest d={d} n={n}", flush=True)
+    vd = torch.tensor(v, device="cuda")
+    y = gofd.apply_afd(gctx, op, vd).cpu().numpy()
+    y32 = gofd.apply_afd(gctx, op, vd, gofd.FP32_GRID).cpu().numpy()
+    W = g.W
+    nodes = [(0,) * d, (W - 1,) * d, tuple([W // 2] * d), tuple(np.random.default_rng(9).integers(0, W, size=d)),
+             tuple([1] + [W - 2] * (d - 1))]
+    ref = afd.apply_rows(T, v, nodes)
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(np.array([y[k] for k in nodes]) - ref)) < 1e-12 * scale
+    assert np.max(np.abs(np.array([y32[k] for k in nodes]) - ref)) < 1e-5 * scale
 
 
 @pytest.fixture(scope="module")

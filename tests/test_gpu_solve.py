@@ -182,6 +182,30 @@ def test_lshape_full_size_solves_oracle_system(gctx, s):
     assert np.linalg.norm(a - c) / np.linalg.norm(a) < 1e-6
 
 
+def test_bench_configuration_full_size(gctx):
+    """The benchmark step exactly: both orders of C2 in one batched FP32-grid solve with FP64 residual
+    replacement (drop 0.1), no preconditioner, tol 1e-8; each solution checked by the oracle's residual."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    cfg = config_inputs("c2")
+    m, g, f = cfg["mesh"], cfg["grid"], cfg["f"][0]
+    tr = gofd.Transfer(gctx, _dev(m.X), _dev(m.elems, torch.int32), g)
+    ops = [gofd.FdOp(gctx, s, g) for s in cfg["s"]]
+    pcs = [gofd.Precond(gctx, tr, op, "NONE") for op in ops]
+    fd = _dev(f)
+    us, infos = gofd.solve_batched(gctx, [tr] * 2, ops, pcs, [fd, fd], tol=cfg["tol"],
+                                   mode=gofd.MODE_FP32_RELIABLE, inner_tol=0.1)
+    otr = transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
+    for k, s in enumerate(cfg["s"]):
+        print(s, infos[k], flush=True)
+        T = ops[k].table()
+        b = operator.rhs_grid(otr, s, f)
+        u = us[k].cpu().numpy()
+        r = operator.apply_K(otr, T, u[otr.J], "fft") - b
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1.5e-8
+        assert np.all(u[otr.bnd] == 0.0)
+
+
 def test_stage_timing_reports_every_stage(gctx, c1_setup):
     import paper_2307_14437_amd as gofd
     m, g, otr, T, tr, op, K = c1_setup
