@@ -129,19 +129,13 @@ __device__ __forceinline__ void make_record(const double* __restrict__ X, const 
   }
 }
 
-// weights of grid node k (linear number) from its element's record
+// weights of the grid node with axis indices idx[0..D-1] from its element's record
 template <int D>
-__device__ __forceinline__ void node_weights(const GridGeom& g, const ElemRec<D>* __restrict__ recs, int e,
-                                             long long k, int* vid, double* lam) {
+__device__ __forceinline__ void rec_weights(const GridGeom& g, const ElemRec<D>& rec, const int* idx, int* vid,
+                                            double* lam) {
 #pragma clang fp contract(off)
-  const ElemRec<D> rec = recs[e];
   double dx[3];
-  long long rem = k;
-  for (int a = 0; a < D; ++a) {
-    const int i = (int)(rem % g.W);
-    rem /= g.W;
-    dx[a] = node_coord(g, a, i) - rec.x0[a];
-  }
+  for (int a = 0; a < D; ++a) dx[a] = node_coord(g, a, idx[a]) - rec.x0[a];
   double s = 0.0;
   for (int r = 1; r <= D; ++r) {
     double l = 0.0;
@@ -151,4 +145,18 @@ __device__ __forceinline__ void node_weights(const GridGeom& g, const ElemRec<D>
   }
   lam[0] = 1.0 - s;
   for (int r = 0; r <= D; ++r) vid[r] = rec.v[r];
+}
+
+// weights of grid node k (linear number) from its element's record
+template <int D>
+__device__ __forceinline__ void node_weights(const GridGeom& g, const ElemRec<D>* __restrict__ recs, int e,
+                                             long long k, int* vid, double* lam) {
+  const ElemRec<D> rec = recs[e];
+  int idx[3];
+  long long rem = k;
+  for (int a = 0; a < D; ++a) {
+    idx[a] = (int)(rem % g.W);
+    rem /= g.W;
+  }
+  rec_weights<D>(g, rec, idx, vid, lam);
 }

@@ -23,6 +23,8 @@ struct CgItem {
   const int* ell_idx;         // 3D: compact row of each inside node or -1
   const int4* ell_v;          // 3D: vertex ids of the rows
   const double2* ell_w;       // 3D: weights of the rows
+  const int4* row32_v;        // 2D: per-node vertex ids (and weight 0) for the FP32 gather
+  const float2* row32_w;      // 2D: per-node weights 1 and 2 for the FP32 gather
   GridGeom g;
   long long nv;               // vertices of the mesh
   long long off;              // offset of the item's vectors in the batch vectors

@@ -46,39 +46,155 @@ inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); 
 #endif
 constexpr int GATHER_NPT = GOFD_GATHER_NPT;   // nodes per thread of the gather (build-time knob)
 
+// Every load of the gathers is unconditional, from in-range indices: a node
+// past the end reads the last node, a node outside the mesh reads the row of
+// element 0 (compact row 0 in 3D) and weighs it by zero.  Per-lane branches
+// around dependent loads would make each node of a thread wait for the one
+// before it.
+
+// 2D: interpolation rows of NPT nodes (column ci, row ri) from their element records
+template <int NPT>
+__device__ __forceinline__ void rows_2d_ij(const GridGeom& g, const ElemRec2* recs, const int* e, const int* ci,
+                                           const int* ri, int (*vid)[4], double (*lam)[4]) {
+  static_assert(sizeof(ElemRec2) == 64, "record layout");
+  const int4* rq = reinterpret_cast<const int4*>(recs);
+  const double2* rd = reinterpret_cast<const double2*>(recs);
+  ElemRec2 rec[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const long long c = e[j] >= 0 ? e[j] : 0;
+    const int4 v = gload(rq, 4 * c);
+    const double2 x0 = gload(rd, 4 * c + 1), g0 = gload(rd, 4 * c + 2), g1 = gload(rd, 4 * c + 3);
+    rec[j].v[0] = v.x, rec[j].v[1] = v.y, rec[j].v[2] = v.z, rec[j].v[3] = v.w;
+    rec[j].x0[0] = x0.x, rec[j].x0[1] = x0.y;
+    rec[j].g[0][0] = g0.x, rec[j].g[0][1] = g0.y, rec[j].g[1][0] = g1.x, rec[j].g[1][1] = g1.y;
+  }
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int idx[2] = {ci[j], ri[j]};
+    rec_weights<2>(g, rec[j], idx, vid[j], lam[j]);
+    vid[j][3] = vid[j][0];
+    lam[j][3] = 0.0;
+    if (e[j] < 0) lam[j][0] = lam[j][1] = lam[j][2] = 0.0;
+  }
+}
+
+// the same for nodes given by their linear numbers k
+template <int NPT>
+__device__ __forceinline__ void rows_2d(const GridGeom& g, const ElemRec2* recs, const int* e, const unsigned* k,
+                                        int (*vid)[4], double (*lam)[4]) {
+  int ci[NPT], ri[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const unsigned W = (unsigned)g.W;
+    ci[j] = (int)(k[j] % W);
+    ri[j] = (int)(k[j] / W);
+  }
+  rows_2d_ij<NPT>(g, recs, e, ci, ri, vid, lam);
+}
+
+// 2D, FP32 pipeline: interpolation rows of NPT nodes k from the per-node
+// single-precision rows (weights widened to double for the sum)
+template <int NPT>
+__device__ __forceinline__ void rows_2d_32(const int4* rv, const float2* rw, const long long* k, int (*vid)[4],
+                                           double (*lam)[4]) {
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int4 v = gload(rv, k[j]);
+    const float2 w = gload(rw, k[j]);
+    vid[j][0] = v.x, vid[j][1] = v.y, vid[j][2] = v.z, vid[j][3] = v.x;
+    lam[j][0] = (double)__int_as_float(v.w), lam[j][1] = (double)w.x, lam[j][2] = (double)w.y, lam[j][3] = 0.0;
+  }
+}
+
+// 3D: interpolation rows of NPT nodes from the compact per-node rows
+template <int NPT>
+__device__ __forceinline__ void rows_3d(const int4* ev, const double2* ew, const int* c, int (*vid)[4],
+                                        double (*lam)[4]) {
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const long long cc = c[j] >= 0 ? c[j] : 0;
+    const int4 v = gload(ev, cc);
+    const double2 w01 = gload(ew, 2 * cc), w23 = gload(ew, 2 * cc + 1);
+    vid[j][0] = v.x, vid[j][1] = v.y, vid[j][2] = v.z, vid[j][3] = v.w;
+    lam[j][0] = w01.x, lam[j][1] = w01.y, lam[j][2] = w23.x, lam[j][3] = w23.y;
+    if (c[j] < 0) lam[j][0] = lam[j][1] = lam[j][2] = lam[j][3] = 0.0;
+  }
+}
+
+// sum_r lam_r * (u * scale * mask)[vid_r] for NPT rows (scale and mask optional)
+template <int D, int NPT>
+__device__ __forceinline__ void row_values(const double* u, const double* scale, const double* mask,
+                                           const int (*vid)[4], const double (*lam)[4], double* out) {
+  const auto gu = gmem(u);
+  double uv[NPT][D + 1];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j)
+#pragma unroll
+    for (int r = 0; r <= D; ++r) uv[j][r] = gu[vid[j][r]];
+  if (scale) {
+    const auto gs = gmem(scale);
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+#pragma unroll
+      for (int r = 0; r <= D; ++r) uv[j][r] *= gs[vid[j][r]];
+  }
+  if (mask) {
+    const auto gm = gmem(mask);
+#pragma unroll
+    for (int j = 0; j < NPT; ++j)
+#pragma unroll
+      for (int r = 0; r <= D; ++r) uv[j][r] *= gm[vid[j][r]];
+  }
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r <= D; ++r) s += lam[j][r] * uv[j][r];
+    out[j] = s;
+  }
+}
+
+// 2D: the FP64 pipeline evaluates each node's weights from its element's
+// record (element, record, vertex values: three dependent loads); the FP32
+// pipeline reads the per-node single-precision rows (row, vertex values: two)
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_gather(GridGeom g, const ElemRec<D>* __restrict__ recs,
-                                                const int* __restrict__ elem, const double* __restrict__ u,
+                                                const int* __restrict__ elem, const int4* __restrict__ rv,
+                                                const float2* __restrict__ rw, const double* __restrict__ u,
                                                 const double* __restrict__ scale, const double* __restrict__ mask,
                                                 long long nv, long long n_nodes, R* __restrict__ out, Skip skip) {
+  static_assert(D == 2, "3D gathers from compact rows");
   const long long k0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * (256 * GATHER_NPT) + threadIdx.x;
   const int rhs = blockIdx.y;
-  int e[GATHER_NPT];
+  int vid[GATHER_NPT][4];
+  double lam[GATHER_NPT][4], val[GATHER_NPT];
+  if constexpr (sizeof(R) == 4) {
+    long long kc[GATHER_NPT];
 #pragma unroll
-  for (int j = 0; j < GATHER_NPT; ++j) {
-    const long long k = k0 + j * 256;
-    e[j] = k < n_nodes ? elem[k] : -2;
-  }
-  if (skip(rhs)) return;
-  const double* ur = u + rhs * nv;
-#pragma unroll
-  for (int j = 0; j < GATHER_NPT; ++j) {
-    const long long k = k0 + j * 256;
-    if (e[j] == -2) continue;
-    double s = 0.0;
-    if (e[j] >= 0) {
-      int vid[D + 1];
-      double lam[D + 1];
-      node_weights<D>(g, recs, e[j], k, vid, lam);
-#pragma unroll
-      for (int r = 0; r <= D; ++r) {
-        double uv = ur[vid[r]];
-        if (scale) uv *= scale[vid[r]];
-        if (mask) uv *= mask[vid[r]];
-        s += lam[r] * uv;
-      }
+    for (int j = 0; j < GATHER_NPT; ++j) {
+      const long long k = k0 + j * 256;
+      kc[j] = k < n_nodes ? k : n_nodes - 1;
     }
-    out[rhs * n_nodes + k] = (R)s;
+    rows_2d_32<GATHER_NPT>(rv, rw, kc, vid, lam);
+    if (skip(rhs)) return;
+  } else {
+    int e[GATHER_NPT];
+    unsigned kc[GATHER_NPT];
+#pragma unroll
+    for (int j = 0; j < GATHER_NPT; ++j) {
+      const long long k = k0 + j * 256;
+      kc[j] = (unsigned)(k < n_nodes ? k : n_nodes - 1);
+      e[j] = gmem(elem)[kc[j]];
+    }
+    if (skip(rhs)) return;
+    rows_2d<GATHER_NPT>(g, recs, e, kc, vid, lam);
+  }
+  row_values<2, GATHER_NPT>(u + rhs * nv, scale, mask, vid, lam, val);
+#pragma unroll
+  for (int j = 0; j < GATHER_NPT; ++j) {
+    const long long k = k0 + j * 256;
+    if (k < n_nodes) out[rhs * n_nodes + k] = (R)val[j];
   }
 }
 
@@ -95,22 +211,11 @@ __global__ __launch_bounds__(256) void k_gather_ell(const int* __restrict__ idx,
   if (k >= n_nodes) return;
   const int c = idx[k];
   if (skip(rhs)) return;
-  double s = 0.0;
-  if (c >= 0) {
-    const int4 v = ev[c];
-    const double2 w01 = ew[2 * (long long)c], w23 = ew[2 * (long long)c + 1];
-    const int vid[4] = {v.x, v.y, v.z, v.w};
-    const double lam[4] = {w01.x, w01.y, w23.x, w23.y};
-    const double* ur = u + rhs * nv;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double uv = ur[vid[r]];
-      if (scale) uv *= scale[vid[r]];
-      if (mask) uv *= mask[vid[r]];
-      s += lam[r] * uv;
-    }
-  }
-  out[rhs * n_nodes + k] = (R)s;
+  int vid[1][4];
+  double lam[1][4], val[1];
+  rows_3d<1>(ev, ew, &c, vid, lam);
+  row_values<3, 1>(u + rhs * nv, scale, mask, vid, lam, val);
+  out[rhs * n_nodes + k] = (R)val[0];
 }
 
 // Batched gather: item blockIdx.y of the batch (its mesh, its vector at
@@ -122,44 +227,96 @@ __global__ __launch_bounds__(256) void k_gather_items(const CgItem* __restrict__
   const int it = blockIdx.y;
   const CgItem& I = items[it];
   const long long k0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * (256 * GATHER_NPT) + threadIdx.x;
-  int e[GATHER_NPT];
+  int vid[GATHER_NPT][4];
+  double lam[GATHER_NPT][4], val[GATHER_NPT];
+  if constexpr (D == 2 && sizeof(R) == 4) {
+    // FP32 pipeline: per-node single-precision rows
+    long long kc[GATHER_NPT];
 #pragma unroll
-  for (int j = 0; j < GATHER_NPT; ++j) {
-    const long long k = k0 + j * 256;
-    if constexpr (D == 2)
-      e[j] = k < n_nodes ? I.elem[k] : -2;
-    else
-      e[j] = k < n_nodes ? I.ell_idx[k] : -2;
-  }
-  if (skip(it)) return;
-  const double* ur = ubase + I.off;
-  const double* mask = use_mask ? I.imask : nullptr;
-#pragma unroll
-  for (int j = 0; j < GATHER_NPT; ++j) {
-    const long long k = k0 + j * 256;
-    if (e[j] == -2) continue;
-    double s = 0.0;
-    if (e[j] >= 0) {
-      int vid[D + 1];
-      double lam[D + 1];
-      if constexpr (D == 2) {
-        node_weights<2>(I.g, static_cast<const ElemRec2*>(I.recs), e[j], k, vid, lam);
-      } else {
-        const int4 v = I.ell_v[e[j]];
-        const double2 w01 = I.ell_w[2 * (long long)e[j]], w23 = I.ell_w[2 * (long long)e[j] + 1];
-        vid[0] = v.x, vid[1] = v.y, vid[2] = v.z, vid[3] = v.w;
-        lam[0] = w01.x, lam[1] = w01.y, lam[2] = w23.x, lam[3] = w23.y;
-      }
-#pragma unroll
-      for (int r = 0; r <= D; ++r) {
-        double uv = ur[vid[r]];
-        if (mask) uv *= mask[vid[r]];
-        s += lam[r] * uv;
-      }
+    for (int j = 0; j < GATHER_NPT; ++j) {
+      const long long k = k0 + j * 256;
+      kc[j] = k < n_nodes ? k : n_nodes - 1;
     }
-    out[it * n_nodes + k] = (R)s;
+    rows_2d_32<GATHER_NPT>(I.row32_v, I.row32_w, kc, vid, lam);
+    if (skip(it)) return;
+  } else {
+    const auto elem = gmem(D == 2 ? I.elem : I.ell_idx);
+    int e[GATHER_NPT];
+    unsigned kc[GATHER_NPT];
+#pragma unroll
+    for (int j = 0; j < GATHER_NPT; ++j) {
+      const long long k = k0 + j * 256;
+      kc[j] = (unsigned)(k < n_nodes ? k : n_nodes - 1);
+      e[j] = elem[kc[j]];
+    }
+    if (skip(it)) return;
+    if constexpr (D == 2)
+      rows_2d<GATHER_NPT>(I.g, static_cast<const ElemRec2*>(I.recs), e, kc, vid, lam);
+    else
+      rows_3d<GATHER_NPT>(I.ell_v, I.ell_w, e, vid, lam);
+  }
+  row_values<D, GATHER_NPT>(ubase + I.off, nullptr, use_mask ? I.imask : nullptr, vid, lam, val);
+#pragma unroll
+  for (int j = 0; j < GATHER_NPT; ++j) {
+    const long long k = k0 + j * 256;
+    if (k < n_nodes) out[it * n_nodes + k] = (R)val[j];
   }
 }
+
+// ---------------------------------------------------------------- row-pair sources
+// Input of the first row pass: for the row pair (row0, row0 + 1), thread t
+// of the TPL threads of the pair gets element m of its line, the complex
+// value (row0, col) + i (row0 + 1, col) at col = t + m TPL; columns past the
+// window and rows past the grid give zero.  Loads read clamped in-range
+// positions and are masked after.
+template <int E, int TPL>
+struct PairCols {
+  static constexpr int M = E / 2 + 1;     // columns beyond L/2 are outside the window (W <= L/2 + 1)
+  int r0c, r1c;
+  bool has0, has1;
+  __device__ __forceinline__ PairCols(int row0, int W) {
+    has0 = row0 < W;
+    has1 = row0 + 1 < W;
+    r0c = has0 ? row0 : W - 1;
+    r1c = has1 ? row0 + 1 : r0c;
+  }
+  __device__ __forceinline__ static int col(int t, int m) { return t + m * TPL; }
+  __device__ __forceinline__ static int clamp(int c, int W) { return c < W ? c : W - 1; }
+  template <typename R>
+  __device__ __forceinline__ void put(cplx<R>* v, int t, int W, const double* a, const double* b) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      R x = 0, y = 0;
+      if (m < M) {
+        const bool in = col(t, m) < W;
+        if (has0 && in) x = (R)a[m];
+        if (has1 && in) y = (R)b[m];
+      }
+      v[m] = {x, y};
+    }
+  }
+};
+
+// a grid field (nrhs fields of W^2 values)
+template <typename T>
+struct SrcPairGrid {
+  const T* f;
+  long long n_nodes;
+  template <typename R, int E, int TPL>
+  __device__ __forceinline__ void load(int rhs, int row0, int W, int t, cplx<R>* v) const {
+    const PairCols<E, TPL> pc(row0, W);
+    constexpr int M = PairCols<E, TPL>::M;
+    const T* fr = f + rhs * n_nodes;
+    double a[M], b[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int cc = pc.clamp(pc.col(t, m), W);
+      a[m] = (double)fr[(long long)pc.r0c * W + cc];
+      b[m] = (double)fr[(long long)pc.r1c * W + cc];
+    }
+    pc.template put<R>(v, t, W, a, b);
+  }
+};
 
 // ---------------------------------------------------------------- spectra layout
 // Z holds, per rhs, the L/2 column slots of the W window rows after the row
@@ -191,19 +348,12 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passA(Src src, cplx<R>* __res
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
   cplx<R> v[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int col = t + m * TPL;       // columns beyond L/2 are outside the window (W <= L/2 + 1)
-    R x = 0, y = 0;
-    if (m <= E / 2 && col < W) {
-      if (has0) x = (R)src(rhs, (long long)row0 * W + col);
-      if (has1) y = (R)src(rhs, (long long)(row0 + 1) * W + col);
-    }
-    v[m] = {x, y};
-  }
+  src.template load<R, E, TPL>(rhs, row0, W, t, v);
+  gofd_fft::Twiddles<R, L, E> tws;
+  tws.load(tw, t);
   // the finished-rhs test after the loads, so that its latency overlaps theirs
   if (skip(rhs)) return;
-  fft_regs<R, L, E, false>(v, buf, tw, t);
+  fft_regs<R, L, E, false>(v, buf, tws, t);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < E; ++m) buf[pidx<E>(t + m * TPL)] = v[m];
@@ -245,7 +395,7 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passA(Src src, cplx<R>* __res
 // (K u, u) of CG when v = I u, and the sums of its slice of the level-1
 // partials of gamma and (r, r): dpart[rhs][q][block], q = gamma, (r, r), delta.
 template <typename R, int L, int E, int LB, bool DOT>
-__global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, int W, int half,
+__global__ __launch_bounds__(LB*(L / E), 2) void k_passB(cplx<R>* __restrict__ Z, int W, int half,
                                                       const R* That, const cplx<R>* __restrict__ tw,
                                                       long long zs, Skip skip, double* __restrict__ dpart,
                                                       gofd_cg::Level1 lv1, const void* const* __restrict__ that_tab) {
@@ -260,12 +410,22 @@ __global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, i
   cplx<R>* buf = sbuf + c * PL;
   const int slot = b * LB + c;
   cplx<R>* Zc = Z + blockIdx.y * zs + zidx<R>(slot, 0, W);
+  // rows i >= W are zero (W <= L/2 + 1: only elements m <= E/2 can hold rows
+  // of the window); the loads read clamped rows and are masked after, so that
+  // they are all in flight together
   cplx<R> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int i = t + m * TPL;
-    v[m] = (m <= E / 2 && i < W) ? Zc[(long long)i * 4] : cplx<R>{0, 0};
+    if (m <= E / 2) {
+      v[m] = Zc[(long long)(i < W ? i : W - 1) * 4];
+      if (i >= W) v[m] = cplx<R>{0, 0};
+    } else {
+      v[m] = cplx<R>{0, 0};
+    }
   }
+  gofd_fft::Twiddles<R, L, E> tws;
+  tws.load(tw, t);
   // multipliers of this slot, fetched before the transform; element k1 of the
   // line takes row min(k1, L - k1) of the stored (L/2+1)-row spectrum column
   // (for slot 0 this is column k0 = 0; column L/2 is read when it is used)
@@ -291,7 +451,7 @@ __global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, i
   }
   if (skip(blockIdx.y)) return;
   double& dacc = red[2];
-  fft_regs<R, L, E, false>(v, buf, tw, t);
+  fft_regs<R, L, E, false>(v, buf, tws, t);
   if (b == 0) {                     // block-uniform: this block holds slot 0
     __syncthreads();
 #pragma unroll
@@ -316,11 +476,15 @@ __global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, i
     }
   }
   if (slot != 0) {
+    // terms That_k |V_k|^2 in the grid precision (products of grid values),
+    // summed in double
+    double dsum = 0.0;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if constexpr (DOT) dacc += 2.0 * (double)pm[m] * ((double)v[m].x * v[m].x + (double)v[m].y * v[m].y);
+      if constexpr (DOT) dsum += (double)(pm[m] * (v[m].x * v[m].x + v[m].y * v[m].y));
       v[m] = {v[m].x * pm[m], v[m].y * pm[m]};
     }
+    dacc += 2.0 * dsum;
   }
   if constexpr (DOT) {
     static_assert(NT % 64 == 0 || NT < 64, "block size");
@@ -333,7 +497,8 @@ __global__ __launch_bounds__(LB*(L / E)) void k_passB(cplx<R>* __restrict__ Z, i
     }
   }
   __syncthreads();
-  fft_regs<R, L, E, true>(v, buf, tw, t);
+  tws.opaque();
+  fft_regs<R, L, E, true>(v, buf, tws, t);
 #pragma unroll
   for (int m = 0; m <= E / 2; ++m) {
     const int i = t + m * TPL;
@@ -372,6 +537,9 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restri
     fin.run<NT>(rhs, shf);
     return;
   }
+  // rows past the window read a window row (loads in flight together) and
+  // count as zero
+  const int r0c = has0 ? row0 : W - 1, r1c = has1 ? row0 + 1 : r0c;
   cplx<R> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -379,8 +547,10 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restri
     const bool dcnq = (m == 0 || m == E / 2) && t == 0;      // k = 0 or k = L/2: packed slot 0
     const bool mirror = !dcnq && m >= E / 2;                  // k > L/2: conjugate of slot L - k
     const int sl = dcnq ? 0 : (mirror ? L - k : k);
-    const cplx<R> a = has0 ? Zr[zidx<R>(sl, row0, W)] : cplx<R>{0, 0};
-    const cplx<R> bb = has1 ? Zr[zidx<R>(sl, row0 + 1, W)] : cplx<R>{0, 0};
+    cplx<R> a = Zr[zidx<R>(sl, r0c, W)];
+    cplx<R> bb = Zr[zidx<R>(sl, r1c, W)];
+    if (!has0) a = cplx<R>{0, 0};
+    if (!has1) bb = cplx<R>{0, 0};
     if (dcnq)
       v[m] = (m == 0) ? cplx<R>{a.x, bb.x} : cplx<R>{a.y, bb.y};
     else if (mirror)
@@ -388,8 +558,10 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restri
     else
       v[m] = {a.x - bb.y, a.y + bb.x};                        // a + i b
   }
+  gofd_fft::Twiddles<R, L, E> tws;
+  tws.load(tw, t);
   if (skip(rhs)) return;
-  fft_regs<R, L, E, true>(v, buf, tw, t);
+  fft_regs<R, L, E, true>(v, buf, tws, t);
   if (!has0) return;
   Y* yr = y + rhs * n_nodes + (long long)row0 * W;
 #pragma unroll
@@ -596,16 +768,16 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
     if (d == 3)
       return conv3_run(ctx, op, nrhs, v, nullptr, y, fp32, passes & 7, skip.flag, skip.stride, dpart, lv1, fin,
                        that_tab);
-    SrcGrid<double> src{v, nn};
+    SrcPairGrid<double> src{v, nn};
     return fp32 ? dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin,
                                      that_tab)
                 : dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin,
                                       that_tab);
   }
-  GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
-  const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if (g->pregathered) passes &= ~8;
   hipStream_t st = ctx->stream;
+  GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
+  const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if ((passes & 8) && g->items) {
     // batched: every item gathers from its own mesh
 #define GOFD_GI(R, D) \
@@ -627,10 +799,10 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
     if (d == 2) {
       if (fp32)
         GOFD_LAUNCH(ctx, (k_gather<float, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
-                    tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(), skip);
+                    tr->elem.as<int>(), tr->row32_v.as<int4>(), tr->row32_w.as<float2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(), skip);
       else
         GOFD_LAUNCH(ctx, (k_gather<double, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
-                    tr->elem.as<int>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(), skip);
+                    tr->elem.as<int>(), tr->row32_v.as<int4>(), tr->row32_w.as<float2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(), skip);
     } else {
       const dim3 ge(grid1(nn, 256), nrhs);
       if (fp32)
@@ -648,10 +820,10 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
     return conv3_run(ctx, op, nrhs, fp32 ? nullptr : op->G.as<double>(), fp32 ? op->G.as<float>() : nullptr, y, fp32,
                      passes & 7, skip.flag, skip.stride, dpart, lv1, fin, that_tab);
   if (fp32) {
-    SrcGrid<float> src{op->G.as<float>(), nn};
+    SrcPairGrid<float> src{op->G.as<float>(), nn};
     return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab);
   }
-  SrcGrid<double> src{op->G.as<double>(), nn};
+  SrcPairGrid<double> src{op->G.as<double>(), nn};
   return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin, that_tab);
 }
 

@@ -54,19 +54,25 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_p3A(Src src, cplx<R>* __restr
   const int rhs = blockIdx.y;
   const bool has0 = row0 < nrow;
   const bool has1 = row0 + 1 < nrow;
+  const long long r0c = has0 ? row0 : nrow - 1, r1c = has1 ? row0 + 1 : r0c;
   cplx<R> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int col = t + m * TPL;
     R x = 0, y = 0;
-    if (m <= E / 2 && col < W) {
-      if (has0) x = (R)src(rhs, row0 * W + col);
-      if (has1) y = (R)src(rhs, (row0 + 1) * W + col);
+    if (m <= E / 2) {                  // loads from clamped positions, masked after
+      const int cc = col < W ? col : W - 1;
+      x = (R)src(rhs, r0c * W + cc);
+      y = (R)src(rhs, r1c * W + cc);
+      if (!has0 || col >= W) x = 0;
+      if (!has1 || col >= W) y = 0;
     }
     v[m] = {x, y};
   }
+  gofd_fft::Twiddles<R, L, E> tws;
+  tws.load(tw, t);
   if (skip(rhs)) return;
-  fft_regs<R, L, E, false>(v, buf, tw, t);
+  fft_regs<R, L, E, false>(v, buf, tws, t);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < E; ++m) buf[pidx<E>(t + m * TPL)] = v[m];
@@ -107,17 +113,28 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3BD(cplx<R>* __restrict__ Z1, c
   const long long nrow = (long long)W * W;
   cplx<R>* Z1r = Z1 + blockIdx.y * z1s;
   cplx<R>* Z2r = Z2 + blockIdx.y * z2s;
+  // loads from clamped in-range positions, masked after (all in flight together)
+  const int sc = act ? slot : H;
   cplx<R> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int i = t + m * TPL;
-    if constexpr (!INV)
-      v[m] = (act && m <= E / 2 && i < W) ? Z1r[z1idx(slot, (long long)i2 * W + i, nrow)] : cplx<R>{0, 0};
-    else
-      v[m] = act ? Z2r[z2idx(slot, i2, i, W, L)] : cplx<R>{0, 0};
+    if constexpr (!INV) {
+      if (m <= E / 2) {
+        v[m] = Z1r[z1idx(sc, (long long)i2 * W + (i < W ? i : W - 1), nrow)];
+        if (!act || i >= W) v[m] = cplx<R>{0, 0};
+      } else {
+        v[m] = cplx<R>{0, 0};
+      }
+    } else {
+      v[m] = Z2r[z2idx(sc, i2, i, W, L)];
+      if (!act) v[m] = cplx<R>{0, 0};
+    }
   }
+  gofd_fft::Twiddles<R, L, E> tws;
+  tws.load(tw, t);
   if (skip(blockIdx.y)) return;
-  fft_regs<R, L, E, INV>(v, buf, tw, t);
+  fft_regs<R, L, E, INV>(v, buf, tws, t);
   if (!act) return;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -136,7 +153,7 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3BD(cplx<R>* __restrict__ Z1, c
 // 0 < k0 < L/2 count twice) and the sums of its slice of the level-1
 // partials: dpart[rhs][q][block], q = gamma, (r, r), delta.
 template <typename R, int L, int E, int LB, bool DOT>
-__global__ __launch_bounds__(LB*(L / E)) void k_p3C(cplx<R>* __restrict__ Z2, int W, int half, int nsb,
+__global__ __launch_bounds__(LB*(L / E), 2) void k_p3C(cplx<R>* __restrict__ Z2, int W, int half, int nsb,
                                                      const R* That, const cplx<R>* __restrict__ tw,
                                                      long long z2s, Skip skip, double* __restrict__ dpart,
                                                      gofd_cg::Level1 lv1, const void* const* __restrict__ that_tab) {
@@ -159,14 +176,23 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3C(cplx<R>* __restrict__ Z2, in
   if (that_tab) That = static_cast<const R*>(that_tab[blockIdx.y]);     // per-item spectrum (batched solves)
   // That is half^3 with axis 0 fastest; by symmetry of the kernel the axes
   // may take k0, k1, k2 in any order: index (k2 half + k1) half + k0
-  const R* Tc = That + (long long)kk1 * half + (act ? slot : 0);
+  const int sc = act ? slot : H;
+  const R* Tc = That + (long long)kk1 * half + sc;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int i = t + m * TPL;
-    v[m] = (act && m <= E / 2 && i < W) ? Zr[z2idx(slot, i, k1, W, L)] : cplx<R>{0, 0};
+    if (m <= E / 2) {
+      v[m] = Zr[z2idx(sc, i < W ? i : W - 1, k1, W, L)];
+      if (!act || i >= W) v[m] = cplx<R>{0, 0};
+    } else {
+      v[m] = cplx<R>{0, 0};
+    }
     const int kk2 = (i <= H) ? i : L - i;
-    pm[m] = act ? Tc[(long long)kk2 * half * half] : (R)0;
+    pm[m] = Tc[(long long)kk2 * half * half];
+    if (!act) pm[m] = (R)0;
   }
+  gofd_fft::Twiddles<R, L, E> tws;
+  tws.load(tw, t);
   double red[3] = {0.0, 0.0, 0.0};
   if constexpr (DOT) {
     const int chunk = (lv1.n1 + gridDim.x - 1) / gridDim.x;
@@ -177,13 +203,16 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3C(cplx<R>* __restrict__ Z2, in
     }
   }
   if (skip(blockIdx.y)) return;
-  fft_regs<R, L, E, false>(v, buf, tw, t);
+  fft_regs<R, L, E, false>(v, buf, tws, t);
   const double wgt = (slot == 0 || slot == H) ? 1.0 : 2.0;
+  // terms That_k |V_k|^2 in the grid precision, summed in double
+  double dsum = 0.0;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
-    if constexpr (DOT) red[2] += wgt * (double)pm[m] * ((double)v[m].x * v[m].x + (double)v[m].y * v[m].y);
+    if constexpr (DOT) dsum += (double)(pm[m] * (v[m].x * v[m].x + v[m].y * v[m].y));
     v[m] = {v[m].x * pm[m], v[m].y * pm[m]};
   }
+  red[2] += wgt * dsum;
   if constexpr (DOT) {
     gofd_cg::block_sum_n<NT, 3>(red, shd);
     if (threadIdx.x == 0) {
@@ -194,7 +223,8 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3C(cplx<R>* __restrict__ Z2, in
     }
   }
   __syncthreads();
-  fft_regs<R, L, E, true>(v, buf, tw, t);
+  tws.opaque();
+  fft_regs<R, L, E, true>(v, buf, tws, t);
   if (!act) return;
 #pragma unroll
   for (int m = 0; m <= E / 2; ++m) {
@@ -229,22 +259,28 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_p3E(const cplx<R>* __restrict
   const bool has0 = row0 < nrow;
   const bool has1 = row0 + 1 < nrow;
   const cplx<R>* Zr = Z1 + rhs * z1s;
+  // rows past the end read row nrow - 1 (loads in flight together) and count as zero
+  const long long r0c = has0 ? row0 : nrow - 1, r1c = has1 ? row0 + 1 : r0c;
   cplx<R> v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + m * TPL;
     const bool mirror = k > H;
     const int sl = mirror ? L - k : k;
-    cplx<R> a = has0 ? Zr[z1idx(sl, row0, nrow)] : cplx<R>{0, 0};
-    cplx<R> bb = has1 ? Zr[z1idx(sl, row0 + 1, nrow)] : cplx<R>{0, 0};
+    cplx<R> a = Zr[z1idx(sl, r0c, nrow)];
+    cplx<R> bb = Zr[z1idx(sl, r1c, nrow)];
+    if (!has0) a = cplx<R>{0, 0};
+    if (!has1) bb = cplx<R>{0, 0};
     if (k == 0 || k == H) {                          // exactly real for real rows
       a.y = 0;
       bb.y = 0;
     }
     v[m] = mirror ? cplx<R>{a.x + bb.y, bb.x - a.y} : cplx<R>{a.x - bb.y, a.y + bb.x};
   }
+  gofd_fft::Twiddles<R, L, E> tws;
+  tws.load(tw, t);
   if (skip(rhs)) return;
-  fft_regs<R, L, E, true>(v, buf, tw, t);
+  fft_regs<R, L, E, true>(v, buf, tws, t);
   if (!has0) return;
   Y* yr = y + rhs * n_nodes + row0 * W;
 #pragma unroll

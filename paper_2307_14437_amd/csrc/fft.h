@@ -180,33 +180,81 @@ __device__ __forceinline__ void twiddle(cplx<R>* a, const cplx<R>* wb) {
   for (int r = 1; r < RAD; ++r) a[r] = INV ? cmulc(a[r], w[r]) : cmul(a[r], w[r]);
 }
 
+// Base twiddles of one thread: for every stage after the first and every
+// butterfly of the thread, the table entries w^1, w^2, w^4, w^8 (up to the
+// stage's radix) at its k.  They depend on the thread position only, so a
+// kernel loads them once at its start, where their latency overlaps the data
+// loads, and the forward and inverse transforms of a line share them.
+constexpr int ilog2c(int x) {
+  int n = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++n;
+  }
+  return n;
+}
+template <int L, int E>
+constexpr int stage_radix(int NS) {
+  return (L / NS >= E) ? E : L / NS;
+}
+// slots used by the stages after the first and before the one of size NS
+template <int L, int E>
+constexpr int tw_slots_before(int NS_end) {
+  int n = 0;
+  for (int NS = stage_radix<L, E>(1); NS < NS_end && NS < L; NS *= stage_radix<L, E>(NS))
+    n += (E / stage_radix<L, E>(NS)) * ilog2c(stage_radix<L, E>(NS));
+  return n;
+}
+
+template <typename R, int L, int E>
+struct Twiddles {
+  static constexpr int N = tw_slots_before<L, E>(L);
+  cplx<R> w[N > 0 ? N : 1];
+
+  template <int NS>
+  __device__ __forceinline__ void load_from(const cplx<R>* __restrict__ tw, int t) {
+    if constexpr (NS < L) {
+      constexpr int RAD = stage_radix<L, E>(NS);
+      constexpr int PER = E / RAD, NB = ilog2c(RAD), TPL = L / E, TWS = L / (NS * RAD);
+      constexpr int OFF = tw_slots_before<L, E>(NS);
+#pragma unroll
+      for (int p = 0; p < PER; ++p) {
+        const int k = (t + p * TPL) & (NS - 1);
+#pragma unroll
+        for (int q = 0; q < NB; ++q) w[OFF + p * NB + q] = tw[(k << q) * TWS];
+      }
+      load_from<NS * RAD>(tw, t);
+    }
+  }
+  // tw: the table exp(-2 pi i j / L), j = 0..L-1
+  __device__ __forceinline__ void load(const cplx<R>* __restrict__ tw, int t) {
+    load_from<stage_radix<L, E>(1)>(tw, t);
+  }
+  // Between two transforms of one kernel: the compiler may no longer assume
+  // the values unchanged, so it derives the twiddle products of the second
+  // transform again instead of keeping those of the first in registers.
+  __device__ __forceinline__ void opaque() {
+#pragma unroll
+    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(w[i].x), "+v"(w[i].y));
+  }
+};
+
 // One Stockham stage and, recursively, the ones after it.  LDS protocol: the
 // first stage writes the buffer (callers guarantee no thread still reads
 // it), every later stage waits for the previous writes, reads, and (unless
 // it is the last) waits again before overwriting the buffer.
 template <typename R, int L, int E, bool INV, int NS>
-__device__ __forceinline__ void rstage(cplx<R> (&v)[E], cplx<R>* buf, const cplx<R>* __restrict__ tw, int t) {
+__device__ __forceinline__ void rstage(cplx<R> (&v)[E], cplx<R>* buf, const Twiddles<R, L, E>& tws, int t) {
   constexpr int TPL = L / E;
   constexpr int REM = L / NS;
   constexpr int RAD = (REM >= E) ? E : REM;
   constexpr int PER = E / RAD;                  // butterflies per thread
   constexpr bool FIRST = (NS == 1);
   constexpr bool LAST = (NS * RAD == L);
-  constexpr int TWS = L / (NS * RAD);           // twiddle table stride
+  constexpr int NB = ilog2c(RAD);
   static_assert(RAD >= 2 && PER * RAD == E, "radix plan");
   cplx<R> a[PER][RAD];
-  cplx<R> wb[PER][4];
-  if constexpr (!FIRST) {
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int k = (t + p * TPL) & (NS - 1);
-      wb[p][0] = tw[k * TWS];
-      if constexpr (RAD >= 4) wb[p][1] = tw[2 * k * TWS];
-      if constexpr (RAD >= 8) wb[p][2] = tw[4 * k * TWS];
-      if constexpr (RAD >= 16) wb[p][3] = tw[8 * k * TWS];
-    }
-    __syncthreads();
-  }
+  if constexpr (!FIRST) __syncthreads();
 #pragma unroll
   for (int p = 0; p < PER; ++p)
 #pragma unroll
@@ -220,7 +268,10 @@ __device__ __forceinline__ void rstage(cplx<R> (&v)[E], cplx<R>* buf, const cplx
   if constexpr (!FIRST && !LAST) __syncthreads();
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    if constexpr (!FIRST) twiddle<R, RAD, INV>(a[p], wb[p]);
+    if constexpr (!FIRST) {
+      constexpr int OFF = tw_slots_before<L, E>(NS);
+      twiddle<R, RAD, INV>(a[p], &tws.w[OFF + p * NB]);
+    }
     dft<R, RAD, INV>(a[p]);
     if constexpr (LAST) {
 #pragma unroll
@@ -233,16 +284,17 @@ __device__ __forceinline__ void rstage(cplx<R> (&v)[E], cplx<R>* buf, const cplx
       for (int r = 0; r < RAD; ++r) buf[pidx<E>(base + r * NS)] = a[p][r];
     }
   }
-  if constexpr (!LAST) rstage<R, L, E, INV, NS * RAD>(v, buf, tw, t);
+  if constexpr (!LAST) rstage<R, L, E, INV, NS * RAD>(v, buf, tws, t);
 }
 
 // Forward (INV = false, exponent -) or unnormalised inverse (exponent +)
 // transform of the line held in v by threads t = 0..L/E-1, with buf (padded
-// length) as exchange space.  On entry no thread may still read buf; on exit
-// other threads may still read it (synchronise before writing it again).
+// length) as exchange space and the thread's base twiddles tws.  On entry no
+// thread may still read buf; on exit other threads may still read it
+// (synchronise before writing it again).
 template <typename R, int L, int E, bool INV>
-__device__ __forceinline__ void fft_regs(cplx<R> (&v)[E], cplx<R>* buf, const cplx<R>* __restrict__ tw, int t) {
-  rstage<R, L, E, INV, 1>(v, buf, tw, t);
+__device__ __forceinline__ void fft_regs(cplx<R> (&v)[E], cplx<R>* buf, const Twiddles<R, L, E>& tws, int t) {
+  rstage<R, L, E, INV, 1>(v, buf, tws, t);
 }
 
 }  // namespace gofd_fft

@@ -129,6 +129,8 @@ struct gofd_transfer_s {
   DevBuf ell_idx;    // 3D: int32[n_nodes+1], compact row of each inside node or -1
   DevBuf ell_v;      // 3D: int32[n_inside*4], vertex ids of the interpolation row
   DevBuf ell_w;      // 3D: double[n_inside*4], barycentric weights (same bits as the CSC)
+  DevBuf row32_v;    // 2D: int4[n_nodes]: vertex ids of each node's row and the bits of weight 0
+  DevBuf row32_w;    // 2D: float2[n_nodes]: weights 1 and 2 (all rounded like csc_w32; zero outside)
   std::vector<int32_t> elems_host;
   std::vector<uint8_t> bmask_host;
   std::vector<double> X_host;
@@ -157,6 +159,33 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   const int x = b % 8, i = b / 8;
   const int start = (x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
   return start + i;
+}
+
+// Global-memory view of a device pointer.  Pointers read from descriptors in
+// memory are generic to the compiler, whose loads through them become flat
+// instructions that the wave must track on two counters; through this view
+// they are global loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// Loads of 16-byte vectors through a global view (the HIP vector classes
+// cannot be copied from a qualified address space; the builtin vector types can)
+typedef int gint4_t __attribute__((ext_vector_type(4)));
+typedef double gdouble2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int4 gload(const int4* p, long long i) {
+  const gint4_t v = gmem(reinterpret_cast<const gint4_t*>(p))[i];
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 gload(const double2* p, long long i) {
+  const gdouble2_t v = gmem(reinterpret_cast<const gdouble2_t*>(p))[i];
+  return make_double2(v.x, v.y);
+}
+typedef float gfloat2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gload(const float2* p, long long i) {
+  const gfloat2_t v = gmem(reinterpret_cast<const gfloat2_t*>(p))[i];
+  return make_float2(v.x, v.y);
 }
 
 // ------------------------------------------------------------------ internal API
@@ -190,7 +219,7 @@ struct GatherSpec {
 // nrhs*W^d doubles) or a gather spec; output grid field y (double or float,
 // nrhs*W^d).  fp32 selects the single-precision pipeline.
 // passes: bit mask of the kernels to launch (1: pass A, 2: pass B, 4: pass C,
-// 8: the gather I u when g is given), 15 = all.
+// 8: the gather I u when g is given, into the operator's G workspace), 15 = all.
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g,
                void* y, bool fp32, int passes = 15);
 

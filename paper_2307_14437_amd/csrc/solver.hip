@@ -224,64 +224,57 @@ __global__ __launch_bounds__(BS) void k_scatter_cg(const CgItem* __restrict__ it
                                                    double* __restrict__ u, int per, double* __restrict__ partG,
                                                    double* __restrict__ partR) {
   constexpr int VPB = BS / G;                 // vertices per block pass
+  constexpr int U = G >= 16 ? 4 : 64 / G;     // entries per lane loaded together (64 per vertex)
   __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
   const int it = blockIdx.y;
   const CgItem& I = items[it];
   const long long o = I.off, nv = I.nv;
   const int dk = I.dk;
-  const int* __restrict__ off = I.csc_off;
-  const int* __restrict__ node = I.csc_node;
-  const WT* __restrict__ wts;
+  const auto off = gmem(I.csc_off);
+  const auto node = gmem(I.csc_node);
+  const auto imask = gmem(I.imask);
+  const auto dscale = gmem(I.dscale);
+  const __attribute__((address_space(1))) WT* wts;
   if constexpr (sizeof(WT) == 4)
-    wts = reinterpret_cast<const WT*>(I.csc_w32);
+    wts = gmem(reinterpret_cast<const WT*>(I.csc_w32));
   else
-    wts = reinterpret_cast<const WT*>(I.csc_w);
+    wts = gmem(reinterpret_cast<const WT*>(I.csc_w));
   const int lane = threadIdx.x % G;
   const long long g0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * per;
   const Y* yr = y + it * n_nodes;
-  // first segment bounds before the finished-rhs test, so that the loads overlap
-  const long long vf = g0 * VPB + threadIdx.x / G;
-  int f0 = 0, f1 = 0;
-  if (vf < nv) {
-    f0 = off[vf];
-    f1 = off[vf + 1];
-  }
   const Scal& S = sc[it];
-  if (S.done) return;                         // block-uniform
+  const bool done = S.done;                   // block-uniform
   const double alpha = S.alpha, beta = S.beta;
   double acc2[2] = {0.0, 0.0};                // (r, r), (r, u)
-  for (int q = 0; q < per; ++q) {
+  for (int q = 0; q < per && !done; ++q) {
+    // Every load below is unconditional, from clamped in-range indices (a
+    // vertex past the end reads the last vertex, an entry past its vertex
+    // reads entry 0 with weight zero), so that all of them can be in flight
+    // together; every lane of a vertex group reads the vertex's own vectors.
     const long long v = (g0 + q) * VPB + threadIdx.x / G;
-    double acc = 0.0;
-    double vm = 0, vs = 0, vp = 0, vu = 0, vr = 0, vx = 0, vd = 0;
-    if (v < nv) {
-      const int i0 = q == 0 ? f0 : off[v], i1 = q == 0 ? f1 : off[v + 1];
-      // the vertex's own vectors, fetched with the first entries
-      if (lane == 0) {
-        vm = I.imask[v];
-        vs = s[o + v];
-        vp = p[o + v];
-        vu = u[o + v];
-        vr = r[o + v];
-        vx = x[o + v];
-        if (dk > 0) vd = I.dscale[v];
-      }
-      int nd[4];
-      WT wt[4];
+    const bool valid = v < nv;
+    const long long vc = valid ? v : nv - 1;
+    const int i0 = off[vc], i1r = off[vc + 1];
+    const int i1 = valid ? i1r : i0;
+    const double vm = imask[vc], vs = s[o + vc], vp = p[o + vc], vu = u[o + vc], vr = r[o + vc],
+                 vx = x[o + vc], vd = dscale[vc];
+    int nd[U];
+    WT wt[U];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int i = i0 + lane + k * G;
-        nd[k] = i < i1 ? node[i] : -1;
-        wt[k] = i < i1 ? wts[i] : (WT)0;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (nd[k] >= 0) acc += (double)wt[k] * (double)yr[nd[k]];
-      for (int i = i0 + lane + 4 * G; i < i1; i += G) acc += (double)wts[i] * (double)yr[node[i]];
+    for (int k = 0; k < U; ++k) {
+      const int i = i0 + lane + k * G;
+      const int ic = i < i1 ? i : 0;
+      nd[k] = node[ic];
+      wt[k] = wts[ic];
+      if (i >= i1) wt[k] = (WT)0;
     }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) acc += (double)wt[k] * (double)yr[nd[k]];
+    for (int i = i0 + lane + U * G; i < i1; i += G) acc += (double)wts[i] * (double)yr[node[i]];
 #pragma unroll
     for (int k = G / 2; k > 0; k >>= 1) acc += __shfl_xor(acc, k, G);
-    if (lane == 0 && v < nv) {
+    if (lane == 0 && valid) {
       const double wv = vm * acc;
       const double sn = fma(beta, vs, wv);
       const double pn = fma(beta, vp, vu);
@@ -298,6 +291,7 @@ __global__ __launch_bounds__(BS) void k_scatter_cg(const CgItem* __restrict__ it
       }
     }
   }
+  if (done) return;
   block_sum_n<BS, 2>(acc2, sh);
   if (threadIdx.x == 0) {
     partR[(long long)it * gridDim.x + blockIdx.x] = acc2[0];
@@ -653,6 +647,8 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
       I.ell_idx = tr->ell_idx.as<int>();
       I.ell_v = tr->ell_v.as<int4>();
       I.ell_w = tr->ell_w.as<double2>();
+      I.row32_v = tr->row32_v.as<int4>();
+      I.row32_w = tr->row32_w.as<float2>();
       I.g.d = tr->d;
       I.g.W = tr->W;
       I.g.h = tr->h;
@@ -904,6 +900,9 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
   // residual replacement: true residual of x in double precision, then the
   // state's flags from it (reads the state back into tmp)
   std::vector<double> rr_ref(ni, HUGE_VAL);
+  // items whose stop a replacement has confirmed with the true residual: they
+  // trigger no further replacement
+  std::vector<char> settled(ni, 0);
   auto replace_residual = [&](std::vector<Scal>& tmp) -> int {
     GOFD_TRY(apply_K_plain(ctx, B, w, w.x.as<double>(), w.q.as<double>()));
     hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, ni), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
@@ -914,7 +913,10 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
     HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
-    for (int k = 0; k < ni; ++k) rr_ref[k] = tmp[k].rr;
+    for (int k = 0; k < ni; ++k) {
+      rr_ref[k] = tmp[k].rr;
+      settled[k] = tmp[k].done ? 1 : 0;
+    }
     return GOFD_OK;
   };
   // Iteration j tests x_j (its last pass) and then applies step j, so after
@@ -950,7 +952,9 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     if (replace_drop > 0.0) {
       bool need = false;
       for (int k = 0; k < ni; ++k)
-        if (tmp[k].status == ST_OK && (tmp[k].done || tmp[k].rr < replace_drop * replace_drop * rr_ref[k])) need = true;
+        if (tmp[k].status == ST_OK && !settled[k] &&
+            (tmp[k].done || tmp[k].rr < replace_drop * replace_drop * rr_ref[k]))
+          need = true;
       if (need) {
         if ((rc = replace_residual(tmp)) != GOFD_OK) break;
         if (n_replace) ++*n_replace;

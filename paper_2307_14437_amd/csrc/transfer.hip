@@ -203,6 +203,26 @@ __global__ void k_colsum(const int* __restrict__ off, long long nv, const double
   imask[v] = bmask[v] ? 0.0 : 1.0;
 }
 
+// single-precision interpolation row of every node (2D): vertex ids and the
+// weights rounded to float exactly as the I^T entries are; nodes outside the
+// mesh get vertex 0 with weight zero
+__global__ void k_fill_rows32(GridGeom g, const ElemRec2* __restrict__ recs, const int* __restrict__ elem_of_node,
+                              long long n, int4* __restrict__ rv, float2* __restrict__ rw) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int e = elem_of_node[k];
+  if (e < 0) {
+    rv[k] = make_int4(0, 0, 0, 0);
+    rw[k] = make_float2(0.f, 0.f);
+    return;
+  }
+  int vid[3];
+  double lam[3];
+  node_weights<2>(g, recs, e, k, vid, lam);
+  rv[k] = make_int4(vid[0], vid[1], vid[2], __float_as_int((float)lam[0]));
+  rw[k] = make_float2((float)lam[1], (float)lam[2]);
+}
+
 template <int D>
 __global__ void k_export_ell(GridGeom g, const ElemRec<D>* __restrict__ recs,
                              const int* __restrict__ elem_of_node, long long n, int* __restrict__ verts,
@@ -427,6 +447,13 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   GOFD_TRY(dev_reserve(ctx, tr->csc_w32, sizeof(float) * std::max<int64_t>(nnz, 1)));
   GOFD_TRY(dev_reserve(ctx, node_tmp, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
   GOFD_TRY(dev_reserve(ctx, w_tmp, sizeof(double) * std::max<int64_t>(nnz, 1)));
+  if (nnz == 0) {
+    // one zero entry (node 0, weight 0): kernels read entry 0 in place of a
+    // missing one and weight it by zero
+    HIP_TRY(ctx, hipMemsetAsync(tr->csc_node.p, 0, sizeof(int32_t), st));
+    HIP_TRY(ctx, hipMemsetAsync(tr->csc_w.p, 0, sizeof(double), st));
+    HIP_TRY(ctx, hipMemsetAsync(tr->csc_w32.p, 0, sizeof(float), st));
+  }
   HIP_TRY(ctx, hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nv + 1), st));
   if (d == 2)
     hipLaunchKernelGGL(k_count<2>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
@@ -451,6 +478,11 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
     GOFD_TRY(dev_reserve(ctx, tr->ell_idx, sizeof(int32_t) * (n_nodes + 1)));
     GOFD_TRY(dev_reserve(ctx, tr->ell_v, sizeof(int32_t) * 4 * std::max<int64_t>(n_inside, 1)));
     GOFD_TRY(dev_reserve(ctx, tr->ell_w, sizeof(double) * 4 * std::max<int64_t>(n_inside, 1)));
+    if (n_inside == 0) {
+      // one zero row (vertex 0, weights 0), read in place of a missing one
+      HIP_TRY(ctx, hipMemsetAsync(tr->ell_v.p, 0, sizeof(int32_t) * 4, st));
+      HIP_TRY(ctx, hipMemsetAsync(tr->ell_w.p, 0, sizeof(double) * 4, st));
+    }
     DevBuf flag;
     GOFD_TRY(dev_reserve(ctx, flag, sizeof(int32_t) * (n_nodes + 1)));
     hipLaunchKernelGGL(k_inside_flag, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
@@ -460,6 +492,12 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
                        tr->elem.as<int>(), (long long)n_nodes, tr->ell_idx.as<int>(), tr->ell_v.as<int>(),
                        tr->ell_w.as<double>());
     HIP_TRY(ctx, hipStreamSynchronize(st));
+  }
+  if (d == 2) {
+    GOFD_TRY(dev_reserve(ctx, tr->row32_v, sizeof(int4) * n_nodes));
+    GOFD_TRY(dev_reserve(ctx, tr->row32_w, sizeof(float2) * n_nodes));
+    hipLaunchKernelGGL(k_fill_rows32, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec2>(),
+                       tr->elem.as<int>(), (long long)n_nodes, tr->row32_v.as<int4>(), tr->row32_w.as<float2>());
   }
   GOFD_TRY(dev_reserve(ctx, tr->D, sizeof(double) * nv));
   GOFD_TRY(dev_reserve(ctx, tr->dscale, sizeof(double) * nv));

@@ -25,12 +25,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 # stage of a CG iteration -> kernel symbol fragment (single-precision grid, 2D, L = 2048)
-STAGE_SYMBOLS = {
-    "gather": "k_gather<float, 2>",
-    "passA": "k_passA<float, 2048",
-    "passB": "k_passB<float, 2048, 16, 2, true>",
-    "passC": "k_passC<float, float, 2048",
-    "scatter": "k_scatter_cg<float, float",
+STAGE_SYMBOLS = {   # fragments that together name the kernel of each stage
+    "gather": ("k_gather_items<float, 2>",),
+    "passA": ("k_passA<float, 2048",),
+    "passB": ("k_passB<float, 2048, 16, 2, true>",),
+    "passC": ("k_passC<float, float, 2048",),
+    "scatter": ("k_scatter_cg<float, float",),
 }
 
 
@@ -60,7 +60,7 @@ def main(argv):
     kw = copy_bytes / (sum(Wc[copy]) / len(Wc[copy]) * 1024)      # the same for WRITE_SIZE
     stages = {}
     for st, frag in STAGE_SYMBOLS.items():
-        names = [k for k in F if frag in k]
+        names = [k for k in F if all(f in k for f in frag)]
         if not names:
             continue
         k = names[0]

@@ -71,3 +71,26 @@ def test_batched_item_matches_oracle(gctx):
     uref[otr.J] = osolve.solve_dense(K, operator.rhs_grid(otr, p["s"], p["f"][0]))
     u = us[1].cpu().numpy()
     assert np.linalg.norm(u - uref) <= 1e-10 * np.linalg.norm(uref)
+
+
+def test_batched_fp32_replacement_count(gctx):
+    # residual replacements are batch events; an item whose stop a replacement
+    # has confirmed triggers no more of them while the others continue
+    import torch
+    import paper_2307_14437_amd as gofd
+    m = star_mesh(31, 900)
+    g = grid_for_box(2, 64, R=1.6)
+    tr = gofd.Transfer(gctx, _dev(m.X), _dev(m.elems, torch.int32), g)
+    ops = [gofd.FdOp(gctx, s, g, M=512) for s in (0.2, 0.8)]
+    pcs = [gofd.Precond(gctx, tr, op, "NONE") for op in ops]
+    f = _dev(fourier_rhs(7, g)[None, :])
+    tol, drop = 1e-10, 0.1
+    us, infos = gofd.solve_batched(gctx, [tr, tr], ops, pcs, [f, f], tol=tol, mode=gofd.MODE_FP32_RELIABLE,
+                                   inner_tol=drop)
+    print(infos, flush=True)
+    it = sorted(i["iterations"] for i in infos)
+    assert it[1] >= it[0] + 20                  # the fast item stops well before the slow one
+    for i in infos:
+        assert i["status"] == 0 and i["rel_residual"] <= tol
+        # (r, r) falls by tol^2 overall, drop^2 per replacement, plus one at each item's stop
+        assert i["refinements"] <= round(np.log(tol) / np.log(drop)) + 4

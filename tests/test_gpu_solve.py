@@ -217,3 +217,4 @@ def test_stage_timing_reports_every_stage(gctx, c1_setup):
     assert np.all(st[:5] > 0) and np.all(st[:5] < 10.0) and st[5] == 0.0
     assert i1[0]["iterations"] == i0[0]["iterations"]                  # same iterates without the graph
     assert np.array_equal(u0.cpu().numpy(), u1.cpu().numpy())
+
