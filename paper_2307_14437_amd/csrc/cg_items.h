@@ -25,6 +25,13 @@ struct CgItem {
   const double2* ell_w;       // 3D: weights of the rows
   const int4* row32_v;        // 2D: per-node vertex ids (and weight 0) for the FP32 gather
   const float2* row32_w;      // 2D: per-node weights 1 and 2 for the FP32 gather
+  const int* rp_meta;         // 2D row-pair form of I^T (int4 per row pair), or null
+  const int* rp_tseg;
+  const unsigned short* rp_code;
+  const float* rp_w32;
+  const double* rp_w64;
+  const int* rp_dest;
+  const int* pv_off;          // partial slots of each vertex
   GridGeom g;
   long long nv;               // vertices of the mesh
   long long off;              // offset of the item's vectors in the batch vectors

@@ -395,7 +395,7 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passA(Src src, cplx<R>* __res
 // (K u, u) of CG when v = I u, and the sums of its slice of the level-1
 // partials of gamma and (r, r): dpart[rhs][q][block], q = gamma, (r, r), delta.
 template <typename R, int L, int E, int LB, bool DOT>
-__global__ __launch_bounds__(LB*(L / E), 2) void k_passB(cplx<R>* __restrict__ Z, int W, int half,
+__global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_passB(cplx<R>* __restrict__ Z, int W, int half,
                                                       const R* That, const cplx<R>* __restrict__ tw,
                                                       long long zs, Skip skip, double* __restrict__ dpart,
                                                       gofd_cg::Level1 lv1, const void* const* __restrict__ that_tab) {
@@ -514,17 +514,34 @@ __global__ __launch_bounds__(LB*(L / E), 2) void k_passB(cplx<R>* __restrict__ Z
 // With fin active, one extra block (the last) finishes the CG reductions of
 // the iteration instead (the step's scalars are needed only by later
 // kernels), concurrently with the transforms.
-template <typename R, typename Y, int L, int E, int LINES>
-__global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restrict__ Z, int W,
+//
+// With SCAT (2D CG iteration, row-pair form of I^T present for the item), the
+// block does not write y: it sums, for each segment of its row pair (the
+// entries of one vertex in these two rows), weight times y over the
+// segment's entries and writes the sum to the segment's partial slot.  The
+// entries, in the thread-interleaved layout of the transfer, are fetched at
+// the start so that they arrive during the transform.
+struct RowScatter {
+  const CgItem* items;     // per-item row-pair arrays
+  double* P;               // partial slots, item it at it * pstride
+  long long pstride;
+  int ent_max;             // most entries per thread of a row pair
+};
+template <typename R, typename Y, int L, int E, int LINES, bool SCAT, int EPRE = 1>
+__global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (sizeof(R) == 4 ? 3 : 2) : 1) void k_passC(const cplx<R>* __restrict__ Z, int W,
                                                          const cplx<R>* __restrict__ tw, long long zs,
                                                          Y* __restrict__ y, long long n_nodes, Skip skip,
-                                                         gofd_cg::Finish fin) {
+                                                         gofd_cg::Finish fin, RowScatter rs) {
   constexpr int TPL = L / E;
   constexpr int PL = padded_len<L, E>();
   constexpr int H = L / 2;
   constexpr int NT = LINES * TPL;
+  constexpr int SEGL = RP_SEGCAP / LINES;                  // segment sums per row pair
+  constexpr int QD = (SEGL + TPL - 1) / TPL;               // segments per thread in the write-out
+  static_assert(2 * (L / 2 + 1) <= 2 * PL, "row pair fits the exchange buffer");
   __shared__ cplx<R> sbuf[LINES * PL];
   __shared__ double shf[gofd_cg::block_sum_lds<NT, 3>()];
+  __shared__ double segs[SCAT ? RP_SEGCAP : 1];
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
   const int nrb = gridDim.x - (fin.sc ? 1 : 0);                            // row-pair blocks
@@ -560,8 +577,102 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restri
   }
   gofd_fft::Twiddles<R, L, E> tws;
   tws.load(tw, t);
+  // row-pair I^T: this thread's entries and the row pair's segment slots
+  int4 meta = make_int4(0, 0, 0, 0);
+  int tseg = 0;
+  int code[SCAT ? EPRE : 1];
+  R wt[SCAT ? EPRE : 1];
+  int dst[SCAT ? QD : 1];
+  const unsigned short* gcode = nullptr;
+  const R* gw = nullptr;
+  if constexpr (SCAT) {
+    const CgItem& I = rs.items[rhs];
+    const int rp = has0 ? row0 / 2 : 0;
+    meta = gload(reinterpret_cast<const int4*>(I.rp_meta), rp);
+    if (!has0) meta = make_int4(0, 0, 0, 0);
+    if constexpr (LINES == 1) {                // one row pair per block: its descriptor is uniform
+      meta.x = __builtin_amdgcn_readfirstlane(meta.x);
+      meta.y = __builtin_amdgcn_readfirstlane(meta.y);
+      meta.z = __builtin_amdgcn_readfirstlane(meta.z);
+      meta.w = __builtin_amdgcn_readfirstlane(meta.w);
+    }
+    tseg = gmem(I.rp_tseg)[(long long)rp * TPL + t];
+    // entries m < EPRE of this thread, read ahead past its count ENT (meta.y;
+    // the arrays carry RP_EPRE * TPL padding entries at the end, so the reads
+    // stay in range); the extra ones become padding (node 0, weight 0).  The
+    // launch picks EPRE from the transfer's largest ENT.
+    gcode = I.rp_code + meta.x + t;
+    if constexpr (sizeof(R) == 4)
+      gw = reinterpret_cast<const R*>(I.rp_w32) + meta.x + t;
+    else
+      gw = reinterpret_cast<const R*>(I.rp_w64) + meta.x + t;
+#pragma unroll
+    for (int m = 0; m < EPRE; ++m) {
+      code[m] = gmem(gcode)[m * TPL];
+      wt[m] = gmem(gw)[m * TPL];
+    }
+#pragma unroll
+    for (int m = 0; m < EPRE; ++m)
+      if (m >= meta.y) {
+        code[m] = 0;
+        wt[m] = (R)0;
+      }
+#pragma unroll
+    for (int q = 0; q < QD; ++q) {
+      const int i = t + q * TPL;
+      dst[q] = gmem(I.rp_dest)[i < meta.w ? meta.z + i : 0];
+    }
+  }
   if (skip(rhs)) return;
   fft_regs<R, L, E, true>(v, buf, tws, t);
+  if constexpr (SCAT) {
+    // the row pair's values into the exchange buffer (after every thread has
+    // left the transform), then the segment sums (every thread reaches the
+    // barriers: a line without rows has no entries)
+    R* yl = reinterpret_cast<R*>(buf);
+    double* sg = segs + line * SEGL;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m <= E / 2; ++m) {
+      const int col = t + m * TPL;
+      if (col < W) {
+        yl[col] = v[m].x;
+        yl[W + col] = v[m].y;
+      }
+    }
+    __syncthreads();
+    // every node value first, then the sums in entry order: a segment's sum
+    // is stored at its last entry (a predicated store, no branch around loads)
+    R yv[EPRE];
+#pragma unroll
+    for (int m = 0; m < EPRE; ++m) yv[m] = yl[code[m] & RP_NODE];
+    double acc = 0.0;
+    int j = tseg;
+#pragma unroll
+    for (int m = 0; m < EPRE; ++m) {
+      acc += (double)wt[m] * (double)yv[m];
+      const bool end = (code[m] & RP_END) != 0;
+      if (end) sg[j] = acc;
+      j += end ? 1 : 0;
+      acc = end ? 0.0 : acc;
+    }
+    for (int m = EPRE; m < meta.y; ++m) {      // rows pairs with more entries per thread
+      const int c = gmem(gcode)[(long long)m * TPL];
+      acc += (double)gmem(gw)[(long long)m * TPL] * (double)yl[c & RP_NODE];
+      if (c & RP_END) {
+        sg[j++] = acc;
+        acc = 0.0;
+      }
+    }
+    __syncthreads();
+    double* P = rs.P + rhs * rs.pstride;
+#pragma unroll
+    for (int q = 0; q < QD; ++q) {
+      const int i = t + q * TPL;
+      if (i < meta.w) P[dst[q]] = sg[i];
+    }
+    return;
+  }
   if (!has0) return;
   Y* yr = y + rhs * n_nodes + (long long)row0 * W;
 #pragma unroll
@@ -579,7 +690,7 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passC(const cplx<R>* __restri
 // Values per thread of the row passes (A, C) and of the column pass (B):
 // build-time tuning knobs, powers of two in 4..16.
 #ifndef GOFD_FFT_E_ROWS
-#define GOFD_FFT_E_ROWS 16
+#define GOFD_FFT_E_ROWS 8
 #endif
 #ifndef GOFD_FFT_E_COLS
 #define GOFD_FFT_E_COLS 16
@@ -608,7 +719,8 @@ struct Cfg {
 
 template <typename R, int L, class Src, typename Y>
 int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
-           double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab) {
+           double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab,
+           const RowScatter& rs) {
   const int W = op->W, half = op->half;
   const long long zs = (long long)W * (L / 2);
   const cplx<R>* tw;
@@ -637,9 +749,22 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   else if (passes & 2)
     GOFD_LAUNCH(ctx, (k_passB<R, L, C::EB, C::LB, false>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
                        st, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab);
-  if (passes & 4)
-    GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A>), dim3(nbA + (fin.sc ? 1 : 0), nrhs), dim3(C::LINES_A * C::TA), 0, st, Z,
-                       W, tw, zs, y, (long long)W * W, skip, fin);
+  if ((passes & 4) && rs.items) {
+    // entries read ahead per thread: the first of 16, 24, 32 that covers the
+    // transfer's largest count (more run in a loop)
+    const dim3 gC(nbA + (fin.sc ? 1 : 0), nrhs), bC(C::LINES_A * C::TA);
+    if (rs.ent_max <= 16)
+      GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A, true, 16>), gC, bC, 0, st, Z, W, tw, zs, y,
+                  (long long)W * W, skip, fin, rs);
+    else if (rs.ent_max <= 24)
+      GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A, true, 24>), gC, bC, 0, st, Z, W, tw, zs, y,
+                  (long long)W * W, skip, fin, rs);
+    else
+      GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A, true, 32>), gC, bC, 0, st, Z, W, tw, zs, y,
+                  (long long)W * W, skip, fin, rs);
+  } else if (passes & 4)
+    GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A, false>), dim3(nbA + (fin.sc ? 1 : 0), nrhs),
+                dim3(C::LINES_A * C::TA), 0, st, Z, W, tw, zs, y, (long long)W * W, skip, fin, rs);
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
 }
@@ -647,18 +772,19 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
 template <typename R, class Src, typename Y>
 int dispatch_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
                 double* dpart = nullptr, const gofd_cg::Level1& lv1 = gofd_cg::Level1(),
-                const gofd_cg::Finish& fin = gofd_cg::Finish(), const void* const* that_tab = nullptr) {
+                const gofd_cg::Finish& fin = gofd_cg::Finish(), const void* const* that_tab = nullptr,
+                const RowScatter& rs = RowScatter{}) {
   switch (op->L) {
-    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 8: return run_2d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 16: return run_2d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 32: return run_2d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 64: return run_2d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 128: return run_2d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 256: return run_2d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 512: return run_2d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 1024: return run_2d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 2048: return run_2d<R, 2048>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
+    case 4096: return run_2d<R, 4096>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab, rs);
     default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "FFT length " + std::to_string(op->L) + " not built");
   }
 }
@@ -819,12 +945,15 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   if (d == 3)
     return conv3_run(ctx, op, nrhs, fp32 ? nullptr : op->G.as<double>(), fp32 ? op->G.as<float>() : nullptr, y, fp32,
                      passes & 7, skip.flag, skip.stride, dpart, lv1, fin, that_tab);
+  const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_max};
   if (fp32) {
     SrcPairGrid<float> src{op->G.as<float>(), nn};
-    return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab);
+    return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab,
+                              rs);
   }
   SrcPairGrid<double> src{op->G.as<double>(), nn};
-  return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin, that_tab);
+  return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin, that_tab,
+                             rs);
 }
 
 template <typename R>
@@ -905,6 +1034,18 @@ static int next_pow2(long long x) {
   return p;
 }
 
+int conv_period(int N) { return std::max(8, next_pow2(4LL * N)); }
+
+int conv_rowpass_threads(int L) {
+  const int E = std::min(GOFD_FFT_E_ROWS, L);
+  return L / E;
+}
+
+int conv_rowpass_lines(int L) {
+  const int T = conv_rowpass_threads(L);
+  return T >= 64 ? 1 : 64 / T;
+}
+
 int fdop_init_geometry(gofd_ctx_s* ctx, gofd_fdop_s* op, double s, const gofd_grid* grid) {
   if (!grid || (grid->d != 2 && grid->d != 3) || grid->N < 1 || !(grid->R > 0))
     return gofd_fail(ctx, GOFD_E_ARG, "bad grid");
@@ -913,7 +1054,7 @@ int fdop_init_geometry(gofd_ctx_s* ctx, gofd_fdop_s* op, double s, const gofd_gr
   op->d = grid->d;
   op->N = grid->N;
   op->W = 2 * grid->N + 1;
-  op->L = std::max(8, next_pow2(4LL * grid->N));     // L >= 4N keeps the embedding exact (R7); 8 is the smallest built
+  op->L = conv_period(grid->N);     // L >= 4N keeps the embedding exact (R7); 8 is the smallest built
   op->half = op->L / 2 + 1;
   op->s = s;
   op->R = grid->R;

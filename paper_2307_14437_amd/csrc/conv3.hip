@@ -153,7 +153,7 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3BD(cplx<R>* __restrict__ Z1, c
 // 0 < k0 < L/2 count twice) and the sums of its slice of the level-1
 // partials: dpart[rhs][q][block], q = gamma, (r, r), delta.
 template <typename R, int L, int E, int LB, bool DOT>
-__global__ __launch_bounds__(LB*(L / E), 2) void k_p3C(cplx<R>* __restrict__ Z2, int W, int half, int nsb,
+__global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p3C(cplx<R>* __restrict__ Z2, int W, int half, int nsb,
                                                      const R* That, const cplx<R>* __restrict__ tw,
                                                      long long z2s, Skip skip, double* __restrict__ dpart,
                                                      gofd_cg::Level1 lv1, const void* const* __restrict__ that_tab) {

@@ -131,6 +131,18 @@ struct gofd_transfer_s {
   DevBuf ell_w;      // 3D: double[n_inside*4], barycentric weights (same bits as the CSC)
   DevBuf row32_v;    // 2D: int4[n_nodes]: vertex ids of each node's row and the bits of weight 0
   DevBuf row32_w;    // 2D: float2[n_nodes]: weights 1 and 2 (all rounded like csc_w32; zero outside)
+  // 2D row-pair form of I^T (the last row pass sums each vertex's entries in
+  // its rows; see build_rowpairs): present when rp_ok
+  bool rp_ok = false;
+  int64_t n_slots = 0;  // partial sums: one per (vertex, row pair) with entries
+  int rp_ent_max = 0;   // most entries of a thread in a row pair
+  DevBuf rp_meta;    // int4[pairs]: entry base, entries per thread, segment base, segments
+  DevBuf rp_tseg;    // int32[pairs * threads]: first segment of each thread
+  DevBuf rp_code;    // uint16[...]: local node (2 rows) | end-of-segment flag, thread-interleaved
+  DevBuf rp_w32;     // float[...]: weights (csc_w32 values), same layout
+  DevBuf rp_w64;     // double[...]: weights (csc_w values)
+  DevBuf rp_dest;    // int32[segments]: partial slot of each segment (vertex-major)
+  DevBuf pv_off;     // int32[nv + 1]: partial slots of each vertex
   std::vector<int32_t> elems_host;
   std::vector<uint8_t> bmask_host;
   std::vector<double> X_host;
@@ -213,6 +225,12 @@ struct GatherSpec {
   bool items_mask = false;             // multiply by the item's interior mask
   const void* const* that64_tab = nullptr;   // per-item spectrum of the embedded kernel (device tables)
   const void* const* that32_tab = nullptr;
+  // 2D batches whose transfers have the row-pair form of I^T: pass C sums
+  // the segments into the partial slots (item it at rp_P + it * rp_pstride)
+  // instead of writing the grid field
+  double* rp_P = nullptr;
+  long long rp_pstride = 0;
+  int rp_ent_max = 0;                  // most entries per thread of a row pair (all items)
 };
 
 // Apply A_FD with the FFT embedding: input either a grid field (v != nullptr,
@@ -220,6 +238,20 @@ struct GatherSpec {
 // nrhs*W^d).  fp32 selects the single-precision pipeline.
 // passes: bit mask of the kernels to launch (1: pass A, 2: pass B, 4: pass C,
 // 8: the gather I u when g is given, into the operator's G workspace), 15 = all.
+// FFT period of the embedding for a grid of half-width N, and the threads
+// and row pairs per block of the row passes for period L
+int conv_period(int N);
+int conv_rowpass_threads(int L);
+int conv_rowpass_lines(int L);
+// Row-pair I^T form: capacity (doubles) of the per-block segment sums;
+// entries per thread the last row pass fetches ahead (the entry arrays carry
+// that many rows of padding); 16-bit entry code: local node in the low 15
+// bits, RP_END on the last entry of a segment (padding: node 0, weight 0)
+constexpr int RP_SEGCAP = 1024;
+constexpr int RP_EPRE = 32;
+constexpr int RP_NODE = 0x7fff;
+constexpr int RP_END = 0x8000;
+
 int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, const GatherSpec* g,
                void* y, bool fp32, int passes = 15);
 

@@ -299,6 +299,68 @@ __global__ __launch_bounds__(BS) void k_scatter_cg(const CgItem* __restrict__ it
   }
 }
 
+// The same step with w = mask * I^T y from the partial slots of the row-pair
+// form (pass C left the sum of each vertex's entries in each row pair): one
+// vertex per thread adds its slots in order.  Item blockIdx.y.
+__global__ __launch_bounds__(BS) void k_vertex_cg(const CgItem* __restrict__ items, const double* __restrict__ P,
+                                                  long long pstride, const Scal* __restrict__ sc,
+                                                  double* __restrict__ x, double* __restrict__ p,
+                                                  double* __restrict__ s, double* __restrict__ r,
+                                                  double* __restrict__ u, double* __restrict__ partG,
+                                                  double* __restrict__ partR) {
+  constexpr int PU = 8;                       // slots loaded together
+  __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  const long long o = I.off, nv = I.nv;
+  const int dk = I.dk;
+  const auto pv = gmem(I.pv_off);
+  const auto imask = gmem(I.imask);
+  const auto dscale = gmem(I.dscale);
+  const auto Pi = gmem(P + it * pstride);
+  const Scal& S = sc[it];
+  if (S.done) return;                         // block-uniform
+  const double alpha = S.alpha, beta = S.beta;
+  // loads from clamped in-range positions (all in flight together)
+  const long long v = (long long)xcd_remap(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+  const bool valid = v < nv;
+  const long long vc = valid ? v : nv - 1;
+  const int a = pv[vc], br = pv[vc + 1];
+  const int b = valid ? br : a;
+  const double vm = imask[vc], vs = s[o + vc], vp = p[o + vc], vu = u[o + vc], vr = r[o + vc], vx = x[o + vc],
+               vd = dscale[vc];
+  double pp[PU];
+#pragma unroll
+  for (int k = 0; k < PU; ++k) pp[k] = Pi[a + k < b ? a + k : 0];
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < PU; ++k)
+    if (a + k < b) acc += pp[k];
+  for (int i = a + PU; i < b; ++i) acc += Pi[i];
+  double acc2[2] = {0.0, 0.0};                // (r, r), (r, u)
+  if (valid) {
+    const double wv = vm * acc;
+    const double sn = fma(beta, vs, wv);
+    const double pn = fma(beta, vp, vu);
+    const double rn = fma(-alpha, sn, vr);
+    s[o + v] = sn;
+    p[o + v] = pn;
+    x[o + v] = fma(alpha, pn, vx);
+    r[o + v] = rn;
+    acc2[0] = rn * rn;
+    if (dk >= 0) {
+      const double un = dk ? rn * vd : rn;
+      u[o + v] = un;
+      acc2[1] = rn * un;
+    }
+  }
+  block_sum_n<BS, 2>(acc2, sh);
+  if (threadIdx.x == 0) {
+    partR[(long long)it * gridDim.x + blockIdx.x] = acc2[0];
+    if (dk >= 0) partG[(long long)it * gridDim.x + blockIdx.x] = acc2[1];
+  }
+}
+
 // r = b - q (q = K x), partials of (r, r) and (b, b); used by the refinement
 // loop (FP64 residual).  Item blockIdx.y.
 __global__ __launch_bounds__(BS) void k_residual(const CgItem* __restrict__ items, const double* __restrict__ b,
@@ -616,6 +678,9 @@ struct Batch {
   int nitems = 0;
   long long ntot = 0, nv_max = 0;
   bool any_ic = false;
+  bool rp = true;                  // every transfer has the row-pair form of I^T
+  long long slots_max = 0;         // most partial slots of an item
+  int rp_ent_max = 0;              // most entries per thread of a row pair
   gofd_fdop_s* op0 = nullptr;      // shape and FFT workspaces of the batch
   DevBuf items, tab64, tab32;      // CgItem[nitems]; spectrum pointer tables
 };
@@ -634,6 +699,9 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
     B.pitem.push_back((int)h.size());
     B.any_ic = B.any_ic || is_ic(P.pc);
     B.nv_max = std::max<long long>(B.nv_max, tr->nv);
+    B.rp = B.rp && tr->rp_ok;
+    B.slots_max = std::max<long long>(B.slots_max, tr->n_slots);
+    B.rp_ent_max = std::max(B.rp_ent_max, tr->rp_ent_max);
     for (int k = 0; k < P.nrhs; ++k) {
       CgItem I{};
       I.csc_off = tr->csc_off.as<int>();
@@ -649,6 +717,15 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
       I.ell_w = tr->ell_w.as<double2>();
       I.row32_v = tr->row32_v.as<int4>();
       I.row32_w = tr->row32_w.as<float2>();
+      if (tr->rp_ok) {
+        I.rp_meta = tr->rp_meta.as<int>();
+        I.rp_tseg = tr->rp_tseg.as<int>();
+        I.rp_code = tr->rp_code.as<unsigned short>();
+        I.rp_w32 = tr->rp_w32.as<float>();
+        I.rp_w64 = tr->rp_w64.as<double>();
+        I.rp_dest = tr->rp_dest.as<int>();
+        I.pv_off = tr->pv_off.as<int>();
+      }
       I.g.d = tr->d;
       I.g.W = tr->W;
       I.g.h = tr->h;
@@ -679,6 +756,7 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
 
 struct Work {
   DevBuf x, r, u, p, s, b, xr, dvec, q, grid;
+  DevBuf P;                     // row-pair form: partial slots, double[nitems][slots_max]
   DevBuf scal;                  // Scal[nitems]
   DevBuf partG, partR;          // double[nitems][nbs]: gamma and (r, r) partials
   DevBuf partD;                 // double[nitems][3][pass-B blocks]: partials summed by the column pass
@@ -695,9 +773,16 @@ int reserve_work(gofd_ctx_s* ctx, Work& w, const Batch& B) {
   const int ni = B.nitems;
   GOFD_TRY(dev_reserve(ctx, w.grid, sizeof(double) * nn * ni));
   GOFD_TRY(dev_reserve(ctx, w.scal, sizeof(Scal) * ni));
-  const long long groups = (B.nv_max + BS / SCAT_G - 1) / (BS / SCAT_G);
-  w.per = (int)std::max<long long>(1, (groups + MAX_SC - 1) / MAX_SC);
-  w.nbs = (int)std::max<long long>(1, (groups + w.per - 1) / w.per);
+  if (B.rp) {
+    // vertex kernel: one vertex per thread
+    GOFD_TRY(dev_reserve(ctx, w.P, sizeof(double) * std::max<long long>(B.slots_max, 1) * ni));
+    w.per = 1;
+    w.nbs = (int)std::max<long long>(1, (B.nv_max + BS - 1) / BS);
+  } else {
+    const long long groups = (B.nv_max + BS / SCAT_G - 1) / (BS / SCAT_G);
+    w.per = (int)std::max<long long>(1, (groups + MAX_SC - 1) / MAX_SC);
+    w.nbs = (int)std::max<long long>(1, (groups + w.per - 1) / w.per);
+  }
   GOFD_TRY(dev_reserve(ctx, w.partG, sizeof(double) * w.nbs * ni));
   GOFD_TRY(dev_reserve(ctx, w.partR, sizeof(double) * w.nbs * ni));
   GOFD_TRY(dev_reserve(ctx, w.partials, sizeof(double) * 2 * NB_DOT * ni));
@@ -795,6 +880,11 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
   g.fin.sc = w.scal.as<Scal>();
   g.fin.part = w.partD.as<double>();
   g.fin.nb = conv_passB_blocks(B.op0, fp32);
+  if (B.rp) {
+    g.rp_P = w.P.as<double>();
+    g.rp_pstride = std::max<long long>(B.slots_max, 1);
+    g.rp_ent_max = B.rp_ent_max;
+  }
   if (prof) {
     // the same launches one stage at a time, each kernel recording its own
     // start and end events
@@ -815,7 +905,11 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
 #define GOFD_SCATTER_ARGS(Y)                                                                                     \
   B.items.as<CgItem>(), Y, nn, w.scal.as<Scal>(), w.x.as<double>(), w.p.as<double>(), w.s.as<double>(),          \
       w.r.as<double>(), w.u.as<double>(), w.per, w.partG.as<double>(), w.partR.as<double>()
-  if (fp32)
+  if (B.rp)
+    GOFD_LAUNCH(ctx, k_vertex_cg, gs, dim3(BS), 0, st, B.items.as<CgItem>(), w.P.as<double>(), g.rp_pstride,
+                w.scal.as<Scal>(), w.x.as<double>(), w.p.as<double>(), w.s.as<double>(), w.r.as<double>(),
+                w.u.as<double>(), w.partG.as<double>(), w.partR.as<double>());
+  else if (fp32)
     GOFD_LAUNCH(ctx, (k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st, GOFD_SCATTER_ARGS(w.grid.as<float>()));
   else
     GOFD_LAUNCH(ctx, (k_scatter_cg<double, double, SCAT_G>), gs, dim3(BS), 0, st,

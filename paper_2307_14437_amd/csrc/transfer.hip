@@ -353,6 +353,152 @@ static double min_height(int d, const std::vector<double>& X, const std::vector<
 
 // ---------------------------------------------------------------- ABI
 
+// ---------------------------------------------------------------- row-pair form of I^T (2D)
+//
+// The CG iteration forms (I^T y)_j = sum_k lambda_j(k) y_k inside the last
+// row pass, which holds two rows of y at a time: for each row pair the
+// entries (j, k) of the rows' nodes are grouped by vertex into segments, each
+// segment's sum goes to one partial slot of its vertex (slots of a vertex are
+// contiguous, in row-pair order), and a vertex kernel adds its partials.
+// The sums run in a fixed order, so results are reproducible.
+//
+// Layout for the row pass (T threads per row pair, as it is launched): the
+// segments of a row pair, in vertex order, are split into T contiguous runs
+// of about equal entry count; thread t's entries are stored at
+// base + m T + t (m = 0..ENT-1, padded with zero weights), each with its
+// local node (row offset times W plus column) and a flag on the last entry
+// of each segment.  Leaves rp_ok false (nothing built) when a row pair has
+// more segments than a block can hold.
+static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vector<int32_t>& offh) {
+  hipStream_t st = ctx->stream;
+  tr->rp_ok = false;
+  if (tr->d != 2 || tr->nnz == 0) return GOFD_OK;
+  const int64_t nv = tr->nv, nnz = tr->nnz;
+  const int W = tr->W;
+  const int L = conv_period(tr->N);
+  const int T = conv_rowpass_threads(L);
+  const int lines = conv_rowpass_lines(L);
+  const int pairs = (W + 1) / 2;
+  std::vector<int32_t> node(nnz);
+  std::vector<double> wv(nnz);
+  HIP_TRY(ctx, hipMemcpyAsync(node.data(), tr->csc_node.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipMemcpyAsync(wv.data(), tr->csc_w.p, sizeof(double) * nnz, hipMemcpyDeviceToHost, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  // segments: runs of a vertex's entries (sorted by node) within one row
+  // pair; numbered vertex-major, which makes a segment's number its slot
+  std::vector<int32_t> seg_rp, seg_a, seg_b;
+  std::vector<int32_t> pv(nv + 1, 0);
+  for (int64_t v = 0; v < nv; ++v) {
+    int32_t i = offh[v];
+    while (i < offh[v + 1]) {
+      const int rp = (node[i] / W) / 2;
+      int32_t j = i + 1;
+      while (j < offh[v + 1] && (node[j] / W) / 2 == rp) ++j;
+      seg_rp.push_back(rp);
+      seg_a.push_back(i);
+      seg_b.push_back(j);
+      i = j;
+    }
+    pv[v + 1] = (int32_t)seg_rp.size();
+  }
+  const int64_t nseg = (int64_t)seg_rp.size();
+  // segments of each row pair, in vertex order
+  std::vector<int32_t> rp_cnt(pairs + 1, 0);
+  for (int64_t q = 0; q < nseg; ++q) ++rp_cnt[seg_rp[q] + 1];
+  for (int r = 0; r < pairs; ++r) {
+    if (rp_cnt[r + 1] > RP_SEGCAP / lines) return GOFD_OK;     // too many for a block: keep the CSC form
+    rp_cnt[r + 1] += rp_cnt[r];
+  }
+  std::vector<int32_t> dest(nseg), fill(rp_cnt.begin(), rp_cnt.end() - 1);
+  for (int64_t q = 0; q < nseg; ++q) dest[fill[seg_rp[q]]++] = (int32_t)q;
+  // per row pair: a balanced contiguous split over the T threads
+  if (2 * (int64_t)W > RP_NODE + 1) return GOFD_OK;        // local node numbers must fit the 15-bit code
+  // per row pair: segments over the T threads by longest-first onto the
+  // least-loaded thread (ties: the lower thread), then laid out thread by
+  // thread, each thread's in vertex order
+  std::vector<int32_t> meta(4 * (size_t)pairs), tseg((size_t)pairs * T), load(T), order, perm;
+  std::vector<std::vector<int32_t>> owned(T);
+  std::vector<uint16_t> code;
+  std::vector<float> w32;
+  std::vector<double> w64;
+  int64_t ebase = 0;
+  int ent_max = 0;
+  for (int r = 0; r < pairs; ++r) {
+    const int32_t s0 = rp_cnt[r], s1 = rp_cnt[r + 1];
+    auto len = [&](int32_t p) { return seg_b[dest[p]] - seg_a[dest[p]]; };
+    order.resize(s1 - s0);
+    for (int32_t p = s0; p < s1; ++p) order[p - s0] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return len(x) > len(y); });
+    std::fill(load.begin(), load.end(), 0);
+    for (auto& o : owned) o.clear();
+    for (int32_t p : order) {
+      int k = 0;
+      for (int c = 1; c < T; ++c)
+        if (load[c] < load[k]) k = c;
+      load[k] += len(p);
+      owned[k].push_back(p);
+    }
+    perm.clear();
+    int32_t ent = 0;
+    for (int k = 0; k < T; ++k) {
+      std::sort(owned[k].begin(), owned[k].end());
+      tseg[(size_t)r * T + k] = (int32_t)perm.size();
+      perm.insert(perm.end(), owned[k].begin(), owned[k].end());
+      ent = std::max(ent, load[k]);
+    }
+    ent_max = std::max(ent_max, ent);
+    meta[4 * (size_t)r + 0] = (int32_t)ebase;
+    meta[4 * (size_t)r + 1] = ent;
+    meta[4 * (size_t)r + 2] = s0;
+    meta[4 * (size_t)r + 3] = s1 - s0;
+    code.resize(ebase + (int64_t)ent * T, 0);
+    w32.resize(ebase + (int64_t)ent * T, 0.f);
+    w64.resize(ebase + (int64_t)ent * T, 0.0);
+    for (int k = 0; k < T; ++k) {
+      int64_t m = 0;
+      for (int32_t p : owned[k]) {
+        const int32_t q = dest[p];
+        for (int32_t i = seg_a[q]; i < seg_b[q]; ++i, ++m) {
+          const int32_t row = node[i] / W, col = node[i] % W;
+          const int64_t at = ebase + m * T + k;
+          code[at] = (uint16_t)(((row - 2 * r) * W + col) | (i + 1 == seg_b[q] ? RP_END : 0));
+          w64[at] = wv[i];
+          w32[at] = (float)wv[i];
+        }
+      }
+    }
+    // the row pair's segments in thread order: slot of each
+    for (size_t i = 0; i < perm.size(); ++i) perm[i] = dest[perm[i]];
+    std::copy(perm.begin(), perm.end(), dest.begin() + s0);
+    ebase += (int64_t)ent * T;
+    if (ebase >= ((int64_t)1 << 30)) return GOFD_OK;
+  }
+  // padding read ahead past the last row pair (no node, weight zero)
+  const int64_t total = ebase + (int64_t)RP_EPRE * T;
+  code.resize(total, 0);
+  w32.resize(total, 0.f);
+  w64.resize(total, 0.0);
+  GOFD_TRY(dev_reserve(ctx, tr->rp_meta, sizeof(int32_t) * meta.size()));
+  GOFD_TRY(dev_reserve(ctx, tr->rp_tseg, sizeof(int32_t) * tseg.size()));
+  GOFD_TRY(dev_reserve(ctx, tr->rp_code, sizeof(uint16_t) * total));
+  GOFD_TRY(dev_reserve(ctx, tr->rp_w32, sizeof(float) * total));
+  GOFD_TRY(dev_reserve(ctx, tr->rp_w64, sizeof(double) * total));
+  GOFD_TRY(dev_reserve(ctx, tr->rp_dest, sizeof(int32_t) * std::max<int64_t>(nseg, 1)));
+  GOFD_TRY(dev_reserve(ctx, tr->pv_off, sizeof(int32_t) * (nv + 1)));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->rp_meta.p, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->rp_tseg.p, tseg.data(), sizeof(int32_t) * tseg.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->rp_code.p, code.data(), sizeof(uint16_t) * total, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->rp_w32.p, w32.data(), sizeof(float) * total, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->rp_w64.p, w64.data(), sizeof(double) * total, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->rp_dest.p, dest.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipMemcpyAsync(tr->pv_off.p, pv.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));      // the host arrays go out of scope
+  tr->n_slots = nseg;
+  tr->rp_ent_max = ent_max;
+  tr->rp_ok = true;
+  return GOFD_OK;
+}
+
 extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double* X_dev, int64_t ne,
                                    const int32_t* elems_dev, const gofd_grid* grid, gofd_transfer* out,
                                    gofd_transfer_info* info) {
@@ -540,6 +686,7 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   if (info) *info = inf;
   if (inf.n_interior > 0 && !(dmin > 0.0))
     return gofd_fail(ctx, GOFD_E_ZERO_COLSUM, "an interior vertex has zero column sum D_j (grid too coarse)");
+  GOFD_TRY(build_rowpairs(ctx, tr, offh));
   *out = guard.release();
   return GOFD_OK;
 }
