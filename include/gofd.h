@@ -110,6 +110,9 @@ typedef struct {
   double h_bound;           /* a_h / ((d+1) sqrt(d)), the sufficient spacing of eq. hFD-1  */
   int64_t exact_tests;      /* orientation signs decided by exact expansion arithmetic    */
   int64_t max_col_count;    /* largest number of grid nodes touching one vertex          */
+  int64_t rp_slots;         /* 2D: partial sums of the row-pair form of I^T used inside   */
+                            /* CG (one per vertex and row pair it touches); 0 if absent  */
+  int64_t rp_entries;       /* 2D: stored entries of that form (with per-thread padding)  */
 } gofd_transfer_info;
 
 /* Build I_h^FD, its transpose structure and D_h (Section 3.1, eqs. interp-1 to

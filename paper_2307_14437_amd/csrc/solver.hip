@@ -1024,7 +1024,71 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     HIP_TRY(ctx, hipStreamSynchronize(st));
     for (int k = 0; k < ni; ++k) rr_ref[k] = tmp[k].rr;
   }
-  while (it < max_iter) {
+  auto need_replace = [&](const std::vector<Scal>& st_) {
+    bool need = false;
+    for (int k = 0; k < ni; ++k)
+      if (st_[k].status == ST_OK && !settled[k] &&
+          (st_[k].done || st_[k].rr < replace_drop * replace_drop * rr_ref[k]))
+        need = true;
+    return need;
+  };
+  if (!history && !prof) {
+    // Pipelined checks: up to two chunks of iterations in flight, each
+    // followed by an asynchronous copy of the state into its own page-locked
+    // slot; the host decides on the older chunk's state while the newer one
+    // runs.  Items that stopped skip their work in the chunk run past their
+    // stop, and a residual replacement first drains the stream.
+    const size_t need_bytes = sizeof(Scal) * 2 * (size_t)ni;
+    if (ctx->host_state_bytes < need_bytes) {
+      if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+      ctx->host_state = nullptr;
+      ctx->host_state_bytes = 0;
+      HIP_TRY(ctx, hipHostMalloc(&ctx->host_state, need_bytes, hipHostMallocDefault));
+      ctx->host_state_bytes = need_bytes;
+    }
+    for (auto& e : ctx->check_ev)
+      if (!e) HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    Scal* hb = static_cast<Scal*>(ctx->host_state);
+    auto issue = [&](int slot) -> int {
+      if (use_graph) {
+        if (hipGraphLaunch(exec, st) != hipSuccess) return gofd_fail(ctx, GOFD_E_HIP, "graph launch failed");
+      } else {
+        for (int j = 0; j < check_every; ++j) GOFD_TRY(cg_iteration(ctx, B, w, fp32, nullptr));
+      }
+      it += check_every;
+      HIP_TRY(ctx, hipMemcpyAsync(hb + (size_t)slot * ni, w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
+      HIP_TRY(ctx, hipEventRecord(ctx->check_ev[slot], st));
+      return GOFD_OK;
+    };
+    int slot = 0, nfl = 0;       // oldest chunk's slot, chunks in flight
+    while (rc == GOFD_OK) {
+      while (nfl < 2 && it < max_iter && rc == GOFD_OK) {
+        rc = issue((slot + nfl) % 2);
+        ++nfl;
+      }
+      if (rc != GOFD_OK || nfl == 0) break;
+      if (hipEventSynchronize(ctx->check_ev[slot]) != hipSuccess) {
+        rc = gofd_fail(ctx, GOFD_E_HIP, "reading solver state failed");
+        break;
+      }
+      std::copy(hb + (size_t)slot * ni, hb + (size_t)(slot + 1) * ni, tmp.begin());
+      slot = (slot + 1) % 2;
+      --nfl;
+      if (replace_drop > 0.0 && need_replace(tmp)) {
+        if (hipStreamSynchronize(st) != hipSuccess) {
+          rc = gofd_fail(ctx, GOFD_E_HIP, "stream synchronisation failed");
+          break;
+        }
+        nfl = 0;
+        if ((rc = replace_residual(tmp)) != GOFD_OK) break;
+        if (n_replace) ++*n_replace;
+      }
+      bool all = true;
+      for (int k = 0; k < ni; ++k) all = all && tmp[k].done;
+      if (all) break;
+    }
+  }
+  while (it < max_iter && (history || prof) && rc == GOFD_OK) {
     const int chunk = history ? 1 : check_every;
     if (use_graph && !history) {
       if (hipGraphLaunch(exec, st) != hipSuccess) {
@@ -1043,21 +1107,15 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     }
     // the state's rr is that of the iterate tested last: x_{it-1}
     if (history && it - 1 <= max_iter) history[it - 1] = tmp[0].bb > 0 ? std::sqrt(tmp[0].rr / tmp[0].bb) : 0.0;
-    if (replace_drop > 0.0) {
-      bool need = false;
-      for (int k = 0; k < ni; ++k)
-        if (tmp[k].status == ST_OK && !settled[k] &&
-            (tmp[k].done || tmp[k].rr < replace_drop * replace_drop * rr_ref[k]))
-          need = true;
-      if (need) {
-        if ((rc = replace_residual(tmp)) != GOFD_OK) break;
-        if (n_replace) ++*n_replace;
-      }
+    if (replace_drop > 0.0 && need_replace(tmp)) {
+      if ((rc = replace_residual(tmp)) != GOFD_OK) break;
+      if (n_replace) ++*n_replace;
     }
     bool all = true;
     for (int k = 0; k < ni; ++k) all = all && tmp[k].done;
     if (all) break;
   }
+  (void)hipStreamSynchronize(st);       // a chunk may still run: finish it before the graph goes
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (rc != GOFD_OK) return rc;

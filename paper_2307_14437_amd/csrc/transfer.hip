@@ -495,6 +495,8 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   HIP_TRY(ctx, hipStreamSynchronize(st));      // the host arrays go out of scope
   tr->n_slots = nseg;
   tr->rp_ent_max = ent_max;
+  tr->info.rp_slots = nseg;
+  tr->info.rp_entries = ebase;
   tr->rp_ok = true;
   return GOFD_OK;
 }
@@ -687,6 +689,7 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   if (inf.n_interior > 0 && !(dmin > 0.0))
     return gofd_fail(ctx, GOFD_E_ZERO_COLSUM, "an interior vertex has zero column sum D_j (grid too coarse)");
   GOFD_TRY(build_rowpairs(ctx, tr, offh));
+  if (info) *info = tr->info;
   *out = guard.release();
   return GOFD_OK;
 }

@@ -27,10 +27,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # stage of a CG iteration -> kernel symbol fragment (single-precision grid, 2D, L = 2048)
 STAGE_SYMBOLS = {   # fragments that together name the kernel of each stage
     "gather": ("k_gather_items<float, 2>",),
-    "passA": ("k_passA<float, 2048",),
+    "passA": ("k_passA<float, 2048", "SrcPairGrid<float>"),
     "passB": ("k_passB<float, 2048, 16, 2, true>",),
-    "passC": ("k_passC<float, float, 2048",),
-    "scatter": ("k_scatter_cg<float, float",),
+    "passC": ("k_passC<float, float, 2048", "true"),
+    "scatter": ("k_vertex_cg",),
 }
 
 
