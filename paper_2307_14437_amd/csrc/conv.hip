@@ -318,6 +318,33 @@ struct SrcPairGrid {
   }
 };
 
+// the FP32 gather of batch item `it` (its mesh, its vector at ubase + off)
+// straight from the per-node single-precision rows: row, then vertex values,
+// for every node of the thread in flight together
+struct SrcPairGatherRows {
+  const CgItem* items;
+  const double* ubase;
+  int use_mask;
+  template <typename R, int E, int TPL>
+  __device__ __forceinline__ void load(int it, int row0, int W, int t, cplx<R>* v) const {
+    const PairCols<E, TPL> pc(row0, W);
+    constexpr int M = PairCols<E, TPL>::M;
+    const CgItem& I = items[it];
+    long long k[2 * M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int cc = pc.clamp(pc.col(t, m), W);
+      k[m] = (long long)pc.r0c * W + cc;
+      k[M + m] = (long long)pc.r1c * W + cc;
+    }
+    int vid[2 * M][4];
+    double lam[2 * M][4], val[2 * M];
+    rows_2d_32<2 * M>(I.row32_v, I.row32_w, k, vid, lam);
+    row_values<2, 2 * M>(ubase + I.off, nullptr, use_mask ? I.imask : nullptr, vid, lam, val);
+    pc.template put<R>(v, t, W, val, val + M);
+  }
+};
+
 // ---------------------------------------------------------------- spectra layout
 // Z holds, per rhs, the L/2 column slots of the W window rows after the row
 // transform, in tiles of four slots: Z[slot/4][row][slot%4].  A block of the
@@ -904,6 +931,13 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   hipStream_t st = ctx->stream;
   GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
   const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
+  if (conv_gather_fused(op, fp32) && g->items && (passes & 8) && (passes & 1)) {
+    // the FP32 gather of a batch runs inside the first row pass
+    SrcPairGatherRows src{g->items, g->ubase, g->items_mask ? 1 : 0};
+    const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_max};
+    return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes & 7, skip, dpart, lv1, fin,
+                              that_tab, rs);
+  }
   if ((passes & 8) && g->items) {
     // batched: every item gathers from its own mesh
 #define GOFD_GI(R, D) \
@@ -1035,6 +1069,11 @@ static int next_pow2(long long x) {
 }
 
 int conv_period(int N) { return std::max(8, next_pow2(4LL * N)); }
+
+#ifndef GOFD_FUSE_GATHER
+#define GOFD_FUSE_GATHER 1
+#endif
+bool conv_gather_fused(const gofd_fdop_s* op, bool fp32) { return GOFD_FUSE_GATHER && op->d == 2 && fp32; }
 
 int conv_rowpass_threads(int L) {
   const int E = std::min(GOFD_FFT_E_ROWS, L);

@@ -246,6 +246,9 @@ struct GatherSpec {
 // FFT period of the embedding for a grid of half-width N, and the threads
 // and row pairs per block of the row passes for period L
 int conv_period(int N);
+// whether the batched gather of conv_apply runs inside the first row pass
+// (passes 8 and 1 together; 2D, FP32 pipeline, from the per-node rows)
+bool conv_gather_fused(const gofd_fdop_s* op, bool fp32);
 int conv_rowpass_threads(int L);
 int conv_rowpass_lines(int L);
 // Row-pair I^T form: capacity (doubles) of the per-block segment sums;

@@ -888,11 +888,15 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
   if (prof) {
     // the same launches one stage at a time, each kernel recording its own
     // start and end events
+    // (a gather that runs inside the first row pass is timed with it)
     static const int stage_passes[4] = {8, 1, 2, 4};
+    const bool fused = conv_gather_fused(B.op0, fp32);
     for (int k = 0; k < 4; ++k) {
+      if (k == GOFD_ST_GATHER && fused) continue;
       ctx->timer_start = prof->ev[2 * k];
       ctx->timer_stop = prof->ev[2 * k + 1];
-      GOFD_TRY(conv_apply(ctx, B.op0, B.nitems, nullptr, &g, w.grid.p, fp32, stage_passes[k]));
+      GOFD_TRY(conv_apply(ctx, B.op0, B.nitems, nullptr, &g, w.grid.p, fp32,
+                          stage_passes[k] | (k == GOFD_ST_PASS_A && fused ? 8 : 0)));
       ctx->timer_start = ctx->timer_stop = nullptr;
     }
     ctx->timer_start = prof->ev[8];
@@ -926,6 +930,7 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
     HIP_TRY(ctx, hipStreamSynchronize(st));
     for (int k = 0; k < GOFD_N_STAGES; ++k) {
       if (k == GOFD_ST_PRECOND && !B.any_ic) continue;
+      if (k == GOFD_ST_GATHER && conv_gather_fused(B.op0, fp32)) continue;
       float ms = 0.f;
       HIP_TRY(ctx, hipEventElapsedTime(&ms, prof->ev[2 * k], prof->ev[2 * k + 1]));
       prof->sum[k] += ms;

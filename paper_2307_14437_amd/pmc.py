@@ -26,8 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 # stage of a CG iteration -> kernel symbol fragment (single-precision grid, 2D, L = 2048)
 STAGE_SYMBOLS = {   # fragments that together name the kernel of each stage
-    "gather": ("k_gather_items<float, 2>",),
-    "passA": ("k_passA<float, 2048", "SrcPairGrid<float>"),
+    "passA": ("k_passA<float, 2048", "SrcPairGatherRows"),
     "passB": ("k_passB<float, 2048, 16, 2, true>",),
     "passC": ("k_passC<float, float, 2048", "true"),
     "scatter": ("k_vertex_cg",),
@@ -66,7 +65,8 @@ def main(argv):
         k = names[0]
         f = sum(F[k]) / len(F[k]) * 1024 * kf
         w = sum(Wr[k]) / len(Wr[k]) * 1024 * kw if k in Wr else 0.0
-        stages[st] = {"kernel": k.split("(")[0], "dispatches": len(F[k]), "fetch_bytes": f, "write_bytes": w,
+        name = k.replace("(anonymous namespace)::", "").split("(")[0]
+        stages[st] = {"kernel": name, "dispatches": len(F[k]), "fetch_bytes": f, "write_bytes": w,
                       "bytes": f + w}
     res = {"source_hash": source_hash(), "fetch_factor": kf, "write_factor": kw, "copy_bytes": copy_bytes,
            "stages": stages}
