@@ -633,10 +633,25 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
       gw = reinterpret_cast<const R*>(I.rp_w32) + meta.x + t;
     else
       gw = reinterpret_cast<const R*>(I.rp_w64) + meta.x + t;
+    // the second half only where the row pair's count needs it (a uniform
+    // branch with one row pair per block)
 #pragma unroll
-    for (int m = 0; m < EPRE; ++m) {
+    for (int m = 0; m < EPRE / 2; ++m) {
       code[m] = gmem(gcode)[m * TPL];
       wt[m] = gmem(gw)[m * TPL];
+    }
+    if (LINES > 1 || meta.y > EPRE / 2) {
+#pragma unroll
+      for (int m = EPRE / 2; m < EPRE; ++m) {
+        code[m] = gmem(gcode)[m * TPL];
+        wt[m] = gmem(gw)[m * TPL];
+      }
+    } else {
+#pragma unroll
+      for (int m = EPRE / 2; m < EPRE; ++m) {
+        code[m] = 0;
+        wt[m] = (R)0;
+      }
     }
 #pragma unroll
     for (int m = 0; m < EPRE; ++m)
@@ -673,22 +688,24 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
     R yv[EPRE];
 #pragma unroll
     for (int m = 0; m < EPRE; ++m) yv[m] = yl[code[m] & RP_NODE];
-    double acc = 0.0;
+    // (a segment's entries are summed in the grid precision, the segments of
+    // a vertex in double by the vertex kernel)
+    R acc = 0;
     int j = tseg;
 #pragma unroll
     for (int m = 0; m < EPRE; ++m) {
-      acc += (double)wt[m] * (double)yv[m];
+      acc = fma(wt[m], yv[m], acc);
       const bool end = (code[m] & RP_END) != 0;
-      if (end) sg[j] = acc;
+      if (end) sg[j] = (double)acc;
       j += end ? 1 : 0;
-      acc = end ? 0.0 : acc;
+      acc = end ? (R)0 : acc;
     }
     for (int m = EPRE; m < meta.y; ++m) {      // rows pairs with more entries per thread
       const int c = gmem(gcode)[(long long)m * TPL];
-      acc += (double)gmem(gw)[(long long)m * TPL] * (double)yl[c & RP_NODE];
+      acc = fma(gmem(gw)[(long long)m * TPL], yl[c & RP_NODE], acc);
       if (c & RP_END) {
-        sg[j++] = acc;
-        acc = 0.0;
+        sg[j++] = (double)acc;
+        acc = 0;
       }
     }
     __syncthreads();
