@@ -155,6 +155,15 @@ def main():
         t = time.perf_counter()
         pcs.append(gofd.Precond(ctx, tr, ops[-1], args.precond))
         setup[f"precond_ms_s{s}"] = (time.perf_counter() - t) * 1e3
+    # column-pass schedules for this FFT length, tuned on the device (setup, outside the timed region)
+    _sync(); t = time.perf_counter()
+    sched = {}
+    for fp32 in (True, False):
+        sc, times = gofd.autotune(ctx, g, fp32=fp32)
+        sched["fp32" if fp32 else "fp64"] = {"schedule": sc, "values_per_thread_slots_per_block":
+                                             list(gofd.COL_SCHEDULES[sc]),
+                                             "candidates_us": [round(x * 1e3, 2) for x in times]}
+    _sync(); setup["autotune_ms"] = (time.perf_counter() - t) * 1e3
 
     def step(mode):
         it = args.drop if mode == gofd.MODE_FP32_RELIABLE else args.inner_tol
@@ -249,7 +258,7 @@ def main():
         "config": {"workload": "2D L-shape, 67k-vertex graded Delaunay mesh, 1024x1024 overlay grid, "
                                "s in {0.25, 0.75}, 16-mode Fourier f, tol 1e-8",
                    "nv": tr.nv, "grid": f"{W}x{W}", "fft_length": 2 * (W - 1), "precond": args.precond,
-                   "fp32_mode": "reliable updating", "drop": args.drop},
+                   "fp32_mode": "reliable updating", "drop": args.drop, "column_pass_schedule": sched},
         "fp64": {"solves_per_s": len(svals) / (ms_step64 * 1e-3), "ms_per_step": ms_step64,
                  "iterations": {str(k): v for k, v in its64.items()}},
         "fp32_reliable": {"iterations": {str(s): info32[i]["iterations"] for i, s in enumerate(svals)},

@@ -202,6 +202,26 @@ int gofd_apply_afd(gofd_ctx ctx, gofd_fdop op, int nrhs, const double* v_dev, do
 int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const double* u_dev,
                   double* y_dev, int flags);
 
+/* Column-pass schedules (2D): the pass that transforms the spectrum columns,
+ * multiplies by the kernel's spectrum and transforms back (eq. AU-1) has
+ * GOFD_N_COL_SCHED schedules (values per thread and column slots per block:
+ * 0 = 16/2, the built-in default, 1 = 16/1, 2 = 8/2, 3 = 16/4).  The schedule
+ * for a (period L, precision) pair is a property of the context and applies
+ * to every later product of that shape; results agree between schedules to
+ * rounding.
+ * gofd_autotune times every schedule of the given grid's period on the device
+ * (a zero field of the grid's window, 20 launches each after 3 untimed ones,
+ * GOFD_FP32_GRID in flags selecting the precision), installs the fastest and
+ * returns its number in *sched (host, nullable) and the average durations in
+ * ms in times[GOFD_N_COL_SCHED] (host, nullable).  Synchronises.
+ * gofd_set_schedule installs a known schedule (e.g. from a cache of earlier
+ * tuning runs).  Errors: GOFD_E_ARG (bad grid or schedule number),
+ * GOFD_E_UNSUPPORTED (d = 3: the 3D passes have one schedule per length),
+ * GOFD_E_OOM, GOFD_E_HIP. */
+enum { GOFD_N_COL_SCHED = 4 };
+int gofd_autotune(gofd_ctx ctx, const gofd_grid* grid, int flags, int* sched, double* times);
+int gofd_set_schedule(gofd_ctx ctx, const gofd_grid* grid, int flags, int sched);
+
 /* Timing of one kernel of the K product in isolation (for roofline reports):
  * launches kernel `which` (GOFD_K_PASS_A: first FFT pass (rows), PASS_B: the
  * column pass with the spectral multiply, PASS_C: last FFT pass, SCATTER: the

@@ -110,6 +110,8 @@ def _load():
         "gofd_solve_adjoint": [vp, vp, vp, vp, vp, vp, vp, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp,
                                ctypes.POINTER(SolveInfo)],
         "gofd_time_kernel": [vp, vp, vp, i32, i32, vp, i32, i32, ctypes.POINTER(dbl)],
+        "gofd_autotune": [vp, ctypes.POINTER(_Grid), i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
+        "gofd_set_schedule": [vp, ctypes.POINTER(_Grid), i32, i32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -384,6 +386,73 @@ def solve_adjoint(ctx: Context, tr: Transfer, op: FdOp, dLdu, u, f, tol=1e-10, p
                                      float(tol), ctypes.byref(opts), _ptr(gf) if gf is not None else None,
                                      _ptr(gX) if gX is not None else None, _ptr(lam), ctypes.byref(info)))
     return gf, (gX.view(tr.nv, tr.d) if gX is not None else None), lam, info.as_dict()
+
+
+N_COL_SCHED = 4
+COL_SCHEDULES = ((16, 2), (16, 1), (8, 2), (16, 4))     # (values per thread, column slots per block)
+
+
+def fft_period(N: int) -> int:
+    """FFT length of the embedding for a grid of half-width N (as the library computes it)."""
+    L = 1
+    while L < 4 * N:
+        L <<= 1
+    return max(8, L)
+
+
+def _cache_key(arch: str, grid, fp32: bool) -> str:
+    return f"{arch}/d{grid.d}/L{fft_period(grid.N)}/{'fp32' if fp32 else 'fp64'}"
+
+
+def cache_lookup(path, key):
+    """Schedule stored under key in the JSON tuning cache at path, or None."""
+    import json
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        entry = json.load(fh).get(key)
+    return None if entry is None else int(entry["schedule"])
+
+
+def cache_store(path, key, sched, times):
+    """Record a tuning result under key in the JSON cache at path (other keys are kept)."""
+    import json
+    data = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            data = json.load(fh)
+    data[key] = {"schedule": int(sched), "ms": [float(t) for t in times]}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune(ctx: Context, grid, fp32=True, cache=None):
+    """Pick the column-pass schedule for the grid's FFT length and precision (2D): from the JSON cache
+    when it holds this device architecture, length and precision, else by timing every schedule on the
+    device (the result is then stored in the cache).  Returns (schedule, times in ms or None)."""
+    import torch
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    key = _cache_key(arch, grid, fp32)
+    g = _grid(grid)
+    flags = FP32_GRID if fp32 else 0
+    hit = cache_lookup(cache, key)
+    if hit is not None:
+        ctx.check(lib.gofd_set_schedule(ctx.handle, ctypes.byref(g), flags, hit))
+        return hit, None
+    s = ctypes.c_int()
+    t = (ctypes.c_double * N_COL_SCHED)()
+    ctx.check(lib.gofd_autotune(ctx.handle, ctypes.byref(g), flags, ctypes.byref(s), t))
+    if cache:
+        cache_store(cache, key, s.value, list(t))
+    return s.value, list(t)
+
+
+def set_schedule(ctx: Context, grid, sched, fp32=True):
+    """Install a column-pass schedule (0..N_COL_SCHED-1) for the grid's FFT length and precision."""
+    g = _grid(grid)
+    ctx.check(lib.gofd_set_schedule(ctx.handle, ctypes.byref(g), FP32_GRID if fp32 else 0, int(sched)))
 
 
 def time_kernel(ctx: Context, tr: Transfer, op: FdOp, which, u, flags=0, reps=20):

@@ -731,15 +731,15 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
 
 // ---------------------------------------------------------------- launch
 
-// Values per thread of the row passes (A, C) and of the column pass (B):
-// build-time tuning knobs, powers of two in 4..16.
+// Values per thread of the row passes (A, C) and of the default column-pass
+// schedule (B): build-time knobs, powers of two in 4..16.
 #ifndef GOFD_FFT_E_ROWS
 #define GOFD_FFT_E_ROWS 8
 #endif
 #ifndef GOFD_FFT_E_COLS
 #define GOFD_FFT_E_COLS 16
 #endif
-// most column slots per block of pass B (1, 2 or 4)
+// most column slots per block of the default column-pass schedule (1, 2 or 4)
 #ifndef GOFD_FFT_LB
 #define GOFD_FFT_LB 2
 #endif
@@ -749,17 +749,59 @@ struct Cfg {
   static constexpr int EA = (L >= GOFD_FFT_E_ROWS) ? GOFD_FFT_E_ROWS : L;
   static constexpr int TA = L / EA;                                         // threads per row pair
   static constexpr int LINES_A = (TA >= 64) ? 1 : 64 / TA;                  // row pairs per block
-  static constexpr int EB = (L >= GOFD_FFT_E_COLS) ? GOFD_FFT_E_COLS : L;
-  static constexpr int TB = L / EB;                                         // threads per column slot
-  static constexpr int LINE_BYTES = padded_len<L, EB>() * (int)sizeof(cplx<R>);
-  static constexpr int LB_MEM = (GOFD_FFT_LB >= 4 && 4 * LINE_BYTES <= 150 * 1024)
-                                    ? 4
-                                    : ((GOFD_FFT_LB >= 2 && 2 * LINE_BYTES <= 150 * 1024) ? 2 : 1);
-  static constexpr int LB = (LB_MEM * TB <= 1024) ? LB_MEM : ((2 * TB <= 1024) ? 2 : 1);   // slots per block
-  static_assert(4 % LB == 0 && (L / 2) % 4 == 0, "tile layout");
   static_assert(LINES_A * TA <= 1024 && LINES_A * padded_len<L, EA>() * (int)sizeof(cplx<R>) <= 150 * 1024,
                 "row pass block");
 };
+
+// Schedules of the column pass (values per thread, column slots per block):
+// schedule 0 is the built-in default; gofd_autotune times the others on the
+// device and records the fastest per (L, precision) in the context.
+struct ColSched {
+  int e, lb;
+};
+constexpr ColSched kColSched[GOFD_N_COL_SCHED] = {{GOFD_FFT_E_COLS, GOFD_FFT_LB}, {16, 1}, {8, 2}, {16, 4}};
+
+template <typename R, int L, int S>
+struct ColCfg {
+  static constexpr int E = (L >= kColSched[S].e) ? kColSched[S].e : L;
+  static constexpr int T = L / E;                                           // threads per column slot
+  static constexpr int LINE_BYTES = padded_len<L, E>() * (int)sizeof(cplx<R>);
+  static constexpr int LB0 = kColSched[S].lb;
+  static constexpr int LB_MEM = (LB0 >= 4 && 4 * LINE_BYTES <= 150 * 1024)
+                                    ? 4
+                                    : ((LB0 >= 2 && 2 * LINE_BYTES <= 150 * 1024) ? 2 : 1);
+  static constexpr int LB = (LB_MEM * T <= 512) ? LB_MEM : ((2 * T <= 512) ? 2 : 1);     // slots per block
+  static_assert(4 % LB == 0 && (L / 2) % 4 == 0, "tile layout");
+};
+
+template <typename R, int L, int S>
+void launch_passB_s(gofd_ctx_s* ctx, hipStream_t st, int nrhs, cplx<R>* Z, int W, int half, const R* That,
+                    const cplx<R>* tw, long long zs, Skip skip, double* dpart, const gofd_cg::Level1& lv1,
+                    const void* const* that_tab) {
+  using C = ColCfg<R, L, S>;
+  if (dpart)
+    GOFD_LAUNCH(ctx, (k_passB<R, L, C::E, C::LB, true>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::T), 0, st, Z,
+                W, half, That, tw, zs, skip, dpart, lv1, that_tab);
+  else
+    GOFD_LAUNCH(ctx, (k_passB<R, L, C::E, C::LB, false>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::T), 0, st,
+                Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab);
+}
+
+template <typename R, int L>
+int passB_blocks_L(int s) {
+  switch (s) {
+    case 1: return (L / 2) / ColCfg<R, L, 1>::LB;
+    case 2: return (L / 2) / ColCfg<R, L, 2>::LB;
+    case 3: return (L / 2) / ColCfg<R, L, 3>::LB;
+    default: return (L / 2) / ColCfg<R, L, 0>::LB;
+  }
+}
+
+// schedule in force for (L, precision) in this context
+static int col_sched(const gofd_ctx_s* ctx, int L, bool fp32) {
+  auto it = ctx->col_sched.find(std::make_pair(L, fp32));
+  return it == ctx->col_sched.end() ? 0 : it->second;
+}
 
 template <typename R, int L, class Src, typename Y>
 int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
@@ -787,12 +829,14 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   if (passes & 1)
     GOFD_LAUNCH(ctx, (k_passA<R, L, C::EA, C::LINES_A, Src>), dim3(nbA, nrhs), dim3(C::LINES_A * C::TA), 0, st,
                        src, Z, W, tw, zs, skip);
-  if ((passes & 2) && dpart)
-    GOFD_LAUNCH(ctx, (k_passB<R, L, C::EB, C::LB, true>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
-                       st, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab);
-  else if (passes & 2)
-    GOFD_LAUNCH(ctx, (k_passB<R, L, C::EB, C::LB, false>), dim3((L / 2) / C::LB, nrhs), dim3(C::LB * C::TB), 0,
-                       st, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab);
+  if (passes & 2) {
+    switch (col_sched(ctx, L, sizeof(R) == 4)) {
+      case 1: launch_passB_s<R, L, 1>(ctx, st, nrhs, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab); break;
+      case 2: launch_passB_s<R, L, 2>(ctx, st, nrhs, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab); break;
+      case 3: launch_passB_s<R, L, 3>(ctx, st, nrhs, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab); break;
+      default: launch_passB_s<R, L, 0>(ctx, st, nrhs, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab);
+    }
+  }
   if ((passes & 4) && rs.items) {
     // entries read ahead per thread: the first of 16, 24, 32 that covers the
     // transfer's largest count (more run in a loop)
@@ -1008,25 +1052,26 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
 }
 
 template <typename R>
-static int passB_blocks(int L) {
+static int passB_blocks(int L, int s) {
   switch (L) {
-    case 8: return 4 / Cfg<R, 8>::LB;
-    case 16: return 8 / Cfg<R, 16>::LB;
-    case 32: return 16 / Cfg<R, 32>::LB;
-    case 64: return 32 / Cfg<R, 64>::LB;
-    case 128: return 64 / Cfg<R, 128>::LB;
-    case 256: return 128 / Cfg<R, 256>::LB;
-    case 512: return 256 / Cfg<R, 512>::LB;
-    case 1024: return 512 / Cfg<R, 1024>::LB;
-    case 2048: return 1024 / Cfg<R, 2048>::LB;
-    case 4096: return 2048 / Cfg<R, 4096>::LB;
+    case 8: return passB_blocks_L<R, 8>(s);
+    case 16: return passB_blocks_L<R, 16>(s);
+    case 32: return passB_blocks_L<R, 32>(s);
+    case 64: return passB_blocks_L<R, 64>(s);
+    case 128: return passB_blocks_L<R, 128>(s);
+    case 256: return passB_blocks_L<R, 256>(s);
+    case 512: return passB_blocks_L<R, 512>(s);
+    case 1024: return passB_blocks_L<R, 1024>(s);
+    case 2048: return passB_blocks_L<R, 2048>(s);
+    case 4096: return passB_blocks_L<R, 4096>(s);
     default: return 1;
   }
 }
 
 int conv_passB_blocks(const gofd_fdop_s* op, bool fp32) {
   if (op->d == 3) return conv3_passC_blocks(op, fp32);
-  return fp32 ? passB_blocks<float>(op->L) : passB_blocks<double>(op->L);
+  const int s = col_sched(op->ctx, op->L, fp32);
+  return fp32 ? passB_blocks<float>(op->L, s) : passB_blocks<double>(op->L, s);
 }
 
 // ---------------------------------------------------------------- ABI
@@ -1034,6 +1079,98 @@ int conv_passB_blocks(const gofd_fdop_s* op, bool fp32) {
 bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op) {
   return tr->d == op->d && tr->N == op->N && tr->R == op->R && tr->center[0] == op->center[0] &&
          tr->center[1] == op->center[1] && tr->center[2] == op->center[2];
+}
+
+// Column-pass schedule tuning (2D): time every schedule on a zero field of
+// the grid's window (one field, the CG variant of the pass), keep the fastest.
+template <typename R, int L>
+static int tune_L(gofd_ctx_s* ctx, int W, double* times) {
+  const int half = L / 2 + 1;
+  const long long zs = (long long)W * (L / 2);
+  const cplx<R>* tw = sizeof(R) == 8 ? reinterpret_cast<const cplx<R>*>(twiddles64(ctx, L))
+                                     : reinterpret_cast<const cplx<R>*>(twiddles32(ctx, L));
+  if (!tw) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
+  DevBuf Z, T, dp;
+  GOFD_TRY(dev_reserve(ctx, Z, sizeof(cplx<R>) * zs));
+  GOFD_TRY(dev_reserve(ctx, T, sizeof(R) * (long long)half * half));
+  GOFD_TRY(dev_reserve(ctx, dp, sizeof(double) * 3 * (L / 2)));
+  hipStream_t st = ctx->stream;
+  HIP_TRY(ctx, hipMemsetAsync(Z.p, 0, sizeof(cplx<R>) * zs, st));
+  HIP_TRY(ctx, hipMemsetAsync(T.p, 0, sizeof(R) * (long long)half * half, st));
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  const gofd_cg::Level1 lv1;
+  const Skip skip{nullptr, 0};
+  constexpr int reps = 20;
+  int best = 0;
+  for (int s = 0; s < GOFD_N_COL_SCHED; ++s) {
+    auto run = [&]() {
+      switch (s) {
+        case 1: launch_passB_s<R, L, 1>(ctx, st, 1, Z.as<cplx<R>>(), W, half, T.as<R>(), tw, zs, skip, dp.as<double>(), lv1, nullptr); break;
+        case 2: launch_passB_s<R, L, 2>(ctx, st, 1, Z.as<cplx<R>>(), W, half, T.as<R>(), tw, zs, skip, dp.as<double>(), lv1, nullptr); break;
+        case 3: launch_passB_s<R, L, 3>(ctx, st, 1, Z.as<cplx<R>>(), W, half, T.as<R>(), tw, zs, skip, dp.as<double>(), lv1, nullptr); break;
+        default: launch_passB_s<R, L, 0>(ctx, st, 1, Z.as<cplx<R>>(), W, half, T.as<R>(), tw, zs, skip, dp.as<double>(), lv1, nullptr);
+      }
+    };
+    for (int k = 0; k < 3; ++k) run();
+    (void)hipEventRecord(e0, st);
+    for (int k = 0; k < reps; ++k) run();
+    (void)hipEventRecord(e1, st);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return gofd_fail(ctx, GOFD_E_HIP, "timing the column pass failed");
+    }
+    times[s] = ms / reps;
+    if (times[s] < times[best]) best = s;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(ctx, hipGetLastError());
+  return best;
+}
+
+template <typename R>
+static int tune_2d(gofd_ctx_s* ctx, int L, int W, double* times) {
+  switch (L) {
+    case 8: return tune_L<R, 8>(ctx, W, times);
+    case 16: return tune_L<R, 16>(ctx, W, times);
+    case 32: return tune_L<R, 32>(ctx, W, times);
+    case 64: return tune_L<R, 64>(ctx, W, times);
+    case 128: return tune_L<R, 128>(ctx, W, times);
+    case 256: return tune_L<R, 256>(ctx, W, times);
+    case 512: return tune_L<R, 512>(ctx, W, times);
+    case 1024: return tune_L<R, 1024>(ctx, W, times);
+    case 2048: return tune_L<R, 2048>(ctx, W, times);
+    case 4096: return tune_L<R, 4096>(ctx, W, times);
+    default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "FFT length");
+  }
+}
+
+extern "C" int gofd_autotune(gofd_ctx ctx, const gofd_grid* grid, int flags, int* sched, double* times) {
+  if (!ctx || !grid || grid->N < 1) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  if (grid->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "schedule tuning is 2D only");
+  const bool fp32 = flags & GOFD_FP32_GRID;
+  const int L = conv_period(grid->N), W = 2 * grid->N + 1;
+  double t[GOFD_N_COL_SCHED];
+  for (double& x : t) x = HUGE_VAL;
+  const int best = fp32 ? tune_2d<float>(ctx, L, W, t) : tune_2d<double>(ctx, L, W, t);
+  if (best < 0) return best;
+  ctx->col_sched[std::make_pair(L, fp32)] = best;
+  if (sched) *sched = best;
+  if (times)
+    for (int s = 0; s < GOFD_N_COL_SCHED; ++s) times[s] = t[s];
+  return GOFD_OK;
+}
+
+extern "C" int gofd_set_schedule(gofd_ctx ctx, const gofd_grid* grid, int flags, int sched) {
+  if (!ctx || !grid || grid->N < 1 || sched < 0 || sched >= GOFD_N_COL_SCHED)
+    return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  if (grid->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "schedules are 2D only");
+  ctx->col_sched[std::make_pair(conv_period(grid->N), (flags & GOFD_FP32_GRID) != 0)] = sched;
+  return GOFD_OK;
 }
 
 extern "C" int gofd_apply_afd(gofd_ctx ctx, gofd_fdop op, int nrhs, const double* v, double* y, int flags) {

@@ -73,6 +73,7 @@ struct gofd_ctx_s {
   int num_cu = 256;
   std::string last_error;
   std::map<int, TwiddleTables*> twiddles;   // keyed by L
+  std::map<std::pair<int, bool>, int> col_sched;   // column-pass schedule per (L, FP32), see gofd_autotune
   DevBuf scratch;                           // small reduction scratch (partials, counters)
   DevBuf flag;                              // int status flags
   // When set, the next kernel launched through GOFD_LAUNCH records these

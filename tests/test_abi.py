@@ -34,3 +34,14 @@ def test_status_names():
     import paper_2307_14437_amd as gofd
     assert gofd.lib.gofd_strerror(-4) == b"GOFD_E_ZERO_COLSUM"
     assert gofd.lib.gofd_strerror(0) == b"GOFD_OK"
+
+
+def test_tuning_cache_roundtrip(tmp_path):
+    import paper_2307_14437_amd as gofd
+    path = str(tmp_path / "c.json")
+    assert gofd.cache_lookup(path, "gfx950/d2/L2048/fp32") is None
+    gofd.cache_store(path, "gfx950/d2/L2048/fp32", 1, [1.0, 0.5, 2.0, 3.0])
+    gofd.cache_store(path, "gfx950/d2/L1024/fp64", 2, [1.0, 1.0, 0.5, 1.0])
+    assert gofd.cache_lookup(path, "gfx950/d2/L2048/fp32") == 1
+    assert gofd.cache_lookup(path, "gfx950/d2/L1024/fp64") == 2
+    assert [gofd.fft_period(n) for n in (1, 2, 3, 32, 33, 512)] == [8, 8, 16, 128, 256, 2048]
