@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_gather(GridGeom g, const ElemRec<D>* __
                                                 long long nv, long long n_nodes, R* __restrict__ out, Skip skip) {
   static_assert(D == 2, "3D gathers from compact rows");
   const long long k0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * (256 * GATHER_NPT) + threadIdx.x;
-  const int rhs = blockIdx.y;
+  const int rhs = skip.item(blockIdx.y);
   int vid[GATHER_NPT][4];
   double lam[GATHER_NPT][4], val[GATHER_NPT];
   if constexpr (sizeof(R) == 4) {
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_gather_ell(const int* __restrict__ idx,
                                                     const double* __restrict__ mask, long long nv, long long n_nodes,
                                                     R* __restrict__ out, Skip skip) {
   const long long k = (long long)xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  const int rhs = blockIdx.y;
+  const int rhs = skip.item(blockIdx.y);
   if (k >= n_nodes) return;
   const int c = idx[k];
   if (skip(rhs)) return;
@@ -224,7 +224,7 @@ template <typename R, int D>
 __global__ __launch_bounds__(256) void k_gather_items(const CgItem* __restrict__ items,
                                                       const double* __restrict__ ubase, int use_mask,
                                                       long long n_nodes, R* __restrict__ out, Skip skip) {
-  const int it = blockIdx.y;
+  const int it = skip.item(blockIdx.y);
   const CgItem& I = items[it];
   const long long k0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * (256 * GATHER_NPT) + threadIdx.x;
   int vid[GATHER_NPT][4];
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_passA(Src src, cplx<R>* __res
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
   const int row0 = (xcd_remap(blockIdx.x, gridDim.x) * LINES + line) * 2;   // row bands per XCD
-  const int rhs = blockIdx.y;
+  const int rhs = skip.item(blockIdx.y);
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
   cplx<R> v[E];
@@ -436,7 +436,8 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
   const int c = threadIdx.x % LB, t = threadIdx.x / LB;
   cplx<R>* buf = sbuf + c * PL;
   const int slot = b * LB + c;
-  cplx<R>* Zc = Z + blockIdx.y * zs + zidx<R>(slot, 0, W);
+  const int rhs = skip.item(blockIdx.y);
+  cplx<R>* Zc = Z + rhs * zs + zidx<R>(slot, 0, W);
   // rows i >= W are zero (W <= L/2 + 1: only elements m <= E/2 can hold rows
   // of the window); the loads read clamped rows and are masked after, so that
   // they are all in flight together
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
   // line takes row min(k1, L - k1) of the stored (L/2+1)-row spectrum column
   // (for slot 0 this is column k0 = 0; column L/2 is read when it is used)
   R pm[E];
-  if (that_tab) That = static_cast<const R*>(that_tab[blockIdx.y]);     // per-item spectrum (batched solves)
+  if (that_tab) That = static_cast<const R*>(that_tab[rhs]);     // per-item spectrum (batched solves)
   {
     const R* Tc = That + (long long)slot * half;
 #pragma unroll
@@ -472,11 +473,11 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
     const int chunk = (lv1.n1 + gridDim.x - 1) / gridDim.x;
     const int lo = blockIdx.x * chunk, hi = min(lo + chunk, lv1.n1);
     for (int i = lo + threadIdx.x; i < hi; i += NT) {
-      red[0] += lv1.partG[(long long)blockIdx.y * lv1.n1 + i];
-      red[1] += lv1.partR[(long long)blockIdx.y * lv1.n1 + i];
+      red[0] += lv1.partG[(long long)rhs * lv1.n1 + i];
+      red[1] += lv1.partR[(long long)rhs * lv1.n1 + i];
     }
   }
-  if (skip(blockIdx.y)) return;
+  if (skip(rhs)) return;
   double& dacc = red[2];
   fft_regs<R, L, E, false>(v, buf, tws, t);
   if (b == 0) {                     // block-uniform: this block holds slot 0
@@ -517,7 +518,7 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
     static_assert(NT % 64 == 0 || NT < 64, "block size");
     gofd_cg::block_sum_n<NT, 3>(red, shd);
     if (threadIdx.x == 0) {
-      double* d = dpart + (long long)blockIdx.y * 3 * gridDim.x;
+      double* d = dpart + (long long)rhs * 3 * gridDim.x;
       d[blockIdx.x] = red[0];
       d[gridDim.x + blockIdx.x] = red[1];
       d[2 * gridDim.x + blockIdx.x] = red[2];
@@ -573,7 +574,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
   cplx<R>* buf = sbuf + line * PL;
   const int nrb = gridDim.x - (fin.sc ? 1 : 0);                            // row-pair blocks
   const int row0 = (xcd_remap(min((int)blockIdx.x, nrb - 1), nrb) * LINES + line) * 2;   // row bands per XCD
-  const int rhs = blockIdx.y;
+  const int rhs = skip.item(blockIdx.y);
   const bool has0 = row0 < W;
   const bool has1 = row0 + 1 < W;
   const cplx<R>* Zr = Z + rhs * zs;
@@ -973,7 +974,7 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   if (d != 2 && d != 3) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "dimension");
   long long nn = 1;
   for (int a = 0; a < d; ++a) nn *= op->W;
-  const Skip skip{g ? g->skip : nullptr, g ? g->skip_stride : 0};
+  const Skip skip{g ? g->skip : nullptr, g ? g->skip_stride : 0, g ? g->amap : nullptr};
   double* dpart = g ? g->dpart : nullptr;
   const gofd_cg::Level1 lv1 = g ? g->lv1 : gofd_cg::Level1();
   const gofd_cg::Finish fin = g ? g->fin : gofd_cg::Finish();
@@ -1039,7 +1040,7 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   }
   if (d == 3)
     return conv3_run(ctx, op, nrhs, fp32 ? nullptr : op->G.as<double>(), fp32 ? op->G.as<float>() : nullptr, y, fp32,
-                     passes & 7, skip.flag, skip.stride, dpart, lv1, fin, that_tab);
+                     passes & 7, skip.flag, skip.stride, dpart, lv1, fin, that_tab, skip.map);
   const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_max};
   if (fp32) {
     SrcPairGrid<float> src{op->G.as<float>(), nn};

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_p3A(Src src, cplx<R>* __restr
   cplx<R>* buf = sbuf + line * PL;
   const long long nrow = (long long)W * W;
   const long long row0 = ((long long)xcd_remap(blockIdx.x, gridDim.x) * LINES + line) * 2;
-  const int rhs = blockIdx.y;
+  const int rhs = skip.item(blockIdx.y);
   const bool has0 = row0 < nrow;
   const bool has1 = row0 + 1 < nrow;
   const long long r0c = has0 ? row0 : nrow - 1, r1c = has1 ? row0 + 1 : r0c;
@@ -111,8 +111,9 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3BD(cplx<R>* __restrict__ Z1, c
   const int slot = sb * LB + c;
   const bool act = slot <= H;
   const long long nrow = (long long)W * W;
-  cplx<R>* Z1r = Z1 + blockIdx.y * z1s;
-  cplx<R>* Z2r = Z2 + blockIdx.y * z2s;
+  const int rhs = skip.item(blockIdx.y);
+  cplx<R>* Z1r = Z1 + rhs * z1s;
+  cplx<R>* Z2r = Z2 + rhs * z2s;
   // loads from clamped in-range positions, masked after (all in flight together)
   const int sc = act ? slot : H;
   cplx<R> v[E];
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(LB*(L / E)) void k_p3BD(cplx<R>* __restrict__ Z1, c
   }
   gofd_fft::Twiddles<R, L, E> tws;
   tws.load(tw, t);
-  if (skip(blockIdx.y)) return;
+  if (skip(rhs)) return;
   fft_regs<R, L, E, INV>(v, buf, tws, t);
   if (!act) return;
 #pragma unroll
@@ -169,11 +170,12 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
   cplx<R>* buf = sbuf + c * PL;
   const int slot = sb * LB + c;
   const bool act = slot <= H;
-  cplx<R>* Zr = Z2 + blockIdx.y * z2s;
+  const int rhs = skip.item(blockIdx.y);
+  cplx<R>* Zr = Z2 + rhs * z2s;
   cplx<R> v[E];
   R pm[E];
   const int kk1 = (k1 <= H) ? k1 : L - k1;
-  if (that_tab) That = static_cast<const R*>(that_tab[blockIdx.y]);     // per-item spectrum (batched solves)
+  if (that_tab) That = static_cast<const R*>(that_tab[rhs]);     // per-item spectrum (batched solves)
   // That is half^3 with axis 0 fastest; by symmetry of the kernel the axes
   // may take k0, k1, k2 in any order: index (k2 half + k1) half + k0
   const int sc = act ? slot : H;
@@ -198,11 +200,11 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
     const int chunk = (lv1.n1 + gridDim.x - 1) / gridDim.x;
     const int lo = blockIdx.x * chunk, hi = min(lo + chunk, lv1.n1);
     for (int i = lo + threadIdx.x; i < hi; i += NT) {
-      red[0] += lv1.partG[(long long)blockIdx.y * lv1.n1 + i];
-      red[1] += lv1.partR[(long long)blockIdx.y * lv1.n1 + i];
+      red[0] += lv1.partG[(long long)rhs * lv1.n1 + i];
+      red[1] += lv1.partR[(long long)rhs * lv1.n1 + i];
     }
   }
-  if (skip(blockIdx.y)) return;
+  if (skip(rhs)) return;
   fft_regs<R, L, E, false>(v, buf, tws, t);
   const double wgt = (slot == 0 || slot == H) ? 1.0 : 2.0;
   // terms That_k |V_k|^2 in the grid precision, summed in double
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
   if constexpr (DOT) {
     gofd_cg::block_sum_n<NT, 3>(red, shd);
     if (threadIdx.x == 0) {
-      double* d = dpart + (long long)blockIdx.y * 3 * gridDim.x;
+      double* d = dpart + (long long)rhs * 3 * gridDim.x;
       d[blockIdx.x] = red[0];
       d[gridDim.x + blockIdx.x] = red[1];
       d[2 * gridDim.x + blockIdx.x] = red[2];
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_p3E(const cplx<R>* __restrict
   __shared__ double shf[gofd_cg::block_sum_lds<NT, 3>()];
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
-  const int rhs = blockIdx.y;
+  const int rhs = skip.item(blockIdx.y);
   if (fin.sc && blockIdx.x == gridDim.x - 1) {     // block-uniform: the finishing block
     fin.run<NT>(rhs, shf);
     return;
@@ -398,8 +400,8 @@ int conv3_passC_blocks(const gofd_fdop_s* op, bool fp32) {
 
 int conv3_run(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v64, const float* v32, void* y, bool fp32,
               int passes, const int* skip_flag, int skip_stride, double* dpart, const gofd_cg::Level1& lv1,
-              const gofd_cg::Finish& fin, const void* const* that_tab) {
-  const Skip skip{skip_flag, skip_stride};
+              const gofd_cg::Finish& fin, const void* const* that_tab, const int* amap) {
+  const Skip skip{skip_flag, skip_stride, amap};
   const long long nn = (long long)op->W * op->W * op->W;
   if (fp32) {
     if (v32) {

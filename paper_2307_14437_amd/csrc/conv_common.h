@@ -3,11 +3,15 @@
 
 #include <hip/hip_runtime.h>
 
-// Optional per-rhs flag (a converged solve): blocks of a finished rhs return at once.
+// Optional per-rhs flag (a converged solve): blocks of a finished rhs return
+// at once.  With a map, the launch covers only the rhs listed there: block
+// row blockIdx.y works on rhs map[blockIdx.y].
 struct Skip {
   const int* flag;
   int stride;
+  const int* map = nullptr;
   __device__ __forceinline__ bool operator()(int rhs) const { return flag && flag[(long long)rhs * stride]; }
+  __device__ __forceinline__ int item(int y) const { return map ? map[y] : y; }
 };
 
 // Grid field source of the first pass: nrhs fields of n_nodes values.

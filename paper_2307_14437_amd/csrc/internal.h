@@ -237,6 +237,9 @@ struct GatherSpec {
   double* rp_P = nullptr;
   long long rp_pstride = 0;
   int rp_ent_max = 0;                  // most entries per thread of a row pair (all items)
+  // optional list of the items still iterating: the launches cover nrhs
+  // items, block row y working on item amap[y] (workspaces stay per item)
+  const int* amap = nullptr;
 };
 
 // Apply A_FD with the FFT embedding: input either a grid field (v != nullptr,
@@ -275,7 +278,7 @@ int conv_passB_blocks(const gofd_fdop_s* op, bool fp32);
 // conv3_workspace(op) complex values per rhs.
 int conv3_run(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v64, const float* v32, void* y, bool fp32,
               int passes, const int* skip_flag, int skip_stride, double* dpart, const gofd_cg::Level1& lv1,
-              const gofd_cg::Finish& fin, const void* const* that_tab = nullptr);
+              const gofd_cg::Finish& fin, const void* const* that_tab = nullptr, const int* amap = nullptr);
 long long conv3_workspace(const gofd_fdop_s* op);
 int conv3_passC_blocks(const gofd_fdop_s* op, bool fp32);
 

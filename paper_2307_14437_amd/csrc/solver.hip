@@ -222,11 +222,11 @@ __global__ __launch_bounds__(BS) void k_scatter_cg(const CgItem* __restrict__ it
                                                    double* __restrict__ x, double* __restrict__ p,
                                                    double* __restrict__ s, double* __restrict__ r,
                                                    double* __restrict__ u, int per, double* __restrict__ partG,
-                                                   double* __restrict__ partR) {
+                                                   double* __restrict__ partR, const int* __restrict__ amap) {
   constexpr int VPB = BS / G;                 // vertices per block pass
   constexpr int U = G >= 16 ? 4 : 64 / G;     // entries per lane loaded together (64 per vertex)
   __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
-  const int it = blockIdx.y;
+  const int it = amap ? amap[blockIdx.y] : blockIdx.y;
   const CgItem& I = items[it];
   const long long o = I.off, nv = I.nv;
   const int dk = I.dk;
@@ -307,10 +307,10 @@ __global__ __launch_bounds__(BS) void k_vertex_cg(const CgItem* __restrict__ ite
                                                   double* __restrict__ x, double* __restrict__ p,
                                                   double* __restrict__ s, double* __restrict__ r,
                                                   double* __restrict__ u, double* __restrict__ partG,
-                                                  double* __restrict__ partR) {
+                                                  double* __restrict__ partR, const int* __restrict__ amap) {
   constexpr int PU = 8;                       // slots loaded together
   __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
-  const int it = blockIdx.y;
+  const int it = amap ? amap[blockIdx.y] : blockIdx.y;
   const CgItem& I = items[it];
   const long long o = I.off, nv = I.nv;
   const int dk = I.dk;
@@ -757,6 +757,8 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
 struct Work {
   DevBuf x, r, u, p, s, b, xr, dvec, q, grid;
   DevBuf P;                     // row-pair form: partial slots, double[nitems][slots_max]
+  DevBuf amap;                  // int[nitems]: the items still iterating (first nact entries)
+  int nact = 0;                 // items the iteration's launches cover
   DevBuf scal;                  // Scal[nitems]
   DevBuf partG, partR;          // double[nitems][nbs]: gamma and (r, r) partials
   DevBuf partD;                 // double[nitems][3][pass-B blocks]: partials summed by the column pass
@@ -786,6 +788,8 @@ int reserve_work(gofd_ctx_s* ctx, Work& w, const Batch& B) {
   GOFD_TRY(dev_reserve(ctx, w.partG, sizeof(double) * w.nbs * ni));
   GOFD_TRY(dev_reserve(ctx, w.partR, sizeof(double) * w.nbs * ni));
   GOFD_TRY(dev_reserve(ctx, w.partials, sizeof(double) * 2 * NB_DOT * ni));
+  GOFD_TRY(dev_reserve(ctx, w.amap, sizeof(int) * ni));
+  w.nact = ni;
   GOFD_TRY(dev_reserve(ctx, w.out2, sizeof(double) * 2 * ni));
   return GOFD_OK;
 }
@@ -873,6 +877,8 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
   g.that32_tab = static_cast<const void* const*>(B.tab32.p);
   g.skip = &w.scal.as<Scal>()->done;
   g.skip_stride = (int)(sizeof(Scal) / sizeof(int));
+  const int* amap = w.nact < B.nitems ? w.amap.as<int>() : nullptr;   // the items still iterating
+  g.amap = amap;
   g.dpart = w.partD.as<double>();
   g.lv1.partG = w.partG.as<double>();
   g.lv1.partR = w.partR.as<double>();
@@ -895,24 +901,24 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
       if (k == GOFD_ST_GATHER && fused) continue;
       ctx->timer_start = prof->ev[2 * k];
       ctx->timer_stop = prof->ev[2 * k + 1];
-      GOFD_TRY(conv_apply(ctx, B.op0, B.nitems, nullptr, &g, w.grid.p, fp32,
+      GOFD_TRY(conv_apply(ctx, B.op0, w.nact, nullptr, &g, w.grid.p, fp32,
                           stage_passes[k] | (k == GOFD_ST_PASS_A && fused ? 8 : 0)));
       ctx->timer_start = ctx->timer_stop = nullptr;
     }
     ctx->timer_start = prof->ev[8];
     ctx->timer_stop = prof->ev[9];
   } else {
-    GOFD_TRY(conv_apply(ctx, B.op0, B.nitems, nullptr, &g, w.grid.p, fp32));
+    GOFD_TRY(conv_apply(ctx, B.op0, w.nact, nullptr, &g, w.grid.p, fp32));
   }
-  const dim3 gs(w.nbs, B.nitems);
+  const dim3 gs(w.nbs, w.nact);
   const long long nn = grid_nodes(B.op0);
 #define GOFD_SCATTER_ARGS(Y)                                                                                     \
   B.items.as<CgItem>(), Y, nn, w.scal.as<Scal>(), w.x.as<double>(), w.p.as<double>(), w.s.as<double>(),          \
-      w.r.as<double>(), w.u.as<double>(), w.per, w.partG.as<double>(), w.partR.as<double>()
+      w.r.as<double>(), w.u.as<double>(), w.per, w.partG.as<double>(), w.partR.as<double>(), amap
   if (B.rp)
     GOFD_LAUNCH(ctx, k_vertex_cg, gs, dim3(BS), 0, st, B.items.as<CgItem>(), w.P.as<double>(), g.rp_pstride,
                 w.scal.as<Scal>(), w.x.as<double>(), w.p.as<double>(), w.s.as<double>(), w.r.as<double>(),
-                w.u.as<double>(), w.partG.as<double>(), w.partR.as<double>());
+                w.u.as<double>(), w.partG.as<double>(), w.partR.as<double>(), amap);
   else if (fp32)
     GOFD_LAUNCH(ctx, (k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st, GOFD_SCATTER_ARGS(w.grid.as<float>()));
   else
@@ -973,29 +979,63 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     use_graph = false;                // stages timed one by one, state read every iteration
     check_every = 1;
   }
+  w.nact = ni;                          // every item iterates at the start
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  if (use_graph && !history) {
+  // capture check_every iterations over the current item list (graph replays
+  // keep its launch shapes)
+  auto capture = [&]() -> int {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
       use_graph = false;
-    } else {
-      int rc = GOFD_OK;
-      for (int j = 0; j < check_every && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, B, w, fp32);
-      hipError_t e = hipStreamEndCapture(st, &graph);
-      if (rc != GOFD_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rc;
-      }
-      if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        if (graph) (void)hipGraphDestroy(graph);
-        graph = nullptr;
-        exec = nullptr;
-        use_graph = false;
-      }
+      return GOFD_OK;
     }
-  }
+    int rc = GOFD_OK;
+    for (int j = 0; j < check_every && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, B, w, fp32);
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc != GOFD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      graph = nullptr;
+      return rc;
+    }
+    if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      if (graph) (void)hipGraphDestroy(graph);
+      graph = nullptr;
+      exec = nullptr;
+      use_graph = false;
+    }
+    return GOFD_OK;
+  };
+  if (use_graph && !history) GOFD_TRY(capture());
+  // Active items: once at most half of the items the launches cover still
+  // iterate (or a replacement reopened one outside them), the launches are
+  // narrowed to those items (block rows map to them) and the graph captured
+  // again.  Stopped items would otherwise still occupy launch slots.
+  std::vector<char> in_map(ni, 1);
+  std::vector<int> act_h;
+  auto compact = [&](const std::vector<Scal>& st_) -> int {
+    act_h.clear();
+    bool missing = false;
+    for (int k = 0; k < ni; ++k)
+      if (st_[k].status == ST_OK && !st_[k].done) {
+        act_h.push_back(k);
+        missing = missing || !in_map[k];
+      }
+    if (act_h.empty() || (!missing && 2 * (int)act_h.size() > w.nact)) return GOFD_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(st));          // nothing in flight reads the old list
+    HIP_TRY(ctx, hipMemcpyAsync(w.amap.p, act_h.data(), sizeof(int) * act_h.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    w.nact = (int)act_h.size();
+    std::fill(in_map.begin(), in_map.end(), 0);
+    for (int k : act_h) in_map[k] = 1;
+    if (use_graph) GOFD_TRY(capture());
+    return GOFD_OK;
+  };
   // residual replacement: true residual of x in double precision, then the
   // state's flags from it (reads the state back into tmp)
   std::vector<double> rr_ref(ni, HUGE_VAL);
@@ -1091,6 +1131,9 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
       bool all = true;
       for (int k = 0; k < ni; ++k) all = all && tmp[k].done;
       if (all) break;
+      const int before = w.nact;
+      if ((rc = compact(tmp)) != GOFD_OK) break;
+      if (w.nact != before) nfl = 0;                  // compact drained the stream
     }
   }
   while (it < max_iter && (history || prof) && rc == GOFD_OK) {
