@@ -259,7 +259,7 @@ int conv_rowpass_lines(int L);
 // entries per thread the last row pass fetches ahead (the entry arrays carry
 // that many rows of padding); 16-bit entry code: local node in the low 15
 // bits, RP_END on the last entry of a segment (padding: node 0, weight 0)
-constexpr int RP_SEGCAP = 1024;
+constexpr int RP_SEGCAP = 2048;
 constexpr int RP_EPRE = 32;
 constexpr int RP_NODE = 0x7fff;
 constexpr int RP_END = 0x8000;

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <queue>
+#include <thread>
 
 #include "bary.h"
 #include "internal.h"
@@ -415,69 +417,80 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   if (2 * (int64_t)W > RP_NODE + 1) return GOFD_OK;        // local node numbers must fit the 15-bit code
   // per row pair: segments over the T threads by longest-first onto the
   // least-loaded thread (ties: the lower thread), then laid out thread by
-  // thread, each thread's in vertex order
-  std::vector<int32_t> meta(4 * (size_t)pairs), tseg((size_t)pairs * T), load(T), order, perm;
-  std::vector<std::vector<int32_t>> owned(T);
-  std::vector<uint16_t> code;
-  std::vector<float> w32;
-  std::vector<double> w64;
+  // thread, each thread's in vertex order.  Row pairs are independent: the
+  // plans and then the entries are made by host threads over row pairs.
+  std::vector<int32_t> meta(4 * (size_t)pairs), tseg((size_t)pairs * T), ent(pairs), plan(nseg);
+  auto len = [&](int32_t p) { return seg_b[dest[p]] - seg_a[dest[p]]; };
+  const int nthr = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+  auto parallel_rows = [&](auto&& body) {
+    std::vector<std::thread> pool;
+    for (int h = 0; h < nthr; ++h)
+      pool.emplace_back([&, h]() {
+        for (int r = h; r < pairs; r += nthr) body(r);
+      });
+    for (auto& th : pool) th.join();
+  };
+  parallel_rows([&](int r) {
+    const int32_t s0 = rp_cnt[r], s1 = rp_cnt[r + 1];
+    std::vector<int32_t> order(s1 - s0), load(T, 0);
+    std::vector<std::vector<int32_t>> owned(T);
+    for (int32_t p = s0; p < s1; ++p) order[p - s0] = p;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return len(x) > len(y); });
+    std::priority_queue<std::pair<int32_t, int>, std::vector<std::pair<int32_t, int>>,
+                        std::greater<std::pair<int32_t, int>>> heap;
+    for (int c = 0; c < T; ++c) heap.push({0, c});
+    for (int32_t p : order) {
+      const int k = heap.top().second;
+      heap.pop();
+      load[k] += len(p);
+      owned[k].push_back(p);
+      heap.push({load[k], k});
+    }
+    int32_t pos = s0, e = 0;
+    for (int k = 0; k < T; ++k) {
+      std::sort(owned[k].begin(), owned[k].end());
+      tseg[(size_t)r * T + k] = pos - s0;
+      for (int32_t p : owned[k]) plan[pos++] = dest[p];     // segment (= slot) at each position
+      e = std::max(e, load[k]);
+    }
+    ent[r] = e;
+  });
   int64_t ebase = 0;
   int ent_max = 0;
   for (int r = 0; r < pairs; ++r) {
-    const int32_t s0 = rp_cnt[r], s1 = rp_cnt[r + 1];
-    auto len = [&](int32_t p) { return seg_b[dest[p]] - seg_a[dest[p]]; };
-    order.resize(s1 - s0);
-    for (int32_t p = s0; p < s1; ++p) order[p - s0] = p;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return len(x) > len(y); });
-    std::fill(load.begin(), load.end(), 0);
-    for (auto& o : owned) o.clear();
-    for (int32_t p : order) {
-      int k = 0;
-      for (int c = 1; c < T; ++c)
-        if (load[c] < load[k]) k = c;
-      load[k] += len(p);
-      owned[k].push_back(p);
-    }
-    perm.clear();
-    int32_t ent = 0;
-    for (int k = 0; k < T; ++k) {
-      std::sort(owned[k].begin(), owned[k].end());
-      tseg[(size_t)r * T + k] = (int32_t)perm.size();
-      perm.insert(perm.end(), owned[k].begin(), owned[k].end());
-      ent = std::max(ent, load[k]);
-    }
-    ent_max = std::max(ent_max, ent);
     meta[4 * (size_t)r + 0] = (int32_t)ebase;
-    meta[4 * (size_t)r + 1] = ent;
-    meta[4 * (size_t)r + 2] = s0;
-    meta[4 * (size_t)r + 3] = s1 - s0;
-    code.resize(ebase + (int64_t)ent * T, 0);
-    w32.resize(ebase + (int64_t)ent * T, 0.f);
-    w64.resize(ebase + (int64_t)ent * T, 0.0);
+    meta[4 * (size_t)r + 1] = ent[r];
+    meta[4 * (size_t)r + 2] = rp_cnt[r];
+    meta[4 * (size_t)r + 3] = rp_cnt[r + 1] - rp_cnt[r];
+    ent_max = std::max(ent_max, ent[r]);
+    ebase += (int64_t)ent[r] * T;
+    if (ebase >= ((int64_t)1 << 30)) return GOFD_OK;
+  }
+  // entries (padding: node 0, weight 0; RP_EPRE * T more read ahead past the last row pair)
+  const int64_t total = ebase + (int64_t)RP_EPRE * T;
+  std::vector<uint16_t> code(total, 0);
+  std::vector<float> w32(total, 0.f);
+  std::vector<double> w64(total, 0.0);
+  parallel_rows([&](int r) {
+    const int64_t base = meta[4 * (size_t)r];
+    const int32_t s0 = rp_cnt[r], s1 = rp_cnt[r + 1];
     for (int k = 0; k < T; ++k) {
+      const int32_t p0 = s0 + tseg[(size_t)r * T + k];
+      const int32_t p1 = (k + 1 < T) ? s0 + tseg[(size_t)r * T + k + 1] : s1;
       int64_t m = 0;
-      for (int32_t p : owned[k]) {
-        const int32_t q = dest[p];
+      for (int32_t p = p0; p < p1; ++p) {
+        const int32_t q = plan[p];
         for (int32_t i = seg_a[q]; i < seg_b[q]; ++i, ++m) {
           const int32_t row = node[i] / W, col = node[i] % W;
-          const int64_t at = ebase + m * T + k;
+          const int64_t at = base + m * T + k;
           code[at] = (uint16_t)(((row - 2 * r) * W + col) | (i + 1 == seg_b[q] ? RP_END : 0));
           w64[at] = wv[i];
           w32[at] = (float)wv[i];
         }
       }
     }
-    // the row pair's segments in thread order: slot of each
-    for (size_t i = 0; i < perm.size(); ++i) perm[i] = dest[perm[i]];
-    std::copy(perm.begin(), perm.end(), dest.begin() + s0);
-    ebase += (int64_t)ent * T;
-    if (ebase >= ((int64_t)1 << 30)) return GOFD_OK;
-  }
-  // padding read ahead past the last row pair (no node, weight zero)
-  const int64_t total = ebase + (int64_t)RP_EPRE * T;
-  code.resize(total, 0);
-  w32.resize(total, 0.f);
-  w64.resize(total, 0.0);
+  });
+  dest.swap(plan);                                  // the slot of each segment, row pair by row pair in thread order
   GOFD_TRY(dev_reserve(ctx, tr->rp_meta, sizeof(int32_t) * meta.size()));
   GOFD_TRY(dev_reserve(ctx, tr->rp_tseg, sizeof(int32_t) * tseg.size()));
   GOFD_TRY(dev_reserve(ctx, tr->rp_code, sizeof(uint16_t) * total));
