@@ -211,9 +211,10 @@ int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const 
  * rounding.
  * gofd_autotune times every schedule of the given grid's period on the device
  * (a zero field of the grid's window, 20 launches each after 3 untimed ones,
- * GOFD_FP32_GRID in flags selecting the precision), installs the fastest and
- * returns its number in *sched (host, nullable) and the average durations in
- * ms in times[GOFD_N_COL_SCHED] (host, nullable).  Synchronises.
+ * GOFD_FP32_GRID in flags selecting the precision), installs the fastest
+ * (the default unless another is at least 5 % faster) and returns its number
+ * in *sched (host, nullable) and the average durations in ms in
+ * times[GOFD_N_COL_SCHED] (host, nullable).  Synchronises.
  * gofd_set_schedule installs a known schedule (e.g. from a cache of earlier
  * tuning runs).  Errors: GOFD_E_ARG (bad grid or schedule number),
  * GOFD_E_UNSUPPORTED (d = 3: the 3D passes have one schedule per length),

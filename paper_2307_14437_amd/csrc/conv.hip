@@ -1125,8 +1125,11 @@ static int tune_L(gofd_ctx_s* ctx, int W, double* times) {
       return gofd_fail(ctx, GOFD_E_HIP, "timing the column pass failed");
     }
     times[s] = ms / reps;
-    if (times[s] < times[best]) best = s;
   }
+  // another schedule replaces the default only when clearly faster (5 %):
+  // closer timings are within the noise of this measurement
+  for (int s = 1; s < GOFD_N_COL_SCHED; ++s)
+    if (times[s] < 0.95 * times[0] && times[s] < times[best]) best = s;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIP_TRY(ctx, hipGetLastError());

@@ -27,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # stage of a CG iteration -> kernel symbol fragment (single-precision grid, 2D, L = 2048)
 STAGE_SYMBOLS = {   # fragments that together name the kernel of each stage
     "passA": ("k_passA<float, 2048", "SrcPairGatherRows"),
-    "passB": ("k_passB<float, 2048, 16, 2, true>",),
+    "passB": ("k_passB<float, 2048", "true>"),
     "passC": ("k_passC<float, float, 2048", "true"),
     "scatter": ("k_vertex_cg",),
 }
@@ -62,7 +62,7 @@ def main(argv):
         names = [k for k in F if all(f in k for f in frag)]
         if not names:
             continue
-        k = names[0]
+        k = max(names, key=lambda n: len(F[n]))      # the launch the iterations used most
         f = sum(F[k]) / len(F[k]) * 1024 * kf
         w = sum(Wr[k]) / len(Wr[k]) * 1024 * kw if k in Wr else 0.0
         name = k.replace("(anonymous namespace)::", "").split("(")[0]

@@ -74,7 +74,8 @@ def test_autotune_picks_its_fastest_and_caches(gctx, tmp_path):
         s, times = gofd.autotune(gctx, g, fp32=True, cache=cache)
         print(s, times, flush=True)
         assert 0 <= s < gofd.N_COL_SCHED and len(times) == gofd.N_COL_SCHED
-        assert all(t > 0 for t in times) and times[s] == min(times)
+        assert all(t > 0 for t in times)
+        assert times[s] == min(times) or (s == 0 and min(times) >= 0.95 * times[0])
         data = json.load(open(cache))
         assert len(data) == 1 and list(data.values())[0]["schedule"] == s
         s2, t2 = gofd.autotune(gctx, g, fp32=True, cache=cache)      # served from the cache
