@@ -280,11 +280,13 @@ enum {
 typedef struct {
   int mode;              /* GOFD_MODE_*                                                     */
   int max_iter;          /* total CG iterations allowed (0 = 20000)                         */
-  int check_every;       /* host reads of the convergence flag every k iterations (0 = 8)   */
+  int check_every;       /* host reads of the CG state every k iterations (0 = 8); without  */
+                         /* a graph the chunks shrink to 2 iterations near the tolerance    */
   double inner_tol;      /* FP32_REFINE: relative tolerance of each correction solve (0 =   */
                          /* 1e-5); FP32_RELIABLE: residual drop between replacements (0 = 1e-2) */
   int max_refine;        /* FP32 mode: maximum outer refinement steps (0 = 30)              */
-  int use_graph;         /* capture k CG iterations in a hipGraph and replay it (1 = yes)   */
+  int use_graph;         /* 1: capture k CG iterations in a hipGraph and replay it; 0: launch */
+                         /* the kernels directly (the default: shorter gaps on gfx950)      */
   double* history;       /* optional host array of max_iter+1 relative residuals, or NULL   */
   double* stage_ms;      /* optional host array of GOFD_N_STAGES: the iterations then run   */
                          /* without a graph, each stage bracketed by HIP events on the       */
@@ -322,7 +324,9 @@ int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, in
  * FFT length); within a group the CG iterations of all (problem, rhs) items
  * advance together, every stage of an iteration one kernel launch for the
  * whole group (items index per-item descriptors of their mesh, vectors and
- * kernel spectrum), captured in a hipGraph; converged items are masked.  IC(1)
+ * kernel spectrum), launched directly or from a hipGraph (opts->use_graph);
+ * converged items are masked and, once few remain, the launches narrowed to
+ * them.  IC(1)
  * triangular solves run per problem.  Groups are solved one after another.
  * info: host array of sum(nrhs) entries in problem order (nullable).
  * Errors: as gofd_solve. */

@@ -319,7 +319,7 @@ class Precond:
 STAGES = ("gather", "passA", "passB", "passC", "scatter", "precond")
 
 
-def _opts(mode=MODE_FP64, max_iter=0, check_every=0, inner_tol=0.0, max_refine=0, use_graph=1, history=None,
+def _opts(mode=MODE_FP64, max_iter=0, check_every=0, inner_tol=0.0, max_refine=0, use_graph=0, history=None,
           stage_ms=None):
     o = SolveOpts(int(mode), int(max_iter), int(check_every), float(inner_tol), int(max_refine), int(use_graph),
                   None, None)

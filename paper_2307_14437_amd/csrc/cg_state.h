@@ -109,14 +109,29 @@ struct Level1 {
   int n1 = 0;
 };
 
+// The state of one item into page-locked host memory for the host to read
+// while the device runs on: the fields first, then (after a system-scope
+// fence) pad = 1 as the mark that they are complete.  The host clears the
+// mark before it issues the launch that writes the slot.
+__device__ __forceinline__ void state_to_host(Scal* h, const Scal& S) {
+  Scal H = S;
+  H.pad = 0;
+  *h = H;
+  __threadfence_system();
+  __hip_atomic_store(&h->pad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
+}
+
 // Finishing step run by one block of NT threads: sums the three arrays of nb
 // partials left by the column pass (gamma, (r, r), delta; layout
 // part[rhs][3][nb]) in a fixed order and writes the decided state.  Inactive
-// when sc is null.
+// when sc is null.  With host given (page-locked host memory, one Scal per
+// item), the state also goes there (state_to_host).
 struct Finish {
   Scal* sc = nullptr;
   const double* part = nullptr;
   int nb = 0;
+  Scal* host = nullptr;
 
   template <int NT>
   __device__ __forceinline__ void run(int rhs, double* sh) const {
@@ -141,12 +156,13 @@ struct Finish {
     block_sum_n<NT, 3>(t, sh);
     if (threadIdx.x == 0) {
       const Scal S = sc[rhs];
+      Scal O = S;
       if (!S.done) {
-        Scal O;
         double alpha = 0.0, beta = 0.0;
         cg_decide(S, t[0], t[1], t[2], O, alpha, beta);
         sc[rhs] = O;
       }
+      if (host) state_to_host(host + rhs, O);
     }
   }
 };

@@ -26,8 +26,6 @@ int dev_reserve(gofd_ctx_s* ctx, DevBuf& b, size_t bytes) {
 gofd_ctx_s::~gofd_ctx_s() {
   for (auto& kv : twiddles) delete kv.second;
   if (host_state) (void)hipHostFree(host_state);
-  for (auto& e : check_ev)
-    if (e) (void)hipEventDestroy(e);
   if (ev_in) (void)hipEventDestroy(ev_in);
   if (ev_out) (void)hipEventDestroy(ev_out);
   if (work) (void)hipStreamDestroy(work);

@@ -230,12 +230,15 @@ struct Twiddles {
   __device__ __forceinline__ void load(const cplx<R>* __restrict__ tw, int t) {
     load_from<stage_radix<L, E>(1)>(tw, t);
   }
-  // Between two transforms of one kernel: the compiler may no longer assume
-  // the values unchanged, so it derives the twiddle products of the second
-  // transform again instead of keeping those of the first in registers.
+  // Between two transforms of one kernel (double precision): the compiler may
+  // no longer assume the values unchanged, so it derives the twiddle products
+  // of the second transform again instead of keeping those of the first in
+  // registers, which would not fit.  In single precision they fit and are kept.
   __device__ __forceinline__ void opaque() {
+    if constexpr (sizeof(R) == 8) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) asm volatile("" : "+v"(w[i].x), "+v"(w[i].y));
+      for (int i = 0; i < N; ++i) asm volatile("" : "+v"(w[i].x), "+v"(w[i].y));
+    }
   }
 };
 

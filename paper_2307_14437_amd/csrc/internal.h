@@ -79,11 +79,11 @@ struct gofd_ctx_s {
   // When set, the next kernel launched through GOFD_LAUNCH records these
   // events at its own start and end (stage timing); the launch clears them.
   hipEvent_t timer_start = nullptr, timer_stop = nullptr;
-  // page-locked host copies of the CG state (two slots) and their events:
-  // the host reads one check's state while the next chunk of iterations runs
+  // page-locked host copies of the CG state (two chunk slots, written by the
+  // last iteration of each chunk, and one for a residual replacement): the
+  // host reads one check's state while the next chunk of iterations runs
   void* host_state = nullptr;
   size_t host_state_bytes = 0;
-  hipEvent_t check_ev[2] = {nullptr, nullptr};
   ~gofd_ctx_s();
 };
 

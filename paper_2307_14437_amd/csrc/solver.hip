@@ -25,9 +25,11 @@
 // in single precision; an outer loop in double precision recomputes the true
 // residual r = b - K x with a double-precision product, solves K d = r to a
 // modest relative tolerance and updates x += d (iterative refinement).
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <memory>
 
 #include "bary.h"
@@ -197,17 +199,21 @@ __global__ __launch_bounds__(BS) void k_cg_replace(const CgItem* __restrict__ it
 
 // one block per rhs: after a replacement the true (r, r) decides whether the
 // rhs has converged; a rhs that had stopped on its recursive residual resumes
-// when the true one is still above the tolerance
-__global__ __launch_bounds__(BS) void k_cg_reopen(const double* __restrict__ partR, int nb, Scal* __restrict__ sc) {
+// when the true one is still above the tolerance.  With host given, every
+// rhs's state also goes there (state_to_host).
+__global__ __launch_bounds__(BS) void k_cg_reopen(const double* __restrict__ partR, int nb, Scal* __restrict__ sc,
+                                                  Scal* __restrict__ host) {
   __shared__ double sh[BS];
   const int rhs = blockIdx.x;
   const double rr = sum_fixed(partR + (long long)rhs * nb, nb, sh);
   if (threadIdx.x != 0) return;
   Scal S = sc[rhs];
-  if (S.status != ST_OK) return;
-  S.rr = rr;
-  S.done = (rr <= S.tol2) ? 1 : 0;
-  sc[rhs] = S;
+  if (S.status == ST_OK) {
+    S.rr = rr;
+    S.done = (rr <= S.tol2) ? 1 : 0;
+    sc[rhs] = S;
+  }
+  if (host) state_to_host(host + rhs, S);
 }
 
 // w = mask * I^T y (the product K u, G lanes per vertex) and, in the same
@@ -867,7 +873,9 @@ struct StageProf {
 // with the delta partials and the step decision, scatter with the vector
 // update), then for IC(1) problems the triangular solves u = M^{-1} r with
 // the next gamma.
-int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf* prof = nullptr) {
+// With host_out given, the step decision also stores the state there.
+int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf* prof = nullptr,
+                 Scal* host_out = nullptr) {
   hipStream_t st = ctx->stream;
   GatherSpec g;
   g.items = B.items.as<CgItem>();
@@ -886,6 +894,7 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
   g.fin.sc = w.scal.as<Scal>();
   g.fin.part = w.partD.as<double>();
   g.fin.nb = conv_passB_blocks(B.op0, fp32);
+  g.fin.host = host_out;
   if (B.rp) {
     g.rp_P = w.P.as<double>();
     g.rp_pstride = std::max<long long>(B.slots_max, 1);
@@ -980,38 +989,69 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     check_every = 1;
   }
   w.nact = ni;                          // every item iterates at the start
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  // capture check_every iterations over the current item list (graph replays
-  // keep its launch shapes)
+  // Page-locked state slots for the pipelined checks: chunk slots 0 and 1
+  // (the last iteration of a chunk stores its state there) and slot 2 for a
+  // residual replacement.
+  const bool piped = !history && !prof;
+  Scal* hb = nullptr;       // host view
+  Scal* hd = nullptr;       // device view of the same memory
+  if (piped) {
+    const size_t need_bytes = sizeof(Scal) * 3 * (size_t)ni;
+    if (ctx->host_state_bytes < need_bytes) {
+      if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+      ctx->host_state = nullptr;
+      ctx->host_state_bytes = 0;
+      // coherent: the kernels' stores bypass the device caches
+      HIP_TRY(ctx, hipHostMalloc(&ctx->host_state, need_bytes, hipHostMallocCoherent));
+      ctx->host_state_bytes = need_bytes;
+    }
+    hb = static_cast<Scal*>(ctx->host_state);
+    HIP_TRY(ctx, hipHostGetDevicePointer((void**)&hd, ctx->host_state, 0));
+  }
+  // one chunk of n iterations whose last iteration stores the state into
+  // chunk slot `slot` (none without the pipelined checks)
+  auto chunk_launches = [&](int slot, int n) -> int {
+    for (int j = 0; j < n; ++j)
+      GOFD_TRY(cg_iteration(ctx, B, w, fp32, nullptr, (hd && j == n - 1) ? hd + (size_t)slot * ni : nullptr));
+    return GOFD_OK;
+  };
+  // one graph executable per chunk slot, captured over the current item list
+  // (graph replays keep its launch shapes); two chunks in flight use both
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  auto drop_graphs = [&]() {
+    for (int k = 0; k < 2; ++k) {
+      if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+      if (graph[k]) (void)hipGraphDestroy(graph[k]);
+      exec[k] = nullptr;
+      graph[k] = nullptr;
+    }
+  };
   auto capture = [&]() -> int {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
-    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      (void)hipGetLastError();
-      use_graph = false;
-      return GOFD_OK;
-    }
-    int rc = GOFD_OK;
-    for (int j = 0; j < check_every && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, B, w, fp32);
-    hipError_t e = hipStreamEndCapture(st, &graph);
-    if (rc != GOFD_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      graph = nullptr;
-      return rc;
-    }
-    if (e != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGetLastError();
-      if (graph) (void)hipGraphDestroy(graph);
-      graph = nullptr;
-      exec = nullptr;
-      use_graph = false;
+    drop_graphs();
+    for (int k = 0; k < 2; ++k) {
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        use_graph = false;
+        drop_graphs();
+        return GOFD_OK;
+      }
+      const int rc = chunk_launches(k, check_every);
+      hipError_t e = hipStreamEndCapture(st, &graph[k]);
+      if (rc != GOFD_OK) {
+        drop_graphs();
+        return rc;
+      }
+      if (e != hipSuccess || hipGraphInstantiate(&exec[k], graph[k], nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        drop_graphs();
+        use_graph = false;
+        return GOFD_OK;
+      }
     }
     return GOFD_OK;
   };
-  if (use_graph && !history) GOFD_TRY(capture());
+  if (use_graph && piped) GOFD_TRY(capture());
   // Active items: once at most half of the items the launches cover still
   // iterate (or a replacement reopened one outside them), the launches are
   // narrowed to those items (block rows map to them) and the graph captured
@@ -1033,6 +1073,9 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     w.nact = (int)act_h.size();
     std::fill(in_map.begin(), in_map.end(), 0);
     for (int k : act_h) in_map[k] = 1;
+    if (hb)                 // no launch stores the state of the items left out
+      for (int k = 0; k < ni; ++k)
+        if (!in_map[k]) hb[k] = hb[ni + k] = st_[k];
     if (use_graph) GOFD_TRY(capture());
     return GOFD_OK;
   };
@@ -1047,7 +1090,8 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, ni), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
                        w.q.as<double>(), w.r.as<double>(), w.u.as<double>(), w.scal.as<Scal>(), w.partG.as<double>(),
                        w.partR.as<double>());
-    hipLaunchKernelGGL(k_cg_reopen, dim3(ni), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>());
+    hipLaunchKernelGGL(k_cg_reopen, dim3(ni), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>(),
+                       nullptr);
     HIP_TRY(ctx, hipGetLastError());
     if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
     HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
@@ -1077,76 +1121,129 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
         need = true;
     return need;
   };
-  if (!history && !prof) {
-    // Pipelined checks: up to two chunks of iterations in flight, each
-    // followed by an asynchronous copy of the state into its own page-locked
-    // slot; the host decides on the older chunk's state while the newer one
+  if (piped) {
+    // Pipelined checks: up to two chunks of iterations in flight, the last
+    // iteration of each storing the state into the chunk's page-locked slot
+    // (with a mark per item that the host clears before the issue and polls
+    // for); the host decides on the older chunk's state while the newer one
     // runs.  Items that stopped skip their work in the chunk run past their
-    // stop, and a residual replacement first drains the stream.
-    const size_t need_bytes = sizeof(Scal) * 2 * (size_t)ni;
-    if (ctx->host_state_bytes < need_bytes) {
-      if (ctx->host_state) (void)hipHostFree(ctx->host_state);
-      ctx->host_state = nullptr;
-      ctx->host_state_bytes = 0;
-      HIP_TRY(ctx, hipHostMalloc(&ctx->host_state, need_bytes, hipHostMallocDefault));
-      ctx->host_state_bytes = need_bytes;
-    }
-    for (auto& e : ctx->check_ev)
-      if (!e) HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    Scal* hb = static_cast<Scal*>(ctx->host_state);
-    auto issue = [&](int slot) -> int {
-      if (use_graph) {
-        if (hipGraphLaunch(exec, st) != hipSuccess) return gofd_fail(ctx, GOFD_E_HIP, "graph launch failed");
-      } else {
-        for (int j = 0; j < check_every; ++j) GOFD_TRY(cg_iteration(ctx, B, w, fp32, nullptr));
-      }
-      it += check_every;
-      HIP_TRY(ctx, hipMemcpyAsync(hb + (size_t)slot * ni, w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
-      HIP_TRY(ctx, hipEventRecord(ctx->check_ev[slot], st));
-      return GOFD_OK;
+    // stop.  A residual replacement is queued behind the chunks in flight and
+    // writes its state into slot 2; the states of chunks issued before it are
+    // superseded and not acted on.  Chunks issued after it run on, unless
+    // every item had stopped or is close to its tolerance (the replacement
+    // may confirm the stop).  Without a graph, chunks shrink to two
+    // iterations once every item is within 100x of its tolerance in the
+    // residual norm, so that fewer iterations run past a stop.
+    auto clear_marks = [&](int slot, bool all_items) {
+      for (int k = 0; k < ni; ++k)
+        if (all_items || in_map[k]) hb[(size_t)slot * ni + k].pad = 0;
     };
-    int slot = 0, nfl = 0;       // oldest chunk's slot, chunks in flight
-    while (rc == GOFD_OK) {
-      while (nfl < 2 && it < max_iter && rc == GOFD_OK) {
-        rc = issue((slot + nfl) % 2);
-        ++nfl;
-      }
-      if (rc != GOFD_OK || nfl == 0) break;
-      if (hipEventSynchronize(ctx->check_ev[slot]) != hipSuccess) {
-        rc = gofd_fail(ctx, GOFD_E_HIP, "reading solver state failed");
-        break;
-      }
-      std::copy(hb + (size_t)slot * ni, hb + (size_t)(slot + 1) * ni, tmp.begin());
-      slot = (slot + 1) % 2;
-      --nfl;
-      if (replace_drop > 0.0 && need_replace(tmp)) {
-        if (hipStreamSynchronize(st) != hipSuccess) {
-          rc = gofd_fail(ctx, GOFD_E_HIP, "stream synchronisation failed");
+    // wait until every expected item of the slot carries its mark; a stream
+    // that has gone idle (or failed) without them is an error
+    auto wait_marks = [&](int slot, bool all_items) -> int {
+      const volatile Scal* v = hb + (size_t)slot * ni;
+      for (long long spin = 0;; ++spin) {
+        bool ready = true;
+        for (int k = 0; k < ni && ready; ++k)
+          if (all_items || in_map[k]) ready = v[k].pad == 1;
+        if (ready) break;
+        if ((spin & 1023) == 1023) {
+          const hipError_t q = hipStreamQuery(st);
+          if (q == hipErrorNotReady) continue;
+          if (q != hipSuccess) return gofd_fail(ctx, GOFD_E_HIP, "solver iterations failed");
+          bool late = true;        // the stream is idle: the marks must be there now
+          for (int k = 0; k < ni && late; ++k)
+            if (all_items || in_map[k]) late = v[k].pad == 1;
+          if (!late) return gofd_fail(ctx, GOFD_E_HIP, "solver state not written");
           break;
         }
-        nfl = 0;
-        if ((rc = replace_residual(tmp)) != GOFD_OK) break;
-        if (n_replace) ++*n_replace;
+        __builtin_ia32_pause();
+      }
+      std::atomic_thread_fence(std::memory_order_acquire);
+      return GOFD_OK;
+    };
+    auto issue = [&](int slot, int n) -> int {
+      clear_marks(slot, false);
+      if (use_graph) {
+        if (hipGraphLaunch(exec[slot], st) != hipSuccess) return gofd_fail(ctx, GOFD_E_HIP, "graph launch failed");
+      } else {
+        GOFD_TRY(chunk_launches(slot, n));
+      }
+      it += n;
+      return GOFD_OK;
+    };
+    auto issue_replace = [&]() -> int {
+      clear_marks(2, true);
+      GOFD_TRY(apply_K_plain(ctx, B, w, w.x.as<double>(), w.q.as<double>()));
+      hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, ni), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
+                         w.q.as<double>(), w.r.as<double>(), w.u.as<double>(), w.scal.as<Scal>(),
+                         w.partG.as<double>(), w.partR.as<double>());
+      hipLaunchKernelGGL(k_cg_reopen, dim3(ni), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>(),
+                         hd + 2 * (size_t)ni);
+      HIP_TRY(ctx, hipGetLastError());
+      if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
+      return GOFD_OK;
+    };
+    // every item stopped or within 100x of its tolerance (residual norm)
+    auto near_stop = [&](const std::vector<Scal>& st_) {
+      bool near = true;
+      for (int k = 0; k < ni; ++k) near = near && (st_[k].done || st_[k].rr <= 1e4 * st_[k].tol2);
+      return near;
+    };
+    std::deque<int> fl;      // slots of the launches in flight, in stream order
+    int next = 0;            // chunk slot of the next chunk
+    int nch = 0;             // chunks in flight
+    int chunk = check_every; // iterations per chunk
+    bool superseded = false; // a replacement is in flight
+    bool hold = false;       // issue no chunk until the replacement's state is read
+    while (rc == GOFD_OK) {
+      while (!hold && nch < 2 && it < max_iter && rc == GOFD_OK) {
+        rc = issue(next, use_graph ? check_every : chunk);
+        fl.push_back(next);
+        ++nch;
+        next ^= 1;
+      }
+      if (rc != GOFD_OK || fl.empty()) break;
+      const int slot = fl.front();
+      fl.pop_front();
+      if ((rc = wait_marks(slot, slot == 2)) != GOFD_OK) break;
+      std::copy(hb + (size_t)slot * ni, hb + (size_t)(slot + 1) * ni, tmp.begin());
+      if (slot == 2) {
+        for (int k = 0; k < ni; ++k) {
+          rr_ref[k] = tmp[k].rr;
+          settled[k] = tmp[k].done ? 1 : 0;
+        }
+        superseded = hold = false;
+      } else {
+        --nch;
+        if (superseded) continue;
+        if (near_stop(tmp)) chunk = std::min(chunk, 2);
+        if (replace_drop > 0.0 && need_replace(tmp)) {
+          if ((rc = issue_replace()) != GOFD_OK) break;
+          fl.push_back(2);
+          superseded = true;
+          if (n_replace) ++*n_replace;
+          hold = near_stop(tmp);
+          continue;
+        }
       }
       bool all = true;
       for (int k = 0; k < ni; ++k) all = all && tmp[k].done;
       if (all) break;
       const int before = w.nact;
       if ((rc = compact(tmp)) != GOFD_OK) break;
-      if (w.nact != before) nfl = 0;                  // compact drained the stream
+      if (w.nact != before) {                          // compact drained the stream
+        fl.clear();
+        nch = 0;
+      }
     }
   }
-  while (it < max_iter && (history || prof) && rc == GOFD_OK) {
+  // residual history or stage timing: no graph, the state read after every
+  // iteration (stage timing: every check_every, which it set to one)
+  while (it < max_iter && !piped && rc == GOFD_OK) {
     const int chunk = history ? 1 : check_every;
-    if (use_graph && !history) {
-      if (hipGraphLaunch(exec, st) != hipSuccess) {
-        rc = gofd_fail(ctx, GOFD_E_HIP, "graph launch failed");
-        break;
-      }
-    } else {
-      for (int j = 0; j < chunk && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, B, w, fp32, prof);
-      if (rc != GOFD_OK) break;
-    }
+    for (int j = 0; j < chunk && rc == GOFD_OK; ++j) rc = cg_iteration(ctx, B, w, fp32, prof);
+    if (rc != GOFD_OK) break;
     it += chunk;
     if (hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
@@ -1163,9 +1260,8 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     for (int k = 0; k < ni; ++k) all = all && tmp[k].done;
     if (all) break;
   }
-  (void)hipStreamSynchronize(st);       // a chunk may still run: finish it before the graph goes
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamSynchronize(st);       // a chunk may still run: finish it before the graphs go
+  drop_graphs();
   if (rc != GOFD_OK) return rc;
   HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -1226,7 +1322,7 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
   const int mode = o ? o->mode : GOFD_MODE_FP64;
   const int max_iter = (o && o->max_iter > 0) ? o->max_iter : 20000;
   const int check = (o && o->check_every > 0) ? o->check_every : 8;
-  const bool graph = o ? o->use_graph != 0 : true;
+  const bool graph = o ? o->use_graph != 0 : false;
   double* history = o ? o->history : nullptr;
   StageProf profobj(o && o->stage_ms);
   StageProf* prof = (o && o->stage_ms) ? &profobj : nullptr;

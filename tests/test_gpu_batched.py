@@ -94,3 +94,17 @@ def test_batched_fp32_replacement_count(gctx):
         assert i["status"] == 0 and i["rel_residual"] <= tol
         # (r, r) falls by tol^2 overall, drop^2 per replacement, plus one at each item's stop
         assert i["refinements"] <= round(np.log(tol) / np.log(drop)) + 4
+
+
+def test_batched_direct_launches_match_graph_replay(gctx):
+    # per-item arithmetic does not depend on the launch path, the check interval
+    # or the narrowing of the launches to the items still iterating
+    import paper_2307_14437_amd as gofd
+    P = _problems(gctx)
+    args = ([p["tr"] for p in P], [p["op"] for p in P], [p["pc"] for p in P], [_dev(p["f"]) for p in P])
+    ref, iref = gofd.solve_batched(gctx, *args, tol=1e-12, use_graph=1)
+    for ug, ce in ((0, 8), (0, 1), (1, 2)):
+        us, infos = gofd.solve_batched(gctx, *args, tol=1e-12, use_graph=ug, check_every=ce)
+        assert [i["iterations"] for i in infos] == [i["iterations"] for i in iref], (ug, ce)
+        for a, b in zip(us, ref):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), (ug, ce)

@@ -220,3 +220,24 @@ def test_stage_timing_reports_every_stage(gctx, c1_setup):
     assert i1[0]["iterations"] == i0[0]["iterations"]                  # same iterates without the graph
     assert np.array_equal(u0.cpu().numpy(), u1.cpu().numpy())
 
+
+
+@pytest.mark.parametrize("pc_name", ["NONE", "IC1_9"])
+def test_direct_launches_match_graph_replay(gctx, c1_setup, pc_name):
+    # the same kernels in the same order: FP64 iterates agree bit for bit whatever
+    # the check interval and launch path; with reliable updating the replacement
+    # points follow the checks, so results agree to the solve tolerance
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    f = _dev(np.ones((g.W, g.W)))
+    pc = gofd.Precond(gctx, tr, op, pc_name)
+    ref, iref = gofd.solve(gctx, tr, op, f, tol=1e-12, pc=pc, use_graph=1)
+    ref = ref.cpu().numpy()
+    for ug, ce in ((1, 3), (0, 1), (0, 3), (0, 8)):
+        u, info = gofd.solve(gctx, tr, op, f, tol=1e-12, pc=pc, use_graph=ug, check_every=ce)
+        assert info[0]["iterations"] == iref[0]["iterations"], (ug, ce)
+        assert np.array_equal(u.cpu().numpy(), ref), (ug, ce)
+    for ug in (1, 0):
+        u, info = gofd.solve(gctx, tr, op, f, tol=1e-11, pc=pc, use_graph=ug, mode=gofd.MODE_FP32_RELIABLE)
+        assert info[0]["rel_residual"] <= 1e-11
+        assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref), ug
