@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="restarted-refinement comparison: inner tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
+    ap.add_argument("--col-schedule", type=int, default=-1,
+                    help="column-pass schedule for both precisions instead of tuning it (counter runs)")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -159,7 +161,11 @@ def main():
     _sync(); t = time.perf_counter()
     sched = {}
     for fp32 in (True, False):
-        sc, times = gofd.autotune(ctx, g, fp32=fp32)
+        if args.col_schedule >= 0:
+            sc, times = args.col_schedule, []
+            gofd.set_schedule(ctx, g, sc, fp32=fp32)
+        else:
+            sc, times = gofd.autotune(ctx, g, fp32=fp32)
         sched["fp32" if fp32 else "fp64"] = {"schedule": sc, "values_per_thread_slots_per_block":
                                              list(gofd.COL_SCHEDULES[sc]),
                                              "candidates_us": [round(x * 1e3, 2) for x in times]}

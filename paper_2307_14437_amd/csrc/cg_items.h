@@ -32,6 +32,9 @@ struct CgItem {
   const double* rp_w64;
   const int* rp_dest;
   const int* pv_off;          // partial slots of each vertex
+  const int* rp_pos;          // row-pair-major position of each slot
+  const int4* seg_row;        // per node: local segments and weights of the FP32 gather through the slots
+  const float* seg_row_w2;
   GridGeom g;
   long long nv;               // vertices of the mesh
   long long off;              // offset of the item's vectors in the batch vectors

@@ -345,6 +345,63 @@ struct SrcPairGatherRows {
   }
 };
 
+// The FP32 gather of batch item `it` through its row pair's slots: the line's
+// threads stage the slot values of the row pair (one per vertex with entries
+// in its two rows, at row-pair-major positions meta.z ..) in LDS while the
+// node rows load, and each node then adds its three weighted values from
+// there.  No load waits for another load's result but for the row pair's
+// descriptor.
+struct SrcPairSegRows {
+  const CgItem* items;
+  const float* us;
+  long long ustride;
+  template <typename R, int E, int TPL>
+  __device__ __forceinline__ void load(int it, int row0, int W, int t, cplx<R>* v) const {
+    const PairCols<E, TPL> pc(row0, W);
+    constexpr int M = PairCols<E, TPL>::M;
+    constexpr int LINES = TPL >= 64 ? 1 : 64 / TPL;     // row pairs per block of the row passes
+    constexpr int SEGL = RP_SEGCAP / LINES;              // slots a row pair may have
+    constexpr int NLD = SEGL / TPL;
+    static_assert(NLD * TPL == SEGL, "slot staging");
+    __shared__ float su[RP_SEGCAP];
+    const CgItem& I = items[it];
+    const int rp = min(row0 >> 1, ((W + 1) >> 1) - 1);
+    const int4 meta = gload(reinterpret_cast<const int4*>(I.rp_meta), rp);   // z: first slot, w: slots
+    int4 a[2 * M];
+    float w2[2 * M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int cc = pc.clamp(pc.col(t, m), W);
+      const long long k0 = (long long)pc.r0c * W + cc, k1 = (long long)pc.r1c * W + cc;
+      a[m] = gload(I.seg_row, k0);
+      a[M + m] = gload(I.seg_row, k1);
+      w2[m] = gmem(I.seg_row_w2)[k0];
+      w2[M + m] = gmem(I.seg_row_w2)[k1];
+    }
+    const float* ui = us + it * ustride + (meta.w > 0 ? meta.z : 0);
+    float uv[NLD];
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int idx = t + j * TPL;
+      uv[j] = gmem(ui)[idx < meta.w ? idx : 0];
+    }
+    float* sl = su + (threadIdx.x / TPL) * SEGL;
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) sl[t + j * TPL] = (t + j * TPL < meta.w) ? uv[j] : 0.f;
+    __syncthreads();
+    double val[2 * M];
+#pragma unroll
+    for (int j = 0; j < 2 * M; ++j) {
+      const int s0 = a[j].x & 0xffff, s1 = (int)((unsigned)a[j].x >> 16), s2 = a[j].y;
+      float x = __int_as_float(a[j].z) * sl[s0];
+      x = fmaf(__int_as_float(a[j].w), sl[s1], x);
+      x = fmaf(w2[j], sl[s2], x);
+      val[j] = (double)x;
+    }
+    pc.template put<R>(v, t, W, val, val + M);
+  }
+};
+
 // ---------------------------------------------------------------- spectra layout
 // Z holds, per rhs, the L/2 column slots of the W window rows after the row
 // transform, in tiles of four slots: Z[slot/4][row][slot%4].  A block of the
@@ -732,10 +789,13 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
 
 // ---------------------------------------------------------------- launch
 
-// Values per thread of the row passes (A, C) and of the default column-pass
-// schedule (B): build-time knobs, powers of two in 4..16.
+// Values per thread of the row passes (C; A unless set apart) and of the
+// default column-pass schedule (B): build-time knobs, powers of two in 4..16.
 #ifndef GOFD_FFT_E_ROWS
 #define GOFD_FFT_E_ROWS 8
+#endif
+#ifndef GOFD_FFT_E_PASSA
+#define GOFD_FFT_E_PASSA GOFD_FFT_E_ROWS
 #endif
 #ifndef GOFD_FFT_E_COLS
 #define GOFD_FFT_E_COLS 16
@@ -751,6 +811,12 @@ struct Cfg {
   static constexpr int TA = L / EA;                                         // threads per row pair
   static constexpr int LINES_A = (TA >= 64) ? 1 : 64 / TA;                  // row pairs per block
   static_assert(LINES_A * TA <= 1024 && LINES_A * padded_len<L, EA>() * (int)sizeof(cplx<R>) <= 150 * 1024,
+                "row pass block");
+  // the forward row pass (A)
+  static constexpr int E1 = (L >= GOFD_FFT_E_PASSA) ? GOFD_FFT_E_PASSA : L;
+  static constexpr int T1 = L / E1;
+  static constexpr int LINES_1 = (T1 >= 64) ? 1 : 64 / T1;
+  static_assert(LINES_1 * T1 <= 1024 && LINES_1 * padded_len<L, E1>() * (int)sizeof(cplx<R>) <= 150 * 1024,
                 "row pass block");
 };
 
@@ -828,8 +894,8 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   const int nbA = (pairs + C::LINES_A - 1) / C::LINES_A;
   hipStream_t st = ctx->stream;
   if (passes & 1)
-    GOFD_LAUNCH(ctx, (k_passA<R, L, C::EA, C::LINES_A, Src>), dim3(nbA, nrhs), dim3(C::LINES_A * C::TA), 0, st,
-                       src, Z, W, tw, zs, skip);
+    GOFD_LAUNCH(ctx, (k_passA<R, L, C::E1, C::LINES_1, Src>), dim3((pairs + C::LINES_1 - 1) / C::LINES_1, nrhs),
+                dim3(C::LINES_1 * C::T1), 0, st, src, Z, W, tw, zs, skip);
   if (passes & 2) {
     switch (col_sched(ctx, L, sizeof(R) == 4)) {
       case 1: launch_passB_s<R, L, 1>(ctx, st, nrhs, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab); break;
@@ -995,8 +1061,15 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if (conv_gather_fused(op, fp32) && g->items && (passes & 8) && (passes & 1)) {
     // the FP32 gather of a batch runs inside the first row pass
-    SrcPairGatherRows src{g->items, g->ubase, g->items_mask ? 1 : 0};
     const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_max};
+#if GOFD_FFT_E_PASSA == GOFD_FFT_E_ROWS      // the slot capacity of a row pair follows the row passes' lines
+    if (g->rp_us && d == 2) {
+      SrcPairSegRows src{g->items, g->rp_us, g->rp_pstride};
+      return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes & 7, skip, dpart, lv1, fin,
+                                that_tab, rs);
+    }
+#endif
+    SrcPairGatherRows src{g->items, g->ubase, g->items_mask ? 1 : 0};
     return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes & 7, skip, dpart, lv1, fin,
                               that_tab, rs);
   }

@@ -140,6 +140,7 @@ struct gofd_transfer_s {
   // 2D row-pair form of I^T (the last row pass sums each vertex's entries in
   // its rows; see build_rowpairs): present when rp_ok
   bool rp_ok = false;
+  bool seg_rows_ok = false;   // seg_row / rp_pos present (at most three entries per node)
   int64_t n_slots = 0;  // partial sums: one per (vertex, row pair) with entries
   int rp_ent_max = 0;   // most entries of a thread in a row pair
   DevBuf rp_meta;    // int4[pairs]: entry base, entries per thread, segment base, segments
@@ -149,6 +150,11 @@ struct gofd_transfer_s {
   DevBuf rp_w64;     // double[...]: weights (csc_w values)
   DevBuf rp_dest;    // int32[segments]: partial slot of each segment (vertex-major)
   DevBuf pv_off;     // int32[nv + 1]: partial slots of each vertex
+  // the FP32 gather through the segments: the slot values of a row pair are
+  // staged in LDS, and each node reads its (up to) three from there
+  DevBuf rp_pos;     // int32[segments]: row-pair-major position of each slot (inverse of rp_dest)
+  DevBuf seg_row;    // int4[n_nodes]: local segment of corners 0 | 1 << 16, corner 2, bits of weights 0 and 1
+  DevBuf seg_row_w2; // float[n_nodes]: weight of corner 2 (weights as in rp_w32; zero outside)
   std::vector<int32_t> elems_host;
   std::vector<uint8_t> bmask_host;
   std::vector<double> X_host;
@@ -237,6 +243,10 @@ struct GatherSpec {
   double* rp_P = nullptr;
   long long rp_pstride = 0;
   int rp_ent_max = 0;                  // most entries per thread of a row pair (all items)
+  // with rp_us as well (every item has seg_row): the FP32 gather reads the
+  // vector's values per slot (item it at rp_us + it * rp_pstride, row-pair-major
+  // positions) instead of per vertex
+  const float* rp_us = nullptr;
   // optional list of the items still iterating: the launches cover nrhs
   // items, block row y working on item amap[y] (workspaces stay per item)
   const int* amap = nullptr;

@@ -313,7 +313,8 @@ __global__ __launch_bounds__(BS) void k_vertex_cg(const CgItem* __restrict__ ite
                                                   double* __restrict__ x, double* __restrict__ p,
                                                   double* __restrict__ s, double* __restrict__ r,
                                                   double* __restrict__ u, double* __restrict__ partG,
-                                                  double* __restrict__ partR, const int* __restrict__ amap) {
+                                                  double* __restrict__ partR, const int* __restrict__ amap,
+                                                  float* __restrict__ us) {
   constexpr int PU = 8;                       // slots loaded together
   __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
   const int it = amap ? amap[blockIdx.y] : blockIdx.y;
@@ -336,8 +337,13 @@ __global__ __launch_bounds__(BS) void k_vertex_cg(const CgItem* __restrict__ ite
   const double vm = imask[vc], vs = s[o + vc], vp = p[o + vc], vu = u[o + vc], vr = r[o + vc], vx = x[o + vc],
                vd = dscale[vc];
   double pp[PU];
+  int ps[PU];
+  const auto pos = gmem(I.rp_pos);
 #pragma unroll
   for (int k = 0; k < PU; ++k) pp[k] = Pi[a + k < b ? a + k : 0];
+  if (us)
+#pragma unroll
+    for (int k = 0; k < PU; ++k) ps[k] = pos[a + k < b ? a + k : 0];
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < PU; ++k)
@@ -358,12 +364,34 @@ __global__ __launch_bounds__(BS) void k_vertex_cg(const CgItem* __restrict__ ite
       const double un = dk ? rn * vd : rn;
       u[o + v] = un;
       acc2[1] = rn * un;
+      if (us) {                               // u at the vertex's slots for the next gather
+        float* ui = us + it * pstride;
+        const float uf = (float)un;
+#pragma unroll
+        for (int k = 0; k < PU; ++k)
+          if (a + k < b) ui[ps[k]] = uf;
+        for (int i = a + PU; i < b; ++i) ui[pos[i]] = uf;
+      }
     }
   }
   block_sum_n<BS, 2>(acc2, sh);
   if (threadIdx.x == 0) {
     partR[(long long)it * gridDim.x + blockIdx.x] = acc2[0];
     if (dk >= 0) partG[(long long)it * gridDim.x + blockIdx.x] = acc2[1];
+  }
+}
+
+// u at every slot of each vertex (row-pair-major positions), for the FP32
+// gather through the slots: after the start and after a residual replacement
+// (the vertex kernel keeps it current in between).  Item blockIdx.y.
+__global__ __launch_bounds__(BS) void k_u_to_slots(const CgItem* __restrict__ items, const double* __restrict__ u,
+                                                   float* __restrict__ us, long long ustride) {
+  const int it = blockIdx.y;
+  const CgItem& I = items[it];
+  float* ui = us + it * ustride;
+  for (long long v = (long long)blockIdx.x * BS + threadIdx.x; v < I.nv; v += (long long)gridDim.x * BS) {
+    const float uf = (float)u[I.off + v];
+    for (int i = I.pv_off[v]; i < I.pv_off[v + 1]; ++i) ui[I.rp_pos[i]] = uf;
   }
 }
 
@@ -685,6 +713,7 @@ struct Batch {
   long long ntot = 0, nv_max = 0;
   bool any_ic = false;
   bool rp = true;                  // every transfer has the row-pair form of I^T
+  bool seg = true;                 // ... and the per-node segment rows (FP32 gather through the slots)
   long long slots_max = 0;         // most partial slots of an item
   int rp_ent_max = 0;              // most entries per thread of a row pair
   gofd_fdop_s* op0 = nullptr;      // shape and FFT workspaces of the batch
@@ -706,6 +735,7 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
     B.any_ic = B.any_ic || is_ic(P.pc);
     B.nv_max = std::max<long long>(B.nv_max, tr->nv);
     B.rp = B.rp && tr->rp_ok;
+    B.seg = B.seg && tr->rp_ok && tr->seg_rows_ok;
     B.slots_max = std::max<long long>(B.slots_max, tr->n_slots);
     B.rp_ent_max = std::max(B.rp_ent_max, tr->rp_ent_max);
     for (int k = 0; k < P.nrhs; ++k) {
@@ -731,6 +761,11 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
         I.rp_w64 = tr->rp_w64.as<double>();
         I.rp_dest = tr->rp_dest.as<int>();
         I.pv_off = tr->pv_off.as<int>();
+        if (tr->seg_rows_ok) {
+          I.rp_pos = tr->rp_pos.as<int>();
+          I.seg_row = tr->seg_row.as<int4>();
+          I.seg_row_w2 = tr->seg_row_w2.as<float>();
+        }
       }
       I.g.d = tr->d;
       I.g.W = tr->W;
@@ -749,6 +784,7 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
   }
   B.nitems = (int)h.size();
   B.ntot = off;
+  B.seg = B.seg && B.rp && !B.any_ic;        // IC(1) makes u in its own kernels
   GOFD_TRY(dev_reserve(ctx, B.items, sizeof(CgItem) * h.size()));
   GOFD_TRY(dev_reserve(ctx, B.tab64, sizeof(void*) * h.size()));
   GOFD_TRY(dev_reserve(ctx, B.tab32, sizeof(void*) * h.size()));
@@ -763,6 +799,7 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
 struct Work {
   DevBuf x, r, u, p, s, b, xr, dvec, q, grid;
   DevBuf P;                     // row-pair form: partial slots, double[nitems][slots_max]
+  DevBuf us;                    // with the segment rows: u per slot, float[nitems][slots_max] (row-pair-major)
   DevBuf amap;                  // int[nitems]: the items still iterating (first nact entries)
   int nact = 0;                 // items the iteration's launches cover
   DevBuf scal;                  // Scal[nitems]
@@ -784,6 +821,7 @@ int reserve_work(gofd_ctx_s* ctx, Work& w, const Batch& B) {
   if (B.rp) {
     // vertex kernel: one vertex per thread
     GOFD_TRY(dev_reserve(ctx, w.P, sizeof(double) * std::max<long long>(B.slots_max, 1) * ni));
+    if (B.seg) GOFD_TRY(dev_reserve(ctx, w.us, sizeof(float) * std::max<long long>(B.slots_max, 1) * ni));
     w.per = 1;
     w.nbs = (int)std::max<long long>(1, (B.nv_max + BS - 1) / BS);
   } else {
@@ -873,6 +911,16 @@ struct StageProf {
 // with the delta partials and the step decision, scatter with the vector
 // update), then for IC(1) problems the triangular solves u = M^{-1} r with
 // the next gamma.
+// whether the FP32 gather of the iterations reads u per slot
+static bool seg_gather(const Batch& B, bool fp32) { return B.rp && B.seg && fp32 && conv_gather_fused(B.op0, fp32); }
+
+// u per slot from u (before the first iteration and after a replacement)
+static void refresh_slots(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32) {
+  if (!seg_gather(B, fp32)) return;
+  hipLaunchKernelGGL(k_u_to_slots, dim3(w.nbs, B.nitems), dim3(BS), 0, ctx->stream, B.items.as<CgItem>(),
+                     w.u.as<double>(), w.us.as<float>(), std::max<long long>(B.slots_max, 1));
+}
+
 // With host_out given, the step decision also stores the state there.
 int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf* prof = nullptr,
                  Scal* host_out = nullptr) {
@@ -899,6 +947,7 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
     g.rp_P = w.P.as<double>();
     g.rp_pstride = std::max<long long>(B.slots_max, 1);
     g.rp_ent_max = B.rp_ent_max;
+    if (seg_gather(B, fp32)) g.rp_us = w.us.as<float>();
   }
   if (prof) {
     // the same launches one stage at a time, each kernel recording its own
@@ -927,7 +976,7 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
   if (B.rp)
     GOFD_LAUNCH(ctx, k_vertex_cg, gs, dim3(BS), 0, st, B.items.as<CgItem>(), w.P.as<double>(), g.rp_pstride,
                 w.scal.as<Scal>(), w.x.as<double>(), w.p.as<double>(), w.s.as<double>(), w.r.as<double>(),
-                w.u.as<double>(), w.partG.as<double>(), w.partR.as<double>(), amap);
+                w.u.as<double>(), w.partG.as<double>(), w.partR.as<double>(), amap, g.rp_us ? w.us.as<float>() : nullptr);
   else if (fp32)
     GOFD_LAUNCH(ctx, (k_scatter_cg<float, float, SCAT_G>), gs, dim3(BS), 0, st, GOFD_SCATTER_ARGS(w.grid.as<float>()));
   else
@@ -981,6 +1030,7 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
                      w.partG.as<double>(), w.partR.as<double>());
   hipLaunchKernelGGL(k_cg_init, dim3(ni), dim3(BS), 0, st, w.partG.as<double>(), w.partR.as<double>(), w.nbs,
                      w.scal.as<Scal>(), tol);
+  refresh_slots(ctx, B, w, fp32);
   HIP_TRY(ctx, hipGetLastError());
   hs.resize(ni);
   check_every = std::max(1, check_every);
@@ -1092,6 +1142,7 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
                        w.partR.as<double>());
     hipLaunchKernelGGL(k_cg_reopen, dim3(ni), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>(),
                        nullptr);
+    refresh_slots(ctx, B, w, fp32);
     HIP_TRY(ctx, hipGetLastError());
     if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
     HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
@@ -1180,6 +1231,7 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
                          w.partG.as<double>(), w.partR.as<double>());
       hipLaunchKernelGGL(k_cg_reopen, dim3(ni), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>(),
                          hd + 2 * (size_t)ni);
+      refresh_slots(ctx, B, w, fp32);
       HIP_TRY(ctx, hipGetLastError());
       if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
       return GOFD_OK;

@@ -4,6 +4,7 @@
 // Section 3.1 of the paper: (I_h^FD)_{k,j} = phi_j(x_k^FD) (eq. IhFD-1); a node
 // outside the closed mesh has a zero row; D_{h,j} = sum_k (I_h^FD)_{k,j}.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -374,6 +375,7 @@ static double min_height(int d, const std::vector<double>& X, const std::vector<
 static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vector<int32_t>& offh) {
   hipStream_t st = ctx->stream;
   tr->rp_ok = false;
+  tr->seg_rows_ok = false;
   if (tr->d != 2 || tr->nnz == 0) return GOFD_OK;
   const int64_t nv = tr->nv, nnz = tr->nnz;
   const int W = tr->W;
@@ -471,6 +473,13 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   std::vector<uint16_t> code(total, 0);
   std::vector<float> w32(total, 0.f);
   std::vector<double> w64(total, 0.0);
+  // per node: the local segments (position within the row pair) and weights
+  // of its entries, for the FP32 gather through the slots
+  const int64_t n_nodes = (int64_t)W * W;
+  std::vector<int32_t> srow(4 * (size_t)n_nodes, 0);
+  std::vector<float> srow_w2(n_nodes, 0.f);
+  std::vector<uint8_t> scnt(n_nodes, 0);
+  std::atomic<bool> srow_ok{true};
   parallel_rows([&](int r) {
     const int64_t base = meta[4 * (size_t)r];
     const int32_t s0 = rp_cnt[r], s1 = rp_cnt[r + 1];
@@ -486,11 +495,29 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
           code[at] = (uint16_t)(((row - 2 * r) * W + col) | (i + 1 == seg_b[q] ? RP_END : 0));
           w64[at] = wv[i];
           w32[at] = (float)wv[i];
+          // the nodes of rows 2r, 2r+1 belong to this row pair only
+          const int64_t n = node[i];
+          const int c = scnt[n]++;
+          const int32_t loc = p - s0;
+          if (c == 0) {
+            srow[4 * n] = loc;
+            srow[4 * n + 2] = (int32_t)__builtin_bit_cast(uint32_t, (float)wv[i]);
+          } else if (c == 1) {
+            srow[4 * n] |= loc << 16;
+            srow[4 * n + 3] = (int32_t)__builtin_bit_cast(uint32_t, (float)wv[i]);
+          } else if (c == 2) {
+            srow[4 * n + 1] = loc;
+            srow_w2[n] = (float)wv[i];
+          } else {
+            srow_ok = false;
+          }
         }
       }
     }
   });
   dest.swap(plan);                                  // the slot of each segment, row pair by row pair in thread order
+  std::vector<int32_t> pos(std::max<int64_t>(nseg, 1), 0);
+  for (int64_t p = 0; p < nseg; ++p) pos[dest[p]] = (int32_t)p;
   GOFD_TRY(dev_reserve(ctx, tr->rp_meta, sizeof(int32_t) * meta.size()));
   GOFD_TRY(dev_reserve(ctx, tr->rp_tseg, sizeof(int32_t) * tseg.size()));
   GOFD_TRY(dev_reserve(ctx, tr->rp_code, sizeof(uint16_t) * total));
@@ -505,6 +532,17 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   HIP_TRY(ctx, hipMemcpyAsync(tr->rp_w64.p, w64.data(), sizeof(double) * total, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(tr->rp_dest.p, dest.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, st));
   HIP_TRY(ctx, hipMemcpyAsync(tr->pv_off.p, pv.data(), sizeof(int32_t) * (nv + 1), hipMemcpyHostToDevice, st));
+  tr->seg_rows_ok = srow_ok;
+  if (srow_ok) {
+    GOFD_TRY(dev_reserve(ctx, tr->rp_pos, sizeof(int32_t) * pos.size()));
+    GOFD_TRY(dev_reserve(ctx, tr->seg_row, sizeof(int32_t) * srow.size()));
+    GOFD_TRY(dev_reserve(ctx, tr->seg_row_w2, sizeof(float) * srow_w2.size()));
+    HIP_TRY(ctx, hipMemcpyAsync(tr->rp_pos.p, pos.data(), sizeof(int32_t) * pos.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(tr->seg_row.p, srow.data(), sizeof(int32_t) * srow.size(), hipMemcpyHostToDevice,
+                                st));
+    HIP_TRY(ctx, hipMemcpyAsync(tr->seg_row_w2.p, srow_w2.data(), sizeof(float) * srow_w2.size(),
+                                hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(ctx, hipStreamSynchronize(st));      // the host arrays go out of scope
   tr->n_slots = nseg;
   tr->rp_ent_max = ent_max;
