@@ -114,9 +114,16 @@ struct Level1 {
 // fence) pad = 1 as the mark that they are complete.  The host clears the
 // mark before it issues the launch that writes the slot.
 __device__ __forceinline__ void state_to_host(Scal* h, const Scal& S) {
-  Scal H = S;
-  H.pad = 0;
-  *h = H;
+  h->alpha = S.alpha;
+  h->beta = S.beta;
+  h->gamma = S.gamma;
+  h->rr = S.rr;
+  h->bb = S.bb;
+  h->tol2 = S.tol2;
+  h->rrn = S.rrn;
+  h->done = S.done;
+  h->iters = S.iters;
+  h->status = S.status;
   __threadfence_system();
   __hip_atomic_store(&h->pad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __threadfence_system();
