@@ -42,19 +42,21 @@ def _sync():
 def _kernel_bytes(W, L, tr, m, b, precond):
     """Algorithmic HBM bytes per launch of each kernel of one CG iteration of the 2D product in the FP32
     pipeline (one field, grid values of b = 4 bytes): every array the kernel needs is read or written once.
-    The first row pass gathers each node's value from the per-node single-precision rows (three vertex
-    ids, three weights: 24 bytes) and the vertex values; the last row pass reads the row-pair entries of
-    I^T (16-bit local node, weight) and writes one partial sum per (vertex, row pair); the vertex kernel
-    adds a vertex's partials and applies the CG step."""
+    The first row pass reads each node's segment row (three local segment numbers and weights: 20 bytes)
+    and its row pair's slot values of u (4 bytes per slot, staged in LDS); the last row pass reads the
+    row-pair entries of I^T (16-bit local node, weight) and writes one partial sum per (vertex, row pair);
+    the vertex kernel adds a vertex's partials, applies the CG step and stores the new u at its slots."""
     nn, H = W * W, L // 2
     info = tr.info
     nnz, nv, slots = info["nnz"], tr.nv, info["rp_slots"]
     vec = 8 * nv * (6 + 5 + (1 if precond == "DIAG" else 0))   # mask, s, p, u, r, x (+ D^-1) in; s, p, x, r, u out
     return {
-        "passA": 24 * nn + 8 * nv + 2 * b * W * H,        # node rows, u; W rows of L/2 complex slots out
+        "passA": 20 * nn + 16 * ((W + 1) // 2) + 4 * slots + 2 * b * W * H,   # node rows, row-pair
+                                                          # descriptors, u per slot; W rows of L/2 slots out
         "passB": 4 * b * W * H + b * H * (H + 1),         # slots in and out; multiplier columns
         "passC": 2 * b * W * H + (2 + b) * nnz + 8 * slots,   # slots in; entries; partial sums out
-        "scatter": 4 * (nv + 1) + 8 * slots + vec,        # partial offsets and sums; CG vectors
+        "scatter": 4 * (nv + 1) + (8 + 4 + 4) * slots + vec,   # partial offsets, sums, slot positions,
+                                                               # u per slot out; CG vectors
     }
 
 
