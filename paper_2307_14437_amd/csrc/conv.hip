@@ -610,7 +610,7 @@ struct RowScatter {
   const CgItem* items;     // per-item row-pair arrays
   double* P;               // partial slots, item it at it * pstride
   long long pstride;
-  int ent_max;             // most entries per thread of a row pair
+  int ent_ahead;           // entries read ahead per thread (covers most row pairs)
 };
 template <typename R, typename Y, int L, int E, int LINES, bool SCAT, int EPRE = 1>
 __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (sizeof(R) == 4 ? 3 : 2) : 1) void k_passC(const cplx<R>* __restrict__ Z, int W,
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
     // entries m < EPRE of this thread, read ahead past its count ENT (meta.y;
     // the arrays carry RP_EPRE * TPL padding entries at the end, so the reads
     // stay in range); the extra ones become padding (node 0, weight 0).  The
-    // launch picks EPRE from the transfer's largest ENT.
+    // launch picks EPRE from the count that covers most row pairs.
     gcode = I.rp_code + meta.x + t;
     if constexpr (sizeof(R) == 4)
       gw = reinterpret_cast<const R*>(I.rp_w32) + meta.x + t;
@@ -906,12 +906,12 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   }
   if ((passes & 4) && rs.items) {
     // entries read ahead per thread: the first of 16, 24, 32 that covers the
-    // transfer's largest count (more run in a loop)
+    // count of 90% of the row pairs (more run in a loop)
     const dim3 gC(nbA + (fin.sc ? 1 : 0), nrhs), bC(C::LINES_A * C::TA);
-    if (rs.ent_max <= 16)
+    if (rs.ent_ahead <= 16)
       GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A, true, 16>), gC, bC, 0, st, Z, W, tw, zs, y,
                   (long long)W * W, skip, fin, rs);
-    else if (rs.ent_max <= 24)
+    else if (rs.ent_ahead <= 24)
       GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A, true, 24>), gC, bC, 0, st, Z, W, tw, zs, y,
                   (long long)W * W, skip, fin, rs);
     else
@@ -1061,7 +1061,7 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if (conv_gather_fused(op, fp32) && g->items && (passes & 8) && (passes & 1)) {
     // the FP32 gather of a batch runs inside the first row pass
-    const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_max};
+    const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_ahead};
 #if GOFD_FFT_E_PASSA == GOFD_FFT_E_ROWS      // the slot capacity of a row pair follows the row passes' lines
     if (g->rp_us && d == 2) {
       SrcPairSegRows src{g->items, g->rp_us, g->rp_pstride};
@@ -1114,7 +1114,7 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   if (d == 3)
     return conv3_run(ctx, op, nrhs, fp32 ? nullptr : op->G.as<double>(), fp32 ? op->G.as<float>() : nullptr, y, fp32,
                      passes & 7, skip.flag, skip.stride, dpart, lv1, fin, that_tab, skip.map);
-  const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_max};
+  const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_ahead};
   if (fp32) {
     SrcPairGrid<float> src{op->G.as<float>(), nn};
     return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab,

@@ -142,7 +142,7 @@ struct gofd_transfer_s {
   bool rp_ok = false;
   bool seg_rows_ok = false;   // seg_row / rp_pos present (at most three entries per node)
   int64_t n_slots = 0;  // partial sums: one per (vertex, row pair) with entries
-  int rp_ent_max = 0;   // most entries of a thread in a row pair
+  int rp_ent_ahead = 0;   // entries per thread that cover 90% of the row pairs (the last row pass reads them ahead)
   DevBuf rp_meta;    // int4[pairs]: entry base, entries per thread, segment base, segments
   DevBuf rp_tseg;    // int32[pairs * threads]: first segment of each thread
   DevBuf rp_code;    // uint16[...]: local node (2 rows) | end-of-segment flag, thread-interleaved
@@ -242,7 +242,7 @@ struct GatherSpec {
   // instead of writing the grid field
   double* rp_P = nullptr;
   long long rp_pstride = 0;
-  int rp_ent_max = 0;                  // most entries per thread of a row pair (all items)
+  int rp_ent_ahead = 0;                // entries per thread read ahead (covers most row pairs of all items)
   // with rp_us as well (every item has seg_row): the FP32 gather reads the
   // vector's values per slot (item it at rp_us + it * rp_pstride, row-pair-major
   // positions) instead of per vertex

@@ -715,7 +715,7 @@ struct Batch {
   bool rp = true;                  // every transfer has the row-pair form of I^T
   bool seg = true;                 // ... and the per-node segment rows (FP32 gather through the slots)
   long long slots_max = 0;         // most partial slots of an item
-  int rp_ent_max = 0;              // most entries per thread of a row pair
+  int rp_ent_ahead = 0;            // entries of a thread the last row pass reads ahead (largest of the items)
   gofd_fdop_s* op0 = nullptr;      // shape and FFT workspaces of the batch
   DevBuf items, tab64, tab32;      // CgItem[nitems]; spectrum pointer tables
 };
@@ -737,7 +737,7 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
     B.rp = B.rp && tr->rp_ok;
     B.seg = B.seg && tr->rp_ok && tr->seg_rows_ok;
     B.slots_max = std::max<long long>(B.slots_max, tr->n_slots);
-    B.rp_ent_max = std::max(B.rp_ent_max, tr->rp_ent_max);
+    B.rp_ent_ahead = std::max(B.rp_ent_ahead, tr->rp_ent_ahead);
     for (int k = 0; k < P.nrhs; ++k) {
       CgItem I{};
       I.csc_off = tr->csc_off.as<int>();
@@ -946,7 +946,7 @@ int cg_iteration(gofd_ctx_s* ctx, const Batch& B, Work& w, bool fp32, StageProf*
   if (B.rp) {
     g.rp_P = w.P.as<double>();
     g.rp_pstride = std::max<long long>(B.slots_max, 1);
-    g.rp_ent_max = B.rp_ent_max;
+    g.rp_ent_ahead = B.rp_ent_ahead;
     if (seg_gather(B, fp32)) g.rp_us = w.us.as<float>();
   }
   if (prof) {

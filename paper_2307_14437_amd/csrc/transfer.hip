@@ -458,13 +458,11 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
     ent[r] = e;
   });
   int64_t ebase = 0;
-  int ent_max = 0;
   for (int r = 0; r < pairs; ++r) {
     meta[4 * (size_t)r + 0] = (int32_t)ebase;
     meta[4 * (size_t)r + 1] = ent[r];
     meta[4 * (size_t)r + 2] = rp_cnt[r];
     meta[4 * (size_t)r + 3] = rp_cnt[r + 1] - rp_cnt[r];
-    ent_max = std::max(ent_max, ent[r]);
     ebase += (int64_t)ent[r] * T;
     if (ebase >= ((int64_t)1 << 30)) return GOFD_OK;
   }
@@ -545,7 +543,12 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   }
   HIP_TRY(ctx, hipStreamSynchronize(st));      // the host arrays go out of scope
   tr->n_slots = nseg;
-  tr->rp_ent_max = ent_max;
+  // read ahead what 90% of the row pairs need (the rest loop over their remainder)
+  {
+    std::vector<int> e(ent.begin(), ent.end());
+    std::sort(e.begin(), e.end());
+    tr->rp_ent_ahead = e.empty() ? 0 : e[std::min<size_t>(e.size() - 1, (e.size() * 9) / 10)];
+  }
   tr->info.rp_slots = nseg;
   tr->info.rp_entries = ebase;
   tr->rp_ok = true;
