@@ -1159,17 +1159,16 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
   int rc = GOFD_OK;
   std::vector<Scal> tmp(ni);
   if (history) history[0] = 1.0;
-  if (replace_drop > 0.0) {
-    HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
-    for (int k = 0; k < ni; ++k) rr_ref[k] = tmp[k].rr;
-  }
+  // (until the first replacement the reference is the starting residual,
+  // (r, r) = (b, b) from x = 0)
   auto need_replace = [&](const std::vector<Scal>& st_) {
     bool need = false;
-    for (int k = 0; k < ni; ++k)
+    for (int k = 0; k < ni; ++k) {
+      if (rr_ref[k] == HUGE_VAL) rr_ref[k] = st_[k].bb;
       if (st_[k].status == ST_OK && !settled[k] &&
           (st_[k].done || st_[k].rr < replace_drop * replace_drop * rr_ref[k]))
         need = true;
+    }
     return need;
   };
   if (piped) {
