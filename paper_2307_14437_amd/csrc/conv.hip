@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <type_traits>
 
 #include "bary.h"
 #include "cg_items.h"
@@ -893,9 +894,17 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   const int pairs = (W + 1) / 2;
   const int nbA = (pairs + C::LINES_A - 1) / C::LINES_A;
   hipStream_t st = ctx->stream;
-  if (passes & 1)
-    GOFD_LAUNCH(ctx, (k_passA<R, L, C::E1, C::LINES_1, Src>), dim3((pairs + C::LINES_1 - 1) / C::LINES_1, nrhs),
-                dim3(C::LINES_1 * C::T1), 0, st, src, Z, W, tw, zs, skip);
+  if (passes & 1) {
+    // the gather through the slots does its FFT with 16 values per thread
+    // when both row passes still hold one row pair per block (the slot
+    // capacity of a row pair is the same then)
+    constexpr bool WIDE = std::is_same<Src, SrcPairSegRows>::value && L / 16 >= 64 && C::TA >= 64;
+    constexpr int EP = WIDE ? 16 : C::E1;
+    constexpr int TP = L / EP;
+    constexpr int LP = (TP >= 64) ? 1 : 64 / TP;
+    GOFD_LAUNCH(ctx, (k_passA<R, L, EP, LP, Src>), dim3((pairs + LP - 1) / LP, nrhs), dim3(LP * TP), 0, st, src, Z,
+                W, tw, zs, skip);
+  }
   if (passes & 2) {
     switch (col_sched(ctx, L, sizeof(R) == 4)) {
       case 1: launch_passB_s<R, L, 1>(ctx, st, nrhs, Z, W, half, That, tw, zs, skip, dpart, lv1, that_tab); break;
