@@ -41,7 +41,10 @@ namespace {
 inline unsigned grid1(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 constexpr int NB_DOT = 256;      // blocks of the residual kernel (fixed: deterministic sums)
-constexpr int BS = 256;
+#ifndef GOFD_BS
+#define GOFD_BS 128
+#endif
+constexpr int BS = GOFD_BS;       // threads per block of the CG vector kernels (build-time knob)
 constexpr int MAX_SC = 16384;    // most blocks of the CG scatter (one partial sum each)
 #ifndef GOFD_SCAT_G
 #define GOFD_SCAT_G 16
