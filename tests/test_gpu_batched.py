@@ -51,7 +51,7 @@ def test_batched_matches_individual_solves(gctx, mode):
             print(mode, k, infos[k], ii[0], flush=True)
             assert infos[k]["rel_residual"] <= 1e-12 and infos[k]["status"] == 0
             assert np.linalg.norm(u[r] - ui) <= 1e-9 * np.linalg.norm(ui)
-            # FP32: a residual replacement triggered by one item replaces every item's residual
+            # FP32: the replacement points follow the checks, which differ between a batch and one item
             slack = 2 if mode == "fp64" else 3 + ii[0]["iterations"] // 10
             assert abs(infos[k]["iterations"] - ii[0]["iterations"]) <= slack
             k += 1
@@ -74,8 +74,9 @@ def test_batched_item_matches_oracle(gctx):
 
 
 def test_batched_fp32_replacement_count(gctx):
-    # residual replacements are batch events; an item whose stop a replacement
-    # has confirmed triggers no more of them while the others continue
+    # residual replacements are per item (only the items whose residual has
+    # dropped, or that stopped, are replaced); an item whose stop a replacement
+    # has confirmed has no more of them while the others continue
     import torch
     import paper_2307_14437_amd as gofd
     m = star_mesh(31, 900)
