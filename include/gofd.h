@@ -113,6 +113,8 @@ typedef struct {
   int64_t rp_slots;         /* 2D: partial sums of the row-pair form of I^T used inside   */
                             /* CG (one per vertex and row pair it touches); 0 if absent  */
   int64_t rp_entries;       /* 2D: stored entries of that form (with per-thread padding)  */
+  int64_t rp_seg_rows;      /* 2D: 1 if the per-node segment rows of the FP32 gather      */
+                            /* through the row-pair slots were built, else 0              */
 } gofd_transfer_info;
 
 /* Build I_h^FD, its transpose structure and D_h (Section 3.1, eqs. interp-1 to

@@ -52,7 +52,7 @@ class TransferInfo(ctypes.Structure):
                 ("n_interior", ctypes.c_int64), ("n_boundary", ctypes.c_int64),
                 ("dmin_interior", ctypes.c_double), ("a_h", ctypes.c_double), ("h_bound", ctypes.c_double),
                 ("exact_tests", ctypes.c_int64), ("max_col_count", ctypes.c_int64),
-                ("rp_slots", ctypes.c_int64), ("rp_entries", ctypes.c_int64)]
+                ("rp_slots", ctypes.c_int64), ("rp_entries", ctypes.c_int64), ("rp_seg_rows", ctypes.c_int64)]
 
 
 class FdwOpts(ctypes.Structure):

@@ -551,6 +551,7 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   }
   tr->info.rp_slots = nseg;
   tr->info.rp_entries = ebase;
+  tr->info.rp_seg_rows = srow_ok ? 1 : 0;
   tr->rp_ok = true;
   return GOFD_OK;
 }

@@ -4,6 +4,8 @@ import os
 import re
 import subprocess
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -45,3 +47,34 @@ def test_tuning_cache_roundtrip(tmp_path):
     assert gofd.cache_lookup(path, "gfx950/d2/L2048/fp32") == 1
     assert gofd.cache_lookup(path, "gfx950/d2/L1024/fp64") == 2
     assert [gofd.fft_period(n) for n in (1, 2, 3, 32, 33, 512)] == [8, 8, 16, 128, 256, 2048]
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    # every structure the binding mirrors has the C layout of include/gofd.h:
+    # size and the offset of each field, from a C program built with gcc
+    import ctypes
+    import shutil
+    import subprocess
+    import paper_2307_14437_amd as gofd
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    pairs = [("gofd_grid", gofd._Grid), ("gofd_transfer_info", gofd.TransferInfo),
+             ("gofd_fdw_opts", gofd.FdwOpts), ("gofd_precond_info", gofd.PrecondInfo),
+             ("gofd_solve_opts", gofd.SolveOpts), ("gofd_solve_info", gofd.SolveInfo)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gofd.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

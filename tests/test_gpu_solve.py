@@ -192,6 +192,7 @@ def test_bench_configuration_full_size(gctx):
     tr = gofd.Transfer(gctx, _dev(m.X), _dev(m.elems, torch.int32), g)
     # the CG iterations use the row-pair form of I^T: one partial slot per (vertex, row pair)
     assert tr.info["rp_slots"] >= tr.nv and tr.info["rp_entries"] >= tr.info["nnz"]
+    assert tr.info["rp_seg_rows"] == 1          # the FP32 gather goes through the row-pair slots
     ops = [gofd.FdOp(gctx, s, g) for s in cfg["s"]]
     pcs = [gofd.Precond(gctx, tr, op, "NONE") for op in ops]
     fd = _dev(f)
