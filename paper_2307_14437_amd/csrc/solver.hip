@@ -400,6 +400,48 @@ __global__ __launch_bounds__(BS) void k_u_to_slots(const CgItem* __restrict__ it
   }
 }
 
+// Residual replacement from the row-pair form: q = mask * (sum of each
+// vertex's partial slots, left by the last row pass of an FP64 product of x),
+// r = b - q, u = M_diag r, u at the vertex's slots (us, if given) and the
+// partials of gamma and (r, r), as k_cg_replace.  Item map[blockIdx.y] (or
+// blockIdx.y).
+__global__ __launch_bounds__(BS) void k_cg_replace_rp(const CgItem* __restrict__ items,
+                                                      const double* __restrict__ P, long long pstride,
+                                                      const double* __restrict__ b, double* __restrict__ r,
+                                                      double* __restrict__ u, const Scal* __restrict__ sc,
+                                                      double* __restrict__ partG, double* __restrict__ partR,
+                                                      const int* __restrict__ map, float* __restrict__ us) {
+  __shared__ double sh[gofd_cg::block_sum_lds<BS, 2>()];
+  const int it = map ? map[blockIdx.y] : blockIdx.y;
+  const CgItem& I = items[it];
+  if (sc[it].status != ST_OK) return;
+  const long long o = I.off, nv = I.nv;
+  const int dk = I.dk;
+  const double* Pi = P + it * pstride;
+  double acc[2] = {0.0, 0.0};
+  for (long long v = (long long)blockIdx.x * BS + threadIdx.x; v < nv; v += (long long)gridDim.x * BS) {
+    double w = 0.0;
+    for (int i = I.pv_off[v]; i < I.pv_off[v + 1]; ++i) w += Pi[i];
+    const double ri = b[o + v] - I.imask[v] * w;
+    r[o + v] = ri;
+    acc[1] += ri * ri;
+    if (dk >= 0) {
+      const double ui = dk ? ri * I.dscale[v] : ri;
+      u[o + v] = ui;
+      acc[0] += ri * ui;
+      if (us) {
+        float* ui32 = us + it * pstride;
+        for (int i = I.pv_off[v]; i < I.pv_off[v + 1]; ++i) ui32[I.rp_pos[i]] = (float)ui;
+      }
+    }
+  }
+  block_sum_n<BS, 2>(acc, sh);
+  if (threadIdx.x == 0) {
+    if (dk >= 0) partG[(long long)it * gridDim.x + blockIdx.x] = acc[0];
+    partR[(long long)it * gridDim.x + blockIdx.x] = acc[1];
+  }
+}
+
 // r = b - q (q = K x), partials of (r, r) and (b, b); used by the refinement
 // loop (FP64 residual).  Item blockIdx.y.
 __global__ __launch_bounds__(BS) void k_residual(const CgItem* __restrict__ items, const double* __restrict__ b,
@@ -852,6 +894,23 @@ long long grid_nodes(const gofd_fdop_s* op) {
   return nn;
 }
 
+// FP64 product of x through the row-pair form into the partial slots (the
+// last row pass sums each vertex's entries per row pair), for replacements
+// (with map given: only the n items map[0..n) of the batch)
+int apply_K_slots(gofd_ctx_s* ctx, const Batch& B, Work& w, const double* v, const int* map, int n) {
+  GatherSpec g;
+  g.items = B.items.as<CgItem>();
+  g.ubase = v;
+  g.items_mask = true;
+  g.amap = map;
+  g.that64_tab = static_cast<const void* const*>(B.tab64.p);
+  g.that32_tab = static_cast<const void* const*>(B.tab32.p);
+  g.rp_P = w.P.as<double>();
+  g.rp_pstride = std::max<long long>(B.slots_max, 1);
+  g.rp_ent_ahead = B.rp_ent_ahead;
+  return conv_apply(ctx, B.op0, n, nullptr, &g, w.grid.p, false);
+}
+
 // q = K v for every item in double precision (masked), for true residuals;
 // v and q are batch vectors
 // (with map given: only the n items map[0..n) of the batch)
@@ -1150,16 +1209,32 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
   // items whose stop a replacement has confirmed with the true residual: they
   // trigger no further replacement
   std::vector<char> settled(ni, 0);
-  auto replace_residual = [&](std::vector<Scal>& tmp) -> int {
-    GOFD_TRY(apply_K_plain(ctx, B, w, w.x.as<double>(), w.q.as<double>()));
-    hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, ni), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
-                       w.q.as<double>(), w.r.as<double>(), w.u.as<double>(), w.scal.as<Scal>(), w.partG.as<double>(),
-                       w.partR.as<double>(), nullptr);
-    hipLaunchKernelGGL(k_cg_reopen, dim3(ni), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>(),
-                       nullptr, nullptr);
-    refresh_slots(ctx, B, w, fp32);
+  // the launches of a replacement for the n items of map (every item with map
+  // null): r = b - K x with an FP64 product (through the row-pair slots when
+  // the batch has them), u = M r, the partials, u at the slots, and the
+  // states (also into host, if given)
+  auto replace_launch = [&](const int* map, int n, Scal* host) -> int {
+    if (B.rp) {
+      GOFD_TRY(apply_K_slots(ctx, B, w, w.x.as<double>(), map, n));
+      hipLaunchKernelGGL(k_cg_replace_rp, dim3(w.nbs, n), dim3(BS), 0, st, B.items.as<CgItem>(), w.P.as<double>(),
+                         std::max<long long>(B.slots_max, 1), w.b.as<double>(), w.r.as<double>(),
+                         w.u.as<double>(), w.scal.as<Scal>(), w.partG.as<double>(), w.partR.as<double>(), map,
+                         seg_gather(B, fp32) ? w.us.as<float>() : nullptr);
+    } else {
+      GOFD_TRY(apply_K_plain(ctx, B, w, w.x.as<double>(), w.q.as<double>(), map, n));
+      hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, n), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
+                         w.q.as<double>(), w.r.as<double>(), w.u.as<double>(), w.scal.as<Scal>(),
+                         w.partG.as<double>(), w.partR.as<double>(), map);
+      refresh_slots(ctx, B, w, fp32, map, n);
+    }
+    hipLaunchKernelGGL(k_cg_reopen, dim3(n), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>(), host,
+                       map);
     HIP_TRY(ctx, hipGetLastError());
     if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
+    return GOFD_OK;
+  };
+  auto replace_residual = [&](std::vector<Scal>& tmp) -> int {
+    GOFD_TRY(replace_launch(nullptr, ni, nullptr));
     HIP_TRY(ctx, hipMemcpyAsync(tmp.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     for (int k = 0; k < ni; ++k) {
@@ -1201,11 +1276,12 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     // stop.  A residual replacement (of the items whose stop is not yet
     // confirmed) is queued behind the chunks in flight and writes their states
     // into slot 2; the states of chunks issued before it are superseded and
-    // not acted on.  Chunks issued after it run on, unless
-    // every item had stopped or is close to its tolerance (the replacement
-    // may confirm the stop).  Without a graph, chunks shrink to two
-    // iterations once every item is within 100x of its tolerance in the
-    // residual norm, so that fewer iterations run past a stop.
+    // not acted on.  Chunks issued after it run on, unless every item had
+    // stopped or is close to its tolerance (the replacement may confirm the
+    // stop).  Without a graph, chunks shrink to two iterations once every item
+    // is within 100x of its tolerance in the residual norm, so that fewer
+    // iterations run past a stop.
+
     // items whose state a launch into the slot writes: the items the chunk's
     // launches cover, or the items of the pending replacement
     auto expect = [&](int slot, int k) { return slot == 2 ? rsel[k] != 0 : in_map[k] != 0; };
@@ -1260,16 +1336,7 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
         HIP_TRY(ctx, hipMemcpyAsync(w.rmap.p, hmap, sizeof(int) * nr, hipMemcpyHostToDevice, st));
         map = w.rmap.as<int>();
       }
-      GOFD_TRY(apply_K_plain(ctx, B, w, w.x.as<double>(), w.q.as<double>(), map, nr));
-      hipLaunchKernelGGL(k_cg_replace, dim3(w.nbs, nr), dim3(BS), 0, st, B.items.as<CgItem>(), w.b.as<double>(),
-                         w.q.as<double>(), w.r.as<double>(), w.u.as<double>(), w.scal.as<Scal>(),
-                         w.partG.as<double>(), w.partR.as<double>(), map);
-      hipLaunchKernelGGL(k_cg_reopen, dim3(nr), dim3(BS), 0, st, w.partR.as<double>(), w.nbs, w.scal.as<Scal>(),
-                         hd + 2 * (size_t)ni, map);
-      refresh_slots(ctx, B, w, fp32, map, nr);
-      HIP_TRY(ctx, hipGetLastError());
-      if (B.any_ic) GOFD_TRY(precond_apply(ctx, B, w, w.scal.as<Scal>(), w.partG.as<double>()));
-      return GOFD_OK;
+      return replace_launch(map, nr, hd + 2 * (size_t)ni);
     };
     // every item stopped or within 100x of its tolerance (residual norm)
     auto near_stop = [&](const std::vector<Scal>& st_) {
