@@ -1499,6 +1499,7 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
     return GOFD_OK;
   };
   int rc = GOFD_OK;
+  bool confirmed = false;         // final residuals known from the last replacements
   if (mode == GOFD_MODE_FP64 || mode == GOFD_MODE_FP32_RELIABLE) {
     const bool rel32 = mode == GOFD_MODE_FP32_RELIABLE;
     const double drop = rel32 ? ((o && o->inner_tol > 0) ? o->inner_tol : 1e-2) : 0.0;
@@ -1512,6 +1513,11 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
       if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
       else if (!hs[k].done) status[k] = GOFD_E_NOT_CONVERGED;
     }
+    // with reliable updating every stop was confirmed by a replacement, whose
+    // (r, r) is that of b - K x in double precision for the x copied out (a
+    // stopped item's x no longer changes)
+    confirmed = rel32 && nrep.size() == (size_t)ni;
+    for (int k = 0; k < ni && confirmed; ++k) confirmed = status[k] == GOFD_OK && nrep[k] > 0;
   } else if (mode == GOFD_MODE_FP32_REFINE) {
     const double inner = (o && o->inner_tol > 0) ? o->inner_tol : 1e-5;
     const int max_ref = (o && o->max_refine > 0) ? o->max_refine : 30;
@@ -1559,9 +1565,16 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
     return gofd_fail(ctx, GOFD_E_ARG, "unknown solve mode");
   }
   // final relative residual in double precision (of the solution just copied out)
-  const double* xfin = (mode == GOFD_MODE_FP32_REFINE) ? w.xr.as<double>() : w.x.as<double>();
-  std::vector<double> rr, bb;
-  GOFD_TRY(true_residual(ctx, B, w, xfin, w.b.as<double>(), w.r.as<double>(), rr, bb));
+  std::vector<double> rr(ni), bb(ni);
+  if (confirmed) {
+    for (int k = 0; k < ni; ++k) {
+      rr[k] = hs[k].rr;
+      bb[k] = hs[k].bb;
+    }
+  } else {
+    const double* xfin = (mode == GOFD_MODE_FP32_REFINE) ? w.xr.as<double>() : w.x.as<double>();
+    GOFD_TRY(true_residual(ctx, B, w, xfin, w.b.as<double>(), w.r.as<double>(), rr, bb));
+  }
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   int worst = GOFD_OK;
   for (int k = 0; k < ni; ++k) {
