@@ -26,6 +26,7 @@ int dev_reserve(gofd_ctx_s* ctx, DevBuf& b, size_t bytes) {
 gofd_ctx_s::~gofd_ctx_s() {
   for (auto& kv : twiddles) delete kv.second;
   if (host_state) (void)hipHostFree(host_state);
+  if (solver_ws && solver_ws_free) solver_ws_free(solver_ws);
   if (ev_in) (void)hipEventDestroy(ev_in);
   if (ev_out) (void)hipEventDestroy(ev_out);
   if (work) (void)hipStreamDestroy(work);

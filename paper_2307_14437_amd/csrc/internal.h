@@ -83,6 +83,11 @@ struct gofd_ctx_s {
   // last iteration of each chunk, and one for a residual replacement): the
   // host reads one check's state while the next chunk of iterations runs
   void* host_state = nullptr;
+  // the solver's device workspace (CG vectors, grid, partial slots, ...),
+  // kept from one solve to the next so that a solve allocates only when it
+  // needs more than the last one
+  void* solver_ws = nullptr;
+  void (*solver_ws_free)(void*) = nullptr;
   size_t host_state_bytes = 0;
   ~gofd_ctx_s();
 };

@@ -859,6 +859,16 @@ struct Work {
   int per = 1;                  // vertex groups per scatter block
 };
 
+// the context's solver workspace (made on first use, freed with the context;
+// one solve at a time uses it)
+static Work& ctx_work(gofd_ctx_s* ctx) {
+  if (!ctx->solver_ws) {
+    ctx->solver_ws = new Work();
+    ctx->solver_ws_free = [](void* p) { delete static_cast<Work*>(p); };
+  }
+  return *static_cast<Work*>(ctx->solver_ws);
+}
+
 int reserve_work(gofd_ctx_s* ctx, Work& w, const Batch& B) {
   const size_t vb = sizeof(double) * std::max<long long>(B.ntot, 1);
   for (DevBuf* b : {&w.x, &w.r, &w.u, &w.p, &w.s, &w.b, &w.xr, &w.dvec, &w.q}) GOFD_TRY(dev_reserve(ctx, *b, vb));
@@ -1608,7 +1618,7 @@ extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_pre
   WorkStream ws(ctx);
   Batch B;
   GOFD_TRY(batch_init(ctx, B, {Problem{tr, op, pc, nrhs}}));
-  Work w;
+  Work& w = ctx_work(ctx);
   GOFD_TRY(reserve_work(ctx, w, B));
   GOFD_TRY(form_rhs(ctx, B.probs[0], f, f_loc, w.b.as<double>()));
   double* outs[1] = {u};
@@ -1643,7 +1653,7 @@ extern "C" int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* 
     for (int q : members) probs.push_back(Problem{trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q]});
     Batch B;
     GOFD_TRY(batch_init(ctx, B, probs));
-    Work w;
+    Work& w = ctx_work(ctx);
     GOFD_TRY(reserve_work(ctx, w, B));
     std::vector<double*> outs;
     for (size_t j = 0; j < members.size(); ++j) {
@@ -1781,7 +1791,7 @@ extern "C" int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, 
   GOFD_TRY(check_problem(ctx, tr, op, pc, 1));
   Batch B;
   GOFD_TRY(batch_init(ctx, B, {Problem{tr, op, pc, 1}}));
-  Work w;
+  Work& w = ctx_work(ctx);
   GOFD_TRY(reserve_work(ctx, w, B));
   const long long nv = tr->nv, nn = tr->n_nodes;
   // adjoint right-hand side: dL/du on the interior block (K is symmetric)
