@@ -751,6 +751,27 @@ int diag_kind_of(const gofd_precond_s* pc) {
 // A batch: problems of one grid shape (d, W, L), solved together.  Items are
 // (problem, rhs) pairs in problem order; the vectors of all items are laid
 // end to end (item i at off[i], N_v of its mesh entries each).
+// a non-owning view of device memory
+struct DevView {
+  void* p = nullptr;
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// the batch descriptors (CgItem array and spectrum pointer tables) on the
+// device, and their page-locked staging copy; kept in the context
+struct BatchBufs {
+  DevBuf desc;
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  ~BatchBufs() {
+    if (stage) (void)hipHostFree(stage);
+  }
+};
+static BatchBufs& ctx_batch(gofd_ctx_s* ctx);
+
 struct Batch {
   std::vector<Problem> probs;
   std::vector<long long> poff;     // offset of problem q's first vector
@@ -765,7 +786,7 @@ struct Batch {
   long long slots_max = 0;         // most partial slots of an item
   int rp_ent_ahead = 0;            // entries of a thread the last row pass reads ahead (largest of the items)
   gofd_fdop_s* op0 = nullptr;      // shape and FFT workspaces of the batch
-  DevBuf items, tab64, tab32;      // CgItem[nitems]; spectrum pointer tables
+  DevView items, tab64, tab32;     // CgItem[nitems]; spectrum pointer tables (in the context's buffers)
 };
 
 int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
@@ -833,14 +854,27 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
   B.nitems = (int)h.size();
   B.ntot = off;
   B.seg = B.seg && B.rp && !B.any_ic;        // IC(1) makes u in its own kernels
-  GOFD_TRY(dev_reserve(ctx, B.items, sizeof(CgItem) * h.size()));
-  GOFD_TRY(dev_reserve(ctx, B.tab64, sizeof(void*) * h.size()));
-  GOFD_TRY(dev_reserve(ctx, B.tab32, sizeof(void*) * h.size()));
-  hipStream_t st = ctx->stream;
-  HIP_TRY(ctx, hipMemcpyAsync(B.items.p, h.data(), sizeof(CgItem) * h.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(B.tab64.p, t64.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipMemcpyAsync(B.tab32.p, t32.data(), sizeof(void*) * h.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(ctx, hipStreamSynchronize(st));      // the host arrays go out of scope
+  // one block [CgItem x n | void* x n | void* x n], staged in page-locked
+  // memory (the previous solve on the context has finished with it) and
+  // copied in one transfer, without waiting for it
+  const size_t n = h.size(), o64 = sizeof(CgItem) * n, o32 = o64 + sizeof(void*) * n, bytes = o32 + sizeof(void*) * n;
+  BatchBufs& bb = ctx_batch(ctx);
+  if (bb.stage_bytes < bytes) {
+    if (bb.stage) (void)hipHostFree(bb.stage);
+    bb.stage = nullptr;
+    bb.stage_bytes = 0;
+    HIP_TRY(ctx, hipHostMalloc(&bb.stage, bytes, hipHostMallocDefault));
+    bb.stage_bytes = bytes;
+  }
+  char* sp = static_cast<char*>(bb.stage);
+  std::memcpy(sp, h.data(), o64);
+  std::memcpy(sp + o64, t64.data(), o32 - o64);
+  std::memcpy(sp + o32, t32.data(), bytes - o32);
+  GOFD_TRY(dev_reserve(ctx, bb.desc, bytes));
+  HIP_TRY(ctx, hipMemcpyAsync(bb.desc.p, bb.stage, bytes, hipMemcpyHostToDevice, ctx->stream));
+  B.items.p = bb.desc.p;
+  B.tab64.p = static_cast<char*>(bb.desc.p) + o64;
+  B.tab32.p = static_cast<char*>(bb.desc.p) + o32;
   return GOFD_OK;
 }
 
@@ -859,15 +893,21 @@ struct Work {
   int per = 1;                  // vertex groups per scatter block
 };
 
-// the context's solver workspace (made on first use, freed with the context;
-// one solve at a time uses it)
-static Work& ctx_work(gofd_ctx_s* ctx) {
+// the context's solver workspace and batch descriptors (made on first use,
+// freed with the context; one solve at a time uses them)
+struct SolverCache {
+  Work w;
+  BatchBufs b;
+};
+static SolverCache& ctx_cache(gofd_ctx_s* ctx) {
   if (!ctx->solver_ws) {
-    ctx->solver_ws = new Work();
-    ctx->solver_ws_free = [](void* p) { delete static_cast<Work*>(p); };
+    ctx->solver_ws = new SolverCache();
+    ctx->solver_ws_free = [](void* p) { delete static_cast<SolverCache*>(p); };
   }
-  return *static_cast<Work*>(ctx->solver_ws);
+  return *static_cast<SolverCache*>(ctx->solver_ws);
 }
+static Work& ctx_work(gofd_ctx_s* ctx) { return ctx_cache(ctx).w; }
+static BatchBufs& ctx_batch(gofd_ctx_s* ctx) { return ctx_cache(ctx).b; }
 
 int reserve_work(gofd_ctx_s* ctx, Work& w, const Batch& B) {
   const size_t vb = sizeof(double) * std::max<long long>(B.ntot, 1);
@@ -1432,8 +1472,11 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
   (void)hipStreamSynchronize(st);       // a chunk may still run: finish it before the graphs go
   drop_graphs();
   if (rc != GOFD_OK) return rc;
-  HIP_TRY(ctx, hipMemcpyAsync(hs.data(), w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
+  // the final states (through the page-locked replacement slot when there is one)
+  Scal* dst = hb ? hb + 2 * (size_t)ni : hs.data();
+  HIP_TRY(ctx, hipMemcpyAsync(dst, w.scal.p, sizeof(Scal) * ni, hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
+  if (hb) std::copy(dst, dst + ni, hs.begin());
   return GOFD_OK;
 }
 
