@@ -620,7 +620,6 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
                                                          gofd_cg::Finish fin, RowScatter rs) {
   constexpr int TPL = L / E;
   constexpr int PL = padded_len<L, E>();
-  constexpr int H = L / 2;
   constexpr int NT = LINES * TPL;
   constexpr int SEGL = RP_SEGCAP / LINES;                  // segment sums per row pair
   constexpr int QD = (SEGL + TPL - 1) / TPL;               // segments per thread in the write-out

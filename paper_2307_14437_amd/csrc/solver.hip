@@ -1226,10 +1226,11 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
     return GOFD_OK;
   };
   if (use_graph && piped) GOFD_TRY(capture());
-  // Active items: once at most half of the items the launches cover still
+  // Active items: once at most 7/8 of the items the launches cover still
   // iterate (or a replacement reopened one outside them), the launches are
   // narrowed to those items (block rows map to them) and the graph captured
-  // again.  Stopped items would otherwise still occupy launch slots.
+  // again.  Stopped items would otherwise still occupy launch slots (narrowing
+  // drains the stream once; at 1/2 the stopped items' blocks cost more).
   std::vector<char> in_map(ni, 1);
   std::vector<int> act_h;
   auto compact = [&](const std::vector<Scal>& st_) -> int {
@@ -1240,7 +1241,7 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
         act_h.push_back(k);
         missing = missing || !in_map[k];
       }
-    if (act_h.empty() || (!missing && 2 * (int)act_h.size() > w.nact)) return GOFD_OK;
+    if (act_h.empty() || (!missing && 8 * (int)act_h.size() > 7 * w.nact)) return GOFD_OK;
     HIP_TRY(ctx, hipStreamSynchronize(st));          // nothing in flight reads the old list
     HIP_TRY(ctx, hipMemcpyAsync(w.amap.p, act_h.data(), sizeof(int) * act_h.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
