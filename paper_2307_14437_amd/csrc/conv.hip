@@ -563,14 +563,14 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
   }
   if (slot != 0) {
     // terms That_k |V_k|^2 in the grid precision (products of grid values),
-    // summed in double
-    double dsum = 0.0;
+    // a thread's E terms summed in that precision, the threads' sums in double
+    R dsum = 0;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if constexpr (DOT) dsum += (double)(pm[m] * (v[m].x * v[m].x + v[m].y * v[m].y));
+      if constexpr (DOT) dsum += pm[m] * (v[m].x * v[m].x + v[m].y * v[m].y);
       v[m] = {v[m].x * pm[m], v[m].y * pm[m]};
     }
-    dacc += 2.0 * dsum;
+    dacc += 2.0 * (double)dsum;
   }
   if constexpr (DOT) {
     static_assert(NT % 64 == 0 || NT < 64, "block size");
