@@ -626,7 +626,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
   static_assert(2 * (L / 2 + 1) <= 2 * PL, "row pair fits the exchange buffer");
   __shared__ cplx<R> sbuf[LINES * PL];
   __shared__ double shf[gofd_cg::block_sum_lds<NT, 3>()];
-  __shared__ double segs[SCAT ? RP_SEGCAP : 1];
+  __shared__ R segs[SCAT ? RP_SEGCAP : 1];                // segment sums, grid precision
   const int line = threadIdx.x / TPL, t = threadIdx.x % TPL;
   cplx<R>* buf = sbuf + line * PL;
   const int nrb = gridDim.x - (fin.sc ? 1 : 0);                            // row-pair blocks
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
     // left the transform), then the segment sums (every thread reaches the
     // barriers: a line without rows has no entries)
     R* yl = reinterpret_cast<R*>(buf);
-    double* sg = segs + line * SEGL;
+    R* sg = segs + line * SEGL;
     __syncthreads();
 #pragma unroll
     for (int m = 0; m <= E / 2; ++m) {
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
     for (int m = 0; m < EPRE; ++m) {
       acc = fma(wt[m], yv[m], acc);
       const bool end = (code[m] & RP_END) != 0;
-      if (end) sg[j] = (double)acc;
+      if (end) sg[j] = acc;
       j += end ? 1 : 0;
       acc = end ? (R)0 : acc;
     }
@@ -762,7 +762,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
       const int c = gmem(gcode)[(long long)m * TPL];
       acc = fma(gmem(gw)[(long long)m * TPL], yl[c & RP_NODE], acc);
       if (c & RP_END) {
-        sg[j++] = (double)acc;
+        sg[j++] = acc;
         acc = 0;
       }
     }
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
 #pragma unroll
     for (int q = 0; q < QD; ++q) {
       const int i = t + q * TPL;
-      if (i < meta.w) P[dst[q]] = sg[i];
+      if (i < meta.w) P[dst[q]] = (double)sg[i];
     }
     return;
   }
