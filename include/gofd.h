@@ -241,8 +241,8 @@ int gofd_time_kernel(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int which, in
 typedef enum {
   GOFD_PC_NONE = 0,       /* plain CG                                                      */
   GOFD_PC_DIAG = 1,       /* M = D_h: CG on the symmetric form A~_h (eq. Ah-3)             */
-  GOFD_PC_IC1_5 = 5,      /* IC(1) of I^T A_FD^(5) I  (Section 3.4, 2D)                     */
-  GOFD_PC_IC1_9 = 9,      /* IC(1) of I^T A_FD^(9) I  (Section 3.4, 2D)                     */
+  GOFD_PC_IC1_5 = 5,      /* IC(1) of I^T A_FD^(5) I  (Section 3.3, 2D)                     */
+  GOFD_PC_IC1_9 = 9,      /* IC(1) of I^T A_FD^(9) I  (Section 3.3, 2D)                     */
   GOFD_PC_IC1_27 = 27     /* IC(1) of I^T A_FD^(27) I (Example 4, 3D)                       */
 } gofd_pc_kind;
 
@@ -254,7 +254,7 @@ typedef struct {
 } gofd_precond_info;
 
 /* Build a preconditioner for eq. GoFD-2 on the interior block.  For the IC(1)
- * kinds: the entries of A_FD on the 5/9/27-point pattern (Section 3.4), the
+ * kinds: the entries of A_FD on the 5/9/27-point pattern (Section 3.3), the
  * sparse triple product I^T A_FD^(p) I, a level-of-fill <= 1 incomplete
  * Cholesky factorisation in the mesh's vertex order (pivot <= 0: restart on
  * A + alpha diag(A), alpha = 1e-3 doubling), uploaded with its dependency

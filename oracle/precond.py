@@ -1,4 +1,4 @@
-"""Sparse preconditioner for GoFD-2 (Section 3.4, "Preconditioning with sparse matrices").
+"""Sparse preconditioner for GoFD-2 (Section 3.3, "Preconditioning with sparse matrices").
 
 1. Take the entries of A_FD on a Laplacian-like pattern: 5-point or 9-point
    in 2D (the paper), 27-point in 3D (Example 4).  This is the matrix

@@ -1,8 +1,8 @@
-"""Solving GoFD-2 (Section 3.3): dense LU for tiny systems, (preconditioned) CG otherwise.
+"""Solving GoFD-2 (Section 3.2): dense LU for tiny systems, (preconditioned) CG otherwise.
 
 The paper solves eq. GoFD-2 with the conjugate gradient method, optionally
 preconditioned by the incomplete Cholesky factor of A_h^(5/9/27) (Section
-3.4).  It does not state x_0 or the stopping test; the reading used here is
+3.3).  It does not state x_0 or the stopping test; the reading used here is
 x_0 = 0 and ||b - K x_k||_2 <= tol ||b||_2 on the recursively updated
 residual (Hestenes-Stiefel CG).
 """

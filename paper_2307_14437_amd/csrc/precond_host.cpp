@@ -1,4 +1,4 @@
-// Host construction of the sparse preconditioner of Section 3.4:
+// Host construction of the sparse preconditioner of Section 3.3:
 //   A_FD^(p): the entries of A_FD on the 5/9/27-point pattern,
 //   A_h^(p) = I^T A_FD^(p) I restricted to the interior vertices (eq. Ah-4),
 //   incomplete Cholesky with level-1 fill.

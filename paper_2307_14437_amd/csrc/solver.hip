@@ -18,7 +18,7 @@
 // replayed.
 //
 // Preconditioners: none; D_h (CG on the symmetric form of eq. Ah-3); the IC(1)
-// factor of A_h^(5/9/27) (Section 3.4), applied with two level-scheduled
+// factor of A_h^(5/9/27) (Section 3.3), applied with two level-scheduled
 // triangular solves.
 //
 // FP32 mode: the grid-side arrays and FFTs of every K product inside CG run

@@ -1,4 +1,4 @@
-"""Parity of the GoFD-2 solve (Section 3.3), its preconditioner (Section 3.4) and the FP32 +
+"""Parity of the GoFD-2 solve (Section 3.2), its preconditioner (Section 3.3) and the FP32 +
 refinement mode with the oracle."""
 
 import numpy as np

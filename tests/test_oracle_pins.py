@@ -1,0 +1,239 @@
+"""Further pins of the oracle: eq. GoFD-3's right-hand side, the shift restart
+of incomplete Cholesky, the exact ball solutions for k > 0 (eqs. exam-0,
+exam-2) and the 2D Toeplitz coefficients to 1e-12 by an identity that shares
+nothing with the oracle's two routes."""
+
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse as sp
+
+from oracle import exact, fdweights as fw, grid as ogrid, operator, precond, solve, transfer
+from workloads import disk_mesh, grid_for_box, structured_box_mesh
+
+
+# ---------------------------------------------------------------- eq. GoFD-3
+
+
+def _spacing2_mesh():
+    """Vertices on every second node of a 33^2 grid (mesh spacing 2h), squares
+    split along alternating diagonals."""
+    g = grid_for_box(2, 32, R=1.0)
+    lo = ogrid.axis_coords(0.0, g.R, g.N)[4]
+    mesh = structured_box_mesh((lo, lo), 2 * g.h, 12, 12)
+    return g, mesh
+
+
+def test_column_sums_on_a_spacing_two_mesh():
+    # Hand count of D_j = sum_k phi_j(x_k) with the grid twice as fine as the
+    # mesh: phi_j is 1 at its own node and 1/2 at the midpoint of each of its
+    # edges (the only other nodes where it is nonzero).  An interior vertex
+    # has 8 edges where the diagonals meet (D = 5) and 4 elsewhere (D = 3).
+    g, mesh = _spacing2_mesh()
+    tr = transfer.Transfer(mesh.X, mesh.elems, 2, g.N, g.R, g.center)
+    edges = set()
+    for t in mesh.elems:
+        for a in range(3):
+            i, j = int(t[a]), int(t[(a + 1) % 3])
+            edges.add((min(i, j), max(i, j)))
+    deg = np.zeros(mesh.nv, dtype=int)
+    for i, j in edges:
+        deg[i] += 1
+        deg[j] += 1
+    J = tr.J
+    assert set(np.unique(deg[J])) == {4, 8}
+    assert np.array_equal(tr.D[J], 1.0 + 0.5 * deg[J])
+
+
+def test_gofd3_rhs_with_unit_f_equals_gofd1_rhs():
+    # f = 1 both at the vertices and at the grid nodes: eq. GoFD-3 multiplied
+    # through by D_h has right side h^{2s} D_J, eq. GoFD-2 has h^{2s} I_J^T 1,
+    # and I^T 1 = D by definition of the column sums.
+    for g, mesh in (_spacing2_mesh(), (grid_for_box(2, 32, R=1.1), disk_mesh(seed=4, n_boundary=30,
+                                                                             spacing=0.2))):
+        tr = transfer.Transfer(mesh.X, mesh.elems, 2, g.N, g.R, g.center)
+        assert np.ptp(tr.D[tr.J]) > 0.5                   # D is far from constant: a dropped D shows
+        for s in (0.3, 0.7):
+            bv = operator.rhs_vertex(tr, s, np.ones(mesh.nv))
+            bg = operator.rhs_grid(tr, s, np.ones((g.W, g.W)))
+            assert np.allclose(bv, bg, rtol=1e-13, atol=0)
+
+
+def test_gofd3_recovers_a_manufactured_solution():
+    # eq. GoFD-3 as printed: h^{-2s} D^{-1} I^T A_FD I u = f_h.  Take f_h from a
+    # chosen u0 (zero on Dirichlet vertices) through A_h; solving the
+    # simplified system K u_J = rhs_vertex(f_h) must give u0 back.
+    mesh = disk_mesh(seed=6, n_boundary=30, spacing=0.2)
+    g = grid_for_box(2, 24, R=1.1)
+    tr = transfer.Transfer(mesh.X, mesh.elems, 2, g.N, g.R, g.center)
+    s = 0.6
+    T = fw.filon_richardson(s, 2, 2 * g.N, 256)
+    u0 = np.zeros(mesh.nv)
+    u0[tr.J] = np.random.default_rng(2).standard_normal(tr.J.size)
+    f_h = operator.apply_Ah(tr, T, u0, "direct") / g.h ** (2 * s)
+    uJ = solve.solve_dense(operator.dense_K(tr, T), operator.rhs_vertex(tr, s, f_h))
+    assert np.max(np.abs(uJ - u0[tr.J])) < 1e-11 * np.max(np.abs(u0))
+
+
+# ---------------------------------------------------------------- IC shift restart
+
+
+KERSHAW = np.array([[3.0, -2.0, 0.0, 2.0],
+                    [-2.0, 3.0, -2.0, 0.0],
+                    [0.0, -2.0, 3.0, -2.0],
+                    [2.0, 0.0, -2.0, 3.0]])
+
+
+def _kershaw_ic0_pivots(alpha):
+    """Squared pivots of IC(0) of Kershaw's matrix with diagonal 3(1+alpha),
+    worked by hand: the dropped entry is L_42 (a_42 = 0 and level 1)."""
+    d = 3.0 * (1.0 + alpha)
+    p2 = d - 4.0 / d                  # l22^2 = d - l21^2,          l21 = -2/sqrt(d)
+    p3 = d - 4.0 / p2                 # l33^2 = d - l32^2,          l32 = -2/sqrt(p2)
+    p4 = d - 4.0 / d - 4.0 / p3       # l44^2 = d - l41^2 - l43^2,  l41 = 2/sqrt(d), l43 = -2/sqrt(p3)
+    return d, p2, p3, p4
+
+
+def test_ic_shift_restart_on_kershaw_matrix():
+    # Kershaw (1978): SPD, yet incomplete Cholesky on its own pattern meets a
+    # negative pivot (l44^2 = -5 at alpha = 0).  The restart rule shifts by
+    # alpha diag(A), alpha = 1e-3, 2e-3, 4e-3, ... until every pivot is positive.
+    assert np.all(np.linalg.eigvalsh(KERSHAW) > 0)
+    assert _kershaw_ic0_pivots(0.0)[3] == pytest.approx(-5.0, rel=1e-15)
+    alpha = 1e-3
+    while min(_kershaw_ic0_pivots(alpha)) <= 0.0:
+        alpha *= 2
+    L, a = precond.ic1(sp.csr_matrix(KERSHAW), level=0)
+    assert a == alpha and a > 0.1
+    piv = _kershaw_ic0_pivots(a)
+    assert np.allclose(np.diag(L.toarray()) ** 2, piv, rtol=1e-13)
+    As = KERSHAW + a * np.diag(np.diag(KERSHAW))
+    Lc = L.tocoo()
+    M = (L @ L.T).toarray()
+    assert np.max(np.abs(M[Lc.row, Lc.col] - As[Lc.row, Lc.col])) < 1e-13
+    assert set(zip(Lc.row.tolist(), Lc.col.tolist())) == {(0, 0), (1, 0), (1, 1), (2, 1), (2, 2), (3, 0),
+                                                         (3, 2), (3, 3)}
+
+
+def test_ic_level_one_on_kershaw_matrix_is_complete_cholesky():
+    # level-1 fill adds (4,2), the only fill of the 4-cycle, so IC(1) is the
+    # exact Cholesky factor and needs no shift
+    L, a = precond.ic1(sp.csr_matrix(KERSHAW), level=1)
+    assert a == 0.0
+    assert np.allclose(L.toarray(), np.linalg.cholesky(KERSHAW), rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- exact solutions, k > 0
+
+
+def _jacobi_by_hand(k, a, b, x):
+    """P_k^{(a,b)} written out for k = 1, 2 (the standard normalisation)."""
+    if k == 1:
+        return (a + 1) + (a + b + 2) * (x - 1) / 2
+    if k == 2:
+        return ((a + 1) * (a + 2) / 2 + (a + 2) * (a + b + 3) * (x - 1) / 2
+                + (a + b + 3) * (a + b + 4) * (x - 1) ** 2 / 8)
+    raise ValueError(k)
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2])
+def test_ball_solution_polynomial_part(d, k):
+    s = 0.35
+    x = np.random.default_rng(k + d).uniform(-0.6, 0.6, size=(20, d))
+    r2 = np.sum(x ** 2, axis=1)
+    P = _jacobi_by_hand(k, s, d / 2 - 1, 2 * r2 - 1)
+    assert np.allclose(exact.u_ball(x, s, d, k), (1 - r2) ** s * P, rtol=1e-13)
+    # f/P is the constant 2^{2s} Gamma(1+s+k) Gamma(d/2+s+k) / (k! Gamma(d/2+k));
+    # at s = 1/2, d = 2, k = 1 it is 2 Gamma(5/2)^2 / Gamma(2) = 9 pi / 8
+    c = exact.f_ball(x, s, d, k) / P
+    assert np.allclose(c, c[0], rtol=1e-13)
+    c12 = exact.f_ball(np.array([[0.1, 0.2]]), 0.5, 2, 1) / _jacobi_by_hand(1, 0.5, 0.0, 2 * 0.05 - 1)
+    assert c12[0] == pytest.approx(9 * math.pi / 8, rel=1e-14)
+
+
+@pytest.mark.parametrize("s", [0.3, 0.5, 0.8])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_ball_solution_is_the_limit_of_the_1d_fd_scheme(s, k):
+    # In 1D the unit ball is (-1, 1); the uniform-grid FD scheme (closed-form T,
+    # eq. T-1D-0) with u = 0 outside converges to the exact solution at the
+    # rate O(h^{min(1, s+1/2)}).  A wrong constant or Jacobi normalisation in
+    # (f, u) leaves an O(1) error that does not shrink.
+    errs = []
+    for n in (256, 1024, 4096):
+        h = 2.0 / n
+        x = -1 + h * np.arange(1, n)
+        T = fw.closed_form_1d(s, n)
+        u = scipy.linalg.solve_toeplitz(T[:n - 1], h ** (2 * s) * exact.f_ball(x[:, None], s, 1, k))
+        ue = exact.u_ball(x[:, None], s, 1, k)
+        errs.append(np.linalg.norm(u - ue) / np.linalg.norm(ue))
+    rate = math.log(errs[0] / errs[-1]) / math.log(16)
+    assert errs[-1] < 5e-3
+    assert rate > min(1.0, s + 0.5) - 0.1
+
+
+def test_disk_solution_k1_converges():
+    # eq. exam-0 with k = 1 on the unit disk (d = 2): non-constant f, sign change of u
+    s, k = 0.5, 1
+    errs = []
+    for nb, sp_, n in ((50, 0.116, 32), (100, 0.058, 64)):
+        mesh = disk_mesh(seed=22, n_boundary=nb, spacing=sp_)
+        g = grid_for_box(2, n, R=1.0)
+        tr = transfer.Transfer(mesh.X, mesh.elems, 2, g.N, g.R, g.center)
+        T = fw.filon_richardson(s, 2, 2 * g.N, 1024)
+        nodes = ogrid.node_coords(2, g.N, g.R, g.center)
+        b = operator.rhs_grid(tr, s, exact.f_ball(nodes, s, 2, k))
+        uJ, _, _ = solve.pcg(lambda v: operator.apply_K(tr, T, v, "fft"), b, tol=1e-12, maxiter=5000)
+        u = np.zeros(mesh.nv)
+        u[tr.J] = uJ
+        ue = exact.u_ball(mesh.X, s, 2, k)
+        errs.append(exact.l2_error(mesh.X, mesh.elems, u - ue) / exact.l2_error(mesh.X, mesh.elems, ue))
+    assert errs[1] < 0.05
+    assert errs[0] / errs[1] > 1.6
+
+
+# ---------------------------------------------------------------- 2D T to 1e-12
+
+
+def _t2d_hypergeometric(s, p):
+    """T_{(p,0)} in 2D from the inner integral in closed form.
+
+    T_{(p,0)} = pi^{-2} int_0^pi cos(p x) int_0^pi (a(x) + 2 - 2 cos y)^s dy dx with
+    a(x) = 4 sin^2(x/2) (eqs. FL-6, T-1), and for B < A
+    int_0^pi (A - B cos y)^s dy = pi A^s 2F1(-s/2, (1-s)/2; 1; B^2/A^2)
+    (binomial series of (1 - (B/A) cos y)^s, odd powers integrate to zero).
+    """
+    with mp.workdps(25):
+        s = mp.mpf(s)
+
+        def inner(x):
+            A = 4 * mp.sin(x / 2) ** 2 + 2
+            return mp.pi * A ** s * mp.hyp2f1(-s / 2, (1 - s) / 2, 1, 4 / A ** 2)
+
+        v = mp.quad(lambda x: inner(x) * mp.cos(p * x), [0, mp.pi / 4, mp.pi / 2, mp.pi]) / mp.pi ** 2
+        return float(v)
+
+
+@pytest.mark.parametrize("s", [0.25, 0.5, 0.75])
+def test_2d_coefficients_to_1e12(s):
+    for p in (0, 1, 3):
+        truth = _t2d_hypergeometric(s, p)
+        assert abs(fw.bessel_route(s, (p, 0)) - truth) < 1e-12 * max(1.0, abs(truth))
+    # s = 1/2 also has the elliptic form pi^{-2} int_0^pi 2 sqrt(a+4) E(4/(a+4)) dx for T_00
+    if s == 0.5:
+        with mp.workdps(25):
+            ell = mp.quad(lambda x: 2 * mp.sqrt(4 * mp.sin(x / 2) ** 2 + 4)
+                          * mp.ellipe(4 / (4 * mp.sin(x / 2) ** 2 + 4)), [0, mp.pi]) / mp.pi ** 2
+        assert abs(float(ell) - _t2d_hypergeometric(0.5, 0)) < 1e-14
+        assert abs(float(ell) - 1.91618279737) < 5e-12      # the value quoted with the method's survey
+
+
+@pytest.mark.parametrize("s", [0.25, 0.75])
+def test_filon_richardson_within_its_error_model(s):
+    # after Richardson over M and M/2 the remaining error is ~C M^{-2-2s} (here M = 2^12)
+    F = fw.filon_richardson(s, 2, 3, 2 ** 12)
+    for p in (0, 1, 3):
+        assert abs(F[0, p] - _t2d_hypergeometric(s, p)) < 50 * 4096.0 ** (-2 - 2 * s)
