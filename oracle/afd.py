@@ -11,14 +11,20 @@ octant table of ``fdweights``.
 * ``apply_fft``     -- the paper's circulant-embedding evaluation (eq. AU-1):
   the DFT of T on the 4N-periodic grid in the paper's centred index range
   -2N..2N-1, the DFT of the zero-extended u, the product with the phase
-  (-1)^{p+2N} per axis and an inverse DFT (scipy's FFT on every host core as
-  the DFT primitive).
+  (-1)^{p+2N} per axis and an inverse DFT (scipy's FFT on the host cores as the
+  DFT primitive).
 """
 
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import scipy.fft
+
+# host threads for the DFTs: the process's CPU share (OMP_NUM_THREADS when the
+# environment sets it, else the cores this process may run on)
+WORKERS = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
 
 
 def _check(T: np.ndarray, v: np.ndarray):
@@ -89,10 +95,10 @@ def apply_fft(T: np.ndarray, v: np.ndarray) -> np.ndarray:
     L = 4 * N
     p = np.arange(L) - 2 * N                         # paper's p
     Tfull = T[tuple(np.meshgrid(*([np.abs(p)] * d), indexing="ij"))]
-    That = scipy.fft.fftn(Tfull, workers=-1)
+    That = scipy.fft.fftn(Tfull, workers=WORKERS)
     uext = np.zeros((L,) * d)
     uext[(slice(0, W),) * d] = v                     # position m + N for m = -N..N
-    uhat = scipy.fft.fftn(uext, workers=-1)
+    uhat = scipy.fft.fftn(uext, workers=WORKERS)
     k = np.arange(L)
     phase1 = np.where(k % 2 == 0, 1.0, -1.0)          # (-1)^{p+2N} = (-1)^k
     phase = np.ones((L,) * d)
@@ -100,5 +106,5 @@ def apply_fft(T: np.ndarray, v: np.ndarray) -> np.ndarray:
         shape = [1] * d
         shape[a] = L
         phase = phase * phase1.reshape(shape)
-    y = scipy.fft.ifftn(That * uhat * phase, workers=-1)
+    y = scipy.fft.ifftn(That * uhat * phase, workers=WORKERS)
     return y[(slice(0, W),) * d].real.copy()          # positions j + N for j = -N..N
