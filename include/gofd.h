@@ -204,6 +204,30 @@ int gofd_apply_afd(gofd_ctx ctx, gofd_fdop op, int nrhs, const double* v_dev, do
 int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const double* u_dev,
                   double* y_dev, int flags);
 
+/* Allocation-free variant of gofd_apply_Ah, for callers that cannot allocate
+ * device memory while they run: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, flags, results and
+ * errors as gofd_apply_Ah (the operator must have been created in ctx).  The
+ * product's grid workspaces (the grid result A_FD I u, the gathered field I u
+ * and the spectra of the FFT passes) live in one static device array of
+ * GOFD_NOALLOC_WS_BYTES bytes per GPU, which the library holds from its load
+ * until the process ends, instead of buffers of the operator; the call
+ * allocates nothing.  It needs, with b = 8 (b = 4 with GOFD_FP32_GRID) and
+ * each part rounded up to 256 bytes,
+ *   2 b W^d nrhs + 2 b W (L/2) nrhs                        (d = 2),
+ *   2 b W^3 nrhs + 2 b 4 ceil((L/2+1)/4) W (W + L) nrhs    (d = 3),
+ * where L is the FFT period (4N rounded up to a power of two); a request
+ * beyond the array fails with GOFD_E_ARG and a message giving the bytes
+ * needed (2D double precision: one field at W = 1025, seven at W = 513).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, threads or contexts)
+ * race, and the caller must order them.  Enqueued on the context's stream;
+ * asynchronous.  GOFD_E_HIP if the runtime could not give the array's device
+ * address when the context was created. */
+enum { GOFD_NOALLOC_WS_BYTES = 64 << 20 };
+int gofd_apply_Ah_noalloc(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const double* u_dev,
+                          double* y_dev, int flags);
+
 /* Column-pass schedules (2D): the pass that transforms the spectrum columns,
  * multiplies by the kernel's spectrum and transforms back (eq. AU-1) has
  * GOFD_N_COL_SCHED schedules (values per thread and column slots per block:

@@ -98,6 +98,7 @@ def _load():
         "gofd_fdop_free": [vp],
         "gofd_apply_afd": [vp, vp, i32, vp, vp, i32],
         "gofd_apply_Ah": [vp, vp, vp, i32, vp, vp, i32],
+        "gofd_apply_Ah_noalloc": [vp, vp, vp, i32, vp, vp, i32],
         "gofd_precond_create": [vp, vp, vp, i32, ctypes.POINTER(vp), ctypes.POINTER(PrecondInfo)],
         "gofd_precond_free": [vp],
         "gofd_precond_export": [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -130,6 +131,7 @@ EXPORTED = [
     "gofd_create", "gofd_destroy", "gofd_set_stream", "gofd_last_error", "gofd_strerror",
     "gofd_build_transfer", "gofd_transfer_free", "gofd_transfer_export", "gofd_fd_weights",
     "gofd_fdop_from_table", "gofd_fdop_get_table", "gofd_fdop_free", "gofd_apply_afd", "gofd_apply_Ah",
+    "gofd_apply_Ah_noalloc",
     "gofd_precond_create", "gofd_precond_free", "gofd_precond_export", "gofd_solve", "gofd_solve_batched",
     "gofd_solve_adjoint", "gofd_time_kernel",
 ]
@@ -277,6 +279,16 @@ def apply_Ah(ctx: Context, tr: Transfer, op: FdOp, u, flags=0):
     nrhs = u.numel() // tr.nv
     y = ctx._torch.empty_like(u)
     ctx.check(lib.gofd_apply_Ah(ctx.handle, tr.handle, op.handle, nrhs, _ptr(u), _ptr(y), int(flags)))
+    return y
+
+
+def apply_Ah_noalloc(ctx: Context, tr: Transfer, op: FdOp, u, y, flags=0):
+    """gofd_apply_Ah_noalloc: y (caller-allocated, like u) = A_h u with the product's workspaces in the
+    library's static device array (the call allocates nothing; calls on one GPU must not overlap)."""
+    if not (u.is_contiguous() and y.is_contiguous()) or y.numel() != u.numel():
+        raise ValueError("u and y must be contiguous and of the same size")
+    nrhs = u.numel() // tr.nv
+    ctx.check(lib.gofd_apply_Ah_noalloc(ctx.handle, tr.handle, op.handle, nrhs, _ptr(u), _ptr(y), int(flags)))
     return y
 
 

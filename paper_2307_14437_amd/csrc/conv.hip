@@ -887,8 +887,8 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   }
   if (!tw) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
   if (2 * (W - 1) > L) return gofd_fail(ctx, GOFD_E_ARG, "internal: window wider than half the period");
-  GOFD_TRY(dev_reserve(ctx, op->Z, sizeof(cplx<R>) * zs * nrhs));
-  cplx<R>* Z = op->Z.as<cplx<R>>();
+  if (!ctx->ws_Z) GOFD_TRY(dev_reserve(ctx, op->Z, sizeof(cplx<R>) * zs * nrhs));
+  cplx<R>* Z = ctx->ws_Z ? static_cast<cplx<R>*>(ctx->ws_Z) : op->Z.as<cplx<R>>();
   using C = Cfg<R, L>;
   const int pairs = (W + 1) / 2;
   const int nbA = (pairs + C::LINES_A - 1) / C::LINES_A;
@@ -1065,7 +1065,8 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   }
   if (g->pregathered) passes &= ~8;
   hipStream_t st = ctx->stream;
-  GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
+  if (!ctx->ws_G) GOFD_TRY(dev_reserve(ctx, op->G, (fp32 ? sizeof(float) : sizeof(double)) * nn * nrhs));
+  void* const Gp = ctx->ws_G ? ctx->ws_G : op->G.p;    // the gathered field I u
   const dim3 gg(grid1(nn, 256 * GATHER_NPT), nrhs);
   if (conv_gather_fused(op, fp32) && g->items && (passes & 8) && (passes & 1)) {
     // the FP32 gather of a batch runs inside the first row pass
@@ -1084,7 +1085,7 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
   if ((passes & 8) && g->items) {
     // batched: every item gathers from its own mesh
 #define GOFD_GI(R, D) \
-  GOFD_LAUNCH(ctx, (k_gather_items<R, D>), gg, dim3(256), 0, st, g->items, g->ubase, g->items_mask ? 1 : 0, nn, op->G.as<R>(), skip)
+  GOFD_LAUNCH(ctx, (k_gather_items<R, D>), gg, dim3(256), 0, st, g->items, g->ubase, g->items_mask ? 1 : 0, nn, static_cast<R*>(Gp), skip)
     if (d == 2) {
       if (fp32) GOFD_GI(float, 2); else GOFD_GI(double, 2);
     } else {
@@ -1102,33 +1103,33 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
     if (d == 2) {
       if (fp32)
         GOFD_LAUNCH(ctx, (k_gather<float, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
-                    tr->elem.as<int>(), tr->row32_v.as<int4>(), tr->row32_w.as<float2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(), skip);
+                    tr->elem.as<int>(), tr->row32_v.as<int4>(), tr->row32_w.as<float2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, static_cast<float*>(Gp), skip);
       else
         GOFD_LAUNCH(ctx, (k_gather<double, 2>), gg, dim3(256), 0, st, geom, tr->rec.as<ElemRec2>(),
-                    tr->elem.as<int>(), tr->row32_v.as<int4>(), tr->row32_w.as<float2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(), skip);
+                    tr->elem.as<int>(), tr->row32_v.as<int4>(), tr->row32_w.as<float2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, static_cast<double*>(Gp), skip);
     } else {
       const dim3 ge(grid1(nn, 256), nrhs);
       if (fp32)
         GOFD_LAUNCH(ctx, (k_gather_ell<float>), ge, dim3(256), 0, st, tr->ell_idx.as<int>(), tr->ell_v.as<int4>(),
-                    tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<float>(),
+                    tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, static_cast<float*>(Gp),
                     skip);
       else
         GOFD_LAUNCH(ctx, (k_gather_ell<double>), ge, dim3(256), 0, st, tr->ell_idx.as<int>(), tr->ell_v.as<int4>(),
-                    tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, op->G.as<double>(),
+                    tr->ell_w.as<double2>(), g->u, g->col_scale, g->mask, (long long)tr->nv, nn, static_cast<double*>(Gp),
                     skip);
     }
     HIP_TRY(ctx, hipGetLastError());
   }
   if (d == 3)
-    return conv3_run(ctx, op, nrhs, fp32 ? nullptr : op->G.as<double>(), fp32 ? op->G.as<float>() : nullptr, y, fp32,
+    return conv3_run(ctx, op, nrhs, fp32 ? nullptr : static_cast<double*>(Gp), fp32 ? static_cast<float*>(Gp) : nullptr, y, fp32,
                      passes & 7, skip.flag, skip.stride, dpart, lv1, fin, that_tab, skip.map);
   const RowScatter rs{g->rp_P ? g->items : nullptr, g->rp_P, g->rp_pstride, g->rp_ent_ahead};
   if (fp32) {
-    SrcPairGrid<float> src{op->G.as<float>(), nn};
+    SrcPairGrid<float> src{static_cast<float*>(Gp), nn};
     return dispatch_2d<float>(ctx, op, nrhs, src, static_cast<float*>(y), passes, skip, dpart, lv1, fin, that_tab,
                               rs);
   }
-  SrcPairGrid<double> src{op->G.as<double>(), nn};
+  SrcPairGrid<double> src{static_cast<double*>(Gp), nn};
   return dispatch_2d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin, that_tab,
                              rs);
 }
@@ -1271,8 +1272,8 @@ extern "C" int gofd_apply_afd(gofd_ctx ctx, gofd_fdop op, int nrhs, const double
   return GOFD_OK;
 }
 
-extern "C" int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const double* u, double* y,
-                             int flags) {
+int apply_Ah_impl(gofd_ctx_s* ctx, gofd_transfer_s* tr, gofd_fdop_s* op, int nrhs, const double* u, double* y,
+                  int flags, void* ygrid) {
   if (!ctx || !tr || !op || !u || !y || nrhs < 1) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
   if (!same_grid(tr, op)) return gofd_fail(ctx, GOFD_E_ARG, "transfer and operator use different grids");
   const bool fp32 = flags & GOFD_FP32_GRID;
@@ -1281,15 +1282,18 @@ extern "C" int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int n
   const bool interior = flags & GOFD_INTERIOR;
   if (sym && unscaled) return gofd_fail(ctx, GOFD_E_ARG, "SYMMETRIC and UNSCALED are exclusive");
   const long long n_nodes = tr->n_nodes;
-  GOFD_TRY(dev_reserve(ctx, op->Y, (fp32 ? sizeof(float) : sizeof(double)) * n_nodes * nrhs));
+  if (!ygrid) {
+    GOFD_TRY(dev_reserve(ctx, op->Y, (fp32 ? sizeof(float) : sizeof(double)) * n_nodes * nrhs));
+    ygrid = op->Y.p;
+  }
   GatherSpec g;
   g.tr = tr;
   g.u = u;
   g.col_scale = sym ? tr->dsqrt.as<double>() : nullptr;
   g.mask = interior ? tr->imask.as<double>() : nullptr;
-  GOFD_TRY(conv_apply(ctx, op, nrhs, nullptr, &g, op->Y.p, fp32));
+  GOFD_TRY(conv_apply(ctx, op, nrhs, nullptr, &g, ygrid, fp32));
   const double* scale = unscaled ? nullptr : (sym ? tr->dsqrt.as<double>() : tr->dscale.as<double>());
-  GOFD_TRY(scatter_apply(ctx, tr, nrhs, op->Y.p, fp32, scale, interior ? tr->imask.as<double>() : nullptr, y));
+  GOFD_TRY(scatter_apply(ctx, tr, nrhs, ygrid, fp32, scale, interior ? tr->imask.as<double>() : nullptr, y));
   if (flags & GOFD_SCALE_H2S) {
     const double f = 1.0 / op->h2s;
     long long n = tr->nv * nrhs;
@@ -1297,6 +1301,11 @@ extern "C" int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int n
   }
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
+}
+
+extern "C" int gofd_apply_Ah(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const double* u, double* y,
+                             int flags) {
+  return apply_Ah_impl(ctx, tr, op, nrhs, u, y, flags, nullptr);
 }
 
 // ---------------------------------------------------------------- operator from a table

@@ -327,8 +327,8 @@ int run_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   }
   if (!tw) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
   if (2 * (W - 1) > L) return gofd_fail(ctx, GOFD_E_ARG, "internal: window wider than half the period");
-  GOFD_TRY(dev_reserve(ctx, op->Z, sizeof(cplx<R>) * (z1s + z2s) * nrhs));
-  cplx<R>* Z1 = op->Z.as<cplx<R>>();
+  if (!ctx->ws_Z) GOFD_TRY(dev_reserve(ctx, op->Z, sizeof(cplx<R>) * (z1s + z2s) * nrhs));
+  cplx<R>* Z1 = ctx->ws_Z ? static_cast<cplx<R>*>(ctx->ws_Z) : op->Z.as<cplx<R>>();
   cplx<R>* Z2 = Z1 + z1s * nrhs;
   hipStream_t st = ctx->stream;
   const long long pairs = ((long long)W * W + 1) / 2;

@@ -69,6 +69,7 @@ extern "C" int gofd_create(gofd_ctx* out, void* hip_stream) {
     delete c;
     return GOFD_E_HIP;
   }
+  (void)noalloc_ws_lookup(c->device);   // once per device, with the device current
   *out = c;
   return GOFD_OK;
 }
@@ -151,6 +152,8 @@ static TwiddleTables* get_tables(gofd_ctx_s* ctx, int L) {
   ctx->twiddles[L] = tt;
   return tt;
 }
+
+bool twiddles_ready(const gofd_ctx_s* ctx, int L) { return ctx->twiddles.count(L) != 0; }
 
 const cplx<double>* twiddles64(gofd_ctx_s* ctx, int L) {
   auto* t = get_tables(ctx, L);

@@ -89,6 +89,12 @@ struct gofd_ctx_s {
   void* solver_ws = nullptr;
   void (*solver_ws_free)(void*) = nullptr;
   size_t host_state_bytes = 0;
+  // Workspace override: while set (by gofd_apply_Ah_noalloc, for the length
+  // of one call), the products take the gathered field I u from ws_G and the
+  // spectra of the FFT passes from ws_Z instead of reserving the operator's
+  // buffers, so that they allocate nothing
+  void* ws_G = nullptr;
+  void* ws_Z = nullptr;
   ~gofd_ctx_s();
 };
 
@@ -116,6 +122,12 @@ struct WorkStream {
 
 const cplx<double>* twiddles64(gofd_ctx_s* ctx, int L);
 const cplx<float>* twiddles32(gofd_ctx_s* ctx, int L);
+// whether the twiddle tables of period L already exist (no allocation)
+bool twiddles_ready(const gofd_ctx_s* ctx, int L);
+// Device address of the allocation-free entry point's static workspace on the
+// context's device, looked up once per device at context creation; nullptr
+// if the lookup failed (the entry point then reports GOFD_E_HIP).
+void* noalloc_ws_lookup(int device);
 
 // ------------------------------------------------------------------ handles
 
@@ -283,6 +295,12 @@ int conv_apply(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v, cons
                void* y, bool fp32, int passes = 15);
 
 bool same_grid(const gofd_transfer_s* tr, const gofd_fdop_s* op);
+
+// A_h u and its variants (the flags of gofd_apply_Ah); ygrid: workspace for
+// the grid result A_FD I u (nrhs fields of W^d values in the grid precision),
+// or nullptr to use the operator's buffer.
+int apply_Ah_impl(gofd_ctx_s* ctx, gofd_transfer_s* tr, gofd_fdop_s* op, int nrhs, const double* u, double* y,
+                  int flags, void* ygrid);
 
 // Number of blocks of the column pass (one partial of (A v, v) each; in 3D
 // the z-line pass).
