@@ -318,6 +318,10 @@ typedef struct {
                          /* without a graph, each stage bracketed by HIP events on the       */
                          /* library's stream, and the average milliseconds per launch of     */
                          /* every stage are written here (0 for a stage that never ran)      */
+  const double* x0;      /* gofd_solve only: optional device array of nrhs * N_v doubles,    */
+                         /* the initial guess (Dirichlet entries ignored; NULL = 0).  CG    */
+                         /* then runs on the correction K d = b - K x0 with the stop still  */
+                         /* ||b - K u|| <= tol ||b||, and u = x0 + d                         */
 } gofd_solve_opts;
 
 /* stages of one CG iteration, in the order of stage_ms */
@@ -336,7 +340,7 @@ typedef struct {
  * values outside the mesh are ignored since their rows of I are zero) or
  * eq. GoFD-3 (f_loc = GOFD_F_VERTEX: N_v doubles per rhs) for u on the
  * vertices, with u = 0 on Dirichlet vertices, to ||b - K u||_2 <= tol ||b||_2
- * (CG from u = 0).  pc may be NULL (plain CG) or a gofd_precond.
+ * (CG from u = 0, or from opts->x0).  pc may be NULL (plain CG) or a gofd_precond.
  *   f_dev: nrhs right-hand sides; u_dev: nrhs * N_v doubles (output).
  *   info: host array of nrhs entries (nullable).
  * Errors: GOFD_E_ARG, GOFD_E_NOT_CONVERGED, GOFD_E_BREAKDOWN, GOFD_E_HIP. */
@@ -373,6 +377,58 @@ int gofd_solve_adjoint(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precon
                        const double* dLdu_dev, const double* u_dev, const double* f_dev, double tol,
                        const gofd_solve_opts* opts, double* grad_f_dev, double* grad_X_dev,
                        double* lambda_dev, gofd_solve_info* info);
+
+/* ---------------------------------------------------------------- truncated CG */
+
+typedef struct gofd_cg_tape_s* gofd_cg_tape;
+
+typedef struct {
+  int iterations;        /* n: CG iterations run                                           */
+  int checkpoints;       /* stored checkpoints (iterations 0, c, 2c, ... <= n)             */
+  double rel_residual;   /* sqrt(gamma_n / (b, b)) of the recursive residual               */
+  int converged;         /* 1 if the tolerance stopped the iteration before max_iter       */
+} gofd_cg_tape_info;
+
+/* Conjugate gradients on eq. GoFD-2 (Section 3.2; f on the grid, W^d doubles,
+ * one right-hand side), textbook form in double precision, started from
+ * x0_dev (N_v doubles, Dirichlet entries ignored; NULL = 0) and stopped after
+ * max_iter iterations or once ||r|| <= tol ||b|| (tol = 0: exactly max_iter
+ * iterations unless the residual vanishes).  Writes x_n to x_dev (N_v).
+ * The iterate (x, r, p) is kept on the device every ckpt_every = c
+ * iterations (checkpoints 0, c, 2c, ...), with every iteration's gamma,
+ * delta, alpha and beta, in the tape returned in *tape (library-owned, freed
+ * with gofd_cg_tape_free; it refers to tr and op, which must outlive it).
+ * Device memory of the tape: 3 N_v (max_iter / c + 1) + 4 (max_iter + 1)
+ * doubles + a copy of f.  info (host, nullable).
+ * Errors: GOFD_E_ARG, GOFD_E_BREAKDOWN (p^T K p <= 0 or non-finite: no tape),
+ * GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_cg_checkpointed(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, const double* f_dev,
+                         const double* x0_dev, int max_iter, double tol, int ckpt_every, double* x_dev,
+                         gofd_cg_tape* tape, gofd_cg_tape_info* info);
+
+/* Reverse-mode (unrolled) gradient of the truncated solve recorded in tape:
+ * given xbar_dev = dL/dx_n (N_v doubles; Dirichlet entries ignored), the
+ * gradients of L through the n CG iterations with respect to f (grad_f_dev,
+ * W^d doubles), the vertex coordinates (grad_X_dev, N_v x d, with point
+ * location held fixed) and x_0 (grad_x0_dev, N_v); each output nullable.
+ * The iteration count n is held fixed (the stopping test is piecewise
+ * constant).  The iterates of each segment of c iterations are recomputed
+ * from its checkpoint, so the call costs about 2n + 2 products and holds c
+ * vertex vectors (and c grid fields when grad_X_dev is given).  When the
+ * truncated solve has converged the result approaches the adjoint of the
+ * converged system (gofd_solve_adjoint).  Synchronises.
+ * Errors: GOFD_E_ARG (tape from another context), GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_cg_unrolled_grad(gofd_ctx ctx, gofd_cg_tape tape, const double* xbar_dev, double* grad_f_dev,
+                          double* grad_X_dev, double* grad_x0_dev);
+
+/* Copy checkpoint j (0 <= j <= n / c) of a tape: x_{jc}, r_{jc}, p_{jc} to
+ * device buffers of N_v doubles (each nullable), and the scalar record to a
+ * host array of 4 (max_iter + 1) doubles (nullable): gamma_0..gamma_n, then
+ * delta_i, alpha_i, beta_i for i < n, each array max_iter + 1 long.
+ * Synchronises. */
+int gofd_cg_tape_read(gofd_ctx ctx, gofd_cg_tape tape, int j, double* x_dev, double* r_dev, double* p_dev,
+                      double* scalars_host);
+int gofd_cg_tape_free(gofd_cg_tape tape);
 
 #ifdef __cplusplus
 }

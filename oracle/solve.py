@@ -49,3 +49,33 @@ def pcg(apply_K, b, tol=1e-10, maxiter=10000, precond=None, x0=None):
         rz = rz_new
         p = z + beta * p
     raise RuntimeError(f"CG did not converge in {maxiter} iterations (rel. residual {hist[-1]:.3e})")
+
+
+def cg_iterates(apply_K, b, iters, x0=None):
+    """Exactly `iters` iterations of textbook CG (the steps of ``pcg`` without a
+    preconditioner or a stopping test) from x0 (default 0).  Returns the list of
+    iterates (x_i, r_i, p_i) for i = 0..iters and the scalars gamma_i = (r_i, r_i),
+    delta_i = (p_i, K p_i), alpha_i, beta_i.  Used as the truncated solve whose
+    derivative the unrolled gradient computes (parity of the checkpoints and
+    finite-difference pins)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply_K(x) if x0 is not None else b.copy()
+    p = r.copy()
+    g = float(r @ r)
+    out = [(x.copy(), r.copy(), p.copy())]
+    sc = {"gamma": [g], "delta": [], "alpha": [], "beta": []}
+    for _ in range(iters):
+        q = apply_K(p)
+        d = float(p @ q)
+        a = g / d
+        x = x + a * p
+        r = r - a * q
+        g1 = float(r @ r)
+        beta = g1 / g
+        p = r + beta * p
+        g = g1
+        out.append((x.copy(), r.copy(), p.copy()))
+        for k, v in (("gamma", g1), ("delta", d), ("alpha", a), ("beta", beta)):
+            sc[k].append(v)
+    return out, sc

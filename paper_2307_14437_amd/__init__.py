@@ -55,6 +55,11 @@ class TransferInfo(ctypes.Structure):
                 ("rp_slots", ctypes.c_int64), ("rp_entries", ctypes.c_int64), ("rp_seg_rows", ctypes.c_int64)]
 
 
+class CgTapeInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("checkpoints", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("converged", ctypes.c_int)]
+
+
 class FdwOpts(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("richardson", ctypes.c_int)]
 
@@ -67,7 +72,8 @@ class PrecondInfo(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("max_iter", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("history", ctypes.POINTER(ctypes.c_double)), ("stage_ms", ctypes.POINTER(ctypes.c_double))]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("stage_ms", ctypes.POINTER(ctypes.c_double)),
+                ("x0", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -111,6 +117,11 @@ def _load():
         "gofd_solve_adjoint": [vp, vp, vp, vp, vp, vp, vp, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp,
                                ctypes.POINTER(SolveInfo)],
         "gofd_time_kernel": [vp, vp, vp, i32, i32, vp, i32, i32, ctypes.POINTER(dbl)],
+        "gofd_cg_checkpointed": [vp, vp, vp, vp, vp, i32, dbl, i32, vp, ctypes.POINTER(vp),
+                                 ctypes.POINTER(CgTapeInfo)],
+        "gofd_cg_unrolled_grad": [vp, vp, vp, vp, vp, vp],
+        "gofd_cg_tape_read": [vp, vp, i32, vp, vp, vp, ctypes.POINTER(dbl)],
+        "gofd_cg_tape_free": [vp],
         "gofd_autotune": [vp, ctypes.POINTER(_Grid), i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
         "gofd_set_schedule": [vp, ctypes.POINTER(_Grid), i32, i32],
     }
@@ -133,7 +144,8 @@ EXPORTED = [
     "gofd_fdop_from_table", "gofd_fdop_get_table", "gofd_fdop_free", "gofd_apply_afd", "gofd_apply_Ah",
     "gofd_apply_Ah_noalloc",
     "gofd_precond_create", "gofd_precond_free", "gofd_precond_export", "gofd_solve", "gofd_solve_batched",
-    "gofd_solve_adjoint", "gofd_time_kernel",
+    "gofd_solve_adjoint", "gofd_time_kernel", "gofd_cg_checkpointed", "gofd_cg_unrolled_grad",
+    "gofd_cg_tape_read", "gofd_cg_tape_free",
 ]
 
 K_PASS_A, K_PASS_B, K_PASS_C, K_SCATTER, K_GATHER = 0, 1, 2, 3, 4
@@ -331,10 +343,19 @@ class Precond:
 STAGES = ("gather", "passA", "passB", "passC", "scatter", "precond")
 
 
+def _torch_float64():
+    import torch
+    return torch.float64
+
+
 def _opts(mode=MODE_FP64, max_iter=0, check_every=0, inner_tol=0.0, max_refine=0, use_graph=0, history=None,
-          stage_ms=None):
+          stage_ms=None, x0=None):
     o = SolveOpts(int(mode), int(max_iter), int(check_every), float(inner_tol), int(max_refine), int(use_graph),
-                  None, None)
+                  None, None, None)
+    if x0 is not None:
+        if not x0.is_contiguous() or x0.dtype != _torch_float64():
+            raise ValueError("x0 must be a contiguous float64 device tensor")
+        o.x0 = x0.data_ptr()
     if history is not None:
         o.history = history.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     if stage_ms is not None:
@@ -398,6 +419,57 @@ def solve_adjoint(ctx: Context, tr: Transfer, op: FdOp, dLdu, u, f, tol=1e-10, p
                                      float(tol), ctypes.byref(opts), _ptr(gf) if gf is not None else None,
                                      _ptr(gX) if gX is not None else None, _ptr(lam), ctypes.byref(info)))
     return gf, (gX.view(tr.nv, tr.d) if gX is not None else None), lam, info.as_dict()
+
+
+class CgTape:
+    """Truncated CG of eq. GoFD-2 with checkpointed iterates (gofd_cg_checkpointed); x holds x_n."""
+
+    def __init__(self, ctx: Context, tr: Transfer, op: FdOp, f, x0=None, max_iter=100, tol=0.0, ckpt_every=8):
+        torch = ctx._torch
+        self.ctx, self.tr, self.op, self.max_iter = ctx, tr, op, int(max_iter)
+        f = f.contiguous()
+        self.x = torch.empty(tr.nv, dtype=torch.float64, device=f.device)
+        h = ctypes.c_void_p()
+        info = CgTapeInfo()
+        ctx.check(lib.gofd_cg_checkpointed(ctx.handle, tr.handle, op.handle, _ptr(f),
+                                           _ptr(x0.contiguous()) if x0 is not None else None, self.max_iter,
+                                           float(tol), int(ckpt_every), _ptr(self.x), ctypes.byref(h),
+                                           ctypes.byref(info)))
+        self.handle = h
+        self.info = {k: getattr(info, k) for k, _ in CgTapeInfo._fields_}
+
+    def grad(self, xbar, want_f=True, want_X=True, want_x0=False):
+        """Unrolled gradients (grad_f on the grid, grad_X as N_v x d, grad_x0) of a loss with dL/dx_n = xbar."""
+        torch = self.ctx._torch
+        dev = xbar.device
+        gf = torch.empty(self.tr.n_nodes, dtype=torch.float64, device=dev) if want_f else None
+        gX = torch.empty(self.tr.nv * self.tr.d, dtype=torch.float64, device=dev) if want_X else None
+        g0 = torch.empty(self.tr.nv, dtype=torch.float64, device=dev) if want_x0 else None
+        self.ctx.check(lib.gofd_cg_unrolled_grad(self.ctx.handle, self.handle, _ptr(xbar.contiguous()),
+                                                 _ptr(gf) if gf is not None else None,
+                                                 _ptr(gX) if gX is not None else None,
+                                                 _ptr(g0) if g0 is not None else None))
+        return gf, (gX.view(self.tr.nv, self.tr.d) if gX is not None else None), g0
+
+    def checkpoint(self, j):
+        """(x, r, p) of checkpoint j and the scalar record (gamma, delta, alpha, beta arrays)."""
+        torch = self.ctx._torch
+        x, r, p = (torch.empty(self.tr.nv, dtype=torch.float64, device=self.x.device) for _ in range(3))
+        sc = np.empty(4 * (self.max_iter + 1), dtype=np.float64)
+        self.ctx.check(lib.gofd_cg_tape_read(self.ctx.handle, self.handle, int(j), _ptr(x), _ptr(r), _ptr(p),
+                                             sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return x, r, p, sc.reshape(4, self.max_iter + 1)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gofd_cg_tape_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 N_COL_SCHED = 4

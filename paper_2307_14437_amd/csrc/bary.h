@@ -160,3 +160,37 @@ __device__ __forceinline__ void node_weights(const GridGeom& g, const ElemRec<D>
   }
   rec_weights<D>(g, rec, idx, vid, lam);
 }
+
+// inverse of the (D+1)x(D+1) matrix E = [[x_0 .. x_D]; [1 .. 1]] by Gauss-Jordan
+template <int D>
+__device__ void inverse_E(const double* V, double* Ei) {
+  constexpr int n = D + 1;
+  double A[n][2 * n];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < 2 * n; ++j) A[i][j] = 0.0;
+  for (int r = 0; r < n; ++r) {        // column r = vertex r
+    for (int a = 0; a < D; ++a) A[a][r] = V[r * D + a];
+    A[D][r] = 1.0;
+  }
+  for (int i = 0; i < n; ++i) A[i][n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int i = c + 1; i < n; ++i)
+      if (fabs(A[i][c]) > fabs(A[piv][c])) piv = i;
+    if (piv != c)
+      for (int j = 0; j < 2 * n; ++j) {
+        const double t = A[c][j];
+        A[c][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    const double inv = 1.0 / A[c][c];
+    for (int j = 0; j < 2 * n; ++j) A[c][j] *= inv;
+    for (int i = 0; i < n; ++i) {
+      if (i == c) continue;
+      const double f = A[i][c];
+      for (int j = 0; j < 2 * n; ++j) A[i][j] -= f * A[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Ei[i * n + j] = A[i][n + j];
+}

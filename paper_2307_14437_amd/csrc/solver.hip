@@ -147,8 +147,11 @@ __global__ __launch_bounds__(BS) void k_cg_start(const CgItem* __restrict__ item
 
 // one block per rhs: initial state (gamma_prev = inf, alpha_prev = 1 make the
 // first beta zero and the first alpha gamma / delta)
+// bref (nullable): per item, the (b, b) the tolerance refers to when the
+// system being solved is the correction K d = b - K x0 of a warm start
 __global__ __launch_bounds__(BS) void k_cg_init(const double* __restrict__ partG, const double* __restrict__ partR,
-                                                int nb, Scal* __restrict__ sc, double tol) {
+                                                int nb, Scal* __restrict__ sc, double tol,
+                                                const double* __restrict__ bref) {
   __shared__ double sh[BS];
   const int rhs = blockIdx.x;
   const double g = sum_fixed(partG + (long long)rhs * nb, nb, sh);
@@ -159,8 +162,8 @@ __global__ __launch_bounds__(BS) void k_cg_init(const double* __restrict__ partG
   S.beta = 0.0;
   S.gamma = HUGE_VAL;
   S.rr = bb;
-  S.bb = bb;
-  S.tol2 = tol * tol * bb;
+  S.bb = bref ? bref[rhs] : bb;
+  S.tol2 = tol * tol * S.bb;
   S.done = (bb == 0.0) ? 1 : 0;
   S.status = ST_OK;
   if (!(g > 0.0) && bb > 0.0) {
@@ -891,6 +894,11 @@ struct Work {
   DevBuf partials, out2;        // residual partials, ||r||^2 and ||b||^2
   int nbs = 1;                  // blocks of the CG vector kernels (scatter, start) per item
   int per = 1;                  // vertex groups per scatter block
+  // warm start (gofd_solve with an initial guess): w.b holds b - K x0 and the
+  // tolerance refers to (b, b) of the original right-hand sides, per item
+  DevBuf bref;
+  const double* bref_on = nullptr;   // device copy while a warm-started solve runs, else null
+  std::vector<double> bref_host;
 };
 
 // the context's solver workspace and batch descriptors (made on first use,
@@ -1153,7 +1161,7 @@ int pcg_run(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, bool fp32, int
                      w.x.as<double>(), w.r.as<double>(), w.u.as<double>(), w.p.as<double>(), w.s.as<double>(),
                      w.partG.as<double>(), w.partR.as<double>());
   hipLaunchKernelGGL(k_cg_init, dim3(ni), dim3(BS), 0, st, w.partG.as<double>(), w.partR.as<double>(), w.nbs,
-                     w.scal.as<Scal>(), tol);
+                     w.scal.as<Scal>(), tol, w.bref_on);
   refresh_slots(ctx, B, w, fp32);
   HIP_TRY(ctx, hipGetLastError());
   hs.resize(ni);
@@ -1505,6 +1513,19 @@ int true_residual(gofd_ctx_s* ctx, const Batch& B, Work& w, const double* x, con
   return GOFD_OK;
 }
 
+__global__ void k_mask_copy(const double* __restrict__ a, const double* __restrict__ mask, long long n,
+                            double* __restrict__ b) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i] * mask[i];
+}
+
+// b += mask a
+__global__ void k_add_masked(const double* __restrict__ a, const double* __restrict__ mask, long long n,
+                             double* __restrict__ b) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] += a[i] * mask[i];
+}
+
 // right-hand sides of problem q into the batch vector b
 int form_rhs(gofd_ctx_s* ctx, const Problem& P, const double* f, int f_loc, double* b) {
   gofd_transfer_s* tr = P.tr;
@@ -1586,6 +1607,7 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
     for (int ref = 0; ref <= max_ref; ++ref) {
       // true residual of the current iterate (b - K xr); first pass has xr = 0
       GOFD_TRY(true_residual(ctx, B, w, w.xr.as<double>(), bsave.as<double>(), w.b.as<double>(), rr, bb));
+      if (w.bref_on) bb = w.bref_host;
       bool all = true;
       for (int k = 0; k < ni; ++k) {
         rel[k] = bb[k] > 0 ? std::sqrt(rr[k] / bb[k]) : 0.0;
@@ -1593,8 +1615,11 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
         all = all && conv[k];
       }
       if (all || ref == max_ref || total_it >= max_iter) break;
-      // correction: K d = r with single-precision grid products
+      // correction: K d = r with single-precision grid products (tolerance relative to this r)
+      const double* bref_keep = w.bref_on;
+      w.bref_on = nullptr;
       rc = pcg_run(ctx, B, w, inner, true, max_iter - total_it, check, graph, hs, nullptr, 0.0, nullptr, prof);
+      w.bref_on = bref_keep;
       if (rc != GOFD_OK) return rc;
       int mx = 0;
       for (int k = 0; k < ni; ++k) {
@@ -1628,6 +1653,7 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
   } else {
     const double* xfin = (mode == GOFD_MODE_FP32_REFINE) ? w.xr.as<double>() : w.x.as<double>();
     GOFD_TRY(true_residual(ctx, B, w, xfin, w.b.as<double>(), w.r.as<double>(), rr, bb));
+    if (w.bref_on) bb = w.bref_host;
   }
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   int worst = GOFD_OK;
@@ -1666,7 +1692,32 @@ extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_pre
   GOFD_TRY(reserve_work(ctx, w, B));
   GOFD_TRY(form_rhs(ctx, B.probs[0], f, f_loc, w.b.as<double>()));
   double* outs[1] = {u};
-  return solve_system(ctx, B, w, tol, opts, outs, info);
+  const double* x0 = opts ? opts->x0 : nullptr;
+  if (!x0) return solve_system(ctx, B, w, tol, opts, outs, info);
+  // warm start: CG from x0 is CG from 0 on the correction K d = b - K x0,
+  // stopped at ||b - K x0 - K d|| <= tol ||b||; then u = x0 + d
+  hipStream_t st = ctx->stream;
+  const long long nv = tr->nv, ntot = nv * nrhs;
+  for (int k = 0; k < nrhs; ++k)
+    hipLaunchKernelGGL(k_mask_copy, dim3(grid1(nv, 256)), dim3(256), 0, st, x0 + k * nv, tr->imask.as<double>(), nv,
+                       w.xr.as<double>() + k * nv);
+  std::vector<double> rr, bb;
+  GOFD_TRY(true_residual(ctx, B, w, w.xr.as<double>(), w.b.as<double>(), w.r.as<double>(), rr, bb));
+  HIP_TRY(ctx, hipMemcpyAsync(w.b.p, w.r.p, sizeof(double) * ntot, hipMemcpyDeviceToDevice, st));
+  GOFD_TRY(dev_reserve(ctx, w.bref, sizeof(double) * nrhs));
+  HIP_TRY(ctx, hipMemcpyAsync(w.bref.p, bb.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  w.bref_host = bb;
+  w.bref_on = w.bref.as<double>();
+  const int rc = solve_system(ctx, B, w, tol, opts, outs, info);
+  w.bref_on = nullptr;
+  // u = d + x0 (interior) also when the solve reports an error: u then holds its last iterate
+  for (int k = 0; k < nrhs; ++k)
+    hipLaunchKernelGGL(k_add_masked, dim3(grid1(nv, 256)), dim3(256), 0, st, x0 + k * nv, tr->imask.as<double>(), nv,
+                       u + k * nv);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return rc;
 }
 
 // Problems are grouped by grid shape (d, W, L); each group is one batch whose
@@ -1676,6 +1727,7 @@ extern "C" int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* 
                                   double tol, const gofd_solve_opts* opts, double* const* u, gofd_solve_info* info) {
   if (!ctx || nprob < 1 || !trs || !ops || !nrhs || !f || !u) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
   if (!(tol > 0.0)) return gofd_fail(ctx, GOFD_E_ARG, "tol must be positive");
+  if (opts && opts->x0) return gofd_fail(ctx, GOFD_E_ARG, "an initial guess is taken by gofd_solve only");
   std::vector<int> item0(nprob + 1, 0);
   for (int q = 0; q < nprob; ++q) {
     GOFD_TRY(check_problem(ctx, trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q]));
@@ -1740,40 +1792,6 @@ __global__ void k_gather_grid(GridGeom g, const ElemRec<D>* __restrict__ recs,
   v[k] = c * s;
 }
 
-// inverse of the (D+1)x(D+1) matrix E = [[x_0 .. x_D]; [1 .. 1]] by Gauss-Jordan
-template <int D>
-__device__ void inverse_E(const double* V, double* Ei) {
-  constexpr int n = D + 1;
-  double A[n][2 * n];
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < 2 * n; ++j) A[i][j] = 0.0;
-  for (int r = 0; r < n; ++r) {        // column r = vertex r
-    for (int a = 0; a < D; ++a) A[a][r] = V[r * D + a];
-    A[D][r] = 1.0;
-  }
-  for (int i = 0; i < n; ++i) A[i][n + i] = 1.0;
-  for (int c = 0; c < n; ++c) {
-    int piv = c;
-    for (int i = c + 1; i < n; ++i)
-      if (fabs(A[i][c]) > fabs(A[piv][c])) piv = i;
-    if (piv != c)
-      for (int j = 0; j < 2 * n; ++j) {
-        const double t = A[c][j];
-        A[c][j] = A[piv][j];
-        A[piv][j] = t;
-      }
-    const double inv = 1.0 / A[c][c];
-    for (int j = 0; j < 2 * n; ++j) A[c][j] *= inv;
-    for (int i = 0; i < n; ++i) {
-      if (i == c) continue;
-      const double f = A[i][c];
-      for (int j = 0; j < 2 * n; ++j) A[i][j] -= f * A[c][j];
-    }
-  }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) Ei[i * n + j] = A[i][n + j];
-}
-
 // dL/dX_{j,a} = sum over nodes k touching vertex j (as vertex i of elem(k)) of
 //   sum_r G_r(k) * (-(E^{-1})_{r,a} phi_i(x_k)),  G_r = lam_{v_r} r_k - (A I lam)_k u_{v_r}
 // One thread per vertex, nodes in ascending order: deterministic.
@@ -1816,11 +1834,6 @@ __global__ void k_rgrid(const double* __restrict__ f, const double* __restrict__
   if (k < n) r[k] = elem[k] >= 0 ? h2s * f[k] - yu[k] : 0.0;
 }
 
-__global__ void k_mask_copy(const double* __restrict__ a, const double* __restrict__ mask, long long n,
-                            double* __restrict__ b) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i] * mask[i];
-}
 
 }  // namespace
 

@@ -120,3 +120,36 @@ def test_adjoint3_matches_oracle(gctx):
     gfo, gXo = adjoint.gradients(otr, T, s, f, uJ, uJ - ut[otr.J])
     assert np.max(np.abs(fd.grad.cpu().numpy() - gfo)) <= 1e-9 * np.max(np.abs(gfo))
     assert np.max(np.abs(Xd.grad.cpu().numpy() - gXo)) <= 1e-8 * np.max(np.abs(gXo))
+
+
+@pytest.mark.parametrize("n,s,M", [(4, 0.3, 64), (8, 0.5, 128), (16, 0.7, 128), (32, 0.5, 256)])
+def test_fd_weights3_match_oracle_filon(gctx, n, s, M):
+    """The device's 3D T table (Filon's rule along every axis, eq. Tp-1D-2, Richardson over M and M/2,
+    Section 2.3) against the oracle's at the same level, with and without the extrapolation."""
+    import paper_2307_14437_amd as gofd
+    g = grid_for_box(3, n, R=1.0)
+    print(f"fd_weights 3D n={n} s={s} M={M}", flush=True)
+    Mused = M
+    while Mused // 2 < 2 * (2 * g.N) + 1:
+        Mused *= 2
+    Tg = gofd.FdOp(gctx, s, g, M=M).table()
+    To = fw.filon_richardson(s, 3, 2 * g.N, Mused)
+    assert Tg.shape == To.shape
+    assert np.max(np.abs(Tg - To)) < 1e-13 * abs(To[0, 0, 0])
+    T1 = gofd.FdOp(gctx, s, g, M=M, richardson=False).table()
+    assert np.max(np.abs(T1 - fw.filon(s, 3, 2 * g.N, Mused))) < 1e-13 * abs(To[0, 0, 0])
+    # the table is symmetric under axis permutations (psi~ is), which an index mix-up would break
+    assert np.max(np.abs(Tg - Tg.transpose(1, 0, 2))) < 1e-15 * abs(To[0, 0, 0])
+    assert np.max(np.abs(Tg - Tg.transpose(2, 1, 0))) < 1e-15 * abs(To[0, 0, 0])
+
+
+def test_fd_weights3_default_level_against_bessel(gctx):
+    """At the paper's 3D level (M = 2^11 with Richardson) the table agrees with the independent
+    subordination/Bessel route within the quadrature's remaining error ~C M^{-2-2s}."""
+    import paper_2307_14437_amd as gofd
+    g = grid_for_box(3, 16, R=1.0)
+    for s in (0.3, 0.7):
+        print(f"fd_weights 3D default level s={s}", flush=True)
+        T = gofd.FdOp(gctx, s, g).table()
+        for p in [(0, 0, 0), (0, 0, 1), (0, 1, 1), (1, 1, 1), (1, 2, 3), (0, 5, 9), (16, 16, 16)]:
+            assert abs(T[p] - fw.bessel_route(s, p)) < 2e-9 * abs(T[0, 0, 0]), p

@@ -242,3 +242,31 @@ def test_direct_launches_match_graph_replay(gctx, c1_setup, pc_name):
         u, info = gofd.solve(gctx, tr, op, f, tol=1e-11, pc=pc, use_graph=ug, mode=gofd.MODE_FP32_RELIABLE)
         assert info[0]["rel_residual"] <= 1e-11
         assert np.linalg.norm(u.cpu().numpy() - ref) <= 1e-9 * np.linalg.norm(ref), ug
+
+
+@pytest.mark.parametrize("mode_name", ["MODE_FP64", "MODE_FP32_RELIABLE", "MODE_FP32_REFINE"])
+def test_warm_start_from_x0(gctx, c1_setup, mode_name):
+    """CG from an initial guess: same solution and stopping test (relative to ||b||), fewer iterations
+    from a good guess, none to speak of from the solution itself; Dirichlet entries of x0 ignored."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    mode = getattr(gofd, mode_name)
+    f = _dev(np.ones((g.W, g.W)))
+    uref = _full(otr, solve.solve_dense(K, operator.rhs_grid(otr, 0.5, np.ones((g.W, g.W)))))
+    u0, i0 = gofd.solve(gctx, tr, op, f, tol=1e-10, mode=mode)
+    x0 = uref + 1e-6 * np.random.default_rng(1).standard_normal(m.nv) * np.abs(uref).max()
+    x0[otr.bnd] = 5.0                                   # ignored: Dirichlet vertices stay zero
+    u1, i1 = gofd.solve(gctx, tr, op, f, tol=1e-10, mode=mode, x0=_dev(x0))
+    print(mode_name, i0[0], i1[0], flush=True)
+    u1 = u1.cpu().numpy()
+    assert np.all(u1[otr.bnd] == 0.0)
+    assert i1[0]["rel_residual"] <= 1e-10
+    assert np.linalg.norm(u1 - uref) <= 1e-8 * np.linalg.norm(uref)
+    assert i1[0]["iterations"] < i0[0]["iterations"]
+    u2, i2 = gofd.solve(gctx, tr, op, f, tol=1e-10, mode=mode, x0=_dev(uref))
+    assert i2[0]["iterations"] <= 2 and i2[0]["rel_residual"] <= 1e-10
+    assert np.linalg.norm(u2.cpu().numpy() - uref) <= 1e-10 * np.linalg.norm(uref)
+    with pytest.raises(gofd.GofdError) as e:
+        gofd.solve_batched(gctx, [tr], [op], [None], [f], tol=1e-10, x0=_dev(uref))
+    assert e.value.code == gofd.E_ARG
