@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="restarted-refinement comparison: inner tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
+    ap.add_argument("--pc-lines", default="IC1_9_MC",
+                    help="comma-separated preconditioners timed beside plain CG on the same step ('' for none)")
     ap.add_argument("--col-schedule", type=int, default=-1,
                     help="column-pass schedule for both precisions instead of tuning it (counter runs)")
     args = ap.parse_args()
@@ -228,6 +230,39 @@ def main():
     _sync()
     ms_step64 = (time.perf_counter() - t0) * 1e3 / args.steps
 
+    # the paper's sparse preconditioner (IC(1) of A_h^(9), Section 3.3) in multicolour order: the same
+    # batched FP32 step, with the two triangular solves of every iteration on the device
+    pc_lines = {}
+    for name in args.pc_lines.split(",") if args.pc_lines else []:
+        _sync(); t = time.perf_counter()
+        pcs_x = [gofd.Precond(ctx, tr, op, name) for op in ops]
+        _sync(); t_setup = (time.perf_counter() - t) * 1e3
+
+        def step_pc(mode):
+            it = args.drop if mode == gofd.MODE_FP32_RELIABLE else args.inner_tol
+            return gofd.solve_batched(ctx, [tr] * len(svals), ops, pcs_x, [fd] * len(svals), tol=tol, mode=mode,
+                                      inner_tol=it)
+        res = {}
+        for mname, mode in (("fp32_reliable", gofd.MODE_FP32_RELIABLE), ("fp64", gofd.MODE_FP64)):
+            step_pc(mode)
+            _sync(); t0 = time.perf_counter()
+            for _ in range(max(1, args.steps // 4)):
+                up, ip = step_pc(mode)
+            _sync()
+            msp = (time.perf_counter() - t0) * 1e3 / max(1, args.steps // 4)
+            res[mname] = {"solves_per_s": len(svals) / (msp * 1e-3), "ms_per_step": msp,
+                          "iterations": {str(s): ip[i]["iterations"] for i, s in enumerate(svals)},
+                          "rel_error_vs_oracle": oracle_errors(cfg, tr, up)}
+        st_ms = np.zeros(len(gofd.STAGES))
+        gofd.solve(ctx, tr, ops[1], fd, tol=tol, pc=pcs_x[1], mode=gofd.MODE_FP32_RELIABLE, inner_tol=args.drop,
+                   stage_ms=st_ms)
+        pc_lines[name] = {"setup_ms_per_s": t_setup / len(svals), "colours": pcs_x[1].info["colours"],
+                          "levels": pcs_x[1].info["levels"], "nnz_L": pcs_x[1].info["nnz_L"],
+                          "apply_us": st_ms[gofd.STAGES.index("precond")] * 1e3,
+                          "product_us": float(sum(st_ms[:5])) * 1e3, **res}
+        for p_ in pcs_x:
+            p_.close()
+
     errs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for a, b in zip(u32, u64)]
     err_oracle = {"fp32_reliable": oracle_errors(cfg, tr, u32), "fp64": oracle_errors(cfg, tr, u64),
                   "fp32_restarted_refinement": oracle_errors(cfg, tr, ur)}
@@ -294,6 +329,7 @@ def main():
         "rel_error_vs_oracle": err_oracle,
         "all_within_1e-8_of_oracle": (None if any(v is None for v in err_oracle.values()) else
                                       all(e <= 1e-8 for v in err_oracle.values() for e in v.values())),
+        "preconditioned": pc_lines,
         "fp64": {"solves_per_s": len(svals) / (ms_step64 * 1e-3), "ms_per_step": ms_step64,
                  "iterations": {str(k): v for k, v in its64.items()}},
         "fp32_reliable": {"iterations": {str(s): info32[i]["iterations"] for i, s in enumerate(svals)},

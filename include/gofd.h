@@ -267,7 +267,8 @@ typedef enum {
   GOFD_PC_DIAG = 1,       /* M = D_h: CG on the symmetric form A~_h (eq. Ah-3)             */
   GOFD_PC_IC1_5 = 5,      /* IC(1) of I^T A_FD^(5) I  (Section 3.3, 2D)                     */
   GOFD_PC_IC1_9 = 9,      /* IC(1) of I^T A_FD^(9) I  (Section 3.3, 2D)                     */
-  GOFD_PC_IC1_27 = 27     /* IC(1) of I^T A_FD^(27) I (Example 4, 3D)                       */
+  GOFD_PC_IC1_27 = 27,    /* IC(1) of I^T A_FD^(27) I (Example 4, 3D)                       */
+  GOFD_PC_MULTICOLOR = 256  /* flag added to an IC kind: the factor in multicolour order      */
 } gofd_pc_kind;
 
 typedef struct {
@@ -275,6 +276,7 @@ typedef struct {
   int64_t nnz_L;          /* nonzeros of the lower factor                                  */
   int levels;             /* dependency levels of the forward triangular solve             */
   double setup_ms;        /* host + device setup time                                      */
+  int colours;            /* GOFD_PC_MULTICOLOR: colours of the ordering (0 otherwise)     */
 } gofd_precond_info;
 
 /* Build a preconditioner for eq. GoFD-2 on the interior block.  For the IC(1)
@@ -282,8 +284,14 @@ typedef struct {
  * sparse triple product I^T A_FD^(p) I, a level-of-fill <= 1 incomplete
  * Cholesky factorisation in the mesh's vertex order (pivot <= 0: restart on
  * A + alpha diag(A), alpha = 1e-3 doubling), uploaded with its dependency
- * levels for the triangular solves.  Setup runs on the host (the factor is
- * sequential by nature); applies run on the device.  info nullable. */
+ * levels for the triangular solves.  With GOFD_PC_MULTICOLOR added to the
+ * kind, the vertices are first coloured greedily (in vertex order, each the
+ * smallest colour none of its neighbours in A^(p) has) and ordered by
+ * (colour, vertex); the factor is that of P A P^T with level-1 fill kept only
+ * between vertices of different colours, so it has at most as many dependency
+ * levels as colours and each level is one device-wide launch.  Setup runs on
+ * the host (the factor is sequential by nature); applies run on the device.
+ * info nullable. */
 int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int kind, gofd_precond* out,
                         gofd_precond_info* info);
 int gofd_precond_free(gofd_precond pc);
@@ -291,6 +299,10 @@ int gofd_precond_free(gofd_precond pc);
  * identity rows).  Sizes from info->nnz_L; host buffers (synchronises). */
 int gofd_precond_export(gofd_ctx ctx, gofd_precond pc, int32_t* rowptr_host, int32_t* cols_host,
                         double* vals_host);
+/* Elimination order of the factor: row i of L is vertex perm_host[i] (N_v
+ * int32, host; the identity without GOFD_PC_MULTICOLOR).  The factor exported
+ * above is in that order. */
+int gofd_precond_export_order(gofd_ctx ctx, gofd_precond pc, int32_t* perm_host);
 
 enum { GOFD_F_GRID = 0, GOFD_F_VERTEX = 1 };
 enum {

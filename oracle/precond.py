@@ -16,6 +16,14 @@ doubled until the factorisation succeeds.
 
 Counts of iterations that the preconditioner saves are shown in the paper
 only in figures, so the iteration counts themselves are "parity unpinned".
+
+Multicolour variant (a reading for data-parallel triangular solves; the
+paper fixes no ordering): colour the graph of A greedily (vertices in index
+order, each taking the smallest colour that no already coloured neighbour
+has), order the vertices by (colour, index), and factor P A P^T with the
+level-1 fill kept only between vertices of different colours.  Vertices of
+one colour are then never coupled in the factor, so a triangular solve has at
+most as many dependency levels as there are colours.
 """
 
 from __future__ import annotations
@@ -166,3 +174,55 @@ def apply_ic(L: sp.csr_matrix, r: np.ndarray) -> np.ndarray:
     from scipy.sparse.linalg import spsolve_triangular
     y = spsolve_triangular(L, r, lower=True)
     return spsolve_triangular(L.T.tocsr(), y, lower=False)
+
+
+def greedy_colouring(A: sp.csr_matrix) -> np.ndarray:
+    """Colour of each vertex: in index order, the smallest colour not used by an already coloured
+    neighbour in the graph of A."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    colour = -np.ones(n, dtype=np.int64)
+    for i in range(n):
+        taken = {int(colour[j]) for j in A.indices[A.indptr[i]:A.indptr[i + 1]] if colour[j] >= 0}
+        c = 0
+        while c in taken:
+            c += 1
+        colour[i] = c
+    return colour
+
+
+def ic1_multicolour(A: sp.csr_matrix, level: int = 1):
+    """Multicolour IC(level): returns (L for P A P^T, perm, colour of each factor row, alpha), where
+    row i of L is vertex perm[i] and the fill between equal colours is dropped."""
+    A = sp.csr_matrix(A)
+    colour = greedy_colouring(A)
+    perm = np.lexsort((np.arange(A.shape[0]), colour))
+    Ap = A[perm][:, perm].tocsr()
+    cp = colour[perm]
+    pattern = [[j for j in row if j == i or cp[j] != cp[i]] for i, row in enumerate(ic1_pattern(Ap, level))]
+    alpha = 0.0
+    while True:
+        As = Ap if alpha == 0.0 else (Ap + alpha * sp.diags(Ap.diagonal())).tocsr()
+        L, ok = ic_numeric(As, pattern)
+        if ok:
+            return L, perm, cp, alpha
+        alpha = 1e-3 if alpha == 0.0 else 2 * alpha
+
+
+def apply_ic_ordered(L: sp.csr_matrix, perm: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """z = P^T (L L^T)^{-1} P r for a factor in the order perm."""
+    z = np.empty_like(r)
+    z[perm] = apply_ic(L, r[perm])
+    return z
+
+
+def dependency_levels(L: sp.csr_matrix) -> int:
+    """Longest chain of the forward solve: level(i) = 1 + max level of the columns j < i of row i."""
+    L = sp.csr_matrix(L)
+    lev = np.zeros(L.shape[0], dtype=np.int64)
+    for i in range(L.shape[0]):
+        cols = L.indices[L.indptr[i]:L.indptr[i + 1]]
+        cols = cols[cols < i]
+        lev[i] = lev[cols].max() + 1 if cols.size else 0
+    return int(lev.max()) + 1 if L.shape[0] else 0
+

@@ -30,7 +30,10 @@ FP32_GRID, SYMMETRIC, UNSCALED, SCALE_H2S, INTERIOR = 1, 2, 4, 8, 16
 
 # preconditioners
 PC_NONE, PC_DIAG, PC_IC1_5, PC_IC1_9, PC_IC1_27 = 0, 1, 5, 9, 27
-PC_BY_NAME = {"NONE": PC_NONE, "DIAG": PC_DIAG, "IC1_5": PC_IC1_5, "IC1_9": PC_IC1_9, "IC1_27": PC_IC1_27}
+PC_MULTICOLOR = 256
+PC_BY_NAME = {"NONE": PC_NONE, "DIAG": PC_DIAG, "IC1_5": PC_IC1_5, "IC1_9": PC_IC1_9, "IC1_27": PC_IC1_27,
+              "IC1_5_MC": PC_IC1_5 | PC_MULTICOLOR, "IC1_9_MC": PC_IC1_9 | PC_MULTICOLOR,
+              "IC1_27_MC": PC_IC1_27 | PC_MULTICOLOR}
 
 F_GRID, F_VERTEX = 0, 1
 MODE_FP64, MODE_FP32_REFINE, MODE_FP32_RELIABLE = 0, 1, 2
@@ -66,7 +69,7 @@ class FdwOpts(ctypes.Structure):
 
 class PrecondInfo(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_double), ("nnz_L", ctypes.c_int64), ("levels", ctypes.c_int),
-                ("setup_ms", ctypes.c_double)]
+                ("setup_ms", ctypes.c_double), ("colours", ctypes.c_int)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -109,6 +112,7 @@ def _load():
         "gofd_precond_free": [vp],
         "gofd_precond_export": [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(dbl)],
+        "gofd_precond_export_order": [vp, vp, ctypes.POINTER(ctypes.c_int32)],
         "gofd_solve": [vp, vp, vp, vp, i32, vp, i32, dbl, ctypes.POINTER(SolveOpts), vp,
                        ctypes.POINTER(SolveInfo)],
         "gofd_solve_batched": [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -143,7 +147,8 @@ EXPORTED = [
     "gofd_build_transfer", "gofd_transfer_free", "gofd_transfer_export", "gofd_fd_weights",
     "gofd_fdop_from_table", "gofd_fdop_get_table", "gofd_fdop_free", "gofd_apply_afd", "gofd_apply_Ah",
     "gofd_apply_Ah_noalloc",
-    "gofd_precond_create", "gofd_precond_free", "gofd_precond_export", "gofd_solve", "gofd_solve_batched",
+    "gofd_precond_create", "gofd_precond_free", "gofd_precond_export", "gofd_precond_export_order",
+    "gofd_solve", "gofd_solve_batched",
     "gofd_solve_adjoint", "gofd_time_kernel", "gofd_cg_checkpointed", "gofd_cg_unrolled_grad",
     "gofd_cg_tape_read", "gofd_cg_tape_free",
 ]
@@ -327,6 +332,13 @@ class Precond:
                                                ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                                va.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return sp.csr_matrix((va, ci, rp), shape=(self.nv, self.nv))
+
+    def order(self):
+        """Elimination order of the factor: row i of export() is vertex order()[i]."""
+        perm = np.empty(self.nv, dtype=np.int32)
+        self.ctx.check(lib.gofd_precond_export_order(self.ctx.handle, self.handle,
+                                                     perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return perm
 
     def close(self):
         if getattr(self, "handle", None):

@@ -209,3 +209,61 @@ bool ic_numeric(const HostCsr& A, double shift, const std::vector<int64_t>& Lptr
   }
   return true;
 }
+
+int greedy_colouring(const HostCsr& A, std::vector<int32_t>& colour) {
+  const int64_t n = A.n;
+  colour.assign(n, -1);
+  std::vector<int64_t> stamp(1, -1);    // stamp[c] == i: colour c is taken by a neighbour of i
+  int ncol = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+      const int32_t c = colour[A.col[e]];
+      if (c >= 0) stamp[c] = i;
+    }
+    int32_t c = 0;
+    while (c < (int32_t)stamp.size() && stamp[c] == i) ++c;
+    if (c == (int32_t)stamp.size()) stamp.push_back(-1);
+    colour[i] = c;
+    ncol = std::max(ncol, (int)c + 1);
+  }
+  return ncol;
+}
+
+void permute_symmetric(const HostCsr& A, const std::vector<int32_t>& perm, HostCsr& B) {
+  const int64_t n = A.n;
+  std::vector<int32_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[perm[i]] = (int32_t)i;
+  B.n = n;
+  B.rowptr.assign(n + 1, 0);
+  B.col.clear();
+  B.val.clear();
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t v = perm[i];
+    row.clear();
+    for (int64_t e = A.rowptr[v]; e < A.rowptr[v + 1]; ++e) row.push_back({inv[A.col[e]], A.val[e]});
+    std::sort(row.begin(), row.end());
+    for (auto& pr : row) {
+      B.col.push_back(pr.first);
+      B.val.push_back(pr.second);
+    }
+    B.rowptr[i + 1] = (int64_t)B.col.size();
+  }
+}
+
+void drop_same_colour(const std::vector<int32_t>& colour, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol) {
+  const int64_t n = (int64_t)Lptr.size() - 1;
+  std::vector<int64_t> ptr(n + 1, 0);
+  std::vector<int32_t> col;
+  col.reserve(Lcol.size());
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = Lptr[i]; e < Lptr[i + 1]; ++e) {
+      const int32_t j = Lcol[e];
+      if (j == i || colour[j] != colour[i]) col.push_back(j);
+    }
+    ptr[i + 1] = (int64_t)col.size();
+  }
+  Lptr.swap(ptr);
+  Lcol.swap(col);
+}
+

@@ -26,3 +26,11 @@ bool assemble_pattern_matrix(const HostTransfer& t, const double* T, int npts, H
 void ic_symbolic(const HostCsr& A, int level, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol);
 bool ic_numeric(const HostCsr& A, double shift, const std::vector<int64_t>& Lptr, const std::vector<int32_t>& Lcol,
                 std::vector<double>& Lval);
+// Greedy colouring of the graph of A: vertices in index order, each taking the
+// smallest colour no already coloured neighbour has.  Returns the colour count.
+int greedy_colouring(const HostCsr& A, std::vector<int32_t>& colour);
+// B = P A P^T for the order perm (B_ij = A_{perm[i], perm[j]}), rows sorted.
+void permute_symmetric(const HostCsr& A, const std::vector<int32_t>& perm, HostCsr& B);
+// Drop the off-diagonal entries of a lower pattern that join two vertices of
+// the same colour (colour given in the pattern's numbering).
+void drop_same_colour(const std::vector<int32_t>& colour, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol);

@@ -552,6 +552,55 @@ __global__ __launch_bounds__(1024) void k_trsv_levels(const int* __restrict__ pt
   }
 }
 
+// One dependency level of a triangular solve with its rows spread over the
+// grid (blockIdx.x) and one right-hand side per blockIdx.y: used when the
+// factor has few levels (multicolour order), one launch per level, so that
+// no workgroup waits on another.
+template <bool LOWER>
+__global__ void k_trsv_level(const int* __restrict__ ptr, const int* __restrict__ col,
+                             const double* __restrict__ val, const int* __restrict__ rows, int r0, int r1,
+                             const double* __restrict__ rhs_in, double* __restrict__ out, long long stride,
+                             const Scal* __restrict__ sc) {
+  const int k = blockIdx.y;
+  if (sc && sc[k].done) return;
+  const int t = r0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= r1) return;
+  const double* b = rhs_in + k * stride;
+  double* y = out + k * stride;
+  const int row = rows[t];
+  const int e0 = ptr[row], e1 = ptr[row + 1];
+  const int dpos = LOWER ? e1 - 1 : e0;
+  const int lo = LOWER ? e0 : e0 + 1, hi = LOWER ? e1 - 1 : e1;
+  double s = 0.0;
+  for (int i = lo; i < hi; ++i) s += val[i] * y[col[i]];
+  y[row] = (b[row] - s) / val[dpos];
+}
+
+// out[i] = in[perm[i]] (to = true) or out[perm[i]] = in[i], per right-hand side blockIdx.y
+template <bool TO>
+__global__ void k_permute(const double* __restrict__ in, const int* __restrict__ perm, long long n,
+                          long long stride, const Scal* __restrict__ sc, double* __restrict__ out) {
+  const int k = blockIdx.y;
+  if (sc && sc[k].done) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (TO) out[k * stride + i] = in[k * stride + perm[i]];
+  else out[k * stride + perm[i]] = in[k * stride + i];
+}
+
+// gamma = (r, u) per right-hand side (one block each), written as partial 0 of nbu, the others zero
+__global__ __launch_bounds__(1024) void k_dot_rhs(const double* __restrict__ r, const double* __restrict__ u,
+                                                  long long n, long long stride, const Scal* __restrict__ sc,
+                                                  double* __restrict__ partG, int nbu) {
+  __shared__ double sh[1024 / 64];
+  const int k = blockIdx.x;
+  if (sc && sc[k].done) return;
+  double s = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 1024) s += r[k * stride + i] * u[k * stride + i];
+  block_sum_n<1024, 1>(&s, sh);
+  for (int i = threadIdx.x; i < nbu; i += 1024) partG[(long long)k * nbu + i] = (i == 0) ? s : 0.0;
+}
+
 __global__ void k_fill_d(double* __restrict__ p, long long n, double v) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -569,8 +618,17 @@ struct gofd_precond_s {
   int Lnlev = 0, Unlev = 0;
   std::vector<int32_t> hLptr, hLcol;
   std::vector<double> hLval;
+  // multicolour order: factor row i is vertex perm[i] (vectors are permuted
+  // around the solves); few levels, so each level is its own launch
+  DevBuf perm;
+  std::vector<int32_t> hperm;
+  std::vector<int32_t> hLlp, hUlp;   // level boundaries (host copies for the per-level launches)
   gofd_precond_info info{};
 };
+
+// levels at most this many: one launch per level over the whole device; more:
+// one workgroup per right-hand side with a barrier per level
+constexpr int TRSV_LEVEL_LAUNCH_MAX = 64;
 
 static int host_transfer(gofd_ctx_s* ctx, gofd_transfer_s* tr, HostTransfer& h) {
   hipStream_t st = ctx->stream;
@@ -611,10 +669,12 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     if (info) *info = pc->info;
     return GOFD_OK;
   }
+  const bool mc = (kind & GOFD_PC_MULTICOLOR) != 0;
+  const int base = kind & ~GOFD_PC_MULTICOLOR;
   int npts = 0;
-  if (kind == GOFD_PC_IC1_5 && tr->d == 2) npts = 5;
-  if (kind == GOFD_PC_IC1_9 && tr->d == 2) npts = 9;
-  if (kind == GOFD_PC_IC1_27 && tr->d == 3) npts = 27;
+  if (base == GOFD_PC_IC1_5 && tr->d == 2) npts = 5;
+  if (base == GOFD_PC_IC1_9 && tr->d == 2) npts = 9;
+  if (base == GOFD_PC_IC1_27 && tr->d == 3) npts = 27;
   if (!npts) return gofd_fail(ctx, GOFD_E_ARG, "preconditioner kind does not match the dimension");
   HostTransfer ht;
   GOFD_TRY(host_transfer(ctx, tr, ht));
@@ -623,7 +683,29 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     return gofd_fail(ctx, GOFD_E_ARG, "pattern assembly failed");
   std::vector<int64_t> Lptr;
   std::vector<int32_t> Lcol;
-  ic_symbolic(A, 1, Lptr, Lcol);
+  if (mc) {
+    // greedy colouring of A's graph, vertices ordered by (colour, index); the
+    // factor is computed for P A P^T with level-1 fill kept only between
+    // vertices of different colours, so a colour's rows never depend on each other
+    std::vector<int32_t> colour;
+    pc->info.colours = greedy_colouring(A, colour);
+    pc->hperm.resize(A.n);
+    for (int64_t i = 0; i < A.n; ++i) pc->hperm[i] = (int32_t)i;
+    std::stable_sort(pc->hperm.begin(), pc->hperm.end(),
+                     [&](int32_t a, int32_t b) { return colour[a] < colour[b]; });
+    HostCsr B;
+    permute_symmetric(A, pc->hperm, B);
+    A.rowptr.swap(B.rowptr);
+    A.col.swap(B.col);
+    A.val.swap(B.val);
+    std::vector<int32_t> pcol(A.n);
+    for (int64_t i = 0; i < A.n; ++i) pcol[i] = colour[pc->hperm[i]];
+    colour.swap(pcol);
+    ic_symbolic(A, 1, Lptr, Lcol);
+    drop_same_colour(colour, Lptr, Lcol);
+  } else {
+    ic_symbolic(A, 1, Lptr, Lcol);
+  }
   std::vector<double> Lval;
   double alpha = 0.0;
   while (!ic_numeric(A, alpha, Lptr, Lcol, Lval)) {
@@ -684,8 +766,14 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     std::vector<int32_t> cur2(Ulp.begin(), Ulp.end() - 1);
     for (int64_t i = 0; i < n; ++i) Ulr[cur2[lev[i]]++] = (int32_t)i;
     pc->Unlev = depth;
+    pc->hLlp = Llp;
+    pc->hUlp = Ulp;
   }
   hipStream_t st = ctx->stream;
+  if (mc) {
+    GOFD_TRY(dev_reserve(ctx, pc->perm, sizeof(int32_t) * n));
+    HIP_TRY(ctx, hipMemcpyAsync(pc->perm.p, pc->hperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+  }
   GOFD_TRY(dev_reserve(ctx, pc->Lptr, sizeof(int32_t) * (n + 1)));
   GOFD_TRY(dev_reserve(ctx, pc->Lcol, sizeof(int32_t) * nnz));
   GOFD_TRY(dev_reserve(ctx, pc->Lval, sizeof(double) * nnz));
@@ -722,6 +810,13 @@ extern "C" int gofd_precond_free(gofd_precond pc) {
   return GOFD_OK;
 }
 
+extern "C" int gofd_precond_export_order(gofd_ctx ctx, gofd_precond pc, int32_t* perm) {
+  if (!ctx || !pc || !perm) return gofd_fail(ctx, GOFD_E_ARG, "null argument");
+  if (pc->hLptr.empty()) return gofd_fail(ctx, GOFD_E_ARG, "preconditioner has no factor");
+  for (int64_t i = 0; i < pc->nv; ++i) perm[i] = pc->hperm.empty() ? (int32_t)i : pc->hperm[i];
+  return GOFD_OK;
+}
+
 extern "C" int gofd_precond_export(gofd_ctx ctx, gofd_precond pc, int32_t* rowptr, int32_t* cols, double* vals) {
   if (!ctx || !pc || !rowptr || !cols || !vals) return gofd_fail(ctx, GOFD_E_ARG, "null argument");
   if (pc->hLptr.empty()) return gofd_fail(ctx, GOFD_E_ARG, "preconditioner has no factor");
@@ -743,7 +838,8 @@ struct Problem {
 };
 
 bool is_ic(const gofd_precond_s* pc) {
-  return pc && (pc->kind == GOFD_PC_IC1_5 || pc->kind == GOFD_PC_IC1_9 || pc->kind == GOFD_PC_IC1_27);
+  const int base = pc ? (pc->kind & ~GOFD_PC_MULTICOLOR) : 0;
+  return pc && (base == GOFD_PC_IC1_5 || base == GOFD_PC_IC1_9 || base == GOFD_PC_IC1_27);
 }
 
 // 1: diagonal (D_h), 0: none, -1: IC(1) factor
@@ -883,6 +979,7 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
 
 struct Work {
   DevBuf x, r, u, p, s, b, xr, dvec, q, grid;
+  DevBuf pr, pu;                // r and u in a preconditioner's multicolour order
   DevBuf P;                     // row-pair form: partial slots, double[nitems][slots_max]
   DevBuf us;                    // with the segment rows: u per slot, float[nitems][slots_max] (row-pair-major)
   DevBuf amap;                  // int[nitems]: the items still iterating (first nact entries)
@@ -920,6 +1017,8 @@ static BatchBufs& ctx_batch(gofd_ctx_s* ctx) { return ctx_cache(ctx).b; }
 int reserve_work(gofd_ctx_s* ctx, Work& w, const Batch& B) {
   const size_t vb = sizeof(double) * std::max<long long>(B.ntot, 1);
   for (DevBuf* b : {&w.x, &w.r, &w.u, &w.p, &w.s, &w.b, &w.xr, &w.dvec, &w.q}) GOFD_TRY(dev_reserve(ctx, *b, vb));
+  if (B.any_ic)
+    for (DevBuf* b : {&w.pr, &w.pu}) GOFD_TRY(dev_reserve(ctx, *b, vb));
   long long nn = 1;
   for (int a = 0; a < B.op0->d; ++a) nn *= B.op0->W;
   const int ni = B.nitems;
@@ -1001,6 +1100,39 @@ int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, doub
     const long long n = P.tr->nv, o = B.poff[q];
     const int i0 = B.pitem[q];
     const Scal* scq = sc ? sc + i0 : nullptr;
+    if (pc->Lnlev <= TRSV_LEVEL_LAUNCH_MAX && pc->Unlev <= TRSV_LEVEL_LAUNCH_MAX) {
+      // few levels: one launch per level over the device; vectors in the
+      // factor's order when it has one (pr, pu: permuted r and u)
+      const bool perm = !pc->hperm.empty();
+      const double* rin = w.r.as<double>() + o;
+      double* uout = w.u.as<double>() + o;
+      const dim3 gp(grid1(n, 256), P.nrhs);
+      if (perm) {
+        hipLaunchKernelGGL(k_permute<true>, gp, dim3(256), 0, st, rin, pc->perm.as<int>(), n, n, scq,
+                           w.pr.as<double>() + o);
+        rin = w.pr.as<double>() + o;
+        uout = w.pu.as<double>() + o;
+      }
+      for (int l = 0; l < pc->Lnlev; ++l) {
+        const int r0 = pc->hLlp[l], r1 = pc->hLlp[l + 1];
+        hipLaunchKernelGGL(k_trsv_level<true>, dim3(grid1(r1 - r0, 256), P.nrhs), dim3(256), 0, st,
+                           pc->Lptr.as<int>(), pc->Lcol.as<int>(), pc->Lval.as<double>(), pc->Llev_rows.as<int>(), r0,
+                           r1, rin, w.dvec.as<double>() + o, n, scq);
+      }
+      for (int l = 0; l < pc->Unlev; ++l) {
+        const int r0 = pc->hUlp[l], r1 = pc->hUlp[l + 1];
+        hipLaunchKernelGGL(k_trsv_level<false>, dim3(grid1(r1 - r0, 256), P.nrhs), dim3(256), 0, st,
+                           pc->Uptr.as<int>(), pc->Ucol.as<int>(), pc->Uval.as<double>(), pc->Ulev_rows.as<int>(), r0,
+                           r1, w.dvec.as<double>() + o, uout, n, scq);
+      }
+      if (perm)
+        hipLaunchKernelGGL(k_permute<false>, gp, dim3(256), 0, st, uout, pc->perm.as<int>(), n, n, scq,
+                           w.u.as<double>() + o);
+      if (partG)
+        hipLaunchKernelGGL(k_dot_rhs, dim3(P.nrhs), dim3(1024), 0, st, w.r.as<double>() + o, w.u.as<double>() + o, n,
+                           n, scq, partG + (long long)i0 * w.nbs, w.nbs);
+      continue;
+    }
     hipLaunchKernelGGL((k_trsv_levels<true>), dim3(P.nrhs), dim3(1024), 0, st, pc->Lptr.as<int>(),
                        pc->Lcol.as<int>(), pc->Lval.as<double>(), pc->Llev_ptr.as<int>(), pc->Llev_rows.as<int>(),
                        pc->Lnlev, w.r.as<double>() + o, w.dvec.as<double>() + o, n, scq, nullptr, nullptr, w.nbs);
@@ -1615,6 +1747,12 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
         all = all && conv[k];
       }
       if (all || ref == max_ref || total_it >= max_iter) break;
+      // items already within the tolerance take no further correction: a zero right-hand side stops their
+      // CG before the first iteration, so d = 0 and their x stays as it is
+      for (int k = 0; k < ni; ++k)
+        if (conv[k])
+          hipLaunchKernelGGL(k_fill_d, dim3(grid1(B.inv[k], 256)), dim3(256), 0, st, w.b.as<double>() + B.ioff[k],
+                             B.inv[k], 0.0);
       // correction: K d = r with single-precision grid products (tolerance relative to this r)
       const double* bref_keep = w.bref_on;
       w.bref_on = nullptr;
@@ -1623,10 +1761,9 @@ static int solve_system(gofd_ctx_s* ctx, const Batch& B, Work& w, double tol, co
       if (rc != GOFD_OK) return rc;
       int mx = 0;
       for (int k = 0; k < ni; ++k) {
-        if (!conv[k]) {
-          iters[k] += hs[k].iters;
-          refs[k] += 1;
-        }
+        if (conv[k]) continue;
+        iters[k] += hs[k].iters;
+        refs[k] += 1;
         mx = std::max(mx, hs[k].iters);
         if (hs[k].status == ST_BREAKDOWN) status[k] = GOFD_E_BREAKDOWN;
       }

@@ -69,6 +69,21 @@ def test_c2_solutions_within_1e8_of_oracle(gctx, c2_gpu, mode_name):
         assert e <= 1e-8
 
 
+def test_c2_multicolour_ic1_solutions_within_1e8_of_oracle(gctx, c2_gpu):
+    """The same step preconditioned by IC(1) of A_h^(9) in multicolour order (Section 3.3)."""
+    import paper_2307_14437_amd as gofd
+    cfg, tr, ops, refs, fd = c2_gpu
+    pcs = [gofd.Precond(gctx, tr, op, "IC1_9_MC") for op in ops]
+    print("IC1_9_MC", pcs[1].info, flush=True)
+    assert pcs[1].info["levels"] <= pcs[1].info["colours"] <= 32
+    for mode in (gofd.MODE_FP32_RELIABLE, gofd.MODE_FP64):
+        us, infos = gofd.solve_batched(gctx, [tr] * 2, ops, pcs, [fd, fd], tol=cfg["tol"], mode=mode, inner_tol=0.1)
+        errs = _errors(us, refs)
+        print(mode, [i["iterations"] for i in infos], errs, flush=True)
+        for e in errs:
+            assert e <= 1e-8
+
+
 def test_c2_tight_fp64_solve_matches_oracle(gctx, c2_gpu):
     """FP64 GPU solves driven to a relative residual of 1e-12: what remains is the difference of the two
     T tables (<= 1e-13 relative) times the condition number (~1.3e3 at s = 0.75)."""

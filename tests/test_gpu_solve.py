@@ -35,7 +35,7 @@ def _full(otr, uJ):
     return u
 
 
-@pytest.mark.parametrize("pc_name", ["NONE", "DIAG", "IC1_5", "IC1_9"])
+@pytest.mark.parametrize("pc_name", ["NONE", "DIAG", "IC1_5", "IC1_9", "IC1_5_MC", "IC1_9_MC"])
 def test_c1_solve_matches_dense_lu(gctx, c1_setup, pc_name):
     import paper_2307_14437_amd as gofd
     m, g, otr, T, tr, op, K = c1_setup
@@ -81,6 +81,31 @@ def test_ic1_factor_matches_oracle(gctx, c1_setup):
         assert np.max(np.abs(Lgi.data - Lo.data)) < 1e-12 * np.max(np.abs(Lo.data))
         Lb = Lg[otr.bnd]                                  # Dirichlet rows are identity rows
         assert np.array_equal(Lb.indices, np.nonzero(otr.bnd)[0]) and np.all(Lb.data == 1.0)
+
+
+def test_multicolour_ic1_factor_matches_oracle(gctx, c1_setup):
+    """Multicolour IC(1): the library's order and factor equal the oracle's (Dirichlet vertices are
+    isolated identity rows of colour 0 in the library's matrix and absent from the oracle's), and the
+    triangular solves run in as many device-wide levels as the factor has."""
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    for name, npts in (("IC1_9_MC", 9), ("IC1_5_MC", 5)):
+        pc = gofd.Precond(gctx, tr, op, name)
+        order = pc.order()
+        Lg = pc.export().tocsr()
+        Lo, perm, cp, alpha = precond.ic1_multicolour(precond.Ah_pattern(otr, T, npts))
+        assert alpha == pc.info["shift"] == 0.0
+        assert pc.info["colours"] == cp.max() + 1 and pc.info["levels"] <= pc.info["colours"]
+        interior = ~otr.bnd[order]
+        assert np.array_equal(order[interior], otr.J[perm])           # integer work: bit-exact
+        rows = np.nonzero(interior)[0]
+        Lgi = Lg[rows][:, rows].tocsr()
+        Lgi.sort_indices()
+        Lo = Lo.tocsr()
+        Lo.sort_indices()
+        assert np.array_equal(Lgi.indptr, Lo.indptr) and np.array_equal(Lgi.indices, Lo.indices)
+        assert np.max(np.abs(Lgi.data - Lo.data)) < 1e-12 * np.max(np.abs(Lo.data))
+        print(name, pc.info, flush=True)
 
 
 def test_c1_fp32_refinement_reaches_fp64_accuracy(gctx, c1_setup):

@@ -237,3 +237,50 @@ def test_filon_richardson_within_its_error_model(s):
     F = fw.filon_richardson(s, 2, 3, 2 ** 12)
     for p in (0, 1, 3):
         assert abs(F[0, p] - _t2d_hypergeometric(s, p)) < 50 * 4096.0 ** (-2 - 2 * s)
+
+
+# ---------------------------------------------------------------- multicolour IC(1)
+
+
+def test_multicolour_ic1_on_the_c1_mesh(c1):
+    m, g = c1["mesh"], c1["grid"]
+    tr = transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
+    T = fw.filon_richardson(0.5, 2, 2 * g.N, 1024)
+    A = precond.Ah_pattern(tr, T, 9)
+    L, perm, cp, alpha = precond.ic1_multicolour(A)
+    assert alpha == 0.0
+    n = A.shape[0]
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    # a proper colouring of A's graph, colours in non-decreasing order along the factor
+    Ac = A.tocoo()
+    colour = np.empty(n, dtype=int)
+    colour[perm] = cp
+    off = Ac.row != Ac.col
+    assert np.all(colour[Ac.row[off]] != colour[Ac.col[off]])
+    assert np.all(np.diff(cp) >= 0)
+    # greedy: every vertex of colour c > 0 has a lower-numbered neighbour of each colour below c
+    Acsr = A.tocsr()
+    for v in range(n):
+        nb = Acsr.indices[Acsr.indptr[v]:Acsr.indptr[v + 1]]
+        lower = {int(colour[j]) for j in nb if j < v}
+        assert set(range(colour[v])) <= lower
+    # no factor entry joins two vertices of one colour, so the levels are at most the colours
+    Lc = L.tocoo()
+    offl = Lc.row != Lc.col
+    assert np.all(cp[Lc.row[offl]] != cp[Lc.col[offl]])
+    assert precond.dependency_levels(L) <= cp.max() + 1 < 20
+    # (L L^T)_ij = (P A P^T)_ij on the kept pattern, which contains the lower pattern of P A P^T
+    Ap = A.tocsr()[perm][:, perm].toarray()
+    M = (L @ L.T).toarray()
+    assert np.max(np.abs(M[Lc.row, Lc.col] - Ap[Lc.row, Lc.col])) < 1e-12 * np.abs(Ap).max()
+    lowA = np.argwhere(np.tril(Ap) != 0)
+    Lmask = L.toarray() != 0
+    assert np.all(Lmask[lowA[:, 0], lowA[:, 1]])
+    # as a preconditioner of eq. GoFD-2 it leaves the solution unchanged and cuts iterations
+    K = operator.dense_K(tr, T)
+    b = operator.rhs_grid(tr, 0.5, np.ones((g.W, g.W)))
+    x = solve.solve_dense(K, b)
+    xm, itm, _ = solve.pcg(lambda v: K @ v, b, tol=1e-13, precond=lambda r: precond.apply_ic_ordered(L, perm, r))
+    _, it0, _ = solve.pcg(lambda v: K @ v, b, tol=1e-13)
+    assert np.max(np.abs(xm - x)) < 1e-11 * np.max(np.abs(x))
+    assert itm < it0
