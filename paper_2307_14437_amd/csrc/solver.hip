@@ -556,24 +556,32 @@ __global__ __launch_bounds__(1024) void k_trsv_levels(const int* __restrict__ pt
 // grid (blockIdx.x) and one right-hand side per blockIdx.y: used when the
 // factor has few levels (multicolour order), one launch per level, so that
 // no workgroup waits on another.
+// TRSV_LANES lanes share a row: each takes every TRSV_LANES-th entry, so the
+// row's loads are in flight together, and a fixed butterfly adds the lanes'
+// sums (the same order every time).
+constexpr int TRSV_LANES = 16;
 template <bool LOWER>
-__global__ void k_trsv_level(const int* __restrict__ ptr, const int* __restrict__ col,
-                             const double* __restrict__ val, const int* __restrict__ rows, int r0, int r1,
-                             const double* __restrict__ rhs_in, double* __restrict__ out, long long stride,
-                             const Scal* __restrict__ sc) {
+__global__ __launch_bounds__(256) void k_trsv_level(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                    const double* __restrict__ val, const int* __restrict__ rows,
+                                                    int r0, int r1, const double* __restrict__ rhs_in,
+                                                    double* __restrict__ out, long long stride,
+                                                    const Scal* __restrict__ sc) {
   const int k = blockIdx.y;
   if (sc && sc[k].done) return;
-  const int t = r0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (t >= r1) return;
+  const int lane = threadIdx.x % TRSV_LANES;
+  const int t = r0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) / TRSV_LANES);
+  const bool ok = t < r1;
   const double* b = rhs_in + k * stride;
   double* y = out + k * stride;
-  const int row = rows[t];
+  const int row = rows[ok ? t : r0];
   const int e0 = ptr[row], e1 = ptr[row + 1];
   const int dpos = LOWER ? e1 - 1 : e0;
   const int lo = LOWER ? e0 : e0 + 1, hi = LOWER ? e1 - 1 : e1;
   double s = 0.0;
-  for (int i = lo; i < hi; ++i) s += val[i] * y[col[i]];
-  y[row] = (b[row] - s) / val[dpos];
+  for (int i = lo + lane; i < hi; i += TRSV_LANES) s += val[i] * y[col[i]];
+#pragma unroll
+  for (int o = TRSV_LANES / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, TRSV_LANES);
+  if (ok && lane == 0) y[row] = (b[row] - s) / val[dpos];
 }
 
 // out[i] = in[perm[i]] (to = true) or out[perm[i]] = in[i], per right-hand side blockIdx.y
@@ -588,17 +596,18 @@ __global__ void k_permute(const double* __restrict__ in, const int* __restrict__
   else out[k * stride + perm[i]] = in[k * stride + i];
 }
 
-// gamma = (r, u) per right-hand side (one block each), written as partial 0 of nbu, the others zero
-__global__ __launch_bounds__(1024) void k_dot_rhs(const double* __restrict__ r, const double* __restrict__ u,
-                                                  long long n, long long stride, const Scal* __restrict__ sc,
-                                                  double* __restrict__ partG, int nbu) {
-  __shared__ double sh[1024 / 64];
-  const int k = blockIdx.x;
+// gamma = (r, u): nbu partials per right-hand side (blockIdx.y), block b over a grid-stride slice
+__global__ __launch_bounds__(BS) void k_dot_rhs(const double* __restrict__ r, const double* __restrict__ u,
+                                                long long n, long long stride, const Scal* __restrict__ sc,
+                                                double* __restrict__ partG, int nbu) {
+  __shared__ double sh[gofd_cg::block_sum_lds<BS, 1>()];
+  const int k = blockIdx.y;
   if (sc && sc[k].done) return;
-  double s = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 1024) s += r[k * stride + i] * u[k * stride + i];
-  block_sum_n<1024, 1>(&s, sh);
-  for (int i = threadIdx.x; i < nbu; i += 1024) partG[(long long)k * nbu + i] = (i == 0) ? s : 0.0;
+  double s[1] = {0.0};
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < n; i += (long long)nbu * BS)
+    s[0] += r[k * stride + i] * u[k * stride + i];
+  block_sum_n<BS, 1>(s, sh);
+  if (threadIdx.x == 0) partG[(long long)k * nbu + blockIdx.x] = s[0];
 }
 
 __global__ void k_fill_d(double* __restrict__ p, long long n, double v) {
@@ -1115,13 +1124,13 @@ int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, doub
       }
       for (int l = 0; l < pc->Lnlev; ++l) {
         const int r0 = pc->hLlp[l], r1 = pc->hLlp[l + 1];
-        hipLaunchKernelGGL(k_trsv_level<true>, dim3(grid1(r1 - r0, 256), P.nrhs), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_trsv_level<true>, dim3(grid1((long long)(r1 - r0) * TRSV_LANES, 256), P.nrhs), dim3(256), 0, st,
                            pc->Lptr.as<int>(), pc->Lcol.as<int>(), pc->Lval.as<double>(), pc->Llev_rows.as<int>(), r0,
                            r1, rin, w.dvec.as<double>() + o, n, scq);
       }
       for (int l = 0; l < pc->Unlev; ++l) {
         const int r0 = pc->hUlp[l], r1 = pc->hUlp[l + 1];
-        hipLaunchKernelGGL(k_trsv_level<false>, dim3(grid1(r1 - r0, 256), P.nrhs), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_trsv_level<false>, dim3(grid1((long long)(r1 - r0) * TRSV_LANES, 256), P.nrhs), dim3(256), 0, st,
                            pc->Uptr.as<int>(), pc->Ucol.as<int>(), pc->Uval.as<double>(), pc->Ulev_rows.as<int>(), r0,
                            r1, w.dvec.as<double>() + o, uout, n, scq);
       }
@@ -1129,8 +1138,8 @@ int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, doub
         hipLaunchKernelGGL(k_permute<false>, gp, dim3(256), 0, st, uout, pc->perm.as<int>(), n, n, scq,
                            w.u.as<double>() + o);
       if (partG)
-        hipLaunchKernelGGL(k_dot_rhs, dim3(P.nrhs), dim3(1024), 0, st, w.r.as<double>() + o, w.u.as<double>() + o, n,
-                           n, scq, partG + (long long)i0 * w.nbs, w.nbs);
+        hipLaunchKernelGGL(k_dot_rhs, dim3(w.nbs, P.nrhs), dim3(BS), 0, st, w.r.as<double>() + o,
+                           w.u.as<double>() + o, n, n, scq, partG + (long long)i0 * w.nbs, w.nbs);
       continue;
     }
     hipLaunchKernelGGL((k_trsv_levels<true>), dim3(P.nrhs), dim3(1024), 0, st, pc->Lptr.as<int>(),
