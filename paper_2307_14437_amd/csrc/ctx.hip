@@ -24,12 +24,43 @@ int dev_reserve(gofd_ctx_s* ctx, DevBuf& b, size_t bytes) {
 }
 
 gofd_ctx_s::~gofd_ctx_s() {
-  for (auto& kv : twiddles) delete kv.second;
+  for (gofd_ctx_s* c : children) delete c;
+  if (!borrowed_twiddles)
+    for (auto& kv : twiddles) delete kv.second;
   if (host_state) (void)hipHostFree(host_state);
   if (solver_ws && solver_ws_free) solver_ws_free(solver_ws);
   if (ev_in) (void)hipEventDestroy(ev_in);
   if (ev_out) (void)hipEventDestroy(ev_out);
   if (work) (void)hipStreamDestroy(work);
+  if (owns_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+gofd_ctx_s* ctx_child(gofd_ctx_s* parent, size_t index) {
+  while (parent->children.size() <= index) {
+    auto* c = new (std::nothrow) gofd_ctx_s();
+    if (!c) return nullptr;
+    c->device = parent->device;
+    c->num_cu = parent->num_cu;
+    c->twiddles = parent->twiddles;
+    c->borrowed_twiddles = true;
+    c->col_sched = parent->col_sched;
+    c->owns_stream = true;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        dev_reserve(c, c->scratch, 1 << 20) != GOFD_OK || dev_reserve(c, c->flag, 256) != GOFD_OK ||
+        hipMemset(c->flag.p, 0, 256) != hipSuccess || hipMemset(c->scratch.p, 0, 1 << 20) != hipSuccess) {
+      delete c;
+      return nullptr;
+    }
+    parent->children.push_back(c);
+  }
+  gofd_ctx_s* c = parent->children[index];
+  // tables and schedules made or tuned on the parent since the child was created
+  c->twiddles = parent->twiddles;
+  c->col_sched = parent->col_sched;
+  return c;
 }
 
 WorkStream::WorkStream(gofd_ctx_s* c) : ctx(c), saved(c->stream) {

@@ -95,8 +95,19 @@ struct gofd_ctx_s {
   // buffers, so that they allocate nothing
   void* ws_G = nullptr;
   void* ws_Z = nullptr;
+  // Child contexts of a batched solve whose problems have several grid
+  // shapes: one per shape group, each with its own streams, solver
+  // workspace and page-locked state, so the groups run concurrently from
+  // host threads.  A child borrows the parent's twiddle tables and column
+  // schedules; children are kept for later calls and freed with the parent.
+  std::vector<gofd_ctx_s*> children;
+  bool borrowed_twiddles = false;
+  bool owns_stream = false;          // a child's stream (created with it)
   ~gofd_ctx_s();
 };
+
+// A child context for concurrent work on the parent's device (see children).
+gofd_ctx_s* ctx_child(gofd_ctx_s* parent, size_t index);
 
 // Launch on a stream; if the context holds a pending pair of timing events,
 // the launch records them at the kernel's start and end (AMD extended launch).

@@ -31,6 +31,8 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <thread>
+#include <vector>
 
 #include "bary.h"
 #include "internal.h"
@@ -1868,6 +1870,33 @@ extern "C" int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_pre
 
 // Problems are grouped by grid shape (d, W, L); each group is one batch whose
 // CG iterations advance together, every stage one launch for the group.
+// One shape group of a batched call: its problems' items advance together.
+// Fills inf (one entry per item of the group, problem order) and returns the
+// solve's status.
+static int solve_group(gofd_ctx_s* ctx, const std::vector<int>& members, const gofd_transfer* trs,
+                       const gofd_fdop* ops, const gofd_precond* pcs, const int* nrhs, const double* const* f,
+                       int f_loc, double tol, const gofd_solve_opts* opts, double* const* u,
+                       std::vector<gofd_solve_info>& inf) {
+  std::vector<Problem> probs;
+  for (int q : members) probs.push_back(Problem{trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q]});
+  Batch B;
+  GOFD_TRY(batch_init(ctx, B, probs));
+  Work& w = ctx_work(ctx);
+  GOFD_TRY(reserve_work(ctx, w, B));
+  std::vector<double*> outs;
+  for (size_t j = 0; j < members.size(); ++j) {
+    GOFD_TRY(form_rhs(ctx, B.probs[j], f[members[j]], f_loc, w.b.as<double>() + B.poff[j]));
+    outs.push_back(u[members[j]]);
+  }
+  inf.assign(B.nitems, gofd_solve_info{});
+  return solve_system(ctx, B, w, tol, opts, outs.data(), inf.data());
+}
+
+// Problems are grouped by grid shape (d, W, L); each group is one batch whose
+// CG iterations advance together, every stage one launch for the group.
+// Several groups run concurrently, each from a host thread on a child context
+// (own streams and workspaces), ordered after the caller's stream on entry
+// and before it on exit.
 extern "C" int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* trs, const gofd_fdop* ops,
                                   const gofd_precond* pcs, const int* nrhs, const double* const* f, int f_loc,
                                   double tol, const gofd_solve_opts* opts, double* const* u, gofd_solve_info* info) {
@@ -1880,35 +1909,61 @@ extern "C" int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* 
     if (!f[q] || !u[q]) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
     item0[q + 1] = item0[q] + nrhs[q];
   }
-  WorkStream ws(ctx);
-  std::vector<char> done(nprob, 0);
-  int worst = GOFD_OK;
-  for (int q0 = 0; q0 < nprob; ++q0) {
-    if (done[q0]) continue;
-    std::vector<int> members;
-    for (int q = q0; q < nprob; ++q)
-      if (!done[q] && ops[q]->d == ops[q0]->d && ops[q]->W == ops[q0]->W && ops[q]->L == ops[q0]->L) {
-        members.push_back(q);
-        done[q] = 1;
-      }
-    std::vector<Problem> probs;
-    for (int q : members) probs.push_back(Problem{trs[q], ops[q], pcs ? pcs[q] : nullptr, nrhs[q]});
-    Batch B;
-    GOFD_TRY(batch_init(ctx, B, probs));
-    Work& w = ctx_work(ctx);
-    GOFD_TRY(reserve_work(ctx, w, B));
-    std::vector<double*> outs;
-    for (size_t j = 0; j < members.size(); ++j) {
-      GOFD_TRY(form_rhs(ctx, B.probs[j], f[members[j]], f_loc, w.b.as<double>() + B.poff[j]));
-      outs.push_back(u[members[j]]);
+  std::vector<std::vector<int>> groups;
+  {
+    std::vector<char> done(nprob, 0);
+    for (int q0 = 0; q0 < nprob; ++q0) {
+      if (done[q0]) continue;
+      std::vector<int> members;
+      for (int q = q0; q < nprob; ++q)
+        if (!done[q] && ops[q]->d == ops[q0]->d && ops[q]->W == ops[q0]->W && ops[q]->L == ops[q0]->L) {
+          members.push_back(q);
+          done[q] = 1;
+        }
+      groups.push_back(members);
     }
-    std::vector<gofd_solve_info> inf(B.nitems);
-    const int rc = solve_system(ctx, B, w, tol, opts, outs.data(), inf.data());
-    if (rc != GOFD_OK && rc != GOFD_E_NOT_CONVERGED && rc != GOFD_E_BREAKDOWN) return rc;
-    if (rc != GOFD_OK && worst == GOFD_OK) worst = rc;
-    if (info)
-      for (size_t j = 0; j < members.size(); ++j)
-        for (int k = 0; k < nrhs[members[j]]; ++k) info[item0[members[j]] + k] = inf[B.pitem[j] + k];
+  }
+  const size_t ng = groups.size();
+  std::vector<std::vector<gofd_solve_info>> infs(ng);
+  std::vector<int> rcs(ng, GOFD_OK);
+  WorkStream ws(ctx);
+  // host-side outputs of stage timing and residual history are single arrays: groups one after another then
+  const bool concurrent = ng > 1 && !(opts && (opts->stage_ms || opts->history));
+  if (!concurrent) {
+    for (size_t g = 0; g < ng; ++g) {
+      rcs[g] = solve_group(ctx, groups[g], trs, ops, pcs, nrhs, f, f_loc, tol, opts, u, infs[g]);
+      if (rcs[g] != GOFD_OK && rcs[g] != GOFD_E_NOT_CONVERGED && rcs[g] != GOFD_E_BREAKDOWN) return rcs[g];
+    }
+  } else {
+    std::vector<gofd_ctx_s*> kids(ng);
+    for (size_t g = 0; g < ng; ++g)
+      if (!(kids[g] = ctx_child(ctx, g))) return gofd_fail(ctx, GOFD_E_HIP, "could not create a stream context");
+    hipEvent_t start;
+    HIP_TRY(ctx, hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    HIP_TRY(ctx, hipEventRecord(start, ctx->stream));
+    for (size_t g = 0; g < ng; ++g) HIP_TRY(ctx, hipStreamWaitEvent(kids[g]->stream, start, 0));
+    std::vector<std::thread> th;
+    for (size_t g = 0; g < ng; ++g)
+      th.emplace_back([&, g]() {
+        (void)hipSetDevice(ctx->device);
+        WorkStream wsg(kids[g]);
+        rcs[g] = solve_group(kids[g], groups[g], trs, ops, pcs, nrhs, f, f_loc, tol, opts, u, infs[g]);
+      });
+    for (auto& t : th) t.join();
+    // the caller's work continues once every group has finished
+    for (size_t g = 0; g < ng; ++g) HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, kids[g]->ev_out, 0));
+    (void)hipEventDestroy(start);
+    for (size_t g = 0; g < ng; ++g)
+      if (rcs[g] != GOFD_OK && rcs[g] != GOFD_E_NOT_CONVERGED && rcs[g] != GOFD_E_BREAKDOWN)
+        return gofd_fail(ctx, rcs[g], kids[g]->last_error);
+  }
+  int worst = GOFD_OK;
+  for (size_t g = 0; g < ng; ++g) {
+    if (rcs[g] != GOFD_OK && worst == GOFD_OK) worst = rcs[g];
+    if (!info) continue;
+    int it = 0;
+    for (int q : groups[g])
+      for (int k = 0; k < nrhs[q]; ++k) info[item0[q] + k] = infs[g][it++];
   }
   if (worst != GOFD_OK) return gofd_fail(ctx, worst, "solve did not reach the tolerance for every right-hand side");
   return GOFD_OK;

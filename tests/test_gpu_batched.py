@@ -109,3 +109,59 @@ def test_batched_direct_launches_match_graph_replay(gctx):
         assert [i["iterations"] for i in infos] == [i["iterations"] for i in iref], (ug, ce)
         for a, b in zip(us, ref):
             assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), (ug, ce)
+
+
+def test_shape_groups_run_concurrently_with_the_same_results(gctx):
+    """Problems of different grid shapes form groups that run concurrently (a host thread and streams
+    each); every item's FP64 iterates are those of the groups solved one after another (stage timing
+    forces that path)."""
+    import paper_2307_14437_amd as gofd
+    P = _problems(gctx)
+    args = ([p["tr"] for p in P], [p["op"] for p in P], [p["pc"] for p in P], [_dev(p["f"]) for p in P])
+    conc, ic = gofd.solve_batched(gctx, *args, tol=1e-12)
+    seq, iseq = gofd.solve_batched(gctx, *args, tol=1e-12, stage_ms=np.zeros(len(gofd.STAGES)))
+    assert [i["iterations"] for i in ic] == [i["iterations"] for i in iseq]
+    for a, b in zip(conc, seq):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_c4_members_of_three_grid_sizes_match_the_oracle(gctx):
+    """Members of the 64-mesh star workload with 128^2, 256^2 and 512^2 grids, 16 Fourier right-hand sides
+    each, solved in one batched FP32-grid call (three concurrent shape groups) to 1e-11; items checked
+    against the oracle's FFT-product CG solution (same T level on both sides: M = 2048, raised to
+    4096 for the 512^2 grid)."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    from workloads.configs import c4_plan, c4_problem
+    plan = c4_plan()
+    picks = []
+    for n in (128, 256, 512):
+        cand = [m for m in plan if 2 * m["grid"].N == n]
+        picks.append(min(cand, key=lambda m: m["nv"]))
+    probs = [c4_problem(m) for m in picks]
+    trs, ops, fs = [], [], []
+    for pr in probs:
+        g = pr["grid"]
+        print(f"c4 member: nv={pr['mesh'].nv} grid {2 * g.N} s={pr['s']:.3f}", flush=True)
+        trs.append(gofd.Transfer(gctx, _dev(pr["mesh"].X), _dev(pr["mesh"].elems, torch.int32), g))
+        ops.append(gofd.FdOp(gctx, pr["s"], g, M=2048))
+        fs.append(_dev(np.stack(pr["f"])))
+    us, infos = gofd.solve_batched(gctx, trs, ops, [None] * 3, fs, tol=1e-11, mode=gofd.MODE_FP32_RELIABLE,
+                                   inner_tol=0.1)
+    assert all(i["status"] == 0 and i["rel_residual"] <= 1e-11 for i in infos)
+    for q, pr in enumerate(probs):
+        m, g, s = pr["mesh"], pr["grid"], pr["s"]
+        otr = transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
+        M = 2048
+        while M // 2 < 2 * (2 * g.N) + 1:          # the level both sides raise M to
+            M *= 2
+        T = fw.filon_richardson(s, 2, 2 * g.N, M)
+        u = us[q].cpu().numpy().reshape(16, -1)
+        for r in ((0, 15) if q == 0 else (q * 7,)):
+            b = operator.rhs_grid(otr, s, pr["f"][r])
+            uJ, it, _ = osolve.pcg(lambda v: operator.apply_K(otr, T, v, "fft"), b, tol=1e-13, maxiter=5000)
+            uref = np.zeros(m.nv)
+            uref[otr.J] = uJ
+            err = np.linalg.norm(u[r] - uref) / np.linalg.norm(uref)
+            print(f"  rhs {r}: oracle iterations {it}, rel error {err:.2e}", flush=True)
+            assert err <= 1e-8
