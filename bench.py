@@ -289,13 +289,15 @@ def main():
     sched = {}
     for fp32 in (True, False):
         if args.col_schedule >= 0:
-            sc, times = args.col_schedule, []
-            gofd.set_schedule(ctx, g, sc, fp32=fp32)
+            r = {"col": args.col_schedule, "row": 0, "times": None}
+            gofd.set_schedule(ctx, g, args.col_schedule, fp32=fp32)
         else:
-            sc, times = gofd.autotune(ctx, g, fp32=fp32)
-        sched["fp32" if fp32 else "fp64"] = {"schedule": sc, "values_per_thread_slots_per_block":
-                                             list(gofd.COL_SCHEDULES[sc]),
-                                             "candidates_us": [round(x * 1e3, 2) for x in times]}
+            r = gofd.autotune_all(ctx, g, fp32=fp32)
+        us_ = [None if x is None else round(x * 1e3, 2) for x in (r["times"] or [])]
+        sched["fp32" if fp32 else "fp64"] = {"schedule": r["col"], "values_per_thread_slots_per_block":
+                                             list(gofd.COL_SCHEDULES[r["col"]]), "candidates_us": us_[:4],
+                                             "row_pass_values_per_thread": r["row"] or 8,
+                                             "row_pass_candidates_us_8_16": us_[4:6]}
     _sync(); setup["autotune_ms"] = (time.perf_counter() - t) * 1e3
 
     def step(mode):

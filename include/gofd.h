@@ -228,24 +228,33 @@ enum { GOFD_NOALLOC_WS_BYTES = 64 << 20 };
 int gofd_apply_Ah_noalloc(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int nrhs, const double* u_dev,
                           double* y_dev, int flags);
 
-/* Column-pass schedules (2D): the pass that transforms the spectrum columns,
- * multiplies by the kernel's spectrum and transforms back (eq. AU-1) has
- * GOFD_N_COL_SCHED schedules (values per thread and column slots per block:
- * 0 = 16/2, the built-in default, 1 = 16/1, 2 = 8/2, 3 = 16/4).  The schedule
- * for a (period L, precision) pair is a property of the context and applies
- * to every later product of that shape; results agree between schedules to
- * rounding.
- * gofd_autotune times every schedule of the given grid's period on the device
- * (a zero field of the grid's window, 20 launches each after 3 untimed ones,
- * GOFD_FP32_GRID in flags selecting the precision), installs the fastest
- * (the default unless another is at least 5 % faster) and returns its number
- * in *sched (host, nullable) and the average durations in ms in
- * times[GOFD_N_COL_SCHED] (host, nullable).  Synchronises.
+/* Schedules of the FFT passes, properties of the context that apply to every
+ * later product of the same (FFT period L, precision); results agree between
+ * schedules to rounding.
+ *  - 2D column pass (transform the spectrum columns, multiply by the kernel's
+ *    spectrum, transform back; eq. AU-1): GOFD_N_COL_SCHED schedules (values
+ *    per thread and column slots per block: 0 = 16/2, the built-in default,
+ *    1 = 16/1, 2 = 8/2, 3 = 16/4).
+ *  - 2D first row pass of the products from a grid field (apply calls, FP64
+ *    CG, residual replacements): 8 or 16 values per thread where both are
+ *    built (L >= 1024; 0 = the default, 8).  The FP32 CG's row pass, which
+ *    gathers through the row-pair slots, keeps 16.
+ *  - 3D y/z/y passes: schedule 0 (four column slots per block where they fit,
+ *    the default) or 1 (two).
+ * gofd_autotune times the schedules for the given grid's period on the device
+ * (zero fields of the grid's window, each timed over repeated launches after
+ * untimed ones; GOFD_FP32_GRID in flags selects the precision), installs the
+ * fastest (the default unless another is at least 5 % faster) and reports:
+ * sched (host, nullable) receives 2 ints, the column schedule (3D: the y/z/y
+ * schedule) and the row pass's values per thread (0 if not tuned);
+ * times (host, nullable) receives GOFD_N_TUNE_TIMES average durations in ms:
+ * 2D: times[0..3] the column schedules, times[4..5] the row pass at 8 and 16;
+ * 3D: times[0..1]; entries not timed are +inf.  Synchronises.
  * gofd_set_schedule installs a known schedule (e.g. from a cache of earlier
- * tuning runs).  Errors: GOFD_E_ARG (bad grid or schedule number),
- * GOFD_E_UNSUPPORTED (d = 3: the 3D passes have one schedule per length),
- * GOFD_E_OOM, GOFD_E_HIP. */
-enum { GOFD_N_COL_SCHED = 4 };
+ * tuning runs): the column schedule, or with GOFD_SCHED_ROWS in flags the row
+ * pass's values per thread (0, 8, 16), or in 3D the y/z/y schedule (0, 1).
+ * Errors: GOFD_E_ARG (bad grid or schedule number), GOFD_E_OOM, GOFD_E_HIP. */
+enum { GOFD_N_COL_SCHED = 4, GOFD_N_TUNE_TIMES = 6, GOFD_SCHED_ROWS = 256 };
 int gofd_autotune(gofd_ctx ctx, const gofd_grid* grid, int flags, int* sched, double* times);
 int gofd_set_schedule(gofd_ctx ctx, const gofd_grid* grid, int flags, int sched);
 

@@ -500,55 +500,83 @@ def _cache_key(arch: str, grid, fp32: bool) -> str:
     return f"{arch}/d{grid.d}/L{fft_period(grid.N)}/{'fp32' if fp32 else 'fp64'}"
 
 
-def cache_lookup(path, key):
-    """Schedule stored under key in the JSON tuning cache at path, or None."""
+def cache_lookup(path, key, full=False):
+    """Schedule stored under key in the JSON tuning cache at path (the whole entry with full=True), or None."""
     import json
     if not path or not os.path.exists(path):
         return None
     with open(path) as fh:
         entry = json.load(fh).get(key)
-    return None if entry is None else int(entry["schedule"])
+    if entry is None:
+        return None
+    return entry if full else int(entry["schedule"])
 
 
-def cache_store(path, key, sched, times):
+def cache_store(path, key, sched, times, row=0):
     """Record a tuning result under key in the JSON cache at path (other keys are kept)."""
     import json
     data = {}
     if os.path.exists(path):
         with open(path) as fh:
             data = json.load(fh)
-    data[key] = {"schedule": int(sched), "ms": [float(t) for t in times]}
+    data[key] = {"schedule": int(sched), "row": int(row), "ms": [None if t is None else float(t) for t in times]}
     tmp = path + ".tmp"
     with open(tmp, "w") as fh:
         json.dump(data, fh, indent=1, sort_keys=True)
     os.replace(tmp, path)
 
 
-def autotune(ctx: Context, grid, fp32=True, cache=None):
-    """Pick the column-pass schedule for the grid's FFT length and precision (2D): from the JSON cache
-    when it holds this device architecture, length and precision, else by timing every schedule on the
-    device (the result is then stored in the cache).  Returns (schedule, times in ms or None)."""
+N_TUNE_TIMES = 6
+SCHED_ROWS = 256
+
+
+def autotune_all(ctx: Context, grid, fp32=True, cache=None):
+    """Tune every schedulable pass for the grid's FFT length and precision: 2D the column pass and the first
+    row pass of the products, 3D the y/z/y passes.  From the JSON cache when it holds this device
+    architecture, dimension, length and precision, else timed on the device (and stored in the cache).
+    Returns {"col": .., "row": .., "times": [...] or None} (2D) or {"yzy": .., "times": ...} (3D)."""
     import torch
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
     key = _cache_key(arch, grid, fp32)
     g = _grid(grid)
     flags = FP32_GRID if fp32 else 0
-    hit = cache_lookup(cache, key)
+    hit = cache_lookup(cache, key, full=True)
     if hit is not None:
-        ctx.check(lib.gofd_set_schedule(ctx.handle, ctypes.byref(g), flags, hit))
-        return hit, None
-    s = ctypes.c_int()
-    t = (ctypes.c_double * N_COL_SCHED)()
-    ctx.check(lib.gofd_autotune(ctx.handle, ctypes.byref(g), flags, ctypes.byref(s), t))
-    if cache:
-        cache_store(cache, key, s.value, list(t))
-    return s.value, list(t)
+        ctx.check(lib.gofd_set_schedule(ctx.handle, ctypes.byref(g), flags, int(hit["schedule"])))
+        if grid.d == 2 and hit.get("row"):
+            ctx.check(lib.gofd_set_schedule(ctx.handle, ctypes.byref(g), flags | SCHED_ROWS, int(hit["row"])))
+        out = {"times": None}
+    else:
+        sch = (ctypes.c_int * 2)()
+        t = (ctypes.c_double * N_TUNE_TIMES)()
+        ctx.check(lib.gofd_autotune(ctx.handle, ctypes.byref(g), flags, sch, t))
+        hit = {"schedule": sch[0], "row": sch[1]}
+        out = {"times": [x if x != float("inf") else None for x in t]}
+        if cache:
+            cache_store(cache, key, sch[0], out["times"], row=sch[1])
+    if grid.d == 3:
+        out["yzy"] = int(hit["schedule"])
+    else:
+        out["col"], out["row"] = int(hit["schedule"]), int(hit.get("row", 0))
+    return out
 
 
-def set_schedule(ctx: Context, grid, sched, fp32=True):
-    """Install a column-pass schedule (0..N_COL_SCHED-1) for the grid's FFT length and precision."""
+def autotune(ctx: Context, grid, fp32=True, cache=None):
+    """Tune the grid's passes (autotune_all) and return (column schedule, its candidate times in ms or None)
+    for 2D, (y/z/y schedule, times or None) for 3D."""
+    r = autotune_all(ctx, grid, fp32, cache)
+    t = r["times"]
+    if grid.d == 3:
+        return r["yzy"], (None if t is None else [x for x in t[:2] if x is not None])
+    return r["col"], (None if t is None else t[:N_COL_SCHED])
+
+
+def set_schedule(ctx: Context, grid, sched, fp32=True, rows=False):
+    """Install a schedule for the grid's FFT length and precision: 2D the column pass (0..N_COL_SCHED-1) or,
+    with rows=True, the first row pass's values per thread (0, 8, 16); 3D the y/z/y passes (0, 1)."""
     g = _grid(grid)
-    ctx.check(lib.gofd_set_schedule(ctx.handle, ctypes.byref(g), FP32_GRID if fp32 else 0, int(sched)))
+    flags = (FP32_GRID if fp32 else 0) | (SCHED_ROWS if rows else 0)
+    ctx.check(lib.gofd_set_schedule(ctx.handle, ctypes.byref(g), flags, int(sched)))
 
 
 def time_kernel(ctx: Context, tr: Transfer, op: FdOp, which, u, flags=0, reps=20):

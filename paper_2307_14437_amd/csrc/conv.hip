@@ -870,6 +870,21 @@ static int col_sched(const gofd_ctx_s* ctx, int L, bool fp32) {
   return it == ctx->col_sched.end() ? 0 : it->second;
 }
 
+// values per thread of the first row pass of the products (0: the default)
+static int row_sched(const gofd_ctx_s* ctx, int L, bool fp32) {
+  auto it = ctx->row_sched.find(std::make_pair(L, fp32));
+  return it == ctx->row_sched.end() ? 0 : it->second;
+}
+
+template <typename R, int L, int EP, class Src>
+void launch_passA(gofd_ctx_s* ctx, hipStream_t st, int nrhs, int pairs, const Src& src, cplx<R>* Z, int W,
+                  const cplx<R>* tw, long long zs, Skip skip) {
+  constexpr int TP = L / EP;
+  constexpr int LP = (TP >= 64) ? 1 : 64 / TP;
+  GOFD_LAUNCH(ctx, (k_passA<R, L, EP, LP, Src>), dim3((pairs + LP - 1) / LP, nrhs), dim3(LP * TP), 0, st, src, Z,
+              W, tw, zs, skip);
+}
+
 template <typename R, int L, class Src, typename Y>
 int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
            double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab,
@@ -896,13 +911,17 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   if (passes & 1) {
     // the gather through the slots does its FFT with 16 values per thread
     // when both row passes still hold one row pair per block (the slot
-    // capacity of a row pair is the same then)
-    constexpr bool WIDE = std::is_same<Src, SrcPairSegRows>::value && L / 16 >= 64 && C::TA >= 64;
-    constexpr int EP = WIDE ? 16 : C::E1;
-    constexpr int TP = L / EP;
-    constexpr int LP = (TP >= 64) ? 1 : 64 / TP;
-    GOFD_LAUNCH(ctx, (k_passA<R, L, EP, LP, Src>), dim3((pairs + LP - 1) / LP, nrhs), dim3(LP * TP), 0, st, src, Z,
-                W, tw, zs, skip);
+    // capacity of a row pair is the same then); the products from a grid
+    // field take 8 by default, or 16 where the tuner found that faster
+    constexpr bool SEG = std::is_same<Src, SrcPairSegRows>::value;
+    constexpr bool BOTH = L / 16 >= 64 && C::TA >= 64 && C::E1 == 8;   // 8 and 16 both one row pair per block
+    constexpr bool WIDE = SEG && BOTH;
+    const bool wide = WIDE || (BOTH && !SEG && row_sched(ctx, L, sizeof(R) == 4) == 16);
+    if (wide) {
+      if constexpr (BOTH) launch_passA<R, L, 16, Src>(ctx, st, nrhs, pairs, src, Z, W, tw, zs, skip);
+    } else if constexpr (!WIDE) {
+      launch_passA<R, L, C::E1, Src>(ctx, st, nrhs, pairs, src, Z, W, tw, zs, skip);
+    }
   }
   if (passes & 2) {
     switch (col_sched(ctx, L, sizeof(R) == 4)) {
@@ -1218,6 +1237,67 @@ static int tune_L(gofd_ctx_s* ctx, int W, double* times) {
   return best;
 }
 
+// First row pass of the products (a grid-field source): 8 against 16 values
+// per thread, where both hold one row pair per block (L >= 1024).  times[0]
+// for 8, times[1] for 16; returns the values per thread to use (0: only one
+// width exists for this length).
+template <typename R, int L>
+static int tune_rows_L(gofd_ctx_s* ctx, int W, double* times) {
+  using C = Cfg<R, L>;
+  constexpr bool BOTH = L / 16 >= 64 && C::TA >= 64 && C::E1 == 8;
+  if constexpr (!BOTH) {
+    return 0;
+  } else {
+    const long long zs = (long long)W * (L / 2), nn = (long long)W * W;
+    const cplx<R>* tw = sizeof(R) == 8 ? reinterpret_cast<const cplx<R>*>(twiddles64(ctx, L))
+                                       : reinterpret_cast<const cplx<R>*>(twiddles32(ctx, L));
+    if (!tw) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
+    DevBuf Z, F;
+    GOFD_TRY(dev_reserve(ctx, Z, sizeof(cplx<R>) * zs));
+    GOFD_TRY(dev_reserve(ctx, F, sizeof(R) * nn));
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, hipMemsetAsync(F.p, 0, sizeof(R) * nn, st));
+    const SrcPairGrid<R> src{F.as<R>(), nn};
+    const Skip skip{nullptr, 0};
+    const int pairs = (W + 1) / 2;
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    constexpr int reps = 20;
+    for (int v = 0; v < 2; ++v) {
+      auto run = [&]() {
+        if (v == 0) launch_passA<R, L, 8>(ctx, st, 1, pairs, src, Z.as<cplx<R>>(), W, tw, zs, skip);
+        else launch_passA<R, L, 16>(ctx, st, 1, pairs, src, Z.as<cplx<R>>(), W, tw, zs, skip);
+      };
+      for (int k = 0; k < 3; ++k) run();
+      (void)hipEventRecord(e0, st);
+      for (int k = 0; k < reps; ++k) run();
+      (void)hipEventRecord(e1, st);
+      float ms = 0.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return gofd_fail(ctx, GOFD_E_HIP, "timing the row pass failed");
+      }
+      times[v] = ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(ctx, hipGetLastError());
+    return times[1] < 0.95 * times[0] ? 16 : 8;   // 16 only when clearly faster than the default
+  }
+}
+
+template <typename R>
+static int tune_rows(gofd_ctx_s* ctx, int L, int W, double* times) {
+  switch (L) {
+    case 1024: return tune_rows_L<R, 1024>(ctx, W, times);
+    case 2048: return tune_rows_L<R, 2048>(ctx, W, times);
+    case 4096: return tune_rows_L<R, 4096>(ctx, W, times);
+    default: return 0;
+  }
+}
+
 template <typename R>
 static int tune_2d(gofd_ctx_s* ctx, int L, int W, double* times) {
   switch (L) {
@@ -1236,26 +1316,49 @@ static int tune_2d(gofd_ctx_s* ctx, int L, int W, double* times) {
 }
 
 extern "C" int gofd_autotune(gofd_ctx ctx, const gofd_grid* grid, int flags, int* sched, double* times) {
-  if (!ctx || !grid || grid->N < 1) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
-  if (grid->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "schedule tuning is 2D only");
+  if (!ctx || !grid || grid->N < 1 || (grid->d != 2 && grid->d != 3)) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
   const bool fp32 = flags & GOFD_FP32_GRID;
   const int L = conv_period(grid->N), W = 2 * grid->N + 1;
-  double t[GOFD_N_COL_SCHED];
+  double t[GOFD_N_TUNE_TIMES];
   for (double& x : t) x = HUGE_VAL;
-  const int best = fp32 ? tune_2d<float>(ctx, L, W, t) : tune_2d<double>(ctx, L, W, t);
-  if (best < 0) return best;
-  ctx->col_sched[std::make_pair(L, fp32)] = best;
-  if (sched) *sched = best;
+  int out[2] = {0, 0};
+  if (grid->d == 3) {
+    const int best = conv3_tune(ctx, grid, fp32, t);
+    if (best < 0) return best;
+    out[0] = best;
+  } else {
+    const int best = fp32 ? tune_2d<float>(ctx, L, W, t) : tune_2d<double>(ctx, L, W, t);
+    if (best < 0) return best;
+    ctx->col_sched[std::make_pair(L, fp32)] = best;
+    out[0] = best;
+    ctx->row_sched.erase(std::make_pair(L, fp32));
+    const int rows = fp32 ? tune_rows<float>(ctx, L, W, t + 4) : tune_rows<double>(ctx, L, W, t + 4);
+    if (rows < 0) return rows;
+    if (rows > 0) ctx->row_sched[std::make_pair(L, fp32)] = rows;
+    out[1] = rows;
+  }
+  if (sched) {
+    sched[0] = out[0];
+    sched[1] = out[1];
+  }
   if (times)
-    for (int s = 0; s < GOFD_N_COL_SCHED; ++s) times[s] = t[s];
+    for (int s = 0; s < GOFD_N_TUNE_TIMES; ++s) times[s] = t[s];
   return GOFD_OK;
 }
 
 extern "C" int gofd_set_schedule(gofd_ctx ctx, const gofd_grid* grid, int flags, int sched) {
-  if (!ctx || !grid || grid->N < 1 || sched < 0 || sched >= GOFD_N_COL_SCHED)
-    return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
-  if (grid->d != 2) return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "schedules are 2D only");
-  ctx->col_sched[std::make_pair(conv_period(grid->N), (flags & GOFD_FP32_GRID) != 0)] = sched;
+  if (!ctx || !grid || grid->N < 1 || (grid->d != 2 && grid->d != 3)) return gofd_fail(ctx, GOFD_E_ARG, "bad argument");
+  const auto key = std::make_pair(conv_period(grid->N), (flags & GOFD_FP32_GRID) != 0);
+  if (grid->d == 3) {
+    if (sched != 0 && sched != 1) return gofd_fail(ctx, GOFD_E_ARG, "3D schedules are 0 and 1");
+    ctx->sched3[key] = sched;
+  } else if (flags & GOFD_SCHED_ROWS) {
+    if (sched != 0 && sched != 8 && sched != 16) return gofd_fail(ctx, GOFD_E_ARG, "row pass: 0, 8 or 16 values");
+    ctx->row_sched[key] = sched;
+  } else {
+    if (sched < 0 || sched >= GOFD_N_COL_SCHED) return gofd_fail(ctx, GOFD_E_ARG, "bad column schedule");
+    ctx->col_sched[key] = sched;
+  }
   return GOFD_OK;
 }
 

@@ -297,22 +297,26 @@ __global__ __launch_bounds__(LINES*(L / E)) void k_p3E(const cplx<R>* __restrict
 
 // ---------------------------------------------------------------- launch
 
-template <typename R, int L>
+// ALT = 1 selects the alternative schedule of the y/z/y passes: two slots per
+// block where four are the default (more, smaller blocks)
+template <typename R, int L, int ALT = 0>
 struct Cfg3 {
   static constexpr int E = (L >= 16) ? 16 : L;
   static constexpr int TPL = L / E;
   static constexpr int LINES = (TPL >= 64) ? 1 : 64 / TPL;          // row pairs per block (A, E)
   static constexpr int LINE_BYTES = padded_len<L, E>() * (int)sizeof(cplx<R>);
-  static constexpr int LB = (4 * TPL <= 1024 && 4 * LINE_BYTES <= 150 * 1024) ? 4 : 2;   // slots per block (B-D)
+  static constexpr int LB_DEF = (4 * TPL <= 1024 && 4 * LINE_BYTES <= 150 * 1024) ? 4 : 2;
+  static constexpr bool HAS_ALT = LB_DEF == 4;
+  static constexpr int LB = (ALT && HAS_ALT) ? 2 : LB_DEF;           // slots per block (B-D)
   static constexpr int NSLOT = L / 2 + 1;
   static constexpr int NTILE = (NSLOT + 3) / 4;
   static constexpr int NSB = NTILE * (4 / LB);                       // slot blocks per line set
 };
 
-template <typename R, int L, class Src, typename Y>
+template <typename R, int L, int ALT, class Src, typename Y>
 int run_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip, double* dpart,
            const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab) {
-  using C = Cfg3<R, L>;
+  using C = Cfg3<R, L, ALT>;
   const int W = op->W, half = op->half;
   const long long z1s = (long long)C::NTILE * 4 * W * W;
   const long long z2s = (long long)C::NTILE * 4 * W * L;
@@ -356,25 +360,41 @@ int run_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
   return GOFD_OK;
 }
 
+// schedule of the 3D y/z/y passes in force for (L, precision): 0 or 1 (ALT)
+int sched3_of(const gofd_ctx_s* ctx, int L, bool fp32) {
+  auto it = ctx->sched3.find(std::make_pair(L, fp32));
+  return it == ctx->sched3.end() ? 0 : it->second;
+}
+
+template <typename R, int L, class Src, typename Y>
+int run_3d_s(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
+             double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab) {
+  if (Cfg3<R, L>::HAS_ALT && sched3_of(op->ctx, L, sizeof(R) == 4) == 1)
+    return run_3d<R, L, 1>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+  return run_3d<R, L, 0>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+}
+
 template <typename R, class Src, typename Y>
 int dispatch_3d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int passes, Skip skip,
                 double* dpart, const gofd_cg::Level1& lv1, const gofd_cg::Finish& fin, const void* const* that_tab) {
   switch (op->L) {
-    case 8: return run_3d<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 16: return run_3d<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 32: return run_3d<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 64: return run_3d<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 128: return run_3d<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 256: return run_3d<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 512: return run_3d<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
-    case 1024: return run_3d<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 8: return run_3d_s<R, 8>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 16: return run_3d_s<R, 16>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 32: return run_3d_s<R, 32>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 64: return run_3d_s<R, 64>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 128: return run_3d_s<R, 128>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 256: return run_3d_s<R, 256>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 512: return run_3d_s<R, 512>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
+    case 1024: return run_3d_s<R, 1024>(ctx, op, nrhs, src, y, passes, skip, dpart, lv1, fin, that_tab);
     default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "3D FFT length " + std::to_string(op->L) + " not built");
   }
 }
 
 template <int L>
-constexpr int p3c_blocks(bool fp32) {
-  return fp32 ? Cfg3<float, L>::NSB * L : Cfg3<double, L>::NSB * L;
+int p3c_blocks(const gofd_ctx_s* ctx, bool fp32) {
+  const bool alt = sched3_of(ctx, L, fp32) == 1;
+  if (fp32) return (alt ? Cfg3<float, L, 1>::NSB : Cfg3<float, L>::NSB) * L;
+  return (alt ? Cfg3<double, L, 1>::NSB : Cfg3<double, L>::NSB) * L;
 }
 
 }  // namespace
@@ -386,14 +406,14 @@ long long conv3_workspace(const gofd_fdop_s* op) {
 
 int conv3_passC_blocks(const gofd_fdop_s* op, bool fp32) {
   switch (op->L) {
-    case 8: return p3c_blocks<8>(fp32);
-    case 16: return p3c_blocks<16>(fp32);
-    case 32: return p3c_blocks<32>(fp32);
-    case 64: return p3c_blocks<64>(fp32);
-    case 128: return p3c_blocks<128>(fp32);
-    case 256: return p3c_blocks<256>(fp32);
-    case 512: return p3c_blocks<512>(fp32);
-    case 1024: return p3c_blocks<1024>(fp32);
+    case 8: return p3c_blocks<8>(op->ctx, fp32);
+    case 16: return p3c_blocks<16>(op->ctx, fp32);
+    case 32: return p3c_blocks<32>(op->ctx, fp32);
+    case 64: return p3c_blocks<64>(op->ctx, fp32);
+    case 128: return p3c_blocks<128>(op->ctx, fp32);
+    case 256: return p3c_blocks<256>(op->ctx, fp32);
+    case 512: return p3c_blocks<512>(op->ctx, fp32);
+    case 1024: return p3c_blocks<1024>(op->ctx, fp32);
     default: return 1;
   }
 }
@@ -414,3 +434,84 @@ int conv3_run(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v64, con
   SrcGrid<double> src{v64, nn};
   return dispatch_3d<double>(ctx, op, nrhs, src, static_cast<double*>(y), passes, skip, dpart, lv1, fin, that_tab);
 }
+
+// ---------------------------------------------------------------- schedule tuning (3D)
+
+namespace {
+
+template <typename R, int L, int ALT>
+double time_yzy(gofd_ctx_s* ctx, gofd_fdop_s* op, double* dpart) {
+  const long long nn = (long long)op->W * op->W * op->W;
+  SrcGrid<double> src{nullptr, nn};
+  const Skip skip{nullptr, 0};
+  const gofd_cg::Level1 lv1;
+  const gofd_cg::Finish fin;
+  auto run = [&]() {
+    return run_3d<R, L, ALT>(ctx, op, 1, src, static_cast<R*>(nullptr), 2, skip, dpart, lv1, fin, nullptr);
+  };
+  hipStream_t st = ctx->stream;
+  for (int k = 0; k < 2; ++k)
+    if (run() != GOFD_OK) return -1.0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  constexpr int reps = 10;
+  (void)hipEventRecord(e0, st);
+  for (int k = 0; k < reps; ++k) (void)run();
+  (void)hipEventRecord(e1, st);
+  float ms = -1.f;
+  if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms < 0 ? -1.0 : ms / reps;
+}
+
+template <typename R, int L>
+int tune3_L(gofd_ctx_s* ctx, gofd_fdop_s* op, double* times) {
+  const bool fp32 = sizeof(R) == 4;
+  const long long z = conv3_workspace(op);
+  const long long nh = (long long)op->half * op->half * op->half;
+  GOFD_TRY(dev_reserve(ctx, op->Z, sizeof(cplx<R>) * z));
+  GOFD_TRY(dev_reserve(ctx, fp32 ? op->That32 : op->That64, sizeof(R) * nh));
+  const long long nd = 3LL * std::max(Cfg3<R, L, 0>::NSB, Cfg3<R, L, 1>::NSB) * L;
+  DevBuf dp;
+  GOFD_TRY(dev_reserve(ctx, dp, sizeof(double) * nd));
+  HIP_TRY(ctx, hipMemsetAsync(op->Z.p, 0, sizeof(cplx<R>) * z, ctx->stream));
+  HIP_TRY(ctx, hipMemsetAsync((fp32 ? op->That32 : op->That64).p, 0, sizeof(R) * nh, ctx->stream));
+  times[0] = time_yzy<R, L, 0>(ctx, op, dp.as<double>());
+  if (times[0] < 0) return gofd_fail(ctx, GOFD_E_HIP, "timing the 3D passes failed");
+  if (!Cfg3<R, L>::HAS_ALT) return 0;
+  times[1] = time_yzy<R, L, 1>(ctx, op, dp.as<double>());
+  if (times[1] < 0) return gofd_fail(ctx, GOFD_E_HIP, "timing the 3D passes failed");
+  HIP_TRY(ctx, hipGetLastError());
+  return times[1] < 0.95 * times[0] ? 1 : 0;   // the default unless the other is clearly faster
+}
+
+template <typename R>
+int tune3(gofd_ctx_s* ctx, gofd_fdop_s* op, double* times) {
+  switch (op->L) {
+    case 8: return tune3_L<R, 8>(ctx, op, times);
+    case 16: return tune3_L<R, 16>(ctx, op, times);
+    case 32: return tune3_L<R, 32>(ctx, op, times);
+    case 64: return tune3_L<R, 64>(ctx, op, times);
+    case 128: return tune3_L<R, 128>(ctx, op, times);
+    case 256: return tune3_L<R, 256>(ctx, op, times);
+    case 512: return tune3_L<R, 512>(ctx, op, times);
+    case 1024: return tune3_L<R, 1024>(ctx, op, times);
+    default: return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "3D FFT length");
+  }
+}
+
+}  // namespace
+
+int conv3_tune(gofd_ctx_s* ctx, const gofd_grid* grid, bool fp32, double* times) {
+  gofd_fdop_s op;
+  GOFD_TRY(fdop_init_geometry(ctx, &op, 0.5, grid));
+  if (!twiddles64(ctx, op.L) || !twiddles32(ctx, op.L)) return gofd_fail(ctx, GOFD_E_OOM, "twiddle table");
+  // time with the default schedule installed, then record the choice
+  ctx->sched3.erase(std::make_pair(op.L, fp32));
+  const int best = fp32 ? tune3<float>(ctx, &op, times) : tune3<double>(ctx, &op, times);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (best >= 0) ctx->sched3[std::make_pair(op.L, fp32)] = best;
+  return best;
+}
+

@@ -44,6 +44,8 @@ gofd_ctx_s* ctx_child(gofd_ctx_s* parent, size_t index) {
     c->twiddles = parent->twiddles;
     c->borrowed_twiddles = true;
     c->col_sched = parent->col_sched;
+    c->row_sched = parent->row_sched;
+    c->sched3 = parent->sched3;
     c->owns_stream = true;
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking) != hipSuccess ||
@@ -60,6 +62,8 @@ gofd_ctx_s* ctx_child(gofd_ctx_s* parent, size_t index) {
   // tables and schedules made or tuned on the parent since the child was created
   c->twiddles = parent->twiddles;
   c->col_sched = parent->col_sched;
+  c->row_sched = parent->row_sched;
+  c->sched3 = parent->sched3;
   return c;
 }
 

@@ -74,6 +74,8 @@ struct gofd_ctx_s {
   std::string last_error;
   std::map<int, TwiddleTables*> twiddles;   // keyed by L
   std::map<std::pair<int, bool>, int> col_sched;   // column-pass schedule per (L, FP32), see gofd_autotune
+  std::map<std::pair<int, bool>, int> row_sched;   // 2D first row pass of the products: values per thread
+  std::map<std::pair<int, bool>, int> sched3;      // 3D y/z/y passes: 0 default, 1 two slots per block
   DevBuf scratch;                           // small reduction scratch (partials, counters)
   DevBuf flag;                              // int status flags
   // When set, the next kernel launched through GOFD_LAUNCH records these
@@ -324,6 +326,9 @@ int conv3_run(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const double* v64, con
               int passes, const int* skip_flag, int skip_stride, double* dpart, const gofd_cg::Level1& lv1,
               const gofd_cg::Finish& fin, const void* const* that_tab = nullptr, const int* amap = nullptr);
 long long conv3_workspace(const gofd_fdop_s* op);
+// Time the 3D y/z/y passes in both schedules on a zero field of the grid,
+// install the faster in ctx->sched3; returns it (0 or 1) or an error.
+int conv3_tune(gofd_ctx_s* ctx, const gofd_grid* grid, bool fp32, double* times);
 int conv3_passC_blocks(const gofd_fdop_s* op, bool fp32);
 
 // Reserve the spectra workspace and twiddle tables for nrhs fields, so that

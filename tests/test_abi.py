@@ -46,6 +46,8 @@ def test_tuning_cache_roundtrip(tmp_path):
     gofd.cache_store(path, "gfx950/d2/L1024/fp64", 2, [1.0, 1.0, 0.5, 1.0])
     assert gofd.cache_lookup(path, "gfx950/d2/L2048/fp32") == 1
     assert gofd.cache_lookup(path, "gfx950/d2/L1024/fp64") == 2
+    gofd.cache_store(path, "gfx950/d2/L2048/fp32", 0, [1.0, 2.0, 2.0, 3.0, 1.0, 0.8], row=16)
+    assert gofd.cache_lookup(path, "gfx950/d2/L2048/fp32", full=True)["row"] == 16
     assert [gofd.fft_period(n) for n in (1, 2, 3, 32, 33, 512)] == [8, 8, 16, 128, 256, 2048]
 
 

@@ -16,6 +16,11 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _dev(a, dtype=None):
+    import torch
+    return torch.tensor(a, device="cuda", dtype=dtype)
+
+
 @pytest.mark.parametrize("n", [32, 256])
 def test_every_schedule_matches_the_oracle(gctx, n):
     import torch
@@ -82,3 +87,46 @@ def test_autotune_picks_its_fastest_and_caches(gctx, tmp_path):
         assert s2 == s and t2 is None
     finally:
         gofd.set_schedule(gctx, g, 0, fp32=True)
+
+
+def test_row_pass_and_3d_schedules_tune_and_agree(gctx):
+    """The first row pass of the products at 8 and 16 values per thread (2D, L >= 1024) and the 3D y/z/y
+    passes at four and two slots per block give the same product to rounding; the tuner times both of
+    each and installs what it measured."""
+    import paper_2307_14437_amd as gofd
+    g2 = grid_for_box(2, 512, R=1.0)                     # L = 1024: both row-pass widths exist
+    T2 = fw.filon_richardson(0.4, 2, 2 * g2.N, 4096)
+    op2 = gofd.FdOp(gctx, 0.4, g2, T=T2)
+    v2 = np.random.default_rng(3).standard_normal((1, g2.W, g2.W))
+    ref2 = afd.apply_fft(T2, v2[0])
+    g3 = grid_for_box(3, 32, R=1.0)                      # L = 128
+    T3 = fw.filon_richardson(0.6, 3, 2 * g3.N, 256)
+    op3 = gofd.FdOp(gctx, 0.6, g3, T=T3)
+    v3 = np.random.default_rng(4).standard_normal((1, g3.W, g3.W, g3.W))
+    ref3 = afd.apply_fft(T3, v3[0])
+    try:
+        for fp32 in (False, True):
+            tol = 3e-6 if fp32 else 1e-12
+            flags = gofd.FP32_GRID if fp32 else 0
+            for width in (8, 16):
+                gofd.set_schedule(gctx, g2, width, fp32=fp32, rows=True)
+                y = gofd.apply_afd(gctx, op2, _dev(v2), flags).cpu().numpy()
+                assert _rel(y[0], ref2) < tol, (fp32, width)
+            for sch in (0, 1):
+                gofd.set_schedule(gctx, g3, sch, fp32=fp32)
+                y = gofd.apply_afd(gctx, op3, _dev(v3), flags).cpu().numpy()
+                assert _rel(y[0], ref3) < tol, (fp32, sch)
+            r2 = gofd.autotune_all(gctx, g2, fp32=fp32)
+            print("2D", fp32, r2, flush=True)
+            t = r2["times"]
+            assert r2["row"] in (8, 16) and t[4] > 0 and t[5] > 0
+            assert r2["row"] == (16 if t[5] < 0.95 * t[4] else 8)
+            r3 = gofd.autotune_all(gctx, g3, fp32=fp32)
+            print("3D", fp32, r3, flush=True)
+            t = r3["times"]
+            assert t[0] > 0 and t[1] > 0 and r3["yzy"] == (1 if t[1] < 0.95 * t[0] else 0)
+    finally:
+        for fp32 in (False, True):
+            gofd.set_schedule(gctx, g2, 0, fp32=fp32, rows=True)
+            gofd.set_schedule(gctx, g3, 0, fp32=fp32)
+
