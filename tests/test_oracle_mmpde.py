@@ -1,0 +1,114 @@
+"""Pins of the oracle's mesh adaptation (Section 4): Hessian recovery, the metric of eq. MK-1 and its
+regularisation parameter, the energy of eq. I-h and its gradient, and the moving mesh equations."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mmpde
+from workloads import disk_mesh
+
+
+def _lattice(n=8, a=0.2):
+    """Equilateral triangle lattice (a rhombus of n x n points)."""
+    pts = np.array([[i * a + 0.5 * j * a, j * a * math.sqrt(3) / 2] for j in range(n) for i in range(n)])
+    tris = []
+    for j in range(n - 1):
+        for i in range(n - 1):
+            v = j * n + i
+            tris += [(v, v + 1, v + n), (v + 1, v + n + 1, v + n)]
+    return pts, np.array(tris)
+
+
+def test_hessian_recovery_is_exact_for_quadratics():
+    m = disk_mesh(seed=3, n_boundary=30, spacing=0.15)
+    x, y = m.X[:, 0], m.X[:, 1]
+    u = 1 + 2 * x - y + 3 * x ** 2 - 2 * x * y + 0.5 * y ** 2
+    H = mmpde.vertex_hessians(m.X, m.elems, u)
+    assert np.allclose(H, np.array([[6.0, -2.0], [-2.0, 1.0]]), rtol=0, atol=1e-8)
+    # linear data: zero Hessian
+    assert np.max(np.abs(mmpde.vertex_hessians(m.X, m.elems, 3 * x - y))) < 1e-9
+
+
+def test_abs_sym_and_metric_closed_form():
+    H = np.array([[[-2.0, 0.0], [0.0, 3.0]], [[0.0, 1.0], [1.0, 0.0]]])
+    A = mmpde.abs_sym(H)
+    assert np.allclose(A[0], np.diag([2.0, 3.0]))
+    assert np.allclose(A[1], np.eye(2))                 # eigenvalues +-1 of [[0,1],[1,0]]
+    assert np.allclose(A @ A, H @ H)
+    alpha = 0.7
+    M = mmpde.metric(A, alpha)
+    b0 = np.array([1 + 2 / alpha, 1 + 3 / alpha])
+    assert np.allclose(M[0], np.diag(b0) * (b0[0] * b0[1]) ** (-1 / 6), rtol=1e-14)
+    assert np.allclose(mmpde.metric(A, math.inf), np.eye(2))
+
+
+def test_alpha_solves_its_equation():
+    m = disk_mesh(seed=4, n_boundary=30, spacing=0.15)
+    r2 = np.sum(m.X ** 2, axis=1)
+    u = np.maximum(1 - r2, 0) ** 0.5
+    Hk = mmpde.element_hessians(m.elems, mmpde.vertex_hessians(m.X, m.elems, u))
+    A = mmpde.abs_sym(Hk)
+    area = mmpde.element_areas(m.X, m.elems)
+    alpha = mmpde.alpha_h(A, area)
+    lam = np.linalg.eigvalsh(A)
+    lhs = np.sum(area * np.prod(1 + lam / alpha, axis=1) ** (1 / 3))
+    assert lhs == pytest.approx(2 * np.sum(area), rel=1e-12)
+    assert mmpde.alpha_h(np.zeros_like(A), area) == math.inf
+
+
+def test_energy_of_the_reference_element_and_gradient_by_central_differences():
+    # the reference element itself with M = I: J = I, t = 2, both terms (1/3) 2^{3/2} |K|, |K| = 1
+    Er = mmpde.reference_edges(2)
+    X = np.array([[0.0, 0.0], Er[:, 0], Er[:, 1]])
+    assert mmpde.energy(X, np.array([[0, 1, 2]]), np.eye(2)[None]) == pytest.approx(2 / 3 * 2 ** 1.5, rel=1e-14)
+    rng = np.random.default_rng(5)
+    m = disk_mesh(seed=5, n_boundary=16, spacing=0.35)
+    Mk = []
+    for _ in range(m.ne):
+        Q = rng.standard_normal((2, 2))
+        Mk.append(Q @ Q.T + 0.5 * np.eye(2))
+    Mk = np.array(Mk)
+    G = mmpde.energy_gradient(m.X, m.elems, Mk)
+    eps = 1e-6
+    for i in rng.choice(m.nv, 8, replace=False):
+        for a in range(2):
+            Xp, Xm = m.X.copy(), m.X.copy()
+            Xp[i, a] += eps
+            Xm[i, a] -= eps
+            fd = (mmpde.energy(Xp, m.elems, Mk) - mmpde.energy(Xm, m.elems, Mk)) / (2 * eps)
+            assert G[i, a] == pytest.approx(fd, rel=1e-6, abs=1e-8 * np.abs(G).max())
+
+
+def test_uniform_equilateral_mesh_is_an_equilibrium():
+    # equal equilateral elements satisfy eqs. C-1 and C-2 for a constant metric: by the six-fold symmetry
+    # of the star of an interior vertex its energy gradient vanishes
+    X, T = _lattice()
+    G = mmpde.energy_gradient(X, T, np.broadcast_to(np.eye(2), (len(T), 2, 2)))
+    bnd = mmpde.boundary_mask(T, len(X))
+    assert np.max(np.abs(G[~bnd])) < 1e-12 * np.abs(G).max() + 1e-13
+    Mc = np.broadcast_to(np.diag([3.0, 3.0]), (len(T), 2, 2))
+    G3 = mmpde.energy_gradient(X, T, Mc)
+    assert np.max(np.abs(G3[~bnd])) < 1e-12 * np.abs(G3).max() + 1e-13
+
+
+def test_moving_the_mesh_follows_the_metric():
+    m = disk_mesh(seed=6, n_boundary=40, spacing=0.1)
+    r2 = np.sum(m.X ** 2, axis=1)
+    u = np.maximum(1 - r2, 0) ** 0.5                 # steep near the boundary
+    Hk = mmpde.element_hessians(m.elems, mmpde.vertex_hessians(m.X, m.elems, u))
+    A = mmpde.abs_sym(Hk)
+    area = mmpde.element_areas(m.X, m.elems)
+    M = mmpde.metric(A, mmpde.alpha_h(A, area))
+    bnd = mmpde.boundary_mask(m.elems, m.nv)
+    Y, steps = mmpde.move_mesh(m.X, m.elems, M, bnd)
+    assert steps > 5
+    assert np.all(mmpde.element_areas(Y, m.elems) > 0)
+    assert np.allclose(np.linalg.norm(Y[bnd], axis=1), 1.0, atol=1e-14)
+    assert mmpde.energy(Y, m.elems, M) < mmpde.energy(m.X, m.elems, M)
+    # elements near the boundary shrink, those in the middle grow
+    cen0 = m.X[m.elems].mean(axis=1)
+    near = np.linalg.norm(cen0, axis=1) > 0.85
+    a1 = mmpde.element_areas(Y, m.elems)
+    assert a1[near].mean() < area[near].mean() and a1[~near].mean() > area[~near].mean()
