@@ -23,10 +23,21 @@ Steps of one adaptation level, in the paper's order:
        dx_i/dt = -sqrt(det M(x_i)) / tau  dI_h/dx_i,
    with M(x_i) the mean of the metrics of the elements around vertex i, the
    normal component removed on the boundary (vertices slide along it), over
-   t in (0, 1], tau = 1e-2, connectivity fixed.  Reading of the integrator
-   (the paper uses MATLAB's ode15s): explicit steps of the gradient flow whose
-   length is halved until no element inverts and the energy decreases, and
-   grown by 1.5 after an accepted step.
+   t in (0, 1], tau = 1e-2, connectivity fixed.  The system is stiff (I_h
+   grows like h^-3 as the mesh is refined, so an explicit step must shrink
+   like tau h^3), and the paper integrates it with a stiff solver (MATLAB's
+   ode15s) whose Jacobian comes from finite differences.  Reading of the
+   integrator: linearly implicit (Rosenbrock-Euler) steps
+       (tau/h Q^{-1} + J) dx = -dI_h/dx,   Q = diag(sqrt(det M(x_i))),
+   restricted to the allowed motions (tangential on the boundary), with J
+   the Hessian of I_h assembled from element Hessians taken by central
+   differences of the analytic element gradient (step 1e-5 times the
+   element's longest edge, then symmetrised).  A trial step is halved until
+   the restricted matrix is positive definite, no element inverts and I_h
+   decreases; the next trial step is twice the accepted one.  Integration
+   stops at t = 1, or earlier once the flow is at rest: the restricted
+   gradient has fallen to 1e-6 of its initial norm (the mesh then no longer
+   moves, so the mesh at t = 1 is the one reached).
 
 The derivative dI_h/dx_i is the plain chain rule through eq. I-h (the paper
 points to Huang & Kamenski for the same quantity): with E = [x_1 - x_0, ..,
@@ -45,6 +56,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.sparse as sp
 
 
 # ---------------------------------------------------------------- topology
@@ -192,33 +204,74 @@ def energy(X: np.ndarray, elems: np.ndarray, M: np.ndarray) -> float:
     return total
 
 
-def energy_gradient(X: np.ndarray, elems: np.ndarray, M: np.ndarray) -> np.ndarray:
-    """dI_h/dx_i (nv x 2) by the chain rule through eq. I-h (see the module docstring)."""
+def element_gradients(X: np.ndarray, elems: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """dG_K/dx for the three vertices of every element (N_e x 3 x 2), by the chain rule through eq. I-h
+    (see the module docstring); batched over elements."""
     d = 2
     p = 3.0 * d / 4.0
     Er = reference_edges(d)
     Dr = np.linalg.det(Er)
     B = Er.T @ Er
+    P = np.asarray(X)[np.asarray(elems)]
+    E = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]], axis=2)      # columns x_1 - x_0, x_2 - x_0
+    V = np.linalg.det(E)
+    Ei = np.linalg.inv(E)
+    EiT = np.transpose(Ei, (0, 2, 1))
+    A = np.linalg.inv(M)
+    q = np.sqrt(np.linalg.det(M))
+    X1 = Ei @ A @ EiT
+    t = np.einsum("kij,ji->k", X1, B)
+    dV = V[:, None, None] * EiT
+    dt = -2.0 * EiT @ B @ X1
+    fac = q / math.factorial(d)
+    g1 = (fac / 3.0 * t ** p)[:, None, None] * dV + (fac / 3.0 * V * p * t ** (p - 1.0))[:, None, None] * dt
+    g2 = (d ** p / 3.0 * fac * (q / Dr) ** (-p) * (1.0 - p) * V ** (-p))[:, None, None] * dV
+    gE = g1 + g2
+    g = np.empty(P.shape)
+    g[:, 1] = gE[:, :, 0]
+    g[:, 2] = gE[:, :, 1]
+    g[:, 0] = -(gE[:, :, 0] + gE[:, :, 1])
+    return g
+
+
+def energy_gradient(X: np.ndarray, elems: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """dI_h/dx_i (nv x 2): the element gradients summed at the vertices."""
     X = np.asarray(X)
+    g = element_gradients(X, elems, M)
     G = np.zeros_like(X)
-    for k, t_ in enumerate(np.asarray(elems)):
-        P = X[t_]
-        E = np.stack([P[1] - P[0], P[2] - P[0]], axis=1)
-        V = np.linalg.det(E)
-        Ei = np.linalg.inv(E)
-        A = np.linalg.inv(M[k])
-        q = math.sqrt(np.linalg.det(M[k]))
-        t = np.trace(Ei @ A @ Ei.T @ B)
-        dV = V * Ei.T
-        dt = -2.0 * Ei.T @ B @ Ei @ A @ Ei.T
-        fac = q / math.factorial(d)
-        g1 = fac / 3.0 * (t ** p * dV + V * p * t ** (p - 1.0) * dt)
-        g2 = d ** p / 3.0 * fac * (q / Dr) ** (-p) * (1.0 - p) * V ** (-p) * dV
-        gE = g1 + g2
-        G[t_[1]] += gE[:, 0]
-        G[t_[2]] += gE[:, 1]
-        G[t_[0]] -= gE[:, 0] + gE[:, 1]
+    for a in range(3):
+        np.add.at(G, np.asarray(elems)[:, a], g[:, a])
     return G
+
+
+def element_hessians_fd(X: np.ndarray, elems: np.ndarray, M: np.ndarray, rel_step: float = 1e-5) -> np.ndarray:
+    """Hessian of every element's term of I_h with respect to its six coordinates (N_e x 6 x 6, in the
+    order x_0, y_0, x_1, .., y_2), by central differences of element_gradients with the step rel_step
+    times the element's longest edge, symmetrised."""
+    X = np.asarray(X)
+    elems = np.asarray(elems)
+    P = X[elems]
+    edge = np.max(np.stack([np.linalg.norm(P[:, a] - P[:, (a + 1) % 3], axis=1) for a in range(3)], 1), 1)
+    eps = rel_step * edge
+    ne = P.shape[0]
+    H = np.empty((ne, 6, 6))
+    loc = np.arange(3, dtype=np.int64)[None].repeat(ne, 0)
+    for c in range(6):
+        Pp, Pm = P.copy(), P.copy()
+        Pp[:, c // 2, c % 2] += eps
+        Pm[:, c // 2, c % 2] -= eps
+        Xp, Xm = Pp.reshape(-1, 2), Pm.reshape(-1, 2)             # every element on its own three points
+        el = loc + 3 * np.arange(ne)[:, None]
+        H[:, :, c] = (element_gradients(Xp, el, M) - element_gradients(Xm, el, M)).reshape(ne, 6) / (2 * eps[:, None])
+    return 0.5 * (H + np.transpose(H, (0, 2, 1)))
+
+
+def assemble_hessian(elems: np.ndarray, H: np.ndarray, nv: int) -> sp.csr_matrix:
+    """Sum of the element Hessians into the (2 nv x 2 nv) Hessian of I_h (unknowns x_0, y_0, x_1, ..)."""
+    idx = (2 * np.asarray(elems, dtype=np.int64)[:, :, None] + np.arange(2)[None, None]).reshape(-1, 6)
+    rows = np.repeat(idx, 6, axis=1).ravel()
+    cols = np.tile(idx, (1, 6)).ravel()
+    return sp.csr_matrix((H.ravel(), (rows, cols)), shape=(2 * nv, 2 * nv))
 
 
 # ---------------------------------------------------------------- moving the mesh
@@ -246,35 +299,87 @@ def velocity(X, elems, M, bnd, tau=1e-2, qv=None):
     return v
 
 
-def euler_step(X, v, dt, bnd):
-    """x + dt v, boundary vertices put back on the unit circle."""
-    Y = np.asarray(X) + dt * v
-    Y[bnd] /= np.linalg.norm(Y[bnd], axis=1)[:, None]
+def motion_basis(X: np.ndarray, bnd: np.ndarray, boundary: str = "circle") -> sp.csr_matrix:
+    """Columns spanning the allowed vertex motions (2 nv x n_dof): x and y for an interior vertex, the
+    unit tangent of the circle through a boundary vertex ("circle"), nothing for it ("fixed")."""
+    X = np.asarray(X)
+    rows, cols, vals = [], [], []
+    k = 0
+    for i in range(X.shape[0]):
+        if not bnd[i]:
+            rows += [2 * i, 2 * i + 1]
+            cols += [k, k + 1]
+            vals += [1.0, 1.0]
+            k += 2
+        elif boundary == "circle":
+            r = math.hypot(X[i, 0], X[i, 1])
+            rows += [2 * i, 2 * i + 1]
+            cols += [k, k]
+            vals += [-X[i, 1] / r, X[i, 0] / r]
+            k += 1
+    return sp.csr_matrix((vals, (rows, cols)), shape=(2 * X.shape[0], k))
+
+
+def place(Y: np.ndarray, bnd: np.ndarray, boundary: str = "circle") -> np.ndarray:
+    """Boundary vertices put back on the unit circle."""
+    if boundary == "circle":
+        Y[bnd] /= np.linalg.norm(Y[bnd], axis=1)[:, None]
     return Y
 
 
-def move_mesh(X, elems, M, bnd, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400):
-    """Integrate eq. x-1 over (0, t_end] with the step control described in the module docstring.
-    Returns (new X, number of accepted steps)."""
+def implicit_step(X, elems, M, bnd, qv, h, tau=1e-2, G=None, J=None, boundary="circle"):
+    """One linearly implicit step of length h: X + B z with (B^T (tau/h Q^{-1} + J) B) z = -B^T dI_h/dx.
+    Returns None when that matrix is not positive definite."""
+    X = np.asarray(X)
+    nv = X.shape[0]
+    if G is None:
+        G = energy_gradient(X, elems, M)
+    if J is None:
+        J = assemble_hessian(elems, element_hessians_fd(X, elems, M), nv)
+    Bm = motion_basis(X, bnd, boundary)
+    A = (Bm.T @ (J + sp.diags(np.repeat(tau / (h * qv), 2))) @ Bm).toarray()
+    try:
+        L = np.linalg.cholesky(A)
+    except np.linalg.LinAlgError:
+        return None
+    z = np.linalg.solve(L.T, np.linalg.solve(L, -(Bm.T @ G.ravel())))
+    return place(X + (Bm @ z).reshape(-1, 2), bnd, boundary)
+
+
+def move_mesh(X, elems, M, bnd, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, gtol=1e-6, boundary="circle"):
+    """Integrate eq. x-1 over (0, t_end] with the linearly implicit steps and the step control of the
+    module docstring.  Returns (new X, accepted steps, dict with t, rejected, energy and gradient norms)."""
     X = np.array(X, dtype=np.float64)
-    qv = vertex_metric_sqrtdet(elems, M, X.shape[0])
-    t, dt, steps = 0.0, dt0, 0
-    I0 = energy(X, elems, M)
+    nv = X.shape[0]
+    qv = vertex_metric_sqrtdet(elems, M, nv)
+    t, dt, steps, rejected = 0.0, dt0, 0, 0
+    I0 = I_start = energy(X, elems, M)
+    g0 = None
     while t < t_end and steps < max_steps:
+        G = energy_gradient(X, elems, M)
+        gn = float(np.linalg.norm(motion_basis(X, bnd, boundary).T @ G.ravel()))
+        if g0 is None:
+            g0 = gn
+        if gn <= gtol * g0:
+            break
+        J = assemble_hessian(elems, element_hessians_fd(X, elems, M), nv)
         h = min(dt, t_end - t)
-        v = velocity(X, elems, M, bnd, tau, qv)
         while True:
-            Y = euler_step(X, v, h, bnd)
-            if np.all(element_areas(Y, elems) > 0):
+            Y = implicit_step(X, elems, M, bnd, qv, h, tau, G, J, boundary)
+            if Y is not None and np.all(element_areas(Y, elems) > 0):
                 I1 = energy(Y, elems, M)
                 if I1 < I0:
                     break
             h *= 0.5
+            rejected += 1
             if h < 1e-14:
-                return X, steps
+                return X, steps, dict(t=t, rejected=rejected, energy_start=I_start, energy_end=I0,
+                                      grad0=g0, grad=gn)
         X, I0, t, steps = Y, I1, t + h, steps + 1
-        dt = 1.5 * h
-    return X, steps
+        dt = 2.0 * h
+    G = energy_gradient(X, elems, M)
+    gn = float(np.linalg.norm(motion_basis(X, bnd, boundary).T @ G.ravel()))
+    return X, steps, dict(t=t, rejected=rejected, energy_start=I_start, energy_end=I0, grad0=g0, grad=gn)
 
 
 # ---------------------------------------------------------------- Algorithm amGoFD
@@ -294,5 +399,5 @@ def adapt(X, elems, solve_on, levels=5, tau=1e-2, max_steps=400):
         out.append((X.copy(), u))
         A = abs_sym(element_hessians(elems, vertex_hessians(X, elems, u, rings)))
         M = metric(A, alpha_h(A, element_areas(X, elems)))
-        X, _ = move_mesh(X, elems, M, bnd, tau=tau, max_steps=max_steps)
+        X, _, _ = move_mesh(X, elems, M, bnd, tau=tau, max_steps=max_steps)
     return out

@@ -93,17 +93,49 @@ def test_uniform_equilateral_mesh_is_an_equilibrium():
     assert np.max(np.abs(G3[~bnd])) < 1e-12 * np.abs(G3).max() + 1e-13
 
 
-def test_moving_the_mesh_follows_the_metric():
-    m = disk_mesh(seed=6, n_boundary=40, spacing=0.1)
+def _disk_metric(seed, nb, spc):
+    m = disk_mesh(seed=seed, n_boundary=nb, spacing=spc)
     r2 = np.sum(m.X ** 2, axis=1)
     u = np.maximum(1 - r2, 0) ** 0.5                 # steep near the boundary
     Hk = mmpde.element_hessians(m.elems, mmpde.vertex_hessians(m.X, m.elems, u))
     A = mmpde.abs_sym(Hk)
     area = mmpde.element_areas(m.X, m.elems)
-    M = mmpde.metric(A, mmpde.alpha_h(A, area))
+    return m, mmpde.metric(A, mmpde.alpha_h(A, area)), area
+
+
+def test_hessian_times_vector_is_the_derivative_of_the_gradient():
+    # the assembled element Hessians (differences per element, relative steps) against a central difference
+    # of the whole gradient along one random direction with one absolute step
+    m, M, _ = _disk_metric(7, 30, 0.15)
+    J = mmpde.assemble_hessian(m.elems, mmpde.element_hessians_fd(m.X, m.elems, M), m.nv)
+    assert abs(J - J.T).max() <= 1e-15 * abs(J).max()      # symmetric up to the order of the sums
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal((m.nv, 2))
+    eps = 1e-6
+    d = (mmpde.energy_gradient(m.X + eps * v, m.elems, M) - mmpde.energy_gradient(m.X - eps * v, m.elems, M)) / (2 * eps)
+    Jv = (J @ v.ravel()).reshape(-1, 2)
+    assert np.max(np.abs(Jv - d)) <= 1e-6 * np.max(np.abs(d))
+
+
+def test_short_implicit_step_is_the_explicit_one():
+    # for h -> 0 the linearly implicit step tends to h times the right side of eq. x-1
+    m, M, _ = _disk_metric(9, 30, 0.15)
     bnd = mmpde.boundary_mask(m.elems, m.nv)
-    Y, steps = mmpde.move_mesh(m.X, m.elems, M, bnd)
+    qv = mmpde.vertex_metric_sqrtdet(m.elems, M, m.nv)
+    v = mmpde.velocity(m.X, m.elems, M, bnd, 1e-2, qv)
+    err = []
+    for h in (1e-10, 1e-12):
+        Y = mmpde.implicit_step(m.X, m.elems, M, bnd, qv, h)
+        err.append(np.max(np.abs((Y - m.X) / h - v)) / np.max(np.abs(v)))
+    assert err[1] <= 2e-5 and 50 < err[0] / err[1] < 200          # first order in h
+
+
+def test_moving_the_mesh_follows_the_metric():
+    m, M, area = _disk_metric(6, 40, 0.1)
+    bnd = mmpde.boundary_mask(m.elems, m.nv)
+    Y, steps, info = mmpde.move_mesh(m.X, m.elems, M, bnd)
     assert steps > 5
+    assert info["grad"] <= 1e-6 * info["grad0"]      # the flow has come to rest
     assert np.all(mmpde.element_areas(Y, m.elems) > 0)
     assert np.allclose(np.linalg.norm(Y[bnd], axis=1), 1.0, atol=1e-14)
     assert mmpde.energy(Y, m.elems, M) < mmpde.energy(m.X, m.elems, M)
@@ -112,3 +144,11 @@ def test_moving_the_mesh_follows_the_metric():
     near = np.linalg.norm(cen0, axis=1) > 0.85
     a1 = mmpde.element_areas(Y, m.elems)
     assert a1[near].mean() < area[near].mean() and a1[~near].mean() > area[~near].mean()
+
+
+def test_fixed_boundary_stays():
+    m, M, _ = _disk_metric(10, 30, 0.15)
+    bnd = mmpde.boundary_mask(m.elems, m.nv)
+    Y, steps, info = mmpde.move_mesh(m.X, m.elems, M, bnd, max_steps=5, boundary="fixed")
+    assert steps == 5 and np.array_equal(Y[bnd], m.X[bnd]) and not np.array_equal(Y, m.X)
+    assert info["energy_end"] < info["energy_start"]
