@@ -8,36 +8,50 @@ Steps of one adaptation level, in the paper's order:
    two-ring (the vertex, its neighbours and theirs); its Hessian is the
    vertex Hessian, and H_K is the mean of the vertex Hessians of K.
 2. The metric tensor of eq. MK-1,
-       M_K = det(I + |H_K| / alpha_h)^{-1/(d+4)} (I + |H_K| / alpha_h),
+       M = det(I + |H| / alpha_h)^{-1/(d+4)} (I + |H| / alpha_h),
    |H| = sqrt(H^2), with alpha_h the root of
        sum_K |K| det(I + |H_K| / alpha_h)^{2/(d+4)} = 2 |Omega|
    (the paper prints |H_K(H_K(u))| inside this sum; the reading is |H_K(u)|).
    When every H_K vanishes the sum equals |Omega| for every alpha and there
-   is no root: then M_K = I.
-3. The mesh energy of eq. I-h for the metric held fixed on every element,
+   is no root: then M = I.  Reading: M is a field of position, the
+   piecewise-linear interpolant on the mesh the move starts from of the
+   vertex metrics (eq. MK-1 with the vertex Hessians).
+3. The mesh energy of eq. I-h,
        I_h = 1/3 sum_K sqrt(det M_K) |K| tr(J_K M_K^{-1} J_K^T)^{3d/4}
            + d^{3d/4}/3 sum_K sqrt(det M_K) |K| (sqrt(det M_K) det F'_K)^{-3d/4},
    J_K = (F'_K)^{-1}, F_K the affine map from the equilateral reference
-   simplex of unit volume onto K.
+   simplex of unit volume onto K, and M_K the metric field at the current
+   centroid of K.  The centroid is located in the starting mesh by a walk
+   (from the element where it was at the last accepted step, across the edge
+   opposite the most negative barycentric coordinate, until none is negative
+   or the edge is on the boundary, where the value is extrapolated).  Both
+   the equidistribution of the mesh and its alignment depend on M_K moving
+   with the element: with M_K frozen per element the minimiser of I_h only
+   grades element areas like (sqrt(det M_K))^{-1/3}.
 4. The moving mesh equations (eqs. x-1, mmpde-1):
        dx_i/dt = -sqrt(det M(x_i)) / tau  dI_h/dx_i,
-   with M(x_i) the mean of the metrics of the elements around vertex i, the
-   normal component removed on the boundary (vertices slide along it), over
-   t in (0, 1], tau = 1e-2, connectivity fixed.  The system is stiff (I_h
-   grows like h^-3 as the mesh is refined, so an explicit step must shrink
-   like tau h^3), and the paper integrates it with a stiff solver (MATLAB's
-   ode15s) whose Jacobian comes from finite differences.  Reading of the
-   integrator: linearly implicit (Rosenbrock-Euler) steps
+   with sqrt(det M(x_i)) taken at the vertex metric of the starting mesh,
+   the normal component removed on the boundary (vertices slide along it),
+   over t in (0, 1], tau = 1e-2, connectivity fixed.  The system is stiff
+   (I_h grows like h^-3 as the mesh is refined, so an explicit step must
+   shrink like tau h^3), and the paper integrates it with a stiff solver
+   (MATLAB's ode15s) whose Jacobian comes from finite differences.  Reading
+   of the integrator: linearly implicit (Rosenbrock-Euler) steps
        (tau/h Q^{-1} + J) dx = -dI_h/dx,   Q = diag(sqrt(det M(x_i))),
    restricted to the allowed motions (tangential on the boundary), with J
-   the Hessian of I_h assembled from element Hessians taken by central
+   the Hessian of I_h for the current M_K held fixed (the stiff shape
+   terms; the metric's own variation is left to the right-hand side, as in
+   a W-method), assembled from element Hessians taken by central
    differences of the analytic element gradient (step 1e-5 times the
    element's longest edge, then symmetrised).  A trial step is halved until
    the restricted matrix is positive definite, no element inverts and I_h
    decreases; the next trial step is twice the accepted one.  Integration
    stops at t = 1, or earlier once the flow is at rest: the restricted
    gradient has fallen to 1e-6 of its initial norm (the mesh then no longer
-   moves, so the mesh at t = 1 is the one reached).
+   moves, so the mesh at t = 1 is the one reached), or no step of at least
+   1e-6 times the longest accepted one (and 1e-14) decreases I_h (the
+   gradient of I_h jumps where a centroid crosses an edge of the starting
+   mesh, and the flow comes to rest at such a kink).
 
 The derivative dI_h/dx_i is the plain chain rule through eq. I-h (the paper
 points to Huang & Kamenski for the same quantity): with E = [x_1 - x_0, ..,
@@ -45,7 +59,11 @@ x_d - x_0], V = det E, B = E_ref^T E_ref (the reference simplex's edges),
 A = M^{-1}, t = tr(E^{-1} A E^{-T} B):
     dV/dE = V E^{-T},    dt/dE = -2 E^{-T} B E^{-1} A E^{-T},
 and column j of dG_K/dE is the derivative with respect to vertex j of K
-(j = 1..d), vertex 0 taking minus their sum.
+(j = 1..d), vertex 0 taking minus their sum.  The metric adds, at each
+vertex of K, 1/(d+1) sum_c dG_K/dm_c grad m_c, m_c the components (m11, m12,
+m22) and grad m_c their gradient on the element of the starting mesh that
+holds the centroid; with q = sqrt(det M):
+    dq/dM = q A / 2,    dt/dM = -A C A,   C = E^{-T} B E^{-1}.
 
 Test infrastructure: plain numpy, one element or vertex at a time where a
 loop is clearer.
@@ -277,26 +295,124 @@ def assemble_hessian(elems: np.ndarray, H: np.ndarray, nv: int) -> sp.csr_matrix
 # ---------------------------------------------------------------- moving the mesh
 
 
-def vertex_metric_sqrtdet(elems: np.ndarray, M: np.ndarray, nv: int) -> np.ndarray:
-    """sqrt(det M(x_i)) with M(x_i) the mean of the metrics of the elements around vertex i."""
-    S = np.zeros((nv, 2, 2))
-    c = np.zeros(nv)
-    for k, t_ in enumerate(np.asarray(elems)):
-        for a in t_:
-            S[a] += M[k]
-            c[a] += 1
-    return np.sqrt(np.linalg.det(S / c[:, None, None]))
-
-
-def velocity(X, elems, M, bnd, tau=1e-2, qv=None):
-    """Right side of eq. x-1; boundary vertices (on the unit circle) keep their tangential component."""
+def velocity(X, elems, M, bnd, qv, tau=1e-2):
+    """Right side of eq. x-1 for per-element metrics M; boundary vertices (on the unit circle) keep their
+    tangential component."""
     X = np.asarray(X)
-    if qv is None:
-        qv = vertex_metric_sqrtdet(elems, M, X.shape[0])
-    v = -(qv / tau)[:, None] * energy_gradient(X, elems, M)
+    v = -(np.asarray(qv) / tau)[:, None] * energy_gradient(X, elems, M)
     n = X[bnd] / np.linalg.norm(X[bnd], axis=1)[:, None]
     v[bnd] -= np.sum(v[bnd] * n, axis=1)[:, None] * n
     return v
+
+
+# ---------------------------------------------------------------- the metric as a field of position
+
+
+def element_neighbours(elems: np.ndarray) -> np.ndarray:
+    """(N_e x 3): the element across the edge opposite corner a of element k, or -1 on the boundary."""
+    elems = np.asarray(elems)
+    nb = -np.ones((elems.shape[0], 3), dtype=np.int64)
+    seen = {}
+    for k, t in enumerate(elems):
+        for a in range(3):
+            e = tuple(sorted((int(t[(a + 1) % 3]), int(t[(a + 2) % 3]))))
+            if e in seen:
+                k2, a2 = seen.pop(e)
+                nb[k, a], nb[k2, a2] = k2, k
+            else:
+                seen[e] = (k, a)
+    return nb
+
+
+def barycentric(Xb: np.ndarray, elems: np.ndarray, k: int, x: np.ndarray) -> np.ndarray:
+    P = Xb[elems[k]]
+    T = np.stack([P[1] - P[0], P[2] - P[0]], axis=1)
+    l12 = np.linalg.solve(T, np.asarray(x) - P[0])
+    return np.array([1.0 - l12[0] - l12[1], l12[0], l12[1]])
+
+
+def walk(Xb, elems, nb, k, x, max_moves=10000):
+    """Element of the starting mesh holding x and x's barycentric coordinates there: from element k, cross
+    the edge opposite the most negative coordinate until none is negative or that edge is on the boundary."""
+    for _ in range(max_moves):
+        lam = barycentric(Xb, elems, k, x)
+        a = int(np.argmin(lam))
+        if lam[a] >= 0.0 or nb[k, a] < 0:
+            return k, lam
+        k = int(nb[k, a])
+    raise RuntimeError("point location did not end")
+
+
+class MetricField:
+    """Piecewise-linear metric on the starting mesh (Xb, elems) from vertex metrics Mv (N_v x 2 x 2)."""
+
+    def __init__(self, Xb, elems, Mv):
+        self.Xb = np.array(Xb, dtype=np.float64)
+        self.elems = np.asarray(elems)
+        self.m = np.stack([Mv[:, 0, 0], Mv[:, 0, 1], Mv[:, 1, 1]], axis=1)      # components m11, m12, m22
+        self.nb = element_neighbours(self.elems)
+        # gradient of each component on each element: grad^T [x1 - x0, x2 - x0] = [f1 - f0, f2 - f0]
+        P = self.Xb[self.elems]
+        T = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]], axis=2)
+        f = self.m[self.elems]                                                   # ne x 3 corners x 3 comps
+        df = np.stack([f[:, 1] - f[:, 0], f[:, 2] - f[:, 0]], axis=1)           # ne x 2 x 3
+        self.grad = np.transpose(np.linalg.solve(np.transpose(T, (0, 2, 1)), df), (0, 2, 1))  # ne x 3 x 2
+
+    def at_centroids(self, X, loc):
+        """(M_K as N_e x 2 x 2, gradients of the components N_e x 3 x 2, new locations)."""
+        C = np.asarray(X)[self.elems].mean(axis=1)
+        ne = self.elems.shape[0]
+        M3 = np.empty((ne, 3))
+        G = np.empty((ne, 3, 2))
+        loc = np.array(loc)
+        for k in range(ne):
+            kb, lam = walk(self.Xb, self.elems, self.nb, int(loc[k]), C[k])
+            loc[k] = kb
+            M3[k] = lam @ self.m[self.elems[kb]]
+            G[k] = self.grad[kb]
+        M = np.stack([np.stack([M3[:, 0], M3[:, 1]], 1), np.stack([M3[:, 1], M3[:, 2]], 1)], 1)
+        return M, G, loc
+
+
+def metric_derivatives(X: np.ndarray, elems: np.ndarray, M: np.ndarray) -> np.ndarray:
+    """dG_K/dm_c (N_e x 3) for the components m11, m12, m22 of M_K (m12 standing for both off-diagonal
+    entries), by the formulas in the module docstring."""
+    d = 2
+    p = 3.0 * d / 4.0
+    Er = reference_edges(d)
+    Dr = np.linalg.det(Er)
+    B = Er.T @ Er
+    P = np.asarray(X)[np.asarray(elems)]
+    E = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]], axis=2)
+    V = np.linalg.det(E)
+    Ei = np.linalg.inv(E)
+    C = np.transpose(Ei, (0, 2, 1)) @ B @ Ei
+    A = np.linalg.inv(M)
+    q = np.sqrt(np.linalg.det(M))
+    t = np.einsum("kij,kji->k", A, C)
+    area = V / math.factorial(d)
+    # G = q |K| t^p / 3 + d^p / 3 q |K| (q V / Dr)^{-p}
+    dG_dq = area * t ** p / 3.0 + d ** p / 3.0 * area * (1.0 - p) * q ** (-p) * (V / Dr) ** (-p)
+    dG_dt = q * area * p * t ** (p - 1.0) / 3.0
+    ACA = A @ C @ A
+    dq = np.stack([0.5 * q * A[:, 0, 0], q * A[:, 0, 1], 0.5 * q * A[:, 1, 1]], axis=1)
+    dt = np.stack([-ACA[:, 0, 0], -2.0 * ACA[:, 0, 1], -ACA[:, 1, 1]], axis=1)
+    return dG_dq[:, None] * dq + dG_dt[:, None] * dt
+
+
+def energy_field(X, elems, field: MetricField, loc):
+    """(I_h, dI_h/dx (N_v x 2), M_K, new locations) with M_K the field at the current centroids;
+    I_h = inf (and no gradient) when an element has non-positive area."""
+    X = np.asarray(X)
+    M, GM, loc = field.at_centroids(X, loc)
+    if not np.all(element_areas(X, elems) > 0):
+        return math.inf, None, M, loc
+    g = element_gradients(X, elems, M) + (np.einsum("kc,kcd->kd", metric_derivatives(X, elems, M), GM)
+                                          / 3.0)[:, None, :]
+    G = np.zeros_like(X)
+    for a in range(3):
+        np.add.at(G, np.asarray(elems)[:, a], g[:, a])
+    return energy(X, elems, M), G, M, loc
 
 
 def motion_basis(X: np.ndarray, bnd: np.ndarray, boundary: str = "circle") -> sp.csr_matrix:
@@ -327,68 +443,79 @@ def place(Y: np.ndarray, bnd: np.ndarray, boundary: str = "circle") -> np.ndarra
     return Y
 
 
-def implicit_step(X, elems, M, bnd, qv, h, tau=1e-2, G=None, J=None, boundary="circle"):
-    """One linearly implicit step of length h: X + B z with (B^T (tau/h Q^{-1} + J) B) z = -B^T dI_h/dx.
+def implicit_step(X, bnd, qv, h, G, J, tau=1e-2, boundary="circle"):
+    """One linearly implicit step of length h: X + B z with (B^T (tau/h Q^{-1} + J) B) z = -B^T G.
     Returns None when that matrix is not positive definite."""
     X = np.asarray(X)
-    nv = X.shape[0]
-    if G is None:
-        G = energy_gradient(X, elems, M)
-    if J is None:
-        J = assemble_hessian(elems, element_hessians_fd(X, elems, M), nv)
     Bm = motion_basis(X, bnd, boundary)
-    A = (Bm.T @ (J + sp.diags(np.repeat(tau / (h * qv), 2))) @ Bm).toarray()
+    A = (Bm.T @ (J + sp.diags(np.repeat(tau / (h * np.asarray(qv)), 2))) @ Bm).toarray()
     try:
         L = np.linalg.cholesky(A)
     except np.linalg.LinAlgError:
         return None
-    z = np.linalg.solve(L.T, np.linalg.solve(L, -(Bm.T @ G.ravel())))
+    z = np.linalg.solve(L.T, np.linalg.solve(L, -(Bm.T @ np.asarray(G).ravel())))
     return place(X + (Bm @ z).reshape(-1, 2), bnd, boundary)
 
 
-def move_mesh(X, elems, M, bnd, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, gtol=1e-6, boundary="circle"):
-    """Integrate eq. x-1 over (0, t_end] with the linearly implicit steps and the step control of the
-    module docstring.  Returns (new X, accepted steps, dict with t, rejected, energy and gradient norms)."""
+def move_mesh(X, elems, Mv, bnd, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, gtol=1e-6, boundary="circle",
+              fixed_dt=0.0):
+    """Integrate eq. x-1 over (0, t_end] for the vertex metrics Mv (N_v x 2 x 2) of the mesh X, with the
+    linearly implicit steps and the step control of the module docstring.  With fixed_dt > 0: exactly
+    max_steps steps of that length, no energy test and no gradient stop.
+    Returns (new X, accepted steps, dict with t, rejected, energy and gradient norms)."""
     X = np.array(X, dtype=np.float64)
-    nv = X.shape[0]
-    qv = vertex_metric_sqrtdet(elems, M, nv)
-    t, dt, steps, rejected = 0.0, dt0, 0, 0
-    I0 = I_start = energy(X, elems, M)
-    g0 = None
-    while t < t_end and steps < max_steps:
-        G = energy_gradient(X, elems, M)
-        gn = float(np.linalg.norm(motion_basis(X, bnd, boundary).T @ G.ravel()))
-        if g0 is None:
-            g0 = gn
-        if gn <= gtol * g0:
+    elems = np.asarray(elems)
+    field = MetricField(X, elems, Mv)
+    qv = np.sqrt(np.linalg.det(Mv))
+    loc = np.arange(elems.shape[0])
+    I0, G, M, loc = energy_field(X, elems, field, loc)
+    I_start = I0
+    t, dt, steps, rejected, h_max = 0.0, (fixed_dt if fixed_dt > 0 else dt0), 0, 0, 0.0
+    g0 = float(np.linalg.norm(motion_basis(X, bnd, boundary).T @ G.ravel()))
+    gn = g0
+    while steps < max_steps and (fixed_dt > 0 or t < t_end):
+        if fixed_dt <= 0 and gn <= gtol * g0:
             break
-        J = assemble_hessian(elems, element_hessians_fd(X, elems, M), nv)
-        h = min(dt, t_end - t)
+        J = assemble_hessian(elems, element_hessians_fd(X, elems, M), X.shape[0])
+        h = dt if fixed_dt > 0 else min(dt, t_end - t)
         while True:
-            Y = implicit_step(X, elems, M, bnd, qv, h, tau, G, J, boundary)
+            Y = implicit_step(X, bnd, qv, h, G, J, tau, boundary)
+            if fixed_dt > 0:
+                if Y is None:
+                    raise np.linalg.LinAlgError("step system not positive definite")
+                I1, G1, M1, loc1 = energy_field(Y, elems, field, loc)
+                break
             if Y is not None and np.all(element_areas(Y, elems) > 0):
-                I1 = energy(Y, elems, M)
+                I1, G1, M1, loc1 = energy_field(Y, elems, field, loc)
                 if I1 < I0:
                     break
             h *= 0.5
             rejected += 1
-            if h < 1e-14:
-                return X, steps, dict(t=t, rejected=rejected, energy_start=I_start, energy_end=I0,
-                                      grad0=g0, grad=gn)
-        X, I0, t, steps = Y, I1, t + h, steps + 1
-        dt = 2.0 * h
-    G = energy_gradient(X, elems, M)
-    gn = float(np.linalg.norm(motion_basis(X, bnd, boundary).T @ G.ravel()))
+            if h < 1e-14 or h < 1e-6 * h_max:
+                return X, steps, dict(t=t, rejected=rejected, energy_start=I_start, energy_end=I0, grad0=g0,
+                                      grad=gn)
+        X, I0, G, M, loc, t, steps = Y, I1, G1, M1, loc1, t + h, steps + 1
+        h_max = max(h_max, h)
+        gn = float(np.linalg.norm(motion_basis(X, bnd, boundary).T @ G.ravel())) if G is not None else math.inf
+        if fixed_dt <= 0:
+            dt = 2.0 * h
     return X, steps, dict(t=t, rejected=rejected, energy_start=I_start, energy_end=I0, grad0=g0, grad=gn)
 
 
 # ---------------------------------------------------------------- Algorithm amGoFD
 
 
+def level_metric(X, elems, u, rings=None):
+    """(vertex metrics N_v x 2 x 2, alpha_h) of one adaptation level: vertex Hessians, alpha_h from the
+    element Hessians, eq. MK-1 at the vertices."""
+    Hv = vertex_hessians(X, elems, u, rings)
+    alpha = alpha_h(abs_sym(element_hessians(elems, Hv)), element_areas(X, elems))
+    return metric(abs_sym(Hv), alpha), alpha
+
+
 def adapt(X, elems, solve_on, levels=5, tau=1e-2, max_steps=400):
     """Algorithm amGoFD: for each level, u = solve_on(X) on the current mesh, then a new mesh from the
-    MMPDE method driven by u (the metric of eq. MK-1 from the recovered Hessian).  Returns the list of
-    (X, u) of every level; the connectivity never changes."""
+    MMPDE method driven by u.  Returns the list of (X, u) of every level; the connectivity never changes."""
     X = np.array(X, dtype=np.float64)
     elems = np.asarray(elems)
     bnd = boundary_mask(elems, X.shape[0])
@@ -397,7 +524,6 @@ def adapt(X, elems, solve_on, levels=5, tau=1e-2, max_steps=400):
     for _ in range(levels):
         u = solve_on(X)
         out.append((X.copy(), u))
-        A = abs_sym(element_hessians(elems, vertex_hessians(X, elems, u, rings)))
-        M = metric(A, alpha_h(A, element_areas(X, elems)))
-        X, _, _ = move_mesh(X, elems, M, bnd, tau=tau, max_steps=max_steps)
+        Mv, _ = level_metric(X, elems, u, rings)
+        X, _, _ = move_mesh(X, elems, Mv, bnd, tau=tau, max_steps=max_steps)
     return out
