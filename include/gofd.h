@@ -451,6 +451,124 @@ int gofd_cg_tape_read(gofd_ctx ctx, gofd_cg_tape tape, int j, double* x_dev, dou
                       double* scalars_host);
 int gofd_cg_tape_free(gofd_cg_tape tape);
 
+/* ---------------------------------------------------------------- mesh adaptation (MMPDE), 2D */
+
+/* Algorithm amGoFD of Section 4 moves the vertices of the triangulation
+ * towards a mesh equidistributed in the metric of eq. MK-1 built from the
+ * recovered Hessian of the current solution, by the moving mesh equations
+ * (eqs. x-1, mmpde-1) applied to the energy of eq. I-h; the connectivity
+ * never changes.  The GoFD solve on each new mesh goes through
+ * gofd_build_transfer / gofd_solve as for any other mesh.
+ *
+ * Layout: X (N_v x 2 doubles, row-major), u (N_v doubles), elements
+ * (N_e x 3 int32, vertex indices, counter-clockwise), vertex metrics Mv
+ * (N_v x 3 doubles: m11, m12, m22 of the symmetric 2 x 2 tensor), element
+ * metrics M_K (N_e x 3, same order), vertex Hessians (N_v x 3, same order).
+ * All on the device.
+ * The metric is a field of position: the piecewise-linear interpolant of
+ * the vertex metrics on a background mesh Xb (for a move, the mesh it
+ * starts from).  M_K is its value at the current centroid of K, located in
+ * the background mesh by a walk across the edge opposite the most negative
+ * barycentric coordinate (at most 4096 moves; beyond a boundary edge the
+ * value is extrapolated from that edge's element).
+ * Boundary vertices are those on an edge owned by one element.  With
+ * GOFD_MMPDE_BOUNDARY_CIRCLE they slide along the unit circle (the normal
+ * component of their velocity is removed and each step puts them back on
+ * it), with GOFD_MMPDE_BOUNDARY_FIXED they stay where they are.
+ * Sums over the elements around a vertex run in element order, and every
+ * reduction in a fixed order, so every result is reproducible bit for bit.
+ * Calls on one handle must not overlap. */
+typedef struct gofd_mmpde_s* gofd_mmpde;
+
+enum { GOFD_MMPDE_BOUNDARY_CIRCLE = 0, GOFD_MMPDE_BOUNDARY_FIXED = 1 };
+
+typedef struct {
+  double tau;        /* time scale of eq. x-1 (0: 1e-2)                                          */
+  double t_end;      /* integrate over (0, t_end] (0: 1)                                           */
+  double dt0;        /* first trial step (0: 1e-3)                                                 */
+  int max_steps;     /* accepted steps at most (0: 400)                                            */
+  double fixed_dt;   /* > 0: exactly max_steps steps of this length with no step control           */
+  double gtol;       /* stop once |P grad I_h| <= gtol |P grad I_h(x_start)| (0: 1e-6)             */
+  double cg_tol;     /* relative residual of each step's conjugate-gradient solve (0: 1e-10)      */
+  int max_cg;        /* iterations of each solve at most (0: 20000)                               */
+} gofd_mmpde_opts;
+
+typedef struct {
+  int steps;              /* accepted steps                                                    */
+  int rejected;           /* halvings of the step                                              */
+  double t;               /* time reached                                                      */
+  double energy_start;    /* I_h at the mesh given                                             */
+  double energy_end;      /* I_h at the mesh returned                                          */
+  int64_t cg_iterations;  /* conjugate-gradient iterations over all trial steps                */
+  double grad_start;      /* |P grad I_h| at the mesh given (P: projection onto allowed motions) */
+  double grad_end;        /* |P grad I_h| at the mesh returned                                 */
+} gofd_mmpde_info;
+
+/* Topology of the mesh: vertex two-rings, the elements around every vertex,
+ * element neighbours and the boundary vertices, built on the host from
+ * elems_dev (N_e x 3 int32, copied; every index in [0, N_v)).  *out is
+ * library-owned, freed with gofd_mmpde_free.  Synchronises.
+ * Errors: GOFD_E_ARG (N_v < 3, N_e < 1, an index out of range, a vertex in
+ * no element, unknown boundary mode), GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_mmpde_create(gofd_ctx ctx, int64_t nv, int64_t ne, const int32_t* elems_dev, int boundary,
+                      gofd_mmpde* out);
+int gofd_mmpde_free(gofd_mmpde mm);
+
+/* Vertex metrics of eq. MK-1 for u_dev on the mesh X_dev: the vertex Hessian
+ * is that of the least-squares quadratic through u at the vertex's two-ring
+ * (written to hess_dev when it is not NULL; a two-ring on which quadratics
+ * are not unisolvent gives a zero Hessian), H_K the mean of its vertices'
+ * Hessians, |H| = sqrt(H^2), alpha_h the root of sum_K |K| det(I + |H_K| /
+ * alpha)^{1/3} = 2 |Omega| (bisection in log alpha to relative width 1e-15),
+ * and M_i = det(I + |H_i| / alpha_h)^{-1/6} (I + |H_i| / alpha_h); when every
+ * H_K vanishes alpha_h = +inf and M_i = I.  Writes Mv_dev (N_v x 3) and, when
+ * alpha_host is not NULL, alpha_h.  Synchronises.
+ * Errors: GOFD_E_ARG, GOFD_E_DEGENERATE (the elements' areas do not sum to a
+ * positive value), GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_mmpde_metric(gofd_ctx ctx, gofd_mmpde mm, const double* X_dev, const double* u_dev, double* Mv_dev,
+                      double* hess_dev, double* alpha_host);
+
+/* I_h of eq. I-h for the mesh X_dev in the metric field of (Xb_dev, Mv_dev)
+ * (walks start at each element's own index in the background mesh):
+ * energy_host (nullable; +inf when an element has non-positive area), its
+ * gradient dI_h/dx_i including the metric's variation (grad_dev, N_v x 2,
+ * nullable; no boundary rule) and the element metrics M_K (MK_dev, N_e x 3,
+ * nullable).  Synchronises. Errors: GOFD_E_ARG, GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_mmpde_energy(gofd_ctx ctx, gofd_mmpde mm, const double* Xb_dev, const double* Mv_dev, const double* X_dev,
+                      double* grad_dev, double* MK_dev, double* energy_host);
+
+/* Hessians of the elements' terms of I_h for the element metrics MK_dev held
+ * fixed, with respect to their six vertex coordinates (x_0, y_0, x_1, y_1,
+ * x_2, y_2), by central differences of the analytic element gradient with
+ * the step 1e-5 times the element's longest edge, symmetrised: hess_dev is
+ * N_e x 36 doubles (row-major 6 x 6 per element).  Asynchronous.
+ * Errors: GOFD_E_ARG, GOFD_E_HIP. */
+int gofd_mmpde_element_hessians(gofd_ctx ctx, gofd_mmpde mm, const double* X_dev, const double* MK_dev,
+                                double* hess_dev);
+
+/* Integrates eq. x-1, dx_i/dt = -sqrt(det M(x_i)) / tau dI_h/dx_i, with
+ * Mv_dev the vertex metrics of the mesh X_dev given (its field on that mesh
+ * for the whole move, sqrt(det M(x_i)) from Mv), in place on X_dev.  The
+ * system is stiff; it is integrated by linearly implicit steps of length h:
+ *     P (tau/h Q^{-1} + J) P dx = -P dI_h/dx,   Q = diag(sqrt(det M(x_i))),
+ * P the projection onto the allowed motions, J the sum of the element
+ * Hessians of gofd_mmpde_element_hessians for the current M_K, solved by
+ * conjugate gradients with the vertices' 2 x 2 blocks as preconditioner.  A
+ * trial step is halved until the solve converges with positive curvature
+ * throughout, no element inverts and I_h decreases; the next trial step is
+ * twice the accepted one.  Stops at t_end, after max_steps accepted steps,
+ * once the projected gradient has fallen to gtol of its initial norm (the
+ * flow is at rest), or when no step of at least 1e-6 times the longest
+ * accepted one (and 1e-14) decreases I_h.  With opts->fixed_dt > 0 it takes
+ * exactly max_steps steps of that length, with no energy test and no
+ * gradient stop.  opts and info (host) are nullable.  Synchronises every 8
+ * solver iterations and after every trial step.
+ * Errors: GOFD_E_ARG, GOFD_E_DEGENERATE (the mesh given has an inverted
+ * element), GOFD_E_BREAKDOWN (fixed_dt: a step system was not positive
+ * definite), GOFD_E_HIP, GOFD_E_OOM. */
+int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde mm, double* X_dev, const double* Mv_dev, const gofd_mmpde_opts* opts,
+                    gofd_mmpde_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,18 @@ class CgTapeInfo(ctypes.Structure):
                 ("converged", ctypes.c_int)]
 
 
+class MmpdeOpts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("t_end", ctypes.c_double), ("dt0", ctypes.c_double),
+                ("max_steps", ctypes.c_int), ("fixed_dt", ctypes.c_double), ("gtol", ctypes.c_double),
+                ("cg_tol", ctypes.c_double), ("max_cg", ctypes.c_int)]
+
+
+class MmpdeInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("rejected", ctypes.c_int), ("t", ctypes.c_double),
+                ("energy_start", ctypes.c_double), ("energy_end", ctypes.c_double),
+                ("cg_iterations", ctypes.c_int64), ("grad_start", ctypes.c_double), ("grad_end", ctypes.c_double)]
+
+
 class FdwOpts(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int64), ("richardson", ctypes.c_int)]
 
@@ -128,6 +140,12 @@ def _load():
         "gofd_cg_tape_free": [vp],
         "gofd_autotune": [vp, ctypes.POINTER(_Grid), i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
         "gofd_set_schedule": [vp, ctypes.POINTER(_Grid), i32, i32],
+        "gofd_mmpde_create": [vp, i64, i64, vp, i32, ctypes.POINTER(vp)],
+        "gofd_mmpde_free": [vp],
+        "gofd_mmpde_metric": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl)],
+        "gofd_mmpde_energy": [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl)],
+        "gofd_mmpde_element_hessians": [vp, vp, vp, vp, vp],
+        "gofd_mmpde_move": [vp, vp, vp, vp, ctypes.POINTER(MmpdeOpts), ctypes.POINTER(MmpdeInfo)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -151,6 +169,8 @@ EXPORTED = [
     "gofd_solve", "gofd_solve_batched",
     "gofd_solve_adjoint", "gofd_time_kernel", "gofd_cg_checkpointed", "gofd_cg_unrolled_grad",
     "gofd_cg_tape_read", "gofd_cg_tape_free",
+    "gofd_mmpde_create", "gofd_mmpde_free", "gofd_mmpde_metric", "gofd_mmpde_energy",
+    "gofd_mmpde_element_hessians", "gofd_mmpde_move",
 ]
 
 K_PASS_A, K_PASS_B, K_PASS_C, K_SCATTER, K_GATHER = 0, 1, 2, 3, 4
@@ -475,6 +495,88 @@ class CgTape:
     def close(self):
         if getattr(self, "handle", None):
             lib.gofd_cg_tape_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MMPDE_BOUNDARY_CIRCLE, MMPDE_BOUNDARY_FIXED = 0, 1
+
+
+class Mmpde:
+    """MMPDE mesh adaptation on a fixed triangulation (Section 4): vertex metrics of eq. MK-1 from a solution,
+    the energy of eq. I-h in the metric field of a background mesh and its gradient, and the moving mesh
+    equations (eq. x-1) integrated in place.  Metrics are N x 3 (m11, m12, m22), coordinates N_v x 2, all
+    float64 on the device."""
+
+    def __init__(self, ctx: Context, nv, elems, boundary=MMPDE_BOUNDARY_CIRCLE):
+        torch = ctx._torch
+        if elems.dtype != torch.int32 or not elems.is_cuda:
+            raise TypeError("elems must be a CUDA int32 tensor")
+        elems = elems.contiguous()
+        self.ctx, self.nv, self.ne = ctx, int(nv), int(elems.shape[0])
+        h = ctypes.c_void_p()
+        ctx.check(lib.gofd_mmpde_create(ctx.handle, self.nv, self.ne, _ptr(elems), int(boundary), ctypes.byref(h)))
+        self.handle = h
+
+    def _x(self, X):
+        torch = self.ctx._torch
+        if X.dtype != torch.float64 or not X.is_cuda or tuple(X.shape) != (self.nv, 2):
+            raise TypeError("X must be a CUDA float64 tensor of shape (N_v, 2)")
+        return X.contiguous()
+
+    def metric(self, X, u, with_hessian=False):
+        """(vertex metrics Mv, alpha_h[, vertex Hessians N_v x 3])."""
+        torch = self.ctx._torch
+        X = self._x(X)
+        M = torch.empty(self.nv, 3, dtype=torch.float64, device=X.device)
+        H = torch.empty(self.nv, 3, dtype=torch.float64, device=X.device) if with_hessian else None
+        a = ctypes.c_double()
+        self.ctx.check(lib.gofd_mmpde_metric(self.ctx.handle, self.handle, _ptr(X), _ptr(u.contiguous()), _ptr(M),
+                                             _ptr(H) if H is not None else None, ctypes.byref(a)))
+        return (M, a.value, H) if with_hessian else (M, a.value)
+
+    def energy(self, Xb, Mv, X, grad=True):
+        """(I_h, dI_h/dX or None, element metrics M_K) of the mesh X in the metric field of (Xb, Mv)."""
+        torch = self.ctx._torch
+        Xb, X = self._x(Xb), self._x(X)
+        G = torch.empty(self.nv, 2, dtype=torch.float64, device=X.device) if grad else None
+        MK = torch.empty(self.ne, 3, dtype=torch.float64, device=X.device)
+        e = ctypes.c_double()
+        self.ctx.check(lib.gofd_mmpde_energy(self.ctx.handle, self.handle, _ptr(Xb), _ptr(Mv.contiguous()), _ptr(X),
+                                             _ptr(G) if G is not None else None, _ptr(MK), ctypes.byref(e)))
+        return e.value, G, MK
+
+    def element_hessians(self, X, MK):
+        """N_e x 6 x 6 Hessians of the elements' terms of I_h for the element metrics MK (central differences,
+        symmetrised)."""
+        torch = self.ctx._torch
+        X = self._x(X)
+        H = torch.empty(self.ne, 6, 6, dtype=torch.float64, device=X.device)
+        self.ctx.check(lib.gofd_mmpde_element_hessians(self.ctx.handle, self.handle, _ptr(X), _ptr(MK.contiguous()),
+                                                       _ptr(H)))
+        return H
+
+    def move(self, X, Mv, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, fixed_dt=0.0, gtol=1e-6, cg_tol=1e-10,
+             max_cg=20000):
+        """Moves X (contiguous, modified in place) by eq. x-1 for its vertex metrics Mv; returns the info dict."""
+        if not X.is_contiguous():
+            raise TypeError("X must be contiguous (it is moved in place)")
+        self._x(X)
+        o = MmpdeOpts(float(tau), float(t_end), float(dt0), int(max_steps), float(fixed_dt), float(gtol),
+                      float(cg_tol), int(max_cg))
+        info = MmpdeInfo()
+        self.ctx.check(lib.gofd_mmpde_move(self.ctx.handle, self.handle, _ptr(X), _ptr(Mv.contiguous()),
+                                           ctypes.byref(o), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in MmpdeInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gofd_mmpde_free(self.handle)
             self.handle = None
 
     def __del__(self):
