@@ -60,6 +60,23 @@ def _kernel_bytes(W, L, tr, m, b, precond):
     }
 
 
+def _transfer_kernel_bytes(d, nv, ne, n_nodes, n_inside, nnz):
+    """Algorithmic HBM bytes of each stage of the transfer build (2D records of 48 bytes, 3D of 112)."""
+    rec = 48 if d == 2 else 112
+    X = 8 * d * nv
+    return {
+        "records": 4 * (d + 1) * ne + X + rec * ne,                       # elements, coordinates in; records out
+        "locate": 4 * (d + 1) * ne + X + 4 * n_inside,                    # elements, coordinates; one node write each
+        "count": 4 * n_nodes + 4 * (d + 1) * n_inside + 4 * nnz,         # node elements, their vertices; counts
+        "scan": 8 * (nv + 1),                                             # counts in, offsets out
+        "fill": 4 * n_nodes + rec * n_inside + 4 * nnz + 12 * nnz,       # node elements, records; cursors; entries
+        "sort": 4 * (nv + 1) + 24 * nnz,                                  # offsets; entries in and out
+        "rows": 4 * n_nodes + rec * n_inside + (24 if d == 2 else 48) * n_nodes,  # node rows out
+        "colsum": 4 * (nv + 1) + 8 * nnz + nv + 32 * nv + 4 * nnz,        # offsets, weights, flags; D and scalings,
+                                                                          # FP32 weights out
+    }
+
+
 def _traffic(stage):
     """HBM bytes per launch of the stage's kernel from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy of known size),
@@ -222,10 +239,181 @@ def run_c4(args):
     print(json.dumps(line), flush=True)
 
 
+def _mmpde_kernel_bytes(nv, ne, nbnd):
+    """Algorithmic HBM bytes per launch of each MMPDE kernel (every array the kernel must touch, once)."""
+    vec = 16 * nv                        # one vertex vector (x, y doubles)
+    return {
+        "hess_fd": 12 * ne + vec + 24 * ne + 288 * ne,            # elements, X, M_K in; 36 doubles out
+        "field": 12 * ne + 16 * nv + 12 * ne + 16 * nv + 24 * nv + 48 * ne + 4 * ne + 4 * ne + 24 * ne + 48 * ne,
+        # elements, X; one background element and its vertices, vertex metrics, component gradients; locations
+        # in and out; M_K and gradients out
+        "energy": 12 * ne + vec + 24 * ne,                         # elements, X, M_K in (partials are negligible)
+        "cg_elem": 12 * ne + 288 * ne + vec + 48 * ne,             # elements, Hessians, p in; 6 values out
+        "cg_vert": 4 * (nv + 1) + 12 * ne + 48 * ne + 8 * nv + vec + vec + nbnd + vec,
+        # offsets, corner lists, element products, q, p, X, boundary flags in; w out
+        "cg_update": 2 * vec + 2 * vec + vec + vec + vec + 24 * nv + 8 * nv + vec + nbnd,
+        # dx and r read and written, z written, p and w read, diagonal blocks, q, X, flags
+        "cg_dir": vec + 2 * vec,                                   # z read, p read and written
+    }
+
+
+def run_amgofd(args):
+    """Algorithm amGoFD (Section 4) on the unit disk, Example 1 with s = 0.5, k = 0 (f and the exact solution in
+    closed form): 11,573 triangles (the paper shows adaptive meshes of 11,886).  One step = the algorithm with
+    l_max = 5 from the initial mesh: on each level the overlay grid (R = 1.1, h_FD <= a_h), the transfer, T, the
+    GoFD solve (FP64, D_h preconditioner, tol 1e-10), the vertex metrics and the MMPDE move; then the solve on the
+    final mesh.  Inputs (the initial mesh and its f) are resident in device memory before the timed region."""
+    import numpy as np
+    import torch
+    import paper_2307_14437_amd as gofd
+    from oracle import exact, grid as ogrid, mmpde
+    from workloads import disk_mesh, grid_for_box
+    s, levels = 0.5, 5
+    mesh = disk_mesh(seed=1001, n_boundary=251, spacing=0.025)
+    ctx = gofd.Context()
+    elems = torch.tensor(mesh.elems, dtype=torch.int32, device="cuda")
+    X0 = torch.tensor(mesh.X, device="cuda")
+    mm = gofd.Mmpde(ctx, mesh.nv, elems)
+    bnd = mmpde.boundary_mask(mesh.elems, mesh.nv)
+
+    def min_height(X):
+        P = X[mesh.elems]
+        e1, e2 = P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]
+        area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+        edge = np.max(np.stack([np.linalg.norm(P[:, a] - P[:, (a + 1) % 3], axis=1) for a in range(3)], 1), 1)
+        return float(np.min(2 * area / edge))
+
+    fcache = {}
+
+    def f_grid(N):
+        # the right-hand side on each level's grid: computed once per grid size, outside the timed region
+        if N not in fcache:
+            g = grid_for_box(2, 2 * N, R=1.1)
+            fcache[N] = (g, torch.tensor(exact.f_ball(ogrid.node_coords(2, g.N, g.R, g.center), s, 2, 0)
+                                         .reshape(g.W, g.W), device="cuda"))
+        return fcache[N]
+
+    def one(X, record=None, stats=False):
+        """The algorithm from X (moved in place); returns the solutions and grid sizes of every level."""
+        out = []
+        for lvl in range(levels + 1):
+            t0 = time.perf_counter()
+            Xh = X.cpu().numpy()
+            N = min(1024, int(np.ceil(1.1 / min_height(Xh))))
+            g, f = f_grid(N)
+            t1 = time.perf_counter()
+            tr = gofd.Transfer(ctx, X, elems, g)
+            op = gofd.FdOp(ctx, s, g)
+            pc = gofd.Precond(ctx, tr, op, "DIAG")
+            _sync(); t2 = time.perf_counter()
+            u, info = gofd.solve(ctx, tr, op, f, tol=1e-10, pc=pc)
+            _sync(); t3 = time.perf_counter()
+            rec = {"N": N, "solve_iterations": info[0]["iterations"], "host_grid_choice_ms": (t1 - t0) * 1e3,
+                   "setup_ms": (t2 - t1) * 1e3, "solve_ms": (t3 - t2) * 1e3}
+            out.append((Xh, u.cpu().numpy()))
+            if lvl < levels:
+                Mv, alpha = mm.metric(X, u)
+                _sync(); t4 = time.perf_counter()
+                mi = mm.move(X, Mv, kernel_stats=stats)
+                _sync(); t5 = time.perf_counter()
+                rec.update({"metric_ms": (t4 - t3) * 1e3, "move_ms": (t5 - t4) * 1e3, "move_steps": mi["steps"],
+                            "move_rejected": mi["rejected"], "move_cg_iterations": mi["cg_iterations"],
+                            "move_grad_drop": mi["grad_end"] / mi["grad_start"]})
+                if stats:
+                    rec["kernels"] = mi["kernels"]
+            if record is not None:
+                record.append(rec)
+        return out
+
+    # warm-up pass with kernel timing (also fills the right-hand sides of every grid size used)
+    recs_w = []
+    for _ in range(max(1, args.warmup)):
+        recs_w = []
+        one(X0.clone(), recs_w, stats=True)
+    _sync(); t = time.perf_counter()
+    recs = []
+    for k in range(args.steps):
+        recs = []
+        sols = one(X0.clone(), recs)
+    _sync()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    errs = [exact.l2_error(Xh, mesh.elems, uh - exact.u_ball(Xh, s, 2, 0)) /
+            exact.l2_error(Xh, mesh.elems, exact.u_ball(Xh, s, 2, 0)) for Xh, uh in sols]
+    # dominant MMPDE kernel: the largest mean duration x launches over the warm-up pass's moves
+    kb = _mmpde_kernel_bytes(mesh.nv, mesh.ne, int(bnd.sum()))
+    tot = {n: 0.0 for n in gofd.MMPDE_KERNELS}
+    avg = {n: [] for n in gofd.MMPDE_KERNELS}
+    for r in recs_w:
+        for n, (us, cnt) in r.get("kernels", {}).items():
+            tot[n] += us * cnt
+            avg[n].append(us)
+    dom = max(tot, key=tot.get)
+    dom_us = float(np.mean(avg[dom]))
+    achieved = kb[dom] / (dom_us * 1e-6) / 1e9
+    kernels = {n: {"mean_us": float(np.mean(avg[n])), "launches": int(sum(r["kernels"][n][1] for r in recs_w
+                                                                             if "kernels" in r)),
+                   "algorithmic_bytes": kb[n], "share_of_kernel_time": tot[n] / sum(tot.values())}
+               for n in gofd.MMPDE_KERNELS}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = mmpde_cpu_baseline(mesh, s, recs)
+    line = {
+        "metric": "amGoFD adaptation levels/s (GoFD solve + metric + MMPDE move)", "value": levels / (ms * 1e-3),
+        "unit": "levels/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Algorithm amGoFD, l_max = 5, unit disk (Example 1: s = 0.5, k = 0), "
+                               f"{mesh.nv} vertices, {mesh.ne} triangles, grid R = 1.1, h_FD <= a_h (N <= 1024)",
+                   "levels": levels},
+        "rel_l2_error_fixed_mesh": errs[0], "rel_l2_error_adaptive": errs[-1], "rel_l2_error_per_level": errs,
+        "levels_detail": recs,
+        "roofline": {"bound": "hbm", "kernel": f"mmpde {dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "per_launch_us": dom_us, "algorithmic_bytes": kb[dom]},
+        "mmpde_kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def mmpde_cpu_baseline(mesh, s, recs):
+    """The oracle's pieces of one adaptation level timed once each on the initial mesh (metric with the exact
+    solution's vertex Hessians; the field energy and gradient, the element Hessians and assembly, one implicit
+    step solve by dense Cholesky) and composed into one level with the GPU's accepted and trial steps per level:
+    steps x (Hessians + gradient) + trials x (solve + energy).  The oracle's GoFD solve is not included (a lower
+    bound on the oracle's time per level)."""
+    import numpy as np
+    from oracle import exact, mmpde
+    X, el = mesh.X, mesh.elems
+    bnd = mmpde.boundary_mask(el, mesh.nv)
+    t = time.perf_counter()
+    Mv, _ = mmpde.level_metric(X, el, exact.u_ball(X, s, 2, 0))
+    t_metric = time.perf_counter() - t
+    field = mmpde.MetricField(X, el, Mv)
+    t = time.perf_counter()
+    _, G, M, loc = mmpde.energy_field(X, el, field, np.arange(mesh.ne))
+    t_energy = time.perf_counter() - t
+    t = time.perf_counter()
+    J = mmpde.assemble_hessian(el, mmpde.element_hessians_fd(X, el, M), mesh.nv)
+    t_hess = time.perf_counter() - t
+    t = time.perf_counter()
+    mmpde.implicit_step(X, bnd, np.sqrt(np.linalg.det(Mv)), 1e-7, G, J)
+    t_solve = time.perf_counter() - t
+    moved = [r for r in recs if "move_steps" in r]
+    steps = float(np.mean([r["move_steps"] for r in moved]))
+    trials = float(np.mean([r["move_steps"] + r["move_rejected"] for r in moved]))
+    s_level = t_metric + steps * (t_hess + t_energy) + trials * (t_solve + t_energy)
+    return {"value": 1.0 / s_level, "unit": "levels/s", "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "sample": f"oracle pieces on the initial mesh, each once: metric {t_metric:.2f} s, field energy and "
+                      f"gradient {t_energy:.2f} s, element Hessians {t_hess:.2f} s, one implicit step (dense "
+                      f"Cholesky) {t_solve:.2f} s; composed with the GPU's {steps:.0f} steps and {trials:.0f} trials "
+                      "per level; the oracle's GoFD solve not included"}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
-                    help="c2: the L-shape workload (default); c4: the 64-mesh batched workload")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "amgofd"],
+                    help="c2: the L-shape workload (default); c4: the 64-mesh batched workload; amgofd: Algorithm "
+                         "amGoFD (MMPDE adaptation) on the disk")
     ap.add_argument("--c4-tol", type=float, default=1e-9, help="c4: relative residual of the timed solves")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -240,6 +428,8 @@ def main():
                     help="comma-separated preconditioners timed beside plain CG on the same step ('' for none)")
     ap.add_argument("--col-schedule", type=int, default=-1,
                     help="column-pass schedule for both precisions instead of tuning it (counter runs)")
+    ap.add_argument("--row-schedule", type=int, default=0, choices=[0, 8, 16],
+                    help="with --col-schedule: values per thread of the first row pass (0: the library default)")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -256,6 +446,9 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         run_c4(args)
+        return
+    if args.workload == "amgofd":
+        run_amgofd(args)
         return
 
     import numpy as np
@@ -289,8 +482,10 @@ def main():
     sched = {}
     for fp32 in (True, False):
         if args.col_schedule >= 0:
-            r = {"col": args.col_schedule, "row": 0, "times": None}
+            r = {"col": args.col_schedule, "row": args.row_schedule, "times": None}
             gofd.set_schedule(ctx, g, args.col_schedule, fp32=fp32)
+            if args.row_schedule:
+                gofd.set_schedule(ctx, g, args.row_schedule, fp32=fp32, rows=True)
         else:
             r = gofd.autotune_all(ctx, g, fp32=fp32)
         us_ = [None if x is None else round(x * 1e3, 2) for x in (r["times"] or [])]
@@ -411,6 +606,11 @@ def main():
     achieved = kernels[dom]["GBs"]
     traffic = _traffic(dom)
 
+    # the transfer build (point location, weights, vertex-major structure, column sums): event times per stage
+    tb = _transfer_kernel_bytes(2, tr.nv, tr.ne, tr.info["n_nodes"], tr.info["n_inside"], tr.info["nnz"])
+    transfer_kernels = {k: {"us": us, "bytes": tb[k], "GBs": tb[k] / (us * 1e-6) / 1e9 if us > 0 else None,
+                            "frac": tb[k] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS if us > 0 else None}
+                        for k, us in tr.info["kernel_us"].items()}
     its64 = {s: info64[i]["iterations"] for i, s in enumerate(svals)}
     line = {
         "metric": "PCG solves/s + A_h matvec Gpts/s, batched FP32+refine vs plain FP64 @1e-8",
@@ -446,6 +646,7 @@ def main():
         "matvec_us": {k: v * 1e3 for k, v in mv.items()},
         "kernels_fp32": kernels,
         "setup_ms": setup,
+        "transfer_kernels": transfer_kernels,
         "roofline": {"bound": "hbm", "kernel": f"{dom} (fp32)", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": kernels[dom]["bytes"]},

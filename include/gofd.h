@@ -115,7 +115,21 @@ typedef struct {
   int64_t rp_entries;       /* 2D: stored entries of that form (with per-thread padding)  */
   int64_t rp_seg_rows;      /* 2D: 1 if the per-node segment rows of the FP32 gather      */
                             /* through the row-pair slots were built, else 0              */
+  double kernel_us[8];      /* device time of the build's stages (GOFD_TR_K_*), from HIP  */
+                            /* events at each kernel's start and end (the scan: around it) */
 } gofd_transfer_info;
+
+/* Stages of gofd_build_transfer timed in gofd_transfer_info.kernel_us. */
+enum {
+  GOFD_TR_K_RECORDS = 0,  /* per element: vertex 0 and the barycentric gradients              */
+  GOFD_TR_K_LOCATE = 1,   /* point location: each element's bounding box, exact orientation  */
+  GOFD_TR_K_COUNT = 2,    /* entries per vertex                                                */
+  GOFD_TR_K_SCAN = 3,     /* column offsets (exclusive scan)                                   */
+  GOFD_TR_K_FILL = 4,     /* barycentric weights into the vertex-major structure               */
+  GOFD_TR_K_SORT = 5,     /* each vertex's entries in ascending node order                     */
+  GOFD_TR_K_ROWS = 6,     /* node-major rows of the gather (2D FP32 rows, 3D rows)             */
+  GOFD_TR_K_COLSUM = 7    /* column sums D and the scalings                                    */
+};
 
 /* Build I_h^FD, its transpose structure and D_h (Section 3.1, eqs. interp-1 to
  * IhFD-1; D_h after eq. Ah-1 and Lemma IhFD-1(iv)).
@@ -482,6 +496,25 @@ typedef struct gofd_mmpde_s* gofd_mmpde;
 
 enum { GOFD_MMPDE_BOUNDARY_CIRCLE = 0, GOFD_MMPDE_BOUNDARY_FIXED = 1 };
 
+/* Kernels of a move, for gofd_mmpde_kernel_stats. */
+enum {
+  GOFD_MMPDE_K_HESS = 0,      /* element Hessians by differences (once per step)                   */
+  GOFD_MMPDE_K_FIELD = 1,     /* metric at the centroids (walks; once per trial)                     */
+  GOFD_MMPDE_K_ENERGY = 2,    /* energy partials and inversion test (once per trial)                 */
+  GOFD_MMPDE_K_CG_ELEM = 3,   /* CG: element Hessians times the direction                            */
+  GOFD_MMPDE_K_CG_VERT = 4,   /* CG: vertex sums, shift, projection, (p, w) partials                 */
+  GOFD_MMPDE_K_CG_UPDATE = 5, /* CG: alpha, x, r, preconditioner, partials                           */
+  GOFD_MMPDE_K_CG_DIR = 6,    /* CG: convergence test, beta, direction                               */
+  GOFD_MMPDE_N_KERNELS = 7
+};
+
+typedef struct {
+  double avg_us[GOFD_MMPDE_N_KERNELS];    /* mean duration of the first (up to 32) launches, from HIP
+                                             events recorded at each launch's start and end           */
+  int64_t launches[GOFD_MMPDE_N_KERNELS]; /* launches of the move (CG kernels launched past a solve's
+                                             end return at once and count too)                         */
+} gofd_mmpde_kernel_stats;
+
 typedef struct {
   double tau;        /* time scale of eq. x-1 (0: 1e-2)                                          */
   double t_end;      /* integrate over (0, t_end] (0: 1)                                           */
@@ -491,6 +524,7 @@ typedef struct {
   double gtol;       /* stop once |P grad I_h| <= gtol |P grad I_h(x_start)| (0: 1e-6)             */
   double cg_tol;     /* relative residual of each step's conjugate-gradient solve (0: 1e-10)      */
   int max_cg;        /* iterations of each solve at most (0: 20000)                               */
+  gofd_mmpde_kernel_stats* stats;  /* host, nullable: kernel timings of the move                    */
 } gofd_mmpde_opts;
 
 typedef struct {

@@ -55,7 +55,11 @@ class TransferInfo(ctypes.Structure):
                 ("n_interior", ctypes.c_int64), ("n_boundary", ctypes.c_int64),
                 ("dmin_interior", ctypes.c_double), ("a_h", ctypes.c_double), ("h_bound", ctypes.c_double),
                 ("exact_tests", ctypes.c_int64), ("max_col_count", ctypes.c_int64),
-                ("rp_slots", ctypes.c_int64), ("rp_entries", ctypes.c_int64), ("rp_seg_rows", ctypes.c_int64)]
+                ("rp_slots", ctypes.c_int64), ("rp_entries", ctypes.c_int64), ("rp_seg_rows", ctypes.c_int64),
+                ("kernel_us", ctypes.c_double * 8)]
+
+
+TRANSFER_KERNELS = ("records", "locate", "count", "scan", "fill", "sort", "rows", "colsum")
 
 
 class CgTapeInfo(ctypes.Structure):
@@ -63,10 +67,18 @@ class CgTapeInfo(ctypes.Structure):
                 ("converged", ctypes.c_int)]
 
 
+MMPDE_KERNELS = ("hess_fd", "field", "energy", "cg_elem", "cg_vert", "cg_update", "cg_dir")
+
+
+class MmpdeKernelStats(ctypes.Structure):
+    _fields_ = [("avg_us", ctypes.c_double * len(MMPDE_KERNELS)), ("launches", ctypes.c_int64 * len(MMPDE_KERNELS))]
+
+
 class MmpdeOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("t_end", ctypes.c_double), ("dt0", ctypes.c_double),
                 ("max_steps", ctypes.c_int), ("fixed_dt", ctypes.c_double), ("gtol", ctypes.c_double),
-                ("cg_tol", ctypes.c_double), ("max_cg", ctypes.c_int)]
+                ("cg_tol", ctypes.c_double), ("max_cg", ctypes.c_int),
+                ("stats", ctypes.POINTER(MmpdeKernelStats))]
 
 
 class MmpdeInfo(ctypes.Structure):
@@ -240,6 +252,7 @@ class Transfer:
                                           ctypes.byref(g), ctypes.byref(h), ctypes.byref(info)))
         self.handle = h
         self.info = {k: getattr(info, k) for k, _ in TransferInfo._fields_}
+        self.info["kernel_us"] = dict(zip(TRANSFER_KERNELS, list(info.kernel_us)))
 
     def export(self, part):
         torch = self.ctx._torch
@@ -562,17 +575,22 @@ class Mmpde:
         return H
 
     def move(self, X, Mv, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, fixed_dt=0.0, gtol=1e-6, cg_tol=1e-10,
-             max_cg=20000):
-        """Moves X (contiguous, modified in place) by eq. x-1 for its vertex metrics Mv; returns the info dict."""
+             max_cg=20000, kernel_stats=False):
+        """Moves X (contiguous, modified in place) by eq. x-1 for its vertex metrics Mv; returns the info dict
+        (with kernel_stats: also "kernels", name -> (mean us of the first launches, launches))."""
         if not X.is_contiguous():
             raise TypeError("X must be contiguous (it is moved in place)")
         self._x(X)
+        ks = MmpdeKernelStats() if kernel_stats else None
         o = MmpdeOpts(float(tau), float(t_end), float(dt0), int(max_steps), float(fixed_dt), float(gtol),
-                      float(cg_tol), int(max_cg))
+                      float(cg_tol), int(max_cg), ctypes.pointer(ks) if ks is not None else None)
         info = MmpdeInfo()
         self.ctx.check(lib.gofd_mmpde_move(self.ctx.handle, self.handle, _ptr(X), _ptr(Mv.contiguous()),
                                            ctypes.byref(o), ctypes.byref(info)))
-        return {k: getattr(info, k) for k, _ in MmpdeInfo._fields_}
+        out = {k: getattr(info, k) for k, _ in MmpdeInfo._fields_}
+        if ks is not None:
+            out["kernels"] = {n: (ks.avg_us[i], ks.launches[i]) for i, n in enumerate(MMPDE_KERNELS)}
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -664,7 +664,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
   tws.load(tw, t);
   // row-pair I^T: this thread's entries and the row pair's segment slots
   int4 meta = make_int4(0, 0, 0, 0);
-  int tseg = 0;
+  int tseg = 0, tcnt = 0, mlast = 0;
   int code[SCAT ? EPRE : 1];
   R wt[SCAT ? EPRE : 1];
   int dst[SCAT ? QD : 1];
@@ -681,11 +681,16 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
       meta.z = __builtin_amdgcn_readfirstlane(meta.z);
       meta.w = __builtin_amdgcn_readfirstlane(meta.w);
     }
-    tseg = gmem(I.rp_tseg)[(long long)rp * TPL + t];
-    // entries m < EPRE of this thread, read ahead past its count ENT (meta.y;
-    // the arrays carry RP_EPRE * TPL padding entries at the end, so the reads
-    // stay in range); the extra ones become padding (node 0, weight 0).  The
-    // launch picks EPRE from the count that covers most row pairs.
+    int tword = gmem(I.rp_tseg)[(long long)rp * TPL + t];
+    if (!has0) tword = 0;
+    tseg = tword & 0xffff;
+    tcnt = tword >> 16;
+    // entries m < EPRE of this thread, read ahead: a load past the thread's
+    // own count (its padding, up to the row pair's count meta.y, and beyond)
+    // re-reads its last entry, a line already fetched, and the value becomes
+    // padding (node 0, weight 0), as the stored padding is.  The launch picks
+    // EPRE from the count that covers most row pairs.
+    mlast = tcnt > 0 ? tcnt - 1 : 0;
     gcode = I.rp_code + meta.x + t;
     if constexpr (sizeof(R) == 4)
       gw = reinterpret_cast<const R*>(I.rp_w32) + meta.x + t;
@@ -695,14 +700,16 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
     // branch with one row pair per block)
 #pragma unroll
     for (int m = 0; m < EPRE / 2; ++m) {
-      code[m] = gmem(gcode)[m * TPL];
-      wt[m] = gmem(gw)[m * TPL];
+      const int mm = min(m, mlast);
+      code[m] = gmem(gcode)[mm * TPL];
+      wt[m] = gmem(gw)[mm * TPL];
     }
     if (LINES > 1 || meta.y > EPRE / 2) {
 #pragma unroll
       for (int m = EPRE / 2; m < EPRE; ++m) {
-        code[m] = gmem(gcode)[m * TPL];
-        wt[m] = gmem(gw)[m * TPL];
+        const int mm = min(m, mlast);
+        code[m] = gmem(gcode)[mm * TPL];
+        wt[m] = gmem(gw)[mm * TPL];
       }
     } else {
 #pragma unroll
@@ -713,7 +720,7 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
     }
 #pragma unroll
     for (int m = 0; m < EPRE; ++m)
-      if (m >= meta.y) {
+      if (m >= tcnt) {
         code[m] = 0;
         wt[m] = (R)0;
       }
@@ -759,8 +766,15 @@ __global__ __launch_bounds__(LINES*(L / E), (SCAT && LINES * (L / E) >= 256) ? (
       acc = end ? (R)0 : acc;
     }
     for (int m = EPRE; m < meta.y; ++m) {      // rows pairs with more entries per thread
-      const int c = gmem(gcode)[(long long)m * TPL];
-      acc = fma(gmem(gw)[(long long)m * TPL], yl[c & RP_NODE], acc);
+      const int mm = min(m, mlast);
+      const bool real = m < tcnt;
+      int c = gmem(gcode)[(long long)mm * TPL];
+      R wv = gmem(gw)[(long long)mm * TPL];
+      if (!real) {
+        c = 0;
+        wv = (R)0;
+      }
+      acc = fma(wv, yl[c & RP_NODE], acc);
       if (c & RP_END) {
         sg[j++] = acc;
         acc = 0;

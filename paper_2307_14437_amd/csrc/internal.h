@@ -174,7 +174,7 @@ struct gofd_transfer_s {
   int64_t n_slots = 0;  // partial sums: one per (vertex, row pair) with entries
   int rp_ent_ahead = 0;   // entries per thread that cover 90% of the row pairs (the last row pass reads them ahead)
   DevBuf rp_meta;    // int4[pairs]: entry base, entries per thread, segment base, segments
-  DevBuf rp_tseg;    // int32[pairs * threads]: first segment of each thread
+  DevBuf rp_tseg;    // int32[pairs * threads]: first segment of each thread | its entry count << 16
   DevBuf rp_code;    // uint16[...]: local node (2 rows) | end-of-segment flag, thread-interleaved
   DevBuf rp_w32;     // float[...]: weights (csc_w32 values), same layout
   DevBuf rp_w64;     // double[...]: weights (csc_w values)

@@ -774,6 +774,57 @@ __global__ void k_place(const double* __restrict__ X, const double* __restrict__
   Y[2 * i + 1] = y;
 }
 
+// kernel timing of a move: the first launches of each kernel record HIP events at their start and end
+struct KTimer {
+  static constexpr int SAMPLES = 32;
+  bool on = false;
+  hipEvent_t ev[GOFD_MMPDE_N_KERNELS][SAMPLES][2] = {};
+  int used[GOFD_MMPDE_N_KERNELS] = {};
+  long long launches[GOFD_MMPDE_N_KERNELS] = {};
+  ~KTimer() {
+    for (auto& k : ev)
+      for (auto& smp : k)
+        for (auto& e : smp)
+          if (e) (void)hipEventDestroy(e);
+  }
+  // events for the next launch of kernel k, or false
+  bool next(int k, hipEvent_t* a, hipEvent_t* b) {
+    ++launches[k];
+    if (!on || used[k] >= SAMPLES) return false;
+    hipEvent_t* p = ev[k][used[k]];
+    if (!p[0] && (hipEventCreate(&p[0]) != hipSuccess || hipEventCreate(&p[1]) != hipSuccess)) return false;
+    *a = p[0];
+    *b = p[1];
+    ++used[k];
+    return true;
+  }
+  void write(gofd_mmpde_kernel_stats* out) const {
+    for (int k = 0; k < GOFD_MMPDE_N_KERNELS; ++k) {
+      double sum = 0.0;
+      int n = 0;
+      for (int i = 0; i < used[k]; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[k][i][0], ev[k][i][1]) == hipSuccess) {
+          sum += ms;
+          ++n;
+        }
+      }
+      out->avg_us[k] = n ? sum * 1e3 / n : 0.0;
+      out->launches[k] = launches[k];
+    }
+  }
+};
+
+// launch, timed by the move's KTimer when it has events left for this kernel
+#define MM_LAUNCH(T, K, KERNEL, GRID, BLOCK, STREAM, ...)                                          \
+  do {                                                                                             \
+    hipEvent_t ea_, eb_;                                                                           \
+    if ((T) && (T)->next((K), &ea_, &eb_))                                                          \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, ea_, eb_, 0, __VA_ARGS__);             \
+    else                                                                                           \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                             \
+  } while (0)
+
 // scratch (doubles): Hv 3nv | aH 3ne | lam 2ne | area ne | alpha 1 | G 6ne | Hk 36ne | Jd 3nv | qv nv |
 // pg, dx, r, z, p, w, Y, Xb 2nv each | GMb 6ne | MK 2 x 3ne | GK 2 x 6ne | part 8 MNB | st 4 | out 2;
 // ints: loc 2 x ne
@@ -827,9 +878,11 @@ int scratch(gofd_ctx_s* ctx, gofd_mmpde_s* m, Scratch& s) {
 // blocks of the vertex reductions: a function of N_v only, so that the sums keep their order
 inline int vertex_blocks(long long nv) { return (int)std::min<long long>(MNB, grid1(nv, MB)); }
 
-int energy_check(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, const double* M, Scratch& s, double* host2) {
+int energy_check(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, const double* M, Scratch& s, double* host2,
+                 KTimer* T = nullptr) {
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_energy_check, dim3(MNB), dim3(MB), 0, st, X, m->elems.as<int>(), M, (long long)m->ne, s.part);
+  MM_LAUNCH(T, GOFD_MMPDE_K_ENERGY, k_energy_check, dim3(MNB), dim3(MB), st, X, m->elems.as<int>(), M,
+            (long long)m->ne, s.part);
   hipLaunchKernelGGL(k_finish2, dim3(1), dim3(MB), 0, st, s.part, MNB, s.out);
   HIP_TRY(ctx, hipMemcpyAsync(host2, s.out, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -855,7 +908,7 @@ int projected_gradient(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, const 
 
 // conjugate gradients on the step system of length h (Hk, Jd, qv, pg ready); *ok = converged, *its added
 int step_solve(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, Scratch& s, double tau, double h, double tol,
-               int max_cg, bool* ok, long long* its) {
+               int max_cg, bool* ok, long long* its, KTimer* T) {
   hipStream_t st = ctx->stream;
   const long long nv = m->nv, ne = m->ne;
   const int nb = vertex_blocks(nv);
@@ -870,13 +923,14 @@ int step_solve(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, Scratch& s, do
   double hs[3] = {0.0, 0.0, 0.0};
   for (int it = 0; it < max_cg; ++it) {
     const int cur = it & 1;
-    hipLaunchKernelGGL(k_cg_ap_elem, dim3(grid1(ne, MB)), dim3(MB), 0, st, m->elems.as<int>(), s.Hk, s.p, ne, s.st,
-                       s.G);
-    hipLaunchKernelGGL(k_cg_ap_vert, dim3(nb), dim3(MB), 0, st, S, m->ve_off.as<int>(), m->ve.as<int>(), s.G, s.p,
-                       s.st, s.w, ppw);
-    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(MB), 0, st, S, ppw, prz[cur], nb, s.st, s.dx, s.r, s.z, s.p,
-                       s.w, prz[cur ^ 1]);
-    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(MB), 0, st, nv, prz[cur], prz[cur ^ 1], nb, s.st, s.z, s.p);
+    MM_LAUNCH(T, GOFD_MMPDE_K_CG_ELEM, k_cg_ap_elem, dim3(grid1(ne, MB)), dim3(MB), st, m->elems.as<int>(), s.Hk,
+              s.p, ne, s.st, s.G);
+    MM_LAUNCH(T, GOFD_MMPDE_K_CG_VERT, k_cg_ap_vert, dim3(nb), dim3(MB), st, S, m->ve_off.as<int>(),
+              m->ve.as<int>(), s.G, s.p, s.st, s.w, ppw);
+    MM_LAUNCH(T, GOFD_MMPDE_K_CG_UPDATE, k_cg_update, dim3(nb), dim3(MB), st, S, ppw, prz[cur], nb, s.st, s.dx,
+              s.r, s.z, s.p, s.w, prz[cur ^ 1]);
+    MM_LAUNCH(T, GOFD_MMPDE_K_CG_DIR, k_cg_dir, dim3(nb), dim3(MB), st, nv, prz[cur], prz[cur ^ 1], nb, s.st, s.z,
+              s.p);
     if ((it + 1) % 8 == 0 || it + 1 == max_cg) {
       HIP_TRY(ctx, hipMemcpyAsync(hs, s.st, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -901,9 +955,10 @@ void field_setup(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* Xb, const doubl
 
 // M_K, GK at the centroids of X into slot j, walking from loc_in
 void field_eval(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, const double* Xb, const double* Mv,
-                const int* loc_in, Scratch& s, int j) {
-  hipLaunchKernelGGL(k_field_eval, dim3(grid1(m->ne, MB)), dim3(MB), 0, ctx->stream, X, m->elems.as<int>(), Xb,
-                     m->nbr.as<int>(), Mv, s.GMb, loc_in, (long long)m->ne, s.loc[j], s.MK[j], s.GK[j]);
+                const int* loc_in, Scratch& s, int j, KTimer* T = nullptr) {
+  MM_LAUNCH(T, GOFD_MMPDE_K_FIELD, k_field_eval, dim3(grid1(m->ne, MB)), dim3(MB), ctx->stream, X,
+            m->elems.as<int>(), Xb, m->nbr.as<int>(), Mv, s.GMb, loc_in, (long long)m->ne, s.loc[j], s.MK[j],
+            s.GK[j]);
 }
 
 }  // namespace
@@ -1069,6 +1124,13 @@ extern "C" int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde m, double* X_dev, const 
   hipStream_t st = ctx->stream;
   const long long nv = m->nv, ne = m->ne;
   const int* el = m->elems.as<int>();
+  std::unique_ptr<KTimer> timer;
+  if (o.stats) {
+    timer.reset(new (std::nothrow) KTimer());
+    if (!timer) return gofd_fail(ctx, GOFD_E_OOM, "kernel timer");
+    timer->on = true;
+  }
+  KTimer* T = timer.get();
   // the metric field lives on the mesh the move starts from
   HIP_TRY(ctx, hipMemcpyAsync(s.Xb, X_dev, sizeof(double) * 2 * nv, hipMemcpyDeviceToDevice, st));
   field_setup(ctx, m, s.Xb, Mv_dev, s);
@@ -1088,20 +1150,21 @@ extern "C" int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde m, double* X_dev, const 
     GOFD_TRY(projected_gradient(ctx, m, X_dev, s.MK[acc], s.GK[acc], s, &gn));
     if (g0 < 0) g0 = gn;
     if (!fixed && gn <= gtol * g0) break;
-    hipLaunchKernelGGL(k_elem_hess_fd, dim3(grid1(ne, MB)), dim3(MB), 0, st, X_dev, el, s.MK[acc], ne, s.Hk);
+    MM_LAUNCH(T, GOFD_MMPDE_K_HESS, k_elem_hess_fd, dim3(grid1(ne, MB)), dim3(MB), st, X_dev, el, s.MK[acc], ne,
+              s.Hk);
     hipLaunchKernelGGL(k_hess_diag, dim3(grid1(nv, MB)), dim3(MB), 0, st, m->ve_off.as<int>(), m->ve.as<int>(), s.Hk,
                        nv, s.Jd);
     double h = fixed ? dt : std::min(dt, t_end - t);
     double e1[2] = {I0, 0.0};
     for (;;) {
       bool ok = false;
-      GOFD_TRY(step_solve(ctx, m, X_dev, s, tau, h, cg_tol, max_cg, &ok, &cg_its));
+      GOFD_TRY(step_solve(ctx, m, X_dev, s, tau, h, cg_tol, max_cg, &ok, &cg_its, T));
       if (fixed && !ok) return gofd_fail(ctx, GOFD_E_BREAKDOWN, "step system not positive definite");
       if (ok) {
         hipLaunchKernelGGL(k_place, dim3(grid1(nv, MB)), dim3(MB), 0, st, X_dev, s.dx, m->bnd.as<uint8_t>(), nv,
                            m->boundary, s.Y);
-        field_eval(ctx, m, s.Y, s.Xb, Mv_dev, s.loc[acc], s, acc ^ 1);
-        GOFD_TRY(energy_check(ctx, m, s.Y, s.MK[acc ^ 1], s, e1));
+        field_eval(ctx, m, s.Y, s.Xb, Mv_dev, s.loc[acc], s, acc ^ 1, T);
+        GOFD_TRY(energy_check(ctx, m, s.Y, s.MK[acc ^ 1], s, e1, T));
         if (fixed || (e1[1] == 0.0 && e1[0] < I0)) break;
       }
       h *= 0.5;
@@ -1122,6 +1185,10 @@ extern "C" int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde m, double* X_dev, const 
   }
   GOFD_TRY(projected_gradient(ctx, m, X_dev, s.MK[acc], s.GK[acc], s, &gn));
   if (g0 < 0) g0 = gn;
+  if (T) {
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    T->write(o.stats);
+  }
   if (info) {
     info->steps = steps;
     info->rejected = rejected;

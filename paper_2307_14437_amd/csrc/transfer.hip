@@ -421,7 +421,8 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   // least-loaded thread (ties: the lower thread), then laid out thread by
   // thread, each thread's in vertex order.  Row pairs are independent: the
   // plans and then the entries are made by host threads over row pairs.
-  std::vector<int32_t> meta(4 * (size_t)pairs), tseg((size_t)pairs * T), ent(pairs), plan(nseg);
+  std::vector<int32_t> meta(4 * (size_t)pairs), tseg((size_t)pairs * T), tcnt((size_t)pairs * T), ent(pairs),
+      plan(nseg);
   auto len = [&](int32_t p) { return seg_b[dest[p]] - seg_a[dest[p]]; };
   const int nthr = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
   auto parallel_rows = [&](auto&& body) {
@@ -452,6 +453,7 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
     for (int k = 0; k < T; ++k) {
       std::sort(owned[k].begin(), owned[k].end());
       tseg[(size_t)r * T + k] = pos - s0;
+      tcnt[(size_t)r * T + k] = load[k];
       for (int32_t p : owned[k]) plan[pos++] = dest[p];     // segment (= slot) at each position
       e = std::max(e, load[k]);
     }
@@ -517,6 +519,12 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   std::vector<int32_t> pos(std::max<int64_t>(nseg, 1), 0);
   for (int64_t p = 0; p < nseg; ++p) pos[dest[p]] = (int32_t)p;
   GOFD_TRY(dev_reserve(ctx, tr->rp_meta, sizeof(int32_t) * meta.size()));
+  // on the device each thread's word also carries its entry count (bits 16..31), so that its loads stop at
+  // its last entry: first segment < RP_SEGCAP fits the low 16 bits
+  for (size_t i = 0; i < tseg.size(); ++i) {
+    if (tcnt[i] > 0xffff) return GOFD_OK;
+    tseg[i] |= tcnt[i] << 16;
+  }
   GOFD_TRY(dev_reserve(ctx, tr->rp_tseg, sizeof(int32_t) * tseg.size()));
   GOFD_TRY(dev_reserve(ctx, tr->rp_code, sizeof(uint16_t) * total));
   GOFD_TRY(dev_reserve(ctx, tr->rp_w32, sizeof(float) * total));
@@ -555,6 +563,35 @@ static int build_rowpairs(gofd_ctx_s* ctx, gofd_transfer_s* tr, const std::vecto
   tr->rp_ok = true;
   return GOFD_OK;
 }
+
+// device time of the build's stages: events recorded at each kernel's start and end
+struct BuildTimer {
+  hipEvent_t ev[8][2] = {};
+  bool ok = true;
+  BuildTimer() {
+    for (auto& p : ev)
+      for (auto& e : p) ok = ok && hipEventCreate(&e) == hipSuccess;
+  }
+  ~BuildTimer() {
+    for (auto& p : ev)
+      for (auto& e : p)
+        if (e) (void)hipEventDestroy(e);
+  }
+  void write(double* us) const {     // after the stream has been synchronised
+    for (int k = 0; k < 8; ++k) {
+      float ms = 0.0f;
+      us[k] = ok && hipEventElapsedTime(&ms, ev[k][0], ev[k][1]) == hipSuccess ? ms * 1e3 : 0.0;
+    }
+  }
+};
+
+#define TR_LAUNCH(TM, K, KERNEL, GRID, BLOCK, STREAM, ...)                                              \
+  do {                                                                                                  \
+    if ((TM).ok)                                                                                        \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, (TM).ev[K][0], (TM).ev[K][1], 0, __VA_ARGS__); \
+    else                                                                                                \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, STREAM, __VA_ARGS__);                                  \
+  } while (0)
 
 extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double* X_dev, int64_t ne,
                                    const int32_t* elems_dev, const gofd_grid* grid, gofd_transfer* out,
@@ -607,22 +644,23 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   HIP_TRY(ctx, hipMemcpyAsync(tr->elems.p, elems_dev, sizeof(int32_t) * ne * (d + 1), hipMemcpyDeviceToDevice, st));
 
   GridGeom g = make_geom(tr);
+  BuildTimer tm;
   GOFD_TRY(dev_reserve(ctx, tr->rec, (d == 2 ? sizeof(ElemRec2) : sizeof(ElemRec3)) * ne));
   if (d == 2)
-    hipLaunchKernelGGL(k_make_records<2>, dim3(grid1(ne, 256)), dim3(256), 0, st, tr->X.as<double>(),
-                       tr->elems.as<int>(), (long long)ne, tr->rec.as<ElemRec2>());
+    TR_LAUNCH(tm, GOFD_TR_K_RECORDS, k_make_records<2>, dim3(grid1(ne, 256)), dim3(256), st, tr->X.as<double>(),
+              tr->elems.as<int>(), (long long)ne, tr->rec.as<ElemRec2>());
   else
-    hipLaunchKernelGGL(k_make_records<3>, dim3(grid1(ne, 256)), dim3(256), 0, st, tr->X.as<double>(),
-                       tr->elems.as<int>(), (long long)ne, tr->rec.as<ElemRec3>());
+    TR_LAUNCH(tm, GOFD_TR_K_RECORDS, k_make_records<3>, dim3(grid1(ne, 256)), dim3(256), st, tr->X.as<double>(),
+              tr->elems.as<int>(), (long long)ne, tr->rec.as<ElemRec3>());
   unsigned long long* counters = ctx->scratch.as<unsigned long long>();
   HIP_TRY(ctx, hipMemsetAsync(counters, 0, 8 * sizeof(unsigned long long), st));
   hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(), n_nodes, NO_ELEM);
   if (d == 2)
-    hipLaunchKernelGGL(k_locate<2>, dim3(grid1(ne, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
-                       tr->elems.as<int>(), (long long)ne, tr->elem.as<int>(), counters);
+    TR_LAUNCH(tm, GOFD_TR_K_LOCATE, k_locate<2>, dim3(grid1(ne, 256)), dim3(256), st, g, tr->X.as<double>(),
+              tr->elems.as<int>(), (long long)ne, tr->elem.as<int>(), counters);
   else
-    hipLaunchKernelGGL(k_locate<3>, dim3(grid1(ne, 256)), dim3(256), 0, st, g, tr->X.as<double>(),
-                       tr->elems.as<int>(), (long long)ne, tr->elem.as<int>(), counters);
+    TR_LAUNCH(tm, GOFD_TR_K_LOCATE, k_locate<3>, dim3(grid1(ne, 256)), dim3(256), st, g, tr->X.as<double>(),
+              tr->elems.as<int>(), (long long)ne, tr->elem.as<int>(), counters);
   hipLaunchKernelGGL(k_finish_location, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
                      n_nodes, counters);
   HIP_TRY(ctx, hipGetLastError());
@@ -659,22 +697,25 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   }
   HIP_TRY(ctx, hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (nv + 1), st));
   if (d == 2)
-    hipLaunchKernelGGL(k_count<2>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
-                       tr->elems.as<int>(), n_nodes, cnt.as<int>());
+    TR_LAUNCH(tm, GOFD_TR_K_COUNT, k_count<2>, dim3(grid1(n_nodes, 256)), dim3(256), st, tr->elem.as<int>(),
+              tr->elems.as<int>(), n_nodes, cnt.as<int>());
   else
-    hipLaunchKernelGGL(k_count<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
-                       tr->elems.as<int>(), n_nodes, cnt.as<int>());
+    TR_LAUNCH(tm, GOFD_TR_K_COUNT, k_count<3>, dim3(grid1(n_nodes, 256)), dim3(256), st, tr->elem.as<int>(),
+              tr->elems.as<int>(), n_nodes, cnt.as<int>());
+  if (tm.ok) HIP_TRY(ctx, hipEventRecord(tm.ev[GOFD_TR_K_SCAN][0], st));
   GOFD_TRY(scan_exclusive_i32(ctx, cnt.as<int32_t>(), tr->csc_off.as<int32_t>(), nv));
+  if (tm.ok) HIP_TRY(ctx, hipEventRecord(tm.ev[GOFD_TR_K_SCAN][1], st));
   HIP_TRY(ctx, hipMemcpyAsync(cursor.p, tr->csc_off.p, sizeof(int32_t) * (nv + 1), hipMemcpyDeviceToDevice, st));
   if (d == 2)
-    hipLaunchKernelGGL(k_fill_csc<2>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec2>(),
-                       tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(), w_tmp.as<double>());
+    TR_LAUNCH(tm, GOFD_TR_K_FILL, k_fill_csc<2>, dim3(grid1(n_nodes, 256)), dim3(256), st, g,
+              tr->rec.as<ElemRec2>(), tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(),
+              w_tmp.as<double>());
   else
-    hipLaunchKernelGGL(k_fill_csc<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec3>(),
-                       tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(), w_tmp.as<double>());
-  hipLaunchKernelGGL(k_sort_segments, dim3(grid1(nv * 64, 256)), dim3(256), 0, st, tr->csc_off.as<int>(),
-                     (long long)nv, node_tmp.as<int>(), w_tmp.as<double>(), tr->csc_node.as<int>(),
-                     tr->csc_w.as<double>());
+    TR_LAUNCH(tm, GOFD_TR_K_FILL, k_fill_csc<3>, dim3(grid1(n_nodes, 256)), dim3(256), st, g,
+              tr->rec.as<ElemRec3>(), tr->elem.as<int>(), n_nodes, cursor.as<int>(), node_tmp.as<int>(),
+              w_tmp.as<double>());
+  TR_LAUNCH(tm, GOFD_TR_K_SORT, k_sort_segments, dim3(grid1(nv * 64, 256)), dim3(256), st, tr->csc_off.as<int>(),
+            (long long)nv, node_tmp.as<int>(), w_tmp.as<double>(), tr->csc_node.as<int>(), tr->csc_w.as<double>());
   if (d == 3) {
     // compact interpolation rows for the gather: in 3D the nodes of an element
     // lie in different planes, so per-node rows stream better than records
@@ -691,25 +732,26 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
     hipLaunchKernelGGL(k_inside_flag, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, tr->elem.as<int>(),
                        (long long)n_nodes, flag.as<int>());
     GOFD_TRY(scan_exclusive_i32(ctx, flag.as<int32_t>(), tr->ell_idx.as<int32_t>(), n_nodes));
-    hipLaunchKernelGGL(k_fill_ell<3>, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec3>(),
-                       tr->elem.as<int>(), (long long)n_nodes, tr->ell_idx.as<int>(), tr->ell_v.as<int>(),
-                       tr->ell_w.as<double>());
+    TR_LAUNCH(tm, GOFD_TR_K_ROWS, k_fill_ell<3>, dim3(grid1(n_nodes, 256)), dim3(256), st, g,
+              tr->rec.as<ElemRec3>(), tr->elem.as<int>(), (long long)n_nodes, tr->ell_idx.as<int>(),
+              tr->ell_v.as<int>(), tr->ell_w.as<double>());
     HIP_TRY(ctx, hipStreamSynchronize(st));
   }
   if (d == 2) {
     GOFD_TRY(dev_reserve(ctx, tr->row32_v, sizeof(int4) * n_nodes));
     GOFD_TRY(dev_reserve(ctx, tr->row32_w, sizeof(float2) * n_nodes));
-    hipLaunchKernelGGL(k_fill_rows32, dim3(grid1(n_nodes, 256)), dim3(256), 0, st, g, tr->rec.as<ElemRec2>(),
-                       tr->elem.as<int>(), (long long)n_nodes, tr->row32_v.as<int4>(), tr->row32_w.as<float2>());
+    TR_LAUNCH(tm, GOFD_TR_K_ROWS, k_fill_rows32, dim3(grid1(n_nodes, 256)), dim3(256), st, g,
+              tr->rec.as<ElemRec2>(), tr->elem.as<int>(), (long long)n_nodes, tr->row32_v.as<int4>(),
+              tr->row32_w.as<float2>());
   }
   GOFD_TRY(dev_reserve(ctx, tr->D, sizeof(double) * nv));
   GOFD_TRY(dev_reserve(ctx, tr->dscale, sizeof(double) * nv));
   GOFD_TRY(dev_reserve(ctx, tr->dsqrt, sizeof(double) * nv));
   GOFD_TRY(dev_reserve(ctx, tr->imask, sizeof(double) * nv));
-  hipLaunchKernelGGL(k_colsum, dim3(grid1(nv, 256)), dim3(256), 0, st, tr->csc_off.as<int>(), (long long)nv,
-                     tr->csc_w.as<double>(), tr->bmask.as<unsigned char>(), tr->D.as<double>(),
-                     tr->dscale.as<double>(), tr->dsqrt.as<double>(), tr->imask.as<double>(),
-                     tr->csc_w32.as<float>(), (long long)nnz);
+  TR_LAUNCH(tm, GOFD_TR_K_COLSUM, k_colsum, dim3(grid1(nv, 256)), dim3(256), st, tr->csc_off.as<int>(),
+            (long long)nv, tr->csc_w.as<double>(), tr->bmask.as<unsigned char>(), tr->D.as<double>(),
+            tr->dscale.as<double>(), tr->dsqrt.as<double>(), tr->imask.as<double>(), tr->csc_w32.as<float>(),
+            (long long)nnz);
   HIP_TRY(ctx, hipGetLastError());
 
   // statistics and checks on the host
@@ -739,6 +781,7 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   inf.max_col_count = maxc;
   inf.a_h = min_height(d, tr->X_host, tr->elems_host);
   inf.h_bound = inf.a_h / ((d + 1) * std::sqrt((double)d));
+  tm.write(inf.kernel_us);     // the stream was synchronised above
   tr->info = inf;
   if (info) *info = inf;
   if (inf.n_interior > 0 && !(dmin > 0.0))

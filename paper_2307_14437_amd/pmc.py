@@ -5,8 +5,8 @@ runs: FETCH_SIZE and WRITE_SIZE of the benchmark, and the same two counters of a
 device-to-device copy of known size (`bench.py --copy-probe MiB`).  The copy
 gives the factor between each counter (KiB per dispatch) and the bytes actually
 moved; the benchmark's per-kernel averages are scaled by it.  Writes a JSON
-summary keyed by the stages of one CG iteration, with a hash of the library
-sources, so that a reader can tell when the kernels have changed since.
+summary keyed by the stages of one CG iteration, with a hash of the sources of
+the measured kernels, so that a reader can tell when they have changed since.
 
 Usage (plain script, does not load the library):
   python paper_2307_14437_amd/pmc.py FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR COPY_MIB OUT.json
@@ -33,9 +33,14 @@ STAGE_SYMBOLS = {   # fragments that together name the kernel of each stage
 }
 
 
+# the sources of the measured kernels (the FFT passes, the vertex CG kernel) and the headers they include
+KERNEL_SOURCES = ("conv.hip", "conv_common.h", "fft.h", "solver.hip", "cg_state.h", "cg_items.h", "bary.h",
+                  "internal.h")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    for f in sorted(os.path.join(HERE, "csrc", n) for n in KERNEL_SOURCES):
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
