@@ -45,7 +45,8 @@ Steps of one adaptation level, in the paper's order:
    differences of the analytic element gradient (step 1e-5 times the
    element's longest edge, then symmetrised).  A trial step is halved until
    the restricted matrix is positive definite, no element inverts and I_h
-   decreases; the next trial step is twice the accepted one.  Integration
+   decreases; the next trial step is twice the accepted one, or the accepted
+   one itself when it had to be halved.  Integration
    stops at t = 1, or earlier once the flow is at rest: the restricted
    gradient has fallen to 1e-6 of its initial norm (the mesh then no longer
    moves, so the mesh at t = 1 is the one reached), or no step of at least
@@ -478,6 +479,7 @@ def move_mesh(X, elems, Mv, bnd, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, g
             break
         J = assemble_hessian(elems, element_hessians_fd(X, elems, M), X.shape[0])
         h = dt if fixed_dt > 0 else min(dt, t_end - t)
+        halved = False
         while True:
             Y = implicit_step(X, bnd, qv, h, G, J, tau, boundary)
             if fixed_dt > 0:
@@ -491,6 +493,7 @@ def move_mesh(X, elems, Mv, bnd, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, g
                     break
             h *= 0.5
             rejected += 1
+            halved = True
             if h < 1e-14 or h < 1e-6 * h_max:
                 return X, steps, dict(t=t, rejected=rejected, energy_start=I_start, energy_end=I0, grad0=g0,
                                       grad=gn)
@@ -498,7 +501,7 @@ def move_mesh(X, elems, Mv, bnd, tau=1e-2, t_end=1.0, dt0=1e-3, max_steps=400, g
         h_max = max(h_max, h)
         gn = float(np.linalg.norm(motion_basis(X, bnd, boundary).T @ G.ravel())) if G is not None else math.inf
         if fixed_dt <= 0:
-            dt = 2.0 * h
+            dt = h if halved else 2.0 * h
     return X, steps, dict(t=t, rejected=rejected, energy_start=I_start, energy_end=I0, grad0=g0, grad=gn)
 
 
