@@ -248,12 +248,11 @@ def _mmpde_kernel_bytes(nv, ne, nbnd):
         # elements, X; one background element and its vertices, vertex metrics, component gradients; locations
         # in and out; M_K and gradients out
         "energy": 12 * ne + vec + 24 * ne,                         # elements, X, M_K in (partials are negligible)
-        "cg_elem": 12 * ne + 288 * ne + vec + 48 * ne,             # elements, Hessians, p in; 6 values out
-        "cg_vert": 4 * (nv + 1) + 12 * ne + 48 * ne + 8 * nv + vec + vec + nbnd + vec,
-        # offsets, corner lists, element products, q, p, X, boundary flags in; w out
+        "cg_elem": 12 * ne + 288 * ne + 2 * vec + 48 * ne,         # elements, Hessians, z and p in; 6 values out
+        "cg_vert": 4 * (nv + 1) + 12 * ne + 48 * ne + 8 * nv + vec + 2 * vec + vec + nbnd + vec,
+        # offsets, corner lists, element products, q, z, p read and written, X, boundary flags; w out
         "cg_update": 2 * vec + 2 * vec + vec + vec + vec + 24 * nv + 8 * nv + vec + nbnd,
         # dx and r read and written, z written, p and w read, diagonal blocks, q, X, flags
-        "cg_dir": vec + 2 * vec,                                   # z read, p read and written
     }
 
 

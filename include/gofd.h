@@ -501,11 +501,10 @@ enum {
   GOFD_MMPDE_K_HESS = 0,      /* element Hessians by differences (once per step)                   */
   GOFD_MMPDE_K_FIELD = 1,     /* metric at the centroids (walks; once per trial)                     */
   GOFD_MMPDE_K_ENERGY = 2,    /* energy partials and inversion test (once per trial)                 */
-  GOFD_MMPDE_K_CG_ELEM = 3,   /* CG: element Hessians times the direction                            */
-  GOFD_MMPDE_K_CG_VERT = 4,   /* CG: vertex sums, shift, projection, (p, w) partials                 */
+  GOFD_MMPDE_K_CG_ELEM = 3,   /* CG: convergence test, beta, element Hessians times the new direction */
+  GOFD_MMPDE_K_CG_VERT = 4,   /* CG: new direction stored, vertex sums, shift, projection, (p, w)     */
   GOFD_MMPDE_K_CG_UPDATE = 5, /* CG: alpha, x, r, preconditioner, partials                           */
-  GOFD_MMPDE_K_CG_DIR = 6,    /* CG: convergence test, beta, direction                               */
-  GOFD_MMPDE_N_KERNELS = 7
+  GOFD_MMPDE_N_KERNELS = 6
 };
 
 typedef struct {
@@ -590,13 +589,14 @@ int gofd_mmpde_element_hessians(gofd_ctx ctx, gofd_mmpde mm, const double* X_dev
  * conjugate gradients with the vertices' 2 x 2 blocks as preconditioner.  A
  * trial step is halved until the solve converges with positive curvature
  * throughout, no element inverts and I_h decreases; the next trial step is
- * twice the accepted one.  Stops at t_end, after max_steps accepted steps,
+ * twice the accepted one, or the same after a halving.  Stops at t_end, after max_steps accepted steps,
  * once the projected gradient has fallen to gtol of its initial norm (the
  * flow is at rest), or when no step of at least 1e-6 times the longest
  * accepted one (and 1e-14) decreases I_h.  With opts->fixed_dt > 0 it takes
  * exactly max_steps steps of that length, with no energy test and no
- * gradient stop.  opts and info (host) are nullable.  Synchronises every 8
- * solver iterations and after every trial step.
+ * gradient stop.  opts and info (host) are nullable.  The solver's
+ * iterations go out in chunks of 8 whose state the host reads while the
+ * next chunk runs; synchronises after every trial step.
  * Errors: GOFD_E_ARG, GOFD_E_DEGENERATE (the mesh given has an inverted
  * element), GOFD_E_BREAKDOWN (fixed_dt: a step system was not positive
  * definite), GOFD_E_HIP, GOFD_E_OOM. */

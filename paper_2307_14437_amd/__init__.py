@@ -67,7 +67,7 @@ class CgTapeInfo(ctypes.Structure):
                 ("converged", ctypes.c_int)]
 
 
-MMPDE_KERNELS = ("hess_fd", "field", "energy", "cg_elem", "cg_vert", "cg_update", "cg_dir")
+MMPDE_KERNELS = ("hess_fd", "field", "energy", "cg_elem", "cg_vert", "cg_update")
 
 
 class MmpdeKernelStats(ctypes.Structure):

@@ -226,27 +226,38 @@ __global__ void k_scan_add(int32_t* __restrict__ out, const int32_t* __restrict_
   if (i < n) out[i] += block_prefix[blockIdx.x];
 }
 
-int scan_exclusive_i32(gofd_ctx_s* ctx, const int32_t* in, int32_t* out, int64_t n) {
-  int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  if (nb < 1) nb = 1;
-  DevBuf sums, pref;
-  GOFD_TRY(dev_reserve(ctx, sums, sizeof(int32_t) * (nb + 1)));
-  GOFD_TRY(dev_reserve(ctx, pref, sizeof(int32_t) * (nb + 1)));
-  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SCAN_BLOCK), 0, ctx->stream, in, out,
-                     sums.as<int32_t>(), n);
+__global__ void k_scan_total(const int32_t* __restrict__ in, int32_t* __restrict__ out, int64_t n) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+// ints of the block sums and their prefixes over every level of a scan of n values
+static int64_t scan_ws_ints(int64_t n) {
+  int64_t t = 0;
+  for (;;) {
+    const int64_t nb = std::max<int64_t>(1, (n + SCAN_BLOCK - 1) / SCAN_BLOCK);
+    t += 2 * (nb + 1);
+    if (nb <= 1) return t;
+    n = nb;
+  }
+}
+
+static void scan_levels(hipStream_t st, const int32_t* in, int32_t* out, int64_t n, int32_t* ws) {
+  const int64_t nb = std::max<int64_t>(1, (n + SCAN_BLOCK - 1) / SCAN_BLOCK);
+  int32_t* sums = ws;
+  int32_t* pref = ws + nb + 1;
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SCAN_BLOCK), 0, st, in, out, sums, n);
   if (nb > 1) {
-    GOFD_TRY(scan_exclusive_i32(ctx, sums.as<int32_t>(), pref.as<int32_t>(), nb));
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, ctx->stream, out, pref.as<int32_t>(), n);
+    scan_levels(st, sums, pref, nb, ws + 2 * (nb + 1));
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_BLOCK), 0, st, out, pref, n);
   }
-  // total into out[n]: last exclusive value + last input
-  std::vector<int32_t> tail(2, 0);
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  if (n > 0) {
-    HIP_TRY(ctx, hipMemcpy(&tail[0], out + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIP_TRY(ctx, hipMemcpy(&tail[1], in + (n - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
-  }
-  int32_t total = tail[0] + tail[1];
-  HIP_TRY(ctx, hipMemcpy(out + n, &total, sizeof(int32_t), hipMemcpyHostToDevice));
+}
+
+// out[0..n] = exclusive prefix sums of in[0..n) and the total, on the context's stream (no host round trip;
+// the levels' block sums live in a workspace of the context)
+int scan_exclusive_i32(gofd_ctx_s* ctx, const int32_t* in, int32_t* out, int64_t n) {
+  GOFD_TRY(dev_reserve(ctx, ctx->scan_ws, sizeof(int32_t) * scan_ws_ints(n)));
+  scan_levels(ctx->stream, in, out, n, ctx->scan_ws.as<int32_t>());
+  hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, ctx->stream, in, out, n);
   HIP_TRY(ctx, hipGetLastError());
   return GOFD_OK;
 }

@@ -77,6 +77,7 @@ struct gofd_ctx_s {
   std::map<std::pair<int, bool>, int> row_sched;   // 2D first row pass of the products: values per thread
   std::map<std::pair<int, bool>, int> sched3;      // 3D y/z/y passes: 0 default, 1 two slots per block
   DevBuf scratch;                           // small reduction scratch (partials, counters)
+  DevBuf scan_ws;                           // block sums of the prefix-sum helper
   DevBuf flag;                              // int status flags
   // When set, the next kernel launched through GOFD_LAUNCH records these
   // events at its own start and end (stage timing); the launch clears them.

@@ -33,7 +33,7 @@
 //    gradients with the 2 x 2 vertex blocks as preconditioner; a trial step
 //    is halved until the solve succeeds (the matrix is positive definite on
 //    the Krylov space), no element inverts and I_h decreases, and the next
-//    trial step is twice the accepted one; the move ends at t_end, at rest
+//    trial step is twice the accepted one (the same after a halving); the move ends at t_end, at rest
 //    (small projected gradient), or once no step of at least 1e-6 times the
 //    longest accepted one (and 1e-14) decreases I_h.
 // Vertex sums over elements run in a fixed order (vertex -> element lists
@@ -60,6 +60,13 @@ struct gofd_mmpde_s {
   DevBuf iwork;       // int32[2*ne]: centroid locations (accepted, trial)
   DevBuf work;        // scratch: vertex Hessians, element data, gradients, trial positions, partials
   size_t work_bytes = 0;
+  double* hst = nullptr;       // page-locked copies of a step solve's state, one slot per chunk in flight
+  hipEvent_t ev[2] = {};       // recorded after each chunk's copy
+  ~gofd_mmpde_s() {
+    if (hst) (void)hipHostFree(hst);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -633,7 +640,8 @@ __device__ inline bool precond(const StepSys& S, long long i, double rx, double 
   return true;
 }
 
-// dx = 0, r = -P g, z = B^{-1} r, p = z; partials of (r, z), (r, r) and failure
+// dx = 0, r = -P g, z = B^{-1} r, p = 0 (the first direction is z: see k_cg_elem); partials of (r, z),
+// (r, r) and failure
 __global__ __launch_bounds__(MB) void k_cg_init(StepSys S, const double* __restrict__ pg, double* __restrict__ dx,
                                                 double* __restrict__ r, double* __restrict__ z,
                                                 double* __restrict__ p, double* __restrict__ part) {
@@ -646,19 +654,26 @@ __global__ __launch_bounds__(MB) void k_cg_init(StepSys S, const double* __restr
     dx[2 * i] = dx[2 * i + 1] = 0.0;
     r[2 * i] = rx;
     r[2 * i + 1] = ry;
-    z[2 * i] = p[2 * i] = zx;
-    z[2 * i + 1] = p[2 * i + 1] = zy;
+    z[2 * i] = zx;
+    z[2 * i + 1] = zy;
+    p[2 * i] = p[2 * i + 1] = 0.0;
     v[0] += rx * zx + ry * zy;
     v[1] += rx * rx + ry * ry;
   }
   store_partials<3>(v, sh, part);
 }
 
+// state from the initial partials; the partial slots of the iterations: pr[0] = (r, z) and (r, r) of the
+// first iterate, pr[1] = the same (r, z), read as the previous one (so that the first beta is 1 and the first
+// direction z + 1 * 0 = z)
 __global__ __launch_bounds__(MB) void k_cg_start(const double* __restrict__ part, int nb, double tol,
-                                                 double* __restrict__ st) {
+                                                 double* __restrict__ st, double* __restrict__ pr0,
+                                                 double* __restrict__ pr1) {
   __shared__ double sh[gofd_cg::block_sum_lds<MB, 1>()];
   const double rr = sum_partials(part + nb, nb, sh);
   const double bad = sum_partials(part + 2 * nb, nb, sh);
+  for (int b = threadIdx.x; b < 2 * nb; b += MB) pr0[b] = part[b];
+  for (int b = threadIdx.x; b < nb; b += MB) pr1[b] = part[b];
   if (threadIdx.x == 0) {
     st[0] = bad > 0.0 ? 2.0 : (rr == 0.0 ? 1.0 : 0.0);
     st[1] = tol * tol * rr;
@@ -666,15 +681,39 @@ __global__ __launch_bounds__(MB) void k_cg_start(const double* __restrict__ part
   }
 }
 
-// Z_K = H_K p_K
-__global__ __launch_bounds__(MB) void k_cg_ap_elem(const int* __restrict__ el, const double* __restrict__ Hk,
-                                                   const double* __restrict__ p, long long ne,
-                                                   const double* __restrict__ st, double* __restrict__ Z) {
-  if (st[0] != 0.0) return;
+// the new direction at one coordinate (the same code in both kernels that form it, so the same bits)
+__device__ __forceinline__ double new_dir(double z, double beta, double p) { return z + beta * p; }
+
+// beta = (r, z)_cur / (r, z)_prev from the partials, and the convergence test (r, r)_cur <= tol^2 (r0, r0)
+__device__ inline bool cg_beta(const double* pcur, const double* pprev, int nb, const double* st, double* sh,
+                               double& beta) {
+  const double rz = sum_partials(pcur, nb, sh);
+  const double rzp = sum_partials(pprev, nb, sh);
+  const double rr = sum_partials(pcur + nb, nb, sh);
+  beta = rz / rzp;
+  return rr <= st[1];
+}
+
+// converged: flag set by block 0, every block leaves; else Z_K = H_K p_K, p = z + beta p_prev formed on the fly
+__global__ __launch_bounds__(MB) void k_cg_elem(const int* __restrict__ el, const double* __restrict__ Hk,
+                                                const double* __restrict__ z, const double* __restrict__ p,
+                                                long long ne, const double* __restrict__ pcur,
+                                                const double* __restrict__ pprev, int nb, double* __restrict__ st,
+                                                double* __restrict__ Z) {
+  if (stopped(st)) return;
+  __shared__ double sh[gofd_cg::block_sum_lds<MB, 1>()];
+  double beta;
+  const bool conv = cg_beta(pcur, pprev, nb, st, sh, beta);
+  if (conv) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = 1.0;
+    return;
+  }
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= ne) return;
-  double pk[6];
+  double zk[6], pk[6];
+  load_elem(z, el, k, zk);
   load_elem(p, el, k, pk);
+  for (int c = 0; c < 6; ++c) pk[c] = new_dir(zk[c], beta, pk[c]);
   const double* H = Hk + 36 * k;
   for (int r = 0; r < 6; ++r) {
     double s = 0.0;
@@ -683,29 +722,36 @@ __global__ __launch_bounds__(MB) void k_cg_ap_elem(const int* __restrict__ el, c
   }
 }
 
-// w = P (J p + tau / (h q) p); partials of (p, w)
-__global__ __launch_bounds__(MB) void k_cg_ap_vert(StepSys S, const int* __restrict__ voff, const int* __restrict__ ve,
-                                                   const double* __restrict__ Z, const double* __restrict__ p,
-                                                   const double* __restrict__ st, double* __restrict__ w,
-                                                   double* __restrict__ part) {
+// p = z + beta p_prev (stored); w = P (J p + tau / (h q) p); partials of (p, w)
+__global__ __launch_bounds__(MB) void k_cg_vert(StepSys S, const int* __restrict__ voff, const int* __restrict__ ve,
+                                                const double* __restrict__ Z, const double* __restrict__ z,
+                                                double* __restrict__ p, const double* __restrict__ pcur,
+                                                const double* __restrict__ pprev, int nb, double* __restrict__ st,
+                                                double* __restrict__ w, double* __restrict__ part) {
   if (stopped(st)) return;
   __shared__ double sh[gofd_cg::block_sum_lds<MB, 1>()];
+  double beta;
+  (void)cg_beta(pcur, pprev, nb, st, sh, beta);
   double v[1] = {0.0};
   for (long long i = (long long)blockIdx.x * MB + threadIdx.x; i < S.nv; i += (long long)gridDim.x * MB) {
+    const double px = new_dir(z[2 * i], beta, p[2 * i]), py = new_dir(z[2 * i + 1], beta, p[2 * i + 1]);
+    p[2 * i] = px;
+    p[2 * i + 1] = py;
     double wx, wy;
     gather2(voff, ve, Z, i, wx, wy);
     const double c = S.tau / (S.h * S.qv[i]);
-    wx += c * p[2 * i];
-    wy += c * p[2 * i + 1];
+    wx += c * px;
+    wy += c * py;
     project(S.mode, S.bnd[i], S.X[2 * i], S.X[2 * i + 1], wx, wy);
     w[2 * i] = wx;
     w[2 * i + 1] = wy;
-    v[0] += p[2 * i] * wx + p[2 * i + 1] * wy;
+    v[0] += px * wx + py * wy;
   }
   store_partials<1>(v, sh, part);
 }
 
-// alpha = (r, z) / (p, w); dx += alpha p, r -= alpha w, z = B^{-1} r; partials of (r, z)_new and (r, r)
+// alpha = (r, z) / (p, w); dx += alpha p, r -= alpha w, z = B^{-1} r; partials of the new (r, z) and (r, r);
+// counts the iteration
 __global__ __launch_bounds__(MB) void k_cg_update(StepSys S, const double* __restrict__ part_pw,
                                                   const double* __restrict__ part_rz, int nb, double* __restrict__ st,
                                                   double* __restrict__ dx, double* __restrict__ r,
@@ -735,28 +781,7 @@ __global__ __launch_bounds__(MB) void k_cg_update(StepSys S, const double* __res
     v[1] += rx * rx + ry * ry;
   }
   store_partials<2>(v, sh, part_out);
-}
-
-// converged when (r, r) <= tol^2 (r0, r0); else p = z + beta p, beta = (r, z)_new / (r, z)_old
-__global__ __launch_bounds__(MB) void k_cg_dir(long long nv, const double* __restrict__ part_old,
-                                               const double* __restrict__ part_new, int nb, double* __restrict__ st,
-                                               const double* __restrict__ z, double* __restrict__ p) {
-  if (stopped(st)) return;
-  __shared__ double sh[gofd_cg::block_sum_lds<MB, 1>()];
-  const double rz_old = sum_partials(part_old, nb, sh);
-  const double rz_new = sum_partials(part_new, nb, sh);
-  const double rr = sum_partials(part_new + nb, nb, sh);
-  const bool conv = rr <= st[1];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st[2] += 1.0;
-    if (conv) st[0] = 1.0;
-  }
-  if (conv) return;
-  const double beta = rz_new / rz_old;
-  for (long long i = (long long)blockIdx.x * MB + threadIdx.x; i < nv; i += (long long)gridDim.x * MB) {
-    p[2 * i] = z[2 * i] + beta * p[2 * i];
-    p[2 * i + 1] = z[2 * i + 1] + beta * p[2 * i + 1];
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[2] += 1.0;
 }
 
 // Y = X + dx; boundary vertices put back on the unit circle
@@ -906,44 +931,56 @@ int projected_gradient(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, const 
   return GOFD_OK;
 }
 
-// conjugate gradients on the step system of length h (Hk, Jd, qv, pg ready); *ok = converged, *its added
+// conjugate gradients on the step system of length h (Hk, Jd, qv, pg ready); *ok = converged, *its added.
+// Iterations go out in chunks of 8; each chunk ends with a copy of the state to a page-locked slot and an
+// event, and the host reads a chunk's state while the next one runs (kernels of a chunk issued past the end
+// return at once).
 int step_solve(gofd_ctx_s* ctx, gofd_mmpde_s* m, const double* X, Scratch& s, double tau, double h, double tol,
                int max_cg, bool* ok, long long* its, KTimer* T) {
   hipStream_t st = ctx->stream;
   const long long nv = m->nv, ne = m->ne;
   const int nb = vertex_blocks(nv);
   StepSys S{m->bnd.as<uint8_t>(), X, s.Jd, s.qv, tau, h, m->boundary, nv};
-  // partial buffers: (r,z) ping-pong with (r,r) after each, then (p,w), then init's three
-  double* prz[2] = {s.part, s.part + 2 * MNB};
+  if (!m->hst) {
+    HIP_TRY(ctx, hipHostMalloc((void**)&m->hst, 8 * sizeof(double), hipHostMallocDefault));
+    for (auto& e : m->ev) HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // partial slots: pr[j] = (r, z) then (r, r) of an iterate, ping-pong; (p, w); the initial three
+  double* pr[2] = {s.part, s.part + 2 * MNB};
   double* ppw = s.part + 4 * MNB;
   double* pinit = s.part + 5 * MNB;
   hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(MB), 0, st, S, s.pg, s.dx, s.r, s.z, s.p, pinit);
-  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(MB), 0, st, pinit, nb, tol, s.st);
-  HIP_TRY(ctx, hipMemcpyAsync(prz[0], pinit, sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
-  double hs[3] = {0.0, 0.0, 0.0};
-  for (int it = 0; it < max_cg; ++it) {
-    const int cur = it & 1;
-    MM_LAUNCH(T, GOFD_MMPDE_K_CG_ELEM, k_cg_ap_elem, dim3(grid1(ne, MB)), dim3(MB), st, m->elems.as<int>(), s.Hk,
-              s.p, ne, s.st, s.G);
-    MM_LAUNCH(T, GOFD_MMPDE_K_CG_VERT, k_cg_ap_vert, dim3(nb), dim3(MB), st, S, m->ve_off.as<int>(),
-              m->ve.as<int>(), s.G, s.p, s.st, s.w, ppw);
-    MM_LAUNCH(T, GOFD_MMPDE_K_CG_UPDATE, k_cg_update, dim3(nb), dim3(MB), st, S, ppw, prz[cur], nb, s.st, s.dx,
-              s.r, s.z, s.p, s.w, prz[cur ^ 1]);
-    MM_LAUNCH(T, GOFD_MMPDE_K_CG_DIR, k_cg_dir, dim3(nb), dim3(MB), st, nv, prz[cur], prz[cur ^ 1], nb, s.st, s.z,
-              s.p);
-    if ((it + 1) % 8 == 0 || it + 1 == max_cg) {
-      HIP_TRY(ctx, hipMemcpyAsync(hs, s.st, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_TRY(ctx, hipStreamSynchronize(st));
-      if (hs[0] != 0.0) break;
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(MB), 0, st, pinit, nb, tol, s.st, pr[0], pr[1]);
+  const int CH = 8;
+  int it = 0, chunk = 0;
+  double last[3] = {0.0, 0.0, 0.0};
+  bool done = false;
+  while (!done && it < max_cg) {
+    for (int q = 0; q < CH && it < max_cg; ++q, ++it) {
+      const int cur = it & 1;
+      MM_LAUNCH(T, GOFD_MMPDE_K_CG_ELEM, k_cg_elem, dim3(grid1(ne, MB)), dim3(MB), st, m->elems.as<int>(), s.Hk,
+                s.z, s.p, ne, pr[cur], pr[cur ^ 1], nb, s.st, s.G);
+      MM_LAUNCH(T, GOFD_MMPDE_K_CG_VERT, k_cg_vert, dim3(nb), dim3(MB), st, S, m->ve_off.as<int>(),
+                m->ve.as<int>(), s.G, s.z, s.p, pr[cur], pr[cur ^ 1], nb, s.st, s.w, ppw);
+      MM_LAUNCH(T, GOFD_MMPDE_K_CG_UPDATE, k_cg_update, dim3(nb), dim3(MB), st, S, ppw, pr[cur], nb, s.st, s.dx,
+                s.r, s.z, s.p, s.w, pr[cur ^ 1]);
     }
+    double* slot = m->hst + 4 * (chunk & 1);
+    HIP_TRY(ctx, hipMemcpyAsync(slot, s.st, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipEventRecord(m->ev[chunk & 1], st));
+    if (chunk > 0) {          // the previous chunk's state, while this one runs
+      HIP_TRY(ctx, hipEventSynchronize(m->ev[(chunk - 1) & 1]));
+      const double* prev = m->hst + 4 * ((chunk - 1) & 1);
+      if (prev[0] != 0.0) done = true;
+    }
+    ++chunk;
   }
+  // the last chunk's state is final (nothing changes the state once it has ended)
+  HIP_TRY(ctx, hipEventSynchronize(m->ev[(chunk - 1) & 1]));
+  for (int k = 0; k < 3; ++k) last[k] = m->hst[4 * ((chunk - 1) & 1) + k];
   HIP_TRY(ctx, hipGetLastError());
-  if (hs[0] == 0.0) {      // max_cg reached before the check saw the end
-    HIP_TRY(ctx, hipMemcpyAsync(hs, s.st, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(ctx, hipStreamSynchronize(st));
-  }
-  *ok = hs[0] == 1.0;
-  *its += (long long)hs[2];
+  *ok = last[0] == 1.0;
+  *its += (long long)last[2];
   return GOFD_OK;
 }
 
@@ -1156,6 +1193,7 @@ extern "C" int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde m, double* X_dev, const 
                        nv, s.Jd);
     double h = fixed ? dt : std::min(dt, t_end - t);
     double e1[2] = {I0, 0.0};
+    bool halved = false;
     for (;;) {
       bool ok = false;
       GOFD_TRY(step_solve(ctx, m, X_dev, s, tau, h, cg_tol, max_cg, &ok, &cg_its, T));
@@ -1169,6 +1207,7 @@ extern "C" int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde m, double* X_dev, const 
       }
       h *= 0.5;
       ++rejected;
+      halved = true;
       if (h < 1e-14 || h < 1e-6 * h_max) {
         stalled = true;
         break;
@@ -1181,7 +1220,7 @@ extern "C" int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde m, double* X_dev, const 
     t += h;
     ++steps;
     h_max = std::max(h_max, h);
-    if (!fixed) dt = 2.0 * h;
+    if (!fixed) dt = halved ? h : 2.0 * h;     // after a halving the step is kept, else doubled
   }
   GOFD_TRY(projected_gradient(ctx, m, X_dev, s.MK[acc], s.GK[acc], s, &gn));
   if (g0 < 0) g0 = gn;
