@@ -10,6 +10,7 @@ library can consume its output without sharing any of the method's code.
 from .meshes import (  # noqa: F401
     Mesh,
     disk_mesh,
+    interval_mesh,
     lshape_mesh,
     star_mesh,
     ball_mesh,

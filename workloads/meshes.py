@@ -368,3 +368,14 @@ def ball_mesh(seed: int = 1003, spacing: float = 0.0285, jitter: float = 0.15) -
     vol = np.abs(_signed_volumes(X, tets))
     tets = tets[vol > 1e-9 * spacing ** 3]
     return _finish(X, tets, f"ball(seed={seed})", min_rel_vol=1e-12)
+
+
+def interval_mesh(n: int, seed: int | None = None, jitter: float = 0.0, a: float = -1.0, b: float = 1.0) -> Mesh:
+    """The interval (a, b) in n elements: equispaced vertices, interior ones moved by up to jitter times the
+    spacing (seeded); X is (n+1) x 1, increasing, elements (e, e+1)."""
+    x = np.linspace(a, b, n + 1)
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        x[1:-1] += rng.uniform(-jitter, jitter, n - 1) * (b - a) / n
+    elems = np.stack([np.arange(n), np.arange(1, n + 1)], axis=1).astype(np.int32)
+    return Mesh(x[:, None], elems, f"interval(n={n}, seed={seed})")
