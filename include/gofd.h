@@ -603,6 +603,74 @@ int gofd_mmpde_element_hessians(gofd_ctx ctx, gofd_mmpde mm, const double* X_dev
 int gofd_mmpde_move(gofd_ctx ctx, gofd_mmpde mm, double* X_dev, const double* Mv_dev, const gofd_mmpde_opts* opts,
                     gofd_mmpde_info* info);
 
+/* ---------------------------------------------------------------- GoFD in one dimension */
+
+/* The 1D example of Section 5: the mesh of an interval is its vertices x_0 <
+ * x_1 < .. < x_n (element e = [x_e, x_{e+1}], Dirichlet vertices x_0 and
+ * x_n), the overlay grid has W = 2N+1 nodes z_k = (center - R) + k h, h = R/N
+ * (each operation rounded separately), and T is the closed form of eq.
+ * T-1D-0.  A node belongs to the element of smallest id whose closed
+ * interval holds it (exact comparisons); nodes outside [x_0, x_n] have a zero
+ * row.  A_FD is applied by its circulant embedding of length L = the smallest
+ * power of two >= max(512, 4N) (eq. AU-1); L <= 4096 (N <= 1024), so that one
+ * workgroup holds a line: products and whole CG solves run one workgroup per
+ * field or right-hand side, one launch for all of them.  Vertex vectors have
+ * N_v = n + 1 entries, grid vectors W; several fields or right-hand sides are
+ * stored one after another.  FP64 throughout. */
+typedef struct gofd1d_s* gofd1d;
+
+typedef struct {
+  int W;                  /* grid nodes                                                  */
+  int L;                  /* FFT length                                                  */
+  double h;               /* grid spacing R/N                                            */
+  double a_h;             /* shortest element                                            */
+  double dmin_interior;   /* min D_j over the interior vertices                          */
+  int64_t n_inside;       /* nodes in an element                                         */
+} gofd1d_info;
+
+typedef struct {
+  int iterations;         /* CG iterations                                               */
+  double rel_residual;    /* ||r|| / ||b|| of the recursive residual at exit             */
+  int converged;          /* 1 if ||r|| <= tol ||b||                                     */
+} gofd1d_solve_info;
+
+enum { GOFD1D_ELEM = 0, GOFD1D_WEIGHTS = 1, GOFD1D_D = 2, GOFD1D_T = 3 };
+
+/* Transfer (location, weights, column sums D), T and the spectrum of its
+ * embedding for the mesh x_dev (N_v doubles, strictly increasing; copied),
+ * on the grid (N, R, center), order s in (0, 1).  *out is library-owned,
+ * freed with gofd1d_free.  info (host, nullable).  Synchronises.
+ * Errors: GOFD_E_ARG (N_v < 3, N < 1, R <= 0, s outside (0, 1), vertices
+ * not increasing), GOFD_E_UNSUPPORTED (N > 1024), GOFD_E_RANK (2N+1 < N_v),
+ * GOFD_E_ZERO_COLSUM (an interior vertex touches no node: grid too coarse),
+ * GOFD_E_HIP, GOFD_E_OOM. */
+int gofd1d_create(gofd_ctx ctx, int64_t nv, const double* x_dev, int N, double R, double center, double s,
+                  gofd1d* out, gofd1d_info* info);
+int gofd1d_free(gofd1d h);
+
+/* Copy a part to out_dev: GOFD1D_ELEM (W int32, element of each node or -1),
+ * GOFD1D_WEIGHTS (2W doubles: lambda_0, lambda_1 of each node, 0 outside),
+ * GOFD1D_D (N_v doubles), GOFD1D_T (2N+1 doubles, T_0..T_2N).  Asynchronous.
+ * Errors: GOFD_E_ARG, GOFD_E_HIP. */
+int gofd1d_export(gofd_ctx ctx, gofd1d h, int part, void* out_dev);
+
+/* y = D^{-1} I^T A_FD I u (eq. Ah-1; 0 where D = 0) for nfields fields of N_v
+ * values (u at every vertex, used as given).  Asynchronous.
+ * Errors: GOFD_E_ARG, GOFD_E_HIP, GOFD_E_OOM. */
+int gofd1d_apply_Ah(gofd_ctx ctx, gofd1d h, int nfields, const double* u_dev, double* y_dev);
+
+/* Solves eq. GoFD-2, (I^T A_FD I) u = h^{2s} I^T f on the interior vertices
+ * (u = 0 at x_0 and x_n), for nrhs right-hand sides f given on the grid (W
+ * values each), by CG from u = 0 (precond 0) or CG preconditioned by D_h
+ * (precond 1), stopping when ||r|| <= tol ||b|| or after max_iter iterations
+ * (<= 0: 10 N_v + 100).  Writes u_dev (nrhs x N_v) and info (host, nrhs
+ * entries, nullable).  Synchronises.
+ * Errors: GOFD_E_ARG, GOFD_E_NOT_CONVERGED (some right-hand side reached
+ * max_iter; its best iterate is written), GOFD_E_BREAKDOWN, GOFD_E_HIP,
+ * GOFD_E_OOM. */
+int gofd1d_solve(gofd_ctx ctx, gofd1d h, int nrhs, const double* f_dev, double tol, int max_iter, int precond,
+                 double* u_dev, gofd1d_solve_info* info);
+
 #ifdef __cplusplus
 }
 #endif

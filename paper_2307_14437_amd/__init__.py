@@ -67,6 +67,18 @@ class CgTapeInfo(ctypes.Structure):
                 ("converged", ctypes.c_int)]
 
 
+class Info1D(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int), ("L", ctypes.c_int), ("h", ctypes.c_double), ("a_h", ctypes.c_double),
+                ("dmin_interior", ctypes.c_double), ("n_inside", ctypes.c_int64)]
+
+
+class SolveInfo1D(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double), ("converged", ctypes.c_int)]
+
+
+GOFD1D_ELEM, GOFD1D_WEIGHTS, GOFD1D_D, GOFD1D_T = 0, 1, 2, 3
+
+
 MMPDE_KERNELS = ("hess_fd", "field", "energy", "cg_elem", "cg_vert", "cg_update")
 
 
@@ -152,6 +164,11 @@ def _load():
         "gofd_cg_tape_free": [vp],
         "gofd_autotune": [vp, ctypes.POINTER(_Grid), i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)],
         "gofd_set_schedule": [vp, ctypes.POINTER(_Grid), i32, i32],
+        "gofd1d_create": [vp, i64, vp, i32, dbl, dbl, dbl, ctypes.POINTER(vp), ctypes.POINTER(Info1D)],
+        "gofd1d_free": [vp],
+        "gofd1d_export": [vp, vp, i32, vp],
+        "gofd1d_apply_Ah": [vp, vp, i32, vp, vp],
+        "gofd1d_solve": [vp, vp, i32, vp, dbl, i32, i32, vp, ctypes.POINTER(SolveInfo1D)],
         "gofd_mmpde_create": [vp, i64, i64, vp, i32, ctypes.POINTER(vp)],
         "gofd_mmpde_free": [vp],
         "gofd_mmpde_metric": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl)],
@@ -181,6 +198,7 @@ EXPORTED = [
     "gofd_solve", "gofd_solve_batched",
     "gofd_solve_adjoint", "gofd_time_kernel", "gofd_cg_checkpointed", "gofd_cg_unrolled_grad",
     "gofd_cg_tape_read", "gofd_cg_tape_free",
+    "gofd1d_create", "gofd1d_free", "gofd1d_export", "gofd1d_apply_Ah", "gofd1d_solve",
     "gofd_mmpde_create", "gofd_mmpde_free", "gofd_mmpde_metric", "gofd_mmpde_energy",
     "gofd_mmpde_element_hessians", "gofd_mmpde_move",
 ]
@@ -508,6 +526,67 @@ class CgTape:
     def close(self):
         if getattr(self, "handle", None):
             lib.gofd_cg_tape_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Gofd1D:
+    """GoFD in one dimension (the 1D example of Section 5): a mesh of an interval given by its increasing
+    vertices, the grid (N, R, center), T by the closed form eq. T-1D-0; products and CG solves of eq. GoFD-2
+    run one workgroup per field or right-hand side (FFT length <= 4096)."""
+
+    def __init__(self, ctx: Context, x, N, R, center, s):
+        torch = ctx._torch
+        if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 1:
+            raise TypeError("x must be a 1D CUDA float64 tensor")
+        x = x.contiguous()
+        self.ctx, self.nv, self.N, self.R, self.center, self.s = ctx, int(x.numel()), int(N), float(R), \
+            float(center), float(s)
+        h = ctypes.c_void_p()
+        info = Info1D()
+        ctx.check(lib.gofd1d_create(ctx.handle, self.nv, _ptr(x), self.N, self.R, self.center, self.s,
+                                    ctypes.byref(h), ctypes.byref(info)))
+        self.handle = h
+        self.info = {k: getattr(info, k) for k, _ in Info1D._fields_}
+        self.W = self.info["W"]
+
+    def export(self, part):
+        torch = self.ctx._torch
+        n, dt = {GOFD1D_ELEM: (self.W, torch.int32), GOFD1D_WEIGHTS: (2 * self.W, torch.float64),
+                 GOFD1D_D: (self.nv, torch.float64), GOFD1D_T: (2 * self.N + 1, torch.float64)}[part]
+        out = torch.empty(n, dtype=dt, device="cuda")
+        self.ctx.check(lib.gofd1d_export(self.ctx.handle, self.handle, int(part), _ptr(out)))
+        return out
+
+    def apply_Ah(self, u):
+        """D^{-1} I^T A_FD I u for u of shape (N_v,) or (fields, N_v)."""
+        u = u.contiguous()
+        nf = 1 if u.dim() == 1 else int(u.shape[0])
+        y = self.ctx._torch.empty_like(u)
+        self.ctx.check(lib.gofd1d_apply_Ah(self.ctx.handle, self.handle, nf, _ptr(u), _ptr(y)))
+        return y
+
+    def solve(self, f, tol=1e-10, max_iter=0, precond=0, raise_on_error=True):
+        """u (nrhs, N_v) and per-rhs info for f of shape (W,) or (nrhs, W) on the grid."""
+        torch = self.ctx._torch
+        f = f.contiguous()
+        nrhs = 1 if f.dim() == 1 else int(f.shape[0])
+        u = torch.empty(nrhs, self.nv, dtype=torch.float64, device=f.device)
+        infos = (SolveInfo1D * nrhs)()
+        code = lib.gofd1d_solve(self.ctx.handle, self.handle, nrhs, _ptr(f), float(tol), int(max_iter),
+                                int(precond), _ptr(u), infos)
+        if raise_on_error:
+            self.ctx.check(code)
+        return u, [{k: getattr(i, k) for k, _ in SolveInfo1D._fields_} for i in infos]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.gofd1d_free(self.handle)
             self.handle = None
 
     def __del__(self):

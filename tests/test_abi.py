@@ -64,7 +64,8 @@ def test_struct_layouts_match_binding(tmp_path):
              ("gofd_fdw_opts", gofd.FdwOpts), ("gofd_precond_info", gofd.PrecondInfo),
              ("gofd_solve_opts", gofd.SolveOpts), ("gofd_solve_info", gofd.SolveInfo),
              ("gofd_cg_tape_info", gofd.CgTapeInfo), ("gofd_mmpde_opts", gofd.MmpdeOpts),
-             ("gofd_mmpde_kernel_stats", gofd.MmpdeKernelStats),
+             ("gofd_mmpde_kernel_stats", gofd.MmpdeKernelStats), ("gofd1d_info", gofd.Info1D),
+             ("gofd1d_solve_info", gofd.SolveInfo1D),
              ("gofd_mmpde_info", gofd.MmpdeInfo)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gofd.h"', "int main(void) {"]
     for cname, py in pairs:

@@ -2,6 +2,8 @@
 location ties and nodes outside the mesh, and the fixed-mesh L2 rate of eq. GoFD-2 against the closed-form
 solution (eq. exam-2 with k = 0)."""
 
+import math
+
 import numpy as np
 import pytest
 
@@ -67,3 +69,22 @@ def test_fixed_mesh_l2_rate(s, rate):
     slope = np.polyfit(np.log(2.0 / np.array(ns)), np.log(errs), 1)[0]
     assert errs[-1] < errs[0] / 4
     assert slope > rate - 0.25
+
+
+@pytest.mark.parametrize("s", [0.1, 0.5, 0.9])
+def test_closed_form_T_against_exact_ratios(s):
+    # eq. T-1D-0 gives T_{p+1} / T_p = (p - s) / (p + s + 1): the log-gamma evaluation against rational arithmetic,
+    # within its expected loss of |ln Gamma(p + s + 1)| eps
+    from fractions import Fraction
+    P = 2000
+    T = fw.closed_form_1d(s, P)
+    q = Fraction(str(s))
+    r, ratio = Fraction(1), [1.0]
+    for p in range(P):
+        r = r * (p - q) / (p + q + 1)
+        ratio.append(float(r))
+    ratio = np.array(ratio)
+    rel = np.abs(T / T[0] - ratio) / np.abs(ratio)
+    loss = 8 * np.finfo(float).eps * (1 + np.abs([math.lgamma(p + s + 1) for p in range(P + 1)]))
+    assert np.all(rel <= loss)
+    assert T[0] == pytest.approx(math.gamma(2 * s + 1) / math.gamma(s + 1) ** 2, rel=1e-14)
