@@ -408,11 +408,93 @@ def mmpde_cpu_baseline(mesh, s, recs):
                       "per level; the oracle's GoFD solve not included"}
 
 
+def run_gofd1d(args, nrhs=256, n=900, s=0.5):
+    """GoFD in one dimension: the 1D example of Section 5 (k = 0; f and the exact solution in closed form) on a
+    uniform mesh of (-1, 1) with 900 elements, grid R = 1.1 and h_FD <= a_h / 2 (N = 990, FFT length 4096),
+    s = 0.5, plus 255 further right-hand sides (f + Fourier modes, seeded).  One step = one gofd1d_solve call
+    over the 256 right-hand sides (D_h-preconditioned CG to 1e-10, one workgroup per right-hand side, one
+    launch)."""
+    import numpy as np
+    import torch
+    import paper_2307_14437_amd as gofd
+    from oracle import exact, grid as ogrid
+    from workloads import interval_mesh
+    m = interval_mesh(n)
+    N = int(np.ceil(1.1 * n))
+    z = ogrid.node_coords(1, N, 1.1, (0.0,))
+    f0 = exact.f_ball(z, s, 1, 0)
+    rng = np.random.default_rng(1005)
+    F = np.stack([f0] + [f0 + sum(rng.standard_normal() * np.cos(np.pi * a * (z[:, 0] + 1.1) / 2.2)
+                                  for a in range(1, 5)) for _ in range(nrhs - 1)])
+    ctx = gofd.Context()
+    g = gofd.Gofd1D(ctx, torch.tensor(m.X[:, 0], device="cuda"), N, 1.1, 0.0, s)
+    Fd = torch.tensor(F, device="cuda")
+    tol = 1e-10
+    for _ in range(args.warmup):
+        g.solve(Fd, tol=tol, precond=1)
+    _sync(); t = time.perf_counter()
+    for _ in range(args.steps):
+        u, infos = g.solve(Fd, tol=tol, precond=1)
+    _sync()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    its = [i["iterations"] for i in infos]
+    ue = exact.u_ball(m.X, s, 1, 0)
+    e = u[0].cpu().numpy() - ue
+    dx = np.diff(m.X[:, 0])
+    l2 = lambda v: float(np.sqrt(np.sum(dx / 3 * (v[:-1] ** 2 + v[:-1] * v[1:] + v[1:] ** 2))))
+    L = g.info["L"]
+    # flops of one CG iteration of one right-hand side: two complex transforms of length L (5 L log2 L each), the
+    # spectrum product, the gather and scatter (two weights per node), the vector updates and dots
+    fl_it = 2 * 5 * L * int(np.log2(L)) + 2 * L + 8 * g.W + 20 * m.nv
+    flops = fl_it * sum(its) + 0.0
+    achieved = flops / (ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = gofd1d_cpu_baseline(m, N, s, F[0], tol)
+    line = {
+        "metric": "1D GoFD solves/s (CG of eq. GoFD-2 to 1e-10, one workgroup per right-hand side)",
+        "value": nrhs / (ms * 1e-3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"1D example (k = 0, s = {s}) on a uniform mesh of (-1, 1) with {n} elements, "
+                               f"grid R = 1.1, N = {N} (W = {g.W}, FFT length {L}), {nrhs} right-hand sides, "
+                               "D_h-preconditioned CG to 1e-10"},
+        "iterations_min_max": [min(its), max(its)],
+        "rel_l2_error_vs_exact": l2(e) / l2(ue),
+        "roofline": {"bound": "alu", "kernel": f"k1_cg<{L}>", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": achieved / 78.6, "traffic": None,
+                     "flops_per_launch": flops, "note": "one launch per step; the line transforms run in LDS"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def gofd1d_cpu_baseline(m, N, s, f, tol, repeats=3):
+    """The oracle's CG of eq. GoFD-2 with FFT products (numpy/scipy on the host cores) for one right-hand side of
+    the workload, median of 3."""
+    import numpy as np
+    from oracle import afd, fdweights as fw, operator, solve, transfer
+    tr = transfer.Transfer(m.X, m.elems, 1, N, 1.1, (0.0,))
+    T = fw.closed_form_1d(s, 2 * N)
+    b = operator.rhs_grid(tr, s, f)
+    Dj = tr.D[tr.J]
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        _, its, _ = solve.pcg(lambda v: operator.apply_K(tr, T, v, "fft"), b, tol=tol, maxiter=5000,
+                              precond=lambda r: r / Dj)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    return {"value": 1.0 / med, "unit": "solves/s", "cores": afd.WORKERS, "kind": "oracle",
+            "sample": f"one right-hand side of the workload, D_h-preconditioned CG with FFT products ({its} "
+                      f"iterations), median of {repeats}: {[round(t, 3) for t in times]} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "amgofd"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "amgofd", "gofd1d"],
                     help="c2: the L-shape workload (default); c4: the 64-mesh batched workload; amgofd: Algorithm "
-                         "amGoFD (MMPDE adaptation) on the disk")
+                         "amGoFD (MMPDE adaptation) on the disk; gofd1d: the 1D example, 256 right-hand sides")
     ap.add_argument("--c4-tol", type=float, default=1e-9, help="c4: relative residual of the timed solves")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -448,6 +530,9 @@ def main():
         return
     if args.workload == "amgofd":
         run_amgofd(args)
+        return
+    if args.workload == "gofd1d":
+        run_gofd1d(args)
         return
 
     import numpy as np

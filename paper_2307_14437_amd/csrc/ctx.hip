@@ -252,10 +252,12 @@ static void scan_levels(hipStream_t st, const int32_t* in, int32_t* out, int64_t
   }
 }
 
+int scan_prepare(gofd_ctx_s* ctx, int64_t n) { return dev_reserve(ctx, ctx->scan_ws, sizeof(int32_t) * scan_ws_ints(n)); }
+
 // out[0..n] = exclusive prefix sums of in[0..n) and the total, on the context's stream (no host round trip;
 // the levels' block sums live in a workspace of the context)
 int scan_exclusive_i32(gofd_ctx_s* ctx, const int32_t* in, int32_t* out, int64_t n) {
-  GOFD_TRY(dev_reserve(ctx, ctx->scan_ws, sizeof(int32_t) * scan_ws_ints(n)));
+  GOFD_TRY(scan_prepare(ctx, n));
   scan_levels(ctx->stream, in, out, n, ctx->scan_ws.as<int32_t>());
   hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, ctx->stream, in, out, n);
   HIP_TRY(ctx, hipGetLastError());

@@ -247,6 +247,8 @@ __device__ __forceinline__ float2 gload(const float2* p, long long i) {
 
 // Exclusive scan of int32 counts (n entries) into out (n+1 entries).
 int scan_exclusive_i32(gofd_ctx_s* ctx, const int32_t* in, int32_t* out, int64_t n);
+// reserve the scan's workspace for n values ahead of time (so that a timed scan allocates nothing)
+int scan_prepare(gofd_ctx_s* ctx, int64_t n);
 
 // Grid-space convolution y = A_FD v for fields on the grid; `src` selects how
 // the field is produced (from a grid array or gathered from vertex values).

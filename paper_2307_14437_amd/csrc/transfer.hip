@@ -702,6 +702,7 @@ extern "C" int gofd_build_transfer(gofd_ctx ctx, int d, int64_t nv, const double
   else
     TR_LAUNCH(tm, GOFD_TR_K_COUNT, k_count<3>, dim3(grid1(n_nodes, 256)), dim3(256), st, tr->elem.as<int>(),
               tr->elems.as<int>(), n_nodes, cnt.as<int>());
+  GOFD_TRY(scan_prepare(ctx, nv));
   if (tm.ok) HIP_TRY(ctx, hipEventRecord(tm.ev[GOFD_TR_K_SCAN][0], st));
   GOFD_TRY(scan_exclusive_i32(ctx, cnt.as<int32_t>(), tr->csc_off.as<int32_t>(), nv));
   if (tm.ok) HIP_TRY(ctx, hipEventRecord(tm.ev[GOFD_TR_K_SCAN][1], st));
