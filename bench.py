@@ -500,7 +500,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precond", default="NONE", choices=["NONE", "DIAG", "IC1_9", "IC1_5"])
-    ap.add_argument("--drop", type=float, default=0.1,
+    ap.add_argument("--drop", type=float, default=0.03,
                     help="FP32 mode: residual drop between FP64 residual replacements")
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="restarted-refinement comparison: inner tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
