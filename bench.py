@@ -553,6 +553,13 @@ def main():
     _sync(); t = time.perf_counter()
     tr = gofd.Transfer(ctx, X, E, g)
     _sync(); setup["build_transfer_ms"] = (time.perf_counter() - t) * 1e3
+    # the first build also loads the library's code objects (the first launch of a kernel from a source file
+    # does, between the stage events); a second build of the same mesh gives the stages' steady-state times
+    t = time.perf_counter()
+    tr_warm = gofd.Transfer(ctx, X, E, g)
+    _sync(); setup["build_transfer_ms_warm"] = (time.perf_counter() - t) * 1e3
+    transfer_us = dict(tr_warm.info["kernel_us"])
+    del tr_warm
     ops, pcs = [], []
     for s in svals:
         _sync(); t = time.perf_counter()
@@ -694,7 +701,7 @@ def main():
     tb = _transfer_kernel_bytes(2, tr.nv, tr.ne, tr.info["n_nodes"], tr.info["n_inside"], tr.info["nnz"])
     transfer_kernels = {k: {"us": us, "bytes": tb[k], "GBs": tb[k] / (us * 1e-6) / 1e9 if us > 0 else None,
                             "frac": tb[k] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS if us > 0 else None}
-                        for k, us in tr.info["kernel_us"].items()}
+                        for k, us in transfer_us.items()}
     its64 = {s: info64[i]["iterations"] for i, s in enumerate(svals)}
     line = {
         "metric": "PCG solves/s + A_h matvec Gpts/s, batched FP32+refine vs plain FP64 @1e-8",

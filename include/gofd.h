@@ -311,10 +311,10 @@ typedef struct {
  * kind, the vertices are first coloured greedily (in vertex order, each the
  * smallest colour none of its neighbours in A^(p) has) and ordered by
  * (colour, vertex); the factor is that of P A P^T with level-1 fill kept only
- * between vertices of different colours, so it has at most as many dependency
- * levels as colours and each level is one device-wide launch.  Setup runs on
- * the host (the factor is sequential by nature); applies run on the device.
- * info nullable. */
+ * between vertices of different colours, so a colour's rows depend only on
+ * rows of other colours: each colour is one device-wide launch per triangular
+ * solve (GOFD_E_UNSUPPORTED above 64 colours).  Setup runs on the host (the
+ * factor is sequential by nature); applies run on the device.  info nullable. */
 int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int kind, gofd_precond* out,
                         gofd_precond_info* info);
 int gofd_precond_free(gofd_precond pc);

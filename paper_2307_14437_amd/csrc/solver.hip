@@ -586,6 +586,86 @@ __global__ __launch_bounds__(256) void k_trsv_level(const int* __restrict__ ptr,
   if (ok && lane == 0) y[row] = (b[row] - s) / val[dpos];
 }
 
+// One colour of the triangular solves in multicolour order: the factor's rows
+// r0..r1-1 (row t is vertex perm[t]) depend only on rows of colours that
+// earlier launches solved, so the colour is solved in one launch, its rows
+// contiguous.  TRSV_LANES lanes share a row and each reads its first two
+// entries without waiting (the index clamped into the row, the product masked),
+// any further ones in a loop.
+//   LOWER:  y_t = (r[perm t] - sum_{j<t} L_tj y_j) / L_tt.  With TAIL (the last
+//           colour) the row of U = L^T is solved as well: no row of a later
+//           colour exists, so u_t = y_t / L_tt.
+//   upper:  u_t = (y_t - sum_{j>t} U_tj u_j) / U_tt.
+// A solved u_t goes to pu (factor order, read by later colours) and to
+// u[perm t] (vertex order).  With part given (gamma of CG), block b of the
+// grid-stride launch adds r[perm t] u_t of its rows to part[b]; the TAIL
+// launch, the first of the upper solves, stores instead, so after colour 0
+// part holds the partials of (r, u) in a fixed order.
+template <bool LOWER, bool TAIL>
+__global__ __launch_bounds__(256) void k_trsv_colour(const int* __restrict__ ptr, const int* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const int* __restrict__ perm, int r0, int r1,
+                                                     const double* __restrict__ r, double* __restrict__ y,
+                                                     double* __restrict__ pu, double* __restrict__ u,
+                                                     long long stride, const Scal* __restrict__ sc,
+                                                     double* __restrict__ part, int nbu) {
+  constexpr int RPB = 256 / TRSV_LANES;   // rows per block and pass
+  __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
+  const int k = blockIdx.y;
+  if (sc && sc[k].done) return;
+  const int lane = threadIdx.x % TRSV_LANES;
+  const double* rk = r + k * stride;
+  double* yk = y + k * stride;
+  double* puk = pu + k * stride;
+  const double* dep = LOWER ? yk : puk;
+  const int nrows = r1 - r0;
+  double acc = 0.0;
+  for (int base = blockIdx.x * RPB; base < nrows; base += gridDim.x * RPB) {
+    const int tt = base + (int)threadIdx.x / TRSV_LANES;
+    const bool ok = tt < nrows;
+    const int t = r0 + (ok ? tt : 0);
+    const int e0 = ptr[t], e1 = ptr[t + 1];
+    const int v = perm[t];
+    const int dpos = LOWER ? e1 - 1 : e0;
+    const int lo = LOWER ? e0 : e0 + 1, hi = LOWER ? e1 - 1 : e1;
+    const int ia = lo + lane, ib = ia + TRSV_LANES;
+    const int ca = ia < hi ? ia : dpos, cb = ib < hi ? ib : dpos;
+    const double rv = rk[v];
+    const double rhs = LOWER ? rv : yk[t];
+    const double d = val[dpos];
+    const double va = val[ca], vb = val[cb];
+    const int ja = col[ca], jb = col[cb];
+    // past the row's end the load re-reads the entry's own value (never a
+    // location this launch writes) and the product is masked
+    const double xa = *(ia < hi ? dep + ja : val + ca);
+    const double xb = *(ib < hi ? dep + jb : val + cb);
+    double s = (ia < hi ? va * xa : 0.0) + (ib < hi ? vb * xb : 0.0);
+    for (int i = ib + TRSV_LANES; i < hi; i += TRSV_LANES) s += val[i] * dep[col[i]];
+#pragma unroll
+    for (int o = TRSV_LANES / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, TRSV_LANES);
+    if (ok && lane == 0) {
+      const double yt = (rhs - s) / d;
+      if (LOWER && !TAIL) {
+        yk[t] = yt;
+      } else {
+        const double ut = TAIL ? yt / d : yt;
+        puk[t] = ut;
+        u[k * stride + v] = ut;
+        acc += rv * ut;
+      }
+    }
+  }
+  if (LOWER && !TAIL) return;
+  if (part) {
+    double s1[1] = {acc};
+    gofd_cg::block_sum_n<256, 1>(s1, sh);
+    if (threadIdx.x == 0) {
+      double* p = part + (long long)k * nbu + blockIdx.x;
+      *p = TAIL ? s1[0] : *p + s1[0];
+    }
+  }
+}
+
 // out[i] = in[perm[i]] (to = true) or out[perm[i]] = in[i], per right-hand side blockIdx.y
 template <bool TO>
 __global__ void k_permute(const double* __restrict__ in, const int* __restrict__ perm, long long n,
@@ -634,6 +714,7 @@ struct gofd_precond_s {
   DevBuf perm;
   std::vector<int32_t> hperm;
   std::vector<int32_t> hLlp, hUlp;   // level boundaries (host copies for the per-level launches)
+  std::vector<int32_t> hcp;          // multicolour order: rows of colour c are hcp[c]..hcp[c+1]-1
   gofd_precond_info info{};
 };
 
@@ -700,6 +781,8 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     // vertices of different colours, so a colour's rows never depend on each other
     std::vector<int32_t> colour;
     pc->info.colours = greedy_colouring(A, colour);
+    if (pc->info.colours > TRSV_LEVEL_LAUNCH_MAX)
+      return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "multicolour order needs more than 64 colours");
     pc->hperm.resize(A.n);
     for (int64_t i = 0; i < A.n; ++i) pc->hperm[i] = (int32_t)i;
     std::stable_sort(pc->hperm.begin(), pc->hperm.end(),
@@ -712,6 +795,9 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     std::vector<int32_t> pcol(A.n);
     for (int64_t i = 0; i < A.n; ++i) pcol[i] = colour[pc->hperm[i]];
     colour.swap(pcol);
+    pc->hcp.assign(pc->info.colours + 1, 0);
+    for (int64_t i = 0; i < A.n; ++i) pc->hcp[colour[i] + 1]++;
+    for (int c = 0; c < pc->info.colours; ++c) pc->hcp[c + 1] += pc->hcp[c];
     ic_symbolic(A, 1, Lptr, Lcol);
     drop_same_colour(colour, Lptr, Lcol);
   } else {
@@ -1111,6 +1197,37 @@ int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, doub
     const long long n = P.tr->nv, o = B.poff[q];
     const int i0 = B.pitem[q];
     const Scal* scq = sc ? sc + i0 : nullptr;
+    if (!pc->hcp.empty() && (int)pc->hcp.size() - 1 <= TRSV_LEVEL_LAUNCH_MAX) {
+      // multicolour order: one launch per colour and direction, the last
+      // colour's upper rows solved in the last lower launch; the permutation
+      // and gamma's partials are part of the launches
+      const int C = (int)pc->hcp.size() - 1;
+      const double* rin = w.r.as<double>() + o;
+      double* y = w.dvec.as<double>() + o;
+      double* pu = w.pu.as<double>() + o;
+      double* u = w.u.as<double>() + o;
+      double* part = partG ? partG + (long long)i0 * w.nbs : nullptr;
+      const int* perm_d = pc->perm.as<int>();
+      auto grid_rows = [&](int rows) {
+        return dim3(part ? w.nbs : grid1((long long)std::max(rows, 1) * TRSV_LANES, 256), P.nrhs);
+      };
+      for (int c = 0; c + 1 < C; ++c) {
+        const int r0 = pc->hcp[c], r1 = pc->hcp[c + 1];
+        hipLaunchKernelGGL((k_trsv_colour<true, false>), dim3(grid1((long long)std::max(r1 - r0, 1) * TRSV_LANES, 256), P.nrhs),
+                           dim3(256), 0, st, pc->Lptr.as<int>(), pc->Lcol.as<int>(), pc->Lval.as<double>(), perm_d, r0,
+                           r1, rin, y, pu, u, n, scq, nullptr, 0);
+      }
+      hipLaunchKernelGGL((k_trsv_colour<true, true>), grid_rows(pc->hcp[C] - pc->hcp[C - 1]), dim3(256), 0, st,
+                         pc->Lptr.as<int>(), pc->Lcol.as<int>(), pc->Lval.as<double>(), perm_d, pc->hcp[C - 1],
+                         pc->hcp[C], rin, y, pu, u, n, scq, part, w.nbs);
+      for (int c = C - 2; c >= 0; --c) {
+        const int r0 = pc->hcp[c], r1 = pc->hcp[c + 1];
+        hipLaunchKernelGGL((k_trsv_colour<false, false>), grid_rows(r1 - r0), dim3(256), 0, st, pc->Uptr.as<int>(),
+                           pc->Ucol.as<int>(), pc->Uval.as<double>(), perm_d, r0, r1, rin, y, pu, u, n, scq, part,
+                           w.nbs);
+      }
+      continue;
+    }
     if (pc->Lnlev <= TRSV_LEVEL_LAUNCH_MAX && pc->Unlev <= TRSV_LEVEL_LAUNCH_MAX) {
       // few levels: one launch per level over the device; vectors in the
       // factor's order when it has one (pr, pu: permuted r and u)
