@@ -291,7 +291,11 @@ typedef enum {
   GOFD_PC_IC1_5 = 5,      /* IC(1) of I^T A_FD^(5) I  (Section 3.3, 2D)                     */
   GOFD_PC_IC1_9 = 9,      /* IC(1) of I^T A_FD^(9) I  (Section 3.3, 2D)                     */
   GOFD_PC_IC1_27 = 27,    /* IC(1) of I^T A_FD^(27) I (Example 4, 3D)                       */
-  GOFD_PC_MULTICOLOR = 256  /* flag added to an IC kind: the factor in multicolour order      */
+  GOFD_PC_MULTICOLOR = 256, /* flag added to an IC kind: the factor in multicolour order      */
+  GOFD_PC_LAPLACIAN = 512,  /* flag added to an IC kind: the discrete Laplacian on the kind's
+                               pattern in place of A_FD's entries (Section 3.3)              */
+  GOFD_PC_BLOCK_MULTICOLOR = 1024 /* flag added to an IC kind: the factor in block multicolour
+                               order (exclusive with GOFD_PC_MULTICOLOR)                     */
 } gofd_pc_kind;
 
 typedef struct {
@@ -313,7 +317,20 @@ typedef struct {
  * (colour, vertex); the factor is that of P A P^T with level-1 fill kept only
  * between vertices of different colours, so a colour's rows depend only on
  * rows of other colours: each colour is one device-wide launch per triangular
- * solve (GOFD_E_UNSUPPORTED above 64 colours).  Setup runs on the host (the
+ * solve (GOFD_E_UNSUPPORTED above 64 colours).  With GOFD_PC_LAPLACIAN added,
+ * the matrix factored is I^T (-Delta_h) I with the discrete Laplacian on the
+ * kind's pattern (up to a factor: p - 1 at the centre, -1 at the other p - 1
+ * points; the standard 5-point one and the isotropic 9- and 27-point ones), the
+ * Laplacian taking the place of A_FD in the stiffness matrix as Section 3.3
+ * allows; it does not depend on s.  With GOFD_PC_BLOCK_MULTICOLOR added: the
+ * vertices are grouped into blocks of at most 16 (in vertex order, a vertex
+ * not yet placed starts a block that takes unplaced vertices breadth first,
+ * neighbours in A^(p) in increasing order), the graph of the blocks is
+ * coloured greedily in block order, the vertices are ordered by (block
+ * colour, block, vertex), and the level-1 fill is kept inside a block and
+ * between different colours: one device-wide launch per colour and solve,
+ * each block's own rows solved within one wavefront; colours reports the
+ * block colours.  Setup runs on the host (the
  * factor is sequential by nature); applies run on the device.  info nullable. */
 int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, int kind, gofd_precond* out,
                         gofd_precond_info* info);

@@ -24,6 +24,14 @@ has), order the vertices by (colour, index), and factor P A P^T with the
 level-1 fill kept only between vertices of different colours.  Vertices of
 one colour are then never coupled in the factor, so a triangular solve has at
 most as many dependency levels as there are colours.
+
+Block multicolour variant (the same reading with blocks of at most 16
+vertices grown breadth first, the blocks coloured instead of the vertices;
+ic1_block_multicolour): far fewer colours, each block's own rows solved in
+sequence.
+
+Laplacian variant: the discrete Laplacian on the pattern in place of A_FD's
+entries (laplacian_table), the alternative Section 3.3 names.
 """
 
 from __future__ import annotations
@@ -73,9 +81,22 @@ def afd_pattern_matrix(T, d, W, npts) -> sp.csr_matrix:
 
 
 def Ah_pattern(tr, T, npts) -> sp.csr_matrix:
-    """A_h^(p) = I_J^T A_FD^(p) I_J on the interior block (eq. Ah-4)."""
+    """A_h^(p) = I_J^T A_FD^(p) I_J on the interior block (eq. Ah-4).  T is indexed by the absolute offsets
+    (|o_{d-1}|, ..., |o_0|): the table of A_FD, or laplacian_table(d, npts)."""
     Ap = afd_pattern_matrix(T, tr.d, tr.W, npts)
     return (tr.IJ.T @ Ap @ tr.IJ).tocsr()
+
+
+def laplacian_table(d: int, npts: int) -> np.ndarray:
+    """The discrete Laplacian on the p-point pattern, to take the place of A_FD in the stiffness matrix
+    (Section 3.3 names the direct use of the Laplacian as a preconditioner): p - 1 at the centre and -1 at each
+    of the other p - 1 points, i.e. h^2 (-Delta_h) for the standard 5-point stencil and a multiple of it for the
+    isotropic 9-point (factor 3) and compact 27-point stencils.  The factor does not change preconditioned CG.
+    Indexed like T, by absolute offsets (all at most 1)."""
+    stencil_offsets(d, npts)                        # only the supported patterns
+    t = np.full((2,) * d, -1.0)
+    t[(0,) * d] = npts - 1
+    return t
 
 
 def ic1_pattern(A: sp.csr_matrix, level: int = 1):
@@ -206,6 +227,63 @@ def ic1_multicolour(A: sp.csr_matrix, level: int = 1):
         L, ok = ic_numeric(As, pattern)
         if ok:
             return L, perm, cp, alpha
+        alpha = 1e-3 if alpha == 0.0 else 2 * alpha
+
+
+def grow_blocks(A: sp.csr_matrix, size: int) -> np.ndarray:
+    """Block of each vertex: vertices in index order, each not yet in a block starts one, which then takes
+    not yet placed vertices breadth first (a vertex's neighbours in increasing index) until it has `size`."""
+    A = sp.csr_matrix(A, copy=True)
+    A.sort_indices()
+    n = A.shape[0]
+    blk = -np.ones(n, dtype=np.int64)
+    nb = 0
+    for v in range(n):
+        if blk[v] >= 0:
+            continue
+        blk[v] = nb
+        queue, head, count = [v], 0, 1
+        while head < len(queue) and count < size:
+            u = queue[head]
+            head += 1
+            for j in A.indices[A.indptr[u]:A.indptr[u + 1]]:
+                if count == size:
+                    break
+                if blk[j] < 0:
+                    blk[j] = nb
+                    queue.append(int(j))
+                    count += 1
+        nb += 1
+    return blk
+
+
+def ic1_block_multicolour(A: sp.csr_matrix, size: int = 16, level: int = 1):
+    """Block multicolour IC(level), a reading for triangular solves with few device-wide steps: vertices are
+    grouped into blocks of at most `size` (grow_blocks), the graph of the blocks (two blocks adjacent when A
+    couples a vertex of one to a vertex of the other) is coloured greedily in block order, the vertices are
+    ordered by (colour of their block, block, index) and P A P^T is factored keeping the level-`level` fill
+    inside a block and between blocks of different colours (blocks of one colour are never coupled, so a
+    triangular solve takes one step per colour, each block solved on its own).  Returns (L, perm, block of
+    each factor row, colour of each factor row, alpha)."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    blk = grow_blocks(A, size)
+    nb = int(blk.max()) + 1 if n else 0
+    Ac = A.tocoo()
+    off = blk[Ac.row] != blk[Ac.col]
+    G = sp.csr_matrix((np.ones(int(off.sum())), (blk[Ac.row[off]], blk[Ac.col[off]])), shape=(nb, nb))
+    bcol = greedy_colouring(G)
+    perm = np.lexsort((np.arange(n), blk, bcol[blk]))
+    Ap = A[perm][:, perm].tocsr()
+    pb = blk[perm]
+    pc = bcol[pb]
+    pattern = [[j for j in row if pb[j] == pb[i] or pc[j] != pc[i]] for i, row in enumerate(ic1_pattern(Ap, level))]
+    alpha = 0.0
+    while True:
+        As = Ap if alpha == 0.0 else (Ap + alpha * sp.diags(Ap.diagonal())).tocsr()
+        L, ok = ic_numeric(As, pattern)
+        if ok:
+            return L, perm, pb, pc, alpha
         alpha = 1e-3 if alpha == 0.0 else 2 * alpha
 
 

@@ -31,9 +31,16 @@ FP32_GRID, SYMMETRIC, UNSCALED, SCALE_H2S, INTERIOR = 1, 2, 4, 8, 16
 # preconditioners
 PC_NONE, PC_DIAG, PC_IC1_5, PC_IC1_9, PC_IC1_27 = 0, 1, 5, 9, 27
 PC_MULTICOLOR = 256
-PC_BY_NAME = {"NONE": PC_NONE, "DIAG": PC_DIAG, "IC1_5": PC_IC1_5, "IC1_9": PC_IC1_9, "IC1_27": PC_IC1_27,
-              "IC1_5_MC": PC_IC1_5 | PC_MULTICOLOR, "IC1_9_MC": PC_IC1_9 | PC_MULTICOLOR,
-              "IC1_27_MC": PC_IC1_27 | PC_MULTICOLOR}
+PC_LAPLACIAN = 512
+PC_BLOCK_MULTICOLOR = 1024
+PC_BY_NAME = {"NONE": PC_NONE, "DIAG": PC_DIAG}
+for _p, _k in (("5", PC_IC1_5), ("9", PC_IC1_9), ("27", PC_IC1_27)):
+    # IC1_<p>: A_FD on the pattern; _LAP: the discrete Laplacian on it; _MC: multicolour order, _BMC: block
+    # multicolour order
+    for _lap, _fl in (("", 0), ("_LAP", PC_LAPLACIAN)):
+        PC_BY_NAME[f"IC1_{_p}{_lap}"] = _k | _fl
+        PC_BY_NAME[f"IC1_{_p}{_lap}_MC"] = _k | _fl | PC_MULTICOLOR
+        PC_BY_NAME[f"IC1_{_p}{_lap}_BMC"] = _k | _fl | PC_BLOCK_MULTICOLOR
 
 F_GRID, F_VERTEX = 0, 1
 MODE_FP64, MODE_FP32_REFINE, MODE_FP32_RELIABLE = 0, 1, 2

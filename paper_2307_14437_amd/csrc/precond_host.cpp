@@ -42,7 +42,9 @@ Pattern stencil(int d, int npts) {
 }  // namespace
 
 // A = I_J^T A^(p) I_J as CSR over all vertices (Dirichlet rows/cols dropped).
-bool assemble_pattern_matrix(const HostTransfer& t, const double* T, int npts, HostCsr& A) {
+// T holds the stencil values by |offset| in the octant layout with row length
+// Wt (axis 0 fastest): the table of A_FD (Wt = W), or a 2^d table.
+bool assemble_pattern_matrix(const HostTransfer& t, const double* T, int64_t Wt, int npts, HostCsr& A) {
   const int d = t.d, W = t.W;
   Pattern pat = stencil(d, npts);
   if (pat.n == 0) return false;
@@ -74,8 +76,8 @@ bool assemble_pattern_matrix(const HostTransfer& t, const double* T, int npts, H
           const int32_t e2 = t.elem[k2];
           if (e2 < 0) continue;
           // T at |offset| (octant layout, axis 0 fastest)
-          int64_t ti = std::abs(pat.off[0][q]) + (int64_t)W * std::abs(pat.off[1][q]);
-          if (d == 3) ti += (int64_t)W * W * std::abs(pat.off[2][q]);
+          int64_t ti = std::abs(pat.off[0][q]) + Wt * std::abs(pat.off[1][q]);
+          if (d == 3) ti += Wt * Wt * std::abs(pat.off[2][q]);
           const double tv = T[ti];
           for (int r = 0; r < d1; ++r) {
             const int32_t j2 = t.elems[(int64_t)e2 * d1 + r];
@@ -251,7 +253,54 @@ void permute_symmetric(const HostCsr& A, const std::vector<int32_t>& perm, HostC
   }
 }
 
-void drop_same_colour(const std::vector<int32_t>& colour, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol) {
+int grow_blocks(const HostCsr& A, int size, std::vector<int32_t>& blk) {
+  const int64_t n = A.n;
+  blk.assign(n, -1);
+  std::vector<int32_t> queue;
+  int nb = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (blk[v] >= 0) continue;
+    blk[v] = nb;
+    queue.assign(1, (int32_t)v);
+    size_t head = 0;
+    int count = 1;
+    while (head < queue.size() && count < size) {
+      const int32_t u = queue[head++];
+      for (int64_t e = A.rowptr[u]; e < A.rowptr[u + 1] && count < size; ++e) {
+        const int32_t j = A.col[e];
+        if (blk[j] < 0) {
+          blk[j] = nb;
+          queue.push_back(j);
+          ++count;
+        }
+      }
+    }
+    ++nb;
+  }
+  return nb;
+}
+
+void block_graph(const HostCsr& A, const std::vector<int32_t>& blk, int nb, HostCsr& G) {
+  std::vector<std::vector<int32_t>> adj(nb);
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int64_t e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
+      if (blk[A.col[e]] != blk[i]) adj[blk[i]].push_back(blk[A.col[e]]);
+  G.n = nb;
+  G.rowptr.assign(nb + 1, 0);
+  G.col.clear();
+  G.val.clear();
+  for (int b = 0; b < nb; ++b) {
+    auto& a = adj[b];
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+    G.col.insert(G.col.end(), a.begin(), a.end());
+    G.rowptr[b + 1] = (int64_t)G.col.size();
+  }
+  G.val.assign(G.col.size(), 1.0);
+}
+
+void drop_same_colour(const std::vector<int32_t>& colour, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol,
+                      const std::vector<int32_t>* group) {
   const int64_t n = (int64_t)Lptr.size() - 1;
   std::vector<int64_t> ptr(n + 1, 0);
   std::vector<int32_t> col;
@@ -259,7 +308,7 @@ void drop_same_colour(const std::vector<int32_t>& colour, std::vector<int64_t>& 
   for (int64_t i = 0; i < n; ++i) {
     for (int64_t e = Lptr[i]; e < Lptr[i + 1]; ++e) {
       const int32_t j = Lcol[e];
-      if (j == i || colour[j] != colour[i]) col.push_back(j);
+      if (j == i || colour[j] != colour[i] || (group && (*group)[j] == (*group)[i])) col.push_back(j);
     }
     ptr[i + 1] = (int64_t)col.size();
   }

@@ -22,7 +22,7 @@ struct HostCsr {
   std::vector<double> val;
 };
 
-bool assemble_pattern_matrix(const HostTransfer& t, const double* T, int npts, HostCsr& A);
+bool assemble_pattern_matrix(const HostTransfer& t, const double* T, int64_t Wt, int npts, HostCsr& A);
 void ic_symbolic(const HostCsr& A, int level, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol);
 bool ic_numeric(const HostCsr& A, double shift, const std::vector<int64_t>& Lptr, const std::vector<int32_t>& Lcol,
                 std::vector<double>& Lval);
@@ -32,5 +32,15 @@ int greedy_colouring(const HostCsr& A, std::vector<int32_t>& colour);
 // B = P A P^T for the order perm (B_ij = A_{perm[i], perm[j]}), rows sorted.
 void permute_symmetric(const HostCsr& A, const std::vector<int32_t>& perm, HostCsr& B);
 // Drop the off-diagonal entries of a lower pattern that join two vertices of
-// the same colour (colour given in the pattern's numbering).
-void drop_same_colour(const std::vector<int32_t>& colour, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol);
+// the same colour (colour given in the pattern's numbering), except, with
+// group given, those inside one group.
+void drop_same_colour(const std::vector<int32_t>& colour, std::vector<int64_t>& Lptr, std::vector<int32_t>& Lcol,
+                      const std::vector<int32_t>* group = nullptr);
+// Blocks of at most `size` vertices: in index order, a vertex not yet in a
+// block starts one, which takes not yet placed vertices breadth first (a
+// vertex's neighbours in increasing index, rows of A sorted) until full.
+// Returns the block count; blk[v] is v's block.
+int grow_blocks(const HostCsr& A, int size, std::vector<int32_t>& blk);
+// The graph of the blocks: b and c adjacent when A couples a vertex of b to
+// one of c (b != c); rows sorted, no self entries.
+void block_graph(const HostCsr& A, const std::vector<int32_t>& blk, int nb, HostCsr& G);

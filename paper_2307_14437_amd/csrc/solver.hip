@@ -666,6 +666,114 @@ __global__ __launch_bounds__(256) void k_trsv_colour(const int* __restrict__ ptr
   }
 }
 
+// Block multicolour order: at most BMC_BLOCK rows per block, one wave per
+// block, four lanes per row; lane (i, q) of a wave holds row i's entries
+// (i, q + 4m), m = 0..3, of the block's own matrix (layout of the block
+// arrays: (j / 4) * 64 + i * 4 + j % 4).
+constexpr int BMC_BLOCK = 16;
+
+// x + x from the lane given by a quad permutation (DPP, no LDS): quad_perm
+// [1,0,3,2] (0xB1) adds the neighbour at xor 1, [2,3,0,1] (0x4E) at xor 2
+template <int CTRL>
+__device__ __forceinline__ double quad_add(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return x + __hiloint2double(hi, lo);
+}
+
+// x_i = sum_j m_ij b_j over the block (m the inverse of the block's own
+// triangle): lane (i, q) fetches b of rows q + 4m from their lanes, adds its
+// four products, and the row's four lanes add their sums
+__device__ __forceinline__ double block_product(const double (&m4)[4], double b, int q) {
+  double p = 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) p = fma(m4[m], __shfl(b, 4 * (q + 4 * m)), p);
+  return quad_add<0x4E>(quad_add<0xB1>(p));
+}
+
+// One colour of the triangular solves in block multicolour order: the
+// colour's blocks b0..b1-1 (rows bs[b]..bs[b+1]-1 of the factor's order, row t
+// is vertex perm[t]) depend only on blocks of colours that earlier launches
+// solved.  A wave takes one block at a time (four per workgroup, grid-stride):
+// the lanes of a row add the row's entries to other blocks (the block's slabs
+// of 64 entries, eoff[b]..eoff[b+1]-1, lane i * 4 + q of slab a holding entry
+// q + 4a of row i or -1; four slabs in flight), giving b_t, and the block's
+// rows then follow from the inverse of its own triangle (formed on the host):
+//   LOWER:  y = L_bb^{-1} (r[perm] - L_b,other y_other).  With TAIL (the last
+//           colour) the wave goes on to the block's rows of U = L^T, which
+//           need no other block: u = U_bb^{-1} y.
+//   upper:  u = U_bb^{-1} (y - U_b,other u_other).
+// Outputs and gamma's partials (grid of nbu workgroups) as in k_trsv_colour.
+template <bool LOWER, bool TAIL>
+__global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, int b0, int b1,
+                                                    const int* __restrict__ eoff, const int* __restrict__ ecol,
+                                                    const double* __restrict__ eval, const double* __restrict__ binv,
+                                                    const double* __restrict__ binvU, const int* __restrict__ perm,
+                                                    const double* __restrict__ r, double* __restrict__ y,
+                                                    double* __restrict__ pu, double* __restrict__ u, long long stride,
+                                                    const Scal* __restrict__ sc, double* __restrict__ part, int nbu) {
+  __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
+  const int k = blockIdx.y;
+  if (sc && sc[k].done) return;
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const int i = lane >> 2, q = lane & 3;
+  const double* rk = r + k * stride;
+  double* yk = y + k * stride;
+  double* puk = pu + k * stride;
+  const double* dep = LOWER ? yk : puk;
+  double acc = 0.0;
+  for (int kb = b0 + (int)blockIdx.x * 4 + wave; kb < b1; kb += (int)gridDim.x * 4) {
+    const int t0 = bs[kb], nb = bs[kb + 1] - t0;
+    const int e0 = eoff[kb], ns = (eoff[kb + 1] - e0) >> 6;
+    const bool ok = i < nb;
+    const int t = t0 + (ok ? i : 0);
+    const int v = perm[t];
+    const double rv = rk[v];
+    const double rhs = LOWER ? rv : yk[t];
+    double m4[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) m4[a] = binv[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
+    double s = 0.0;
+    for (int a0 = 0; a0 < ns; a0 += 4) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int idx = e0 + min(a0 + a, ns - 1) * 64 + lane;
+        const int c = ecol[idx];
+        const double w = eval[idx];
+        const bool use = a0 + a < ns && c >= 0;
+        // padding re-reads the entry's own value (never a location this launch writes); the product is masked
+        const double x = *(use ? dep + c : eval + idx);
+        s += use ? w * x : 0.0;
+      }
+    }
+    s = quad_add<0x4E>(quad_add<0xB1>(s));
+    double xi = block_product(m4, ok ? rhs - s : 0.0, q);
+    if constexpr (TAIL) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) m4[a] = binvU[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
+      xi = block_product(m4, ok ? xi : 0.0, q);
+    }
+    if (ok && q == 0) {
+      if (LOWER && !TAIL) {
+        yk[t] = xi;
+      } else {
+        puk[t] = xi;
+        u[k * stride + v] = xi;
+        acc += rv * xi;
+      }
+    }
+  }
+  if (LOWER && !TAIL) return;
+  if (part) {
+    double s1[1] = {acc};
+    gofd_cg::block_sum_n<256, 1>(s1, sh);
+    if (threadIdx.x == 0) {
+      double* p = part + (long long)k * nbu + blockIdx.x;
+      *p = TAIL ? s1[0] : *p + s1[0];
+    }
+  }
+}
+
 // out[i] = in[perm[i]] (to = true) or out[perm[i]] = in[i], per right-hand side blockIdx.y
 template <bool TO>
 __global__ void k_permute(const double* __restrict__ in, const int* __restrict__ perm, long long n,
@@ -715,12 +823,108 @@ struct gofd_precond_s {
   std::vector<int32_t> hperm;
   std::vector<int32_t> hLlp, hUlp;   // level boundaries (host copies for the per-level launches)
   std::vector<int32_t> hcp;          // multicolour order: rows of colour c are hcp[c]..hcp[c+1]-1
+  // block multicolour order: block b is rows hbs[b]..hbs[b+1]-1, colour c is
+  // blocks hbc[c]..hbc[c+1]-1; on the device the block starts, each block's
+  // entries to other blocks in slabs of 64 (offsets Leptr / Ueptr per block,
+  // Lecol / Uecol and values: rows of L, resp. of U = L^T) and the inverse of
+  // each block's own triangle, dense (bL: L_bb^{-1}, bU: U_bb^{-1}; 256 per
+  // block, value (i, j) at ((j / 4) * 64 + i * 4 + j % 4), the register layout
+  // of the solve)
+  std::vector<int32_t> hbs, hbc;
+  DevBuf bs, Leptr, Lecol, Leval, Ueptr, Uecol, Ueval, bL, bU;
   gofd_precond_info info{};
 };
 
 // levels at most this many: one launch per level over the whole device; more:
 // one workgroup per right-hand side with a barrier per level
 constexpr int TRSV_LEVEL_LAUNCH_MAX = 64;
+
+// the block factor's device arrays (see gofd_precond_s); synchronises the
+// stream before the host copies go out of scope
+static int upload_block_factor(gofd_ctx_s* ctx, gofd_precond_s* pc, const std::vector<int64_t>& Lptr,
+                               const std::vector<int32_t>& Lcol, const std::vector<double>& Lval,
+                               const std::vector<int32_t>& Uptr, const std::vector<int32_t>& Ucol,
+                               const std::vector<double>& Uval) {
+  const int64_t n = (int64_t)Lptr.size() - 1;
+  const int nb = (int)pc->hbs.size() - 1;
+  constexpr int BS_ = BMC_BLOCK, BB = BMC_BLOCK * BMC_BLOCK;
+  static_assert(BMC_BLOCK == 16, "a wave holds a block: sixteen rows of four lanes");
+  std::vector<int32_t> fb(n);
+  for (int b = 0; b < nb; ++b)
+    for (int t = pc->hbs[b]; t < pc->hbs[b + 1]; ++t) fb[t] = b;
+  auto slot = [](int i, int j) { return (j / 4) * 64 + i * 4 + (j % 4); };
+  std::vector<double> binv((size_t)nb * BB, 0.0), binvU((size_t)nb * BB, 0.0);
+  std::vector<int32_t> eoffL(nb + 1, 0), eoffU(nb + 1, 0), ecL, ecU;
+  std::vector<double> evL, evU;
+  std::vector<std::vector<std::pair<int32_t, double>>> extL(BS_), extU(BS_);
+  for (int b = 0; b < nb; ++b) {
+    const int t0 = pc->hbs[b], m = pc->hbs[b + 1] - t0;
+    // the block's own triangle (rows of L inside the block, diagonal included) and the entries to other blocks
+    double Lb[BS_][BS_] = {};
+    for (int i = 0; i < m; ++i) {
+      const int64_t t = t0 + i;
+      extL[i].clear();
+      extU[i].clear();
+      for (int64_t e = Lptr[t]; e < Lptr[t + 1]; ++e) {
+        const int32_t j = Lcol[e];
+        if (fb[j] == b) Lb[i][j - t0] = Lval[e];
+        else extL[i].push_back({j, Lval[e]});
+      }
+      for (int64_t e = Uptr[t] + 1; e < Uptr[t + 1]; ++e)
+        if (fb[Ucol[e]] != b) extU[i].push_back({Ucol[e], Uval[e]});
+    }
+    // its inverse, column by column by forward substitution (lower triangular); that of U_bb = L_bb^T is the
+    // transpose
+    for (int c = 0; c < m; ++c) {
+      double x[BS_] = {};
+      for (int i = c; i < m; ++i) {
+        double acc = (i == c) ? 1.0 : 0.0;
+        for (int j = c; j < i; ++j) acc -= Lb[i][j] * x[j];
+        x[i] = acc / Lb[i][i];
+      }
+      for (int i = c; i < m; ++i) {
+        binv[(size_t)b * BB + slot(i, c)] = x[i];
+        binvU[(size_t)b * BB + slot(c, i)] = x[i];
+      }
+    }
+    // slabs of 64: lane i * 4 + q of slab a holds entry q + 4a of row i (col -1: none)
+    auto slabs = [&](std::vector<std::vector<std::pair<int32_t, double>>>& ext, std::vector<int32_t>& off,
+                     std::vector<int32_t>& ec, std::vector<double>& ev) {
+      size_t mx = 0;
+      for (int i = 0; i < m; ++i) mx = std::max(mx, ext[i].size());
+      const int ns = (int)((mx + 3) / 4);
+      for (int a = 0; a < ns; ++a)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int i = lane / 4, e = lane % 4 + 4 * a;
+          const bool has = i < m && e < (int)ext[i].size();
+          ec.push_back(has ? ext[i][e].first : -1);
+          ev.push_back(has ? ext[i][e].second : 0.0);
+        }
+      off[b + 1] = (int32_t)ec.size();
+    };
+    slabs(extL, eoffL, ecL, evL);
+    slabs(extU, eoffU, ecU, evU);
+  }
+  if (ecL.size() >= (size_t)1 << 31 || ecU.size() >= (size_t)1 << 31)
+    return gofd_fail(ctx, GOFD_E_OOM, "block factor too large");
+  hipStream_t st = ctx->stream;
+  auto up = [&](DevBuf& d, const void* h, size_t bytes) -> int {
+    GOFD_TRY(dev_reserve(ctx, d, std::max<size_t>(bytes, 8)));
+    if (bytes) HIP_TRY(ctx, hipMemcpyAsync(d.p, h, bytes, hipMemcpyHostToDevice, st));
+    return GOFD_OK;
+  };
+  GOFD_TRY(up(pc->bs, pc->hbs.data(), sizeof(int32_t) * pc->hbs.size()));
+  GOFD_TRY(up(pc->Leptr, eoffL.data(), sizeof(int32_t) * eoffL.size()));
+  GOFD_TRY(up(pc->Lecol, ecL.data(), sizeof(int32_t) * ecL.size()));
+  GOFD_TRY(up(pc->Leval, evL.data(), sizeof(double) * evL.size()));
+  GOFD_TRY(up(pc->Ueptr, eoffU.data(), sizeof(int32_t) * eoffU.size()));
+  GOFD_TRY(up(pc->Uecol, ecU.data(), sizeof(int32_t) * ecU.size()));
+  GOFD_TRY(up(pc->Ueval, evU.data(), sizeof(double) * evU.size()));
+  GOFD_TRY(up(pc->bL, binv.data(), sizeof(double) * binv.size()));
+  GOFD_TRY(up(pc->bU, binvU.data(), sizeof(double) * binvU.size()));
+  HIP_TRY(ctx, hipStreamSynchronize(st));
+  return GOFD_OK;
+}
 
 static int host_transfer(gofd_ctx_s* ctx, gofd_transfer_s* tr, HostTransfer& h) {
   hipStream_t st = ctx->stream;
@@ -762,7 +966,10 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     return GOFD_OK;
   }
   const bool mc = (kind & GOFD_PC_MULTICOLOR) != 0;
-  const int base = kind & ~GOFD_PC_MULTICOLOR;
+  const bool bmc = (kind & GOFD_PC_BLOCK_MULTICOLOR) != 0;
+  const bool lap = (kind & GOFD_PC_LAPLACIAN) != 0;
+  const int base = kind & ~(GOFD_PC_MULTICOLOR | GOFD_PC_BLOCK_MULTICOLOR | GOFD_PC_LAPLACIAN);
+  if (mc && bmc) return gofd_fail(ctx, GOFD_E_ARG, "multicolour and block multicolour orders exclude each other");
   int npts = 0;
   if (base == GOFD_PC_IC1_5 && tr->d == 2) npts = 5;
   if (base == GOFD_PC_IC1_9 && tr->d == 2) npts = 9;
@@ -771,7 +978,16 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
   HostTransfer ht;
   GOFD_TRY(host_transfer(ctx, tr, ht));
   HostCsr A;
-  if (!assemble_pattern_matrix(ht, op->T_host.data(), npts, A))
+  // the stencil values: A_FD's entries on the pattern, or (Laplacian kinds)
+  // the discrete Laplacian on the same pattern, npts - 1 at the centre and -1
+  // at every other point (5-point: the standard one; 9- and 27-point: the
+  // isotropic compact ones, up to a factor)
+  std::vector<double> lapT;
+  if (lap) {
+    lapT.assign(tr->d == 3 ? 8 : 4, -1.0);
+    lapT[0] = npts - 1;
+  }
+  if (!assemble_pattern_matrix(ht, lap ? lapT.data() : op->T_host.data(), lap ? 2 : op->W, npts, A))
     return gofd_fail(ctx, GOFD_E_ARG, "pattern assembly failed");
   std::vector<int64_t> Lptr;
   std::vector<int32_t> Lcol;
@@ -800,6 +1016,45 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     for (int c = 0; c < pc->info.colours; ++c) pc->hcp[c + 1] += pc->hcp[c];
     ic_symbolic(A, 1, Lptr, Lcol);
     drop_same_colour(colour, Lptr, Lcol);
+  } else if (bmc) {
+    // blocks of at most BMC_BLOCK vertices grown breadth first, the graph of
+    // the blocks coloured greedily, vertices ordered by (block colour, block,
+    // vertex); the level-1 fill is kept inside a block and between colours,
+    // so the blocks of one colour are never coupled in the factor
+    std::vector<int32_t> blk;
+    const int nb = grow_blocks(A, BMC_BLOCK, blk);
+    HostCsr G;
+    block_graph(A, blk, nb, G);
+    std::vector<int32_t> bcol;
+    pc->info.colours = greedy_colouring(G, bcol);
+    if (pc->info.colours > TRSV_LEVEL_LAUNCH_MAX)
+      return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "block multicolour order needs more than 64 colours");
+    pc->hperm.resize(A.n);
+    for (int64_t i = 0; i < A.n; ++i) pc->hperm[i] = (int32_t)i;
+    std::stable_sort(pc->hperm.begin(), pc->hperm.end(), [&](int32_t a, int32_t b) {
+      return bcol[blk[a]] != bcol[blk[b]] ? bcol[blk[a]] < bcol[blk[b]] : blk[a] < blk[b];
+    });
+    HostCsr B;
+    permute_symmetric(A, pc->hperm, B);
+    A.rowptr.swap(B.rowptr);
+    A.col.swap(B.col);
+    A.val.swap(B.val);
+    std::vector<int32_t> pblk(A.n), pcol(A.n);
+    for (int64_t i = 0; i < A.n; ++i) {
+      pblk[i] = blk[pc->hperm[i]];
+      pcol[i] = bcol[pblk[i]];
+    }
+    // blocks in the factor's order (contiguous runs) and each colour's blocks
+    pc->hbs.assign(1, 0);
+    pc->hbc.assign(1, 0);
+    for (int64_t i = 1; i <= A.n; ++i)
+      if (i == A.n || pblk[i] != pblk[i - 1]) {
+        if (i < A.n && pcol[i] != pcol[i - 1]) pc->hbc.push_back((int32_t)pc->hbs.size());
+        pc->hbs.push_back((int32_t)i);
+      }
+    pc->hbc.push_back((int32_t)pc->hbs.size() - 1);
+    ic_symbolic(A, 1, Lptr, Lcol);
+    drop_same_colour(pcol, Lptr, Lcol, &pblk);
   } else {
     ic_symbolic(A, 1, Lptr, Lcol);
   }
@@ -867,7 +1122,8 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     pc->hUlp = Ulp;
   }
   hipStream_t st = ctx->stream;
-  if (mc) {
+  if (bmc) GOFD_TRY(upload_block_factor(ctx, pc, Lptr, Lcol, Lval, Uptr, Ucol, Uval));
+  if (mc || bmc) {
     GOFD_TRY(dev_reserve(ctx, pc->perm, sizeof(int32_t) * n));
     HIP_TRY(ctx, hipMemcpyAsync(pc->perm.p, pc->hperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
   }
@@ -935,7 +1191,7 @@ struct Problem {
 };
 
 bool is_ic(const gofd_precond_s* pc) {
-  const int base = pc ? (pc->kind & ~GOFD_PC_MULTICOLOR) : 0;
+  const int base = pc ? (pc->kind & ~(GOFD_PC_MULTICOLOR | GOFD_PC_BLOCK_MULTICOLOR | GOFD_PC_LAPLACIAN)) : 0;
   return pc && (base == GOFD_PC_IC1_5 || base == GOFD_PC_IC1_9 || base == GOFD_PC_IC1_27);
 }
 
@@ -1197,6 +1453,39 @@ int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, doub
     const long long n = P.tr->nv, o = B.poff[q];
     const int i0 = B.pitem[q];
     const Scal* scq = sc ? sc + i0 : nullptr;
+    if (!pc->hbc.empty()) {
+      // block multicolour order: one launch per colour and direction, the
+      // last colour's blocks of U solved in the last lower launch
+      const int C = (int)pc->hbc.size() - 1;
+      const double* rin = w.r.as<double>() + o;
+      double* y = w.dvec.as<double>() + o;
+      double* pu = w.pu.as<double>() + o;
+      double* u = w.u.as<double>() + o;
+      double* part = partG ? partG + (long long)i0 * w.nbs : nullptr;
+      const int* perm_d = pc->perm.as<int>();
+      auto waves = [](int nblk) { return (unsigned)std::max(1, (nblk + 3) / 4); };
+      for (int c = 0; c + 1 < C; ++c) {
+        const int b0 = pc->hbc[c], b1 = pc->hbc[c + 1];
+        hipLaunchKernelGGL((k_trsv_block<true, false>), dim3(waves(b1 - b0), P.nrhs), dim3(256), 0, st,
+                           pc->bs.as<int>(), b0, b1, pc->Leptr.as<int>(), pc->Lecol.as<int>(), pc->Leval.as<double>(),
+                           pc->bL.as<double>(), nullptr, perm_d, rin, y, pu, u, n, scq, nullptr, 0);
+      }
+      {
+        const int b0 = pc->hbc[C - 1], b1 = pc->hbc[C];
+        hipLaunchKernelGGL((k_trsv_block<true, true>), dim3(part ? w.nbs : waves(b1 - b0), P.nrhs), dim3(256), 0,
+                           st, pc->bs.as<int>(), b0, b1, pc->Leptr.as<int>(), pc->Lecol.as<int>(),
+                           pc->Leval.as<double>(), pc->bL.as<double>(), pc->bU.as<double>(), perm_d, rin, y, pu, u,
+                           n, scq, part, w.nbs);
+      }
+      for (int c = C - 2; c >= 0; --c) {
+        const int b0 = pc->hbc[c], b1 = pc->hbc[c + 1];
+        hipLaunchKernelGGL((k_trsv_block<false, false>), dim3(part ? w.nbs : waves(b1 - b0), P.nrhs), dim3(256), 0,
+                           st, pc->bs.as<int>(), b0, b1, pc->Ueptr.as<int>(), pc->Uecol.as<int>(),
+                           pc->Ueval.as<double>(), pc->bU.as<double>(), nullptr, perm_d, rin, y, pu, u, n, scq,
+                           part, w.nbs);
+      }
+      continue;
+    }
     if (!pc->hcp.empty() && (int)pc->hcp.size() - 1 <= TRSV_LEVEL_LAUNCH_MAX) {
       // multicolour order: one launch per colour and direction, the last
       // colour's upper rows solved in the last lower launch; the permutation

@@ -69,13 +69,18 @@ def test_c2_solutions_within_1e8_of_oracle(gctx, c2_gpu, mode_name):
         assert e <= 1e-8
 
 
-def test_c2_multicolour_ic1_solutions_within_1e8_of_oracle(gctx, c2_gpu):
-    """The same step preconditioned by IC(1) of A_h^(9) in multicolour order (Section 3.3)."""
+@pytest.mark.parametrize("pc_name", ["IC1_9_MC", "IC1_9_LAP_BMC", "IC1_9_BMC"])
+def test_c2_multicolour_ic1_solutions_within_1e8_of_oracle(gctx, c2_gpu, pc_name):
+    """The same step preconditioned by IC(1) of A_h^(9) (Section 3.3) in multicolour order, in block
+    multicolour order, and with the Laplacian on the 9-point pattern in place of A_FD."""
     import paper_2307_14437_amd as gofd
     cfg, tr, ops, refs, fd = c2_gpu
-    pcs = [gofd.Precond(gctx, tr, op, "IC1_9_MC") for op in ops]
-    print("IC1_9_MC", pcs[1].info, flush=True)
-    assert pcs[1].info["levels"] <= pcs[1].info["colours"] <= 32
+    pcs = [gofd.Precond(gctx, tr, op, pc_name) for op in ops]
+    print(pc_name, pcs[1].info, flush=True)
+    if pc_name.endswith("_MC"):
+        assert pcs[1].info["levels"] <= pcs[1].info["colours"] <= 32
+    else:
+        assert pcs[1].info["colours"] <= 12
     for mode in (gofd.MODE_FP32_RELIABLE, gofd.MODE_FP64):
         us, infos = gofd.solve_batched(gctx, [tr] * 2, ops, pcs, [fd, fd], tol=cfg["tol"], mode=mode, inner_tol=0.1)
         errs = _errors(us, refs)

@@ -35,7 +35,8 @@ def _full(otr, uJ):
     return u
 
 
-@pytest.mark.parametrize("pc_name", ["NONE", "DIAG", "IC1_5", "IC1_9", "IC1_5_MC", "IC1_9_MC"])
+@pytest.mark.parametrize("pc_name", ["NONE", "DIAG", "IC1_5", "IC1_9", "IC1_5_MC", "IC1_9_MC", "IC1_5_LAP",
+                                     "IC1_9_LAP_MC", "IC1_9_BMC", "IC1_9_LAP_BMC", "IC1_5_LAP_BMC"])
 def test_c1_solve_matches_dense_lu(gctx, c1_setup, pc_name):
     import paper_2307_14437_amd as gofd
     m, g, otr, T, tr, op, K = c1_setup
@@ -63,6 +64,25 @@ def test_c1_iteration_counts_drop_with_ic1(gctx, c1_setup):
         _, info = gofd.solve(gctx, tr, op, f, tol=1e-10, pc=pc)
         its[name] = info[0]["iterations"]
     assert its["IC1_9"] <= its["IC1_5"] < its["NONE"], its
+
+
+def test_c1_laplacian_preconditioner_pays_near_s_1(gctx, c1_setup):
+    # M = I^T (-Delta_h) I against K = I^T A_FD I: M^{-1} K behaves like (-Delta)^{s-1}, so it gains most as
+    # s -> 1; at s = 0.9 it must cut the iterations of plain CG (counts at s = 0.25 are printed)
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    f = _dev(np.ones((g.W, g.W)))
+    for s_ in (0.9, 0.25):
+        op_s = gofd.FdOp(gctx, s_, g)
+        its = {}
+        for name in ("NONE", "IC1_9", "IC1_9_LAP", "IC1_9_LAP_MC"):
+            pc = gofd.Precond(gctx, tr, op_s, name)
+            _, info = gofd.solve(gctx, tr, op_s, f, tol=1e-10, pc=pc)
+            assert info[0]["status"] == 0 and info[0]["rel_residual"] <= 1e-10
+            its[name] = info[0]["iterations"]
+        print("s", s_, its, flush=True)
+        if s_ == 0.9:
+            assert its["IC1_9_LAP"] < its["NONE"] and its["IC1_9_LAP_MC"] < its["NONE"], its
 
 
 def test_ic1_factor_matches_oracle(gctx, c1_setup):
@@ -106,6 +126,85 @@ def test_multicolour_ic1_factor_matches_oracle(gctx, c1_setup):
         assert np.array_equal(Lgi.indptr, Lo.indptr) and np.array_equal(Lgi.indices, Lo.indices)
         assert np.max(np.abs(Lgi.data - Lo.data)) < 1e-12 * np.max(np.abs(Lo.data))
         print(name, pc.info, flush=True)
+
+
+def test_laplacian_ic1_factors_match_oracle(gctx, c1_setup):
+    """IC(1) of I^T (-Delta_h) I with the Laplacian on the 5- and 9-point patterns in place of A_FD (Section
+    3.3), in vertex and in multicolour order: the same pattern and values as the oracle's factor of
+    Ah_pattern(tr, laplacian_table(2, p), p), and a factor that does not depend on s."""
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    for name, npts, mc in (("IC1_5_LAP", 5, False), ("IC1_9_LAP", 9, False), ("IC1_9_LAP_MC", 9, True)):
+        pc = gofd.Precond(gctx, tr, op, name)
+        Lg = pc.export().tocsr()
+        A = precond.Ah_pattern(otr, precond.laplacian_table(2, npts), npts)
+        if mc:
+            Lo, perm, cp, alpha = precond.ic1_multicolour(A)
+            order = pc.order()
+            interior = ~otr.bnd[order]
+            assert np.array_equal(order[interior], otr.J[perm])
+            rows = np.nonzero(interior)[0]
+        else:
+            Lo, alpha = precond.ic1(A)
+            rows = otr.J
+        assert alpha == pc.info["shift"]
+        Lgi = Lg[rows][:, rows].tocsr()
+        Lgi.sort_indices()
+        Lo = Lo.tocsr()
+        Lo.sort_indices()
+        assert np.array_equal(Lgi.indptr, Lo.indptr) and np.array_equal(Lgi.indices, Lo.indices)
+        assert np.max(np.abs(Lgi.data - Lo.data)) < 1e-12 * np.max(np.abs(Lo.data))
+        op2 = gofd.FdOp(gctx, 0.8, g)                     # another s: the same factor
+        L2 = gofd.Precond(gctx, tr, op2, name).export().tocsr()
+        assert np.array_equal(L2.indices, Lg.indices) and np.array_equal(L2.data, Lg.data)
+        print(name, pc.info, flush=True)
+
+
+def test_block_multicolour_ic1_factor_matches_oracle(gctx, c1_setup):
+    """Block multicolour IC(1) (blocks of 16 grown breadth first, block graph coloured greedily): the
+    library's order equals the oracle's on the interior vertices (Dirichlet vertices are isolated identity
+    rows, each its own block of colour 0, in the library's matrix), and so does the factor."""
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    for name, table, npts in (("IC1_9_LAP_BMC", precond.laplacian_table(2, 9), 9), ("IC1_9_BMC", T, 9),
+                              ("IC1_5_LAP_BMC", precond.laplacian_table(2, 5), 5)):
+        pc = gofd.Precond(gctx, tr, op, name)
+        order = pc.order()
+        Lg = pc.export().tocsr()
+        Lo, perm, pb, pcol, alpha = precond.ic1_block_multicolour(precond.Ah_pattern(otr, table, npts), 16)
+        assert alpha == pc.info["shift"]
+        assert pc.info["colours"] == pcol.max() + 1
+        interior = ~otr.bnd[order]
+        assert np.array_equal(order[interior], otr.J[perm])           # integer work: bit-exact
+        rows = np.nonzero(interior)[0]
+        Lgi = Lg[rows][:, rows].tocsr()
+        Lgi.sort_indices()
+        Lo = Lo.tocsr()
+        Lo.sort_indices()
+        assert np.array_equal(Lgi.indptr, Lo.indptr) and np.array_equal(Lgi.indices, Lo.indices)
+        assert np.max(np.abs(Lgi.data - Lo.data)) < 1e-12 * np.max(np.abs(Lo.data))
+        print(name, pc.info, flush=True)
+
+
+def test_block_multicolour_apply_matches_oracle(gctx, c1_setup):
+    """The block solves on the device apply the oracle's preconditioner: CG preconditioned by the oracle's
+    factor (its order, its triangular solves) takes the GPU's iteration count within two, and the GPU
+    solution matches dense LU."""
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    A = precond.Ah_pattern(otr, precond.laplacian_table(2, 9), 9)
+    Lo, perm, pb, pcol, alpha = precond.ic1_block_multicolour(A, 16)
+    pc = gofd.Precond(gctx, tr, op, "IC1_9_LAP_BMC")
+    f = np.cos(np.arange(g.W * g.W).reshape(g.W, g.W) * 0.01)
+    b = operator.rhs_grid(otr, 0.5, f)
+    its_o = {}
+    for name, M in (("oracle", lambda r: precond.apply_ic_ordered(Lo, perm, r)),):
+        _, its_o[name], _ = solve.pcg(lambda v: K @ v, b, tol=1e-10, precond=M)
+    u, info = gofd.solve(gctx, tr, op, _dev(f), tol=1e-10, pc=pc)
+    print("iterations gpu", info[0]["iterations"], "oracle", its_o["oracle"], flush=True)
+    assert abs(info[0]["iterations"] - its_o["oracle"]) <= 2
+    uref = _full(otr, solve.solve_dense(K, b))
+    assert np.linalg.norm(u.cpu().numpy() - uref) / np.linalg.norm(uref) < 1e-8
 
 
 def test_c1_fp32_refinement_reaches_fp64_accuracy(gctx, c1_setup):

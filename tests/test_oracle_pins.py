@@ -284,3 +284,127 @@ def test_multicolour_ic1_on_the_c1_mesh(c1):
     _, it0, _ = solve.pcg(lambda v: K @ v, b, tol=1e-13)
     assert np.max(np.abs(xm - x)) < 1e-11 * np.max(np.abs(x))
     assert itm < it0
+
+
+# ---------------------------------------------------------------- the Laplacian in place of A_FD (Section 3.3)
+
+
+def _coincident_2d(nx=9, ny=7, N=16, at=3):
+    g = grid_for_box(2, N, R=1.0)
+    lo = ogrid.axis_coords(0.0, g.R, g.N)[at]
+    m = structured_box_mesh((lo, lo), g.h, nx, ny)
+    return m, transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
+
+
+def test_laplacian_5_point_on_a_grid_coincident_mesh():
+    # with the vertices on grid nodes I_J selects the interior vertices, so I_J^T (-Delta_h) I_J is the 5-point
+    # Laplacian (times h^2) on them: 4 on the diagonal, -1 between vertices one grid step apart on an axis,
+    # written out by brute force over vertex pairs
+    m, tr = _coincident_2d()
+    A = precond.Ah_pattern(tr, precond.laplacian_table(2, 5), 5).toarray()
+    J = tr.J
+    h = tr.h
+    P = np.rint(m.X[J] / h).astype(int)
+    ref = np.zeros((len(J), len(J)))
+    for a in range(len(J)):
+        for b in range(len(J)):
+            dx, dy = P[b] - P[a]
+            if dx == 0 and dy == 0:
+                ref[a, b] = 4.0
+            elif abs(dx) + abs(dy) == 1:
+                ref[a, b] = -1.0
+    assert np.array_equal(A, ref)
+
+
+@pytest.mark.parametrize("npts", [9, 5])
+def test_laplacian_pattern_is_consistent(npts):
+    # interior rows far from the boundary: the stencil sums to zero on constants and gives -c h^2 Delta on x^2
+    # and y^2 (c = 1 for the 5-point, 3 for the isotropic 9-point: -2 h^2 and -6 h^2)
+    m, tr = _coincident_2d(nx=12, ny=12, N=16, at=1)
+    A = precond.Ah_pattern(tr, precond.laplacian_table(2, npts), npts)
+    X = m.X[tr.J]
+    h = tr.h
+    lo, hi = X.min(axis=0) + 1.5 * h, X.max(axis=0) - 1.5 * h
+    deep = np.all((X > lo) & (X < hi), axis=1)
+    assert deep.sum() > 20
+    c = {5: 1.0, 9: 3.0}[npts]
+    assert np.allclose((A @ np.ones(len(X)))[deep], 0.0, atol=1e-12)
+    for a in range(2):
+        q = (A @ X[:, a] ** 2)[deep]
+        assert np.allclose(q, -2.0 * c * h * h, rtol=1e-10, atol=1e-14)
+    # a mixed term: only the diagonal neighbours of the 9-point stencil see xy, and they cancel
+    assert np.allclose((A @ (X[:, 0] * X[:, 1]))[deep], 0.0, atol=1e-12)
+
+
+def test_laplacian_27_point_is_consistent():
+    from workloads import structured_box_mesh_3d
+    g = grid_for_box(3, 8, R=1.0)
+    lo = ogrid.axis_coords(0.0, g.R, g.N)[1]
+    m = structured_box_mesh_3d((lo, lo, lo), g.h, 7, 7, 7)
+    tr = transfer.Transfer(m.X, m.elems, 3, g.N, g.R, g.center)
+    A = precond.Ah_pattern(tr, precond.laplacian_table(3, 27), 27)
+    X = m.X[tr.J]
+    h = g.h
+    lo3, hi3 = X.min(axis=0) + 1.5 * h, X.max(axis=0) - 1.5 * h
+    deep = np.all((X > lo3) & (X < hi3), axis=1)
+    assert deep.sum() >= 8
+    assert np.allclose((A @ np.ones(len(X)))[deep], 0.0, atol=1e-12)
+    # 18 of the 26 neighbours are one step off along a given axis: -18 h^2 on x_a^2 (a multiple of -Delta)
+    for a in range(3):
+        assert np.allclose((A @ X[:, a] ** 2)[deep], -18.0 * h * h, rtol=1e-10, atol=1e-14)
+    assert precond.laplacian_table(3, 27)[0, 0, 0] == 26 and np.all(precond.laplacian_table(3, 27).ravel()[1:] == -1)
+
+
+# ---------------------------------------------------------------- block multicolour IC(1)
+
+
+def test_block_multicolour_ic1_on_the_c1_mesh(c1):
+    m, g = c1["mesh"], c1["grid"]
+    tr = transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
+    A = precond.Ah_pattern(tr, precond.laplacian_table(2, 9), 9).tocsr()
+    n = A.shape[0]
+    L, perm, pb, pc, alpha = precond.ic1_block_multicolour(A, 16)
+    assert alpha == 0.0 and np.array_equal(np.sort(perm), np.arange(n))
+    # blocks: at most 16 vertices, each connected in A's graph (grown breadth first), contiguous in the order
+    starts = np.r_[0, np.nonzero(np.diff(pb))[0] + 1, n]
+    assert len(np.unique(pb)) == len(starts) - 1                      # every block is one contiguous run
+    assert np.max(np.diff(starts)) <= 16
+    Ap = A[perm][:, perm].tocsr()
+    for a, b in zip(starts[:-1], starts[1:]):
+        sub = Ap[a:b, a:b]
+        ncomp, _ = sp.csgraph.connected_components(sub, directed=False)
+        assert ncomp == 1
+    # block colours: blocks of one colour are never adjacent in A, colours non-decreasing along the order
+    assert np.all(np.diff(pc) >= 0)
+    Ac = Ap.tocoo()
+    cross = pb[Ac.row] != pb[Ac.col]
+    assert np.all(pc[Ac.row[cross]] != pc[Ac.col[cross]])
+    # greedy in block order: a block of colour c > 0 touches a block of lower id of every colour below c
+    for b in np.unique(pb):
+        rows = np.nonzero(pb == b)[0]
+        nbrs = {int(pb[j]) for i in rows for j in Ap.indices[Ap.indptr[i]:Ap.indptr[i + 1]] if pb[j] < b}
+        assert set(range(pc[rows[0]])) <= {int(pc[np.nonzero(pb == q)[0][0]]) for q in nbrs}
+    # factor: no entry between two blocks of one colour; L L^T = P A P^T on the kept pattern
+    Lc = L.tocoo()
+    offb = pb[Lc.row] != pb[Lc.col]
+    assert np.all(pc[Lc.row[offb]] != pc[Lc.col[offb]])
+    M = (L @ L.T).toarray()
+    Ad = Ap.toarray()
+    assert np.max(np.abs(M[Lc.row, Lc.col] - Ad[Lc.row, Lc.col])) < 1e-12 * np.abs(Ad).max()
+    # few colours: a triangular solve takes one step per colour
+    assert pc.max() + 1 <= 8 < precond.dependency_levels(L)
+
+
+def test_grow_blocks_by_hand():
+    # a path 0-1-2-3-4-5 and an isolated vertex 6: blocks of 4 grow from 0 (0,1,2,3), then 4 (4,5), then 6;
+    # in a star centred on 2 with leaves 0,1,3,4, blocks of 3 from 0 take 0, then 2 (its neighbour), then 1
+    # (2's smallest unplaced neighbour); leaves 3 and 4 only touch the placed centre, so each is alone
+    n = 7
+    e = [(i, i + 1) for i in range(5)]
+    A = sp.csr_matrix((np.ones(2 * len(e)), ([a for a, b in e] + [b for a, b in e], [b for a, b in e] + [a for a, b in e])),
+                      shape=(n, n))
+    assert precond.grow_blocks(A, 4).tolist() == [0, 0, 0, 0, 1, 1, 2]
+    e = [(2, 0), (2, 1), (2, 3), (2, 4)]
+    S = sp.csr_matrix((np.ones(8), ([a for a, b in e] + [b for a, b in e], [b for a, b in e] + [a for a, b in e])),
+                      shape=(5, 5))
+    assert precond.grow_blocks(S, 3).tolist() == [0, 0, 0, 1, 2]
