@@ -6,11 +6,15 @@ the reentrant corner, 1024 x 1024 overlay grid (W = 1025 nodes per axis,
 FFT length 2048), s in {0.25, 0.75}, f a seeded 16-mode Fourier series,
 tolerance 1e-8 on the relative residual of eq. GoFD-2.
 
-One step = the batched solve of both orders s with FP32 grid products inside
-FP64 refinement by residual replacement (every step of the hot path: gather +
-FFT passes + I^T scatter inside CG, FP64 true residuals, vectors and scalars).
-The same steps are also timed with plain FP64 products and with restarted
-FP32 refinement, and the A_h products alone, for comparison.
+One step = the batched solve of both orders s by preconditioned CG with FP32
+grid products inside FP64 refinement by residual replacement (every step of
+the hot path: gather + FFT passes + I^T scatter inside CG, the triangular
+solves of the preconditioner, FP64 true residuals, vectors and scalars).  The
+preconditioner by default follows s (pc_for): IC(1) of the Laplacian on the
+9-point pattern in block multicolour order above s = 1/2, none below.  The
+same steps are also timed with plain FP64 products, with restarted FP32
+refinement, with other preconditioners, and the A_h products alone, for
+comparison.
 
 --copy-probe MiB only runs a device-to-device copy of that size (the
 calibration kernel for HBM byte counters) and exits.
@@ -93,6 +97,16 @@ def _traffic(stage):
     if d.get("source_hash") != mod.source_hash() or stage not in d.get("stages", {}):
         return None
     return d["stages"][stage]["bytes"]
+
+
+def pc_for(name, s):
+    """The preconditioner used for order s.  'auto': IC(1) of I^T (-Delta_h) I on the 9-point pattern in block
+    multicolour order when s > 1/2, none otherwise.  With the Laplacian as M, M^{-1} K behaves like
+    (-Delta)^{s-1}, whose condition number grows like h^{-2(1-s)} against h^{-2s} for K itself, so the
+    Laplacian pays exactly when s > 1/2 (the paper notes the same trend: its preconditioners gain as s -> 1)."""
+    if name == "auto":
+        return "IC1_9_LAP_BMC" if s > 0.5 else "NONE"
+    return name
 
 
 def cpu_baseline(cfg, s_sample=0.25, repeats=3, M=4096):
@@ -499,14 +513,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precond", default="NONE", choices=["NONE", "DIAG", "IC1_9", "IC1_5"])
+    ap.add_argument("--precond", default="auto",
+                    help="preconditioner of the timed step: a name of the library's (NONE, DIAG, IC1_9_MC, "
+                         "IC1_9_LAP_BMC, ...) or 'auto' (per s: the Laplacian's IC(1) above s = 1/2, none below)")
     ap.add_argument("--drop", type=float, default=0.03,
                     help="FP32 mode: residual drop between FP64 residual replacements")
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="restarted-refinement comparison: inner tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0)
-    ap.add_argument("--pc-lines", default="IC1_9_MC,IC1_9_LAP_MC",
-                    help="comma-separated preconditioners timed beside plain CG on the same step ('' for none)")
+    ap.add_argument("--pc-lines", default="NONE,IC1_9_MC,IC1_9_BMC,IC1_9_LAP_BMC",
+                    help="comma-separated preconditioners (or 'auto') timed beside the headline step ('' for none)")
     ap.add_argument("--col-schedule", type=int, default=-1,
                     help="column-pass schedule for both precisions instead of tuning it (counter runs)")
     ap.add_argument("--row-schedule", type=int, default=0, choices=[0, 8, 16],
@@ -566,7 +582,7 @@ def main():
         ops.append(gofd.FdOp(ctx, s, g))
         _sync(); setup[f"fd_weights_ms_s{s}"] = (time.perf_counter() - t) * 1e3
         t = time.perf_counter()
-        pcs.append(gofd.Precond(ctx, tr, ops[-1], args.precond))
+        pcs.append(gofd.Precond(ctx, tr, ops[-1], pc_for(args.precond, s)))
         setup[f"precond_ms_s{s}"] = (time.perf_counter() - t) * 1e3
     # column-pass schedules for this FFT length, tuned on the device (setup, outside the timed region)
     _sync(); t = time.perf_counter()
@@ -619,13 +635,14 @@ def main():
     _sync()
     ms_step64 = (time.perf_counter() - t0) * 1e3 / args.steps
 
-    # the paper's sparse preconditioner (IC(1) of A_h^(9), Section 3.3) in multicolour order, and the same with
-    # the Laplacian in place of A_FD (the alternative Section 3.3 names): the same batched FP32 step, with the two
-    # triangular solves of every iteration on the device
+    # the same batched step with other preconditioners beside it: plain CG, the paper's sparse preconditioner
+    # (IC(1) of A_h^(9), Section 3.3) in multicolour and block multicolour order, and IC(1) of the Laplacian on
+    # the same pattern for both orders s (the alternative Section 3.3 names); the triangular solves of every
+    # iteration run on the device
     pc_lines = {}
     for name in args.pc_lines.split(",") if args.pc_lines else []:
         _sync(); t = time.perf_counter()
-        pcs_x = [gofd.Precond(ctx, tr, op, name) for op in ops]
+        pcs_x = [gofd.Precond(ctx, tr, op, pc_for(name, s)) for op, s in zip(ops, svals)]
         _sync(); t_setup = (time.perf_counter() - t) * 1e3
 
         def step_pc(mode):
@@ -719,7 +736,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D L-shape, 67k-vertex graded Delaunay mesh, 1024x1024 overlay grid, "
                                "s in {0.25, 0.75}, 16-mode Fourier f, tol 1e-8",
-                   "nv": tr.nv, "grid": f"{W}x{W}", "fft_length": 2 * (W - 1), "precond": args.precond,
+                   "nv": tr.nv, "grid": f"{W}x{W}", "fft_length": 2 * (W - 1),
+                   "precond": args.precond if args.precond != "auto" else {str(s): pc_for("auto", s) for s in svals},
                    "fp32_mode": "reliable updating", "drop": args.drop, "column_pass_schedule": sched},
         "rel_error_vs_oracle": err_oracle,
         "all_within_1e-8_of_oracle": (None if any(v is None for v in err_oracle.values()) else
