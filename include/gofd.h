@@ -326,7 +326,9 @@ typedef struct {
  * vertices are grouped into blocks of at most 16 (in vertex order, a vertex
  * not yet placed starts a block that takes unplaced vertices breadth first,
  * neighbours in A^(p) in increasing order), the graph of the blocks is
- * coloured greedily in block order, the vertices are ordered by (block
+ * coloured in smallest-last order (least degree removed first, ties to the
+ * smaller block; coloured in reverse removal order, each block the smallest
+ * free colour), the vertices are ordered by (block
  * colour, block, vertex), and the level-1 fill is kept inside a block and
  * between different colours: one device-wide launch per colour and solve,
  * each block's own rows solved within one wavefront; colours reports the

@@ -26,9 +26,9 @@ one colour are then never coupled in the factor, so a triangular solve has at
 most as many dependency levels as there are colours.
 
 Block multicolour variant (the same reading with blocks of at most 16
-vertices grown breadth first, the blocks coloured instead of the vertices;
-ic1_block_multicolour): far fewer colours, each block's own rows solved in
-sequence.
+vertices grown breadth first, the blocks coloured in smallest-last order
+instead of the vertices; ic1_block_multicolour): far fewer colours, each
+block's own rows solved together.
 
 Laplacian variant: the discrete Laplacian on the pattern in place of A_FD's
 entries (laplacian_table), the alternative Section 3.3 names.
@@ -230,6 +230,39 @@ def ic1_multicolour(A: sp.csr_matrix, level: int = 1):
         alpha = 1e-3 if alpha == 0.0 else 2 * alpha
 
 
+def smallest_last_colouring(A: sp.csr_matrix) -> np.ndarray:
+    """Colour of each vertex in Matula and Beck's smallest-last order: vertices are removed one at a time, each
+    time one of least degree among those left (ties: the smallest index), and coloured in the reverse of that
+    order, each the smallest colour not used by an already coloured neighbour.  It uses at most one colour more
+    than the graph's degeneracy."""
+    A = sp.csr_matrix(A)
+    n = A.shape[0]
+    nbrs = [[int(j) for j in A.indices[A.indptr[v]:A.indptr[v + 1]] if j != v] for v in range(n)]
+    deg = [len(x) for x in nbrs]
+    heap = [(deg[v], v) for v in range(n)]
+    heapq.heapify(heap)
+    removed = [False] * n
+    order = []
+    while heap:
+        d, v = heapq.heappop(heap)
+        if removed[v] or d != deg[v]:
+            continue
+        removed[v] = True
+        order.append(v)
+        for j in nbrs[v]:
+            if not removed[j]:
+                deg[j] -= 1
+                heapq.heappush(heap, (deg[j], j))
+    colour = -np.ones(n, dtype=np.int64)
+    for v in reversed(order):
+        taken = {int(colour[j]) for j in nbrs[v] if colour[j] >= 0}
+        c = 0
+        while c in taken:
+            c += 1
+        colour[v] = c
+    return colour
+
+
 def grow_blocks(A: sp.csr_matrix, size: int) -> np.ndarray:
     """Block of each vertex: vertices in index order, each not yet in a block starts one, which then takes
     not yet placed vertices breadth first (a vertex's neighbours in increasing index) until it has `size`."""
@@ -260,7 +293,7 @@ def grow_blocks(A: sp.csr_matrix, size: int) -> np.ndarray:
 def ic1_block_multicolour(A: sp.csr_matrix, size: int = 16, level: int = 1):
     """Block multicolour IC(level), a reading for triangular solves with few device-wide steps: vertices are
     grouped into blocks of at most `size` (grow_blocks), the graph of the blocks (two blocks adjacent when A
-    couples a vertex of one to a vertex of the other) is coloured greedily in block order, the vertices are
+    couples a vertex of one to a vertex of the other) is coloured in smallest-last order, the vertices are
     ordered by (colour of their block, block, index) and P A P^T is factored keeping the level-`level` fill
     inside a block and between blocks of different colours (blocks of one colour are never coupled, so a
     triangular solve takes one step per colour, each block solved on its own).  Returns (L, perm, block of
@@ -272,7 +305,7 @@ def ic1_block_multicolour(A: sp.csr_matrix, size: int = 16, level: int = 1):
     Ac = A.tocoo()
     off = blk[Ac.row] != blk[Ac.col]
     G = sp.csr_matrix((np.ones(int(off.sum())), (blk[Ac.row[off]], blk[Ac.col[off]])), shape=(nb, nb))
-    bcol = greedy_colouring(G)
+    bcol = smallest_last_colouring(G)
     perm = np.lexsort((np.arange(n), blk, bcol[blk]))
     Ap = A[perm][:, perm].tocsr()
     pb = blk[perm]

@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <functional>
+#include <queue>
 #include <vector>
 
 #include "precond_host.h"
@@ -226,6 +228,46 @@ int greedy_colouring(const HostCsr& A, std::vector<int32_t>& colour) {
     while (c < (int32_t)stamp.size() && stamp[c] == i) ++c;
     if (c == (int32_t)stamp.size()) stamp.push_back(-1);
     colour[i] = c;
+    ncol = std::max(ncol, (int)c + 1);
+  }
+  return ncol;
+}
+
+int smallest_last_colouring(const HostCsr& A, std::vector<int32_t>& colour) {
+  const int64_t n = A.n;
+  std::vector<int32_t> deg(n, 0);
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t e = A.rowptr[v]; e < A.rowptr[v + 1]; ++e) deg[v] += A.col[e] != v;
+  // least degree first, then the smallest index; entries made stale by a later decrease are skipped
+  std::priority_queue<std::pair<int32_t, int32_t>, std::vector<std::pair<int32_t, int32_t>>, std::greater<>> heap;
+  for (int64_t v = 0; v < n; ++v) heap.push({deg[v], (int32_t)v});
+  std::vector<char> removed(n, 0);
+  std::vector<int32_t> order;
+  order.reserve(n);
+  while (!heap.empty()) {
+    const auto [d, v] = heap.top();
+    heap.pop();
+    if (removed[v] || d != deg[v]) continue;
+    removed[v] = 1;
+    order.push_back(v);
+    for (int64_t e = A.rowptr[v]; e < A.rowptr[v + 1]; ++e) {
+      const int32_t j = A.col[e];
+      if (j != v && !removed[j]) heap.push({--deg[j], j});
+    }
+  }
+  colour.assign(n, -1);
+  std::vector<int64_t> stamp(1, -1);
+  int ncol = 0;
+  for (auto it = order.rbegin(); it != order.rend(); ++it) {
+    const int32_t v = *it;
+    for (int64_t e = A.rowptr[v]; e < A.rowptr[v + 1]; ++e) {
+      const int32_t c = colour[A.col[e]];
+      if (c >= 0) stamp[c] = v;
+    }
+    int32_t c = 0;
+    while (c < (int32_t)stamp.size() && stamp[c] == v) ++c;
+    if (c == (int32_t)stamp.size()) stamp.push_back(-1);
+    colour[v] = c;
     ncol = std::max(ncol, (int)c + 1);
   }
   return ncol;

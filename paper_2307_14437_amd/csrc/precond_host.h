@@ -29,6 +29,11 @@ bool ic_numeric(const HostCsr& A, double shift, const std::vector<int64_t>& Lptr
 // Greedy colouring of the graph of A: vertices in index order, each taking the
 // smallest colour no already coloured neighbour has.  Returns the colour count.
 int greedy_colouring(const HostCsr& A, std::vector<int32_t>& colour);
+// Colouring in Matula and Beck's smallest-last order: vertices removed one at
+// a time, each time one of least degree among those left (ties: the smallest
+// index), then coloured in the reverse order, each the smallest colour no
+// already coloured neighbour has.  Returns the colour count.
+int smallest_last_colouring(const HostCsr& A, std::vector<int32_t>& colour);
 // B = P A P^T for the order perm (B_ij = A_{perm[i], perm[j]}), rows sorted.
 void permute_symmetric(const HostCsr& A, const std::vector<int32_t>& perm, HostCsr& B);
 // Drop the off-diagonal entries of a lower pattern that join two vertices of

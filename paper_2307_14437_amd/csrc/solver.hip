@@ -1018,7 +1018,7 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     drop_same_colour(colour, Lptr, Lcol);
   } else if (bmc) {
     // blocks of at most BMC_BLOCK vertices grown breadth first, the graph of
-    // the blocks coloured greedily, vertices ordered by (block colour, block,
+    // the blocks coloured in smallest-last order, vertices ordered by (block colour, block,
     // vertex); the level-1 fill is kept inside a block and between colours,
     // so the blocks of one colour are never coupled in the factor
     std::vector<int32_t> blk;
@@ -1026,7 +1026,7 @@ extern "C" int gofd_precond_create(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op,
     HostCsr G;
     block_graph(A, blk, nb, G);
     std::vector<int32_t> bcol;
-    pc->info.colours = greedy_colouring(G, bcol);
+    pc->info.colours = smallest_last_colouring(G, bcol);
     if (pc->info.colours > TRSV_LEVEL_LAUNCH_MAX)
       return gofd_fail(ctx, GOFD_E_UNSUPPORTED, "block multicolour order needs more than 64 colours");
     pc->hperm.resize(A.n);

@@ -77,7 +77,7 @@ def test_grid_coincident_mesh_reduces_to_fd_3d(gctx):
     assert _rel(y, operator.apply_Ah(otr, T, u, "fft")) < 1e-12
 
 
-@pytest.mark.parametrize("pcn", ["NONE", "DIAG", "IC1_27", "IC1_27_MC", "IC1_27_LAP_MC"])
+@pytest.mark.parametrize("pcn", ["NONE", "DIAG", "IC1_27", "IC1_27_MC", "IC1_27_LAP_MC", "IC1_27_BMC"])
 def test_solve3_matches_dense(gctx, ball_small, pcn):
     import torch
     import paper_2307_14437_amd as gofd

@@ -379,10 +379,10 @@ def test_block_multicolour_ic1_on_the_c1_mesh(c1):
     Ac = Ap.tocoo()
     cross = pb[Ac.row] != pb[Ac.col]
     assert np.all(pc[Ac.row[cross]] != pc[Ac.col[cross]])
-    # greedy in block order: a block of colour c > 0 touches a block of lower id of every colour below c
+    # a block of colour c > 0 touches blocks of every colour below c (each took the smallest free colour)
     for b in np.unique(pb):
         rows = np.nonzero(pb == b)[0]
-        nbrs = {int(pb[j]) for i in rows for j in Ap.indices[Ap.indptr[i]:Ap.indptr[i + 1]] if pb[j] < b}
+        nbrs = {int(pb[j]) for i in rows for j in Ap.indices[Ap.indptr[i]:Ap.indptr[i + 1]] if pb[j] != b}
         assert set(range(pc[rows[0]])) <= {int(pc[np.nonzero(pb == q)[0][0]]) for q in nbrs}
     # factor: no entry between two blocks of one colour; L L^T = P A P^T on the kept pattern
     Lc = L.tocoo()
@@ -408,3 +408,20 @@ def test_grow_blocks_by_hand():
     S = sp.csr_matrix((np.ones(8), ([a for a, b in e] + [b for a, b in e], [b for a, b in e] + [a for a, b in e])),
                       shape=(5, 5))
     assert precond.grow_blocks(S, 3).tolist() == [0, 0, 0, 1, 2]
+
+
+def test_smallest_last_colouring_by_hand():
+    # the path 0 - 2 - 3 - 1: colouring in index order needs three colours (0, 1 -> 0; 2 -> 1; 3 -> 2); smallest
+    # last removes 0, 1 (degree 1), then 2 (degree 1, the smaller index of 2 and 3), then 3, and colours 3, 2, 1, 0
+    e = [(0, 2), (2, 3), (3, 1)]
+    A = sp.csr_matrix((np.ones(6), ([a for a, b in e] + [b for a, b in e], [b for a, b in e] + [a for a, b in e])),
+                      shape=(4, 4))
+    assert precond.greedy_colouring(A).tolist() == [0, 0, 1, 2]
+    assert precond.smallest_last_colouring(A).tolist() == [0, 1, 1, 0]
+    # a wheel: hub 0 and a rim cycle of 5 (odd): three colours for the rim, one for the hub
+    rim = [(i, i % 5 + 1) for i in range(1, 6)]
+    e = [(0, i) for i in range(1, 6)] + rim
+    W = sp.csr_matrix((np.ones(2 * len(e)), ([a for a, b in e] + [b for a, b in e], [b for a, b in e] + [a for a, b in e])),
+                      shape=(6, 6))
+    c = precond.smallest_last_colouring(W)
+    assert c.max() + 1 == 4 and all(c[a] != c[b] for a, b in e)
