@@ -699,6 +699,7 @@ def main():
     # bytes per launch from the layouts (each array read or written once)
     stage_sum = np.zeros(len(gofd.STAGES))
     stage_n = 0
+    precond_apply = {}
     for i, s in enumerate(svals):
         st_ms = np.zeros(len(gofd.STAGES))
         _, inf = gofd.solve(ctx, tr, ops[i], fd, tol=tol, pc=pcs[i], mode=gofd.MODE_FP32_RELIABLE,
@@ -706,6 +707,13 @@ def main():
         n_it = inf[0]["iterations"] + 1
         stage_sum += st_ms * n_it
         stage_n += n_it
+        if pc_for(args.precond, s) not in ("NONE", "DIAG"):
+            # the triangular solves of one iteration (all their launches), against the FFT product's passes
+            precond_apply[str(s)] = {
+                "preconditioner": pc_for(args.precond, s), "colours": pcs[i].info["colours"],
+                "us_per_iteration": st_ms[gofd.STAGES.index("precond")] * 1e3,
+                "product_us_per_iteration": sum(st_ms[gofd.STAGES.index(k)] for k in ("gather", "passA", "passB", "passC")
+                                                if k in gofd.STAGES) * 1e3}
     stage_ms = stage_sum / stage_n
     nb = _kernel_bytes(W, 2 * (W - 1), tr, m, 4, args.precond)
     kernels = {k: {"us": stage_ms[j] * 1e3, "bytes": nb[k], "GBs": nb[k] / (stage_ms[j] * 1e-3) / 1e9,
@@ -742,6 +750,7 @@ def main():
         "rel_error_vs_oracle": err_oracle,
         "all_within_1e-8_of_oracle": (None if any(v is None for v in err_oracle.values()) else
                                       all(e <= 1e-8 for v in err_oracle.values() for e in v.values())),
+        "preconditioner_apply": precond_apply,
         "preconditioned": pc_lines,
         "fp64": {"solves_per_s": len(svals) / (ms_step64 * 1e-3), "ms_per_step": ms_step64,
                  "iterations": {str(k): v for k, v in its64.items()}},

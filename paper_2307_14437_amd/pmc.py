@@ -4,7 +4,8 @@ Reads the counter_collection CSVs of four `rocprofv3 --pmc ... --output-format c
 runs: FETCH_SIZE and WRITE_SIZE of the benchmark, and the same two counters of a
 device-to-device copy of known size (`bench.py --copy-probe MiB`).  The copy
 gives the factor between each counter (KiB per dispatch) and the bytes actually
-moved; the benchmark's per-kernel averages are scaled by it.  Writes a JSON
+moved; the benchmark's per-kernel averages over its one-item dispatches (the
+kernel's smallest grid) are scaled by it.  Writes a JSON
 summary keyed by the stages of one CG iteration, with a hash of the sources of
 the measured kernels, so that a reader can tell when they have changed since.
 
@@ -48,10 +49,16 @@ def source_hash() -> str:
 
 
 def _load(d):
-    out = collections.defaultdict(list)
+    """Counter values per kernel, of the dispatches with the kernel's smallest grid: the launches that cover
+    one item (batched launches cover several items along the grid's y axis)."""
+    rows = collections.defaultdict(list)
     for path in glob.glob(os.path.join(d, "*counter_collection.csv")):
         for r in csv.DictReader(open(path)):
-            out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+            rows[r["Kernel_Name"]].append((int(r["Grid_Size"]), float(r["Counter_Value"])))
+    out = {}
+    for k, v in rows.items():
+        g = min(x[0] for x in v)
+        out[k] = [x[1] for x in v if x[0] == g]
     return out
 
 
