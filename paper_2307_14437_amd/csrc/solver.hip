@@ -698,7 +698,8 @@ __device__ __forceinline__ double block_product(const double (&m4)[4], double b,
 // the lanes of a row add the row's entries to other blocks (the block's slabs
 // of 64 entries, eoff[b]..eoff[b+1]-1, lane i * 4 + q of slab a holding entry
 // q + 4a of row i or -1; four slabs in flight), giving b_t, and the block's
-// rows then follow from the inverse of its own triangle (formed on the host):
+// rows then follow from the inverse of its own triangle (formed on the host;
+// values in single precision, arithmetic in double):
 //   LOWER:  y = L_bb^{-1} (r[perm] - L_b,other y_other).  With TAIL (the last
 //           colour) the wave goes on to the block's rows of U = L^T, which
 //           need no other block: u = U_bb^{-1} y.
@@ -707,8 +708,8 @@ __device__ __forceinline__ double block_product(const double (&m4)[4], double b,
 template <bool LOWER, bool TAIL>
 __global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, int b0, int b1,
                                                     const int* __restrict__ eoff, const int* __restrict__ ecol,
-                                                    const double* __restrict__ eval, const double* __restrict__ binv,
-                                                    const double* __restrict__ binvU, const int* __restrict__ perm,
+                                                    const float* __restrict__ eval, const float* __restrict__ binv,
+                                                    const float* __restrict__ binvU, const int* __restrict__ perm,
                                                     const double* __restrict__ r, double* __restrict__ y,
                                                     double* __restrict__ pu, double* __restrict__ u, long long stride,
                                                     const Scal* __restrict__ sc, double* __restrict__ part, int nbu) {
@@ -732,7 +733,7 @@ __global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, 
     const double rhs = LOWER ? rv : yk[t];
     double m4[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) m4[a] = binv[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
+    for (int a = 0; a < 4; ++a) m4[a] = (double)binv[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
     double s = 0.0;
     for (int a0 = 0; a0 < ns; a0 += 4) {
 #pragma unroll
@@ -741,8 +742,8 @@ __global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, 
         const int c = ecol[idx];
         const double w = eval[idx];
         const bool use = a0 + a < ns && c >= 0;
-        // padding re-reads the entry's own value (never a location this launch writes); the product is masked
-        const double x = *(use ? dep + c : eval + idx);
+        // padding re-reads the row's value of r (never a location this launch writes); the product is masked
+        const double x = *(use ? dep + c : rk + v);
         s += use ? w * x : 0.0;
       }
     }
@@ -750,7 +751,7 @@ __global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, 
     double xi = block_product(m4, ok ? rhs - s : 0.0, q);
     if constexpr (TAIL) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) m4[a] = binvU[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
+      for (int a = 0; a < 4; ++a) m4[a] = (double)binvU[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
       xi = block_product(m4, ok ? xi : 0.0, q);
     }
     if (ok && q == 0) {
@@ -829,7 +830,7 @@ struct gofd_precond_s {
   // Lecol / Uecol and values: rows of L, resp. of U = L^T) and the inverse of
   // each block's own triangle, dense (bL: L_bb^{-1}, bU: U_bb^{-1}; 256 per
   // block, value (i, j) at ((j / 4) * 64 + i * 4 + j % 4), the register layout
-  // of the solve)
+  // of the solve); values stored in single precision, the solves in double
   std::vector<int32_t> hbs, hbc;
   DevBuf bs, Leptr, Lecol, Leval, Ueptr, Uecol, Ueval, bL, bU;
   gofd_precond_info info{};
@@ -853,9 +854,9 @@ static int upload_block_factor(gofd_ctx_s* ctx, gofd_precond_s* pc, const std::v
   for (int b = 0; b < nb; ++b)
     for (int t = pc->hbs[b]; t < pc->hbs[b + 1]; ++t) fb[t] = b;
   auto slot = [](int i, int j) { return (j / 4) * 64 + i * 4 + (j % 4); };
-  std::vector<double> binv((size_t)nb * BB, 0.0), binvU((size_t)nb * BB, 0.0);
+  std::vector<float> binv((size_t)nb * BB, 0.0f), binvU((size_t)nb * BB, 0.0f);
   std::vector<int32_t> eoffL(nb + 1, 0), eoffU(nb + 1, 0), ecL, ecU;
-  std::vector<double> evL, evU;
+  std::vector<float> evL, evU;
   std::vector<std::vector<std::pair<int32_t, double>>> extL(BS_), extU(BS_);
   for (int b = 0; b < nb; ++b) {
     const int t0 = pc->hbs[b], m = pc->hbs[b + 1] - t0;
@@ -883,13 +884,13 @@ static int upload_block_factor(gofd_ctx_s* ctx, gofd_precond_s* pc, const std::v
         x[i] = acc / Lb[i][i];
       }
       for (int i = c; i < m; ++i) {
-        binv[(size_t)b * BB + slot(i, c)] = x[i];
-        binvU[(size_t)b * BB + slot(c, i)] = x[i];
+        binv[(size_t)b * BB + slot(i, c)] = (float)x[i];
+        binvU[(size_t)b * BB + slot(c, i)] = (float)x[i];
       }
     }
     // slabs of 64: lane i * 4 + q of slab a holds entry q + 4a of row i (col -1: none)
     auto slabs = [&](std::vector<std::vector<std::pair<int32_t, double>>>& ext, std::vector<int32_t>& off,
-                     std::vector<int32_t>& ec, std::vector<double>& ev) {
+                     std::vector<int32_t>& ec, std::vector<float>& ev) {
       size_t mx = 0;
       for (int i = 0; i < m; ++i) mx = std::max(mx, ext[i].size());
       const int ns = (int)((mx + 3) / 4);
@@ -898,7 +899,7 @@ static int upload_block_factor(gofd_ctx_s* ctx, gofd_precond_s* pc, const std::v
           const int i = lane / 4, e = lane % 4 + 4 * a;
           const bool has = i < m && e < (int)ext[i].size();
           ec.push_back(has ? ext[i][e].first : -1);
-          ev.push_back(has ? ext[i][e].second : 0.0);
+          ev.push_back(has ? (float)ext[i][e].second : 0.0f);
         }
       off[b + 1] = (int32_t)ec.size();
     };
@@ -916,12 +917,12 @@ static int upload_block_factor(gofd_ctx_s* ctx, gofd_precond_s* pc, const std::v
   GOFD_TRY(up(pc->bs, pc->hbs.data(), sizeof(int32_t) * pc->hbs.size()));
   GOFD_TRY(up(pc->Leptr, eoffL.data(), sizeof(int32_t) * eoffL.size()));
   GOFD_TRY(up(pc->Lecol, ecL.data(), sizeof(int32_t) * ecL.size()));
-  GOFD_TRY(up(pc->Leval, evL.data(), sizeof(double) * evL.size()));
+  GOFD_TRY(up(pc->Leval, evL.data(), sizeof(float) * evL.size()));
   GOFD_TRY(up(pc->Ueptr, eoffU.data(), sizeof(int32_t) * eoffU.size()));
   GOFD_TRY(up(pc->Uecol, ecU.data(), sizeof(int32_t) * ecU.size()));
-  GOFD_TRY(up(pc->Ueval, evU.data(), sizeof(double) * evU.size()));
-  GOFD_TRY(up(pc->bL, binv.data(), sizeof(double) * binv.size()));
-  GOFD_TRY(up(pc->bU, binvU.data(), sizeof(double) * binvU.size()));
+  GOFD_TRY(up(pc->Ueval, evU.data(), sizeof(float) * evU.size()));
+  GOFD_TRY(up(pc->bL, binv.data(), sizeof(float) * binv.size()));
+  GOFD_TRY(up(pc->bU, binvU.data(), sizeof(float) * binvU.size()));
   HIP_TRY(ctx, hipStreamSynchronize(st));
   return GOFD_OK;
 }
@@ -1467,21 +1468,21 @@ int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, doub
       for (int c = 0; c + 1 < C; ++c) {
         const int b0 = pc->hbc[c], b1 = pc->hbc[c + 1];
         hipLaunchKernelGGL((k_trsv_block<true, false>), dim3(waves(b1 - b0), P.nrhs), dim3(256), 0, st,
-                           pc->bs.as<int>(), b0, b1, pc->Leptr.as<int>(), pc->Lecol.as<int>(), pc->Leval.as<double>(),
-                           pc->bL.as<double>(), nullptr, perm_d, rin, y, pu, u, n, scq, nullptr, 0);
+                           pc->bs.as<int>(), b0, b1, pc->Leptr.as<int>(), pc->Lecol.as<int>(), pc->Leval.as<float>(),
+                           pc->bL.as<float>(), nullptr, perm_d, rin, y, pu, u, n, scq, nullptr, 0);
       }
       {
         const int b0 = pc->hbc[C - 1], b1 = pc->hbc[C];
         hipLaunchKernelGGL((k_trsv_block<true, true>), dim3(part ? w.nbs : waves(b1 - b0), P.nrhs), dim3(256), 0,
                            st, pc->bs.as<int>(), b0, b1, pc->Leptr.as<int>(), pc->Lecol.as<int>(),
-                           pc->Leval.as<double>(), pc->bL.as<double>(), pc->bU.as<double>(), perm_d, rin, y, pu, u,
+                           pc->Leval.as<float>(), pc->bL.as<float>(), pc->bU.as<float>(), perm_d, rin, y, pu, u,
                            n, scq, part, w.nbs);
       }
       for (int c = C - 2; c >= 0; --c) {
         const int b0 = pc->hbc[c], b1 = pc->hbc[c + 1];
         hipLaunchKernelGGL((k_trsv_block<false, false>), dim3(part ? w.nbs : waves(b1 - b0), P.nrhs), dim3(256), 0,
                            st, pc->bs.as<int>(), b0, b1, pc->Ueptr.as<int>(), pc->Uecol.as<int>(),
-                           pc->Ueval.as<double>(), pc->bU.as<double>(), nullptr, perm_d, rin, y, pu, u, n, scq,
+                           pc->Ueval.as<float>(), pc->bU.as<float>(), nullptr, perm_d, rin, y, pu, u, n, scq,
                            part, w.nbs);
       }
       continue;
