@@ -160,7 +160,8 @@ def oracle_errors(cfg, tr, us):
 
 def run_c4(args):
     """The batched workload: 64 seeded star-shaped meshes (2k..100k vertices, log-uniform), grids 128^2..1024^2,
-    s ~ U[0.1, 0.9], 16 Fourier right-hand sides each (1024 systems), plain CG to a relative residual of 1e-9
+    s ~ U[0.1, 0.9], 16 Fourier right-hand sides each (1024 systems), CG preconditioned as pc_for chooses (or
+    plain CG, timed beside it) to a relative residual of 1e-9
     (with 1e-8 the FP32 and FP64 solutions of some members differ by 1.3e-8, so the tighter stop is what
     brings every system within 1e-8 of its exact solution: the errors are reported against FP64 solves to
     1e-12, which the tests check against the oracle on members of each grid size).  One step = one
@@ -187,6 +188,11 @@ def run_c4(args):
     ops = [gofd.FdOp(ctx, p["s"], p["grid"]) for p in probs]
     _sync(); t_op = (time.perf_counter() - t) * 1e3
     fs = [torch.tensor(np.stack(p["f"]), device="cuda") for p in probs]
+    # preconditioners per member (pc_for: the Laplacian's block multicolour IC(1) above s = 1/2, none below)
+    t = time.perf_counter()
+    pcs = [gofd.Precond(ctx, tr_, op_, pc_for(args.precond, p["s"])) for tr_, op_, p in zip(trs, ops, probs)]
+    _sync(); t_pc = (time.perf_counter() - t) * 1e3
+    n_ic = sum(pc_for(args.precond, p["s"]) != "NONE" for p in probs)
     shapes = {}
     for p in probs:
         shapes[2 * p["grid"].N] = shapes.get(2 * p["grid"].N, 0) + 1
@@ -196,13 +202,14 @@ def run_c4(args):
             gofd.autotune(ctx, g, fp32=fp32)
     nsys = sum(len(p["f"]) for p in probs)
 
-    def step(mode, sel=None, tol=args.c4_tol):
+    def step(mode, sel=None, tol=args.c4_tol, plain=False):
         idx = range(len(probs)) if sel is None else sel
-        return gofd.solve_batched(ctx, [trs[i] for i in idx], [ops[i] for i in idx], [None] * len(idx),
+        return gofd.solve_batched(ctx, [trs[i] for i in idx], [ops[i] for i in idx],
+                                  [None if plain else pcs[i] for i in idx],
                                   [fs[i] for i in idx], tol=tol, mode=mode,
                                   inner_tol=0.1 if mode == gofd.MODE_FP32_RELIABLE else 1e-4)
 
-    uref, _ = step(gofd.MODE_FP64, tol=1e-12)
+    uref, _ = step(gofd.MODE_FP64, tol=1e-12, plain=True)
 
     res = {}
     for name, mode in (("fp32_reliable", gofd.MODE_FP32_RELIABLE), ("fp64", gofd.MODE_FP64)):
@@ -222,6 +229,17 @@ def run_c4(args):
             a, b = a.view(len(p["f"]), -1), b.view(len(p["f"]), -1)
             e = max(e, float((torch.linalg.norm(a - b, dim=1) / torch.linalg.norm(b, dim=1)).max()))
         return e
+    # the same FP32 step by plain CG (every member without a preconditioner)
+    step(gofd.MODE_FP32_RELIABLE, plain=True)
+    _sync(); t = time.perf_counter()
+    for _ in range(args.steps):
+        us_p, infos_p = step(gofd.MODE_FP32_RELIABLE, plain=True)
+    _sync()
+    ms_p = (time.perf_counter() - t) * 1e3 / args.steps
+    its_p = [i["iterations"] for i in infos_p]
+    res["fp32_reliable_plain_cg"] = {"ms_per_step": ms_p, "solves_per_s": nsys / (ms_p * 1e-3),
+                                     "iterations_min_max": [min(its_p), max(its_p)],
+                                     "max_rel_residual": max(i["rel_residual"] for i in infos_p), "u": us_p}
     for r in res.values():
         r["max_rel_error_vs_fp64_at_1e-12"] = max_err(r["u"])
     # the shape groups one call after another (what the batched call did before the groups ran concurrently)
@@ -242,13 +260,18 @@ def run_c4(args):
         "warmup": args.warmup, "ms_per_step": res["fp32_reliable"]["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32-grid/f64-refine", "data": "synthetic",
         "config": {"workload": "64 star-shaped meshes (2k..100k vertices, log-uniform), grids 128^2..1024^2, "
-                               f"s ~ U[0.1, 0.9], 16 Fourier right-hand sides each, tol {args.c4_tol:g}, plain CG",
+                               f"s ~ U[0.1, 0.9], 16 Fourier right-hand sides each, tol {args.c4_tol:g}, "
+                               + ("PCG (the Laplacian's block multicolour IC(1) for s > 1/2, none below)"
+                                  if args.precond == "auto" else f"preconditioner {args.precond}"),
+                   "members_preconditioned": n_ic,
                    "systems": nsys, "grids": {str(k): v for k, v in sorted(shapes.items())},
                    "vertices": int(sum(p["mesh"].nv for p in probs))},
         "fp32_reliable": res["fp32_reliable"], "fp64": res["fp64"],
+        "fp32_reliable_plain_cg": res["fp32_reliable_plain_cg"],
         "all_within_1e-8": all(r["max_rel_error_vs_fp64_at_1e-12"] <= 1e-8 for r in res.values()),
         "fp32_groups_one_after_another": {"ms_per_step": ms_seq, "solves_per_s": nsys / (ms_seq * 1e-3)},
-        "setup_s": {"inputs_host": t_inputs, "build_transfer": t_tr * 1e-3, "fd_weights": t_op * 1e-3},
+        "setup_s": {"inputs_host": t_inputs, "build_transfer": t_tr * 1e-3, "fd_weights": t_op * 1e-3,
+                    "preconditioners": t_pc * 1e-3},
     }
     print(json.dumps(line), flush=True)
 
