@@ -691,36 +691,67 @@ __device__ __forceinline__ double block_product(const double (&m4)[4], double b,
   return quad_add<0x4E>(quad_add<0xB1>(p));
 }
 
-// One colour of the triangular solves in block multicolour order: the
-// colour's blocks b0..b1-1 (rows bs[b]..bs[b+1]-1 of the factor's order, row t
-// is vertex perm[t]) depend only on blocks of colours that earlier launches
-// solved.  A wave takes one block at a time (four per workgroup, grid-stride):
-// the lanes of a row add the row's entries to other blocks (the block's slabs
-// of 64 entries, eoff[b]..eoff[b+1]-1, lane i * 4 + q of slab a holding entry
-// q + 4a of row i or -1; four slabs in flight), giving b_t, and the block's
-// rows then follow from the inverse of its own triangle (formed on the host;
-// values in single precision, arithmetic in double):
-//   LOWER:  y = L_bb^{-1} (r[perm] - L_b,other y_other).  With TAIL (the last
-//           colour) the wave goes on to the block's rows of U = L^T, which
-//           need no other block: u = U_bb^{-1} y.
-//   upper:  u = U_bb^{-1} (y - U_b,other u_other).
-// Outputs and gamma's partials (grid of nbu workgroups) as in k_trsv_colour.
-template <bool LOWER, bool TAIL>
-__global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, int b0, int b1,
-                                                    const int* __restrict__ eoff, const int* __restrict__ ecol,
-                                                    const float* __restrict__ eval, const float* __restrict__ binv,
-                                                    const float* __restrict__ binvU, const int* __restrict__ perm,
-                                                    const double* __restrict__ r, double* __restrict__ y,
-                                                    double* __restrict__ pu, double* __restrict__ u, long long stride,
-                                                    const Scal* __restrict__ sc, double* __restrict__ part, int nbu) {
-  __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
-  const int k = blockIdx.y;
-  if (sc && sc[k].done) return;
+// One item (problem, right-hand side) of the block multicolour solves: its
+// factor's arrays (see gofd_precond_s), its colour table (colour c is blocks
+// cbeg[c]..cbeg[c+1]-1, ncol colours) and its vectors at off.
+struct BmcItem {
+  const int* bs;
+  const int* cbeg;
+  const int* eoffL;
+  const int* ecolL;
+  const float* evalL;
+  const int* eoffU;
+  const int* ecolU;
+  const float* evalU;
+  const float* binvL;
+  const float* binvU;
+  const int* perm;
+  long long off;
+  int item, ncol;
+};
+
+// One colour of the triangular solves in block multicolour order, for every
+// item of the launch (blockIdx.y): the item's blocks of colour c (rows
+// bs[b]..bs[b+1]-1 of its factor's order, row t is vertex perm[t]) depend only
+// on blocks of colours that earlier launches solved.  A wave takes one block
+// at a time (four per workgroup, grid-stride): the lanes of a row add the
+// row's entries to other blocks (the block's slabs of 64 entries,
+// eoff[b]..eoff[b+1]-1, lane i * 4 + q of slab a holding entry q + 4a of row i
+// or -1; four slabs in flight), giving b_t, and the block's rows then follow
+// from the inverse of its own triangle (formed on the host; values in single
+// precision, arithmetic in double):
+//   LOWER:  y = L_bb^{-1} (r[perm] - L_b,other y_other).  On the item's last
+//           colour the wave goes on to the block's rows of U = L^T, which need
+//           no other block: u = U_bb^{-1} y.
+//   upper:  u = U_bb^{-1} (y - U_b,other u_other)   (colours below the last).
+// A solved u goes to pu (factor order, read by later colours) and to u[perm]
+// (vertex order); with part given, workgroup w adds r[perm t] u_t of its rows
+// to the item's partial w of gamma (part + item * nbu), the last colour's
+// launch storing instead and clearing the partials past its grid, so that
+// after colour 0 the item's nbu partials hold (r, u) in a fixed order.
+//
+// trsv_block_item: the work of one workgroup on one item, blocks b0..b1-1 of
+// the item's colour, the last colour's upper rows too when tail.
+template <bool LOWER>
+__device__ __forceinline__ void trsv_block_item(const int* __restrict__ bs_, const int* __restrict__ eoff_,
+                                                const int* __restrict__ ecol_, const float* __restrict__ eval_,
+                                                const float* __restrict__ binv_, const float* __restrict__ binvU_,
+                                                const int* __restrict__ perm_, long long off, int item, bool tail,
+                                                int b0, int b1, const double* __restrict__ r, double* __restrict__ y,
+                                                double* __restrict__ pu, double* __restrict__ u,
+                                                double* __restrict__ part, int nbu, double* sh) {
+  // the pointers as global ones (loads through them are global, not flat)
+  const auto bs = gmem(bs_);
+  const auto eoff = gmem(eoff_);
+  const auto ecol = gmem(ecol_);
+  const auto eval = gmem(eval_);
+  const auto binv = gmem(binv_);
+  const auto perm = gmem(perm_);
   const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
   const int i = lane >> 2, q = lane & 3;
-  const double* rk = r + k * stride;
-  double* yk = y + k * stride;
-  double* puk = pu + k * stride;
+  const double* rk = r + off;
+  double* yk = y + off;
+  double* puk = pu + off;
   const double* dep = LOWER ? yk : puk;
   double acc = 0.0;
   for (int kb = b0 + (int)blockIdx.x * 4 + wave; kb < b1; kb += (int)gridDim.x * 4) {
@@ -739,40 +770,78 @@ __global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, 
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int idx = e0 + min(a0 + a, ns - 1) * 64 + lane;
-        const int c = ecol[idx];
+        const int cc = ecol[idx];
         const double w = eval[idx];
-        const bool use = a0 + a < ns && c >= 0;
+        const bool use = a0 + a < ns && cc >= 0;
         // padding re-reads the row's value of r (never a location this launch writes); the product is masked
-        const double x = *(use ? dep + c : rk + v);
+        const double x = *(use ? dep + cc : rk + v);
         s += use ? w * x : 0.0;
       }
     }
     s = quad_add<0x4E>(quad_add<0xB1>(s));
     double xi = block_product(m4, ok ? rhs - s : 0.0, q);
-    if constexpr (TAIL) {
+    if (tail) {
+      const auto binvU = gmem(binvU_);
 #pragma unroll
       for (int a = 0; a < 4; ++a) m4[a] = (double)binvU[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
       xi = block_product(m4, ok ? xi : 0.0, q);
     }
     if (ok && q == 0) {
-      if (LOWER && !TAIL) {
+      if (LOWER && !tail) {
         yk[t] = xi;
       } else {
         puk[t] = xi;
-        u[k * stride + v] = xi;
+        u[off + v] = xi;
         acc += rv * xi;
       }
     }
   }
-  if (LOWER && !TAIL) return;
-  if (part) {
-    double s1[1] = {acc};
-    gofd_cg::block_sum_n<256, 1>(s1, sh);
-    if (threadIdx.x == 0) {
-      double* p = part + (long long)k * nbu + blockIdx.x;
-      *p = TAIL ? s1[0] : *p + s1[0];
-    }
+  if (!part || (LOWER && !tail)) return;              // block-uniform
+  double s1[1] = {acc};
+  gofd_cg::block_sum_n<256, 1>(s1, sh);
+  if (threadIdx.x == 0) {
+    double* p = part + (long long)item * nbu;
+    p[blockIdx.x] = tail ? s1[0] : p[blockIdx.x] + s1[0];
+    if (tail && blockIdx.x == 0)
+      for (int w = gridDim.x; w < nbu; ++w) p[w] = 0.0;
   }
+}
+
+// One problem's items (blockIdx.y = right-hand side k, item i0 + k, vectors
+// at off0 + k * stride), its factor's arrays and the colour's block range as
+// arguments; TAIL on the problem's last colour.
+template <bool LOWER, bool TAIL>
+__global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, int b0, int b1,
+                                                    const int* __restrict__ eoff, const int* __restrict__ ecol,
+                                                    const float* __restrict__ eval, const float* __restrict__ binv,
+                                                    const float* __restrict__ binvU, const int* __restrict__ perm,
+                                                    const double* __restrict__ r, double* __restrict__ y,
+                                                    double* __restrict__ pu, double* __restrict__ u, long long off0,
+                                                    long long stride, int i0, const Scal* __restrict__ sc,
+                                                    double* __restrict__ part, int nbu) {
+  __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
+  const int item = i0 + (int)blockIdx.y;
+  if (sc && sc[item].done) return;                    // block-uniform
+  trsv_block_item<LOWER>(bs, eoff, ecol, eval, binv, binvU, perm, off0 + blockIdx.y * stride, item, TAIL, b0, b1,
+                         r, y, pu, u, part, nbu, sh);
+}
+
+// Every item of the table (blockIdx.y) in one launch per colour c; an item
+// without that colour in this direction returns at once.
+template <bool LOWER>
+__global__ __launch_bounds__(256) void k_trsv_block_items(const BmcItem* __restrict__ items, int c,
+                                                          const double* __restrict__ r, double* __restrict__ y,
+                                                          double* __restrict__ pu, double* __restrict__ u,
+                                                          const Scal* __restrict__ sc, double* __restrict__ part,
+                                                          int nbu) {
+  __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
+  const BmcItem I = items[blockIdx.y];                // a kernel argument: global, scalar loads
+  if (sc && sc[I.item].done) return;                  // block-uniform
+  if (LOWER ? c >= I.ncol : c > I.ncol - 2) return;   // the item has no such colour in this direction
+  const int b0 = gmem(I.cbeg)[c], b1 = gmem(I.cbeg)[c + 1];
+  trsv_block_item<LOWER>(I.bs, LOWER ? I.eoffL : I.eoffU, LOWER ? I.ecolL : I.ecolU, LOWER ? I.evalL : I.evalU,
+                         LOWER ? I.binvL : I.binvU, I.binvU, I.perm, I.off, I.item, LOWER && c == I.ncol - 1, b0, b1,
+                         r, y, pu, u, part, nbu, sh);
 }
 
 // out[i] = in[perm[i]] (to = true) or out[perm[i]] = in[i], per right-hand side blockIdx.y
@@ -832,7 +901,7 @@ struct gofd_precond_s {
   // block, value (i, j) at ((j / 4) * 64 + i * 4 + j % 4), the register layout
   // of the solve); values stored in single precision, the solves in double
   std::vector<int32_t> hbs, hbc;
-  DevBuf bs, Leptr, Lecol, Leval, Ueptr, Uecol, Ueval, bL, bU;
+  DevBuf bs, cbeg, Leptr, Lecol, Leval, Ueptr, Uecol, Ueval, bL, bU;
   gofd_precond_info info{};
 };
 
@@ -915,6 +984,7 @@ static int upload_block_factor(gofd_ctx_s* ctx, gofd_precond_s* pc, const std::v
     return GOFD_OK;
   };
   GOFD_TRY(up(pc->bs, pc->hbs.data(), sizeof(int32_t) * pc->hbs.size()));
+  GOFD_TRY(up(pc->cbeg, pc->hbc.data(), sizeof(int32_t) * pc->hbc.size()));
   GOFD_TRY(up(pc->Leptr, eoffL.data(), sizeof(int32_t) * eoffL.size()));
   GOFD_TRY(up(pc->Lecol, ecL.data(), sizeof(int32_t) * ecL.size()));
   GOFD_TRY(up(pc->Leval, evL.data(), sizeof(float) * evL.size()));
@@ -1240,6 +1310,12 @@ struct Batch {
   int rp_ent_ahead = 0;            // entries of a thread the last row pass reads ahead (largest of the items)
   gofd_fdop_s* op0 = nullptr;      // shape and FFT workspaces of the batch
   DevView items, tab64, tab32;     // CgItem[nitems]; spectrum pointer tables (in the context's buffers)
+  // items preconditioned in block multicolour order: their descriptors, the
+  // most colours among them and, per colour, the most blocks of one item
+  DevView bmc;
+  int nbmc = 0, bmc_cols = 0;
+  std::vector<int> bmc_blocks;
+  int nbmc_probs = 0, bmc_prob = -1;  // problems with such items; the (last) one of them
 };
 
 int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
@@ -1306,11 +1382,45 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
   }
   B.nitems = (int)h.size();
   B.ntot = off;
+  std::vector<BmcItem> hb;
+  for (size_t q = 0; q < probs.size(); ++q) {
+    const gofd_precond_s* pc = probs[q].pc;
+    if (!is_ic(pc) || pc->hbc.empty()) continue;
+    const int C = (int)pc->hbc.size() - 1;
+    B.bmc_cols = std::max(B.bmc_cols, C);
+    if ((int)B.bmc_blocks.size() < C) B.bmc_blocks.resize(C, 0);
+    for (int c = 0; c < C; ++c) B.bmc_blocks[c] = std::max(B.bmc_blocks[c], pc->hbc[c + 1] - pc->hbc[c]);
+    for (int k = 0; k < probs[q].nrhs; ++k) {
+      BmcItem e{};
+      e.bs = pc->bs.as<int>();
+      e.cbeg = pc->cbeg.as<int>();
+      e.eoffL = pc->Leptr.as<int>();
+      e.ecolL = pc->Lecol.as<int>();
+      e.evalL = pc->Leval.as<float>();
+      e.eoffU = pc->Ueptr.as<int>();
+      e.ecolU = pc->Uecol.as<int>();
+      e.evalU = pc->Ueval.as<float>();
+      e.binvL = pc->bL.as<float>();
+      e.binvU = pc->bU.as<float>();
+      e.perm = pc->perm.as<int>();
+      e.item = B.pitem[q] + k;
+      e.off = B.ioff[e.item];
+      e.ncol = C;
+      hb.push_back(e);
+    }
+  }
+  B.nbmc = (int)hb.size();
+  for (size_t q = 0; q < probs.size(); ++q)
+    if (is_ic(probs[q].pc) && !probs[q].pc->hbc.empty()) {
+      ++B.nbmc_probs;
+      B.bmc_prob = (int)q;
+    }
   B.seg = B.seg && B.rp && !B.any_ic;        // IC(1) makes u in its own kernels
-  // one block [CgItem x n | void* x n | void* x n], staged in page-locked
-  // memory (the previous solve on the context has finished with it) and
-  // copied in one transfer, without waiting for it
-  const size_t n = h.size(), o64 = sizeof(CgItem) * n, o32 = o64 + sizeof(void*) * n, bytes = o32 + sizeof(void*) * n;
+  // one block [CgItem x n | void* x n | void* x n | BmcItem x nbmc], staged in
+  // page-locked memory (the previous solve on the context has finished with
+  // it) and copied in one transfer, without waiting for it
+  const size_t n = h.size(), o64 = sizeof(CgItem) * n, o32 = o64 + sizeof(void*) * n, ob = o32 + sizeof(void*) * n,
+               bytes = ob + sizeof(BmcItem) * hb.size();
   BatchBufs& bb = ctx_batch(ctx);
   if (bb.stage_bytes < bytes) {
     if (bb.stage) (void)hipHostFree(bb.stage);
@@ -1322,12 +1432,14 @@ int batch_init(gofd_ctx_s* ctx, Batch& B, const std::vector<Problem>& probs) {
   char* sp = static_cast<char*>(bb.stage);
   std::memcpy(sp, h.data(), o64);
   std::memcpy(sp + o64, t64.data(), o32 - o64);
-  std::memcpy(sp + o32, t32.data(), bytes - o32);
+  std::memcpy(sp + o32, t32.data(), ob - o32);
+  if (!hb.empty()) std::memcpy(sp + ob, hb.data(), bytes - ob);
   GOFD_TRY(dev_reserve(ctx, bb.desc, bytes));
   HIP_TRY(ctx, hipMemcpyAsync(bb.desc.p, bb.stage, bytes, hipMemcpyHostToDevice, ctx->stream));
   B.items.p = bb.desc.p;
   B.tab64.p = static_cast<char*>(bb.desc.p) + o64;
   B.tab32.p = static_cast<char*>(bb.desc.p) + o32;
+  B.bmc.p = hb.empty() ? nullptr : static_cast<char*>(bb.desc.p) + ob;
   return GOFD_OK;
 }
 
@@ -1447,6 +1559,55 @@ int apply_K_plain(gofd_ctx_s* ctx, const Batch& B, Work& w, const double* v, dou
 // writes the partials of gamma = (r, u) into partG (if given)
 int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, double* partG) {
   hipStream_t st = ctx->stream;
+  if (B.nbmc) {
+    // the items in block multicolour order: one launch per colour and direction for all of them (an item's
+    // last colour solves its lower and upper rows in one launch); grids of at most nbs workgroups, the
+    // partials' count
+    auto grid = [&](int c) {
+      return dim3((unsigned)std::max(1, std::min(w.nbs, (B.bmc_blocks[c] + 3) / 4)), (unsigned)B.nbmc);
+    };
+    if (B.nbmc_probs == 1) {
+      // one problem: its arrays and block ranges as arguments (no descriptor loads)
+      const Problem& P = B.probs[B.bmc_prob];
+      const gofd_precond_s* pc = P.pc;
+      const int C = (int)pc->hbc.size() - 1;
+      const long long o = B.poff[B.bmc_prob], n = P.tr->nv;
+      const int i0 = B.pitem[B.bmc_prob];
+      // (a launch that writes the partials covers all nbs of them)
+      auto g1 = [&](int c, bool partials) {
+        return dim3(partials ? (unsigned)w.nbs : (unsigned)std::max(1, (pc->hbc[c + 1] - pc->hbc[c] + 3) / 4),
+                    P.nrhs);
+      };
+      for (int c = 0; c < C; ++c) {
+        const int b0 = pc->hbc[c], b1 = pc->hbc[c + 1];
+        if (c + 1 < C)
+          hipLaunchKernelGGL((k_trsv_block<true, false>), g1(c, false), dim3(256), 0, st, pc->bs.as<int>(), b0, b1,
+                             pc->Leptr.as<int>(), pc->Lecol.as<int>(), pc->Leval.as<float>(), pc->bL.as<float>(),
+                             nullptr, pc->perm.as<int>(), w.r.as<double>(), w.dvec.as<double>(), w.pu.as<double>(),
+                             w.u.as<double>(), o, n, i0, sc, nullptr, w.nbs);
+        else
+          hipLaunchKernelGGL((k_trsv_block<true, true>), g1(c, partG != nullptr), dim3(256), 0, st, pc->bs.as<int>(),
+                             b0, b1,
+                             pc->Leptr.as<int>(), pc->Lecol.as<int>(), pc->Leval.as<float>(), pc->bL.as<float>(),
+                             pc->bU.as<float>(), pc->perm.as<int>(), w.r.as<double>(), w.dvec.as<double>(),
+                             w.pu.as<double>(), w.u.as<double>(), o, n, i0, sc, partG, w.nbs);
+      }
+      for (int c = C - 2; c >= 0; --c)
+        hipLaunchKernelGGL((k_trsv_block<false, false>), g1(c, partG != nullptr), dim3(256), 0, st, pc->bs.as<int>(),
+                           pc->hbc[c],
+                           pc->hbc[c + 1], pc->Ueptr.as<int>(), pc->Uecol.as<int>(), pc->Ueval.as<float>(),
+                           pc->bU.as<float>(), nullptr, pc->perm.as<int>(), w.r.as<double>(), w.dvec.as<double>(),
+                           w.pu.as<double>(), w.u.as<double>(), o, n, i0, sc, partG, w.nbs);
+    } else {
+      const BmcItem* items = B.bmc.as<BmcItem>();
+      for (int c = 0; c < B.bmc_cols; ++c)
+        hipLaunchKernelGGL(k_trsv_block_items<true>, grid(c), dim3(256), 0, st, items, c, w.r.as<double>(),
+                           w.dvec.as<double>(), w.pu.as<double>(), w.u.as<double>(), sc, partG, w.nbs);
+      for (int c = B.bmc_cols - 2; c >= 0; --c)
+        hipLaunchKernelGGL(k_trsv_block_items<false>, grid(c), dim3(256), 0, st, items, c, w.r.as<double>(),
+                           w.dvec.as<double>(), w.pu.as<double>(), w.u.as<double>(), sc, partG, w.nbs);
+    }
+  }
   for (size_t q = 0; q < B.probs.size(); ++q) {
     const Problem& P = B.probs[q];
     if (!is_ic(P.pc)) continue;
@@ -1454,39 +1615,7 @@ int precond_apply(gofd_ctx_s* ctx, const Batch& B, Work& w, const Scal* sc, doub
     const long long n = P.tr->nv, o = B.poff[q];
     const int i0 = B.pitem[q];
     const Scal* scq = sc ? sc + i0 : nullptr;
-    if (!pc->hbc.empty()) {
-      // block multicolour order: one launch per colour and direction, the
-      // last colour's blocks of U solved in the last lower launch
-      const int C = (int)pc->hbc.size() - 1;
-      const double* rin = w.r.as<double>() + o;
-      double* y = w.dvec.as<double>() + o;
-      double* pu = w.pu.as<double>() + o;
-      double* u = w.u.as<double>() + o;
-      double* part = partG ? partG + (long long)i0 * w.nbs : nullptr;
-      const int* perm_d = pc->perm.as<int>();
-      auto waves = [](int nblk) { return (unsigned)std::max(1, (nblk + 3) / 4); };
-      for (int c = 0; c + 1 < C; ++c) {
-        const int b0 = pc->hbc[c], b1 = pc->hbc[c + 1];
-        hipLaunchKernelGGL((k_trsv_block<true, false>), dim3(waves(b1 - b0), P.nrhs), dim3(256), 0, st,
-                           pc->bs.as<int>(), b0, b1, pc->Leptr.as<int>(), pc->Lecol.as<int>(), pc->Leval.as<float>(),
-                           pc->bL.as<float>(), nullptr, perm_d, rin, y, pu, u, n, scq, nullptr, 0);
-      }
-      {
-        const int b0 = pc->hbc[C - 1], b1 = pc->hbc[C];
-        hipLaunchKernelGGL((k_trsv_block<true, true>), dim3(part ? w.nbs : waves(b1 - b0), P.nrhs), dim3(256), 0,
-                           st, pc->bs.as<int>(), b0, b1, pc->Leptr.as<int>(), pc->Lecol.as<int>(),
-                           pc->Leval.as<float>(), pc->bL.as<float>(), pc->bU.as<float>(), perm_d, rin, y, pu, u,
-                           n, scq, part, w.nbs);
-      }
-      for (int c = C - 2; c >= 0; --c) {
-        const int b0 = pc->hbc[c], b1 = pc->hbc[c + 1];
-        hipLaunchKernelGGL((k_trsv_block<false, false>), dim3(part ? w.nbs : waves(b1 - b0), P.nrhs), dim3(256), 0,
-                           st, pc->bs.as<int>(), b0, b1, pc->Ueptr.as<int>(), pc->Uecol.as<int>(),
-                           pc->Ueval.as<float>(), pc->bU.as<float>(), nullptr, perm_d, rin, y, pu, u, n, scq,
-                           part, w.nbs);
-      }
-      continue;
-    }
+    if (!pc->hbc.empty()) continue;                   // block multicolour: all items together above
     if (!pc->hcp.empty() && (int)pc->hcp.size() - 1 <= TRSV_LEVEL_LAUNCH_MAX) {
       // multicolour order: one launch per colour and direction, the last
       // colour's upper rows solved in the last lower launch; the permutation
