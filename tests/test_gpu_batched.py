@@ -65,7 +65,7 @@ def test_batched_item_matches_oracle(gctx):
     p = P[1]
     g = p["g"]
     otr = transfer.Transfer(p["m"].X, p["m"].elems, 2, g.N, g.R, g.center)
-    T = p["op"].table()
+    T = fw.filon_richardson(p["s"], 2, 2 * p["g"].N, 512)      # the oracle's table (the GPU's matches it, 1e-13)
     K = operator.dense_K(otr, T)
     uref = np.zeros(p["m"].nv)
     uref[otr.J] = osolve.solve_dense(K, operator.rhs_grid(otr, p["s"], p["f"][0]))
@@ -165,3 +165,53 @@ def test_c4_members_of_three_grid_sizes_match_the_oracle(gctx):
             err = np.linalg.norm(u[r] - uref) / np.linalg.norm(uref)
             print(f"  rhs {r}: oracle iterations {it}, rel error {err:.2e}", flush=True)
             assert err <= 1e-8
+
+
+def test_block_multicolour_items_of_several_problems_in_one_launch(gctx):
+    """Problems preconditioned by IC(1) of the Laplacian in block multicolour order, mixed with unpreconditioned
+    ones, in one shape group: their triangular solves run as one launch per colour and direction over all their
+    items (each item reaching its last colour in its own launch).  Every item matches its problem solved alone
+    (whose launches take the problem's arrays as arguments) and, for the smallest mesh, the oracle's dense
+    solution."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    specs = [  # (mesh, R, s, precond, nrhs): one grid shape (n = 64)
+        (disk_mesh(seed=31, n_boundary=30, spacing=0.14), 1.0, 0.8, "IC1_9_LAP_BMC", 2),
+        (star_mesh(32, 900), 1.6, 0.3, "NONE", 1),
+        (disk_mesh(seed=33, n_boundary=50, spacing=0.07), 1.05, 0.7, "IC1_9_LAP_BMC", 3),
+        (star_mesh(34, 800), 1.6, 0.9, "IC1_5_LAP_BMC", 1),
+    ]
+    P = []
+    for k, (m, R, s, pcn, nr) in enumerate(specs):
+        g = grid_for_box(2, 64, R=R)
+        tr = gofd.Transfer(gctx, _dev(m.X), _dev(m.elems, torch.int32), g)
+        op = gofd.FdOp(gctx, s, g, M=512)
+        pc = gofd.Precond(gctx, tr, op, pcn)
+        f = np.stack([fourier_rhs(300 + 10 * k + r, g) for r in range(nr)])
+        P.append(dict(m=m, g=g, s=s, tr=tr, op=op, pc=pc, f=f))
+    colours = [p["pc"].info["colours"] for p in P if p["pc"].info["colours"]]
+    print("colours", colours, flush=True)
+    assert len(set(colours)) > 1 or len(colours) > 2
+    for mode in (gofd.MODE_FP64, gofd.MODE_FP32_RELIABLE):
+        us, infos = gofd.solve_batched(gctx, [p["tr"] for p in P], [p["op"] for p in P], [p["pc"] for p in P],
+                                       [_dev(p["f"]) for p in P], tol=1e-11, mode=mode, inner_tol=0.1)
+        k = 0
+        for p, u in zip(P, us):
+            ua, ia = gofd.solve(gctx, p["tr"], p["op"], _dev(p["f"]), tol=1e-11, pc=p["pc"], mode=mode,
+                                inner_tol=0.1)
+            u, ua = u.cpu().numpy().reshape(len(p["f"]), -1), ua.cpu().numpy().reshape(len(p["f"]), -1)
+            for r in range(len(p["f"])):
+                assert abs(infos[k]["iterations"] - ia[r]["iterations"]) <= 2, (infos[k], ia[r])
+                assert infos[k]["rel_residual"] <= 1e-11
+                assert np.linalg.norm(u[r] - ua[r]) <= 1e-9 * np.linalg.norm(ua[r])
+                k += 1
+    # the smallest preconditioned problem against the oracle's dense solve
+    p = P[0]
+    otr = transfer.Transfer(p["m"].X, p["m"].elems, 2, p["g"].N, p["g"].R, p["g"].center)
+    T = fw.filon_richardson(p["s"], 2, 2 * p["g"].N, 512)      # the oracle's table (the GPU's matches it, 1e-13)
+    K = operator.dense_K(otr, T)
+    for r in range(len(p["f"])):
+        uref = np.zeros(otr.nv)
+        uref[otr.J] = osolve.solve_dense(K, operator.rhs_grid(otr, p["s"], p["f"][r]))
+        ug = us[0].cpu().numpy().reshape(len(p["f"]), -1)[r]
+        assert np.linalg.norm(ug - uref) <= 1e-9 * np.linalg.norm(uref)
