@@ -946,8 +946,8 @@ int run_2d(gofd_ctx_s* ctx, gofd_fdop_s* op, int nrhs, const Src& src, Y* y, int
     }
   }
   if ((passes & 4) && rs.items) {
-    // entries read ahead per thread: the first of 16, 24, 32 that covers the
-    // count of 90% of the row pairs (more run in a loop)
+    // entries read ahead per thread: 16, 24 or 32, as the transfer chose from
+    // its row pairs' counts (more run in a loop)
     const dim3 gC(nbA + (fin.sc ? 1 : 0), nrhs), bC(C::LINES_A * C::TA);
     if (rs.ent_ahead <= 16)
       GOFD_LAUNCH(ctx, (k_passC<R, Y, L, C::EA, C::LINES_A, true, 16>), gC, bC, 0, st, Z, W, tw, zs, y,

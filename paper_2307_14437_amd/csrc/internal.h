@@ -173,7 +173,7 @@ struct gofd_transfer_s {
   bool rp_ok = false;
   bool seg_rows_ok = false;   // seg_row / rp_pos present (at most three entries per node)
   int64_t n_slots = 0;  // partial sums: one per (vertex, row pair) with entries
-  int rp_ent_ahead = 0;   // entries per thread that cover 90% of the row pairs (the last row pass reads them ahead)
+  int rp_ent_ahead = 0;   // entries per thread the last row pass reads ahead (16, 24 or 32: not above the median count)
   DevBuf rp_meta;    // int4[pairs]: entry base, entries per thread, segment base, segments
   DevBuf rp_tseg;    // int32[pairs * threads]: first segment of each thread | its entry count << 16
   DevBuf rp_code;    // uint16[...]: local node (2 rows) | end-of-segment flag, thread-interleaved
@@ -275,7 +275,7 @@ struct GatherSpec {
   // instead of writing the grid field
   double* rp_P = nullptr;
   long long rp_pstride = 0;
-  int rp_ent_ahead = 0;                // entries per thread read ahead (covers most row pairs of all items)
+  int rp_ent_ahead = 0;                // entries per thread read ahead (the largest choice of the items)
   // with rp_us as well (every item has seg_row): the FP32 gather reads the
   // vector's values per slot (item it at rp_us + it * rp_pstride, row-pair-major
   // positions) instead of per vertex
