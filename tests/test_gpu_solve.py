@@ -394,3 +394,29 @@ def test_warm_start_from_x0(gctx, c1_setup, mode_name):
     with pytest.raises(gofd.GofdError) as e:
         gofd.solve_batched(gctx, [tr], [op], [None], [f], tol=1e-10, x0=_dev(uref))
     assert e.value.code == gofd.E_ARG
+
+
+def test_block_multicolour_single_block_mesh(gctx):
+    """A mesh whose 8 interior vertices form one block: one colour, so the only launch of each apply solves the
+    lower and upper rows together and stores gamma's partials (clearing the ones past its grid); two right-hand
+    sides, against dense LU."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    m = disk_mesh(seed=41, n_boundary=10, spacing=0.5)
+    g = grid_for_box(2, 16, R=1.0)
+    otr = transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
+    assert len(otr.J) <= 16
+    T = fw.filon_richardson(0.75, 2, 2 * g.N, 512)
+    tr = gofd.Transfer(gctx, _dev(m.X), _dev(m.elems, torch.int32), g)
+    op = gofd.FdOp(gctx, 0.75, g, T=T)
+    pc = gofd.Precond(gctx, tr, op, "IC1_9_LAP_BMC")
+    assert pc.info["colours"] == 1
+    K = operator.dense_K(otr, T)
+    F = np.stack([np.cos(np.arange(g.W * g.W).reshape(g.W, g.W) * (0.01 + 0.02 * r)) for r in range(2)])
+    for mode in (gofd.MODE_FP64, gofd.MODE_FP32_RELIABLE):
+        u, infos = gofd.solve(gctx, tr, op, _dev(F), tol=1e-12, pc=pc, mode=mode, inner_tol=0.1)
+        u = u.cpu().numpy()
+        for r in range(2):
+            uref = _full(otr, solve.solve_dense(K, operator.rhs_grid(otr, 0.75, F[r])))
+            assert infos[r]["status"] == 0
+            assert np.linalg.norm(u[r] - uref) <= 1e-10 * np.linalg.norm(uref)
