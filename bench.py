@@ -43,16 +43,27 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def _kernel_bytes(W, L, tr, m, b, precond):
+def _kernel_bytes(W, L, tr, m, b, precond, gather_rows=False):
     """Algorithmic HBM bytes per launch of each kernel of one CG iteration of the 2D product in the FP32
     pipeline (one field, grid values of b = 4 bytes): every array the kernel needs is read or written once.
     The first row pass reads each node's segment row (three local segment numbers and weights: 20 bytes)
     and its row pair's slot values of u (4 bytes per slot, staged in LDS); the last row pass reads the
     row-pair entries of I^T (16-bit local node, weight) and writes one partial sum per (vertex, row pair);
-    the vertex kernel adds a vertex's partials, applies the CG step and stores the new u at its slots."""
+    the vertex kernel adds a vertex's partials, applies the CG step and stores the new u at its slots.
+    gather_rows (an IC(1) item, whose u comes from the triangular solves in vertex order): the first row pass
+    reads each node's FP32 row (three vertex ids and two weights: 24 bytes) and the vertex values of u (8
+    bytes each), and the vertex kernel neither forms nor stores u."""
     nn, H = W * W, L // 2
     info = tr.info
     nnz, nv, slots = info["nnz"], tr.nv, info["rp_slots"]
+    if gather_rows:
+        return {
+            "passA": 24 * nn + 8 * nv + 2 * b * W * H,    # node rows, u; W rows of L/2 slots out
+            "passB": 4 * b * W * H + b * H * (H + 1),
+            "passC": 2 * b * W * H + (2 + b) * nnz + 8 * slots,
+            "scatter": 4 * (nv + 1) + 8 * slots + 8 * nv * (5 + 4),   # offsets, sums; mask, s, p, r, x in;
+                                                                      # s, p, x, r out
+        }
     vec = 8 * nv * (6 + 5 + (1 if precond == "DIAG" else 0))   # mask, s, p, u, r, x (+ D^-1) in; s, p, x, r, u out
     return {
         "passA": 20 * nn + 16 * ((W + 1) // 2) + 4 * slots + 2 * b * W * H,   # node rows, row-pair
@@ -717,34 +728,37 @@ def main():
         mv[name] = e0.elapsed_time(e1) / n
     gpts = {k: W * W / (v * 1e-3) / 1e9 for k, v in mv.items()}
 
-    # per-kernel rooflines (FP32 grid, the mode of the step): the step's solves once more with every
+    # per-kernel rooflines (FP32 grid, the mode of the step): each order's solve once more with every
     # stage of every iteration bracketed by HIP events on the library's stream (no graph); algorithmic
-    # bytes per launch from the layouts (each array read or written once)
-    stage_sum = np.zeros(len(gofd.STAGES))
-    stage_n = 0
+    # bytes per launch from the layouts (each array read or written once).  The roofline kernel is taken
+    # from the solve with the most iterations (its first row pass gathers from vertex values when the
+    # solve is IC(1)-preconditioned)
+    tables = {}
     precond_apply = {}
     for i, s in enumerate(svals):
         st_ms = np.zeros(len(gofd.STAGES))
         _, inf = gofd.solve(ctx, tr, ops[i], fd, tol=tol, pc=pcs[i], mode=gofd.MODE_FP32_RELIABLE,
                             inner_tol=args.drop, stage_ms=st_ms)
-        n_it = inf[0]["iterations"] + 1
-        stage_sum += st_ms * n_it
-        stage_n += n_it
-        if pc_for(args.precond, s) not in ("NONE", "DIAG"):
+        rows = pc_for(args.precond, s) not in ("NONE", "DIAG")
+        nb = _kernel_bytes(W, 2 * (W - 1), tr, m, 4, pc_for(args.precond, s), gather_rows=rows)
+        tables[str(s)] = {
+            "iterations": inf[0]["iterations"], "first_row_pass": "vertex-value gather" if rows else "slots",
+            "kernels": {k: {"us": st_ms[j] * 1e3, "bytes": nb[k], "GBs": nb[k] / (st_ms[j] * 1e-3) / 1e9,
+                            "frac": nb[k] / (st_ms[j] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                        for j, k in enumerate(gofd.STAGES) if k in nb and st_ms[j] > 0}}
+        if rows:
             # the triangular solves of one iteration (all their launches), against the FFT product's passes
             precond_apply[str(s)] = {
                 "preconditioner": pc_for(args.precond, s), "colours": pcs[i].info["colours"],
                 "us_per_iteration": st_ms[gofd.STAGES.index("precond")] * 1e3,
                 "product_us_per_iteration": sum(st_ms[gofd.STAGES.index(k)] for k in ("gather", "passA", "passB", "passC")
                                                 if k in gofd.STAGES) * 1e3}
-    stage_ms = stage_sum / stage_n
-    nb = _kernel_bytes(W, 2 * (W - 1), tr, m, 4, args.precond)
-    kernels = {k: {"us": stage_ms[j] * 1e3, "bytes": nb[k], "GBs": nb[k] / (stage_ms[j] * 1e-3) / 1e9,
-                   "frac": nb[k] / (stage_ms[j] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-               for j, k in enumerate(gofd.STAGES) if k in nb and stage_ms[j] > 0}
+    dom_s = max(tables, key=lambda k: tables[k]["iterations"])
+    kernels = tables[dom_s]["kernels"]
     dom = max(kernels, key=lambda k: kernels[k]["us"])
     achieved = kernels[dom]["GBs"]
-    traffic = _traffic(dom)
+    rows_dom = tables[dom_s]["first_row_pass"] != "slots"
+    traffic = _traffic("passA_rows" if dom == "passA" and rows_dom else dom)
 
     # the transfer build (point location, weights, vertex-major structure, column sums): event times per stage
     tb = _transfer_kernel_bytes(2, tr.nv, tr.ne, tr.info["n_nodes"], tr.info["n_inside"], tr.info["nnz"])
@@ -787,9 +801,13 @@ def main():
         "matvec_gpts": gpts,
         "matvec_us": {k: v * 1e3 for k, v in mv.items()},
         "kernels_fp32": kernels,
+        "kernels_fp32_solve": {"s": float(dom_s), **{k: v for k, v in tables[dom_s].items() if k != "kernels"}},
+        "kernels_fp32_by_s": tables,
         "setup_ms": setup,
         "transfer_kernels": transfer_kernels,
-        "roofline": {"bound": "hbm", "kernel": f"{dom} (fp32)", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": f"{dom} (fp32{', vertex-value gather' if dom == 'passA' and rows_dom else ''}"
+                                               f", s = {dom_s})",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": kernels[dom]["bytes"]},
     }

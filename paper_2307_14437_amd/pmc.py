@@ -28,6 +28,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # stage of a CG iteration -> kernel symbol fragment (single-precision grid, 2D, L = 2048)
 STAGE_SYMBOLS = {   # fragments that together name the kernel of each stage
     "passA": ("k_passA<float, 2048", "SrcPairSegRows"),
+    "passA_rows": ("k_passA<float, 2048", "SrcPairGatherRows"),     # the form of IC(1)-preconditioned items
     "passB": ("k_passB<float, 2048", "true>"),
     "passC": ("k_passC<float, float, 2048", "true"),
     "scatter": ("k_vertex_cg",),
