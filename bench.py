@@ -36,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DEFAULT_DROP = 0.03     # FP32 mode: residual drop between FP64 residual replacements
 
 
 def _sync():
@@ -550,7 +551,7 @@ def main():
     ap.add_argument("--precond", default="auto",
                     help="preconditioner of the timed step: a name of the library's (NONE, DIAG, IC1_9_MC, "
                          "IC1_9_LAP_BMC, ...) or 'auto' (per s: the Laplacian's IC(1) above s = 1/2, none below)")
-    ap.add_argument("--drop", type=float, default=0.03,
+    ap.add_argument("--drop", type=float, default=DEFAULT_DROP,
                     help="FP32 mode: residual drop between FP64 residual replacements")
     ap.add_argument("--inner-tol", type=float, default=1e-4, help="restarted-refinement comparison: inner tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -308,8 +308,11 @@ def test_lshape_full_size_solves_oracle_system(gctx, s):
 
 def test_bench_configuration_full_size(gctx):
     """The benchmark step exactly: both orders of C2 in one batched FP32-grid solve with FP64 residual
-    replacement (drop 0.1), no preconditioner, tol 1e-8; each solution checked by the oracle's residual."""
+    replacement at the benchmark's drop, each order preconditioned as the benchmark chooses (the Laplacian's
+    block multicolour IC(1) above s = 1/2, none below), tol 1e-8; each solution checked by the oracle's
+    residual."""
     import torch
+    import bench
     import paper_2307_14437_amd as gofd
     cfg = config_inputs("c2")
     m, g, f = cfg["mesh"], cfg["grid"], cfg["f"][0]
@@ -318,19 +321,24 @@ def test_bench_configuration_full_size(gctx):
     assert tr.info["rp_slots"] >= tr.nv and tr.info["rp_entries"] >= tr.info["nnz"]
     assert tr.info["rp_seg_rows"] == 1          # the FP32 gather goes through the row-pair slots
     ops = [gofd.FdOp(gctx, s, g) for s in cfg["s"]]
-    pcs = [gofd.Precond(gctx, tr, op, "NONE") for op in ops]
+    names = [bench.pc_for("auto", s) for s in cfg["s"]]
+    assert names == ["NONE", "IC1_9_LAP_BMC"]
+    pcs = [gofd.Precond(gctx, tr, op, n) for op, n in zip(ops, names)]
     fd = _dev(f)
     us, infos = gofd.solve_batched(gctx, [tr] * 2, ops, pcs, [fd, fd], tol=cfg["tol"],
-                                   mode=gofd.MODE_FP32_RELIABLE, inner_tol=0.1)
+                                   mode=gofd.MODE_FP32_RELIABLE, inner_tol=bench.DEFAULT_DROP)
     otr = transfer.Transfer(m.X, m.elems, 2, g.N, g.R, g.center)
     for k, s in enumerate(cfg["s"]):
-        print(s, infos[k], flush=True)
+        print(s, names[k], infos[k], flush=True)
+        assert infos[k]["status"] == 0
         T = ops[k].table()
         b = operator.rhs_grid(otr, s, f)
         u = us[k].cpu().numpy()
         r = operator.apply_K(otr, T, u[otr.J], "fft") - b
         assert np.linalg.norm(r) / np.linalg.norm(b) < 1.5e-8
         assert np.all(u[otr.bnd] == 0.0)
+    # plain CG takes about 290 iterations at s = 0.75 on this mesh; the Laplacian's IC(1) cuts that to about 70
+    assert infos[1]["iterations"] < 140
 
 
 def test_stage_timing_reports_every_stage(gctx, c1_setup):
