@@ -691,6 +691,32 @@ __device__ __forceinline__ double block_product(const double (&m4)[4], double b,
   return quad_add<0x4E>(quad_add<0xB1>(p));
 }
 
+// Sum over slabs a < min(NS, ns) of a block's entries to other blocks, in slab
+// order, added to s0: lane i * 4 + q adds entry q + 4a of row i, w * dep[col]
+// (col -1 marks padding).  All NS column and value loads are issued before any
+// value of dep is read; slabs past ns re-read slab ns - 1 (cached) and padding
+// re-reads `pad` (the row's value of r, never a location the launch writes),
+// their products masked.
+template <int NS, class IP, class FP>
+__device__ __forceinline__ double slab_sum(IP ecol, FP eval, int e0, int ns, int lane, const double* dep,
+                                           const double* pad, double s0 = 0.0) {
+  int cc[NS];
+  float w[NS];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) {
+    const int idx = e0 + min(a, ns - 1) * 64 + lane;
+    cc[a] = ecol[idx];
+    w[a] = eval[idx];
+  }
+  double x[NS];
+#pragma unroll
+  for (int a = 0; a < NS; ++a) x[a] = *(a < ns && cc[a] >= 0 ? dep + cc[a] : pad);
+  double s = s0;
+#pragma unroll
+  for (int a = 0; a < NS; ++a) s += (a < ns && cc[a] >= 0) ? (double)w[a] * x[a] : 0.0;
+  return s;
+}
+
 // One item (problem, right-hand side) of the block multicolour solves: its
 // factor's arrays (see gofd_precond_s), its colour table (colour c is blocks
 // cbeg[c]..cbeg[c+1]-1, ncol colours) and its vectors at off.
@@ -739,7 +765,16 @@ __device__ __forceinline__ void trsv_block_item(const int* __restrict__ bs_, con
                                                 const int* __restrict__ perm_, long long off, int item, bool tail,
                                                 int b0, int b1, const double* __restrict__ r, double* __restrict__ y,
                                                 double* __restrict__ pu, double* __restrict__ u,
-                                                double* __restrict__ part, int nbu, double* sh) {
+                                                double* __restrict__ part, int nbu, const Scal* __restrict__ sc,
+                                                double* sh) {
+  // A finished item stores nothing; its flag, the upper block inverse of the
+  // last colour and the partial this workgroup adds to are all read up front
+  // and waited for only where used, so that each launch waits for three
+  // rounds of loads (block ranges, then indices and inverses, then values).
+  const bool done = sc && sc[item].done;              // block-uniform
+  const bool accum = part && !tail && !LOWER;         // upper colours below the last add to their partial
+  double pprev = 0.0;
+  if (accum && threadIdx.x == 0) pprev = part[(long long)item * nbu + blockIdx.x];
   // the pointers as global ones (loads through them are global, not flat)
   const auto bs = gmem(bs_);
   const auto eoff = gmem(eoff_);
@@ -765,27 +800,23 @@ __device__ __forceinline__ void trsv_block_item(const int* __restrict__ bs_, con
     double m4[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) m4[a] = (double)binv[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
-    double s = 0.0;
-    for (int a0 = 0; a0 < ns; a0 += 4) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int idx = e0 + min(a0 + a, ns - 1) * 64 + lane;
-        const int cc = ecol[idx];
-        const double w = eval[idx];
-        const bool use = a0 + a < ns && cc >= 0;
-        // padding re-reads the row's value of r (never a location this launch writes); the product is masked
-        const double x = *(use ? dep + cc : rk + v);
-        s += use ? w * x : 0.0;
-      }
-    }
-    s = quad_add<0x4E>(quad_add<0xB1>(s));
-    double xi = block_product(m4, ok ? rhs - s : 0.0, q);
+    double m4u[4] = {0.0, 0.0, 0.0, 0.0};
     if (tail) {
       const auto binvU = gmem(binvU_);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) m4[a] = (double)binvU[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
-      xi = block_product(m4, ok ? xi : 0.0, q);
+      for (int a = 0; a < 4; ++a) m4u[a] = (double)binvU[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
     }
+    // the block's slabs all in flight at once (up to 16; a block with more goes on four at a time), so that
+    // a launch waits for one round of column loads and one of values whatever the block's slab count
+    double s = 0.0;
+    if (ns > 8) s = slab_sum<16>(ecol, eval, e0, ns, lane, dep, rk + v);
+    else if (ns > 4) s = slab_sum<8>(ecol, eval, e0, ns, lane, dep, rk + v);
+    else if (ns > 0) s = slab_sum<4>(ecol, eval, e0, ns, lane, dep, rk + v);
+    for (int a0 = 16; a0 < ns; a0 += 4) s = slab_sum<4>(ecol, eval, e0 + a0 * 64, ns - a0, lane, dep, rk + v, s);
+    s = quad_add<0x4E>(quad_add<0xB1>(s));
+    double xi = block_product(m4, ok ? rhs - s : 0.0, q);
+    if (tail) xi = block_product(m4u, ok ? xi : 0.0, q);
+    if (done) break;
     if (ok && q == 0) {
       if (LOWER && !tail) {
         yk[t] = xi;
@@ -796,12 +827,12 @@ __device__ __forceinline__ void trsv_block_item(const int* __restrict__ bs_, con
       }
     }
   }
-  if (!part || (LOWER && !tail)) return;              // block-uniform
+  if (done || !part || (LOWER && !tail)) return;      // block-uniform
   double s1[1] = {acc};
   gofd_cg::block_sum_n<256, 1>(s1, sh);
   if (threadIdx.x == 0) {
     double* p = part + (long long)item * nbu;
-    p[blockIdx.x] = tail ? s1[0] : p[blockIdx.x] + s1[0];
+    p[blockIdx.x] = accum ? pprev + s1[0] : s1[0];
     if (tail && blockIdx.x == 0)
       for (int w = gridDim.x; w < nbu; ++w) p[w] = 0.0;
   }
@@ -821,9 +852,8 @@ __global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, 
                                                     double* __restrict__ part, int nbu) {
   __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
   const int item = i0 + (int)blockIdx.y;
-  if (sc && sc[item].done) return;                    // block-uniform
   trsv_block_item<LOWER>(bs, eoff, ecol, eval, binv, binvU, perm, off0 + blockIdx.y * stride, item, TAIL, b0, b1,
-                         r, y, pu, u, part, nbu, sh);
+                         r, y, pu, u, part, nbu, sc, sh);
 }
 
 // Every item of the table (blockIdx.y) in one launch per colour c; an item
@@ -836,12 +866,11 @@ __global__ __launch_bounds__(256) void k_trsv_block_items(const BmcItem* __restr
                                                           int nbu) {
   __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
   const BmcItem I = items[blockIdx.y];                // a kernel argument: global, scalar loads
-  if (sc && sc[I.item].done) return;                  // block-uniform
   if (LOWER ? c >= I.ncol : c > I.ncol - 2) return;   // the item has no such colour in this direction
   const int b0 = gmem(I.cbeg)[c], b1 = gmem(I.cbeg)[c + 1];
   trsv_block_item<LOWER>(I.bs, LOWER ? I.eoffL : I.eoffU, LOWER ? I.ecolL : I.ecolU, LOWER ? I.evalL : I.evalU,
                          LOWER ? I.binvL : I.binvU, I.binvU, I.perm, I.off, I.item, LOWER && c == I.ncol - 1, b0, b1,
-                         r, y, pu, u, part, nbu, sh);
+                         r, y, pu, u, part, nbu, sc, sh);
 }
 
 // out[i] = in[perm[i]] (to = true) or out[perm[i]] = in[i], per right-hand side blockIdx.y

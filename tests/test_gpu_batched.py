@@ -215,3 +215,40 @@ def test_block_multicolour_items_of_several_problems_in_one_launch(gctx):
         uref[otr.J] = osolve.solve_dense(K, operator.rhs_grid(otr, p["s"], p["f"][r]))
         ug = us[0].cpu().numpy().reshape(len(p["f"]), -1)[r]
         assert np.linalg.norm(ug - uref) <= 1e-9 * np.linalg.norm(uref)
+
+
+def test_block_multicolour_problem_finishing_first_in_a_batch(gctx):
+    """One problem preconditioned in block multicolour order (its solves take its arrays as launch arguments),
+    two right-hand sides, batched with a slower unpreconditioned problem: the preconditioned items finish first
+    and the later launches of their solves store nothing for them.  Every item matches its problem solved
+    alone, and the finished items keep the iterates at which they stopped."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    specs = [  # (mesh, R, s, precond, nrhs): one grid shape (n = 64)
+        (disk_mesh(seed=35, n_boundary=40, spacing=0.09), 1.05, 0.9, "IC1_9_LAP_BMC", 2),
+        (star_mesh(36, 900), 1.6, 0.3, "NONE", 1),
+    ]
+    P = []
+    for k, (m, R, s, pcn, nr) in enumerate(specs):
+        g = grid_for_box(2, 64, R=R)
+        tr = gofd.Transfer(gctx, _dev(m.X), _dev(m.elems, torch.int32), g)
+        op = gofd.FdOp(gctx, s, g, M=512)
+        pc = gofd.Precond(gctx, tr, op, pcn)
+        f = np.stack([fourier_rhs(500 + 10 * k + r, g) for r in range(nr)])
+        P.append(dict(tr=tr, op=op, pc=pc, f=f))
+    for mode in (gofd.MODE_FP64, gofd.MODE_FP32_RELIABLE):
+        us, infos = gofd.solve_batched(gctx, [p["tr"] for p in P], [p["op"] for p in P], [p["pc"] for p in P],
+                                       [_dev(p["f"]) for p in P], tol=1e-11, mode=mode, inner_tol=0.1)
+        print(mode, [i["iterations"] for i in infos], flush=True)
+        assert max(i["iterations"] for i in infos[:2]) < infos[2]["iterations"]   # the BMC items stop first
+        k = 0
+        for p, u in zip(P, us):
+            ua, ia = gofd.solve(gctx, p["tr"], p["op"], _dev(p["f"]), tol=1e-11, pc=p["pc"], mode=mode,
+                                inner_tol=0.1)
+            u, ua = u.cpu().numpy().reshape(len(p["f"]), -1), ua.cpu().numpy().reshape(len(p["f"]), -1)
+            for r in range(len(p["f"])):
+                assert infos[k]["status"] == 0
+                assert abs(infos[k]["iterations"] - ia[r]["iterations"]) <= 2, (infos[k], ia[r])
+                assert infos[k]["rel_residual"] <= 1e-11
+                assert np.linalg.norm(u[r] - ua[r]) <= 1e-9 * np.linalg.norm(ua[r])
+                k += 1
