@@ -757,8 +757,11 @@ struct BmcItem {
 // after colour 0 the item's nbu partials hold (r, u) in a fixed order.
 //
 // trsv_block_item: the work of one workgroup on one item, blocks b0..b1-1 of
-// the item's colour, the last colour's upper rows too when tail.
-template <bool LOWER>
+// the item's colour, the last colour's upper rows too when tail.  WIDE: all
+// slabs of a block in flight at once (launches of one problem, bound by the
+// latency of their few rounds of loads); otherwise four at a time, in fewer
+// registers (launches over many items, bound by how many waves fit).
+template <bool LOWER, bool WIDE>
 __device__ __forceinline__ void trsv_block_item(const int* __restrict__ bs_, const int* __restrict__ eoff_,
                                                 const int* __restrict__ ecol_, const float* __restrict__ eval_,
                                                 const float* __restrict__ binv_, const float* __restrict__ binvU_,
@@ -767,10 +770,11 @@ __device__ __forceinline__ void trsv_block_item(const int* __restrict__ bs_, con
                                                 double* __restrict__ pu, double* __restrict__ u,
                                                 double* __restrict__ part, int nbu, const Scal* __restrict__ sc,
                                                 double* sh) {
-  // A finished item stores nothing; its flag, the upper block inverse of the
-  // last colour and the partial this workgroup adds to are all read up front
-  // and waited for only where used, so that each launch waits for three
-  // rounds of loads (block ranges, then indices and inverses, then values).
+  // A finished item stores nothing (with sc given; callers that test the flag
+  // themselves pass none); its flag, the upper block inverse of the last
+  // colour and the partial this workgroup adds to are all read up front and
+  // waited for only where used, so that each launch waits for three rounds
+  // of loads (block ranges, then indices and inverses, then values).
   const bool done = sc && sc[item].done;              // block-uniform
   const bool accum = part && !tail && !LOWER;         // upper colours below the last add to their partial
   double pprev = 0.0;
@@ -806,13 +810,17 @@ __device__ __forceinline__ void trsv_block_item(const int* __restrict__ bs_, con
 #pragma unroll
       for (int a = 0; a < 4; ++a) m4u[a] = (double)binvU[(long long)kb * (BMC_BLOCK * BMC_BLOCK) + a * 64 + lane];
     }
-    // the block's slabs all in flight at once (up to 16; a block with more goes on four at a time), so that
-    // a launch waits for one round of column loads and one of values whatever the block's slab count
+    // WIDE: the block's slabs all in flight at once (up to 16; a block with more goes on four at a time), so
+    // that a launch waits for one round of column loads and one of values whatever the block's slab count
     double s = 0.0;
-    if (ns > 8) s = slab_sum<16>(ecol, eval, e0, ns, lane, dep, rk + v);
-    else if (ns > 4) s = slab_sum<8>(ecol, eval, e0, ns, lane, dep, rk + v);
-    else if (ns > 0) s = slab_sum<4>(ecol, eval, e0, ns, lane, dep, rk + v);
-    for (int a0 = 16; a0 < ns; a0 += 4) s = slab_sum<4>(ecol, eval, e0 + a0 * 64, ns - a0, lane, dep, rk + v, s);
+    int a0 = 0;
+    if constexpr (WIDE) {
+      if (ns > 8) s = slab_sum<16>(ecol, eval, e0, ns, lane, dep, rk + v);
+      else if (ns > 4) s = slab_sum<8>(ecol, eval, e0, ns, lane, dep, rk + v);
+      else if (ns > 0) s = slab_sum<4>(ecol, eval, e0, ns, lane, dep, rk + v);
+      a0 = 16;
+    }
+    for (; a0 < ns; a0 += 4) s = slab_sum<4>(ecol, eval, e0 + a0 * 64, ns - a0, lane, dep, rk + v, s);
     s = quad_add<0x4E>(quad_add<0xB1>(s));
     double xi = block_product(m4, ok ? rhs - s : 0.0, q);
     if (tail) xi = block_product(m4u, ok ? xi : 0.0, q);
@@ -852,8 +860,8 @@ __global__ __launch_bounds__(256) void k_trsv_block(const int* __restrict__ bs, 
                                                     double* __restrict__ part, int nbu) {
   __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
   const int item = i0 + (int)blockIdx.y;
-  trsv_block_item<LOWER>(bs, eoff, ecol, eval, binv, binvU, perm, off0 + blockIdx.y * stride, item, TAIL, b0, b1,
-                         r, y, pu, u, part, nbu, sc, sh);
+  trsv_block_item<LOWER, true>(bs, eoff, ecol, eval, binv, binvU, perm, off0 + blockIdx.y * stride, item, TAIL, b0,
+                               b1, r, y, pu, u, part, nbu, sc, sh);
 }
 
 // Every item of the table (blockIdx.y) in one launch per colour c; an item
@@ -866,11 +874,14 @@ __global__ __launch_bounds__(256) void k_trsv_block_items(const BmcItem* __restr
                                                           int nbu) {
   __shared__ double sh[gofd_cg::block_sum_lds<256, 1>()];
   const BmcItem I = items[blockIdx.y];                // a kernel argument: global, scalar loads
+  // most workgroups of a launch over many items belong to items that have
+  // finished: those return before any other load
+  if (sc && sc[I.item].done) return;                  // block-uniform
   if (LOWER ? c >= I.ncol : c > I.ncol - 2) return;   // the item has no such colour in this direction
   const int b0 = gmem(I.cbeg)[c], b1 = gmem(I.cbeg)[c + 1];
-  trsv_block_item<LOWER>(I.bs, LOWER ? I.eoffL : I.eoffU, LOWER ? I.ecolL : I.ecolU, LOWER ? I.evalL : I.evalU,
-                         LOWER ? I.binvL : I.binvU, I.binvU, I.perm, I.off, I.item, LOWER && c == I.ncol - 1, b0, b1,
-                         r, y, pu, u, part, nbu, sc, sh);
+  trsv_block_item<LOWER, false>(I.bs, LOWER ? I.eoffL : I.eoffU, LOWER ? I.ecolL : I.ecolU,
+                                LOWER ? I.evalL : I.evalU, LOWER ? I.binvL : I.binvU, I.binvU, I.perm, I.off, I.item,
+                                LOWER && c == I.ncol - 1, b0, b1, r, y, pu, u, part, nbu, nullptr, sh);
 }
 
 // out[i] = in[perm[i]] (to = true) or out[perm[i]] = in[i], per right-hand side blockIdx.y
