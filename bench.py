@@ -749,9 +749,14 @@ def main():
                         for j, k in enumerate(gofd.STAGES) if k in nb and st_ms[j] > 0}}
         if rows:
             # the triangular solves of one iteration (all their launches), against the FFT product's passes
+            ab, ap_us = pcs[i].info["apply_bytes"], st_ms[gofd.STAGES.index("precond")] * 1e3
             precond_apply[str(s)] = {
                 "preconditioner": pc_for(args.precond, s), "colours": pcs[i].info["colours"],
-                "us_per_iteration": st_ms[gofd.STAGES.index("precond")] * 1e3,
+                "us_per_iteration": ap_us,
+                # algorithmic bytes of one apply (all its launches) against HBM: the solves are bound by the
+                # latency of their dependent loads, one launch per colour and direction
+                "bytes": ab, "GBs": ab / (ap_us * 1e-6) / 1e9 if ap_us > 0 else None,
+                "frac": ab / (ap_us * 1e-6) / 1e9 / HBM_PEAK_GBS if ap_us > 0 else None,
                 "product_us_per_iteration": sum(st_ms[gofd.STAGES.index(k)] for k in ("gather", "passA", "passB", "passC")
                                                 if k in gofd.STAGES) * 1e3}
     dom_s = max(tables, key=lambda k: tables[k]["iterations"])

@@ -304,6 +304,13 @@ typedef struct {
   int levels;             /* dependency levels of the forward triangular solve             */
   double setup_ms;        /* host + device setup time                                      */
   int colours;            /* GOFD_PC_MULTICOLOR: colours of the ordering (0 otherwise)     */
+  int64_t apply_bytes;    /* GOFD_PC_BLOCK_MULTICOLOR: algorithmic bytes of one application
+                             (both triangular solves, one right-hand side): each entry to
+                             another block (FP32 value, int32 column) and each FP32 16 x 16
+                             block inverse read once per solve, block starts and slab
+                             offsets, the permutation twice, and the vectors: r read, y
+                             written and read twice, the upper solve's output written and
+                             read once, u written (8 bytes per vertex each); 0 otherwise */
 } gofd_precond_info;
 
 /* Build a preconditioner for eq. GoFD-2 on the interior block.  For the IC(1)

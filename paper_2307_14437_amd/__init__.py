@@ -112,7 +112,7 @@ class FdwOpts(ctypes.Structure):
 
 class PrecondInfo(ctypes.Structure):
     _fields_ = [("shift", ctypes.c_double), ("nnz_L", ctypes.c_int64), ("levels", ctypes.c_int),
-                ("setup_ms", ctypes.c_double), ("colours", ctypes.c_int)]
+                ("setup_ms", ctypes.c_double), ("colours", ctypes.c_int), ("apply_bytes", ctypes.c_int64)]
 
 
 class SolveOpts(ctypes.Structure):

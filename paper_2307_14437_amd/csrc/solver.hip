@@ -1017,6 +1017,12 @@ static int upload_block_factor(gofd_ctx_s* ctx, gofd_precond_s* pc, const std::v
   }
   if (ecL.size() >= (size_t)1 << 31 || ecU.size() >= (size_t)1 << 31)
     return gofd_fail(ctx, GOFD_E_OOM, "block factor too large");
+  // algorithmic bytes of one application (the layout's padding left out)
+  int64_t ext = 0;
+  for (int32_t c : ecL) ext += c >= 0;
+  for (int32_t c : ecU) ext += c >= 0;
+  pc->info.apply_bytes = 8 * ext + 2 * (int64_t)nb * BB * (int64_t)sizeof(float) + 3 * 4 * (int64_t)(nb + 1) +
+                         2 * 4 * n + 7 * 8 * n;
   hipStream_t st = ctx->stream;
   auto up = [&](DevBuf& d, const void* h, size_t bytes) -> int {
     GOFD_TRY(dev_reserve(ctx, d, std::max<size_t>(bytes, 8)));

@@ -183,6 +183,13 @@ def test_block_multicolour_ic1_factor_matches_oracle(gctx, c1_setup):
         Lo.sort_indices()
         assert np.array_equal(Lgi.indptr, Lo.indptr) and np.array_equal(Lgi.indices, Lo.indices)
         assert np.max(np.abs(Lgi.data - Lo.data)) < 1e-12 * np.max(np.abs(Lo.data))
+        # algorithmic bytes of one apply from the oracle's blocks (the Dirichlet rows are one-row blocks of
+        # their own): entries to other blocks in both solves, FP32 inverses, block ranges, permutation, vectors
+        Lc = Lo.tocoo()
+        ext = int(np.count_nonzero(pb[Lc.row] != pb[Lc.col]))
+        nb = int(pb.max()) + 1 + int(otr.bnd.sum())
+        nv = otr.nv
+        assert pc.info["apply_bytes"] == 16 * ext + 2 * nb * 1024 + 12 * (nb + 1) + 8 * nv + 56 * nv
         print(name, pc.info, flush=True)
 
 
