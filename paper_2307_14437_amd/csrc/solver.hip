@@ -743,9 +743,9 @@ struct BmcItem {
 // at a time (four per workgroup, grid-stride): the lanes of a row add the
 // row's entries to other blocks (the block's slabs of 64 entries,
 // eoff[b]..eoff[b+1]-1, lane i * 4 + q of slab a holding entry q + 4a of row i
-// or -1; four slabs in flight), giving b_t, and the block's rows then follow
-// from the inverse of its own triangle (formed on the host; values in single
-// precision, arithmetic in double):
+// or -1; all of them or four at a time in flight, see WIDE below), giving b_t,
+// and the block's rows then follow from the inverse of its own triangle
+// (formed on the host; values in single precision, arithmetic in double):
 //   LOWER:  y = L_bb^{-1} (r[perm] - L_b,other y_other).  On the item's last
 //           colour the wave goes on to the block's rows of U = L^T, which need
 //           no other block: u = U_bb^{-1} y.
