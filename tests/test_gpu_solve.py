@@ -266,6 +266,29 @@ def test_c1_vertex_rhs_and_multi_rhs(gctx, c1_setup):
         assert np.max(np.abs(U[r] - u1.cpu().numpy())) <= 1e-12 * np.max(np.abs(U[r]))
 
 
+@pytest.mark.parametrize("pc_name", ["NONE", "DIAG", "IC1_9_LAP_BMC"])
+def test_zero_right_hand_side(gctx, c1_setup, pc_name):
+    """f = 0 next to a nonzero right-hand side in one call: the zero item stops before any iteration with u
+    exactly 0 (its reference norm is zero, so it never enters the iterations or the preconditioner's solves),
+    and the other item is the one solved alone, in every precision mode."""
+    import paper_2307_14437_amd as gofd
+    m, g, otr, T, tr, op, K = c1_setup
+    pc = gofd.Precond(gctx, tr, op, pc_name)
+    f1 = fourier_rhs(11, g)
+    F = np.stack([np.zeros_like(f1), f1])
+    for mode in (gofd.MODE_FP64, gofd.MODE_FP32_RELIABLE, gofd.MODE_FP32_REFINE):
+        u, infos = gofd.solve(gctx, tr, op, _dev(F), tol=1e-11, pc=pc, mode=mode, inner_tol=0.1)
+        ua, ia = gofd.solve(gctx, tr, op, _dev(f1), tol=1e-11, pc=pc, mode=mode, inner_tol=0.1)
+        u, ua = u.cpu().numpy(), ua.cpu().numpy()
+        print(pc_name, mode, infos, flush=True)
+        assert infos[0]["status"] == 0 and infos[0]["iterations"] == 0
+        assert np.all(u[0] == 0.0)
+        assert infos[1]["status"] == 0 and abs(infos[1]["iterations"] - ia[0]["iterations"]) <= 2
+        assert np.linalg.norm(u[1] - ua.reshape(-1)) <= 1e-9 * np.linalg.norm(ua)
+        b = operator.rhs_grid(otr, 0.5, f1)
+        assert np.linalg.norm(K @ u[1][otr.J] - b) <= 1.5e-11 * np.linalg.norm(b)
+
+
 def test_c1_closed_form_and_history(gctx, c1):
     import torch
     import paper_2307_14437_amd as gofd
