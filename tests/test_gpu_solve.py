@@ -289,6 +289,28 @@ def test_zero_right_hand_side(gctx, c1_setup, pc_name):
         assert np.linalg.norm(K @ u[1][otr.J] - b) <= 1.5e-11 * np.linalg.norm(b)
 
 
+def test_mesh_without_interior_vertices(gctx):
+    """A single triangle: every vertex lies on the boundary, so eq. GoFD-2 has no unknowns.  Each solve stops
+    before any iteration with u = 0 (the Dirichlet values), for every preconditioner kind and precision mode."""
+    import torch
+    import paper_2307_14437_amd as gofd
+    X = np.array([[-0.6, -0.5], [0.7, -0.4], [0.0, 0.65]])
+    E = np.array([[0, 1, 2]])
+    g = grid_for_box(2, 16, R=1.0)
+    otr = transfer.Transfer(X, E, 2, g.N, g.R, g.center)
+    assert len(otr.J) == 0 and otr.bnd.all()
+    tr = gofd.Transfer(gctx, _dev(X), _dev(E, torch.int32), g)
+    op = gofd.FdOp(gctx, 0.5, g, M=128)
+    f = np.ones((g.W, g.W))
+    for pc_name in ("NONE", "DIAG", "IC1_9", "IC1_9_MC", "IC1_9_LAP_BMC"):
+        pc = gofd.Precond(gctx, tr, op, pc_name)
+        for mode in (gofd.MODE_FP64, gofd.MODE_FP32_RELIABLE):
+            u, infos = gofd.solve(gctx, tr, op, _dev(f), tol=1e-10, pc=pc, mode=mode, inner_tol=0.1)
+            print(pc_name, mode, infos, flush=True)
+            assert infos[0]["status"] == 0 and infos[0]["iterations"] == 0
+            assert np.all(u.cpu().numpy() == 0.0)
+
+
 def test_c1_closed_form_and_history(gctx, c1):
     import torch
     import paper_2307_14437_amd as gofd
