@@ -417,8 +417,11 @@ int gofd_solve(gofd_ctx ctx, gofd_transfer tr, gofd_fdop op, gofd_precond pc, in
  * whole group (items index per-item descriptors of their mesh, vectors and
  * kernel spectrum), launched directly or from a hipGraph (opts->use_graph);
  * converged items are masked and, once few remain, the launches narrowed to
- * them.  IC(1)
- * triangular solves run per problem.  Groups are solved one after another.
+ * them.  IC(1) triangular solves: the block multicolour factors of a group's
+ * problems in one launch per colour and direction, other orders per problem.
+ * Groups run concurrently (a host thread and streams each, after the
+ * context's stream on entry and before it on exit); one after another when
+ * stage timing or a residual history is requested.
  * info: host array of sum(nrhs) entries in problem order (nullable).
  * Errors: as gofd_solve. */
 int gofd_solve_batched(gofd_ctx ctx, int nprob, const gofd_transfer* tr, const gofd_fdop* op,
