@@ -539,11 +539,68 @@ def gofd1d_cpu_baseline(m, N, s, f, tol, repeats=3):
                       f"iterations), median of {repeats}: {[round(t, 3) for t in times]} s"}
 
 
+def run_c3(args, pcs_names=("DIAG", "IC1_27_BMC", "IC1_27_LAP_BMC")):
+    """The 3D ball workload: the unit ball, a seeded Delaunay mesh of ~190k vertices (jittered lattice and a
+    Fibonacci-sphere surface), 256^3 overlay grid (W = 257, FFT length 512), s = 1/2, f = 1, tol 1e-8.  One step
+    = one solve; timed for each preconditioner (D_h; IC(1) of A_h^(27) and of the Laplacian on the 27-point
+    pattern, both in block multicolour order) in FP64 and with FP32 grid products inside FP64 residual
+    replacement.  Each solution is compared with the closed form (1 - |x|^2)^{1/2} / 2 (P1 mass-matrix L2 norm
+    over the mesh).  The headline value is the fastest line."""
+    import numpy as np
+    import torch
+    import paper_2307_14437_amd as gofd
+    from oracle import exact
+    from workloads import config_inputs
+    cfg = config_inputs("c3")
+    m, g, s, f = cfg["mesh"], cfg["grid"], cfg["s"][0], cfg["f"][0]
+    ctx = gofd.Context()
+    tr = gofd.Transfer(ctx, torch.tensor(m.X, device="cuda"), torch.tensor(m.elems, device="cuda",
+                                                                          dtype=torch.int32), g)
+    op = gofd.FdOp(ctx, s, g)
+    fd = torch.tensor(f, device="cuda")
+    ue = exact.u_ball_unit_rhs(m.X, s, 3)
+    nue = exact.l2_error(m.X, m.elems, ue)
+    lines = {}
+    for name in pcs_names:
+        _sync(); t = time.perf_counter()
+        pc = gofd.Precond(ctx, tr, op, name)
+        setup_s = time.perf_counter() - t
+        for mode_name in ("MODE_FP32_RELIABLE", "MODE_FP64"):
+            mode = getattr(gofd, mode_name)
+            kw = dict(tol=cfg["tol"], pc=pc, mode=mode, inner_tol=args.drop)
+            for _ in range(args.warmup):
+                gofd.solve(ctx, tr, op, fd, **kw)
+            _sync(); t = time.perf_counter()
+            for _ in range(args.steps):
+                u, info = gofd.solve(ctx, tr, op, fd, **kw)
+            _sync()
+            ms = (time.perf_counter() - t) * 1e3 / args.steps
+            err = exact.l2_error(m.X, m.elems, u.cpu().numpy().reshape(-1) - ue) / nue
+            lines[f"{name} {mode_name[5:].lower()}"] = {
+                "ms_per_step": ms, "solves_per_s": 1e3 / ms, "iterations": info[0]["iterations"],
+                "rel_residual": info[0]["rel_residual"], "rel_l2_error_vs_closed_form": err,
+                "setup_s": setup_s, "colours": pc.info["colours"], "apply_bytes": pc.info["apply_bytes"]}
+    best = min(lines, key=lambda k: lines[k]["ms_per_step"])
+    line = {
+        "metric": "3D GoFD solves/s (PCG of eq. GoFD-2 to 1e-8, unit ball, closed-form check)",
+        "value": lines[best]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": lines[best]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32-grid/f64-refine" if "fp32" in best else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D unit ball, {m.nv}-vertex Delaunay mesh, {g.W - 1}^3 overlay grid, s = {s}, f = 1, "
+                               f"tol {cfg['tol']}", "fastest": best},
+        "lines": lines,
+        "roofline": None, "cpu_baseline": None,
+        "note": "per-kernel figures of the 3D passes come from rocprofv3 runs of this workload"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "amgofd", "gofd1d"],
-                    help="c2: the L-shape workload (default); c4: the 64-mesh batched workload; amgofd: Algorithm "
-                         "amGoFD (MMPDE adaptation) on the disk; gofd1d: the 1D example, 256 right-hand sides")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "amgofd", "gofd1d"],
+                    help="c2: the L-shape workload (default); c3: the 3D ball; c4: the 64-mesh batched workload; "
+                         "amgofd: Algorithm amGoFD (MMPDE adaptation) on the disk; gofd1d: the 1D example, 256 "
+                         "right-hand sides")
     ap.add_argument("--c4-tol", type=float, default=1e-9, help="c4: relative residual of the timed solves")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -576,6 +633,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the workload runs on one "
               "MI355X; see the design notes on sharding)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c3":
+        run_c3(args)
+        return
     if args.workload == "c4":
         run_c4(args)
         return
