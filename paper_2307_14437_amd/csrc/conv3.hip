@@ -164,8 +164,12 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
   constexpr int NT = LB * TPL;
   __shared__ cplx<R> sbuf[LB * PL];
   __shared__ double shd[gofd_cg::block_sum_lds<NT, 3>()];
+  // consecutive blocks take consecutive k1 of one slot group: a block reads
+  // 4 slots (32 or 64 bytes) per z row, and the blocks that share those rows'
+  // cache lines (the next k1) run next to it on the same XCD
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int sb = b % nsb, k1 = b / nsb;
+  const int sb = b / L, k1 = b % L;
+  (void)nsb;
   const int c = threadIdx.x % LB, t = threadIdx.x / LB;
   cplx<R>* buf = sbuf + c * PL;
   const int slot = sb * LB + c;
@@ -177,9 +181,10 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
   const int kk1 = (k1 <= H) ? k1 : L - k1;
   if (that_tab) That = static_cast<const R*>(that_tab[rhs]);     // per-item spectrum (batched solves)
   // That is half^3 with axis 0 fastest; by symmetry of the kernel the axes
-  // may take k0, k1, k2 in any order: index (k2 half + k1) half + k0
+  // may take k0, k1, k2 in any order: index (k0 half + k1) half + k2, so
+  // that a thread's z frequencies are consecutive entries
   const int sc = act ? slot : H;
-  const R* Tc = That + (long long)kk1 * half + sc;
+  const R* Tc = That + ((long long)sc * half + kk1) * half;
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int i = t + m * TPL;
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(LB*(L / E), (LB * (L / E) >= 256) ? 2 : 1) void k_p
       v[m] = cplx<R>{0, 0};
     }
     const int kk2 = (i <= H) ? i : L - i;
-    pm[m] = Tc[(long long)kk2 * half * half];
+    pm[m] = Tc[kk2];
     if (!act) pm[m] = (R)0;
   }
   gofd_fft::Twiddles<R, L, E> tws;
