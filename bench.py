@@ -789,7 +789,7 @@ def main():
         mv[name] = e0.elapsed_time(e1) / n
     gpts = {k: W * W / (v * 1e-3) / 1e9 for k, v in mv.items()}
 
-    # per-kernel rooflines (FP32 grid, the mode of the step): each order's solve once more with every
+    # per-kernel rooflines (FP32 grid, the mode of the step): each order's solve three times more with every
     # stage of every iteration bracketed by HIP events on the library's stream (no graph); algorithmic
     # bytes per launch from the layouts (each array read or written once).  The roofline kernel is taken
     # from the solve with the most iterations (its first row pass gathers from vertex values when the
@@ -797,9 +797,14 @@ def main():
     tables = {}
     precond_apply = {}
     for i, s in enumerate(svals):
-        st_ms = np.zeros(len(gofd.STAGES))
-        _, inf = gofd.solve(ctx, tr, ops[i], fd, tol=tol, pc=pcs[i], mode=gofd.MODE_FP32_RELIABLE,
-                            inner_tol=args.drop, stage_ms=st_ms)
+        # per-stage medians of three stage-timed solves (one solve's averages move with the box's state)
+        runs = []
+        for _ in range(3):
+            st_ms = np.zeros(len(gofd.STAGES))
+            _, inf = gofd.solve(ctx, tr, ops[i], fd, tol=tol, pc=pcs[i], mode=gofd.MODE_FP32_RELIABLE,
+                                inner_tol=args.drop, stage_ms=st_ms)
+            runs.append(st_ms)
+        st_ms = np.median(np.stack(runs), axis=0)
         rows = pc_for(args.precond, s) not in ("NONE", "DIAG")
         nb = _kernel_bytes(W, 2 * (W - 1), tr, m, 4, pc_for(args.precond, s), gather_rows=rows)
         tables[str(s)] = {
